@@ -1,0 +1,394 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types an oracle formula: each compares the oracle with a
+different route (a library routine, a 50-digit power series, a closed form,
+an identity, a bound, or brute force) so that a dropped term, a wrong sign or
+index, or a transposed operand in the oracle fails at least one of them.
+The ``TestMutants`` class plants such mistakes in copies of oracle functions
+and checks that the pins catch them.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.optimize
+
+import datagen
+import oracle as O
+
+RNG = np.random.default_rng(12345)
+
+
+def small_problem(d=40, k=4, counts=None, r=8, seed=7):
+    counts = np.asarray(counts if counts is not None else [3] * k)
+    X = datagen.make_samples(d, counts, r, seed)
+    H_W, H_B = O.scatter_factors(X, counts)
+    return X, counts, H_W, H_B
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ----------------------------------------------------------------------------
+# Check functions (shared by the pins and by the mutation tests)
+# ----------------------------------------------------------------------------
+
+def check_scatter(scatter_factors):
+    """S_W + S_B equals the total scatter about the sample mean (a classical
+    decomposition that holds only for the sample-weighted global centroid),
+    class blocks of H_W sum to zero, and H_B [sqrt(n_j)] = 0."""
+    counts = np.array([2, 5, 3, 7])
+    X = datagen.make_samples(12, counts, 5, seed=3)
+    H_W, H_B = scatter_factors(X, counts)
+    m = X.mean(axis=1, keepdims=True)
+    S_T = (X - m) @ (X - m).T
+    ok = rel(H_W @ H_W.T + H_B @ H_B.T, S_T) < 1e-13
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    for j in range(counts.size):
+        ok &= np.abs(H_W[:, offs[j]:offs[j + 1]].sum(axis=1)).max() < 1e-14
+    ok &= np.abs(H_B @ np.sqrt(counts)).max() < 1e-13
+    # the sum forms of eqs. (1.1)-(1.2)
+    S_W, S_B = O.scatter_sums(X, counts)
+    ok &= rel(H_W @ H_W.T, S_W) < 1e-13 and rel(H_B @ H_B.T, S_B) < 1e-13
+    return bool(ok)
+
+
+def check_expm_vs_scipy(expm_sym):
+    ok = True
+    for trial in range(4):
+        A = RNG.standard_normal((7, 7)) * (0.5 + trial)
+        S = A + A.T
+        for c in (1.0, -1.0, -0.5, 0.3):
+            ok &= rel(expm_sym(S, c), scipy.linalg.expm(c * S)) < 1e-12
+    return bool(ok)
+
+
+def check_thm31(exp_action_thm31):
+    _, _, H_W, H_B = small_problem(d=30, k=3, counts=[4, 2, 5])
+    V = RNG.standard_normal((30, 3))
+    ok = True
+    for H, c in ((H_W, -1.0), (H_W, -0.5), (H_B, 1.0), (H_W, 2.0)):
+        ok &= rel(exp_action_thm31(H, c, V), scipy.linalg.expm(c * H @ H.T) @ V) < 1e-12
+    return bool(ok)
+
+
+def check_example_1_1(eda_dense):
+    """Example 1.1: three independent samples, one per class, so H_W = 0 and
+    the pencil becomes exp(S_B) x = lam x.  Its eigenvalues are exp(sigma_i^2)
+    for the singular values of H_B, together with exp(0) = 1 for the null
+    direction, and the eigenvectors are H_B's left singular vectors."""
+    X = np.asfortranarray(np.array([[1.0, 0.2, -0.3], [0.1, 0.9, 0.4], [0.2, -0.5, 1.1]]))
+    counts = np.array([1, 1, 1])
+    H_W, H_B = O.scatter_factors(X, counts)
+    if np.abs(H_W).max() != 0.0:
+        return False
+    U, s, _ = np.linalg.svd(H_B)
+    expect = np.sort(np.exp(s ** 2))[::-1]
+    res = eda_dense(H_W, H_B, 3)
+    ok = rel(res.lam, expect) < 1e-13
+    # distinct eigenvalues: columns equal the singular vectors up to sign
+    for i in range(3):
+        ok &= abs(abs(res.X[:, i] @ U[:, i]) - 1.0) < 1e-12
+    return bool(ok)
+
+
+def check_dense_order(eda_dense):
+    _, _, H_W, H_B = small_problem(d=25, k=4, counts=[3, 3, 2, 4])
+    full = O.pencil_spectrum(H_W, H_B)
+    res = eda_dense(H_W, H_B, 3)
+    return bool(rel(res.lam, full[:3]) < 1e-12 and np.all(np.diff(res.lam) < 0))
+
+
+# ----------------------------------------------------------------------------
+# Pins
+# ----------------------------------------------------------------------------
+
+def test_scatter_factors_decomposition():
+    assert check_scatter(O.scatter_factors)
+
+
+def test_expm_sym_matches_pade_library():
+    assert check_expm_vs_scipy(O.expm_sym)
+
+
+@pytest.mark.parametrize("c", [1.0, -1.0, -0.5])
+def test_expm_sym_matches_50_digit_power_series(c):
+    H = RNG.standard_normal((5, 3)) * 0.9
+    S = H @ H.T
+    ref = O.expm_taylor_mp(S, c, digits=50)
+    assert rel(O.expm_sym(S, c), ref) < 1e-14
+
+
+def test_phi_identity_against_oracle_exponential():
+    """exp(c H H^T) = I + H phi_c(H^T H) H^T, phi_c(z) = (e^{cz} - 1)/z,
+    phi_c(0) = c: the power series of exp(c H H^T) with one H pulled out on
+    each side.  Checked on rank-deficient scatter factors (H_W has rank n-k,
+    H_B rank k-1) and on a generic H."""
+    _, _, H_W, H_B = small_problem(d=20, k=3, counts=[3, 4, 2])
+    for H in (H_W, H_B, RNG.standard_normal((9, 4))):
+        lam, V = np.linalg.eigh(H.T @ H)
+        for c in (1.0, -1.0, -0.5):
+            with np.errstate(divide="ignore", invalid="ignore"):
+                phi = np.where(np.abs(lam) > 1e-300, np.expm1(c * lam) / lam, c)
+            E = np.eye(H.shape[0]) + H @ (V * phi) @ V.T @ H.T
+            assert rel(E, O.expm_sym(H @ H.T, c)) < 1e-13
+
+
+def test_thm31_route_matches_library_expm():
+    assert check_thm31(O.exp_action_thm31)
+
+
+def test_exp_of_between_scatter_spectrum_closed_form():
+    """eig(exp(S_B)) = {exp(sigma_i(H_B)^2)} U {1} (Theorem 3.1, eq. 3.9)."""
+    _, _, _, H_B = small_problem(d=30, k=5, counts=[3, 2, 4, 3, 2])
+    s = np.linalg.svd(H_B, compute_uv=False)
+    expect = np.sort(np.concatenate([np.exp(s ** 2), np.ones(30 - s.size)]))
+    got = np.linalg.eigvalsh(O.expm_sym(H_B @ H_B.T, 1.0))
+    assert np.max(np.abs(got - expect) / expect) < 1e-13
+
+
+def test_exp_inverse_and_square_root_identities():
+    """exp(S) exp(-S) = I (eq. 2.2) and exp(-S/2)^2 = exp(-S) (eq. 3.11)."""
+    _, _, H_W, _ = small_problem(d=25, k=3)
+    S = H_W @ H_W.T
+    assert np.abs(O.expm_sym(S, 1.0) @ O.expm_sym(S, -1.0) - np.eye(25)).max() < 1e-13
+    Eh = O.expm_sym(S, -0.5)
+    assert rel(Eh @ Eh, O.expm_sym(S, -1.0)) < 1e-14
+
+
+def test_lanczos_and_arnoldi_products_match_dense():
+    _, _, H_W, H_B = small_problem(d=35, k=4, counts=[3, 2, 4, 3])
+    V = RNG.standard_normal((35, 4))
+    assert rel(O.lanczos_action_thm31(H_W, H_B, V), O.lanczos_matrix_dense(H_W, H_B) @ V) < 1e-12
+    assert rel(O.arnoldi_action_thm31(H_W, H_B, V), O.arnoldi_matrix_dense(H_W, H_B) @ V) < 1e-12
+    # and against the library exponential
+    M = scipy.linalg.expm(-0.5 * H_W @ H_W.T) @ scipy.linalg.expm(H_B @ H_B.T) @ scipy.linalg.expm(-0.5 * H_W @ H_W.T)
+    assert rel(O.lanczos_matrix_dense(H_W, H_B), M) < 1e-12
+
+
+def test_example_1_1_closed_form():
+    assert check_example_1_1(O.eda_dense)
+
+
+def test_dense_returns_top_t_descending():
+    assert check_dense_order(O.eda_dense)
+
+
+def test_between_scatter_zero_case():
+    """Equal class means give H_B = 0; the pencil is then I x = lam exp(S_W) x
+    with eigenvalues exp(-sigma_i(H_W)^2) and 1."""
+    rng = np.random.default_rng(5)
+    d, counts = 10, np.array([3, 3])
+    dev = 0.3 * rng.standard_normal((d, 6))
+    dev[:, :3] -= dev[:, :3].mean(axis=1, keepdims=True)
+    dev[:, 3:] -= dev[:, 3:].mean(axis=1, keepdims=True)
+    X = np.asfortranarray(rng.standard_normal((d, 1)) + dev)
+    H_W, H_B = O.scatter_factors(X, counts)
+    assert np.abs(H_B).max() < 1e-14
+    s = np.linalg.svd(H_W, compute_uv=False)
+    expect = np.sort(np.concatenate([np.exp(-s ** 2), np.ones(d - s.size)]))[::-1]
+    got = O.pencil_spectrum(H_W, H_B)
+    assert np.max(np.abs(got - expect) / expect) < 1e-13
+
+
+def test_orthogonal_factor_spaces_case():
+    """If span(H_W) is orthogonal to span(H_B), the spectrum is
+    {e^{sigma_B^2}} U {e^{-sigma_W^2}} U {1} (both exponentials act on
+    orthogonal invariant subspaces, Theorem 3.1)."""
+    rng = np.random.default_rng(6)
+    Q = np.linalg.qr(rng.standard_normal((12, 12)))[0]
+    H_B = Q[:, :3] @ rng.standard_normal((3, 3)) * 0.6
+    H_W = Q[:, 3:7] @ rng.standard_normal((4, 5)) * 0.4
+    sB = np.linalg.svd(H_B, compute_uv=False)
+    sW = np.linalg.svd(H_W, compute_uv=False)[:4]
+    expect = np.sort(np.concatenate([np.exp(sB ** 2), np.exp(-sW ** 2), np.ones(5)]))[::-1]
+    got = O.pencil_spectrum(H_W, H_B)
+    assert np.max(np.abs(got - expect) / expect) < 1e-12
+
+
+def test_pencil_eigenvalues_positive_and_bounded_thm32():
+    """Generalised eigenvalues are positive (SPD pencil) and satisfy the
+    per-index bounds (3.17)-(3.18) of Theorem 3.2."""
+    _, _, H_W, H_B = small_problem(d=40, k=4)
+    lam = O.pencil_spectrum(H_W, H_B)
+    assert np.all(lam > 0)
+    mu = np.sort(np.linalg.eigvalsh(H_B @ H_B.T))[::-1]
+    nu = np.sort(np.linalg.eigvalsh(H_W @ H_W.T))[::-1]
+    lo, hi = O.eig_bounds_thm32(mu, nu)
+    assert np.all(lam >= lo * (1 - 1e-12)) and np.all(lam <= hi * (1 + 1e-12))
+
+
+def test_thm32_bounds_collapse_when_one_factor_vanishes():
+    """With S_W = 0 the bounds of Theorem 3.2 pinch to exp(mu_i); with
+    S_B = 0 to exp(-nu_{d-i+1}).  This pins the index bookkeeping."""
+    mu = np.sort(RNG.uniform(0, 3, 9))[::-1]
+    lo, hi = O.eig_bounds_thm32(mu, np.zeros(9))
+    assert np.allclose(lo, np.exp(mu), rtol=1e-15) and np.allclose(hi, np.exp(mu), rtol=1e-15)
+    nu = np.sort(RNG.uniform(0, 3, 9))[::-1]
+    lo, hi = O.eig_bounds_thm32(np.zeros(9), nu)
+    assert np.allclose(lo, np.exp(-nu[::-1]), rtol=1e-15) and np.allclose(hi, np.exp(-nu[::-1]), rtol=1e-15)
+
+
+def test_unit_eigenvalue_count_thm36_and_exact_inertia():
+    """Theorem 3.6: at least d-n+1 eigenvalues equal 1 for independent
+    samples.  Sharper (Courant-Fischer on span[H_W H_B]): exactly k-1 above 1,
+    d-n+1 equal to 1 and n-k below 1."""
+    d, k, nj = 40, 4, 3
+    _, _, H_W, H_B = small_problem(d=d, k=k, counts=[nj] * k)
+    n = k * nj
+    above, equal, below = O.inertia(O.pencil_spectrum(H_W, H_B), tol=1e-9)
+    assert equal >= d - n + 1
+    assert (above, equal, below) == (k - 1, d - n + 1, n - k)
+
+
+def test_trace_ratio_bruteforce_lemma33_thm34():
+    """Lemma 3.3: tr((V^T E_W V)^{-1} V^T E_B V) <= sum of the t largest
+    eigenvalues, with equality on the dominant eigenspace.  Brute force over
+    4 x 2 matrices (random search + local optimisation from random starts)
+    must not beat the oracle, and its maximiser must span the oracle's X.
+    Theorem 3.4 bounds the maximum."""
+    rng = np.random.default_rng(8)
+    d, t = 4, 2
+    H_W = rng.standard_normal((d, 3)) * 0.7
+    H_B = rng.standard_normal((d, 2)) * 0.8
+    E_B, E_W = O.pencil_dense(H_W, H_B)
+    res = O.eda_dense(H_W, H_B, t)
+    best = res.lam.sum()
+    assert abs(O.trace_ratio(res.X, E_B, E_W) - best) < 1e-12 * best
+    samples = rng.standard_normal((20000, d, t))
+    vals = [O.trace_ratio(V, E_B, E_W) for V in samples]
+    assert max(vals) <= best * (1 + 1e-12)
+    f = lambda v: -O.trace_ratio(v.reshape(d, t), E_B, E_W)
+    opt = min((scipy.optimize.minimize(f, rng.standard_normal(d * t), method="BFGS",
+                                       options={"gtol": 1e-12}) for _ in range(12)),
+              key=lambda r: r.fun)
+    assert abs(-opt.fun - best) < 1e-9 * best
+    Vopt = np.linalg.qr(opt.x.reshape(d, t))[0]
+    assert O.sin_angle(res.X, Vopt) < 1e-4
+    mu = np.sort(np.linalg.eigvalsh(H_B @ H_B.T))[::-1]
+    nu = np.sort(np.linalg.eigvalsh(H_W @ H_W.T))[::-1]
+    lo, hi = O.rho_bounds_thm34(mu, nu, t)
+    assert lo * (1 - 1e-12) <= best <= hi * (1 + 1e-12)
+
+
+def test_lanczos_arnoldi_pencil_share_spectrum():
+    """M, exp(-S_W)exp(S_B) and the pencil have the same eigenvalues, and
+    x = exp(-S_W/2) y maps eigenvectors of M to pencil eigenvectors
+    (eqs. 3.12-3.14)."""
+    _, _, H_W, H_B = small_problem(d=20, k=3, counts=[3, 3, 3])
+    M = O.lanczos_matrix_dense(H_W, H_B)
+    A = O.arnoldi_matrix_dense(H_W, H_B)
+    lm, Y = np.linalg.eigh(M)
+    la = np.sort(np.linalg.eigvals(A).real)
+    lp = np.sort(O.pencil_spectrum(H_W, H_B))
+    assert np.max(np.abs(lm - lp) / lp) < 1e-12 and np.max(np.abs(la - lp) / lp) < 1e-10
+    E_B, E_W = O.pencil_dense(H_W, H_B)
+    x = O.expm_sym(H_W @ H_W.T, -0.5) @ Y
+    R = E_B @ x - (E_W @ x) * lm
+    assert np.abs(R).max() < 1e-12 * lm.max()
+
+
+def test_orth_qr_follows_eigenvalue_order():
+    """orth by QR keeps nested spans: span X[:, :i] = span x[:, :i]."""
+    _, _, H_W, H_B = small_problem(d=30, k=5, counts=[2, 3, 3, 2, 3])
+    res = O.eda_dense(H_W, H_B, 4)
+    assert np.abs(res.X.T @ res.X - np.eye(4)).max() < 1e-14
+    for i in range(1, 5):
+        xi = np.linalg.qr(res.x[:, :i])[0]
+        assert O.sin_angle(xi, res.X[:, :i]) < 1e-12
+    # sign convention: largest-magnitude entry positive
+    idx = np.argmax(np.abs(res.X), axis=0)
+    assert np.all(res.X[idx, np.arange(4)] > 0)
+
+
+def test_sin_angle_known_rotation():
+    th = 0.123
+    X = np.array([[1.0], [0.0], [0.0]])
+    Y = np.array([[np.cos(th)], [np.sin(th)], [0.0]])
+    assert abs(O.sin_angle(X, Y) - np.sin(th)) < 1e-15
+
+
+def test_dense_and_reduced_agree_small():
+    _, counts, H_W, H_B = small_problem(d=60, k=5, counts=[3, 4, 2, 5, 3])
+    a = O.eda_dense(H_W, H_B, 4)
+    b = O.eda_reduced(H_W, H_B, 4)
+    assert np.max(np.abs(a.lam - b.lam) / a.lam) < 1e-12
+    assert O.sin_angle(a.X, b.X) < 1e-11
+    assert np.abs(a.X - b.X).max() < 1e-10  # same sign convention, distinct lam
+
+
+@pytest.mark.slow
+def test_dense_and_reduced_agree_c1():
+    """O1 (dense d x d) against O2 (exact reduction) on the d=1024 workload."""
+    p = datagen.config("C1")
+    H_W, H_B = O.scatter_factors(p.X, p.counts)
+    a = O.eda_dense(H_W, H_B, p.t)
+    b = O.eda_reduced(H_W, H_B, p.t)
+    assert np.max(np.abs(a.lam - b.lam) / a.lam) < 1e-12
+    assert O.sin_angle(a.X, b.X) < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Mutation tests: plausible mistakes planted in copies of oracle functions.
+# ----------------------------------------------------------------------------
+
+class TestMutants:
+    def test_unweighted_global_mean_is_caught(self):
+        def bad(X, counts):
+            H_W, H_B = O.scatter_factors(X, counts)
+            offs = np.concatenate([[0], np.cumsum(counts)])
+            mus = np.stack([X[:, offs[j]:offs[j + 1]].mean(axis=1) for j in range(len(counts))], 1)
+            mu_bad = mus.mean(axis=1)
+            return H_W, np.sqrt(counts)[None, :] * (mus - mu_bad[:, None])
+        assert not check_scatter(bad)
+
+    def test_missing_sqrt_weight_is_caught(self):
+        def bad(X, counts):
+            H_W, H_B = O.scatter_factors(X, counts)
+            return H_W, H_B / np.sqrt(counts)[None, :]
+        assert not check_scatter(bad)
+
+    def test_transposed_eigenvectors_are_caught(self):
+        def bad(S, c=1.0):
+            mu, Z = np.linalg.eigh(S)
+            return (Z.T * np.exp(c * mu)) @ Z
+        assert not check_expm_vs_scipy(bad)
+
+    def test_wrong_exponent_sign_is_caught(self):
+        assert not check_expm_vs_scipy(lambda S, c=1.0: O.expm_sym(S, -c))
+
+    def test_dropped_complement_term_is_caught(self):
+        def bad(H, c, V):
+            Qt, D = O.thm31_basis(H)
+            return Qt @ (np.exp(c * D)[:, None] * (Qt.T @ V))
+        assert not check_thm31(bad)
+
+    def test_swapped_pencil_is_caught(self):
+        def bad(H_W, H_B, t):
+            return O.eda_dense(H_B, H_W, t)
+        assert not check_example_1_1(bad)
+
+    def test_ascending_order_is_caught(self):
+        def bad(H_W, H_B, t):
+            E_B, E_W = O.pencil_dense(H_W, H_B)
+            lam, x = scipy.linalg.eigh(E_B, E_W)
+            return O.EDAResult(lam=lam[:t], log_lam=np.log(lam[:t]), X=O.orth_qr(x[:, :t]), x=x[:, :t])
+        assert not check_dense_order(bad)
+
+
+# ----------------------------------------------------------------------------
+# Stored reference values (tests/golden/oracle_*.txt, written by
+# tests/golden/make_golden.py from the oracle) still match the oracle.
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_golden_values_match_oracle(name):
+    from tests.golden.make_golden import read
+    g = read(name)
+    p = datagen.config(name)
+    H_W, H_B = O.scatter_factors(p.X, p.counts)
+    red = O.eda_reduced(H_W, H_B, p.t)
+    assert np.max(np.abs(red.lam - g["lam"]) / g["lam"]) < 1e-12
+    # and the top of the stored values within Theorem 3.2's bounds in reduced form:
+    # lam_1 <= exp(mu_1 - nu_d) = exp(sigma_B,max^2) since nu_d = 0 for d > n
+    assert g["lam"][0] <= np.exp(g["sigma2_B_max"]) * (1 + 1e-12)
