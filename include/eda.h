@@ -1,0 +1,204 @@
+/*
+ * eda.h -- C ABI of libeda, the MI355X (gfx950) library for the hot path of
+ * inexact-Krylov exponential discriminant analysis (EDA).
+ *
+ * Problem (Wu, Feng, Zhang, Yang, arXiv 1512.06500, Section 1, eq. (1.7)):
+ * find the t dominant eigenpairs of the symmetric-definite pencil
+ *
+ *     exp(S_B) x = lambda exp(S_W) x,   S_W = H_W H_W^T,  S_B = H_B H_B^T,
+ *
+ * with H_W (d x n) and H_B (d x k) the within- and between-class scatter
+ * factors of eqs. (1.1)-(1.2), and return the eigenvectors orthonormalised in
+ * decreasing-lambda order (Algorithm 1 step 4, Algorithm 3 step 6).
+ *
+ * The library never forms a d x d matrix.  Every exponential is applied as
+ *     exp(c H H^T) V = V + H phi_c(H^T H) H^T V,  phi_c(z) = (e^{cz}-1)/z,
+ * which equals the closed form of Theorem 3.1 (eqs. (3.9)-(3.11)) and needs
+ * only the small Gram matrix H^T H and its symmetric eigendecomposition.
+ * The eigenproblem is solved by block Lanczos on the symmetric form
+ * M = exp(-S_W/2) exp(S_B) exp(-S_W/2) (eq. (3.15)), then x = exp(-S_W/2) y
+ * (eq. (3.14)), as in Algorithm 3.
+ *
+ * Conventions for every call:
+ *   - Matrices are column-major with an explicit leading dimension (ld >= rows).
+ *   - Pointers documented as "device" must point to GPU memory of the device
+ *     that was current when the handle was created; "host" pointers to CPU
+ *     memory.  The caller owns every buffer it passes; the library copies
+ *     what it keeps.
+ *   - Work is ordered on the handle's HIP stream.  Calls returning host
+ *     outputs synchronise that stream before returning; the others do not.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Errors are reported by return code only.  Arguments are validated on
+ *     the host before any HIP call, so invalid arguments never reach a
+ *     kernel.  eda_last_error() gives a message for the last failure.
+ */
+#ifndef EDA_H_
+#define EDA_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eda_handle_s* eda_handle;
+
+typedef enum {
+  EDA_OK = 0,
+  EDA_ERR_ARG = 1,        /* invalid argument (shape, ld, null pointer, option)   */
+  EDA_ERR_NOMEM = 2,      /* device or host allocation failed                      */
+  EDA_ERR_HIP = 3,        /* a HIP runtime call failed                             */
+  EDA_ERR_NOCONV = 4,     /* eda_solve: max_iter reached; best pairs still written */
+  EDA_ERR_RANGE = 5,      /* a result is outside the floating-point range          */
+  EDA_ERR_NONFINITE = 6,  /* NaN or Inf found in an input factor                   */
+  EDA_ERR_STATE = 7       /* call order violated (e.g. eda_solve before prepare)  */
+} eda_status;
+
+/* Storage / arithmetic types. */
+typedef enum { EDA_F64 = 0, EDA_F32 = 1, EDA_BF16 = 2, EDA_FP8_E4M3 = 3 } eda_dtype;
+
+/* Which scatter factor an exponential acts on. */
+typedef enum { EDA_W = 0, EDA_B = 1 } eda_which;
+
+/* Operator forms of Section 3.1. */
+typedef enum {
+  EDA_FORM_LANCZOS_M = 0,  /* M = exp(-S_W/2) exp(S_B) exp(-S_W/2), eq. (3.15), product (3.16) */
+  EDA_FORM_ARNOLDI_A = 1   /* A = exp(-S_W) exp(S_B), eq. (3.1), product (3.2)                 */
+} eda_form;
+
+/* Residual measure used by the stopping test of eda_solve. */
+typedef enum {
+  EDA_RES_REL_THETA = 0,   /* ||M y - theta y|| / theta per Ritz pair (default) */
+  EDA_RES_NORMWISE = 1     /* ||M y - theta y|| / theta_1                        */
+} eda_resmode;
+
+/* Solver options.  A zero-initialised struct selects every default. */
+typedef struct {
+  eda_form form;            /* only EDA_FORM_LANCZOS_M is solved at present          */
+  int32_t block;            /* block width b (default 8)                             */
+  int32_t max_basis;        /* basis columns before a thick restart (default
+                               max(2t+2b, t+6b) rounded up to a multiple of b,
+                               capped by d)                                          */
+  int32_t max_iter;         /* maximal block steps (default 4000)                    */
+  eda_resmode resmode;
+  eda_dtype krylov_dtype;   /* arithmetic of the Krylov phase (default EDA_F64)      */
+  eda_dtype refine_dtype;   /* reserved (refinement precision); must be EDA_F64      */
+  uint64_t seed;            /* start-block seed when start_block is NULL             */
+  const void* start_block;  /* device, d x b float64 start block, or NULL            */
+  int64_t ld_start;         /* leading dimension of start_block                      */
+  int32_t check_every;      /* block steps between Rayleigh-Ritz checks (default 2)  */
+  int32_t reserved[7];
+} eda_solve_opts;
+
+/* Per-solve diagnostics. */
+typedef struct {
+  int32_t iters;            /* block Lanczos steps taken                      */
+  int32_t restarts;         /* thick restarts                                 */
+  int32_t refine_passes;    /* FP64 refinement passes                         */
+  int32_t flags;            /* EDA_WARN_* bits                                */
+  int64_t ops;              /* operator applications, counted per column      */
+  double bytes_moved;       /* algorithmic HBM bytes of the operator passes   */
+  double t_prepare_ms;      /* time of the last eda_prepare                   */
+  double t_krylov_ms;       /* Krylov phase of this solve                     */
+  double t_refine_ms;       /* refinement phase of this solve                 */
+  double shift_s;           /* spectral shift s: the operator iterated is e^{-s} M */
+  int64_t op_calls;         /* block operator products M V timed in this solve */
+  double t_op_ms;           /* their total duration (HIP events on the handle's
+                               stream around each product: both streaming
+                               passes over P and the small core product)     */
+  double op_bytes;          /* algorithmic bytes of one timed product:
+                               2 d (n+k) s_P + 3 d b 8 (s_P: bytes per entry) */
+} eda_info;
+
+#define EDA_WARN_DEGENERATE 1  /* t > k-1: the wanted subspace is not unique       */
+#define EDA_WARN_FLOOR 2       /* some pair stopped at its attainable floor, not tol */
+#define EDA_WARN_REPAIRED 4    /* a Krylov block lost rank and was re-orthogonalised */
+
+/* Create a handle bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  *h receives the handle. */
+eda_status eda_create(eda_handle* h, void* hip_stream);
+
+/* Release every device allocation of the handle and the handle itself.
+ * Synchronises the handle's stream first.  NULL is ignored. */
+void eda_destroy(eda_handle h);
+
+/* Message for a status code (static string). */
+const char* eda_strerror(eda_status s);
+
+/* Message for the last failed call on `h` (valid until the next call). */
+const char* eda_last_error(eda_handle h);
+
+/* Scatter factors of eqs. (1.1)-(1.2).
+ * X: device, d x n float64, ld ldx >= d, samples as columns, classes stored
+ *    contiguously (class j occupies counts[j] consecutive columns).
+ * counts: host, k entries, each >= 1, summing to n.
+ * H_W: device out, d x n (ld ldw >= d): X_j - mu_j e^T per class.
+ * H_B: device out, d x k (ld ldb >= d): sqrt(n_j) (mu_j - mu), mu the mean of
+ *      all n samples.  Stream-ordered, no synchronisation. */
+eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k,
+                               const double* X, int64_t ldx, const int64_t* counts,
+                               double* H_W, int64_t ldw, double* H_B, int64_t ldb);
+
+/* Preprocessing of Algorithm 2 (steps 1-4), in Gram form.
+ * H_W: device, d x n float64 (ldw >= d); H_B: device, d x k float64 (ldb >= d).
+ * Requires d >= 2, k >= 2, n >= k.  The factors are copied into library
+ * storage P = [H_W H_B] in `storage` precision (EDA_F64 or EDA_F32), the
+ * Gram matrix P^T P is formed in float64, eig(H_W^T H_W) and eig(H_B^T H_B)
+ * are computed in float64, and the cores of the exponentials are built.
+ * Returns EDA_ERR_NONFINITE if a factor holds NaN/Inf.  Synchronises. */
+eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k,
+                       const double* H_W, int64_t ldw, const double* H_B, int64_t ldb,
+                       eda_dtype storage);
+
+/* Exponential-vector product of Theorem 3.1:
+ *     Out = e^{-s} exp(c S_which) V,   s = max(0, c * lambda_max(S_which)),
+ * with s written to *log_scale (host) so that exp(c S) V = e^{s} Out.
+ * V: device d x b (ldv >= d); Out: device d x b (ldo >= d), must not overlap V.
+ * vdtype: EDA_F64 (V and Out float64) or EDA_F32 (float32).
+ * Stream-ordered; synchronises only when a core for a new c must be built. */
+eda_status eda_expmv(eda_handle h, eda_which which, double c, int64_t b,
+                     const void* V, int64_t ldv, void* Out, int64_t ldo, eda_dtype vdtype,
+                     double* log_scale);
+
+/* Composite operator products (3.16) / (3.2), scaled:
+ *     Out = e^{-s} M V  (EDA_FORM_LANCZOS_M)  or  Out = e^{-s} A V  (EDA_FORM_ARNOLDI_A),
+ * s = lambda_max(S_B) written to *log_scale (host).  Two streaming passes over
+ * P = [H_W H_B].  Same buffer rules as eda_expmv.  Stream-ordered. */
+eda_status eda_opmv(eda_handle h, eda_form form, int64_t b,
+                    const void* V, int64_t ldv, void* Out, int64_t ldo, eda_dtype vdtype,
+                    double* log_scale);
+
+/* Algorithm 3: t dominant eigenpairs of eq. (1.7).
+ * ritz:     host out [t], lambda_i in decreasing order (+inf if > DBL_MAX).
+ * ritz_log: host out [t], log lambda_i.
+ * X:        device out, d x t float64 (ldx >= d), orthonormal: QR of the
+ *           eigenvectors x_i = exp(-S_W/2) y_i in decreasing-lambda order, each
+ *           column's largest-magnitude entry positive.
+ * resid:    host out [t], final residual of each Ritz pair of M, measured
+ *           explicitly with one more operator product (measure from opts).
+ * info:     host out, may be NULL.
+ * Requires 1 <= t < d and t + 2b <= max_basis <= d.  Stops when every pair
+ * has residual <= max(tol, 10 u theta_1/theta_i) (u: unit roundoff of the
+ * Krylov arithmetic).  EDA_ERR_NOCONV if max_iter is reached (outputs still
+ * written).  Synchronises. */
+eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* opt,
+                     double* ritz, double* ritz_log, double* X, int64_t ldx,
+                     double* resid, eda_info* info);
+
+/* Gram matrix G = P^T P of the current preparation (float64, N x N with
+ * N = n + k, P = [H_W H_B]); G: device out (ldg >= N).  Stream-ordered. */
+eda_status eda_gram(eda_handle h, double* G, int64_t ldg);
+
+/* Symmetric eigensolver used for the Gram and Rayleigh-Ritz matrices:
+ * A = Z diag(w) Z^T for symmetric A (n x n float64, device, lda >= n, only
+ * the lower triangle is read; A is not modified).  w: device out [n]
+ * ascending; Z: device out n x n (ldz >= n), orthonormal columns.
+ * 1 <= n <= 2048.  Synchronises. */
+eda_status eda_syev(eda_handle h, int64_t n, const double* A, int64_t lda,
+                    double* w, double* Z, int64_t ldz);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EDA_H_ */

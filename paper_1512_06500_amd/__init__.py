@@ -1,0 +1,293 @@
+"""MI355X (gfx950) inexact-Krylov exponential discriminant analysis.
+
+Thin ctypes binding of ``libeda.so`` (C ABI in ``include/eda.h``).  Every
+step of the computation runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory and the stream.  There
+is no CPU fallback: if the library is missing, loading fails loudly.
+
+Problem (arXiv 1512.06500, eq. (1.7)): the t dominant eigenpairs of
+exp(S_B) x = lambda exp(S_W) x with S_W = H_W H_W^T, S_B = H_B H_B^T.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+__all__ = [
+    "EDAError", "Handle", "SolveResult", "load_library", "library_path", "colmajor",
+    "EDA_OK", "EDA_ERR_ARG", "EDA_ERR_NOMEM", "EDA_ERR_HIP", "EDA_ERR_NOCONV",
+    "EDA_ERR_RANGE", "EDA_ERR_NONFINITE", "EDA_ERR_STATE", "EXPORTED_SYMBOLS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+EDA_OK, EDA_ERR_ARG, EDA_ERR_NOMEM, EDA_ERR_HIP = 0, 1, 2, 3
+EDA_ERR_NOCONV, EDA_ERR_RANGE, EDA_ERR_NONFINITE, EDA_ERR_STATE = 4, 5, 6, 7
+EDA_F64, EDA_F32, EDA_BF16, EDA_FP8_E4M3 = 0, 1, 2, 3
+EDA_W, EDA_B = 0, 1
+EDA_FORM_LANCZOS_M, EDA_FORM_ARNOLDI_A = 0, 1
+EDA_RES_REL_THETA, EDA_RES_NORMWISE = 0, 1
+EDA_WARN_DEGENERATE, EDA_WARN_FLOOR, EDA_WARN_REPAIRED = 1, 2, 4
+
+_DTYPES = {"f64": EDA_F64, "f32": EDA_F32, "bf16": EDA_BF16, "fp8": EDA_FP8_E4M3}
+
+EXPORTED_SYMBOLS = [
+    "eda_create", "eda_destroy", "eda_strerror", "eda_last_error", "eda_scatter_factors",
+    "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_gram", "eda_syev",
+]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("form", ctypes.c_int), ("block", ctypes.c_int32), ("max_basis", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32), ("resmode", ctypes.c_int), ("krylov_dtype", ctypes.c_int),
+        ("refine_dtype", ctypes.c_int), ("seed", ctypes.c_uint64),
+        ("start_block", ctypes.c_void_p), ("ld_start", ctypes.c_int64),
+        ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+        ("refine_passes", ctypes.c_int32), ("flags", ctypes.c_int32), ("ops", ctypes.c_int64),
+        ("bytes_moved", ctypes.c_double), ("t_prepare_ms", ctypes.c_double),
+        ("t_krylov_ms", ctypes.c_double), ("t_refine_ms", ctypes.c_double),
+        ("shift_s", ctypes.c_double), ("op_calls", ctypes.c_int64),
+        ("t_op_ms", ctypes.c_double), ("op_bytes", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+class EDAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[eda status {status}] {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libeda.so")
+
+
+def load_library():
+    """Load libeda.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1512_06500_amd.build.build()")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.eda_create.argtypes = [ctypes.POINTER(vp), vp]
+    L.eda_create.restype = ctypes.c_int
+    L.eda_destroy.argtypes = [vp]
+    L.eda_destroy.restype = None
+    L.eda_strerror.argtypes = [ctypes.c_int]
+    L.eda_strerror.restype = ctypes.c_char_p
+    L.eda_last_error.argtypes = [vp]
+    L.eda_last_error.restype = ctypes.c_char_p
+    L.eda_scatter_factors.argtypes = [vp, i64, i64, i64, vp, i64, ctypes.POINTER(i64), vp, i64,
+                                      vp, i64]
+    L.eda_scatter_factors.restype = ctypes.c_int
+    L.eda_prepare.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, ctypes.c_int]
+    L.eda_prepare.restype = ctypes.c_int
+    L.eda_expmv.argtypes = [vp, ctypes.c_int, dbl, i64, vp, i64, vp, i64, ctypes.c_int,
+                            ctypes.POINTER(dbl)]
+    L.eda_expmv.restype = ctypes.c_int
+    L.eda_opmv.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, i64, ctypes.c_int,
+                           ctypes.POINTER(dbl)]
+    L.eda_opmv.restype = ctypes.c_int
+    L.eda_solve.argtypes = [vp, i32, dbl, ctypes.POINTER(SolveOpts), ctypes.POINTER(dbl),
+                            ctypes.POINTER(dbl), vp, i64, ctypes.POINTER(dbl),
+                            ctypes.POINTER(Info)]
+    L.eda_solve.restype = ctypes.c_int
+    L.eda_gram.argtypes = [vp, vp, i64]
+    L.eda_gram.restype = ctypes.c_int
+    L.eda_syev.argtypes = [vp, i64, vp, i64, vp, vp, i64]
+    L.eda_syev.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def colmajor(t):
+    """Return a column-major (Fortran-order) view/copy of a 2-D tensor."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.stride(0) == 1 and (t.shape[1] <= 1 or t.stride(1) >= max(1, t.shape[0])):
+        return t
+    return t.t().contiguous().t()
+
+
+def _ld(t) -> int:
+    return max(int(t.stride(1)) if t.shape[1] > 1 else int(t.shape[0]), int(t.shape[0]), 1)
+
+
+def _empty_cm(rows: int, cols: int, dtype, device):
+    import torch
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+@dataclasses.dataclass
+class SolveResult:
+    ritz: list
+    ritz_log: list
+    X: object           # torch tensor d x t (column-major), float64
+    resid: list
+    info: dict
+    status: int
+    message: str
+
+
+class Handle:
+    """One libeda handle bound to the current device and a torch stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        h = ctypes.c_void_p()
+        st = self.lib.eda_create(ctypes.byref(h), ctypes.c_void_p(raw))
+        self._h = h
+        if st != EDA_OK:
+            msg = self.lib.eda_last_error(h).decode()
+            self.lib.eda_destroy(h)
+            self._h = None
+            raise EDAError(st, msg)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.d = self.n = self.k = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.eda_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != EDA_OK:
+            raise EDAError(st, self.lib.eda_last_error(self._h).decode())
+
+    def _f64(self, t):
+        t = colmajor(t)
+        if t.dtype != self._torch.float64 or t.device.type != "cuda":
+            raise TypeError("expected a float64 CUDA tensor")
+        return t
+
+    # --- calls ---------------------------------------------------------------
+    def scatter_factors(self, X, counts: Sequence[int]):
+        """H_W, H_B of eqs. (1.1)-(1.2) from class-contiguous samples X (d x n)."""
+        X = self._f64(X)
+        d, n = X.shape
+        k = len(counts)
+        H_W = _empty_cm(d, n, self._torch.float64, X.device)
+        H_B = _empty_cm(d, k, self._torch.float64, X.device)
+        arr = (ctypes.c_int64 * k)(*[int(c) for c in counts])
+        self._check(self.lib.eda_scatter_factors(self._h, d, n, k, X.data_ptr(), _ld(X), arr,
+                                                 H_W.data_ptr(), _ld(H_W), H_B.data_ptr(),
+                                                 _ld(H_B)))
+        return H_W, H_B
+
+    def prepare(self, H_W, H_B, storage: str = "f64"):
+        H_W, H_B = self._f64(H_W), self._f64(H_B)
+        d, n = H_W.shape
+        k = H_B.shape[1]
+        if H_B.shape[0] != d:
+            raise ValueError("H_W and H_B need the same number of rows")
+        self._check(self.lib.eda_prepare(self._h, d, n, k, H_W.data_ptr(), _ld(H_W),
+                                         H_B.data_ptr(), _ld(H_B), _DTYPES[storage]))
+        self.d, self.n, self.k = d, n, k
+        self.storage = storage
+        return self
+
+    def _vblock(self, V, vdtype):
+        V = colmajor(V)
+        want = self._torch.float64 if vdtype == "f64" else self._torch.float32
+        if V.dtype != want or V.device.type != "cuda":
+            raise TypeError(f"expected a {want} CUDA tensor")
+        return V
+
+    def expmv(self, which: str, c: float, V, out=None, vdtype: str = "f64"):
+        """Out = e^{-s} exp(c S_which) V; returns (Out, s)."""
+        V = self._vblock(V, vdtype)
+        d, b = V.shape
+        if out is None:
+            out = _empty_cm(d, b, V.dtype, V.device)
+        ls = ctypes.c_double()
+        self._check(self.lib.eda_expmv(self._h, EDA_W if which == "W" else EDA_B, float(c), b,
+                                       V.data_ptr(), _ld(V), out.data_ptr(), _ld(out),
+                                       _DTYPES[vdtype], ctypes.byref(ls)))
+        return out, ls.value
+
+    def opmv(self, form: str, V, out=None, vdtype: str = "f64"):
+        """Out = e^{-s} M V (form 'M') or e^{-s} A V (form 'A'); returns (Out, s)."""
+        V = self._vblock(V, vdtype)
+        d, b = V.shape
+        if out is None:
+            out = _empty_cm(d, b, V.dtype, V.device)
+        ls = ctypes.c_double()
+        f = EDA_FORM_LANCZOS_M if form == "M" else EDA_FORM_ARNOLDI_A
+        self._check(self.lib.eda_opmv(self._h, f, b, V.data_ptr(), _ld(V), out.data_ptr(),
+                                      _ld(out), _DTYPES[vdtype], ctypes.byref(ls)))
+        return out, ls.value
+
+    def solve(self, t: int, tol: float, block: int = 8, max_basis: int = 0, max_iter: int = 0,
+              seed: int = 0, start_block=None, check_every: int = 0, resmode: str = "rel",
+              raise_on_error: bool = True, X=None) -> SolveResult:
+        torch = self._torch
+        o = SolveOpts()
+        o.form = EDA_FORM_LANCZOS_M
+        o.block = block
+        o.max_basis = max_basis
+        o.max_iter = max_iter
+        o.resmode = EDA_RES_REL_THETA if resmode == "rel" else EDA_RES_NORMWISE
+        o.krylov_dtype = EDA_F64
+        o.refine_dtype = EDA_F64
+        o.seed = seed
+        o.check_every = check_every
+        if start_block is not None:
+            start_block = self._f64(start_block)
+            o.start_block = start_block.data_ptr()
+            o.ld_start = _ld(start_block)
+        if X is None:
+            X = _empty_cm(self.d, t, torch.float64, self.device)
+        ritz = (ctypes.c_double * t)()
+        rlog = (ctypes.c_double * t)()
+        res = (ctypes.c_double * t)()
+        info = Info()
+        st = self.lib.eda_solve(self._h, t, float(tol), ctypes.byref(o), ritz, rlog,
+                                X.data_ptr(), _ld(X), res, ctypes.byref(info))
+        msg = self.lib.eda_last_error(self._h).decode() if st != EDA_OK else ""
+        if st not in (EDA_OK, EDA_ERR_NOCONV) and raise_on_error:
+            raise EDAError(st, msg)
+        return SolveResult(list(ritz), list(rlog), X, list(res), info.as_dict(), st, msg)
+
+    def gram(self):
+        N = self.n + self.k
+        G = _empty_cm(N, N, self._torch.float64, self.device)
+        self._check(self.lib.eda_gram(self._h, G.data_ptr(), _ld(G)))
+        return G
+
+    def syev(self, A):
+        A = self._f64(A)
+        n = A.shape[0]
+        w = self._torch.empty(n, dtype=self._torch.float64, device=A.device)
+        Z = _empty_cm(n, n, self._torch.float64, A.device)
+        self._check(self.lib.eda_syev(self._h, n, A.data_ptr(), _ld(A), w.data_ptr(),
+                                      Z.data_ptr(), _ld(Z)))
+        return w, Z

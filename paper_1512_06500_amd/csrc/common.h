@@ -1,0 +1,155 @@
+// Shared definitions of the libeda HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace eda {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Scalar conversions used by the templated kernels.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ double to_f64(T x);
+template <> __device__ __forceinline__ double to_f64<double>(double x) { return x; }
+template <> __device__ __forceinline__ double to_f64<float>(float x) { return (double)x; }
+
+template <typename T> __device__ __forceinline__ float to_f32(T x);
+template <> __device__ __forceinline__ float to_f32<double>(double x) { return (float)x; }
+template <> __device__ __forceinline__ float to_f32<float>(float x) { return x; }
+
+template <typename ACC, typename T> __device__ __forceinline__ ACC to_acc(T x);
+template <> __device__ __forceinline__ double to_acc<double, double>(double x) { return x; }
+template <> __device__ __forceinline__ double to_acc<double, float>(float x) { return (double)x; }
+template <> __device__ __forceinline__ float to_acc<float, float>(float x) { return x; }
+template <> __device__ __forceinline__ float to_acc<float, double>(double x) { return (float)x; }
+
+template <typename T> __device__ __forceinline__ T from_f64(double x);
+template <> __device__ __forceinline__ double from_f64<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_f64<float>(double x) { return (float)x; }
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (implemented in the .hip files, called by eda_host.cpp).
+// All take the stream last and return hipError_t of the launch.
+// Shapes are validated by the caller; each launcher documents what it needs.
+// ---------------------------------------------------------------------------
+
+enum class DT : int { F64 = 0, F32 = 1 };
+
+// k_basic.hip ---------------------------------------------------------------
+// H_W, H_B from class-contiguous samples (counts given as offsets[k+1] on device).
+hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int64_t ldx,
+                          const int64_t* offsets, double* H_W, int64_t ldw, double* H_B,
+                          int64_t ldb, hipStream_t s);
+// P[:, col0:col0+cols] = cast(H) for rows < d, zero for d <= row < ldp.
+hipError_t launch_pack(int64_t d, int64_t ldp, int64_t cols, const double* H, int64_t ldh,
+                       void* P, DT pdt, int64_t col0, hipStream_t s);
+// flag[0] |= 1 if any entry of the d x cols matrix is NaN/Inf.
+hipError_t launch_nonfinite(int64_t d, int64_t cols, const double* H, int64_t ldh, int* flag,
+                            hipStream_t s);
+// Seeded Gaussian d x b block (SplitMix64 counter hash + Box-Muller), float64.
+hipError_t launch_randn(int64_t d, int64_t b, uint64_t seed, double* V, int64_t ldv,
+                        hipStream_t s);
+// Dst (rows x cols, type dt) = Src (rows x cols, float64 or same dt).
+hipError_t launch_copy2d(int64_t rows, int64_t cols, const void* src, DT sdt, int64_t lds,
+                         void* dst, DT ddt, int64_t ldd, hipStream_t s);
+// f[i] = phi-type weights for a core: see k_basic.hip.
+hipError_t launch_core_weights(int64_t n, const double* lam, double c, double shift, double* f,
+                               hipStream_t s);
+// dst[r + c*ldd] = alpha * (trans ? src[c + r*lds] : src[r + c*lds]), rows x cols of dst.
+hipError_t launch_copy_block(int64_t rows, int64_t cols, double alpha, const double* src,
+                             int64_t lds, bool trans, double* dst, int64_t ldd, hipStream_t s);
+// dst[i + i*ldd] = v[i] for i < cnt (diagonal only).
+hipError_t launch_set_diag(int64_t cnt, const double* v, double* dst, int64_t ldd, hipStream_t s);
+// Column 2-norms / sign fix / scaling helpers.
+hipError_t launch_sign_fix(int64_t d, int64_t t, double* X, int64_t ldx, hipStream_t s);
+hipError_t launch_fill(int64_t count, double value, double* dst, hipStream_t s);
+hipError_t launch_fill_i32(int64_t count, int value, int* dst, hipStream_t s);
+// Symmetrised copy T = (H[0:m,0:m] + H[0:m,0:m]^T)/2.
+hipError_t launch_symmetrize(int64_t m, const double* H, int64_t ldh, double* T, int64_t ldt,
+                             hipStream_t s);
+// Ritz diagnostics: theta (top `cnt` of w ascending, returned descending) and
+// residual estimates ||Bm * S[m-b:m, i]|| for those pairs.
+hipError_t launch_ritz_estimates(int64_t m, int64_t b, int64_t cnt, const double* w,
+                                 const double* S, int64_t lds, const double* Bm, int64_t ldbm,
+                                 double* out_theta, double* out_res, hipStream_t s);
+// Gather eigenvector columns in descending order, row-major: Sd[r*ldsd + i] = S[r + (m-1-i)*lds].
+hipError_t launch_gather_desc(int64_t m, int64_t cnt, const double* S, int64_t lds, double* Sd,
+                              int64_t ldsd, hipStream_t s);
+// flags[1] |= flags[0]; flags[0] = 0.
+hipError_t launch_flag_fold(int* flags, hipStream_t s);
+// R(:, i) = MY(:, i) - theta_i Y(:, i); res[i] = ||R(:, i)||.
+hipError_t launch_ritz_residual(int64_t d, int64_t t, const void* MY, const void* Y,
+                                int64_t ld, DT dt, const double* theta, double* res,
+                                hipStream_t s);
+// Restart coupling: Hn[kk + r, c] = sum_q Bm[r, q] * S[m - b + q, c] for c < kk.
+hipError_t launch_restart_coupling(int64_t m, int64_t b, int64_t kk, const double* Bm,
+                                   int64_t ldbm, const double* Sd, int64_t ldsd, double* Hn,
+                                   int64_t ldh, hipStream_t s);
+
+// k_tsmm.hip ----------------------------------------------------------------
+// Partial sums of A^T B over row chunks: part[(c*m + i)*nb + j], c < chunks.
+// Returns the number of chunks used through *chunks_out (computed from shape).
+int64_t tn_chunks(int64_t d, int64_t m, int64_t nb);
+hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT adt,
+                             int64_t lda, const void* B, DT bdt, int64_t ldb, double* part,
+                             int64_t chunks, const int* gate, hipStream_t s);
+// C_col[i + j*ldc] = beta*C_col + alpha*sum_c part  (if C_col != null)
+// Z_row[i*ldz + j] = zalpha*sum_c part              (if Z_row != null)
+hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const double* part,
+                                  double alpha, double beta, double* C_col, int64_t ldc,
+                                  double zalpha, double* Z_row, int64_t ldz, const int* gate,
+                                  hipStream_t s);
+// Out = alpha * V + A * Z, Z row-major (Z[i*ldz + j]) float64, m columns of A.
+hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
+                     const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
+                     int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
+                     hipStream_t s);
+
+// k_gemm.hip ----------------------------------------------------------------
+// C (m x n) = alpha * op(A) * diag(dk) * op(B) + beta * C, float64, col-major.
+// op(X) = X or X^T; dk may be null (identity).
+hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* dk, const double* B,
+                       int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s);
+// Gram partials: part[c][i][j] over lower-triangle tiles; finalised by launch_gram_reduce.
+int64_t gram_chunks(int64_t d, int64_t N);
+hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int64_t ldp,
+                               double* part, int64_t chunks, hipStream_t s);
+hipError_t launch_gram_reduce(int64_t N, int64_t chunks, const double* part, double* G,
+                              int64_t ldg, hipStream_t s);
+
+// k_chol.hip ----------------------------------------------------------------
+// Cholesky G = R^T R (b x b), outputs R^{-1} row-major (Rinv[i*ldri + j]) and,
+// if Rout != null, Rout = R * Rprev (or R when Rprev is null), col-major.
+// If hcol != null, sets *flag = 1 when some column kept less than `ratio` of
+// its norm through the projection (hcol: m x b projection coefficients).
+hipError_t launch_chol(int64_t b, const double* G, int64_t ldg, double* Rinv, int64_t ldri,
+                       const double* Rprev, int64_t ldrp, double* Rout, int64_t ldro,
+                       const double* hcol, int64_t m, int64_t ldhc, double ratio, int* flag,
+                       const int* gate, hipStream_t s);
+
+// Rank-revealing pivoted Cholesky of a Lanczos block (b <= 64); see k_chol.hip.
+hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
+                        int64_t ldhc, double tau, double ratio, double* Z, int64_t ldz, double* R,
+                        int64_t ldr, int* mask, int* flag, hipStream_t s);
+// Q[:, j] = seeded Gaussian for the columns with mask[j] != 0.
+hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
+                                    double* Q, int64_t ldq, hipStream_t s);
+
+// k_syev.hip ----------------------------------------------------------------
+// Batched symmetric eigensolver, one workgroup per matrix. For matrix q:
+//   A_q at A + q*strideA (lda), w_q at w + q*stridew, Z_q at Z + q*strideZ (ldz).
+// n_q = ns[q] (device int array) or n when ns is null.  Eigenvalues ascending;
+// eigenvectors are computed for the top nvec_q = min(nvec, n_q) eigenvalues
+// (nvec <= 0: all) and stored in columns n_q-nvec_q .. n_q-1 of Z_q.
+size_t syev_work_bytes(int64_t nmax);
+hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
+                       int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
+                       int64_t strideZ, int64_t nvec, double* work, hipStream_t s);
+
+}  // namespace eda

@@ -1,0 +1,390 @@
+// Elementwise and small helper kernels of libeda.
+#include "common.h"
+
+namespace eda {
+
+namespace {
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // Fixed-order reduction: wave butterfly, then wave 0 sums the wave partials in order.
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Scatter factors, Section 1, eqs. (1.1)-(1.2).  One thread per feature row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void scatter_kernel(int64_t d, int64_t n, int64_t k,
+                                                      const double* __restrict__ X, int64_t ldx,
+                                                      const int64_t* __restrict__ offs,
+                                                      double* __restrict__ HW, int64_t ldw,
+                                                      double* __restrict__ HB, int64_t ldb) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= d) return;
+  double total = 0.0;
+  for (int64_t j = 0; j < k; ++j) {
+    const int64_t c0 = offs[j], c1 = offs[j + 1];
+    double s = 0.0;
+    for (int64_t c = c0; c < c1; ++c) s += X[i + c * ldx];
+    total += s;
+    const double mj = s / (double)(c1 - c0);
+    for (int64_t c = c0; c < c1; ++c) HW[i + c * ldw] = X[i + c * ldx] - mj;
+    HB[i + j * ldb] = mj;
+  }
+  const double mu = total / (double)n;  // sample-weighted global centroid
+  for (int64_t j = 0; j < k; ++j) {
+    const double nj = (double)(offs[j + 1] - offs[j]);
+    HB[i + j * ldb] = sqrt(nj) * (HB[i + j * ldb] - mu);
+  }
+}
+
+template <typename TP>
+__global__ __launch_bounds__(256) void pack_kernel(int64_t d, int64_t ldp, const double* __restrict__ H,
+                                                   int64_t ldh, TP* __restrict__ P, int64_t col0) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= ldp) return;
+  const double v = (r < d) ? H[r + c * ldh] : 0.0;
+  P[r + (col0 + c) * ldp] = from_f64<TP>(v);
+}
+
+__global__ __launch_bounds__(256) void nonfinite_kernel(int64_t d, int64_t cols, const double* __restrict__ H,
+                                                        int64_t ldh, int* flag) {
+  const int64_t total = d * cols;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / d, r = e - c * d;
+    const double v = H[r + c * ldh];
+    bad |= !isfinite(v);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014) used as a counter hash.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void randn_kernel(int64_t d, int64_t b, uint64_t seed,
+                                                    double* __restrict__ V, int64_t ldv) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= d * b) return;
+  const int64_t c = e / d, r = e - c * d;
+  const uint64_t base = seed * 0xd1342543de82ef95ull;
+  const uint64_t z1 = splitmix64(base + 2ull * (uint64_t)e);
+  const uint64_t z2 = splitmix64(base + 2ull * (uint64_t)e + 1ull);
+  const double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;  // (0, 1]
+  const double u2 = (double)(z2 >> 11) * 0x1.0p-53;          // [0, 1)
+  V[r + c * ldv] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);  // Box-Muller
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void copy2d_kernel(int64_t rows, const TS* __restrict__ S, int64_t lds,
+                                                     TD* __restrict__ D, int64_t ldd) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= rows) return;
+  D[r + c * ldd] = from_f64<TD>(to_f64<TS>(S[r + c * lds]));
+}
+
+// Weights of a core G = V diag(f) V^T of the exponential exp(c H H^T)
+// scaled by e^{-shift}:  f(l) = e^{-shift} (e^{c l} - 1) / l,  f(0) = c e^{-shift}.
+__global__ __launch_bounds__(256) void core_weights_kernel(int64_t n, const double* __restrict__ lam,
+                                                           double c, double shift,
+                                                           double* __restrict__ f) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double l = lam[i];
+  const double cl = c * l;
+  double v;
+  if (fabs(l) < 1e-300) {
+    v = c * exp(-shift);
+  } else if (cl <= 1.0) {
+    v = exp(-shift) * expm1(cl) / l;
+  } else {
+    v = (exp(cl - shift) - exp(-shift)) / l;
+  }
+  f[i] = v;
+}
+
+// One workgroup per column: make the largest-magnitude entry positive
+// (ties: the smallest row index).
+__global__ __launch_bounds__(256) void sign_fix_kernel(int64_t d, double* __restrict__ X, int64_t ldx) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  double* x = X + blockIdx.x * ldx;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
+    const double a = fabs(x[r]);
+    if (a > best) { best = a; bi = r; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double a = sv[threadIdx.x + s];
+      const int64_t ai = si[threadIdx.x + s];
+      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
+        sv[threadIdx.x] = a;
+        si[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  const double sg = (x[si[0]] < 0.0) ? -1.0 : 1.0;
+  __syncthreads();
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) x[r] *= sg;
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(int64_t count, double v, double* __restrict__ dst) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int64_t count, int v, int* __restrict__ dst) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = v;
+}
+
+__global__ __launch_bounds__(256) void symmetrize_kernel(int64_t m, const double* __restrict__ H, int64_t ldh,
+                                                         double* __restrict__ T, int64_t ldt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t c = e / m, r = e - c * m;
+  T[r + c * ldt] = 0.5 * (H[r + c * ldh] + H[c + r * ldh]);
+}
+
+__global__ __launch_bounds__(64) void ritz_estimates_kernel(int64_t m, int64_t b, int64_t cnt,
+                                                            const double* __restrict__ w,
+                                                            const double* __restrict__ S, int64_t lds,
+                                                            const double* __restrict__ Bm, int64_t ldbm,
+                                                            double* __restrict__ th,
+                                                            double* __restrict__ res) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t col = m - 1 - i;
+  double acc = 0.0;
+  for (int64_t r = 0; r < b; ++r) {
+    double s = 0.0;
+    for (int64_t q = 0; q < b; ++q) s += Bm[r + q * ldbm] * S[(m - b + q) + col * lds];
+    acc += s * s;
+  }
+  th[i] = w[col];
+  res[i] = sqrt(acc);
+}
+
+__global__ __launch_bounds__(256) void gather_desc_kernel(int64_t m, int64_t cnt, const double* __restrict__ S,
+                                                          int64_t lds, double* __restrict__ Sd,
+                                                          int64_t ldsd) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m * cnt) return;
+  const int64_t i = e / m, r = e - i * m;
+  Sd[r * ldsd + i] = S[r + (m - 1 - i) * lds];
+}
+
+__global__ void flag_fold_kernel(int* flags) {
+  if (threadIdx.x == 0) {
+    flags[1] |= flags[0];
+    flags[0] = 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ritz_residual_kernel(int64_t d, const T* __restrict__ MY,
+                                                            const T* __restrict__ Y, int64_t ld,
+                                                            const double* __restrict__ theta,
+                                                            double* __restrict__ res) {
+  __shared__ double red[8];
+  const int64_t c = blockIdx.x;
+  const double th = theta[c];
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
+    const double v = to_f64<T>(MY[r + c * ld]) - th * to_f64<T>(Y[r + c * ld]);
+    acc += v * v;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) res[c] = sqrt(acc);
+}
+
+__global__ __launch_bounds__(256) void restart_coupling_kernel(int64_t m, int64_t b, int64_t kk,
+                                                               const double* __restrict__ Bm, int64_t ldbm,
+                                                               const double* __restrict__ Sd, int64_t ldsd,
+                                                               double* __restrict__ Hn, int64_t ldh) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= b * kk) return;
+  const int64_t c = e / b, r = e - c * b;
+  double s = 0.0;
+  for (int64_t q = 0; q < b; ++q) s += Bm[r + q * ldbm] * Sd[(m - b + q) * ldsd + c];
+  Hn[(kk + r) + c * ldh] = s;
+}
+
+__global__ __launch_bounds__(256) void copy_block_kernel(int64_t rows, int64_t cols, double alpha,
+                                                         const double* __restrict__ S, int64_t lds,
+                                                         bool trans, double* __restrict__ D,
+                                                         int64_t ldd) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t c = e / rows, r = e - c * rows;
+  D[r + c * ldd] = alpha * (trans ? S[c + r * lds] : S[r + c * lds]);
+}
+
+__global__ __launch_bounds__(256) void set_diag_kernel(int64_t cnt, const double* __restrict__ v,
+                                                       double* __restrict__ D, int64_t ldd) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < cnt) D[i + i * ldd] = v[i];
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_copy_block(int64_t rows, int64_t cols, double alpha, const double* src,
+                             int64_t lds, bool trans, double* dst, int64_t ldd, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_block_kernel, dim3(nblk(rows * cols)), dim3(256), 0, s, rows, cols,
+                     alpha, src, lds, trans, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_diag(int64_t cnt, const double* v, double* dst, int64_t ldd, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(set_diag_kernel, dim3(nblk(cnt)), dim3(256), 0, s, cnt, v, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int64_t ldx,
+                          const int64_t* offsets, double* H_W, int64_t ldw, double* H_B,
+                          int64_t ldb, hipStream_t s) {
+  hipLaunchKernelGGL(scatter_kernel, dim3(nblk(d)), dim3(256), 0, s, d, n, k, X, ldx, offsets,
+                     H_W, ldw, H_B, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int64_t d, int64_t ldp, int64_t cols, const double* H, int64_t ldh,
+                       void* P, DT pdt, int64_t col0, hipStream_t s) {
+  if (cols <= 0) return hipSuccess;
+  dim3 g(nblk(ldp), (unsigned)cols);
+  if (pdt == DT::F64)
+    hipLaunchKernelGGL(pack_kernel<double>, g, dim3(256), 0, s, d, ldp, H, ldh, (double*)P, col0);
+  else
+    hipLaunchKernelGGL(pack_kernel<float>, g, dim3(256), 0, s, d, ldp, H, ldh, (float*)P, col0);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(int64_t d, int64_t cols, const double* H, int64_t ldh, int* flag,
+                            hipStream_t s) {
+  int64_t total = d * cols;
+  unsigned g = (unsigned)std::min<int64_t>(2048, (total + 255) / 256);
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(g), dim3(256), 0, s, d, cols, H, ldh, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_randn(int64_t d, int64_t b, uint64_t seed, double* V, int64_t ldv,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(randn_kernel, dim3(nblk(d * b)), dim3(256), 0, s, d, b, seed, V, ldv);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2d(int64_t rows, int64_t cols, const void* src, DT sdt, int64_t lds,
+                         void* dst, DT ddt, int64_t ldd, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  dim3 g(nblk(rows), (unsigned)cols);
+  if (sdt == DT::F64 && ddt == DT::F64)
+    hipLaunchKernelGGL((copy2d_kernel<double, double>), g, dim3(256), 0, s, rows,
+                       (const double*)src, lds, (double*)dst, ldd);
+  else if (sdt == DT::F64 && ddt == DT::F32)
+    hipLaunchKernelGGL((copy2d_kernel<double, float>), g, dim3(256), 0, s, rows,
+                       (const double*)src, lds, (float*)dst, ldd);
+  else if (sdt == DT::F32 && ddt == DT::F64)
+    hipLaunchKernelGGL((copy2d_kernel<float, double>), g, dim3(256), 0, s, rows,
+                       (const float*)src, lds, (double*)dst, ldd);
+  else
+    hipLaunchKernelGGL((copy2d_kernel<float, float>), g, dim3(256), 0, s, rows,
+                       (const float*)src, lds, (float*)dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_weights(int64_t n, const double* lam, double c, double shift, double* f,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(core_weights_kernel, dim3(nblk(n)), dim3(256), 0, s, n, lam, c, shift, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_sign_fix(int64_t d, int64_t t, double* X, int64_t ldx, hipStream_t s) {
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)t), dim3(256), 0, s, d, X, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t count, double value, double* dst, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(count)), dim3(256), 0, s, count, value, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int64_t count, int value, int* dst, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(count)), dim3(256), 0, s, count, value, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(int64_t m, const double* H, int64_t ldh, double* T, int64_t ldt,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(m * m)), dim3(256), 0, s, m, H, ldh, T, ldt);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_estimates(int64_t m, int64_t b, int64_t cnt, const double* w,
+                                 const double* S, int64_t lds, const double* Bm, int64_t ldbm,
+                                 double* out_theta, double* out_res, hipStream_t s) {
+  hipLaunchKernelGGL(ritz_estimates_kernel, dim3(nblk(cnt, 64)), dim3(64), 0, s, m, b, cnt, w, S,
+                     lds, Bm, ldbm, out_theta, out_res);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_desc(int64_t m, int64_t cnt, const double* S, int64_t lds, double* Sd,
+                              int64_t ldsd, hipStream_t s) {
+  hipLaunchKernelGGL(gather_desc_kernel, dim3(nblk(m * cnt)), dim3(256), 0, s, m, cnt, S, lds,
+                     Sd, ldsd);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_fold(int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(flag_fold_kernel, dim3(1), dim3(64), 0, s, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_residual(int64_t d, int64_t t, const void* MY, const void* Y,
+                                int64_t ld, DT dt, const double* theta, double* res,
+                                hipStream_t s) {
+  if (dt == DT::F64)
+    hipLaunchKernelGGL(ritz_residual_kernel<double>, dim3((unsigned)t), dim3(256), 0, s, d,
+                       (const double*)MY, (const double*)Y, ld, theta, res);
+  else
+    hipLaunchKernelGGL(ritz_residual_kernel<float>, dim3((unsigned)t), dim3(256), 0, s, d,
+                       (const float*)MY, (const float*)Y, ld, theta, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_restart_coupling(int64_t m, int64_t b, int64_t kk, const double* Bm,
+                                   int64_t ldbm, const double* Sd, int64_t ldsd, double* Hn,
+                                   int64_t ldh, hipStream_t s) {
+  hipLaunchKernelGGL(restart_coupling_kernel, dim3(nblk(b * kk)), dim3(256), 0, s, m, b, kk, Bm,
+                     ldbm, Sd, ldsd, Hn, ldh);
+  return hipGetLastError();
+}
+
+}  // namespace eda

@@ -1,0 +1,284 @@
+// Cholesky factorisation of a small Gram matrix for Cholesky QR:
+//   G = W^T W = R^T R,  W <- W R^{-1}.
+// One workgroup, the factor kept in LDS (b <= 128).  Outputs R^{-1} in the
+// row-major layout read by the nn kernel, and optionally R * Rprev (the
+// combined triangular factor of two passes) in column-major order.
+//
+// Breakdown handling: a pivot that is not positive (the block lost rank in
+// floating point) is clamped to a tiny positive value so the division stays
+// finite, and *flag is raised; the caller then re-orthogonalises the block.
+// With hcol given, *flag is also raised when a column kept less than `ratio`
+// of its norm through the preceding projection, the case in which classical
+// Gram-Schmidt run twice no longer guarantees orthogonality.
+#include "common.h"
+
+namespace eda {
+
+namespace {
+
+constexpr int CH_MAX = 128;
+
+__global__ __launch_bounds__(256) void chol_kernel(int b, const double* __restrict__ G, int64_t ldg,
+                                                   double* __restrict__ Rinv, int64_t ldri,
+                                                   const double* __restrict__ Rprev, int64_t ldrp,
+                                                   double* __restrict__ Rout, int64_t ldro,
+                                                   const double* __restrict__ hcol, int64_t m,
+                                                   int64_t ldhc, double ratio, int* flag,
+                                                   const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  __shared__ double L[CH_MAX * (CH_MAX + 1)];
+  __shared__ double diag0[CH_MAX];
+  __shared__ int sflag;
+  const int ld = CH_MAX + 1;
+  const int tid = threadIdx.x;
+  if (tid == 0) sflag = 0;
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int c = e / b, r = e - c * b;
+    if (r >= c) L[r + c * ld] = G[r + c * ldg];
+  }
+  __syncthreads();
+  for (int e = tid; e < b; e += blockDim.x) diag0[e] = L[e + e * ld];
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    if (tid == 0) {
+      double p = L[j + j * ld];
+      const double floor_ = 1e-28 * fabs(diag0[j]) + 1e-300;
+      if (!(p > floor_)) {  // also catches NaN
+        p = floor_;
+        sflag = 1;
+      }
+      L[j + j * ld] = sqrt(p);
+    }
+    __syncthreads();
+    const double piv = L[j + j * ld];
+    for (int i = j + 1 + tid; i < b; i += blockDim.x) L[i + j * ld] /= piv;
+    __syncthreads();
+    const int rem = b - j - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int c = j + 1 + e / rem, r = j + 1 + e % rem;
+      if (r >= c) L[r + c * ld] -= L[r + j * ld] * L[c + j * ld];
+    }
+    __syncthreads();
+  }
+  // R = L^T.  Column c of X = R^{-1}: back substitution R X = I, one thread per column.
+  for (int c = tid; c < b; c += blockDim.x) {
+    for (int i = b - 1; i >= 0; --i) {
+      double x;
+      if (i > c) {
+        x = 0.0;
+      } else {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int q = i + 1; q <= c; ++q) s -= L[q + i * ld] * Rinv[(int64_t)q * ldri + c];
+        x = s / L[i + i * ld];
+      }
+      Rinv[(int64_t)i * ldri + c] = x;
+    }
+  }
+  if (Rout != nullptr) {
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int c = e / b, r = e - c * b;
+      double s = 0.0;
+      if (Rprev == nullptr) {
+        s = (r <= c) ? L[c + r * ld] : 0.0;
+      } else {
+        // (R * Rprev)[r, c] = sum_{q >= r} R[r, q] Rprev[q, c]  (R upper, Rprev general)
+        for (int q = r; q < b; ++q) s += L[q + r * ld] * Rprev[q + c * ldrp];
+      }
+      Rout[r + c * ldro] = s;
+    }
+  }
+  if (hcol != nullptr) {
+    for (int c = tid; c < b; c += blockDim.x) {
+      double h2 = 0.0;
+      for (int64_t r = 0; r < m; ++r) {
+        const double v = hcol[r + c * ldhc];
+        h2 += v * v;
+      }
+      const double rc = L[c + c * ld];
+      if (!(rc >= ratio * sqrt(h2 + rc * rc))) atomicOr(&sflag, 1);
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && flag != nullptr && sflag) *flag = 1;
+}
+
+// Rank-revealing (diagonally pivoted) Cholesky of a Lanczos block's Gram
+// matrix G = W^T W, b <= 64, W already projected against the basis with
+// coefficients hcol (m x b).  Columns whose remaining pivot is below
+// (tau * scale)^2, scale^2 = max_j (||h_j||^2 + G_jj) being the largest
+// squared column norm before the projection, are deflated: the Krylov space
+// has become invariant along them.  With r kept columns and permutation p:
+//   W P = [Q_1 Q_2] [[R11 R12], [0, ~0]],   Q_1 = W P[:, :r] R11^{-1}.
+// Outputs: Z (row-major, W Z = [Q_1, 0]), R (col-major, W = [Q_1 Q_2] R with
+// rows >= r zero), mask[j] = 1 for deflated output columns j >= r, and
+// *flag = 1 if a column was deflated or kept less than `ratio` of its norm.
+__global__ __launch_bounds__(64) void pchol_kernel(int b, const double* __restrict__ G, int64_t ldg,
+                                                   const double* __restrict__ hcol, int64_t m,
+                                                   int64_t ldhc, double tau, double ratio,
+                                                   double* __restrict__ Z, int64_t ldz,
+                                                   double* __restrict__ R, int64_t ldr,
+                                                   int* __restrict__ mask, int* flag) {
+  constexpr int PB = 64;
+  __shared__ double A[PB * (PB + 1)];
+  __shared__ double nrm0[PB];
+  __shared__ int perm[PB];
+  __shared__ int s_rank, s_q, s_flag;
+  const int ld = PB + 1;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int c = e / b, r = e - c * b;
+    A[r + c * ld] = G[r + c * ldg];
+  }
+  if (tid < b) {
+    double h2 = 0.0;
+    if (hcol != nullptr)
+      for (int64_t r = 0; r < m; ++r) {
+        const double v = hcol[r + tid * ldhc];
+        h2 += v * v;
+      }
+    nrm0[tid] = G[tid + tid * ldg] + h2;
+    perm[tid] = tid;
+  }
+  if (tid == 0) {
+    s_rank = b;
+    s_flag = 0;
+  }
+  __syncthreads();
+  double scale2 = 0.0;
+  for (int j = 0; j < b; ++j) scale2 = fmax(scale2, nrm0[j]);
+  const double thr = tau * tau * scale2;
+  for (int j = 0; j < b; ++j) {
+    if (tid == 0) {
+      int q = j;
+      double best = A[j + j * ld];
+      for (int i = j + 1; i < b; ++i)
+        if (A[i + i * ld] > best) {
+          best = A[i + i * ld];
+          q = i;
+        }
+      s_q = q;
+      if (!(best > thr)) {
+        s_rank = j;  // every remaining pivot is negligible: deflate them
+      } else {
+        const int t = perm[j];
+        perm[j] = perm[q];
+        perm[q] = t;
+      }
+    }
+    __syncthreads();
+    if (s_rank == j) break;
+    const int q = s_q;
+    if (q != j) {
+      if (tid < b) {  // swap rows j and q
+        const double t = A[j + tid * ld];
+        A[j + tid * ld] = A[q + tid * ld];
+        A[q + tid * ld] = t;
+      }
+      __syncthreads();
+      if (tid < b) {  // swap columns j and q
+        const double t = A[tid + j * ld];
+        A[tid + j * ld] = A[tid + q * ld];
+        A[tid + q * ld] = t;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) A[j + j * ld] = sqrt(A[j + j * ld]);
+    __syncthreads();
+    if (tid > j && tid < b) A[tid + j * ld] /= A[j + j * ld];
+    __syncthreads();
+    // update the whole (symmetric) trailing block: later pivot swaps read
+    // both of its triangles
+    const int rem = b - j - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int c = j + 1 + e / rem, r = j + 1 + e % rem;
+      A[r + c * ld] -= A[r + j * ld] * A[c + j * ld];
+    }
+    __syncthreads();
+  }
+  const int rk = s_rank;
+  // Z: zero, then R11^{-1} scattered to the original row positions.
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int i = e / b, c = e - i * b;
+    Z[(int64_t)i * ldz + c] = 0.0;
+  }
+  __syncthreads();
+  // R11^{-1} (upper, R11[i, q] = L[q, i]) by back substitution, one thread per
+  // column c < rk, written straight into the rows perm[i] of Z.
+  if (tid < rk) {
+    const int c = tid;
+    for (int i = c; i >= 0; --i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int q = i + 1; q <= c; ++q) s -= A[q + i * ld] * Z[(int64_t)perm[q] * ldz + c];
+      Z[(int64_t)perm[i] * ldz + c] = s / A[i + i * ld];
+    }
+  }
+  // R[j, perm[i]] = L[i, j] for j < rk, i >= j; zero elsewhere.
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int ci = e / b, j = e - ci * b;  // output column ci (original index), row j
+    double v = 0.0;
+    if (j < rk) {
+      int i = 0;
+      while (perm[i] != ci) ++i;
+      if (i >= j) v = A[i + j * ld];
+    }
+    R[j + (int64_t)ci * ldr] = v;
+  }
+  if (tid < b) {
+    mask[tid] = (tid >= rk) ? 1 : 0;
+    if (tid < rk && !(A[tid + tid * ld] >= ratio * sqrt(nrm0[perm[tid]]))) atomicOr(&s_flag, 1);
+  }
+  __syncthreads();
+  if (tid == 0 && flag != nullptr && (s_flag || rk < b)) *flag = 1;
+}
+
+// Q[:, j] = seeded Gaussian for every column j with mask[j] != 0.
+__global__ __launch_bounds__(256) void fill_masked_randn_kernel(int64_t d, int64_t b,
+                                                                const int* __restrict__ mask,
+                                                                uint64_t seed, double* Q,
+                                                                int64_t ldq) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= d * b) return;
+  const int64_t c = e / d, r = e - c * d;
+  if (mask[c] == 0) return;
+  uint64_t z1 = (seed ^ 0x2545f4914f6cdd1dull) + 2ull * (uint64_t)e * 0x9e3779b97f4a7c15ull;
+  uint64_t z2 = z1 + 0x9e3779b97f4a7c15ull;
+  z1 = (z1 ^ (z1 >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z1 = (z1 ^ (z1 >> 27)) * 0x94d049bb133111ebull;
+  z1 ^= z1 >> 31;
+  z2 = (z2 ^ (z2 >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z2 = (z2 ^ (z2 >> 27)) * 0x94d049bb133111ebull;
+  z2 ^= z2 >> 31;
+  const double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
+  Q[r + c * ldq] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+}
+
+}  // namespace
+
+hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
+                        int64_t ldhc, double tau, double ratio, double* Z, int64_t ldz, double* R,
+                        int64_t ldr, int* mask, int* flag, hipStream_t s) {
+  if (b < 1 || b > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pchol_kernel, dim3(1), dim3(64), 0, s, (int)b, G, ldg, hcol, m, ldhc, tau,
+                     ratio, Z, ldz, R, ldr, mask, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
+                                    double* Q, int64_t ldq, hipStream_t s) {
+  hipLaunchKernelGGL(fill_masked_randn_kernel, dim3((unsigned)((d * b + 255) / 256)), dim3(256), 0,
+                     s, d, b, mask, seed, Q, ldq);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol(int64_t b, const double* G, int64_t ldg, double* Rinv, int64_t ldri,
+                       const double* Rprev, int64_t ldrp, double* Rout, int64_t ldro,
+                       const double* hcol, int64_t m, int64_t ldhc, double ratio, int* flag,
+                       const int* gate, hipStream_t s) {
+  if (b < 1 || b > CH_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, s, (int)b, G, ldg, Rinv, ldri, Rprev,
+                     ldrp, Rout, ldro, hcol, m, ldhc, ratio, flag, gate);
+  return hipGetLastError();
+}
+
+}  // namespace eda

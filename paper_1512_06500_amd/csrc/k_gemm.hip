@@ -1,0 +1,217 @@
+// Small dense FP64 products: general GEMM for the cores (n x n and n x k
+// factors of the exponentials) and the Gram matrix P^T P of the scatter
+// factors.  Register-tiled FMA kernels: 64 x 64 output tiles, 256 threads,
+// 4 x 4 outputs per thread, K staged through LDS in slices of 16.
+#include "common.h"
+
+namespace eda {
+
+namespace {
+
+constexpr int GT = 64;   // tile edge
+constexpr int GK = 16;   // K slice
+
+// C = alpha op(A) diag(dk) op(B) + beta C
+__global__ __launch_bounds__(256) void gemm_kernel(bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                                                   double alpha, const double* __restrict__ A,
+                                                   int64_t lda, const double* __restrict__ dk,
+                                                   const double* __restrict__ B, int64_t ldb,
+                                                   double beta, double* __restrict__ C,
+                                                   int64_t ldc) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t i0 = blockIdx.x * (int64_t)GT, j0 = blockIdx.y * (int64_t)GT;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+
+  for (int64_t k0 = 0; k0 < k; k0 += GK) {
+    // op(A) tile: rows i0..i0+63, cols k0..k0+15 -> As[kk][ii]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      int ii, kk;
+      if (!ta) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+      const int64_t gi = i0 + ii, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < m && gk < k) {
+        v = ta ? A[gk + gi * lda] : A[gi + gk * lda];
+        if (dk != nullptr) v *= dk[gk];
+      }
+      As[kk][ii] = v;
+    }
+    // op(B) tile: rows k0..k0+15, cols j0..j0+63 -> Bs[kk][jj]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      int jj, kk;
+      if (!tb) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
+      const int64_t gj = j0 + jj, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < n && gk < k) v = tb ? B[gj + gk * ldb] : B[gk + gj * ldb];
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = As[kk][tx + 16 * q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = Bs[kk][ty + 16 * q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int64_t gi = i0 + tx + 16 * p;
+    if (gi >= m) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t gj = j0 + ty + 16 * q;
+      if (gj >= n) continue;
+      double* cp = C + gi + gj * ldc;
+      *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[p][q];
+    }
+  }
+}
+
+// Gram partials over one row chunk for one lower-triangle tile (ti >= tj).
+template <typename TP>
+__global__ __launch_bounds__(256) void gram_partial_kernel(int64_t d, int64_t N,
+                                                           const TP* __restrict__ P, int64_t ldp,
+                                                           double* __restrict__ part,
+                                                           int64_t rows_per_chunk) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  // blockIdx.x enumerates lower-triangle tiles, blockIdx.y row chunks
+  int64_t t = blockIdx.x, ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int64_t tj = t - ti * (ti + 1) / 2;
+  const int64_t i0 = ti * GT, j0 = tj * GT;
+  const int64_t c = blockIdx.y;
+  const int64_t r0 = c * rows_per_chunk;
+  const int64_t r1 = (r0 + rows_per_chunk < d) ? r0 + rows_per_chunk : d;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+
+  for (int64_t k0 = r0; k0 < r1; k0 += GK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int kk = e & 15, ii = e >> 4;
+      const int64_t gk = k0 + kk;
+      const int64_t gi = i0 + ii, gj = j0 + ii;
+      As[kk][ii] = (gi < N && gk < r1) ? to_f64<TP>(P[gk + gi * ldp]) : 0.0;
+      Bs[kk][ii] = (gj < N && gk < r1) ? to_f64<TP>(P[gk + gj * ldp]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = As[kk][tx + 16 * q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = Bs[kk][ty + 16 * q];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+    }
+    __syncthreads();
+  }
+  double* pc = part + c * N * N;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int64_t gi = i0 + tx + 16 * p;
+    if (gi >= N) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t gj = j0 + ty + 16 * q;
+      if (gj >= N) continue;
+      pc[gi + gj * N] = acc[p][q];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t N, int64_t chunks,
+                                                          const double* __restrict__ part,
+                                                          double* __restrict__ G, int64_t ldg) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  const int64_t j = e / N, i = e - j * N;
+  // read from the lower-triangle tile that holds (i, j) or its mirror
+  const bool lower = (i / GT) >= (j / GT);
+  const int64_t src = lower ? (i + j * N) : (j + i * N);
+  double s = 0.0;
+  for (int64_t c = 0; c < chunks; ++c) s += part[c * N * N + src];
+  G[i + j * ldg] = s;
+}
+
+void gram_geometry(int64_t d, int64_t N, int64_t* chunks, int64_t* rows) {
+  const int64_t T = (N + GT - 1) / GT;
+  const int64_t tiles = T * (T + 1) / 2;
+  int64_t c = (1024 + tiles - 1) / tiles;
+  const int64_t cmax = std::max<int64_t>(1, (d + 255) / 256);
+  c = std::max<int64_t>(1, std::min(c, cmax));
+  int64_t rp = (d + c - 1) / c;
+  rp = ((rp + GK - 1) / GK) * GK;
+  *rows = rp;
+  *chunks = (d + rp - 1) / rp;
+}
+
+}  // namespace
+
+hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* dk, const double* B,
+                       int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  dim3 g((unsigned)((m + GT - 1) / GT), (unsigned)((n + GT - 1) / GT));
+  hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, dk, B, ldb,
+                     beta, C, ldc);
+  return hipGetLastError();
+}
+
+int64_t gram_chunks(int64_t d, int64_t N) {
+  int64_t c, r;
+  gram_geometry(d, N, &c, &r);
+  return c;
+}
+
+hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int64_t ldp,
+                               double* part, int64_t chunks, hipStream_t s) {
+  int64_t c, rows;
+  gram_geometry(d, N, &c, &rows);
+  if (c != chunks) return hipErrorInvalidValue;
+  const int64_t T = (N + GT - 1) / GT;
+  dim3 g((unsigned)(T * (T + 1) / 2), (unsigned)chunks);
+  if (pdt == DT::F64)
+    hipLaunchKernelGGL(gram_partial_kernel<double>, g, dim3(256), 0, s, d, N, (const double*)P,
+                       ldp, part, rows);
+  else
+    hipLaunchKernelGGL(gram_partial_kernel<float>, g, dim3(256), 0, s, d, N, (const float*)P, ldp,
+                       part, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(int64_t N, int64_t chunks, const double* part, double* G,
+                              int64_t ldg, hipStream_t s) {
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, N,
+                     chunks, part, G, ldg);
+  return hipGetLastError();
+}
+
+}  // namespace eda

@@ -1,0 +1,121 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and rejects invalid arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1512_06500_amd as eda
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eda.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(eda_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return eda.load_library()
+
+
+@pytest.fixture()
+def handle(lib):
+    h = ctypes.c_void_p()
+    st = lib.eda_create(ctypes.byref(h), None)
+    assert st in (eda.EDA_OK, eda.EDA_ERR_HIP)
+    assert h.value is not None
+    yield h
+    lib.eda_destroy(h)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    declared = header_functions()
+    assert set(declared) == set(eda.EXPORTED_SYMBOLS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_covers_every_status(lib):
+    for s in range(8):
+        msg = lib.eda_strerror(s).decode()
+        assert msg and msg != "unknown status"
+    assert lib.eda_strerror(99).decode() == "unknown status"
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("d,n,k,ldw,ldb,storage", [
+    (1, 10, 2, 1, 1, 0),      # d < 2
+    (100, 10, 1, 100, 100, 0),  # k < 2
+    (100, 3, 4, 100, 100, 0),   # n < k
+    (100, 10, 3, 99, 100, 0),   # ldw < d
+    (100, 10, 3, 100, 50, 0),   # ldb < d
+    (100, 10, 3, 100, 100, 9),  # unknown storage
+    (100, 10, 3, 100, 100, 2),  # bf16 storage not accepted by prepare
+    (4000, 2040, 10, 4000, 4000, 0),  # n + k > 2048
+])
+def test_prepare_rejects_bad_arguments(lib, handle, d, n, k, ldw, ldb, storage):
+    st = lib.eda_prepare(handle, d, n, k, FAKE, ldw, FAKE, ldb, storage)
+    assert st == eda.EDA_ERR_ARG
+    assert lib.eda_last_error(handle).decode()
+
+
+def test_prepare_null_factor(lib, handle):
+    assert lib.eda_prepare(handle, 100, 10, 3, None, 100, FAKE, 100, 0) == eda.EDA_ERR_ARG
+
+
+def test_calls_before_prepare_report_state(lib, handle):
+    ls = ctypes.c_double()
+    assert lib.eda_expmv(handle, 0, -1.0, 1, FAKE, 10, FAKE, 10, 0, ctypes.byref(ls)) == eda.EDA_ERR_STATE
+    assert lib.eda_opmv(handle, 0, 1, FAKE, 10, FAKE, 10, 0, ctypes.byref(ls)) == eda.EDA_ERR_STATE
+    assert lib.eda_gram(handle, FAKE, 10) == eda.EDA_ERR_STATE
+    o = eda.SolveOpts()
+    buf = (ctypes.c_double * 4)()
+    info = eda.Info()
+    assert lib.eda_solve(handle, 2, 1e-8, ctypes.byref(o), buf, buf, FAKE, 10, buf,
+                         ctypes.byref(info)) == eda.EDA_ERR_STATE
+
+
+def test_expmv_rejects_bad_which_and_c(lib, handle):
+    ls = ctypes.c_double()
+    assert lib.eda_expmv(handle, 5, -1.0, 1, FAKE, 10, FAKE, 10, 0, ctypes.byref(ls)) == eda.EDA_ERR_ARG
+    assert lib.eda_expmv(handle, 0, float("nan"), 1, FAKE, 10, FAKE, 10, 0,
+                         ctypes.byref(ls)) == eda.EDA_ERR_ARG
+    assert lib.eda_opmv(handle, 7, 1, FAKE, 10, FAKE, 10, 0, ctypes.byref(ls)) == eda.EDA_ERR_ARG
+
+
+@pytest.mark.parametrize("n,lda,ldz", [(0, 1, 1), (3000, 3000, 3000), (10, 9, 10), (10, 10, 9)])
+def test_syev_rejects_bad_arguments(lib, handle, n, lda, ldz):
+    assert lib.eda_syev(handle, n, FAKE, lda, FAKE, FAKE, ldz) == eda.EDA_ERR_ARG
+
+
+def test_scatter_rejects_bad_counts(lib, handle):
+    counts = (ctypes.c_int64 * 3)(2, 0, 3)
+    assert lib.eda_scatter_factors(handle, 10, 5, 3, FAKE, 10, counts, FAKE, 10, FAKE,
+                                   10) == eda.EDA_ERR_ARG
+    counts = (ctypes.c_int64 * 3)(2, 2, 2)  # sums to 6, not 5
+    assert lib.eda_scatter_factors(handle, 10, 5, 3, FAKE, 10, counts, FAKE, 10, FAKE,
+                                   10) == eda.EDA_ERR_ARG
+    counts = (ctypes.c_int64 * 2)(2, 3)
+    assert lib.eda_scatter_factors(handle, 10, 5, 2, FAKE, 9, counts, FAKE, 10, FAKE,
+                                   10) == eda.EDA_ERR_ARG
+
+
+def test_null_handle(lib):
+    assert lib.eda_prepare(None, 10, 4, 2, FAKE, 10, FAKE, 10, 0) == eda.EDA_ERR_ARG
+    assert lib.eda_create(None, None) == eda.EDA_ERR_ARG
+    lib.eda_destroy(None)  # no-op
+
+
+def test_no_cpu_fallback_without_library(monkeypatch, tmp_path):
+    """The product path fails loudly when the HIP library is missing."""
+    monkeypatch.setattr(eda, "_lib", None)
+    monkeypatch.setattr(eda, "library_path", lambda: str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        eda.load_library()

@@ -1,0 +1,347 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (float64 path):
+* exponential products: ||e^s Out - E V||_F <= 1e-13 ||E||_2 ||V||_F, where E
+  is the dense exponential of the oracle -- a few hundred ulps of the largest
+  term, the rounding of two streamed passes of length d plus the small core;
+* Ritz values: relative error <= max(1e-10, 50 u lam_1 / lam_i);
+* subspace: sin angle(X, X_oracle) <= max(1e-8, 50 u lam_1 / (lam_t - lam_t+1));
+* eigensolver: |w - w_ref| <= 1e-13 ||A||, ||A Z - Z diag(w)|| <= 1e-12 ||A||,
+  ||Z^T Z - I|| <= 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    _t.cuda.set_device(0)
+    return _t
+
+
+@pytest.fixture(scope="module")
+def eda(torch):
+    import paper_1512_06500_amd as m
+    m.load_library()
+    return m
+
+
+def dev(torch, a):
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_op_err(out, ref, E_norm, V):
+    return np.linalg.norm(out - ref) / (E_norm * np.linalg.norm(V))
+
+
+class Case:
+    def __init__(self, name, X, counts, t):
+        self.name, self.X, self.counts, self.t = name, X, np.asarray(counts), t
+        self.H_W, self.H_B = O.scatter_factors(X, counts)
+        self.d = X.shape[0]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    p = datagen.config("C1")
+    return Case("C1", p.X, p.counts, p.t)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    p = datagen.config("C2")
+    return Case("C2", p.X, p.counts, p.t)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    counts = [2, 3, 4, 1, 5]
+    X = datagen.make_samples(333, counts, 12, seed=21)
+    return Case("ragged", X, counts, 4)
+
+
+def prepared(torch, eda, case, storage="f64"):
+    h = eda.Handle()
+    Xd = dev(torch, case.X)
+    H_W, H_B = h.scatter_factors(Xd, case.counts.tolist())
+    h.prepare(H_W, H_B, storage=storage)
+    return h, H_W, H_B
+
+
+# ---------------------------------------------------------------------------
+# a1 / a2: scatter factors, factor ingest and Gram
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cname", ["c1", "ragged"])
+def test_scatter_factors(torch, eda, cname, request):
+    case = request.getfixturevalue(cname)
+    log(f"scatter factors {case.name} d={case.d} counts={case.counts.tolist()}")
+    h, H_W, H_B = prepared(torch, eda, case)
+    torch.cuda.synchronize()
+    assert np.abs(host(H_W) - case.H_W).max() <= 1e-15 * 4
+    assert np.abs(host(H_B) - case.H_B).max() <= 1e-14
+    h.close()
+
+
+@pytest.mark.parametrize("cname", ["c1", "ragged", "c2"])
+def test_gram(torch, eda, cname, request):
+    case = request.getfixturevalue(cname)
+    log(f"gram {case.name}")
+    h, _, _ = prepared(torch, eda, case)
+    G = host(h.gram())
+    P = np.concatenate([case.H_W, case.H_B], axis=1)
+    Gr = P.T @ P
+    assert np.array_equal(G, G.T), "Gram must be exactly symmetric"
+    assert np.linalg.norm(G - Gr) <= 1e-14 * np.linalg.norm(Gr)
+    h.close()
+
+
+# ---------------------------------------------------------------------------
+# a3: symmetric eigensolver
+# ---------------------------------------------------------------------------
+
+def check_eig(A, w, Z, tol_res=1e-12):
+    nrm = max(np.linalg.norm(A, 2), 1e-300)
+    wr = np.linalg.eigvalsh(A)
+    assert np.all(np.diff(w) >= -1e-13 * nrm), "eigenvalues must ascend"
+    assert np.max(np.abs(w - wr)) <= 1e-13 * nrm
+    assert np.linalg.norm(A @ Z - Z * w) <= tol_res * nrm * max(1, np.sqrt(A.shape[0]) / 4)
+    assert np.abs(Z.T @ Z - np.eye(A.shape[0])).max() <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 63, 64, 65, 128, 200, 257])
+def test_syev_random(torch, eda, n):
+    log(f"syev random n={n}")
+    rng = np.random.default_rng(100 + n)
+    B = rng.standard_normal((n, n))
+    A = B + B.T
+    h = eda.Handle()
+    w, Z = h.syev(dev(torch, A))
+    check_eig(A, host(w), host(Z))
+    h.close()
+
+
+def test_syev_special_matrices(torch, eda, c1):
+    log("syev special matrices")
+    h = eda.Handle()
+    cases = {
+        "zero": np.zeros((7, 7)),
+        "identity": np.eye(9),
+        "repeated": np.diag([1.0, 2.0, 2.0, 2.0, 3.0, 3.0, 5.0]),
+        "gram_WW": c1.H_W.T @ c1.H_W,       # rank n-k: a zero cluster of size k
+        "gram_BB": c1.H_B.T @ c1.H_B,       # rank k-1
+    }
+    rng = np.random.default_rng(3)
+    Q = np.linalg.qr(rng.standard_normal((40, 40)))[0]
+    cases["clustered"] = (Q * np.concatenate([np.full(20, 1.0), np.full(10, 1.0 + 1e-9),
+                                              np.linspace(2, 3, 10)])) @ Q.T
+    for name, A in cases.items():
+        log(f"  {name} n={A.shape[0]}")
+        w, Z = h.syev(dev(torch, A))
+        check_eig(A, host(w), host(Z))
+    h.close()
+
+
+# ---------------------------------------------------------------------------
+# a4: low-rank exponential apply
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b", [1, 3, 8, 13])
+def test_expmv_c1(torch, eda, c1, b):
+    log(f"expmv C1 b={b}")
+    h, _, _ = prepared(torch, eda, c1)
+    rng = np.random.default_rng(b)
+    V = rng.standard_normal((c1.d, b))
+    for which, H, c in (("W", c1.H_W, -1.0), ("W", c1.H_W, -0.5), ("W", c1.H_W, 0.7),
+                        ("B", c1.H_B, 1.0), ("B", c1.H_B, -1.0)):
+        E = O.expm_sym(H @ H.T, c)
+        out, s = h.expmv(which, c, dev(torch, V))
+        got = host(out) * np.exp(s)
+        err = rel_op_err(got, E @ V, np.linalg.norm(E, 2), V)
+        log(f"  {which} c={c} s={s:.3f} err={err:.2e}")
+        assert err <= 1e-13
+    h.close()
+
+
+def test_opmv_c1(torch, eda, c1):
+    log("opmv C1 (Lanczos M and Arnoldi A)")
+    h, _, _ = prepared(torch, eda, c1)
+    V = np.random.default_rng(5).standard_normal((c1.d, 8))
+    M = O.lanczos_matrix_dense(c1.H_W, c1.H_B)
+    A = O.arnoldi_matrix_dense(c1.H_W, c1.H_B)
+    for form, E in (("M", M), ("A", A)):
+        out, s = h.opmv(form, dev(torch, V))
+        got = host(out) * np.exp(s)
+        err = rel_op_err(got, E @ V, np.linalg.norm(E, 2), V)
+        log(f"  {form} s={s:.3f} err={err:.2e}")
+        assert err <= 1e-13
+    h.close()
+
+
+def test_expmv_opmv_c2_full_size(torch, eda, c2):
+    """d=10304, n=200, k=40 at b=8, the launch shape the solver uses; the
+    oracle is the closed form of Theorem 3.1 (QR + SVD), norms from the same."""
+    log("expmv/opmv C2 full size")
+    h, _, _ = prepared(torch, eda, c2)
+    V = np.random.default_rng(9).standard_normal((c2.d, 8))
+    sW = np.linalg.svd(c2.H_W, compute_uv=False) ** 2
+    sB = np.linalg.svd(c2.H_B, compute_uv=False) ** 2
+    for which, H, c, En in (("W", c2.H_W, -0.5, 1.0), ("W", c2.H_W, -1.0, 1.0),
+                            ("B", c2.H_B, 1.0, np.exp(sB[0]))):
+        out, s = h.expmv(which, c, dev(torch, V))
+        ref = O.exp_action_thm31(H, c, V)
+        err = rel_op_err(host(out) * np.exp(s), ref, En, V)
+        log(f"  {which} c={c} err={err:.2e}")
+        assert err <= 1e-13
+    out, s = h.opmv("M", dev(torch, V))
+    ref = O.lanczos_action_thm31(c2.H_W, c2.H_B, V)
+    err = rel_op_err(host(out) * np.exp(s), ref, np.exp(sB[0]), V)
+    log(f"  M err={err:.2e}")
+    assert err <= 1e-13
+    h.close()
+
+
+# ---------------------------------------------------------------------------
+# a5-a7: block Lanczos solve, Rayleigh-Ritz, back-transform + orth
+# ---------------------------------------------------------------------------
+
+def check_solution(res, ref, t, lam_all, tol):
+    lam = np.array(res.ritz)
+    fl = O.accuracy_floor(lam_all, t)
+    lam_tol = np.maximum(1e-10, 50 * U * lam_all[0] / ref.lam)
+    relerr = np.abs(lam - ref.lam) / ref.lam
+    X = host(res.X)
+    ang = O.sin_angle(ref.X, X)
+    ang_tol = max(1e-8, 50 * fl["span"])
+    log(f"  status={res.status} iters={res.info['iters']} restarts={res.info['restarts']} "
+        f"lam_err={relerr.max():.2e} sin={ang:.2e} resid={max(res.resid):.2e} "
+        f"krylov_ms={res.info['t_krylov_ms']:.2f}")
+    assert res.status == 0, res.message
+    assert np.all(relerr <= lam_tol)
+    assert ang <= ang_tol
+    assert np.abs(X.T @ X - np.eye(t)).max() <= 1e-13
+    assert np.allclose(np.array(res.ritz_log), np.log(ref.lam), rtol=0, atol=1e-10)
+    tol_i = np.maximum(tol, 10 * U * lam[0] / lam)
+    assert np.all(np.array(res.resid) <= 10 * tol_i)
+    return X
+
+
+def test_solve_c1(torch, eda, c1):
+    log("solve C1 t=9 b=8 tol=1e-10")
+    ref = O.eda_dense(c1.H_W, c1.H_B, c1.t)
+    red = O.eda_reduced(c1.H_W, c1.H_B, c1.t)
+    h, _, _ = prepared(torch, eda, c1)
+    res = h.solve(c1.t, 1e-10, block=8, seed=1)
+    X = check_solution(res, ref, c1.t, red.lam_all, 1e-10)
+    # per-column agreement (distinct, well separated eigenvalues at C1)
+    assert np.abs(X - ref.X).max() <= 1e-8
+    h.close()
+
+
+def test_solve_c2(torch, eda, c2):
+    log("solve C2 t=39 b=8 tol=1e-10")
+    red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
+    h, _, _ = prepared(torch, eda, c2)
+    sb = datagen.start_block(c2.d, 8, 2)
+    res = h.solve(c2.t, 1e-10, block=8, start_block=dev(torch, sb))
+    check_solution(res, red, c2.t, red.lam_all, 1e-10)
+    h.close()
+
+
+def test_solve_c2_thick_restart(torch, eda, c2):
+    log("solve C2 with a small basis (thick restarts)")
+    red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
+    h, _, _ = prepared(torch, eda, c2)
+    res = h.solve(c2.t, 1e-10, block=8, max_basis=72, seed=4, max_iter=3000)
+    assert res.info["restarts"] >= 1
+    check_solution(res, red, c2.t, red.lam_all, 1e-10)
+    h.close()
+
+
+def test_solve_ragged_small_block(torch, eda, ragged):
+    log("solve ragged d=333 n=15 k=5 t=4 b=3")
+    ref = O.eda_dense(ragged.H_W, ragged.H_B, ragged.t)
+    red = O.eda_reduced(ragged.H_W, ragged.H_B, ragged.t)
+    h, _, _ = prepared(torch, eda, ragged)
+    res = h.solve(ragged.t, 1e-10, block=3, seed=2)
+    check_solution(res, ref, ragged.t, red.lam_all, 1e-10)
+    h.close()
+
+
+def test_solve_deterministic(torch, eda, c1):
+    log("solve C1 twice: bitwise identical")
+    h, _, _ = prepared(torch, eda, c1)
+    a = h.solve(c1.t, 1e-10, seed=7)
+    Xa = host(a.X).copy()
+    b = h.solve(c1.t, 1e-10, seed=7)
+    assert a.ritz == b.ritz and np.array_equal(Xa, host(b.X))
+    h.close()
+
+
+def test_solve_iteration_limit_reports_noconv(torch, eda, c2):
+    log("solve C2 max_iter=1")
+    h, _, _ = prepared(torch, eda, c2)
+    res = h.solve(c2.t, 1e-12, max_iter=5, seed=1, check_every=1)
+    assert res.status == eda.EDA_ERR_NOCONV
+    assert np.all(np.isfinite(res.ritz))
+    h.close()
+
+
+def test_degenerate_t_flag(torch, eda, ragged):
+    log("t > k-1 sets the degenerate flag")
+    h, _, _ = prepared(torch, eda, ragged)
+    res = h.solve(6, 1e-8, block=2, seed=1)
+    assert res.info["flags"] & eda.EDA_WARN_DEGENERATE
+    h.close()
+
+
+def test_nonfinite_input_rejected(torch, eda, ragged):
+    log("NaN in H_W")
+    h = eda.Handle()
+    HW = ragged.H_W.copy()
+    HW[5, 3] = np.nan
+    with pytest.raises(eda.EDAError) as ei:
+        h.prepare(dev(torch, HW), dev(torch, ragged.H_B))
+    assert ei.value.status == eda.EDA_ERR_NONFINITE
+    h.close()
+
+
+def test_fp32_storage_c2(torch, eda, c2):
+    """P stored in float32 (Krylov arithmetic float64).  Rounding P to
+    float32 perturbs S_W, S_B by at most about 2 u32 ||H||^2 in norm, which
+    moves log lambda by about 1e-6 (Theorem 3.2 type bound) and the span by
+    at most lam_1 * that / gap (Davis-Kahan): tolerances 1e-5 and 1e-2."""
+    log("solve C2 with float32 storage")
+    red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
+    h, _, _ = prepared(torch, eda, c2, storage="f32")
+    res = h.solve(c2.t, 1e-8, block=8, seed=2)
+    lam = np.array(res.ritz)
+    relerr = np.max(np.abs(lam - red.lam) / red.lam)
+    ang = O.sin_angle(red.X, host(res.X))
+    log(f"  status={res.status} lam_err={relerr:.2e} sin={ang:.2e}")
+    assert res.status == 0
+    assert relerr <= 1e-5 and ang <= 1e-2
+    h.close()
