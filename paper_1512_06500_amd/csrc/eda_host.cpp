@@ -49,8 +49,10 @@ struct eda_handle_s {
   bool prepared = false;
   int64_t d = 0, n = 0, k = 0, N = 0, ldp = 0;
   eda_dtype storage = EDA_F64;
-  Buf P, G, eigW, eigZ, nsbuf, Gh, Gm, GBs, CM, CA, T1, T2, T3, T4, fw;
+  Buf P, G, eigW, eigZ, nsbuf, Gh, Gm, GBs, CM, CA, T1, T2, T3, T4, fw, polyws, normbuf;
   double shiftB = 0.0, alphaB = 1.0;
+  double normW = 0.0;   // ||H_W^T H_W||_1
+  bool w_eig = false;   // eigenpairs of H_W^T H_W available
   std::vector<double> hwW, hwB;
   double t_prepare_ms = 0.0;
 
@@ -163,7 +165,78 @@ eda_status expop(eda_handle h, int64_t c0, int64_t Nc, const double* C, int64_t 
 }
 
 // Core V diag(f) V^T of exp(c H H^T) e^{-shift} for the factor `which`.
+// W-core by a matrix polynomial instead of an eigendecomposition:
+//   G_c = c psi(c G_WW),  psi(X) = sum_{j>=0} X^j / (j+1)!  (psi(z) = (e^z - 1)/z),
+// which equals V diag(phi_c(lambda)) V^T.  X = c G_WW / 2^q with ||X||_1 <= 1,
+// psi(X) by Paterson-Stockmeyer (degree 17, truncation below 1/19! < 1e-17),
+// then q doublings psi(2X) = psi(X) + psi(X) X psi(X) / 2.  Only GEMMs.
+eda_status poly_core_W(eda_handle h, double c, double* out) {
+  const int64_t n = h->n, N = h->N, nn = n * n;
+  hipStream_t s = h->stream;
+  STCHK(ensure(h, h->polyws, (size_t)7 * nn * 8));
+  double* X = h->polyws.d();
+  double* A2 = X + nn;
+  double* A3 = A2 + nn;
+  double* A4 = A3 + nn;
+  double* P = A4 + nn;
+  double* T = P + nn;
+  double* U = T + nn;
+  double nrm = std::fabs(c) * h->normW;
+  int q = 0;
+  while (nrm > 1.0 && q < 60) {
+    nrm *= 0.5;
+    ++q;
+  }
+  const double sc = c * std::ldexp(1.0, -q);
+  double a[18];
+  double f = 1.0;
+  for (int j = 0; j < 18; ++j) {
+    f *= (double)(j + 1);
+    a[j] = 1.0 / f;  // 1/(j+1)!
+  }
+  HIPCHK(launch_copy_block(n, n, sc, h->G.d(), N, false, X, n, s));
+  HIPCHK(launch_gemm(false, false, n, n, n, 1.0, X, n, nullptr, X, n, 0.0, A2, n, s));
+  HIPCHK(launch_gemm(false, false, n, n, n, 1.0, A2, n, nullptr, X, n, 0.0, A3, n, s));
+  HIPCHK(launch_gemm(false, false, n, n, n, 1.0, A2, n, nullptr, A2, n, 0.0, A4, n, s));
+  HIPCHK(launch_lincomb(n, a[16], a[17], X, 0.0, nullptr, 0.0, nullptr, n, P, n, s));
+  for (int kb = 3; kb >= 0; --kb) {
+    HIPCHK(launch_lincomb(n, a[4 * kb], a[4 * kb + 1], X, a[4 * kb + 2], A2, a[4 * kb + 3], A3,
+                          n, T, n, s));
+    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, A4, n, nullptr, P, n, 1.0, T, n, s));
+    std::swap(P, T);
+  }
+  for (int i = 0; i < q; ++i) {
+    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, X, n, nullptr, P, n, 0.0, U, n, s));
+    HIPCHK(launch_copy_block(n, n, 1.0, P, n, false, T, n, s));
+    HIPCHK(launch_gemm(false, false, n, n, n, 0.5, P, n, nullptr, U, n, 1.0, T, n, s));
+    std::swap(P, T);
+    HIPCHK(launch_copy_block(n, n, 2.0, X, n, false, X, n, s));
+  }
+  // symmetrise (rounding) and scale by c
+  HIPCHK(launch_symmetrize(n, P, n, out, n, s));
+  HIPCHK(launch_copy_block(n, n, c, out, n, false, out, n, s));
+  return EDA_OK;
+}
+
+// Eigenpairs of H_W^T H_W on demand (the polynomial route does not need them).
+eda_status ensure_w_eig(eda_handle h) {
+  if (h->w_eig) return EDA_OK;
+  const int64_t n = h->n;
+  STCHK(ensure(h, h->syev_work, syev_work_bytes(n)));
+  HIPCHK(launch_syev(1, n, nullptr, h->G.d(), h->N, 0, h->eigW.d(), 0, h->eigZ.d(), n, 0, 0,
+                     h->syev_work.d(), h->stream));
+  h->hwW.assign(n, 0.0);
+  HIPCHK(hipMemcpyAsync(h->hwW.data(), h->eigW.d(), n * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->w_eig = true;
+  return EDA_OK;
+}
+
 eda_status build_core(eda_handle h, int which, double c, double shift, double* out) {
+  if (which == EDA_W && !h->w_eig) {
+    if (c <= 0.0) return poly_core_W(h, c, out);
+    STCHK(ensure_w_eig(h));
+  }
   const int64_t Nw = which == EDA_W ? h->n : h->k;
   const double* lam = h->eigW.d() + (which == EDA_W ? 0 : h->n);
   const double* Z = h->eigZ.d() + (which == EDA_W ? 0 : h->n * h->n);
@@ -187,7 +260,16 @@ eda_status build_composite_cores(eda_handle h) {
   STCHK(ensure(h, h->T3, (size_t)n * k * 8));
   STCHK(ensure(h, h->T4, (size_t)n * k * 8));
   STCHK(build_core(h, EDA_W, -0.5, 0.0, h->Gh.d()));
-  STCHK(build_core(h, EDA_W, -1.0, 0.0, h->Gm.d()));
+  if (h->w_eig) {
+    STCHK(build_core(h, EDA_W, -1.0, 0.0, h->Gm.d()));
+  } else {
+    // exp(-S_W) = exp(-S_W/2)^2 gives G_m = 2 G_h + G_h (H_W^T H_W) G_h
+    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, h->G.d(), N, nullptr, h->Gh.d(), n, 0.0,
+                       h->CM.d(), n, h->stream));
+    HIPCHK(launch_copy_block(n, n, 2.0, h->Gh.d(), n, false, h->Gm.d(), n, h->stream));
+    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, h->Gh.d(), n, nullptr, h->CM.d(), n, 1.0,
+                       h->Gm.d(), n, h->stream));
+  }
   STCHK(build_core(h, EDA_B, 1.0, h->shiftB, h->GBs.d()));
   const double* K = h->G.d() + n * N;  // H_W^T H_B, n x k, ld N
   hipStream_t s = h->stream;
@@ -284,7 +366,8 @@ void eda_destroy(eda_handle h) {
   if (h == nullptr) return;
   if (h->device >= 0) {
     (void)hipStreamSynchronize(h->stream);
-    Buf* all[] = {&h->P,  &h->G,  &h->eigW, &h->eigZ, &h->nsbuf, &h->Gh,  &h->Gm,  &h->GBs,
+    Buf* all[] = {&h->polyws, &h->normbuf,
+                  &h->P,  &h->G,  &h->eigW, &h->eigZ, &h->nsbuf, &h->Gh,  &h->Gm,  &h->GBs,
                   &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part,
                   &h->Ysm, &h->Zsm, &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
@@ -379,19 +462,34 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const doub
   HIPCHK(launch_gram_partial(d, N, h->P.p, dt_of(storage), h->ldp, h->part.d(), gc, h->stream));
   HIPCHK(launch_gram_reduce(N, gc, h->part.d(), h->G.d(), N, h->stream));
 
-  // a3: eig(H_W^T H_W), eig(H_B^T H_B) in one batched launch
-  int hns[2] = {(int)n, (int)k};
-  STCHK(ensure(h, h->nsbuf, 2 * sizeof(int)));
-  HIPCHK(hipMemcpy(h->nsbuf.p, hns, sizeof(hns), hipMemcpyHostToDevice));
+  // a3: eig(H_B^T H_B) (core of exp(S_B) and the shift).  The W-cores come
+  // from a matrix polynomial (poly_core_W) unless EDA_WCORE=eig selects
+  // eig(H_W^T H_W) + phi weights; both routes are exact up to rounding.
+  const char* wc = std::getenv("EDA_WCORE");
+  const bool w_by_eig = (wc != nullptr && std::strcmp(wc, "eig") == 0);
   STCHK(ensure(h, h->eigW, (size_t)2 * n * 8));
   STCHK(ensure(h, h->eigZ, (size_t)2 * n * n * 8));
-  STCHK(ensure(h, h->syev_work, 2 * syev_work_bytes(n)));
-  HIPCHK(launch_syev(2, n, h->nsbuf.i(), h->G.d(), N, n + n * N, h->eigW.d(), n, h->eigZ.d(), n,
-                     n * n, 0, h->syev_work.d(), h->stream));
-  h->hwW.assign(n, 0.0);
+  STCHK(ensure(h, h->normbuf, 64));
+  h->w_eig = false;
+  if (w_by_eig) {
+    int hns[2] = {(int)n, (int)k};
+    STCHK(ensure(h, h->nsbuf, 2 * sizeof(int)));
+    HIPCHK(hipMemcpy(h->nsbuf.p, hns, sizeof(hns), hipMemcpyHostToDevice));
+    STCHK(ensure(h, h->syev_work, 2 * syev_work_bytes(n)));
+    HIPCHK(launch_syev(2, n, h->nsbuf.i(), h->G.d(), N, n + n * N, h->eigW.d(), n, h->eigZ.d(),
+                       n, n * n, 0, h->syev_work.d(), h->stream));
+    h->hwW.assign(n, 0.0);
+    HIPCHK(hipMemcpyAsync(h->hwW.data(), h->eigW.d(), n * 8, hipMemcpyDeviceToHost, h->stream));
+    h->w_eig = true;
+  } else {
+    STCHK(ensure(h, h->syev_work, syev_work_bytes(k)));
+    HIPCHK(launch_syev(1, k, nullptr, h->G.d() + n + n * N, N, 0, h->eigW.d() + n, 0,
+                       h->eigZ.d() + n * n, n, 0, 0, h->syev_work.d(), h->stream));
+  }
+  HIPCHK(launch_norm1(n, h->G.d(), N, h->normbuf.d(), h->stream));
   h->hwB.assign(k, 0.0);
-  HIPCHK(hipMemcpyAsync(h->hwW.data(), h->eigW.d(), n * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(h->hwB.data(), h->eigW.d() + n, k * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(&h->normW, h->normbuf.d(), 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   double lbmax = 0.0;
   for (double v : h->hwB) lbmax = std::max(lbmax, v);
@@ -420,6 +518,7 @@ eda_status eda_expmv(eda_handle h, eda_which which, double c, int64_t b, const v
   STCHK(need_device(h));
   STCHK(check_dev_ptr(h, V, "V"));
   STCHK(check_dev_ptr(h, Out, "Out"));
+  if (which == EDA_W && c > 0.0) STCHK(ensure_w_eig(h));  // the shift needs lambda_max
   const std::vector<double>& lam = which == EDA_W ? h->hwW : h->hwB;
   double lmax = 0.0;
   for (double v : lam) lmax = std::max(lmax, v);

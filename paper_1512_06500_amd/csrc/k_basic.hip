@@ -247,9 +247,56 @@ __global__ __launch_bounds__(256) void set_diag_kernel(int64_t cnt, const double
   if (i < cnt) D[i + i * ldd] = v[i];
 }
 
+__global__ __launch_bounds__(256) void norm1_kernel(int64_t n, const double* __restrict__ A,
+                                                    int64_t lda, double* __restrict__ out) {
+  __shared__ double red[256];
+  double best = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += fabs(A[i + j * lda]);
+    best = fmax(best, s);
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ __launch_bounds__(256) void lincomb_kernel(int64_t n, double a0, double a1,
+                                                      const double* __restrict__ X1, double a2,
+                                                      const double* __restrict__ X2, double a3,
+                                                      const double* __restrict__ X3, int64_t ldx,
+                                                      double* __restrict__ C, int64_t ldc) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t c = e / n, r = e - c * n;
+  double v = (r == c) ? a0 : 0.0;
+  v += a1 * X1[r + c * ldx];
+  if (a2 != 0.0) v += a2 * X2[r + c * ldx];
+  if (a3 != 0.0) v += a3 * X3[r + c * ldx];
+  C[r + c * ldc] = v;
+}
+
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+hipError_t launch_norm1(int64_t n, const double* A, int64_t lda, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(norm1_kernel, dim3(1), dim3(256), 0, s, n, A, lda, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(int64_t n, double a0, double a1, const double* X1, double a2,
+                          const double* X2, double a3, const double* X3, int64_t ldx,
+                          double* C, int64_t ldc, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n * n)), dim3(256), 0, s, n, a0, a1, X1, a2, X2,
+                     a3, X3, ldx, C, ldc);
+  return hipGetLastError();
+}
 
 hipError_t launch_copy_block(int64_t rows, int64_t cols, double alpha, const double* src,
                              int64_t lds, bool trans, double* dst, int64_t ldd, hipStream_t s) {

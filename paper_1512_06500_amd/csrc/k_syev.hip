@@ -1,18 +1,19 @@
 // Dense symmetric eigensolver for the small matrices of the method: the
-// Gram blocks H_W^T H_W and H_B^T H_B (whose eigenpairs give the cores
-// V phi(Lambda) V^T of the exponentials) and the Rayleigh-Ritz matrices of
-// block Lanczos.  One 1024-thread workgroup per matrix (batched over the
-// grid), float64 throughout.
+// Gram blocks H_B^T H_B and H_W^T H_W (whose eigenpairs give the cores of
+// the exponentials and the spectral shift) and the Rayleigh-Ritz matrices
+// of block Lanczos.  One workgroup per matrix (batched over the grid),
+// float64 throughout.
 //
-//   1. Householder reduction to tridiagonal form T = Q^T A Q (unblocked:
-//      per column one reflector, one symmetric matrix-vector product, one
-//      rank-2 update; the working copy of A stays in L2).
-//   2. Eigenvalues of T by Sturm-count bisection; the workgroup's threads
-//      are split into groups of g lanes that probe g points per step
-//      (multisection), so small matrices converge in few steps.
+//   1. Householder reduction to tridiagonal form T = Q^T A Q.  The working
+//      matrix lives in LDS when it fits (n <= kLdsMax), else in global memory.
+//   2. Eigenvalues of T by Sturm-count multisection: groups of g threads
+//      probe g points per step; the count uses the three-term recurrence of
+//      the leading principal minors (no divisions), rescaled by powers of 2.
 //   3. Eigenvectors of T by inverse iteration, one thread per eigenvalue
-//      (LU with partial pivoting of T - lambda I, three solves), then
-//      modified Gram-Schmidt inside clusters of close eigenvalues.
+//      (LU with partial pivoting of T - lambda I, three solves with
+//      overflow-safe rescaling), then orthonormalisation inside clusters of
+//      close eigenvalues (Cholesky QR twice by the whole workgroup, or
+//      modified Gram-Schmidt for very large clusters).
 //   4. Back-transformation by the stored reflectors, one thread per vector.
 #include "common.h"
 
@@ -20,16 +21,19 @@ namespace eda {
 
 namespace {
 
-constexpr int ST = 1024;      // threads per workgroup
-constexpr int NW = ST / 64;   // waves
 constexpr int SYEV_NMAX = 2048;
+constexpr int kLdsMax = 112;      // largest n whose working matrix is kept in LDS
+constexpr int kStage = 8192;      // doubles of LDS for staged reflectors (global path)
+constexpr int kClusterMax = 64;   // clusters up to this size use Cholesky QR
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
   return v;
 }
 
+template <int NT>
 __device__ __forceinline__ double blk_sum(double v, double* red) {
+  constexpr int NW = NT / 64;
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -40,7 +44,9 @@ __device__ __forceinline__ double blk_sum(double v, double* red) {
   return s;
 }
 
+template <int NT>
 __device__ __forceinline__ double blk_max(double v, double* red) {
+  constexpr int NW = NT / 64;
   for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -51,7 +57,9 @@ __device__ __forceinline__ double blk_max(double v, double* red) {
   return s;
 }
 
+template <int NT>
 __device__ __forceinline__ double blk_min(double v, double* red) {
+  constexpr int NW = NT / 64;
   for (int m = 32; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m));
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -69,32 +77,48 @@ __device__ __forceinline__ uint64_t hash64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// Number of eigenvalues of T below x (Sturm count of the LDL^T pivots).
+// Number of eigenvalues of T below x: sign changes of the leading principal
+// minors p_k of T - xI, p_k = (d_k - x) p_{k-1} - e_{k-1}^2 p_{k-2}, kept in
+// range by exact power-of-two rescaling.  A zero minor is replaced by a tiny
+// value of the sign opposite to its predecessor (counted as a change), the
+// same convention as a zero pivot of the LDL^T form of the count.
 __device__ __forceinline__ int sturm_count(int n, const double* __restrict__ D,
-                                           const double* __restrict__ E2, double x,
-                                           double pivmin) {
-  double q = D[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int c = (q < 0.0);
+                                           const double* __restrict__ E2, double x) {
+  const double hi = 0x1.0p400, lo = 0x1.0p-400;
+  double pm2 = 1.0;        // p_{k-2}
+  double pm1 = D[0] - x;   // p_{k-1} = p_0
+  if (pm1 == 0.0) pm1 = -0x1.0p-1000;
+  int c = (pm1 < 0.0);
   for (int k = 1; k < n; ++k) {
-    q = (D[k] - x) - E2[k - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    c += (q < 0.0);
+    double p = (D[k] - x) * pm1 - E2[k - 1] * pm2;
+    if (p == 0.0) p = (pm1 < 0.0) ? 0x1.0p-1000 : -0x1.0p-1000;
+    c += ((p < 0.0) != (pm1 < 0.0));
+    const double ap = fabs(p);
+    if (ap > hi) {
+      p *= lo;
+      pm1 *= lo;
+    } else if (ap < lo && fabs(pm1) < lo) {
+      p *= hi;
+      pm1 *= hi;
+    }
+    pm2 = pm1;
+    pm1 = p;
   }
   return c;
 }
 
 // LU factorisation with partial pivoting of T - lam I (T tridiagonal: diagonal
-// D, off-diagonal ee).  Stored per position k with stride ST: 1/U(k,k),
+// D, off-diagonal ee).  Stored per position k with stride NT: 1/U(k,k),
 // U(k,k+1), U(k,k+2), the multiplier and the interchange flag.
+template <int NT>
 __device__ void tri_factor(int n, const double* __restrict__ D, const double* __restrict__ ee,
                            double lam, double tiny, double* __restrict__ lu, int64_t nmax) {
   double* U1 = lu;
-  double* U2 = lu + nmax * ST;
-  double* U3 = lu + 2 * nmax * ST;
-  double* Lm = lu + 3 * nmax * ST;
-  double* Pv = lu + 4 * nmax * ST;
-#define LU(arr, k) arr[(int64_t)(k) * ST]
+  double* U2 = lu + nmax * NT;
+  double* U3 = lu + 2 * nmax * NT;
+  double* Lm = lu + 3 * nmax * NT;
+  double* Pv = lu + 4 * nmax * NT;
+#define LU(arr, k) arr[(int64_t)(k) * NT]
   double p = D[0] - lam;
   double qv = (n > 1) ? ee[0] : 0.0;
   double rv = 0.0;
@@ -104,8 +128,9 @@ __device__ void tri_factor(int n, const double* __restrict__ D, const double* __
     const double en = (k + 1 < n - 1) ? ee[k + 1] : 0.0;
     if (fabs(p) >= fabs(ek)) {
       if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
-      const double l = ek / p;
-      LU(U1, k) = 1.0 / p;
+      const double inv = 1.0 / p;
+      const double l = ek * inv;
+      LU(U1, k) = inv;
       LU(U2, k) = qv;
       LU(U3, k) = rv;
       LU(Lm, k) = l;
@@ -113,8 +138,9 @@ __device__ void tri_factor(int n, const double* __restrict__ D, const double* __
       p = an - l * qv;
       qv = en - l * rv;
     } else {
-      const double l = p / ek;
-      LU(U1, k) = 1.0 / ek;
+      const double inv = 1.0 / ek;
+      const double l = p * inv;
+      LU(U1, k) = inv;
       LU(U2, k) = an;
       LU(U3, k) = en;
       LU(Lm, k) = l;
@@ -132,18 +158,18 @@ __device__ void tri_factor(int n, const double* __restrict__ D, const double* __
 }
 
 // Solve (T - lam I) x = y in place (y with stride ys).  The back substitution
-// rescales the computed tail whenever it grows past 2^300, so chains of tiny
-// pivots (split matrices, multiple eigenvalues) cannot overflow.
+// rescales the whole system whenever the solution grows past 2^300, so chains
+// of tiny pivots (split matrices, multiple eigenvalues) cannot overflow.
+template <int NT>
 __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
                           double* __restrict__ y, int64_t ys) {
   const double* U1 = lu;
-  const double* U2 = lu + nmax * ST;
-  const double* U3 = lu + 2 * nmax * ST;
-  const double* Lm = lu + 3 * nmax * ST;
-  const double* Pv = lu + 4 * nmax * ST;
-#define LU(arr, k) arr[(int64_t)(k) * ST]
+  const double* U2 = lu + nmax * NT;
+  const double* U3 = lu + 2 * nmax * NT;
+  const double* Lm = lu + 3 * nmax * NT;
+  const double* Pv = lu + 4 * nmax * NT;
+#define LU(arr, k) arr[(int64_t)(k) * NT]
 #define YV(k) y[(int64_t)(k) * ys]
-  // forward elimination; the running entry stays in a register
   double carry = YV(0);
   for (int k = 0; k < n - 1; ++k) {
     double a = carry, b = YV(k + 1);
@@ -161,8 +187,6 @@ __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
   for (int k = n - 1; k >= 0; --k) {
     double x = (YV(k) - LU(U2, k) * x1 - LU(U3, k) * x2) * LU(U1, k);
     if (!(fabs(x) < big)) {
-      // rescale the whole system (right-hand side of rows < k and the
-      // solution of rows > k) so the remaining steps stay finite
       for (int j = 0; j < n; ++j) YV(j) *= small;
       x1 *= small;
       x2 *= small;
@@ -176,8 +200,8 @@ __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
 #undef LU
 }
 
-__device__ void random_start(int n, int i, double* y, int64_t ys, int first, int step) {
-  for (int k = first; k < n; k += step) {
+__device__ void random_start(int n, int i, double* y, int64_t ys) {
+  for (int k = 0; k < n; ++k) {
     const uint64_t h = hash64(((uint64_t)(i + 1) << 32) ^ (uint64_t)k ^ 0x5bd1e995ull);
     y[(int64_t)k * ys] = ((double)(h >> 11) * 0x1.0p-53) * 2.0 - 1.0;
   }
@@ -211,38 +235,29 @@ __device__ void wave_normalize(int n, double* y, int64_t ys, int lane) {
   for (int k = lane; k < n; k += 64) y[(int64_t)k * ys] *= sc;
 }
 
-struct SyevWork {
-  double* A;    // n x n working copy (ld n), later the reflectors
-  double* dd;   // diagonal of T
-  double* ee;   // off-diagonal of T
-  double* tau;  // reflector scalars
-  double* lam;  // eigenvalues ascending
-  double* Zt;   // eigenvectors of T, layout [pos][slot] (n x nv)
-  double* lu;   // LU of T - lambda I, layout [array][pos][thread]
-};
-
-__device__ SyevWork carve(double* base, int64_t nmax) {
-  SyevWork w;
-  w.A = base;
-  w.dd = w.A + nmax * nmax;
-  w.ee = w.dd + nmax;
-  w.tau = w.ee + nmax;
-  w.lam = w.tau + nmax;
-  w.Zt = w.lam + nmax;
-  w.lu = w.Zt + nmax * nmax;
-  return w;
+// Global work per matrix (doubles): A n^2, d/e/tau/lambda 4n, Z_T n^2,
+// LU 5 n NT (+ n of slack).
+__host__ __device__ inline int64_t syev_work_doubles(int64_t nmax, int nt) {
+  return 5 * nmax + 2 * nmax * nmax + 5 * nmax * (int64_t)nt;
 }
 
-__global__ __launch_bounds__(ST) void syev_kernel(int nfix, const int* __restrict__ ns,
+// LDS layout (doubles):
+//   LDS path:    A [n (n+1)] | sv [n] | sw [n] | red [16] | Gc [kClusterMax^2]
+//   global path: sv [n] | sw [n] | stage [kStage] | red [16]   (Gc = stage)
+__host__ __device__ inline int64_t syev_lds_doubles(int64_t n, bool lds_a) {
+  return lds_a ? n * (n + 1) + 2 * n + 16 + kClusterMax * kClusterMax : 2 * n + kStage + 16;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restrict__ ns,
                                                   const double* __restrict__ Ain, int64_t lda,
                                                   int64_t strideA, double* __restrict__ wout,
                                                   int64_t stridew, double* __restrict__ Zout,
                                                   int64_t ldz, int64_t strideZ, int nvec_req,
-                                                  double* __restrict__ work, int64_t nmax) {
-  __shared__ double sbuf[2 * SYEV_NMAX];
-  __shared__ double red[NW];
-  double* sv = sbuf;
-  double* sw = sbuf + SYEV_NMAX;
+                                                  double* __restrict__ work, int64_t nmax,
+                                                  int lds_a) {
+  constexpr int NW = NT / 64;
+  extern __shared__ double smem[];
   const int q = blockIdx.x;
   const int n = (ns != nullptr) ? ns[q] : nfix;
   if (n <= 0) return;
@@ -250,109 +265,137 @@ __global__ __launch_bounds__(ST) void syev_kernel(int nfix, const int* __restric
   const double* Aq = Ain + q * strideA;
   double* wq = wout + q * stridew;
   double* Zq = Zout + q * strideZ;
-  const int64_t wstride = 5 * nmax + 2 * nmax * nmax + 5 * nmax * (int64_t)ST;
-  SyevWork W = carve(work + q * wstride, nmax);
-  double* A = W.A;
+  double* wk = work + q * syev_work_doubles(nmax, NT);
+  double* gA = wk;                   // n x n (global path)
+  double* dd = gA + nmax * nmax;
+  double* ee = dd + nmax;
+  double* tau = ee + nmax;
+  double* lamv = tau + nmax;
+  double* Zt = lamv + nmax;          // [pos][slot]
+  double* lub = Zt + nmax * nmax;    // LU arrays, [array][pos][thread]
+  double *A, *sv, *sw, *red, *stage, *Gc;
+  int64_t ldA;
+  if (lds_a) {
+    A = smem;
+    ldA = nmax + 1;
+    sv = smem + nmax * (nmax + 1);
+    sw = sv + nmax;
+    red = sw + nmax;
+    Gc = red + 16;
+    stage = nullptr;
+  } else {
+    A = gA;
+    ldA = nmax;
+    sv = smem;
+    sw = sv + nmax;
+    stage = sw + nmax;
+    red = stage + kStage;
+    Gc = stage;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const double eps = 0x1.0p-53;
 
   // ---- 0. symmetrised working copy (lower triangle of the input) ---------
-  for (int64_t e = tid; e < (int64_t)n * n; e += ST) {
+  for (int64_t e = tid; e < (int64_t)n * n; e += NT) {
     const int c = (int)(e / n), r = (int)(e - (int64_t)c * n);
-    A[r + (int64_t)c * n] = (r >= c) ? Aq[r + c * lda] : Aq[c + r * lda];
+    A[r + c * ldA] = (r >= c) ? Aq[r + c * lda] : Aq[c + r * lda];
   }
   __syncthreads();
 
   // ---- 1. Householder tridiagonalisation ---------------------------------
   for (int j = 0; j < n - 2; ++j) {
     const int m1 = n - j - 1;
-    double* col = A + (int64_t)j * n;
+    double* col = A + (int64_t)j * ldA;
     double s = 0.0;
-    for (int r = j + 2 + tid; r < n; r += ST) s += col[r] * col[r];
-    s = blk_sum(s, red);
+    for (int r = j + 2 + tid; r < n; r += NT) s += col[r] * col[r];
+    s = blk_sum<NT>(s, red);
     const double alpha = col[j + 1];
-    double beta, tau, scale;
+    double beta, tv, scale;
     if (s == 0.0) {
-      tau = 0.0;
+      tv = 0.0;
       beta = alpha;
       scale = 0.0;
     } else {
       beta = -copysign(sqrt(alpha * alpha + s), alpha);
-      tau = (beta - alpha) / beta;
+      tv = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    for (int r = j + 1 + tid; r < n; r += ST) sv[r] = (r == j + 1) ? 1.0 : col[r] * scale;
+    for (int r = j + 1 + tid; r < n; r += NT) sv[r] = (r == j + 1) ? 1.0 : col[r] * scale;
     __syncthreads();
-    for (int r = j + 2 + tid; r < n; r += ST) col[r] = sv[r];
+    for (int r = j + 2 + tid; r < n; r += NT) col[r] = sv[r];
     if (tid == 0) {
-      W.dd[j] = A[j + (int64_t)j * n];
-      W.ee[j] = beta;
-      W.tau[j] = tau;
+      dd[j] = A[j + (int64_t)j * ldA];
+      ee[j] = beta;
+      tau[j] = tv;
     }
-    if (tau == 0.0) {
+    if (tv == 0.0) {
       __syncthreads();
       continue;
     }
-    // p = tau * A22 v, one wave per column (A22 symmetric, columns contiguous)
-    for (int r = j + 1 + wid; r < n; r += NW) {
-      const double* ac = A + (int64_t)r * n;
-      double acc = 0.0;
-      for (int c = j + 1 + lane; c < n; c += 64) acc += ac[c] * sv[c];
-      acc = wave_sum(acc);
-      if (lane == 0) sw[r] = tau * acc;
+    // p = tau * A22 v (A22 symmetric: column r equals row r)
+    if (lds_a) {
+      for (int r = j + 1 + tid; r < n; r += NT) {
+        const double* ac = A + (int64_t)r * ldA;
+        double acc = 0.0;
+        for (int c = j + 1; c < n; ++c) acc += ac[c] * sv[c];
+        sw[r] = tv * acc;
+      }
+    } else {
+      for (int r = j + 1 + wid; r < n; r += NW) {
+        const double* ac = A + (int64_t)r * ldA;
+        double acc = 0.0;
+        for (int c = j + 1 + lane; c < n; c += 64) acc += ac[c] * sv[c];
+        acc = wave_sum(acc);
+        if (lane == 0) sw[r] = tv * acc;
+      }
     }
     __syncthreads();
     double kk = 0.0;
-    for (int r = j + 1 + tid; r < n; r += ST) kk += sw[r] * sv[r];
-    kk = blk_sum(kk, red);
-    const double K = 0.5 * tau * kk;
-    for (int r = j + 1 + tid; r < n; r += ST) sw[r] -= K * sv[r];
+    for (int r = j + 1 + tid; r < n; r += NT) kk += sw[r] * sv[r];
+    kk = blk_sum<NT>(kk, red);
+    const double K = 0.5 * tv * kk;
+    for (int r = j + 1 + tid; r < n; r += NT) sw[r] -= K * sv[r];
     __syncthreads();
     const int64_t mm = (int64_t)m1 * m1;
-    for (int64_t e = tid; e < mm; e += ST) {
+    for (int64_t e = tid; e < mm; e += NT) {
       const int c = j + 1 + (int)(e / m1), r = j + 1 + (int)(e % m1);
-      A[r + (int64_t)c * n] -= sv[r] * sw[c] + sw[r] * sv[c];
+      A[r + (int64_t)c * ldA] -= sv[r] * sw[c] + sw[r] * sv[c];
     }
     __syncthreads();
   }
   if (tid == 0) {
     if (n >= 2) {
-      W.dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * n];
-      W.ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * n];
-      W.tau[n - 2] = 0.0;
+      dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * ldA];
+      ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * ldA];
+      tau[n - 2] = 0.0;
     }
-    W.dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * n];
-    W.ee[n - 1] = 0.0;
+    dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * ldA];
+    ee[n - 1] = 0.0;
   }
   __syncthreads();
 
   // ---- 2. eigenvalues by multisection -------------------------------------
   double* D = sv;
   double* E2 = sw;
-  double lo_g = 1e308, hi_g = -1e308, e2max = 0.0;
-  for (int i = tid; i < n; i += ST) {
-    D[i] = W.dd[i];
-    const double el = (i > 0) ? fabs(W.ee[i - 1]) : 0.0;
-    const double er = (i < n - 1) ? fabs(W.ee[i]) : 0.0;
-    if (i < n - 1) {
-      E2[i] = W.ee[i] * W.ee[i];
-      e2max = fmax(e2max, E2[i]);
-    }
-    lo_g = fmin(lo_g, W.dd[i] - el - er);
-    hi_g = fmax(hi_g, W.dd[i] + el + er);
+  double lo_g = 1e308, hi_g = -1e308;
+  for (int i = tid; i < n; i += NT) {
+    D[i] = dd[i];
+    const double el = (i > 0) ? fabs(ee[i - 1]) : 0.0;
+    const double er = (i < n - 1) ? fabs(ee[i]) : 0.0;
+    if (i < n - 1) E2[i] = ee[i] * ee[i];
+    lo_g = fmin(lo_g, dd[i] - el - er);
+    hi_g = fmax(hi_g, dd[i] + el + er);
   }
-  lo_g = blk_min(lo_g, red);
-  hi_g = blk_max(hi_g, red);
-  e2max = blk_max(e2max, red);
+  lo_g = blk_min<NT>(lo_g, red);
+  hi_g = blk_max<NT>(hi_g, red);
   double tnorm = fmax(fabs(lo_g), fabs(hi_g));
   const bool zero_mat = !(tnorm > 0.0);
   if (zero_mat) tnorm = 1.0;
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
-  const double fudge = 2.0 * eps * tnorm + 2.0 * pivmin;
+  const double fudge = 4.0 * eps * tnorm;
   const double atol = 0.5 * eps * tnorm;
   int g = 1;
-  while (g < 64 && 2 * g * n <= ST) g *= 2;
-  const int groups = ST / g;
+  while (g < 64 && 2 * g * n <= NT) g *= 2;
+  const int groups = NT / g;
   const int gl = tid % g, gi = tid / g;
   for (int base = 0; base < n; base += groups) {
     const int i = base + gi;
@@ -361,7 +404,7 @@ __global__ __launch_bounds__(ST) void syev_kernel(int nfix, const int* __restric
       for (int it = 0; it < 200; ++it) {
         if (hi - lo <= fmax(atol, 2.0 * eps * fmax(fabs(lo), fabs(hi)))) break;
         const double x = lo + (double)(gl + 1) * ((hi - lo) / (double)(g + 1));
-        const int cnt = sturm_count(n, D, E2, x, pivmin);
+        const int cnt = sturm_count(n, D, E2, x);
         double nlo = (cnt <= i) ? x : lo;
         double nhi = (cnt > i) ? x : hi;
         for (int m = 1; m < g; m <<= 1) {
@@ -372,49 +415,85 @@ __global__ __launch_bounds__(ST) void syev_kernel(int nfix, const int* __restric
         lo = nlo;
         hi = nhi;
       }
-      if (gl == 0) W.lam[i] = 0.5 * (lo + hi);
+      if (gl == 0) lamv[i] = 0.5 * (lo + hi);
     }
   }
   __syncthreads();
 
   // ---- 3. eigenvectors of T by inverse iteration ---------------------------
-  // Every wanted eigenvector is computed independently, one thread each
-  // (random start, three solves with T - lambda I).  Eigenvalues closer than
-  // ctol (relative to ||T||) form a cluster, whose vectors are then
-  // orthonormalised together by modified Gram-Schmidt (twice), one wave per
-  // cluster: the independent iterates span the cluster's invariant subspace,
-  // and within it mixing only happens between eigenvalues closer than ctol.
   const int n0 = n - nv;  // first computed eigenvalue index
   const double tiny = eps * tnorm;
   const double ctol = 1e-3 * tnorm;
-  for (int slot0 = 0; slot0 < nv; slot0 += ST) {
+  for (int slot0 = 0; slot0 < nv; slot0 += NT) {
     const int slot = slot0 + tid;
     if (slot < nv) {
       const int i = n0 + slot;
-      double* lu = W.lu + tid;
-      tri_factor(n, D, W.ee, W.lam[i], tiny, lu, nmax);
-      double* y = W.Zt + slot;
-      random_start(n, i, y, nv, 0, 1);
+      double* lu = lub + tid;
+      tri_factor<NT>(n, D, ee, lamv[i], tiny, lu, nmax);
+      double* y = Zt + slot;
+      random_start(n, i, y, nv);
       for (int it = 0; it < 3; ++it) {
-        tri_solve(n, lu, nmax, y, nv);
+        tri_solve<NT>(n, lu, nmax, y, nv);
         normalize_serial(n, y, nv);
       }
     }
   }
   __syncthreads();
+
+  // ---- 3b. orthonormalise clusters of close eigenvalues --------------------
+  // The independent iterates of a cluster (gap <= ctol) span its invariant
+  // subspace; they are orthonormalised together, which mixes only vectors of
+  // eigenvalues closer than ctol.
   {
-    int cl = 0;
-    int a = n0;
+    int a = n0, cl = 0;
     while (a < n) {
       int b = a + 1;
-      while (b < n && (W.lam[b] - W.lam[b - 1]) <= ctol) ++b;
-      if (b - a > 1) {
+      while (b < n && (lamv[b] - lamv[b - 1]) <= ctol) ++b;
+      const int c = b - a;
+      if (c > 1 && c <= kClusterMax) {
+        const int s0 = a - n0;
+        for (int pass = 0; pass < 2; ++pass) {
+          const int np = c * (c + 1) / 2;
+          for (int p = tid; p < np; p += NT) {
+            int i = 0;
+            while ((i + 1) * (i + 2) / 2 <= p) ++i;
+            const int jj = p - i * (i + 1) / 2;
+            double sdot = 0.0;
+            for (int pos = 0; pos < n; ++pos)
+              sdot += Zt[(int64_t)pos * nv + s0 + i] * Zt[(int64_t)pos * nv + s0 + jj];
+            Gc[i + jj * c] = sdot;
+          }
+          __syncthreads();
+          for (int jc = 0; jc < c; ++jc) {  // Cholesky G = L L^T, lower triangle
+            if (tid == 0) Gc[jc + jc * c] = sqrt(fmax(Gc[jc + jc * c], 1e-300));
+            __syncthreads();
+            for (int i = jc + 1 + tid; i < c; i += NT) Gc[i + jc * c] /= Gc[jc + jc * c];
+            __syncthreads();
+            const int rem = c - jc - 1;
+            for (int e = tid; e < rem * rem; e += NT) {
+              const int cc = jc + 1 + e / rem, r = jc + 1 + e % rem;
+              if (r >= cc) Gc[r + cc * c] -= Gc[r + jc * c] * Gc[cc + jc * c];
+            }
+            __syncthreads();
+          }
+          // each row z of the cluster block becomes z L^{-T} (forward substitution)
+          for (int pos = tid; pos < n; pos += NT) {
+            double* zr = Zt + (int64_t)pos * nv + s0;
+            for (int j2 = 0; j2 < c; ++j2) {
+              double sacc = zr[j2];
+              for (int i = 0; i < j2; ++i) sacc -= zr[i] * Gc[j2 + i * c];
+              zr[j2] = sacc / Gc[j2 + j2 * c];
+            }
+          }
+          __syncthreads();
+        }
+      } else if (c > kClusterMax) {
         if ((cl % NW) == wid) {
           for (int pass = 0; pass < 2; ++pass) {
             for (int i = a; i < b; ++i) {
-              double* y = W.Zt + (i - n0);
+              double* y = Zt + (i - n0);
               for (int k = a; k < i; ++k) {
-                const double* zk = W.Zt + (k - n0);
+                const double* zk = Zt + (k - n0);
                 double dot = 0.0;
                 for (int pos = lane; pos < n; pos += 64)
                   dot += zk[(int64_t)pos * nv] * y[(int64_t)pos * nv];
@@ -434,27 +513,40 @@ __global__ __launch_bounds__(ST) void syev_kernel(int nfix, const int* __restric
   __syncthreads();
 
   // ---- 4. back-transformation z <- H_0 H_1 ... H_{n-3} z ------------------
-  {
-    const int rb = (n > 0) ? (int)std::max<int64_t>(1, (int64_t)(2 * SYEV_NMAX) / n) : 1;
-    double* R = sbuf;  // reflectors staged in LDS: rb x n <= 2 * SYEV_NMAX
+  if (lds_a) {
+    for (int slot = tid; slot < nv; slot += NT) {
+      double* z = Zt + slot;
+      for (int j = n - 3; j >= 0; --j) {
+        const double tj = tau[j];
+        if (tj == 0.0) continue;
+        const double* v = A + (int64_t)j * ldA;  // v[j+1] = 1 implicit, v[r] for r > j+1
+        double s = z[(int64_t)(j + 1) * nv];
+        for (int r = j + 2; r < n; ++r) s += v[r] * z[(int64_t)r * nv];
+        s *= tj;
+        z[(int64_t)(j + 1) * nv] -= s;
+        for (int r = j + 2; r < n; ++r) z[(int64_t)r * nv] -= s * v[r];
+      }
+    }
+  } else {
+    const int rb = (int)std::max<int64_t>(1, (int64_t)kStage / n);
     for (int jt = n - 3; jt >= 0; jt -= rb) {
       const int jb = std::max(0, jt - rb + 1);  // reflectors jb..jt
       __syncthreads();
-      for (int64_t e = tid; e < (int64_t)(jt - jb + 1) * n; e += ST) {
+      for (int64_t e = tid; e < (int64_t)(jt - jb + 1) * n; e += NT) {
         const int jj = (int)(e / n), r = (int)(e - (int64_t)jj * n);
         const int j = jb + jj;
         double v = 0.0;
         if (r == j + 1) v = 1.0;
-        else if (r > j + 1) v = A[r + (int64_t)j * n];
-        R[e] = v;
+        else if (r > j + 1) v = A[r + (int64_t)j * ldA];
+        stage[e] = v;
       }
       __syncthreads();
-      for (int slot = tid; slot < nv; slot += ST) {
-        double* z = W.Zt + slot;
+      for (int slot = tid; slot < nv; slot += NT) {
+        double* z = Zt + slot;
         for (int j = jt; j >= jb; --j) {
-          const double tj = W.tau[j];
+          const double tj = tau[j];
           if (tj == 0.0) continue;
-          const double* v = R + (int64_t)(j - jb) * n;
+          const double* v = stage + (int64_t)(j - jb) * n;
           double s = 0.0;
           for (int r = j + 1; r < n; ++r) s += v[r] * z[(int64_t)r * nv];
           s *= tj;
@@ -466,27 +558,47 @@ __global__ __launch_bounds__(ST) void syev_kernel(int nfix, const int* __restric
   __syncthreads();
 
   // ---- 5. outputs ----------------------------------------------------------
-  for (int i = tid; i < n; i += ST) wq[i] = zero_mat ? 0.0 : W.lam[i];
-  for (int64_t e = tid; e < (int64_t)nv * n; e += ST) {
+  for (int i = tid; i < n; i += NT) wq[i] = zero_mat ? 0.0 : lamv[i];
+  for (int64_t e = tid; e < (int64_t)nv * n; e += NT) {
     const int slot = (int)(e / n), pos = (int)(e - (int64_t)slot * n);
-    Zq[pos + (int64_t)(n0 + slot) * ldz] = W.Zt[(int64_t)pos * nv + slot];
+    Zq[pos + (int64_t)(n0 + slot) * ldz] = Zt[(int64_t)pos * nv + slot];
   }
+}
+
+template <int NT>
+hipError_t syev_launch_t(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
+                         int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
+                         int64_t strideZ, int64_t nvec, double* work, hipStream_t s) {
+  const bool lds_a = n <= kLdsMax;
+  const size_t lds = (size_t)syev_lds_doubles(n, lds_a) * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)syev_kernel<NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(syev_kernel<NT>, dim3((unsigned)batch), dim3(NT), lds, s, (int)n, ns, A, lda,
+                     strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n, lds_a ? 1 : 0);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 size_t syev_work_bytes(int64_t nmax) {
-  const int64_t per = 5 * nmax + 2 * nmax * nmax + 5 * nmax * (int64_t)ST;
-  return (size_t)per * sizeof(double);
+  // the larger thread count sizes the per-thread LU storage
+  return (size_t)syev_work_doubles(nmax, 1024) * sizeof(double);
 }
 
 hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
                        int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
                        int64_t strideZ, int64_t nvec, double* work, hipStream_t s) {
   if (n < 1 || n > SYEV_NMAX || batch < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(syev_kernel, dim3((unsigned)batch), dim3(ST), 0, s, (int)n, ns, A, lda,
-                     strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n);
-  return hipGetLastError();
+  if (n <= 256)
+    return syev_launch_t<256>(batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ, nvec,
+                              work, s);
+  return syev_launch_t<1024>(batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ, nvec,
+                             work, s);
 }
 
 }  // namespace eda

@@ -132,7 +132,8 @@ def check_eig(A, w, Z, tol_res=1e-12):
     assert np.abs(Z.T @ Z - np.eye(A.shape[0])).max() <= 1e-12
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 63, 64, 65, 128, 200, 257])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 63, 64, 65, 100, 112, 113, 128, 200, 257,
+                               600])
 def test_syev_random(torch, eda, n):
     log(f"syev random n={n}")
     rng = np.random.default_rng(100 + n)
@@ -186,8 +187,18 @@ def test_expmv_c1(torch, eda, c1, b):
     h.close()
 
 
-def test_opmv_c1(torch, eda, c1):
-    log("opmv C1 (Lanczos M and Arnoldi A)")
+@pytest.fixture(params=["poly", "eig"])
+def wcore(request, monkeypatch):
+    """W-cores by the matrix polynomial (default) or by eig(H_W^T H_W)."""
+    if request.param == "eig":
+        monkeypatch.setenv("EDA_WCORE", "eig")
+    else:
+        monkeypatch.delenv("EDA_WCORE", raising=False)
+    return request.param
+
+
+def test_opmv_c1(torch, eda, c1, wcore):
+    log(f"opmv C1 (Lanczos M and Arnoldi A), W-core by {wcore}")
     h, _, _ = prepared(torch, eda, c1)
     V = np.random.default_rng(5).standard_normal((c1.d, 8))
     M = O.lanczos_matrix_dense(c1.H_W, c1.H_B)
@@ -201,10 +212,10 @@ def test_opmv_c1(torch, eda, c1):
     h.close()
 
 
-def test_expmv_opmv_c2_full_size(torch, eda, c2):
+def test_expmv_opmv_c2_full_size(torch, eda, c2, wcore):
     """d=10304, n=200, k=40 at b=8, the launch shape the solver uses; the
     oracle is the closed form of Theorem 3.1 (QR + SVD), norms from the same."""
-    log("expmv/opmv C2 full size")
+    log(f"expmv/opmv C2 full size, W-core by {wcore}")
     h, _, _ = prepared(torch, eda, c2)
     V = np.random.default_rng(9).standard_normal((c2.d, 8))
     sW = np.linalg.svd(c2.H_W, compute_uv=False) ** 2
@@ -261,8 +272,8 @@ def test_solve_c1(torch, eda, c1):
     h.close()
 
 
-def test_solve_c2(torch, eda, c2):
-    log("solve C2 t=39 b=8 tol=1e-10")
+def test_solve_c2(torch, eda, c2, wcore):
+    log(f"solve C2 t=39 b=8 tol=1e-10, W-core by {wcore}")
     red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
     h, _, _ = prepared(torch, eda, c2)
     sb = datagen.start_block(c2.d, 8, 2)
