@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdio>
 
 namespace eda {
 
@@ -32,13 +33,28 @@ template <typename T> __device__ __forceinline__ T from_f64(double x);
 template <> __device__ __forceinline__ double from_f64<double>(double x) { return x; }
 template <> __device__ __forceinline__ float from_f64<float>(double x) { return (float)x; }
 
+// bfloat16 (round to nearest even from float).
+using bf16_t = __hip_bfloat16;
+template <> __device__ __forceinline__ double to_f64<bf16_t>(bf16_t x) {
+  return (double)__bfloat162float(x);
+}
+template <> __device__ __forceinline__ float to_acc<float, bf16_t>(bf16_t x) {
+  return __bfloat162float(x);
+}
+template <> __device__ __forceinline__ double to_acc<double, bf16_t>(bf16_t x) {
+  return (double)__bfloat162float(x);
+}
+template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) {
+  return __float2bfloat16((float)x);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (implemented in the .hip files, called by eda_host.cpp).
 // All take the stream last and return hipError_t of the launch.
 // Shapes are validated by the caller; each launcher documents what it needs.
 // ---------------------------------------------------------------------------
 
-enum class DT : int { F64 = 0, F32 = 1 };
+enum class DT : int { F64 = 0, F32 = 1, BF16 = 2 };
 
 // k_basic.hip ---------------------------------------------------------------
 // H_W, H_B from class-contiguous samples (counts given as offsets[k+1] on device).
@@ -111,10 +127,11 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
                                   double zalpha, double* Z_row, int64_t ldz, const int* gate,
                                   hipStream_t s);
 // Out = alpha * V + A * Z, Z row-major (Z[i*ldz + j]) float64, m columns of A.
+// Out column-major (Out[r + j*ldo]) or, with out_row, row-major (Out[r*ldo + j]).
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
-                     hipStream_t s);
+                     hipStream_t s, bool out_row = false);
 
 // k_gemm.hip ----------------------------------------------------------------
 // C (m x n) = alpha * op(A) * diag(dk) * op(B) + beta * C, float64, col-major.
@@ -145,7 +162,7 @@ hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* h
                         int64_t ldr, int* mask, int* flag, hipStream_t s);
 // Q[:, j] = seeded Gaussian for the columns with mask[j] != 0.
 hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
-                                    double* Q, int64_t ldq, hipStream_t s);
+                                    void* Q, DT qdt, int64_t ldq, hipStream_t s);
 
 // k_syev.hip ----------------------------------------------------------------
 // Batched symmetric eigensolver, one workgroup per matrix. For matrix q:
@@ -154,6 +171,8 @@ hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint6
 // eigenvectors are computed for the top nvec_q = min(nvec, n_q) eigenvalues
 // (nvec <= 0: all) and stored in columns n_q-nvec_q .. n_q-1 of Z_q.
 size_t syev_work_bytes(int64_t nmax);
+void syev_timing_enable(bool on);
+void syev_timing_report(FILE* f);
 hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
                        int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
                        int64_t strideZ, int64_t nvec, double* work, hipStream_t s);

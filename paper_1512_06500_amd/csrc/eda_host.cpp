@@ -154,11 +154,12 @@ eda_status expop(eda_handle h, int64_t c0, int64_t Nc, const double* C, int64_t 
   STCHK(ensure(h, h->Zsm, (size_t)Nc * b * 8));
   HIPCHK(launch_tn_partial(h->d, Nc, b, Pc, pdt, h->ldp, V, vdt, ldv, h->part.d(), chunks,
                            nullptr, h->stream));
-  HIPCHK(launch_reduce_partials(chunks, Nc, b, h->part.d(), 1.0, 0.0, h->Ysm.d(), Nc, 0.0,
-                                nullptr, 0, nullptr, h->stream));
-  // Z^T (b x Nc) = Y^T C^T, i.e. Z row-major with leading dimension b
-  HIPCHK(launch_gemm(true, true, b, Nc, Nc, 1.0, h->Ysm.d(), Nc, nullptr, C, ldc, 0.0,
-                     h->Zsm.d(), b, h->stream));
+  // Y = P_c^T V (row-major, leading dimension b), then Z = C Y (row-major) by
+  // the same streaming kernel with C as the tall operand
+  HIPCHK(launch_reduce_partials(chunks, Nc, b, h->part.d(), 0.0, 0.0, nullptr, 0, 1.0,
+                                h->Ysm.d(), b, nullptr, h->stream));
+  HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, h->Ysm.d(), b, 0.0, nullptr, DT::F64, 0,
+                   h->Zsm.d(), DT::F64, b, nullptr, h->stream, true));
   HIPCHK(launch_nn(h->d, Nc, b, Pc, pdt, h->ldp, h->Zsm.d(), b, alpha, V, vdt, ldv, Out, odt,
                    ldo, nullptr, h->stream));
   return EDA_OK;
@@ -359,11 +360,16 @@ eda_status eda_create(eda_handle* out, void* hip_stream) {
     return fail(h, EDA_ERR_HIP, "no HIP device: the handle can only validate arguments");
   }
   h->device = dev;
+  if (std::getenv("EDA_SYEV_TIMERS") != nullptr) syev_timing_enable(true);
   return EDA_OK;
 }
 
 void eda_destroy(eda_handle h) {
   if (h == nullptr) return;
+  if (h->device >= 0 && std::getenv("EDA_SYEV_TIMERS") != nullptr) {
+    (void)hipStreamSynchronize(h->stream);
+    syev_timing_report(stderr);
+  }
   if (h->device >= 0) {
     (void)hipStreamSynchronize(h->stream);
     Buf* all[] = {&h->polyws, &h->normbuf,

@@ -326,8 +326,10 @@ hipError_t launch_pack(int64_t d, int64_t ldp, int64_t cols, const double* H, in
   dim3 g(nblk(ldp), (unsigned)cols);
   if (pdt == DT::F64)
     hipLaunchKernelGGL(pack_kernel<double>, g, dim3(256), 0, s, d, ldp, H, ldh, (double*)P, col0);
-  else
+  else if (pdt == DT::F32)
     hipLaunchKernelGGL(pack_kernel<float>, g, dim3(256), 0, s, d, ldp, H, ldh, (float*)P, col0);
+  else
+    hipLaunchKernelGGL(pack_kernel<bf16_t>, g, dim3(256), 0, s, d, ldp, H, ldh, (bf16_t*)P, col0);
   return hipGetLastError();
 }
 

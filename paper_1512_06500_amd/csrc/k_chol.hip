@@ -232,9 +232,10 @@ __global__ __launch_bounds__(64) void pchol_kernel(int b, const double* __restri
 }
 
 // Q[:, j] = seeded Gaussian for every column j with mask[j] != 0.
+template <typename T>
 __global__ __launch_bounds__(256) void fill_masked_randn_kernel(int64_t d, int64_t b,
                                                                 const int* __restrict__ mask,
-                                                                uint64_t seed, double* Q,
+                                                                uint64_t seed, T* Q,
                                                                 int64_t ldq) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= d * b) return;
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void fill_masked_randn_kernel(int64_t d, int64
   z2 ^= z2 >> 31;
   const double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;
   const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
-  Q[r + c * ldq] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+  Q[r + c * ldq] = from_f64<T>(sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2));
 }
 
 }  // namespace
@@ -265,9 +266,16 @@ hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* h
 }
 
 hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
-                                    double* Q, int64_t ldq, hipStream_t s) {
-  hipLaunchKernelGGL(fill_masked_randn_kernel, dim3((unsigned)((d * b + 255) / 256)), dim3(256), 0,
-                     s, d, b, mask, seed, Q, ldq);
+                                    void* Q, DT qdt, int64_t ldq, hipStream_t s) {
+  const dim3 g((unsigned)((d * b + 255) / 256));
+  if (qdt == DT::F64)
+    hipLaunchKernelGGL(fill_masked_randn_kernel<double>, g, dim3(256), 0, s, d, b, mask, seed,
+                       (double*)Q, ldq);
+  else if (qdt == DT::F32)
+    hipLaunchKernelGGL(fill_masked_randn_kernel<float>, g, dim3(256), 0, s, d, b, mask, seed,
+                       (float*)Q, ldq);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

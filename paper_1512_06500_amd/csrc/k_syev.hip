@@ -15,6 +15,8 @@
 //      close eigenvalues (Cholesky QR twice by the whole workgroup, or
 //      modified Gram-Schmidt for very large clusters).
 //   4. Back-transformation by the stored reflectors, one thread per vector.
+#include <cstdio>
+
 #include "common.h"
 
 namespace eda {
@@ -89,7 +91,31 @@ __device__ __forceinline__ int sturm_count(int n, const double* __restrict__ D,
   double pm1 = D[0] - x;   // p_{k-1} = p_0
   if (pm1 == 0.0) pm1 = -0x1.0p-1000;
   int c = (pm1 < 0.0);
-  for (int k = 1; k < n; ++k) {
+  auto step = [&](double dk, double e2k) {
+    double p = (dk - x) * pm1 - e2k * pm2;
+    if (p == 0.0) p = (pm1 < 0.0) ? 0x1.0p-1000 : -0x1.0p-1000;
+    c += ((p < 0.0) != (pm1 < 0.0));
+    const double ap = fabs(p);
+    if (ap > hi) {
+      p *= lo;
+      pm1 *= lo;
+    } else if (ap < lo && fabs(pm1) < lo) {
+      p *= hi;
+      pm1 *= hi;
+    }
+    pm2 = pm1;
+    pm1 = p;
+  };
+  int k = 1;
+  for (; k + 3 < n; k += 4) {  // loads of four steps issued together
+    const double d0 = D[k], d1 = D[k + 1], d2 = D[k + 2], d3 = D[k + 3];
+    const double f0 = E2[k - 1], f1 = E2[k], f2 = E2[k + 1], f3 = E2[k + 2];
+    step(d0, f0);
+    step(d1, f1);
+    step(d2, f2);
+    step(d3, f3);
+  }
+  for (; k < n; ++k) {
     double p = (D[k] - x) * pm1 - E2[k - 1] * pm2;
     if (p == 0.0) p = (pm1 < 0.0) ? 0x1.0p-1000 : -0x1.0p-1000;
     c += ((p < 0.0) != (pm1 < 0.0));
@@ -170,8 +196,31 @@ __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
   const double* Pv = lu + 4 * nmax * NT;
 #define LU(arr, k) arr[(int64_t)(k) * NT]
 #define YV(k) y[(int64_t)(k) * ys]
+  // Loads are issued four steps at a time: each original entry is read once,
+  // before the step that overwrites it.
   double carry = YV(0);
-  for (int k = 0; k < n - 1; ++k) {
+  int k = 0;
+  for (; k + 4 <= n - 1; k += 4) {
+    double yb[4], pv[4], lm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      yb[q] = YV(k + 1 + q);
+      pv[q] = LU(Pv, k + q);
+      lm[q] = LU(Lm, k + q);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double a = carry, b = yb[q];
+      if (pv[q] != 0.0) {
+        const double t = a;
+        a = b;
+        b = t;
+      }
+      YV(k + q) = a;
+      carry = b - lm[q] * a;
+    }
+  }
+  for (; k < n - 1; ++k) {
     double a = carry, b = YV(k + 1);
     if (LU(Pv, k) != 0.0) {
       const double t = a;
@@ -184,7 +233,33 @@ __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
   YV(n - 1) = carry;
   const double big = 0x1.0p300, small = 0x1.0p-300;
   double x2 = 0.0, x1 = 0.0;  // x[k+2], x[k+1]
-  for (int k = n - 1; k >= 0; --k) {
+  k = n - 1;
+  for (; k >= 3; k -= 4) {
+    double yv[4], u1[4], u2[4], u3[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      yv[q] = YV(k - q);
+      u1[q] = LU(U1, k - q);
+      u2[q] = LU(U2, k - q);
+      u3[q] = LU(U3, k - q);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double x = (yv[q] - u2[q] * x1 - u3[q] * x2) * u1[q];
+      if (!(fabs(x) < big)) {
+        for (int j = 0; j < n; ++j) YV(j) *= small;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yv[r] *= small;
+        x1 *= small;
+        x2 *= small;
+        x = (yv[q] - u2[q] * x1 - u3[q] * x2) * u1[q];
+      }
+      YV(k - q) = x;
+      x2 = x1;
+      x1 = x;
+    }
+  }
+  for (; k >= 0; --k) {
     double x = (YV(k) - LU(U2, k) * x1 - LU(U3, k) * x2) * LU(U1, k);
     if (!(fabs(x) < big)) {
       for (int j = 0; j < n; ++j) YV(j) *= small;
@@ -248,6 +323,18 @@ __host__ __device__ inline int64_t syev_lds_doubles(int64_t n, bool lds_a) {
   return lds_a ? n * (n + 1) + 2 * n + 16 + kClusterMax * kClusterMax : 2 * n + kStage + 16;
 }
 
+// Optional per-phase cycle counters (matrix 0 of each launch), for profiling.
+__device__ unsigned long long g_syev_cycles[8];
+
+#define SYEV_MARK(ph)                                                           \
+  do {                                                                          \
+    if (timing && q == 0 && tid == 0) {                                         \
+      const unsigned long long now_ = clock64();                                \
+      atomicAdd(&g_syev_cycles[ph], now_ - t_prev);                             \
+      t_prev = now_;                                                            \
+    }                                                                           \
+  } while (0)
+
 template <int NT>
 __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restrict__ ns,
                                                   const double* __restrict__ Ain, int64_t lda,
@@ -255,7 +342,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
                                                   int64_t stridew, double* __restrict__ Zout,
                                                   int64_t ldz, int64_t strideZ, int nvec_req,
                                                   double* __restrict__ work, int64_t nmax,
-                                                  int lds_a) {
+                                                  int lds_a, int timing) {
   constexpr int NW = NT / 64;
   extern __shared__ double smem[];
   const int q = blockIdx.x;
@@ -294,6 +381,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   }
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const double eps = 0x1.0p-53;
+  unsigned long long t_prev = clock64();
 
   // ---- 0. symmetrised working copy (lower triangle of the input) ---------
   for (int64_t e = tid; e < (int64_t)n * n; e += NT) {
@@ -302,6 +390,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   }
   __syncthreads();
 
+  SYEV_MARK(0);
   // ---- 1. Householder tridiagonalisation ---------------------------------
   for (int j = 0; j < n - 2; ++j) {
     const int m1 = n - j - 1;
@@ -374,6 +463,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   }
   __syncthreads();
 
+  SYEV_MARK(1);
   // ---- 2. eigenvalues by multisection -------------------------------------
   double* D = sv;
   double* E2 = sw;
@@ -420,6 +510,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   }
   __syncthreads();
 
+  SYEV_MARK(2);
   // ---- 3. eigenvectors of T by inverse iteration ---------------------------
   const int n0 = n - nv;  // first computed eigenvalue index
   const double tiny = eps * tnorm;
@@ -440,6 +531,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   }
   __syncthreads();
 
+  SYEV_MARK(3);
   // ---- 3b. orthonormalise clusters of close eigenvalues --------------------
   // The independent iterates of a cluster (gap <= ctol) span its invariant
   // subspace; they are orthonormalised together, which mixes only vectors of
@@ -512,58 +604,58 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   }
   __syncthreads();
 
-  // ---- 4. back-transformation z <- H_0 H_1 ... H_{n-3} z ------------------
-  if (lds_a) {
-    for (int slot = tid; slot < nv; slot += NT) {
-      double* z = Zt + slot;
-      for (int j = n - 3; j >= 0; --j) {
-        const double tj = tau[j];
-        if (tj == 0.0) continue;
-        const double* v = A + (int64_t)j * ldA;  // v[j+1] = 1 implicit, v[r] for r > j+1
-        double s = z[(int64_t)(j + 1) * nv];
-        for (int r = j + 2; r < n; ++r) s += v[r] * z[(int64_t)r * nv];
-        s *= tj;
-        z[(int64_t)(j + 1) * nv] -= s;
-        for (int r = j + 2; r < n; ++r) z[(int64_t)r * nv] -= s * v[r];
-      }
+  SYEV_MARK(4);
+  // ---- 4. back-transformation ---------------------------------------------
+  // Q = H_0 H_1 ... H_{n-3} is formed in place of the reflectors (backward
+  // accumulation: Q_j = H_j Q_{j+1}, whose non-trivial block is rows and
+  // columns >= j+1; reflector j sits in column j, outside that block), each
+  // reflector applied by the whole workgroup.  Then Z = Q Z_T.
+  if (tid == 0) A[(n - 1) + (int64_t)(n - 1) * ldA] = 1.0;
+  for (int j = n - 3; j >= 0; --j) {
+    for (int e = tid; e < n - j - 2; e += NT) {
+      A[(j + 1) + (int64_t)(j + 2 + e) * ldA] = 0.0;
+      A[(j + 2 + e) + (int64_t)(j + 1) * ldA] = 0.0;
     }
-  } else {
-    const int rb = (int)std::max<int64_t>(1, (int64_t)kStage / n);
-    for (int jt = n - 3; jt >= 0; jt -= rb) {
-      const int jb = std::max(0, jt - rb + 1);  // reflectors jb..jt
-      __syncthreads();
-      for (int64_t e = tid; e < (int64_t)(jt - jb + 1) * n; e += NT) {
-        const int jj = (int)(e / n), r = (int)(e - (int64_t)jj * n);
-        const int j = jb + jj;
-        double v = 0.0;
-        if (r == j + 1) v = 1.0;
-        else if (r > j + 1) v = A[r + (int64_t)j * ldA];
-        stage[e] = v;
+    if (tid == 0) A[(j + 1) + (int64_t)(j + 1) * ldA] = 1.0;
+    __syncthreads();
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      const double* v = A + (int64_t)j * ldA;  // v[j+1] = 1 implicit, v[r] for r > j+1
+      for (int c = j + 1 + tid; c < n; c += NT) {
+        const double* qc = A + (int64_t)c * ldA;
+        double s = qc[j + 1];
+        for (int r = j + 2; r < n; ++r) s += v[r] * qc[r];
+        sw[c] = tj * s;
       }
       __syncthreads();
-      for (int slot = tid; slot < nv; slot += NT) {
-        double* z = Zt + slot;
-        for (int j = jt; j >= jb; --j) {
-          const double tj = tau[j];
-          if (tj == 0.0) continue;
-          const double* v = stage + (int64_t)(j - jb) * n;
-          double s = 0.0;
-          for (int r = j + 1; r < n; ++r) s += v[r] * z[(int64_t)r * nv];
-          s *= tj;
-          for (int r = j + 1; r < n; ++r) z[(int64_t)r * nv] -= s * v[r];
-        }
+      const int m1 = n - j - 1;
+      for (int64_t e = tid; e < (int64_t)m1 * m1; e += NT) {
+        const int c = j + 1 + (int)(e / m1), r = j + 1 + (int)(e % m1);
+        const double vr = (r == j + 1) ? 1.0 : v[r];
+        A[r + (int64_t)c * ldA] -= vr * sw[c];
       }
+      __syncthreads();
     }
   }
+  for (int e = tid; e < n - 1; e += NT) {
+    A[(int64_t)(e + 1) * ldA] = 0.0;  // row 0
+    A[e + 1] = 0.0;                   // column 0
+  }
+  if (tid == 0) A[0] = 1.0;
   __syncthreads();
 
-  // ---- 5. outputs ----------------------------------------------------------
+  SYEV_MARK(5);
+  // ---- 5. outputs: eigenvalues, Z = Q Z_T ---------------------------------
   for (int i = tid; i < n; i += NT) wq[i] = zero_mat ? 0.0 : lamv[i];
   for (int64_t e = tid; e < (int64_t)nv * n; e += NT) {
     const int slot = (int)(e / n), pos = (int)(e - (int64_t)slot * n);
-    Zq[pos + (int64_t)(n0 + slot) * ldz] = Zt[(int64_t)pos * nv + slot];
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += A[pos + (int64_t)r * ldA] * Zt[(int64_t)r * nv + slot];
+    Zq[pos + (int64_t)(n0 + slot) * ldz] = s;
   }
 }
+
+bool syev_timing = false;
 
 template <int NT>
 hipError_t syev_launch_t(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
@@ -579,11 +671,23 @@ hipError_t syev_launch_t(int64_t batch, int64_t n, const int* ns, const double* 
     attr_set = true;
   }
   hipLaunchKernelGGL(syev_kernel<NT>, dim3((unsigned)batch), dim3(NT), lds, s, (int)n, ns, A, lda,
-                     strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n, lds_a ? 1 : 0);
+                     strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n, lds_a ? 1 : 0,
+                     syev_timing ? 1 : 0);
   return hipGetLastError();
 }
 
 }  // namespace
+
+void syev_timing_enable(bool on) { syev_timing = on; }
+
+void syev_timing_report(FILE* f) {
+  unsigned long long c[8] = {0};
+  if (hipMemcpyFromSymbol(c, HIP_SYMBOL(g_syev_cycles), sizeof(c)) != hipSuccess) return;
+  const char* names[6] = {"copy", "tridiag", "eigvals", "invit", "clusters", "backtrans"};
+  std::fprintf(f, "[eda] syev cycles (matrix 0 of every launch):");
+  for (int i = 0; i < 6; ++i) std::fprintf(f, " %s=%llu", names[i], c[i]);
+  std::fprintf(f, "\n");
+}
 
 size_t syev_work_bytes(int64_t nmax) {
   // the larger thread count sizes the per-thread LU storage

@@ -116,8 +116,17 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t chunks, in
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t mn = m * nb;
   if (e >= mn) return;
+  // fixed order; eight independent loads in flight per thread
   double s = 0.0;
-  for (int64_t c = 0; c < chunks; ++c) s += part[c * mn + e];
+  int64_t c = 0;
+  for (; c + 8 <= chunks; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = part[(c + q) * mn + e];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += v[q];
+  }
+  for (; c < chunks; ++c) s += part[c * mn + e];
   const int64_t i = e / nb, j = e - i * nb;
   if (C != nullptr) {
     double* cp = C + i + j * ldc;
@@ -131,7 +140,7 @@ __global__ __launch_bounds__(256) void nn_kernel(int64_t d, int m, int nb, const
                                                  int64_t lda, const double* __restrict__ Z,
                                                  int64_t ldz, double alpha, const TV* __restrict__ V,
                                                  int64_t ldv, TO* __restrict__ Out, int64_t ldo,
-                                                 const int* __restrict__ gate) {
+                                                 int out_row, const int* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
   __shared__ ACC red[3][64][NN_NB + 1];
   const int lane = threadIdx.x & 63;
@@ -175,7 +184,8 @@ __global__ __launch_bounds__(256) void nn_kernel(int64_t d, int m, int nb, const
       if (!jok[j]) continue;
       double o = (double)acc[j];
       if (alpha != 0.0) o += alpha * to_f64<TV>(V[r + (int64_t)(j0 + j) * ldv]);
-      Out[r + (int64_t)(j0 + j) * ldo] = from_f64<TO>(o);
+      const int64_t oi = out_row ? r * ldo + (j0 + j) : r + (int64_t)(j0 + j) * ldo;
+      Out[oi] = from_f64<TO>(o);
     }
   }
 }
@@ -209,10 +219,11 @@ hipError_t tn_launch_t(int64_t d, int64_t m, int64_t nb, const void* A, int64_t 
 template <typename TA, typename TV, typename TO, typename ACC>
 hipError_t nn_launch_t(int64_t d, int64_t m, int64_t nb, const void* A, int64_t lda,
                        const double* Z, int64_t ldz, double alpha, const void* V, int64_t ldv,
-                       void* Out, int64_t ldo, const int* gate, hipStream_t s) {
+                       void* Out, int64_t ldo, bool out_row, const int* gate, hipStream_t s) {
   dim3 g((unsigned)((d + 63) / 64), (unsigned)((nb + NN_NB - 1) / NN_NB));
   hipLaunchKernelGGL((nn_kernel<TA, TV, TO, ACC>), g, dim3(256), 0, s, d, (int)m, (int)nb,
-                     (const TA*)A, lda, Z, ldz, alpha, (const TV*)V, ldv, (TO*)Out, ldo, gate);
+                     (const TA*)A, lda, Z, ldz, alpha, (const TV*)V, ldv, (TO*)Out, ldo,
+                     out_row ? 1 : 0, gate);
   return hipGetLastError();
 }
 
@@ -228,13 +239,20 @@ hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT
                              int64_t lda, const void* B, DT bdt, int64_t ldb, double* part,
                              int64_t chunks, const int* gate, hipStream_t s) {
   if (d <= 0 || m <= 0 || nb <= 0) return hipSuccess;
+  using bf = __hip_bfloat16;
   if (adt == DT::F64 && bdt == DT::F64)
     return tn_launch_t<double, double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   if (adt == DT::F32 && bdt == DT::F32)
     return tn_launch_t<float, float, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   if (adt == DT::F32 && bdt == DT::F64)
     return tn_launch_t<float, double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
-  return tn_launch_t<double, float, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+  if (adt == DT::F64 && bdt == DT::F32)
+    return tn_launch_t<double, float, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+  if (adt == DT::BF16 && bdt == DT::F32)
+    return tn_launch_t<bf, float, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+  if (adt == DT::BF16 && bdt == DT::F64)
+    return tn_launch_t<bf, double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const double* part,
@@ -251,22 +269,23 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
-                     hipStream_t s) {
+                     hipStream_t s, bool out_row) {
   if (d <= 0 || nb <= 0) return hipSuccess;
   // In-place Out == A is only safe when one workgroup column covers all nb.
   if (Out == A && nb > NN_NB) return hipErrorInvalidValue;
-  if (adt == DT::F64 && vdt == DT::F64 && odt == DT::F64)
-    return nn_launch_t<double, double, double, double>(d, m, nb, A, lda, Z, ldz, alpha, V, ldv,
-                                                       Out, ldo, gate, s);
-  if (adt == DT::F32 && vdt == DT::F32 && odt == DT::F32)
-    return nn_launch_t<float, float, float, float>(d, m, nb, A, lda, Z, ldz, alpha, V, ldv, Out,
-                                                   ldo, gate, s);
-  if (adt == DT::F32 && vdt == DT::F64 && odt == DT::F64)
-    return nn_launch_t<float, double, double, double>(d, m, nb, A, lda, Z, ldz, alpha, V, ldv,
-                                                      Out, ldo, gate, s);
-  if (adt == DT::F64 && vdt == DT::F64 && odt == DT::F32)
-    return nn_launch_t<double, double, float, double>(d, m, nb, A, lda, Z, ldz, alpha, V, ldv,
-                                                      Out, ldo, gate, s);
+  using bf = __hip_bfloat16;
+#define NN_CASE(a, v, o, TA, TV, TO, ACC)                                                     \
+  if (adt == DT::a && vdt == DT::v && odt == DT::o)                                           \
+    return nn_launch_t<TA, TV, TO, ACC>(d, m, nb, A, lda, Z, ldz, alpha, V, ldv, Out, ldo,    \
+                                        out_row, gate, s);
+  NN_CASE(F64, F64, F64, double, double, double, double)
+  NN_CASE(F32, F32, F32, float, float, float, float)
+  NN_CASE(F32, F64, F64, float, double, double, double)
+  NN_CASE(F64, F64, F32, double, double, float, double)
+  NN_CASE(F64, F32, F32, double, float, float, double)
+  NN_CASE(BF16, F32, F32, bf, float, float, float)
+  NN_CASE(BF16, F64, F64, bf, double, double, double)
+#undef NN_CASE
   return hipErrorInvalidValue;
 }
 
