@@ -81,13 +81,19 @@ typedef struct {
                                capped by d)                                          */
   int32_t max_iter;         /* maximal block steps (default 4000)                    */
   eda_resmode resmode;
-  eda_dtype krylov_dtype;   /* arithmetic of the Krylov phase (default EDA_F64)      */
-  eda_dtype refine_dtype;   /* reserved (refinement precision); must be EDA_F64      */
+  eda_dtype krylov_dtype;   /* basis type of the Krylov phase: EDA_F64 (default) or
+                               EDA_F32.  The operator of that phase uses the storage
+                               type given to eda_prepare.                            */
+  eda_dtype refine_dtype;   /* arithmetic of the refinement stage; must be EDA_F64   */
   uint64_t seed;            /* start-block seed when start_block is NULL             */
   const void* start_block;  /* device, d x b float64 start block, or NULL            */
   int64_t ld_start;         /* leading dimension of start_block                      */
   int32_t check_every;      /* block steps between Rayleigh-Ritz checks (default 2)  */
-  int32_t reserved[7];
+  int32_t max_refine;       /* float64 refinement passes after the Krylov phase:
+                               0 = default (16 after a phase with a narrower operator
+                               or basis, 2 after a float64 one); < 0 = none, and the
+                               Krylov-phase pairs are returned with float64 residuals */
+  int32_t reserved[6];
 } eda_solve_opts;
 
 /* Per-solve diagnostics. */
@@ -142,9 +148,12 @@ eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k,
 /* Preprocessing of Algorithm 2 (steps 1-4), in Gram form.
  * H_W: device, d x n float64 (ldw >= d); H_B: device, d x k float64 (ldb >= d).
  * Requires d >= 2, k >= 2, n >= k.  The factors are copied into library
- * storage P = [H_W H_B] in `storage` precision (EDA_F64 or EDA_F32), the
- * Gram matrix P^T P is formed in float64, eig(H_W^T H_W) and eig(H_B^T H_B)
- * are computed in float64, and the cores of the exponentials are built.
+ * storage P = [H_W H_B] in `storage` precision (EDA_F64, EDA_F32 or
+ * EDA_BF16; a narrower storage also keeps a float64 master copy, used for
+ * the Gram matrix, the refinement stage of eda_solve and the back-transform),
+ * the Gram matrix P^T P is formed in float64, eig(H_B^T H_B) (and, when
+ * requested, eig(H_W^T H_W)) are computed in float64, and the cores of the
+ * exponentials are built.
  * Returns EDA_ERR_NONFINITE if a factor holds NaN/Inf.  Synchronises. */
 eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k,
                        const double* H_W, int64_t ldw, const double* H_B, int64_t ldb,
@@ -154,7 +163,8 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k,
  *     Out = e^{-s} exp(c S_which) V,   s = max(0, c * lambda_max(S_which)),
  * with s written to *log_scale (host) so that exp(c S) V = e^{s} Out.
  * V: device d x b (ldv >= d); Out: device d x b (ldo >= d), must not overlap V.
- * vdtype: EDA_F64 (V and Out float64) or EDA_F32 (float32).
+ * vdtype: EDA_F64 (V and Out float64) or EDA_F32 (float32); the factor is
+ * read in the storage type of eda_prepare.
  * Stream-ordered; synchronises only when a core for a new c must be built. */
 eda_status eda_expmv(eda_handle h, eda_which which, double c, int64_t b,
                      const void* V, int64_t ldv, void* Out, int64_t ldo, eda_dtype vdtype,
@@ -177,9 +187,15 @@ eda_status eda_opmv(eda_handle h, eda_form form, int64_t b,
  * resid:    host out [t], final residual of each Ritz pair of M, measured
  *           explicitly with one more operator product (measure from opts).
  * info:     host out, may be NULL.
- * Requires 1 <= t < d and t + 2b <= max_basis <= d.  Stops when every pair
- * has residual <= max(tol, 10 u theta_1/theta_i) (u: unit roundoff of the
- * Krylov arithmetic).  EDA_ERR_NOCONV if max_iter is reached (outputs still
+ * Requires 1 <= t <= 128, t < d and t + 2b <= max_basis <= d.
+ * The Krylov phase (block Lanczos with thick restart on e^{-s} M) runs with
+ * the storage type of P and the basis type opts.krylov_dtype, and stops when
+ * every pair has estimated residual <= max(tol, 10 u theta_1/theta_i), u the
+ * larger unit roundoff of the two types.  A float64 stage follows: explicit
+ * residuals with the float64 operator and, while some pair misses
+ * max(tol, 10 u64 theta_1/theta_i), refinement passes (Rayleigh-Ritz on the
+ * Ritz block and its residual block), at most opts.max_refine of them.
+ * EDA_ERR_NOCONV if max_iter or max_refine is exhausted (outputs still
  * written).  Synchronises. */
 eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* opt,
                      double* ritz, double* ritz_log, double* X, int64_t ldx,

@@ -45,7 +45,8 @@ class SolveOpts(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("resmode", ctypes.c_int), ("krylov_dtype", ctypes.c_int),
         ("refine_dtype", ctypes.c_int), ("seed", ctypes.c_uint64),
         ("start_block", ctypes.c_void_p), ("ld_start", ctypes.c_int64),
-        ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("check_every", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -248,7 +249,8 @@ class Handle:
 
     def solve(self, t: int, tol: float, block: int = 8, max_basis: int = 0, max_iter: int = 0,
               seed: int = 0, start_block=None, check_every: int = 0, resmode: str = "rel",
-              raise_on_error: bool = True, X=None) -> SolveResult:
+              krylov_dtype: str = "f64", max_refine: int = 0, raise_on_error: bool = True,
+              X=None) -> SolveResult:
         torch = self._torch
         o = SolveOpts()
         o.form = EDA_FORM_LANCZOS_M
@@ -256,8 +258,9 @@ class Handle:
         o.max_basis = max_basis
         o.max_iter = max_iter
         o.resmode = EDA_RES_REL_THETA if resmode == "rel" else EDA_RES_NORMWISE
-        o.krylov_dtype = EDA_F64
+        o.krylov_dtype = _DTYPES[krylov_dtype]
         o.refine_dtype = EDA_F64
+        o.max_refine = max_refine
         o.seed = seed
         o.check_every = check_every
         if start_block is not None:

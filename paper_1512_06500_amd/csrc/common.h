@@ -104,10 +104,13 @@ hipError_t launch_gather_desc(int64_t m, int64_t cnt, const double* S, int64_t l
                               int64_t ldsd, hipStream_t s);
 // flags[1] |= flags[0]; flags[0] = 0.
 hipError_t launch_flag_fold(int* flags, hipStream_t s);
-// R(:, i) = MY(:, i) - theta_i Y(:, i); res[i] = ||R(:, i)||.
-hipError_t launch_ritz_residual(int64_t d, int64_t t, const void* MY, const void* Y,
-                                int64_t ld, DT dt, const double* theta, double* res,
-                                hipStream_t s);
+// R(:, i) = MY(:, i) - theta_i Y(:, i) (stored when R != null); res[i] = ||R(:, i)||.
+hipError_t launch_ritz_residual(int64_t d, int64_t t, const double* MY, int64_t ldmy,
+                                const double* Y, int64_t ldy, const double* theta, double* R,
+                                int64_t ldr, double* res, hipStream_t s);
+// out[i] = w[n - 1 - i] for i < cnt.
+hipError_t launch_desc_values(int64_t cnt, const double* w, int64_t n, double* out,
+                              hipStream_t s);
 // Restart coupling: Hn[kk + r, c] = sum_q Bm[r, q] * S[m - b + q, c] for c < kk.
 hipError_t launch_restart_coupling(int64_t m, int64_t b, int64_t kk, const double* Bm,
                                    int64_t ldbm, const double* Sd, int64_t ldsd, double* Hn,
@@ -157,9 +160,11 @@ hipError_t launch_chol(int64_t b, const double* G, int64_t ldg, double* Rinv, in
                        const int* gate, hipStream_t s);
 
 // Rank-revealing pivoted Cholesky of a Lanczos block (b <= 64); see k_chol.hip.
+// With `equil`, the block is first scaled to unit column norms (hcol ignored)
+// and the scaling is folded back into Z and R.
 hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
-                        int64_t ldhc, double tau, double ratio, double* Z, int64_t ldz, double* R,
-                        int64_t ldr, int* mask, int* flag, hipStream_t s);
+                        int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
+                        double* R, int64_t ldr, int* mask, int* flag, hipStream_t s);
 // Q[:, j] = seeded Gaussian for the columns with mask[j] != 0.
 hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
                                     void* Q, DT qdt, int64_t ldq, hipStream_t s);

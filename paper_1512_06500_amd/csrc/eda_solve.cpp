@@ -1,0 +1,553 @@
+// libeda host library, part 2: eda_solve.
+//
+// Block Lanczos with thick restart on the shifted symmetric operator
+// e^{-s} M, M = exp(-S_W/2) exp(S_B) exp(-S_W/2) (eqs. (3.13)-(3.16)), which
+// is step 5 of Algorithm 3 in its Lanczos form, followed by
+//   * an explicit float64 check, and if needed float64 refinement passes
+//     (Rayleigh-Ritz on span[Y, R] with the float64 operator), and
+//   * the back-transform x = exp(-S_W/2) y of eq. (3.14) with
+//     orthonormalisation in decreasing-lambda order (Algorithm 3, step 6).
+// The Krylov phase may run on narrower operands: the operator P = [H_W H_B]
+// in the storage type chosen at eda_prepare (float64, float32, bfloat16) and
+// the basis in float64 or float32.  It then stops at the accuracy those
+// types can reach, and the float64 stage takes the pairs to the tolerance.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "host_internal.h"
+
+using namespace eda;
+
+namespace {
+
+double unit_roundoff(DT t) {
+  switch (t) {
+    case DT::F64: return 0x1.0p-53;
+    case DT::F32: return 0x1.0p-24;
+    default: return 0x1.0p-8;  // bfloat16
+  }
+}
+
+struct Solver {
+  eda_handle h;
+  int64_t d, ldq, b, mmax, ldh, t, kk;
+  DT qdt;       // basis type of the Krylov phase
+  int cur = 0;  // which of the two basis/H buffers is live
+  char* Q() const { return h->Q[cur].c(); }
+  char* Qc(int64_t j) const { return Q() + (size_t)j * ldq * dt_size(qdt); }
+  double* H() const { return h->H[cur].d(); }
+};
+
+// One Cholesky QR pass: G = X^T X, Xout = X R^{-1}.  Optionally records R
+// (combined with Rprev) and raises the repair flag.
+eda_status cholqr_pass(eda_handle h, int64_t d, int64_t cols, const void* X, DT xdt, int64_t ldx,
+                       void* Xout, int64_t ldxo, const double* Rprev, double* Rout, int64_t ldro,
+                       const double* hcol, int64_t mrows, int64_t ldhc, const int* gate,
+                       int* flag) {
+  const int64_t chunks = tn_chunks(d, cols, cols);
+  STCHK(ensure(h, h->part, (size_t)chunks * cols * cols * 8));
+  STCHK(ensure(h, h->Gs, (size_t)cols * cols * 8));
+  STCHK(ensure(h, h->Rinv, (size_t)cols * cols * 8));
+  HIPCHK(launch_tn_partial(d, cols, cols, X, xdt, ldx, X, xdt, ldx, h->part.d(), chunks, gate,
+                           h->stream));
+  HIPCHK(launch_reduce_partials(chunks, cols, cols, h->part.d(), 1.0, 0.0, h->Gs.d(), cols, 0.0,
+                                nullptr, 0, gate, h->stream));
+  HIPCHK(launch_chol(cols, h->Gs.d(), cols, h->Rinv.d(), cols, Rprev, cols, Rout, ldro, hcol,
+                     mrows, ldhc, 1e-4, flag, gate, h->stream));
+  HIPCHK(launch_nn(d, cols, cols, X, xdt, ldx, h->Rinv.d(), cols, 0.0, nullptr, xdt, ldx, Xout,
+                   xdt, ldxo, gate, h->stream));
+  return EDA_OK;
+}
+
+// One classical Gram-Schmidt pass of W (b columns) against Q[:, 0:m]:
+//   h = Q^T W (accumulated into Hcol when given),  W -= Q h.
+eda_status cgs_pass(eda_handle h, int64_t d, int64_t m, const void* Q, DT qdt, int64_t ldq,
+                    void* W, int64_t ldw, int64_t b, double* Hcol, int64_t ldh, double beta,
+                    const int* gate) {
+  const int64_t chunks = tn_chunks(d, m, b);
+  STCHK(ensure(h, h->part, (size_t)chunks * m * b * 8));
+  STCHK(ensure(h, h->hz, (size_t)m * b * 8));
+  HIPCHK(launch_tn_partial(d, m, b, Q, qdt, ldq, W, qdt, ldw, h->part.d(), chunks, gate,
+                           h->stream));
+  HIPCHK(launch_reduce_partials(chunks, m, b, h->part.d(), 1.0, beta, Hcol, ldh, -1.0, h->hz.d(),
+                                b, gate, h->stream));
+  HIPCHK(launch_nn(d, m, b, Q, qdt, ldq, h->hz.d(), b, 1.0, W, qdt, ldw, W, qdt, ldw, gate,
+                   h->stream));
+  return EDA_OK;
+}
+
+// Block step: from the basis Q[:, 0:m+b] (current block Q[:, m:m+b]) build
+// Q[:, m+b:m+2b] and column block m of H.
+eda_status lanczos_step(Solver& S, int64_t m) {
+  eda_handle h = S.h;
+  const int64_t d = S.d, b = S.b, ldq = S.ldq, ldh = S.ldh;
+  const DT qdt = S.qdt;
+  double* H = S.H();
+  void* W = h->Wb.p;
+  int* flags = h->flags.i();
+  // W = e^{-s} M V_j in the Krylov-phase types, timed with a pair of events
+  if (h->op_used + 2 > h->op_ev.size()) {
+    for (int q = 0; q < 64; ++q) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      h->op_ev.push_back(e);
+    }
+  }
+  HIPCHK(hipEventRecord(h->op_ev[h->op_used], h->stream));
+  STCHK(expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, b, S.Qc(m), qdt, ldq, W, qdt, ldq));
+  HIPCHK(hipEventRecord(h->op_ev[h->op_used + 1], h->stream));
+  h->op_used += 2;
+  // CGS2 against Q[:, 0:m+b]
+  double* Hcol = H + m * ldh;
+  STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, W, ldq, b, Hcol, ldh, 0.0, nullptr));
+  STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, W, ldq, b, Hcol, ldh, 1.0, nullptr));
+  // Block orthonormalisation, R = R2 R1 going to H[m+b:m+2b, m:m+b].
+  // Pass 1 is rank revealing: directions along which the Krylov space has
+  // become invariant are deflated and replaced by fresh random directions
+  // with zero coupling (their rows of R1 are zero).
+  char* Qn = S.Qc(m + b);
+  {
+    const int64_t chunks = tn_chunks(d, b, b);
+    HIPCHK(launch_tn_partial(d, b, b, W, qdt, ldq, W, qdt, ldq, h->part.d(), chunks, nullptr,
+                             h->stream));
+    HIPCHK(launch_reduce_partials(chunks, b, b, h->part.d(), 1.0, 0.0, h->Gs.d(), b, 0.0, nullptr,
+                                  0, nullptr, h->stream));
+    HIPCHK(launch_pchol(b, h->Gs.d(), b, Hcol, m + b, ldh, 1e-13, 1e-4, false, h->Rinv.d(), b,
+                        h->R1.d(), b, h->mask.i(), flags, h->stream));
+    HIPCHK(launch_nn(d, b, b, W, qdt, ldq, h->Rinv.d(), b, 0.0, nullptr, qdt, ldq, Qn, qdt, ldq,
+                     nullptr, h->stream));
+    HIPCHK(launch_fill_masked_randn(d, b, h->mask.i(), 0x5eed0000ull + (uint64_t)m, Qn, qdt, ldq,
+                                    h->stream));
+  }
+  STCHK(cholqr_pass(h, d, b, Qn, qdt, ldq, Qn, ldq, h->R1.d(), H + (m + b) + m * ldh, ldh,
+                    nullptr, 0, 0, nullptr, flags));
+  // repair (only runs when the flag was raised): re-orthogonalise the new block
+  STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, Qn, ldq, b, nullptr, 0, 0.0, flags));
+  STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, Qn, ldq, b, nullptr, 0, 0.0, flags));
+  STCHK(cholqr_pass(h, d, b, Qn, qdt, ldq, Qn, ldq, nullptr, nullptr, 0, nullptr, 0, 0, flags,
+                    nullptr));
+  STCHK(cholqr_pass(h, d, b, Qn, qdt, ldq, Qn, ldq, nullptr, nullptr, 0, nullptr, 0, 0, flags,
+                    nullptr));
+  HIPCHK(launch_flag_fold(flags, h->stream));
+  return EDA_OK;
+}
+
+void log_pairs(const char* tag, int64_t m, int64_t cnt, const double* theta, const double* est) {
+  std::fprintf(stderr, "[eda] %s m=%lld theta:", tag, (long long)m);
+  for (int64_t i = 0; i < cnt; ++i) std::fprintf(stderr, " %.6e", theta[i]);
+  std::fprintf(stderr, "\n[eda]   res:");
+  for (int64_t i = 0; i < cnt; ++i) std::fprintf(stderr, " %.2e", est[i]);
+  std::fprintf(stderr, "\n");
+}
+
+// Rayleigh-Ritz on Q[:, 0:m]: eigenpairs of sym(H[0:m,0:m]); returns the top
+// `cnt` Ritz values (descending) and residual estimates on the host.
+eda_status rayleigh_ritz(Solver& S, int64_t m, int64_t nvec, int64_t cnt, double* theta,
+                         double* est) {
+  eda_handle h = S.h;
+  const int64_t ldh = S.ldh, mm = S.mmax;
+  HIPCHK(launch_symmetrize(m, S.H(), ldh, h->T.d(), mm, h->stream));
+  HIPCHK(launch_syev(1, m, nullptr, h->T.d(), mm, 0, h->wT.d(), 0, h->S.d(), mm, 0, nvec,
+                     h->syev_work.d(), h->stream));
+  const double* Bm = S.H() + m + (m - S.b) * ldh;
+  HIPCHK(launch_ritz_estimates(m, S.b, cnt, h->wT.d(), h->S.d(), mm, Bm, ldh, h->dtheta.d(),
+                               h->dres.d(), h->stream));
+  HIPCHK(hipMemcpyAsync(theta, h->dtheta.d(), cnt * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(est, h->dres.d(), cnt * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (std::getenv("EDA_LOG") != nullptr) log_pairs("rr", m, cnt, theta, est);
+  return EDA_OK;
+}
+
+// float64 Rayleigh-Ritz on the w columns of B (with MB = M B): the top t
+// Ritz vectors go to Y = B S_t and MY = MB S_t, the Ritz values (descending)
+// to dtheta.  Uses the workspaces T, S, wT, Sd with leading dimension mm.
+eda_status rr_block(eda_handle h, int64_t d, int64_t ld, int64_t w, int64_t t, int64_t mm,
+                    const double* B, const double* MB, double* Y, double* MY) {
+  hipStream_t s = h->stream;
+  const int64_t chunks = tn_chunks(d, w, w);
+  HIPCHK(launch_tn_partial(d, w, w, B, DT::F64, ld, MB, DT::F64, ld, h->part.d(), chunks, nullptr,
+                           s));
+  HIPCHK(launch_reduce_partials(chunks, w, w, h->part.d(), 1.0, 0.0, h->S.d(), mm, 0.0, nullptr, 0,
+                                nullptr, s));
+  HIPCHK(launch_symmetrize(w, h->S.d(), mm, h->T.d(), mm, s));
+  HIPCHK(launch_syev(1, w, nullptr, h->T.d(), mm, 0, h->wT.d(), 0, h->S.d(), mm, 0, t,
+                     h->syev_work.d(), s));
+  HIPCHK(launch_gather_desc(w, t, h->S.d(), mm, h->Sd.d(), t, s));
+  HIPCHK(launch_desc_values(t, h->wT.d(), w, h->dtheta.d(), s));
+  HIPCHK(launch_nn(d, w, t, B, DT::F64, ld, h->Sd.d(), t, 0.0, nullptr, DT::F64, ld, Y, DT::F64,
+                   ld, nullptr, s));
+  HIPCHK(launch_nn(d, w, t, MB, DT::F64, ld, h->Sd.d(), t, 0.0, nullptr, DT::F64, ld, MY, DT::F64,
+                   ld, nullptr, s));
+  return EDA_OK;
+}
+
+}  // namespace
+
+extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* opt,
+                                double* ritz, double* ritz_log, double* X, int64_t ldx,
+                                double* resid, eda_info* info) {
+  if (h == nullptr) return EDA_ERR_ARG;
+  eda_solve_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opt != nullptr) o = *opt;
+  if (!h->prepared) return fail(h, EDA_ERR_STATE, "eda_prepare has not succeeded");
+  const int64_t d = h->d;
+  if (t < 1 || t >= d) return fail(h, EDA_ERR_ARG, "need 1 <= t < d");
+  if (t > 128) return fail(h, EDA_ERR_ARG, "t > 128 is not supported");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(h, EDA_ERR_ARG, "tol must be positive");
+  if (ritz == nullptr || ritz_log == nullptr || X == nullptr || resid == nullptr)
+    return fail(h, EDA_ERR_ARG, "null output pointer");
+  if (ldx < d) return fail(h, EDA_ERR_ARG, "ldx must be >= d");
+  if (o.form != EDA_FORM_LANCZOS_M) return fail(h, EDA_ERR_ARG, "only the Lanczos form is solved");
+  if (o.krylov_dtype != EDA_F64 && o.krylov_dtype != EDA_F32)
+    return fail(h, EDA_ERR_ARG, "krylov_dtype (basis type) must be EDA_F64 or EDA_F32");
+  if (o.refine_dtype != EDA_F64) return fail(h, EDA_ERR_ARG, "refine_dtype must be EDA_F64");
+  if (o.resmode != EDA_RES_REL_THETA && o.resmode != EDA_RES_NORMWISE)
+    return fail(h, EDA_ERR_ARG, "unknown residual mode");
+  const int64_t b = o.block > 0 ? o.block : 8;
+  if (b > 8) return fail(h, EDA_ERR_ARG, "block width must be in [1, 8]");
+  int64_t mmax = o.max_basis;
+  if (mmax <= 0) {
+    mmax = std::max<int64_t>(2 * t + 2 * b, t + 6 * b);
+    mmax = round_up(mmax, b);
+    mmax = std::min<int64_t>(mmax, std::min<int64_t>(d, 2048 - b));
+  }
+  if (mmax < t + 2 * b || mmax > d || mmax + b > 2048)
+    return fail(h, EDA_ERR_ARG, "max_basis=%lld must satisfy t+2b <= max_basis <= min(d, 2048-b)",
+                (long long)mmax);
+  const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 4000;
+  const int64_t check_every = o.check_every > 0 ? o.check_every : 2;
+  if (o.start_block != nullptr && o.ld_start < d)
+    return fail(h, EDA_ERR_ARG, "ld_start must be >= d");
+  STCHK(need_device(h));
+  STCHK(check_dev_ptr(h, X, "X"));
+  if (o.start_block != nullptr) STCHK(check_dev_ptr(h, o.start_block, "start_block"));
+
+  const DT qdt = o.krylov_dtype == EDA_F32 ? DT::F32 : DT::F64;
+  const bool mixed = (h->storage != EDA_F64) || (qdt != DT::F64);
+  // Float64 passes after the Krylov phase (defaults: 16 after a narrow
+  // phase, 2 as a safety net after a float64 one); negative: none, and no
+  // float64 Rayleigh-Ritz either (the pairs of the Krylov phase are returned
+  // with float64 residuals).
+  const int64_t max_refine = o.max_refine > 0 ? o.max_refine : (o.max_refine < 0 ? -1 : (mixed ? 16 : 2));
+  const double u_lo = std::max(unit_roundoff(dt_of(h->storage)), unit_roundoff(qdt));
+
+  Solver S;
+  S.h = h;
+  S.d = d;
+  S.ldq = h->ldp;
+  S.b = b;
+  S.mmax = mmax;
+  S.ldh = mmax + b;
+  S.t = t;
+  S.qdt = qdt;
+  S.kk = std::min<int64_t>(t + b, mmax - 2 * b);
+  if (S.kk < t) S.kk = t;
+  const int64_t ldq = S.ldq, ldh = S.ldh;
+  const size_t qs = dt_size(qdt);
+  const int64_t wz = std::min<int64_t>(t, d - t);          // refinement expansion width
+  const int64_t mm = std::max<int64_t>(mmax, t + wz);      // leading dimension of T, S
+
+  for (int q = 0; q < 2; ++q) {
+    STCHK(ensure(h, h->Q[q], (size_t)ldq * (mmax + b) * qs));
+    STCHK(ensure(h, h->H[q], (size_t)ldh * ldh * 8));
+  }
+  STCHK(ensure(h, h->Wb, (size_t)ldq * b * qs));
+  STCHK(ensure(h, h->T, (size_t)mm * mm * 8));
+  STCHK(ensure(h, h->wT, (size_t)mm * 8));
+  STCHK(ensure(h, h->S, (size_t)mm * mm * 8));
+  STCHK(ensure(h, h->Sd, (size_t)std::max(mmax * S.kk, (t + wz) * t) * 8));
+  STCHK(ensure(h, h->Yb, (size_t)ldq * std::max<int64_t>(t, b) * 8));
+  // refinement blocks [Y | R] and [MY | MR], two of each, 2t columns apiece
+  STCHK(ensure(h, h->refine, (size_t)8 * ldq * t * 8));
+  STCHK(ensure(h, h->dtheta, (size_t)(S.kk + 8) * 8));
+  STCHK(ensure(h, h->dres, (size_t)(S.kk + 8) * 8));
+  STCHK(ensure(h, h->syev_work, syev_work_bytes(mm)));
+  STCHK(ensure(h, h->flags, 64));
+  STCHK(ensure(h, h->mask, 128 * sizeof(int)));
+  {
+    // size the shared workspaces once for every shape used below
+    const int64_t bt = std::max<int64_t>(b, t);
+    const int64_t shapes[][2] = {{h->N, b},  {mmax + b, b}, {b, b},   {h->N, t},
+                                 {h->n, t},  {t, t},        {t, wz},  {wz, wz},
+                                 {t + wz, t + wz}};
+    size_t pmax = 0;
+    for (const auto& sh : shapes)
+      pmax = std::max(pmax, (size_t)tn_chunks(d, sh[0], sh[1]) * sh[0] * sh[1] * 8);
+    STCHK(ensure(h, h->part, pmax));
+    STCHK(ensure(h, h->Ysm, (size_t)h->N * bt * 8));
+    STCHK(ensure(h, h->Zsm, (size_t)h->N * bt * 8));
+    STCHK(ensure(h, h->hz, (size_t)std::max<int64_t>((mmax + b) * b, (int64_t)t * t) * 8));
+    STCHK(ensure(h, h->Gs, (size_t)bt * bt * 8));
+    STCHK(ensure(h, h->Rinv, (size_t)bt * bt * 8));
+    const int64_t rb = std::max<int64_t>(b, std::min<int64_t>(wz, 64));  // pchol's R
+    STCHK(ensure(h, h->R1, (size_t)rb * rb * 8));
+  }
+
+  hipEvent_t e0, e1, e2;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreate(&e2));
+  HIPCHK(hipEventRecord(e0, h->stream));
+  hipStream_t s = h->stream;
+  h->op_used = 0;
+  HIPCHK(launch_fill_i32(16, 0, h->flags.i(), s));
+  HIPCHK(launch_fill(ldh * ldh, 0.0, h->H[0].d(), s));
+  HIPCHK(launch_fill(ldh * ldh, 0.0, h->H[1].d(), s));
+  S.cur = 0;
+
+  // start block -> Q[:, 0:b] (drawn in float64, then cast to the basis type)
+  void* Wst = h->Wb.p;
+  double* Wst64 = h->Yb.d();
+  if (o.start_block != nullptr)
+    HIPCHK(launch_copy2d(d, b, o.start_block, DT::F64, o.ld_start, Wst, qdt, ldq, s));
+  else {
+    HIPCHK(launch_randn(d, b, o.seed, Wst64, ldq, s));
+    HIPCHK(launch_copy2d(d, b, Wst64, DT::F64, ldq, Wst, qdt, ldq, s));
+  }
+  if (qdt == DT::F64)
+    HIPCHK(launch_fill(ldq * (mmax + b), 0.0, (double*)S.Q(), s));
+  else  // float32 zero has the bit pattern of int32 zero
+    HIPCHK(launch_fill_i32(ldq * (mmax + b), 0, (int*)S.Q(), s));
+  STCHK(cholqr_pass(h, d, b, Wst, qdt, ldq, S.Q(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                    nullptr, nullptr));
+  STCHK(cholqr_pass(h, d, b, S.Q(), qdt, ldq, S.Q(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                    nullptr, nullptr));
+
+  const int64_t nvec = std::min<int64_t>(S.kk, mmax);
+  std::vector<double> theta(S.kk + 8), est(S.kk + 8);
+  int64_t m = 0;
+  int64_t iters = 0, restarts = 0;
+  bool kconv = false;
+  int flags_out = 0;
+  if (t > h->k - 1) flags_out |= EDA_WARN_DEGENERATE;
+  double bytes = 0.0;
+  int64_t ops = 0;
+  const double opbytes = 2.0 * d * h->N * dsize(h->storage) + 3.0 * d * b * qs;
+  int64_t m_rr = 0;
+
+  // ---- Krylov phase -------------------------------------------------------
+  while (true) {
+    STCHK(lanczos_step(S, m));
+    m += b;
+    ++iters;
+    ops += b;
+    bytes += opbytes;
+    const bool need_restart = (m + b > mmax);
+    const bool can_check = (m >= t + b) || need_restart;
+    if (can_check && (iters % check_every == 0 || need_restart || iters >= max_iter)) {
+      const int64_t cnt = need_restart ? S.kk : t;
+      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), cnt, theta.data(), est.data()));
+      m_rr = m;
+      bool ok = true;
+      const double th1 = theta[0];
+      for (int64_t i = 0; i < t; ++i) {
+        const double thi = theta[i];
+        if (!(thi > 0.0)) { ok = false; continue; }
+        const double tol_i = std::max(tol, 10.0 * u_lo * th1 / thi);
+        const double r = (o.resmode == EDA_RES_REL_THETA) ? est[i] / thi : est[i] / th1;
+        if (!(r <= tol_i)) ok = false;
+      }
+      if (ok) { kconv = true; break; }
+      if (iters >= max_iter) break;
+      if (need_restart) {
+        // thick restart: keep the kk leading Ritz vectors and the next block
+        const int64_t kk = S.kk;
+        HIPCHK(launch_gather_desc(m, kk, h->S.d(), mmax, h->Sd.d(), kk, s));
+        const int nxt = 1 - S.cur;
+        char* Qn = h->Q[nxt].c();
+        double* Hn = h->H[nxt].d();
+        HIPCHK(launch_nn(d, m, kk, S.Q(), qdt, ldq, h->Sd.d(), kk, 0.0, nullptr, qdt, ldq, Qn, qdt,
+                         ldq, nullptr, s));
+        HIPCHK(launch_copy2d(d, b, S.Qc(m), qdt, ldq, Qn + (size_t)kk * ldq * qs, qdt, ldq, s));
+        HIPCHK(launch_fill(ldh * ldh, 0.0, Hn, s));
+        HIPCHK(launch_set_diag(kk, h->dtheta.d(), Hn, ldh, s));
+        HIPCHK(launch_restart_coupling(m, b, kk, S.H() + m + (m - b) * ldh, ldh, h->Sd.d(), kk, Hn,
+                                       ldh, s));
+        S.cur = nxt;
+        m = kk;
+        ++restarts;
+      }
+    } else if (iters >= max_iter) {
+      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), std::min<int64_t>(t, m), theta.data(),
+                          est.data()));
+      m_rr = m;
+      break;
+    }
+  }
+  if (m_rr != m || m < t) {
+    if (m < t) return fail(h, EDA_ERR_NOCONV, "basis smaller than t at the iteration limit");
+    STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), t, theta.data(), est.data()));
+  }
+
+  // Ritz vectors Y = Q S_t in float64 (theta in dtheta)
+  const size_t rw = (size_t)ldq * 2 * t;
+  double* XB[2] = {h->refine.d(), h->refine.d() + rw};
+  double* MB[2] = {h->refine.d() + 2 * rw, h->refine.d() + 3 * rw};
+  int cb = 0;
+  HIPCHK(launch_gather_desc(m, t, h->S.d(), mmax, h->Sd.d(), t, s));
+  HIPCHK(launch_nn(d, m, t, S.Q(), qdt, ldq, h->Sd.d(), t, 0.0, nullptr, DT::F64, ldq, XB[0],
+                   DT::F64, ldq, nullptr, s));
+  HIPCHK(hipEventRecord(e1, s));
+
+  // ---- float64 stage --------------------------------------------------------
+  const double opbytes_t = 2.0 * d * h->N * 8.0 + 3.0 * d * t * 8.0;
+  const double opbytes_z = 2.0 * d * h->N * 8.0 + 3.0 * d * wz * 8.0;
+  if (mixed && max_refine >= 0) {
+    // orthonormalise the Ritz block in float64, apply the float64 operator
+    // and take the Rayleigh-Ritz pairs of span(Y)
+    STCHK(cholqr_pass(h, d, t, XB[0], DT::F64, ldq, h->Yb.d(), ldq, nullptr, nullptr, 0, nullptr,
+                      0, 0, nullptr, nullptr));
+    STCHK(cholqr_pass(h, d, t, h->Yb.d(), DT::F64, ldq, XB[0], ldq, nullptr, nullptr, 0, nullptr,
+                      0, 0, nullptr, nullptr));
+    STCHK(expop(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, t, XB[0], DT::F64, ldq, MB[0],
+                DT::F64, ldq));
+    ops += t;
+    bytes += opbytes_t;
+    STCHK(rr_block(h, d, ldq, t, t, mm, XB[0], MB[0], XB[1], MB[1]));
+    cb = 1;
+  } else {
+    STCHK(expop(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, t, XB[0], DT::F64, ldq, MB[0],
+                DT::F64, ldq));
+    ops += t;
+    bytes += opbytes_t;
+  }
+  std::vector<double> res(t);
+  bool converged = false, floor_limited = false;
+  int64_t passes = 0;
+  while (true) {
+    double* Y = XB[cb];
+    double* MY = MB[cb];
+    double* Z = Y + (size_t)t * ldq;
+    HIPCHK(launch_ritz_residual(d, t, MY, ldq, Y, ldq, h->dtheta.d(), Z, ldq, h->dres.d(), s));
+    HIPCHK(hipMemcpyAsync(theta.data(), h->dtheta.d(), t * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(res.data(), h->dres.d(), t * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (std::getenv("EDA_LOG") != nullptr) log_pairs("f64", passes, t, theta.data(), res.data());
+    bool ok = true;
+    floor_limited = false;
+    const double th1 = theta[0];
+    for (int64_t i = 0; i < t; ++i) {
+      const double thi = theta[i];
+      if (!(thi > 0.0)) { ok = false; continue; }
+      const double floor_i = 10.0 * kU64 * th1 / thi;
+      if (floor_i > tol) floor_limited = true;
+      const double r = (o.resmode == EDA_RES_REL_THETA) ? res[i] / thi : res[i] / th1;
+      if (!(r <= std::max(tol, floor_i))) ok = false;
+    }
+    if (ok) { converged = true; break; }
+    if (!kconv || passes >= max_refine) break;
+    // expand with the residual block: Z = orth(R) against Y and itself
+    double* Zt = h->Yb.d();
+    if (wz < t) {  // 2t > d: keep the residuals of the last (least converged) wz pairs
+      HIPCHK(launch_copy2d(d, wz, Z + (size_t)(t - wz) * ldq, DT::F64, ldq, Zt, DT::F64, ldq, s));
+      HIPCHK(launch_copy2d(d, wz, Zt, DT::F64, ldq, Z, DT::F64, ldq, s));
+    }
+    STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Z, ldq, wz, nullptr, 0, 0.0, nullptr));
+    STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Z, ldq, wz, nullptr, 0, 0.0, nullptr));
+    if (wz <= 64) {
+      // rank revealing on unit-norm columns: converged pairs leave columns of
+      // roundoff; those are replaced by random directions
+      const int64_t chunks = tn_chunks(d, wz, wz);
+      HIPCHK(launch_tn_partial(d, wz, wz, Z, DT::F64, ldq, Z, DT::F64, ldq, h->part.d(), chunks,
+                               nullptr, s));
+      HIPCHK(launch_reduce_partials(chunks, wz, wz, h->part.d(), 1.0, 0.0, h->Gs.d(), wz, 0.0,
+                                    nullptr, 0, nullptr, s));
+      HIPCHK(launch_pchol(wz, h->Gs.d(), wz, nullptr, 0, 0, 1e-10, 1e-4, true, h->Rinv.d(), wz,
+                          h->R1.d(), wz, h->mask.i(), nullptr, s));
+      HIPCHK(launch_nn(d, wz, wz, Z, DT::F64, ldq, h->Rinv.d(), wz, 0.0, nullptr, DT::F64, ldq, Zt,
+                       DT::F64, ldq, nullptr, s));
+      HIPCHK(launch_fill_masked_randn(d, wz, h->mask.i(), 0x7e41e000ull + (uint64_t)passes, Zt,
+                                      DT::F64, ldq, s));
+      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
+      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
+      STCHK(cholqr_pass(h, d, wz, Zt, DT::F64, ldq, Z, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                        nullptr, nullptr));
+    } else {
+      STCHK(cholqr_pass(h, d, wz, Z, DT::F64, ldq, Zt, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                        nullptr, nullptr));
+      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
+      STCHK(cholqr_pass(h, d, wz, Zt, DT::F64, ldq, Z, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                        nullptr, nullptr));
+    }
+    STCHK(cholqr_pass(h, d, wz, Z, DT::F64, ldq, Zt, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                      nullptr, nullptr));
+    HIPCHK(launch_copy2d(d, wz, Zt, DT::F64, ldq, Z, DT::F64, ldq, s));
+    STCHK(expop(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, wz, Z, DT::F64, ldq,
+                MY + (size_t)t * ldq, DT::F64, ldq));
+    ops += wz;
+    bytes += opbytes_z;
+    STCHK(rr_block(h, d, ldq, t + wz, t, mm, Y, MY, XB[1 - cb], MB[1 - cb]));
+    cb = 1 - cb;
+    ++passes;
+  }
+  HIPCHK(hipEventRecord(e2, s));
+
+  // back-transform x = exp(-S_W/2) y, orthonormalise in decreasing-lambda
+  // order (Cholesky QR, twice), then fix signs
+  double* Y = XB[cb];
+  STCHK(expop(h, true, 0, h->n, h->Gh.d(), h->n, 1.0, t, Y, DT::F64, ldq, X, DT::F64, ldx));
+  STCHK(cholqr_pass(h, d, t, X, DT::F64, ldx, h->Yb.d(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                    nullptr, nullptr));
+  STCHK(cholqr_pass(h, d, t, h->Yb.d(), DT::F64, ldq, X, ldx, nullptr, nullptr, 0, nullptr, 0, 0,
+                    nullptr, nullptr));
+  HIPCHK(launch_sign_fix(d, t, X, ldx, s));
+  int fl[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(fl, h->flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float kms = 0.f, rms = 0.f;
+  HIPCHK(hipEventElapsedTime(&kms, e0, e1));
+  HIPCHK(hipEventElapsedTime(&rms, e1, e2));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+
+  bool range_err = false;
+  for (int64_t i = 0; i < t; ++i) {
+    const double th = theta[i];
+    if (!(th > 0.0)) {
+      range_err = true;
+      ritz_log[i] = -INFINITY;
+      ritz[i] = 0.0;
+    } else {
+      ritz_log[i] = h->shiftB + std::log(th);
+      ritz[i] = std::exp(ritz_log[i]);
+    }
+    resid[i] = (o.resmode == EDA_RES_REL_THETA) ? res[i] / th : res[i] / theta[0];
+  }
+  if (floor_limited) flags_out |= EDA_WARN_FLOOR;
+  if (fl[1] | fl[0]) flags_out |= EDA_WARN_REPAIRED;
+  if (info != nullptr) {
+    info->iters = (int32_t)iters;
+    info->restarts = (int32_t)restarts;
+    info->refine_passes = (int32_t)passes;
+    info->flags = flags_out;
+    info->ops = ops;
+    info->bytes_moved = bytes;
+    info->t_prepare_ms = h->t_prepare_ms;
+    info->t_krylov_ms = kms;
+    info->t_refine_ms = rms;
+    info->shift_s = h->shiftB;
+    double top = 0.0;
+    for (size_t q = 0; q + 1 < h->op_used; q += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, h->op_ev[q], h->op_ev[q + 1]) == hipSuccess) top += ms;
+    }
+    info->op_calls = (int64_t)(h->op_used / 2);
+    info->t_op_ms = top;
+    info->op_bytes = opbytes;
+  }
+  if (range_err) return fail(h, EDA_ERR_RANGE, "a Ritz value underflowed after the shift");
+  if (!converged) {
+    if (!kconv) return fail(h, EDA_ERR_NOCONV, "max_iter reached before convergence");
+    return fail(h, EDA_ERR_NOCONV, "float64 refinement did not reach the tolerance in %lld passes",
+                (long long)passes);
+  }
+  return EDA_OK;
+}

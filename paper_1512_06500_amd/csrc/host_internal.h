@@ -1,0 +1,98 @@
+// Internal state and helpers shared by the host-side sources of libeda
+// (eda_api.cpp: handle, preparation, products; eda_solve.cpp: the solver).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "eda.h"
+
+namespace eda {
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+  double* d() const { return (double*)p; }
+  float* f() const { return (float*)p; }
+  int* i() const { return (int*)p; }
+  char* c() const { return (char*)p; }
+};
+
+struct CoreEntry {
+  int which = -1;
+  double c = 0.0;
+  double shift = 0.0;
+  Buf buf;
+};
+
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+
+}  // namespace eda
+
+struct eda_handle_s {
+  // events bracketing the operator products of a solve (reused across solves)
+  std::vector<hipEvent_t> op_ev;
+  size_t op_used = 0;
+  hipStream_t stream = nullptr;
+  int device = -1;
+  std::string err;
+
+  // prepared problem
+  bool prepared = false;
+  int64_t d = 0, n = 0, k = 0, N = 0, ldp = 0;
+  eda_dtype storage = EDA_F64;
+  eda::Buf P;    // P = [H_W H_B] in storage precision (ld ldp)
+  eda::Buf P64;  // float64 master of P when storage is not float64
+  eda::Buf G, eigW, eigZ, nsbuf, Gh, Gm, GBs, CM, CA, T1, T2, T3, T4, fw, polyws, normbuf;
+  double shiftB = 0.0, alphaB = 1.0;
+  double normW = 0.0;   // ||H_W^T H_W||_1
+  bool w_eig = false;   // eigenpairs of H_W^T H_W available
+  std::vector<double> hwW, hwB;
+  double t_prepare_ms = 0.0;
+
+  // workspaces
+  eda::Buf part, Ysm, Zsm, syev_work, offs, flags, mask;
+  std::vector<eda::CoreEntry> cores;
+
+  // solver
+  eda::Buf Q[2], H[2], Wb, T, wT, S, Sd, hz, Gs, Rinv, R1, Yb, MYb, dtheta, dres, refine;
+};
+
+namespace eda {
+
+eda_status fail(eda_handle h, eda_status s, const char* fmt, ...);
+eda_status ensure(eda_handle h, Buf& b, size_t bytes);
+void release(Buf& b);
+eda_status need_device(eda_handle h);
+eda_status check_dev_ptr(eda_handle h, const void* p, const char* name);
+
+inline size_t dsize(eda_dtype t) { return t == EDA_F64 ? 8 : (t == EDA_F32 ? 4 : 2); }
+inline DT dt_of(eda_dtype t) {
+  return t == EDA_F64 ? DT::F64 : (t == EDA_F32 ? DT::F32 : DT::BF16);
+}
+inline size_t dt_size(DT t) { return t == DT::F64 ? 8 : (t == DT::F32 ? 4 : 2); }
+inline int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
+
+// Low-rank exponential apply on columns [c0, c0+Nc) of P (the storage copy,
+// or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.
+eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
+                 int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
+                 void* Out, DT odt, int64_t ldo);
+
+}  // namespace eda
+
+#define HIPCHK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      return ::eda::fail(h, EDA_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_));   \
+  } while (0)
+
+#define STCHK(x)                 \
+  do {                           \
+    eda_status s_ = (x);         \
+    if (s_ != EDA_OK) return s_; \
+  } while (0)

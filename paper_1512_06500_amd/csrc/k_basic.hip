@@ -202,21 +202,32 @@ __global__ void flag_fold_kernel(int* flags) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void ritz_residual_kernel(int64_t d, const T* __restrict__ MY,
-                                                            const T* __restrict__ Y, int64_t ld,
+// R[:, c] = MY[:, c] - theta_c Y[:, c] (stored when R is not null) and
+// res[c] = ||R[:, c]||_2, one workgroup per column, fixed-order block sum.
+__global__ __launch_bounds__(256) void ritz_residual_kernel(int64_t d, const double* __restrict__ MY,
+                                                            int64_t ldmy, const double* __restrict__ Y,
+                                                            int64_t ldy,
                                                             const double* __restrict__ theta,
+                                                            double* __restrict__ R, int64_t ldr,
                                                             double* __restrict__ res) {
   __shared__ double red[8];
   const int64_t c = blockIdx.x;
   const double th = theta[c];
   double acc = 0.0;
   for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
-    const double v = to_f64<T>(MY[r + c * ld]) - th * to_f64<T>(Y[r + c * ld]);
+    const double v = MY[r + c * ldmy] - th * Y[r + c * ldy];
+    if (R != nullptr) R[r + c * ldr] = v;
     acc += v * v;
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) res[c] = sqrt(acc);
+}
+
+// out[i] = w[n - 1 - i] for i < cnt (ascending eigenvalues to descending).
+__global__ __launch_bounds__(256) void desc_values_kernel(int64_t cnt, const double* __restrict__ w,
+                                                          int64_t n, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < cnt) out[i] = w[n - 1 - i];
 }
 
 __global__ __launch_bounds__(256) void restart_coupling_kernel(int64_t m, int64_t b, int64_t kk,
@@ -416,15 +427,19 @@ hipError_t launch_flag_fold(int* flags, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ritz_residual(int64_t d, int64_t t, const void* MY, const void* Y,
-                                int64_t ld, DT dt, const double* theta, double* res,
-                                hipStream_t s) {
-  if (dt == DT::F64)
-    hipLaunchKernelGGL(ritz_residual_kernel<double>, dim3((unsigned)t), dim3(256), 0, s, d,
-                       (const double*)MY, (const double*)Y, ld, theta, res);
-  else
-    hipLaunchKernelGGL(ritz_residual_kernel<float>, dim3((unsigned)t), dim3(256), 0, s, d,
-                       (const float*)MY, (const float*)Y, ld, theta, res);
+hipError_t launch_ritz_residual(int64_t d, int64_t t, const double* MY, int64_t ldmy,
+                                const double* Y, int64_t ldy, const double* theta, double* R,
+                                int64_t ldr, double* res, hipStream_t s) {
+  if (t <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ritz_residual_kernel, dim3((unsigned)t), dim3(256), 0, s, d, MY, ldmy, Y, ldy,
+                     theta, R, ldr, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_desc_values(int64_t cnt, const double* w, int64_t n, double* out,
+                              hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(desc_values_kernel, dim3(nblk(cnt)), dim3(256), 0, s, cnt, w, n, out);
   return hipGetLastError();
 }
 

@@ -115,28 +115,34 @@ __global__ __launch_bounds__(256) void chol_kernel(int b, const double* __restri
 __global__ __launch_bounds__(64) void pchol_kernel(int b, const double* __restrict__ G, int64_t ldg,
                                                    const double* __restrict__ hcol, int64_t m,
                                                    int64_t ldhc, double tau, double ratio,
-                                                   double* __restrict__ Z, int64_t ldz,
+                                                   int equil, double* __restrict__ Z, int64_t ldz,
                                                    double* __restrict__ R, int64_t ldr,
                                                    int* __restrict__ mask, int* flag) {
   constexpr int PB = 64;
   __shared__ double A[PB * (PB + 1)];
   __shared__ double nrm0[PB];
+  __shared__ double dsc[PB];  // column scaling (1 unless equilibrated)
   __shared__ int perm[PB];
   __shared__ int s_rank, s_q, s_flag;
   const int ld = PB + 1;
   const int tid = threadIdx.x;
+  if (tid < b) {
+    const double g = G[tid + tid * ldg];
+    dsc[tid] = (equil && g > 0.0) ? 1.0 / sqrt(g) : 1.0;
+  }
+  __syncthreads();
   for (int e = tid; e < b * b; e += blockDim.x) {
     const int c = e / b, r = e - c * b;
-    A[r + c * ld] = G[r + c * ldg];
+    A[r + c * ld] = G[r + c * ldg] * dsc[r] * dsc[c];
   }
   if (tid < b) {
     double h2 = 0.0;
-    if (hcol != nullptr)
+    if (hcol != nullptr && !equil)
       for (int64_t r = 0; r < m; ++r) {
         const double v = hcol[r + tid * ldhc];
         h2 += v * v;
       }
-    nrm0[tid] = G[tid + tid * ldg] + h2;
+    nrm0[tid] = G[tid + tid * ldg] * dsc[tid] * dsc[tid] + h2;
     perm[tid] = tid;
   }
   if (tid == 0) {
@@ -219,10 +225,16 @@ __global__ __launch_bounds__(64) void pchol_kernel(int b, const double* __restri
     if (j < rk) {
       int i = 0;
       while (perm[i] != ci) ++i;
-      if (i >= j) v = A[i + j * ld];
+      if (i >= j) v = A[i + j * ld] / dsc[ci];
     }
     R[j + (int64_t)ci * ldr] = v;
   }
+  __syncthreads();
+  if (equil)  // Z maps the unscaled block: fold the column scaling into its rows
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int i = e / b, c = e - i * b;
+      Z[(int64_t)i * ldz + c] *= dsc[i];
+    }
   if (tid < b) {
     mask[tid] = (tid >= rk) ? 1 : 0;
     if (tid < rk && !(A[tid + tid * ld] >= ratio * sqrt(nrm0[perm[tid]]))) atomicOr(&s_flag, 1);
@@ -257,11 +269,11 @@ __global__ __launch_bounds__(256) void fill_masked_randn_kernel(int64_t d, int64
 }  // namespace
 
 hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
-                        int64_t ldhc, double tau, double ratio, double* Z, int64_t ldz, double* R,
-                        int64_t ldr, int* mask, int* flag, hipStream_t s) {
+                        int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
+                        double* R, int64_t ldr, int* mask, int* flag, hipStream_t s) {
   if (b < 1 || b > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pchol_kernel, dim3(1), dim3(64), 0, s, (int)b, G, ldg, hcol, m, ldhc, tau,
-                     ratio, Z, ldz, R, ldr, mask, flag);
+                     ratio, equil ? 1 : 0, Z, ldz, R, ldr, mask, flag);
   return hipGetLastError();
 }
 

@@ -8,104 +8,103 @@
 //   exp(c H H^T) V = V + H G_c (H^T V)
 // (Theorem 3.1 in Gram form) and also the projections of block classical
 // Gram-Schmidt and the W R^{-1} step of Cholesky QR.  Both are HBM-bound:
-// for nb = 8 every element of A feeds 8 FMAs, far below the FP64 ridge.
+// for nb = 8 every element of A feeds 8 FMAs, far below the FP64 ridge, so
+// the design goal is to keep enough loads in flight, never to save flops.
 //
-// tn mapping: a 256-thread workgroup owns a chunk of rows and 32 columns of A
-// (8 per wave); lanes own rows, so every load of a column is a contiguous
-// 512-byte wave access.  Each lane keeps an 8 x 8 tile of partial dot
-// products in registers and the wave folds the 64 values over its 64 lanes
-// with a butterfly reduce-scatter (63 shuffles), after which lane l holds
-// entry l of the tile.
+// tn mapping: the row reduction is done by the matrix cores.  One
+// v_mfma_f64_16x16x4f64 takes a 16 x 4 slice of A^T and a 4 x 16 slice of B
+// and accumulates their product, so a wave owns 16 columns of A (and up to
+// 16 of B) and sums over 4 rows per instruction without any cross-lane
+// shuffles.  Lane (i = l % 16, q = l / 16) reads 16 consecutive rows of
+// column i (and of B's column i), i.e. every cache line fetched is consumed
+// by the same lane over 16 instructions; which k slot a row occupies does
+// not matter for a sum.  The 4 waves of a workgroup take 4 consecutive
+// 64 S-row ranges of one 16-column tile and are summed through LDS, so each
+// workgroup writes one partial tile.
 //
-// nn mapping: a workgroup owns 64 rows; its 4 waves split the m columns of A
-// and the wave partials are summed in a fixed order through LDS.  Z is read
-// with wave-uniform addresses (scalar loads / broadcast).
+// nn mapping: a workgroup owns R rows and all m columns; its 256 lanes are
+// R rows x G = 256/R column groups (column j goes to group j mod G), so every
+// lane issues m/G independent loads in batches, reading rows of Z from an LDS
+// copy.  The G partial sums of a row are added in a fixed order through LDS.
 #include "common.h"
 
 namespace eda {
 
 namespace {
 
-constexpr int TN_MT = 8;   // A columns per wave
-constexpr int TN_NB = 8;   // B columns per tile
-constexpr int NN_NB = 8;   // output columns per workgroup
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Butterfly reduce-scatter of 64 values across the 64 lanes of a wave: on
-// return lane l holds sum over lanes of v[l].
-template <typename T>
-__device__ __forceinline__ T wave_reduce_scatter64(T (&v)[64], int lane) {
-#pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) {
-    const bool up = (lane & h) != 0;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const T send = up ? v[i] : v[i + h];
-      const T keep = up ? v[i + h] : v[i];
-      v[i] = keep + __shfl_xor(send, h);
-    }
-  }
-  return v[0];
-}
+constexpr int NN_NB = 8;    // output columns per workgroup (grid.y tiles the rest)
+constexpr int NN_ZT = 512;  // rows of Z per LDS tile
 
-template <typename TA, typename TB, typename ACC>
-__global__ __launch_bounds__(256) void tn_partial_kernel(int64_t d, int m, int nb,
-                                                         const TA* __restrict__ A, int64_t lda,
-                                                         const TB* __restrict__ B, int64_t ldb,
-                                                         double* __restrict__ part,
-                                                         int64_t rows_per_chunk,
-                                                         const int* __restrict__ gate) {
+template <typename T> __device__ __forceinline__ double ld64(const T* p) { return to_f64<T>(*p); }
+
+// A^T B partial over one row chunk and one 16-column tile of A, nb <= 16 per
+// z-tile.  part[(chunk * m + i) * nb + j].  S: 64-row steps per wave.
+template <typename TA, typename TB, int S>
+__global__ __launch_bounds__(256) void tn_mfma_kernel(int64_t d, int m, int nb,
+                                                      const TA* __restrict__ A, int64_t lda,
+                                                      const TB* __restrict__ B, int64_t ldb,
+                                                      double* __restrict__ part,
+                                                      const int* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
+  __shared__ f64x4 red[3][64];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int64_t chunk = blockIdx.x;
-  const int i0 = (blockIdx.y * 4 + wid) * TN_MT;
-  const int j0 = blockIdx.z * TN_NB;
-  const int64_t r0 = chunk * rows_per_chunk;
-  const int64_t r1 = (r0 + rows_per_chunk < d) ? r0 + rows_per_chunk : d;
-
-  ACC acc[TN_MT][TN_NB];
+  const int c0 = blockIdx.y * 16;
+  const int j0 = blockIdx.z * 16;
+  const int i = lane & 15, q = lane >> 4;
+  const bool cok = (c0 + i) < m;
+  const bool bok = (j0 + i) < nb;
+  const TA* ap = A + (int64_t)(cok ? c0 + i : c0) * lda;
+  const TB* bp = B + (int64_t)(bok ? j0 + i : j0) * ldb;
+  const int64_t r0 = chunk * (int64_t)(256 * S) + (int64_t)wid * (64 * S);
+  const int64_t r1 = (r0 + 64 * S < d) ? r0 + 64 * S : d;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int i = 0; i < TN_MT; ++i)
+  for (int s = 0; s < S; ++s) {
+    const int64_t rb = r0 + 64 * s;
+    if (rb >= r1) break;
+    const int64_t rs = rb + 16 * q;
+    double a[16], b[16];
+    if (rb + 64 <= r1) {
 #pragma unroll
-    for (int j = 0; j < TN_NB; ++j) acc[i][j] = ACC(0);
-
-  if (i0 < m) {
-    const TA* ap[TN_MT];
-    const TB* bp[TN_NB];
-    bool aok[TN_MT], bok[TN_NB];
+      for (int e = 0; e < 16; ++e) {
+        const double x = ld64(ap + rs + e), y = ld64(bp + rs + e);
+        a[e] = cok ? x : 0.0;
+        b[e] = bok ? y : 0.0;
+      }
+    } else {
 #pragma unroll
-    for (int i = 0; i < TN_MT; ++i) {
-      aok[i] = (i0 + i) < m;
-      ap[i] = A + (int64_t)(aok[i] ? i0 + i : i0) * lda;
+      for (int e = 0; e < 16; ++e) {
+        const bool ok = rs + e < r1;
+        const int64_t rr = ok ? rs + e : rb;
+        const double x = ld64(ap + rr), y = ld64(bp + rr);
+        a[e] = (cok && ok) ? x : 0.0;
+        b[e] = (bok && ok) ? y : 0.0;
+      }
     }
 #pragma unroll
-    for (int j = 0; j < TN_NB; ++j) {
-      bok[j] = (j0 + j) < nb;
-      bp[j] = B + (int64_t)(bok[j] ? j0 + j : j0) * ldb;
-    }
-#pragma unroll 2
-    for (int64_t r = r0 + lane; r < r1; r += 64) {
-      ACC av[TN_MT], bv[TN_NB];
+    for (int e = 0; e < 16; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], acc, 0, 0, 0);
+  }
+  if (wid > 0) red[wid - 1][lane] = acc;
+  __syncthreads();
+  if (wid == 0) {
 #pragma unroll
-      for (int i = 0; i < TN_MT; ++i) av[i] = aok[i] ? to_acc<ACC>(ap[i][r]) : ACC(0);
+    for (int w = 0; w < 3; ++w) acc += red[w][lane];
+    // accumulator layout: lane l, element v holds row 4 v + l / 16, column l % 16
+    const int jj = lane & 15, ib = lane >> 4;
 #pragma unroll
-      for (int j = 0; j < TN_NB; ++j) bv[j] = bok[j] ? to_acc<ACC>(bp[j][r]) : ACC(0);
-#pragma unroll
-      for (int i = 0; i < TN_MT; ++i)
-#pragma unroll
-        for (int j = 0; j < TN_NB; ++j) acc[i][j] += av[i] * bv[j];
+    for (int v = 0; v < 4; ++v) {
+      const int ii = 4 * v + ib;
+      if (c0 + ii < m && j0 + jj < nb) part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] = acc[v];
     }
   }
-
-  ACC v[64];
-#pragma unroll
-  for (int e = 0; e < 64; ++e) v[e] = acc[e / TN_NB][e % TN_NB];
-  const ACC tot = wave_reduce_scatter64<ACC>(v, lane);
-  const int i = lane / TN_NB, j = lane % TN_NB;
-  if (i0 + i < m && j0 + j < nb)
-    part[(chunk * m + (i0 + i)) * (int64_t)nb + (j0 + j)] = (double)tot;
 }
 
+// Sum of the chunk partials, fixed order: wave w adds chunks w, w+4, ... of
+// 64 outputs, then the 4 wave sums are added in order.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t chunks, int64_t m, int64_t nb,
                                                               const double* __restrict__ part,
                                                               double alpha, double beta,
@@ -113,20 +112,29 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t chunks, in
                                                               double zalpha, double* __restrict__ Z,
                                                               int64_t ldz, const int* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  __shared__ double red[3][64];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
   const int64_t mn = m * nb;
-  if (e >= mn) return;
-  // fixed order; eight independent loads in flight per thread
+  const int64_t e = blockIdx.x * (int64_t)64 + lane;
+  const int64_t ee = e < mn ? e : mn - 1;
   double s = 0.0;
-  int64_t c = 0;
-  for (; c + 8 <= chunks; c += 8) {
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = part[(c + q) * mn + e];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) s += v[q];
+  int64_t c = wid;
+  for (; c + 12 < chunks; c += 16) {
+    const double v0 = part[c * mn + ee], v1 = part[(c + 4) * mn + ee];
+    const double v2 = part[(c + 8) * mn + ee], v3 = part[(c + 12) * mn + ee];
+    s += v0;
+    s += v1;
+    s += v2;
+    s += v3;
   }
-  for (; c < chunks; ++c) s += part[c * mn + e];
+  for (; c < chunks; c += 4) s += part[c * mn + ee];
+  if (wid > 0) red[wid - 1][lane] = s;
+  __syncthreads();
+  if (wid != 0 || e >= mn) return;
+  s += red[0][lane];
+  s += red[1][lane];
+  s += red[2][lane];
   const int64_t i = e / nb, j = e - i * nb;
   if (C != nullptr) {
     double* cp = C + i + j * ldc;
@@ -135,104 +143,126 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t chunks, in
   if (Z != nullptr) Z[i * ldz + j] = zalpha * s;
 }
 
-template <typename TA, typename TV, typename TO, typename ACC>
+template <typename TA, typename TV, typename TO, typename ACC, int R, int BATCH>
 __global__ __launch_bounds__(256) void nn_kernel(int64_t d, int m, int nb, const TA* __restrict__ A,
                                                  int64_t lda, const double* __restrict__ Z,
                                                  int64_t ldz, double alpha, const TV* __restrict__ V,
                                                  int64_t ldv, TO* __restrict__ Out, int64_t ldo,
                                                  int out_row, const int* __restrict__ gate) {
   if (gate != nullptr && *gate == 0) return;
-  __shared__ ACC red[3][64][NN_NB + 1];
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int64_t r = blockIdx.x * (int64_t)64 + lane;
+  constexpr int G = 256 / R;
+  __shared__ ACC zs[NN_ZT * NN_NB];
+  __shared__ ACC red[256 * (NN_NB + 1)];
+  const int tid = threadIdx.x;
+  const int rl = tid % R, g = tid / R;
+  const int64_t r = blockIdx.x * (int64_t)R + rl;
   const int j0 = blockIdx.y * NN_NB;
-  const int mq = (m + 3) / 4;
-  const int ib = wid * mq;
-  const int ie = (ib + mq < m) ? ib + mq : m;
-
+  const TA* ar = A + (r < d ? r : d - 1);  // rows past d read row d-1, never stored
   ACC acc[NN_NB];
 #pragma unroll
   for (int j = 0; j < NN_NB; ++j) acc[j] = ACC(0);
-  bool jok[NN_NB];
+  for (int t0 = 0; t0 < m; t0 += NN_ZT) {
+    const int tn = (m - t0 < NN_ZT) ? m - t0 : NN_ZT;
+    __syncthreads();
+    for (int e = tid; e < tn * NN_NB; e += 256) {
+      const int i = e / NN_NB, j = e - i * NN_NB;
+      zs[e] = (j0 + j < nb) ? (ACC)Z[(int64_t)(t0 + i) * ldz + j0 + j] : ACC(0);
+    }
+    __syncthreads();
+    int i = g;
+    for (; i + (BATCH - 1) * G < tn; i += BATCH * G) {
+      ACC a[BATCH];
 #pragma unroll
-  for (int j = 0; j < NN_NB; ++j) jok[j] = (j0 + j) < nb;
-
-  if (r < d) {
-    const TA* ar = A + r;
-#pragma unroll 4
-    for (int i = ib; i < ie; ++i) {
-      const ACC a = to_acc<ACC>(ar[(int64_t)i * lda]);
-      const double* zr = Z + (int64_t)i * ldz + j0;
+      for (int u = 0; u < BATCH; ++u) a[u] = to_acc<ACC>(ar[(int64_t)(t0 + i + u * G) * lda]);
 #pragma unroll
-      for (int j = 0; j < NN_NB; ++j)
-        if (jok[j]) acc[j] += a * (ACC)zr[j];
+      for (int u = 0; u < BATCH; ++u) {
+        const ACC* zr = zs + (i + u * G) * NN_NB;
+#pragma unroll
+        for (int j = 0; j < NN_NB; ++j) acc[j] += a[u] * zr[j];
+      }
+    }
+    for (; i < tn; i += G) {
+      const ACC a = to_acc<ACC>(ar[(int64_t)(t0 + i) * lda]);
+      const ACC* zr = zs + i * NN_NB;
+#pragma unroll
+      for (int j = 0; j < NN_NB; ++j) acc[j] += a * zr[j];
     }
   }
-  if (wid > 0) {
 #pragma unroll
-    for (int j = 0; j < NN_NB; ++j) red[wid - 1][lane][j] = acc[j];
-  }
+  for (int j = 0; j < NN_NB; ++j) red[tid * (NN_NB + 1) + j] = acc[j];
   __syncthreads();
-  if (wid == 0 && r < d) {
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-#pragma unroll
-      for (int j = 0; j < NN_NB; ++j) acc[j] += red[w][lane][j];
-#pragma unroll
-    for (int j = 0; j < NN_NB; ++j) {
-      if (!jok[j]) continue;
-      double o = (double)acc[j];
-      if (alpha != 0.0) o += alpha * to_f64<TV>(V[r + (int64_t)(j0 + j) * ldv]);
-      const int64_t oi = out_row ? r * ldo + (j0 + j) : r + (int64_t)(j0 + j) * ldo;
-      Out[oi] = from_f64<TO>(o);
-    }
+  for (int e = tid; e < R * NN_NB; e += 256) {
+    const int rr = e % R, j = e / R;
+    const int64_t row = blockIdx.x * (int64_t)R + rr;
+    if (row >= d || j0 + j >= nb) continue;
+    ACC s = ACC(0);
+    for (int u = 0; u < G; ++u) s += red[(u * R + rr) * (NN_NB + 1) + j];
+    double o = (double)s;
+    if (alpha != 0.0) o += alpha * to_f64<TV>(V[row + (int64_t)(j0 + j) * ldv]);
+    const int64_t oi = out_row ? row * ldo + (j0 + j) : row + (int64_t)(j0 + j) * ldo;
+    Out[oi] = from_f64<TO>(o);
   }
 }
 
-void tn_geometry(int64_t d, int64_t m, int64_t nb, int64_t* chunks, int64_t* rows) {
-  const int64_t ygroups = ((m + 4 * TN_MT - 1) / (4 * TN_MT)) * ((nb + TN_NB - 1) / TN_NB);
-  const int64_t target = 2048;
-  int64_t c = (target + ygroups - 1) / ygroups;
-  const int64_t cmax = std::max<int64_t>(1, (d + 255) / 256);  // >= 4 rows per lane
-  c = std::max<int64_t>(1, std::min(c, cmax));
-  int64_t rp = (d + c - 1) / c;
-  rp = ((rp + 63) / 64) * 64;
-  *rows = rp;
-  *chunks = (d + rp - 1) / rp;
+// 64 S rows per wave, 4 waves per workgroup: S = 4 when that still gives
+// 1024 workgroups, else 2, else 1.
+int tn_steps(int64_t d, int64_t m) {
+  const int64_t tiles = (m + 15) / 16;
+  for (int S : {4, 2}) {
+    const int64_t chunks = (d + 256 * S - 1) / (256 * S);
+    if (chunks * tiles >= 1024) return S;
+  }
+  return 1;
 }
 
-template <typename TA, typename TB, typename ACC>
+template <typename TA, typename TB>
 hipError_t tn_launch_t(int64_t d, int64_t m, int64_t nb, const void* A, int64_t lda,
                        const void* B, int64_t ldb, double* part, int64_t chunks,
                        const int* gate, hipStream_t s) {
-  int64_t c, rows;
-  tn_geometry(d, m, nb, &c, &rows);
-  if (c != chunks) return hipErrorInvalidValue;
-  dim3 g((unsigned)chunks, (unsigned)((m + 4 * TN_MT - 1) / (4 * TN_MT)),
-         (unsigned)((nb + TN_NB - 1) / TN_NB));
-  hipLaunchKernelGGL((tn_partial_kernel<TA, TB, ACC>), g, dim3(256), 0, s, d, (int)m, (int)nb,
-                     (const TA*)A, lda, (const TB*)B, ldb, part, rows, gate);
+  const int S = tn_steps(d, m);
+  if ((d + 256 * S - 1) / (256 * S) != chunks) return hipErrorInvalidValue;
+  dim3 g((unsigned)chunks, (unsigned)((m + 15) / 16), (unsigned)((nb + 15) / 16));
+  if (S == 4)
+    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 4>), g, dim3(256), 0, s, d, (int)m, (int)nb,
+                       (const TA*)A, lda, (const TB*)B, ldb, part, gate);
+  else if (S == 2)
+    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 2>), g, dim3(256), 0, s, d, (int)m, (int)nb,
+                       (const TA*)A, lda, (const TB*)B, ldb, part, gate);
+  else
+    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 1>), g, dim3(256), 0, s, d, (int)m, (int)nb,
+                       (const TA*)A, lda, (const TB*)B, ldb, part, gate);
   return hipGetLastError();
 }
 
+// Rows per nn workgroup: 64 when that still gives 384 workgroups (long
+// loops, little Z traffic), else 32, else 16 (more workgroups).
 template <typename TA, typename TV, typename TO, typename ACC>
 hipError_t nn_launch_t(int64_t d, int64_t m, int64_t nb, const void* A, int64_t lda,
                        const double* Z, int64_t ldz, double alpha, const void* V, int64_t ldv,
                        void* Out, int64_t ldo, bool out_row, const int* gate, hipStream_t s) {
-  dim3 g((unsigned)((d + 63) / 64), (unsigned)((nb + NN_NB - 1) / NN_NB));
-  hipLaunchKernelGGL((nn_kernel<TA, TV, TO, ACC>), g, dim3(256), 0, s, d, (int)m, (int)nb,
-                     (const TA*)A, lda, Z, ldz, alpha, (const TV*)V, ldv, (TO*)Out, ldo,
-                     out_row ? 1 : 0, gate);
+  const unsigned gy = (unsigned)((nb + NN_NB - 1) / NN_NB);
+  const int orow = out_row ? 1 : 0;
+#define NN_GO(R_, B_)                                                                          \
+  hipLaunchKernelGGL((nn_kernel<TA, TV, TO, ACC, R_, B_>),                                     \
+                     dim3((unsigned)((d + R_ - 1) / R_), gy), dim3(256), 0, s, d, (int)m,     \
+                     (int)nb, (const TA*)A, lda, Z, ldz, alpha, (const TV*)V, ldv, (TO*)Out,  \
+                     ldo, orow, gate)
+  if (d / 64 >= 384)
+    NN_GO(64, 8);
+  else if (d / 32 >= 384)
+    NN_GO(32, 8);
+  else
+    NN_GO(16, 4);
+#undef NN_GO
   return hipGetLastError();
 }
 
 }  // namespace
 
 int64_t tn_chunks(int64_t d, int64_t m, int64_t nb) {
-  int64_t c, rows;
-  tn_geometry(d, m, nb, &c, &rows);
-  return c;
+  (void)nb;
+  const int S = tn_steps(d, m);
+  return (d + 256 * S - 1) / (256 * S);
 }
 
 hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT adt,
@@ -241,17 +271,17 @@ hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT
   if (d <= 0 || m <= 0 || nb <= 0) return hipSuccess;
   using bf = __hip_bfloat16;
   if (adt == DT::F64 && bdt == DT::F64)
-    return tn_launch_t<double, double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+    return tn_launch_t<double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   if (adt == DT::F32 && bdt == DT::F32)
-    return tn_launch_t<float, float, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+    return tn_launch_t<float, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   if (adt == DT::F32 && bdt == DT::F64)
-    return tn_launch_t<float, double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+    return tn_launch_t<float, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   if (adt == DT::F64 && bdt == DT::F32)
-    return tn_launch_t<double, float, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+    return tn_launch_t<double, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   if (adt == DT::BF16 && bdt == DT::F32)
-    return tn_launch_t<bf, float, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+    return tn_launch_t<bf, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   if (adt == DT::BF16 && bdt == DT::F64)
-    return tn_launch_t<bf, double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
+    return tn_launch_t<bf, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
   return hipErrorInvalidValue;
 }
 
@@ -261,7 +291,7 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
                                   hipStream_t s) {
   const int64_t mn = m * nb;
   if (mn <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((mn + 63) / 64)), dim3(256), 0, s,
                      chunks, m, nb, part, alpha, beta, C_col, ldc, zalpha, Z_row, ldz, gate);
   return hipGetLastError();
 }
@@ -271,6 +301,7 @@ hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, in
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
                      hipStream_t s, bool out_row) {
   if (d <= 0 || nb <= 0) return hipSuccess;
+  if (m < 0) return hipErrorInvalidValue;
   // In-place Out == A is only safe when one workgroup column covers all nb.
   if (Out == A && nb > NN_NB) return hipErrorInvalidValue;
   using bf = __hip_bfloat16;
