@@ -173,8 +173,9 @@ hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint6
 // Batched symmetric eigensolver, one workgroup per matrix. For matrix q:
 //   A_q at A + q*strideA (lda), w_q at w + q*stridew, Z_q at Z + q*strideZ (ldz).
 // n_q = ns[q] (device int array) or n when ns is null.  Eigenvalues ascending;
-// eigenvectors are computed for the top nvec_q = min(nvec, n_q) eigenvalues
-// (nvec <= 0: all) and stored in columns n_q-nvec_q .. n_q-1 of Z_q.
+// only the top nvec_q = min(nvec, n_q) eigenvalues (nvec <= 0: all) are
+// computed (the others are returned as 0), with their eigenvectors in columns
+// n_q-nvec_q .. n_q-1 of Z_q.
 size_t syev_work_bytes(int64_t nmax);
 void syev_timing_enable(bool on);
 void syev_timing_report(FILE* f);

@@ -1,7 +1,8 @@
 // Small dense FP64 products: general GEMM for the cores (n x n and n x k
-// factors of the exponentials) and the Gram matrix P^T P of the scatter
-// factors.  Register-tiled FMA kernels: 64 x 64 output tiles, 256 threads,
-// 4 x 4 outputs per thread, K staged through LDS in slices of 16.
+// factors of the exponentials) on the matrix cores, and the Gram matrix
+// P^T P of the scatter factors (register-tiled FMA kernel: 64 x 64 output
+// tiles, 256 threads, 4 x 4 outputs per thread, K staged through LDS in
+// slices of 16).
 #include "common.h"
 
 namespace eda {
@@ -11,76 +12,65 @@ namespace {
 constexpr int GT = 64;   // tile edge
 constexpr int GK = 16;   // K slice
 
-// C = alpha op(A) diag(dk) op(B) + beta C
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MT = 32;  // output tile edge of the matrix-core GEMM
+constexpr int MK = 16;  // K slice
+
+// C = alpha op(A) diag(dk) op(B) + beta C on the matrix cores: a 256-thread
+// workgroup owns a 32 x 32 tile of C, each wave one 16 x 16 block of it,
+// accumulated by v_mfma_f64_16x16x4f64 over K slices of 16 staged in LDS.
+// Operand lane layout: A(i, k) at lane i + 16 k, B(k, j) at lane j + 16 k;
+// accumulator element v of lane l is C(4 v + l / 16, l % 16).
 __global__ __launch_bounds__(256) void gemm_kernel(bool ta, bool tb, int64_t m, int64_t n, int64_t k,
                                                    double alpha, const double* __restrict__ A,
                                                    int64_t lda, const double* __restrict__ dk,
                                                    const double* __restrict__ B, int64_t ldb,
                                                    double beta, double* __restrict__ C,
                                                    int64_t ldc) {
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
+  __shared__ double As[MT][MK + 1];  // op(A)(i, k)
+  __shared__ double Bs[MK][MT + 1];  // op(B)(k, j)
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int64_t i0 = blockIdx.x * (int64_t)GT, j0 = blockIdx.y * (int64_t)GT;
-  double acc[4][4];
+  const int lane = tid & 63, wid = tid >> 6;
+  const int64_t i0 = blockIdx.x * (int64_t)MT, j0 = blockIdx.y * (int64_t)MT;
+  const int bi = (wid >> 1) * 16, bj = (wid & 1) * 16;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = 0; k0 < k; k0 += MK) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-
-  for (int64_t k0 = 0; k0 < k; k0 += GK) {
-    // op(A) tile: rows i0..i0+63, cols k0..k0+15 -> As[kk][ii]
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + q * 256;  // 512 elements of each tile
       int ii, kk;
-      if (!ta) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+      if (!ta) { ii = e & 31; kk = e >> 5; } else { kk = e & 15; ii = e >> 4; }
       const int64_t gi = i0 + ii, gk = k0 + kk;
       double v = 0.0;
       if (gi < m && gk < k) {
         v = ta ? A[gk + gi * lda] : A[gi + gk * lda];
         if (dk != nullptr) v *= dk[gk];
       }
-      As[kk][ii] = v;
-    }
-    // op(B) tile: rows k0..k0+15, cols j0..j0+63 -> Bs[kk][jj]
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
-      int jj, kk;
-      if (!tb) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
-      const int64_t gj = j0 + jj, gk = k0 + kk;
-      double v = 0.0;
-      if (gj < n && gk < k) v = tb ? B[gj + gk * ldb] : B[gk + gj * ldb];
-      Bs[kk][jj] = v;
+      As[ii][kk] = v;
+      int jj, kb;
+      if (!tb) { kb = e & 15; jj = e >> 4; } else { jj = e & 31; kb = e >> 5; }
+      const int64_t gj = j0 + jj, gk2 = k0 + kb;
+      double w = 0.0;
+      if (gj < n && gk2 < k) w = tb ? B[gj + gk2 * ldb] : B[gk2 + gj * ldb];
+      Bs[kb][jj] = w;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = As[kk][tx + 16 * q];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) b[q] = Bs[kk][ty + 16 * q];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+    for (int ks = 0; ks < MK; ks += 4) {
+      const double a = As[bi + (lane & 15)][ks + (lane >> 4)];
+      const double b = Bs[ks + (lane >> 4)][bj + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
   }
+  const int64_t gj = j0 + bj + (lane & 15);
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int64_t gi = i0 + tx + 16 * p;
-    if (gi >= m) continue;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t gj = j0 + ty + 16 * q;
-      if (gj >= n) continue;
-      double* cp = C + gi + gj * ldc;
-      *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[p][q];
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int64_t gi = i0 + bi + 4 * v + (lane >> 4);
+    if (gi >= m || gj >= n) continue;
+    double* cp = C + gi + gj * ldc;
+    *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[v];
   }
 }
 
@@ -179,7 +169,7 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
                        const double* A, int64_t lda, const double* dk, const double* B,
                        int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  dim3 g((unsigned)((m + GT - 1) / GT), (unsigned)((n + GT - 1) / GT));
+  dim3 g((unsigned)((m + MT - 1) / MT), (unsigned)((n + MT - 1) / MT));
   hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, dk, B, ldb,
                      beta, C, ldc);
   return hipGetLastError();

@@ -72,6 +72,32 @@ __device__ __forceinline__ double blk_min(double v, double* red) {
   return s;
 }
 
+// sum_k a[k*sa] b[k*sb], k < len: loads issued eight at a time into four
+// accumulators (fixed order, so the result is reproducible).
+__device__ __forceinline__ double dot_pipe(const double* __restrict__ a, int64_t sa,
+                                           const double* __restrict__ b, int64_t sb, int len) {
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int k = 0;
+  for (; k + 8 <= len; k += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x[u] = a[(int64_t)(k + u) * sa];
+      y[u] = b[(int64_t)(k + u) * sb];
+    }
+    acc0 += x[0] * y[0];
+    acc1 += x[1] * y[1];
+    acc2 += x[2] * y[2];
+    acc3 += x[3] * y[3];
+    acc0 += x[4] * y[4];
+    acc1 += x[5] * y[5];
+    acc2 += x[6] * y[6];
+    acc3 += x[7] * y[7];
+  }
+  for (; k < len; ++k) acc0 += a[(int64_t)k * sa] * b[(int64_t)k * sb];
+  return (acc0 + acc1) + (acc2 + acc3);
+}
+
 __device__ __forceinline__ uint64_t hash64(uint64_t x) {
   x += 0x9e3779b97f4a7c15ull;
   x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -384,10 +410,9 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   unsigned long long t_prev = clock64();
 
   // ---- 0. symmetrised working copy (lower triangle of the input) ---------
-  for (int64_t e = tid; e < (int64_t)n * n; e += NT) {
-    const int c = (int)(e / n), r = (int)(e - (int64_t)c * n);
-    A[r + c * ldA] = (r >= c) ? Aq[r + c * lda] : Aq[c + r * lda];
-  }
+  for (int c = wid; c < n; c += NW)
+    for (int r = lane; r < n; r += 64)
+      A[r + (int64_t)c * ldA] = (r >= c) ? Aq[r + c * lda] : Aq[c + r * lda];
   __syncthreads();
 
   SYEV_MARK(0);
@@ -423,12 +448,8 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
     }
     // p = tau * A22 v (A22 symmetric: column r equals row r)
     if (lds_a) {
-      for (int r = j + 1 + tid; r < n; r += NT) {
-        const double* ac = A + (int64_t)r * ldA;
-        double acc = 0.0;
-        for (int c = j + 1; c < n; ++c) acc += ac[c] * sv[c];
-        sw[r] = tv * acc;
-      }
+      for (int r = j + 1 + tid; r < n; r += NT)
+        sw[r] = tv * dot_pipe(A + (int64_t)r * ldA + j + 1, 1, sv + j + 1, 1, n - j - 1);
     } else {
       for (int r = j + 1 + wid; r < n; r += NW) {
         const double* ac = A + (int64_t)r * ldA;
@@ -445,10 +466,10 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
     const double K = 0.5 * tv * kk;
     for (int r = j + 1 + tid; r < n; r += NT) sw[r] -= K * sv[r];
     __syncthreads();
-    const int64_t mm = (int64_t)m1 * m1;
-    for (int64_t e = tid; e < mm; e += NT) {
-      const int c = j + 1 + (int)(e / m1), r = j + 1 + (int)(e % m1);
-      A[r + (int64_t)c * ldA] -= sv[r] * sw[c] + sw[r] * sv[c];
+    for (int c = j + 1 + wid; c < n; c += NW) {
+      const double svc = sv[c], swc = sw[c];
+      for (int r = j + 1 + lane; r < n; r += 64)
+        A[r + (int64_t)c * ldA] -= sv[r] * swc + sw[r] * svc;
     }
     __syncthreads();
   }
@@ -483,11 +504,12 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   if (zero_mat) tnorm = 1.0;
   const double fudge = 4.0 * eps * tnorm;
   const double atol = 0.5 * eps * tnorm;
+  // only the nv wanted (largest) eigenvalues are located
   int g = 1;
-  while (g < 64 && 2 * g * n <= NT) g *= 2;
+  while (g < 64 && 2 * g * nv <= NT) g *= 2;
   const int groups = NT / g;
   const int gl = tid % g, gi = tid / g;
-  for (int base = 0; base < n; base += groups) {
+  for (int base = n - nv; base < n; base += groups) {
     const int i = base + gi;
     if (i < n) {
       double lo = lo_g - fudge, hi = hi_g + fudge;
@@ -550,10 +572,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
             int i = 0;
             while ((i + 1) * (i + 2) / 2 <= p) ++i;
             const int jj = p - i * (i + 1) / 2;
-            double sdot = 0.0;
-            for (int pos = 0; pos < n; ++pos)
-              sdot += Zt[(int64_t)pos * nv + s0 + i] * Zt[(int64_t)pos * nv + s0 + jj];
-            Gc[i + jj * c] = sdot;
+            Gc[i + jj * c] = dot_pipe(Zt + s0 + i, nv, Zt + s0 + jj, nv, n);
           }
           __syncthreads();
           for (int jc = 0; jc < c; ++jc) {  // Cholesky G = L L^T, lower triangle
@@ -623,16 +642,15 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
       const double* v = A + (int64_t)j * ldA;  // v[j+1] = 1 implicit, v[r] for r > j+1
       for (int c = j + 1 + tid; c < n; c += NT) {
         const double* qc = A + (int64_t)c * ldA;
-        double s = qc[j + 1];
-        for (int r = j + 2; r < n; ++r) s += v[r] * qc[r];
-        sw[c] = tj * s;
+        sw[c] = tj * (qc[j + 1] + dot_pipe(v + j + 2, 1, qc + j + 2, 1, n - j - 2));
       }
       __syncthreads();
-      const int m1 = n - j - 1;
-      for (int64_t e = tid; e < (int64_t)m1 * m1; e += NT) {
-        const int c = j + 1 + (int)(e / m1), r = j + 1 + (int)(e % m1);
-        const double vr = (r == j + 1) ? 1.0 : v[r];
-        A[r + (int64_t)c * ldA] -= vr * sw[c];
+      for (int c = j + 1 + wid; c < n; c += NW) {
+        const double swc = sw[c];
+        for (int r = j + 1 + lane; r < n; r += 64) {
+          const double vr = (r == j + 1) ? 1.0 : v[r];
+          A[r + (int64_t)c * ldA] -= vr * swc;
+        }
       }
       __syncthreads();
     }
@@ -646,13 +664,11 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
 
   SYEV_MARK(5);
   // ---- 5. outputs: eigenvalues, Z = Q Z_T ---------------------------------
-  for (int i = tid; i < n; i += NT) wq[i] = zero_mat ? 0.0 : lamv[i];
-  for (int64_t e = tid; e < (int64_t)nv * n; e += NT) {
-    const int slot = (int)(e / n), pos = (int)(e - (int64_t)slot * n);
-    double s = 0.0;
-    for (int r = 0; r < n; ++r) s += A[pos + (int64_t)r * ldA] * Zt[(int64_t)r * nv + slot];
-    Zq[pos + (int64_t)(n0 + slot) * ldz] = s;
-  }
+  for (int i = tid; i < n; i += NT) wq[i] = (zero_mat || i < n - nv) ? 0.0 : lamv[i];
+  for (int slot = wid; slot < nv; slot += NW)
+    for (int pos = lane; pos < n; pos += 64)
+      Zq[pos + (int64_t)(n0 + slot) * ldz] = dot_pipe(A + pos, ldA, Zt + slot, nv, n);
+  SYEV_MARK(6);
 }
 
 bool syev_timing = false;
@@ -683,9 +699,9 @@ void syev_timing_enable(bool on) { syev_timing = on; }
 void syev_timing_report(FILE* f) {
   unsigned long long c[8] = {0};
   if (hipMemcpyFromSymbol(c, HIP_SYMBOL(g_syev_cycles), sizeof(c)) != hipSuccess) return;
-  const char* names[6] = {"copy", "tridiag", "eigvals", "invit", "clusters", "backtrans"};
+  const char* names[7] = {"copy", "tridiag", "eigvals", "invit", "clusters", "backtrans", "output"};
   std::fprintf(f, "[eda] syev cycles (matrix 0 of every launch):");
-  for (int i = 0; i < 6; ++i) std::fprintf(f, " %s=%llu", names[i], c[i]);
+  for (int i = 0; i < 7; ++i) std::fprintf(f, " %s=%llu", names[i], c[i]);
   std::fprintf(f, "\n");
 }
 
