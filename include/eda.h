@@ -201,6 +201,40 @@ eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* 
                      double* ritz, double* ritz_log, double* X, int64_t ldx,
                      double* resid, eda_info* info);
 
+/* One problem of a batch (eda_solve_batched).  H_W, H_B, X: device;
+ * ritz, ritz_log, resid: host arrays of t entries. */
+typedef struct {
+  int64_t d, n, k;          /* dimension, samples, classes (d >= 2, 2 <= k <= n)   */
+  const double* H_W;        /* d x n float64, ldw >= d                            */
+  int64_t ldw;
+  const double* H_B;        /* d x k float64, ldb >= d                            */
+  int64_t ldb;
+  int32_t t;                /* wanted pairs, 1 <= t <= 128, t < d                 */
+  double tol;               /* residual tolerance as in eda_solve                 */
+  double* ritz;             /* host out [t]                                       */
+  double* ritz_log;         /* host out [t]                                       */
+  double* X;                /* device out, d x t float64, ldx >= d                */
+  int64_t ldx;
+  double* resid;            /* host out [t]                                       */
+} eda_problem;
+
+/* Algorithm 3 for `count` independent problems of different shapes at once
+ * (folds and resampled splits of one data set, say).  Every problem is
+ * prepared as by eda_prepare (storage type `storage`) and solved as by
+ * eda_solve with the options `opt` (start_block must be NULL; problem p
+ * draws its start block from seed opt->seed + p), but the kernels of each
+ * phase run for all problems in one launch: the problems advance in
+ * lockstep, a converged problem drops out of the launches, and the
+ * argument arrays of a step are copied to the device in one transfer.
+ * infos, statuses: host arrays of `count` entries (may be NULL).  Returns
+ * EDA_OK when every problem succeeded, else the first failing status
+ * (argument errors are reported before any work is done).  Uses the
+ * handle's stream and workspaces; does not change the handle's own
+ * preparation.  Synchronises. */
+eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_problem* probs,
+                             eda_dtype storage, const eda_solve_opts* opt, eda_info* infos,
+                             eda_status* statuses);
+
 /* Gram matrix G = P^T P of the current preparation (float64, N x N with
  * N = n + k, P = [H_W H_B]); G: device out (ldg >= N).  Stream-ordered. */
 eda_status eda_gram(eda_handle h, double* G, int64_t ldg);

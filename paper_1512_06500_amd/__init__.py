@@ -35,7 +35,8 @@ _DTYPES = {"f64": EDA_F64, "f32": EDA_F32, "bf16": EDA_BF16, "fp8": EDA_FP8_E4M3
 
 EXPORTED_SYMBOLS = [
     "eda_create", "eda_destroy", "eda_strerror", "eda_last_error", "eda_scatter_factors",
-    "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_gram", "eda_syev",
+    "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_solve_batched", "eda_gram",
+    "eda_syev",
 ]
 
 
@@ -47,6 +48,18 @@ class SolveOpts(ctypes.Structure):
         ("start_block", ctypes.c_void_p), ("ld_start", ctypes.c_int64),
         ("check_every", ctypes.c_int32), ("max_refine", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("H_W", ctypes.c_void_p), ("ldw", ctypes.c_int64),
+        ("H_B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+        ("t", ctypes.c_int32), ("tol", ctypes.c_double),
+        ("ritz", ctypes.POINTER(ctypes.c_double)), ("ritz_log", ctypes.POINTER(ctypes.c_double)),
+        ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+        ("resid", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -110,6 +123,10 @@ def load_library():
                             ctypes.POINTER(dbl), vp, i64, ctypes.POINTER(dbl),
                             ctypes.POINTER(Info)]
     L.eda_solve.restype = ctypes.c_int
+    L.eda_solve_batched.argtypes = [vp, i32, ctypes.POINTER(Problem), ctypes.c_int,
+                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(Info),
+                                    ctypes.POINTER(ctypes.c_int)]
+    L.eda_solve_batched.restype = ctypes.c_int
     L.eda_gram.argtypes = [vp, vp, i64]
     L.eda_gram.restype = ctypes.c_int
     L.eda_syev.argtypes = [vp, i64, vp, i64, vp, vp, i64]
@@ -279,6 +296,54 @@ class Handle:
         if st not in (EDA_OK, EDA_ERR_NOCONV) and raise_on_error:
             raise EDAError(st, msg)
         return SolveResult(list(ritz), list(rlog), X, list(res), info.as_dict(), st, msg)
+
+    def solve_batched(self, problems, storage: str = "f64", block: int = 8, max_iter: int = 0,
+                      seed: int = 0, check_every: int = 0, resmode: str = "rel",
+                      krylov_dtype: str = "f64", max_refine: int = 0):
+        """Solve independent problems together (eda_solve_batched).
+
+        problems: list of (H_W, H_B, t, tol) with H_W, H_B float64 CUDA
+        tensors.  Returns (list of SolveResult, overall status)."""
+        torch = self._torch
+        cnt = len(problems)
+        arr = (Problem * cnt)()
+        keep = []
+        outs = []
+        for i, (H_W, H_B, t, tol) in enumerate(problems):
+            H_W = self._f64(H_W)
+            H_B = self._f64(H_B)
+            d = int(H_W.shape[0])
+            X = _empty_cm(d, t, torch.float64, H_W.device)
+            ritz = (ctypes.c_double * t)()
+            rlog = (ctypes.c_double * t)()
+            res = (ctypes.c_double * t)()
+            keep += [H_W, H_B]
+            outs.append((X, ritz, rlog, res, t))
+            arr[i] = Problem(d, int(H_W.shape[1]), int(H_B.shape[1]), H_W.data_ptr(), _ld(H_W),
+                             H_B.data_ptr(), _ld(H_B), t, float(tol), ritz, rlog, X.data_ptr(),
+                             _ld(X), res)
+        o = SolveOpts()
+        o.form = EDA_FORM_LANCZOS_M
+        o.block = block
+        o.max_iter = max_iter
+        o.resmode = EDA_RES_REL_THETA if resmode == "rel" else EDA_RES_NORMWISE
+        o.krylov_dtype = _DTYPES[krylov_dtype]
+        o.refine_dtype = EDA_F64
+        o.max_refine = max_refine
+        o.seed = seed
+        o.check_every = check_every
+        infos = (Info * cnt)()
+        stats = (ctypes.c_int * cnt)()
+        st = self.lib.eda_solve_batched(self._h, cnt, arr, _DTYPES[storage], ctypes.byref(o),
+                                        infos, stats)
+        msg = self.lib.eda_last_error(self._h).decode() if st != EDA_OK else ""
+        if st not in (EDA_OK, EDA_ERR_NOCONV):
+            raise EDAError(st, msg)
+        results = []
+        for i, (X, ritz, rlog, res, t) in enumerate(outs):
+            results.append(SolveResult(list(ritz), list(rlog), X, list(res), infos[i].as_dict(),
+                                       int(stats[i]), msg if stats[i] != EDA_OK else ""))
+        return results, st
 
     def gram(self):
         N = self.n + self.k

@@ -56,6 +56,157 @@ template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) {
 
 enum class DT : int { F64 = 0, F32 = 1, BF16 = 2 };
 
+// ---------------------------------------------------------------------------
+// Multi-problem launches.  Each kernel below exists once and takes its
+// arguments as a struct: either by value (one problem) or as a device array
+// indexed by blockIdx.z (one entry per problem, sizes may differ; the grid
+// covers the largest entry and surplus workgroups of smaller ones exit).
+// launch_*_multi(count, host, dev, s): `host` holds the count entries (used
+// for the grid, and passed by value when count == 1); `dev` is the same
+// array already resident on the device (may be null when count == 1).
+// ---------------------------------------------------------------------------
+struct TnArgs {      // part[(c * m + i) * nb + j] = sum over chunk c of A(r, i) B(r, j)
+  int64_t d, m, nb, lda, ldb, chunks;
+  const void* A;
+  const void* B;
+  double* part;
+  const int* gate;
+};
+struct ReduceArgs {  // C = beta C + alpha sum_c part (col-major), Z = zalpha sum (row-major)
+  int64_t chunks, m, nb, ldc, ldz;
+  const double* part;
+  double alpha, beta, zalpha;
+  double* C;
+  double* Z;
+  const int* gate;
+};
+struct NnArgs {      // Out = alpha V + A Z
+  int64_t d, m, nb, lda, ldz, ldv, ldo;
+  const void* A;
+  const double* Z;
+  double alpha;
+  const void* V;
+  void* Out;
+  int out_row;
+  const int* gate;
+};
+struct CholArgs {
+  int64_t b, ldg, ldri, ldrp, ldro, m, ldhc;
+  const double* G;
+  double* Rinv;
+  const double* Rprev;
+  double* Rout;
+  const double* hcol;
+  double ratio;
+  int* flag;
+  const int* gate;
+};
+struct PcholArgs {
+  int64_t b, ldg, m, ldhc, ldz, ldr;
+  const double* G;
+  const double* hcol;
+  double tau, ratio;
+  int equil;
+  double* Z;
+  double* R;
+  int* mask;
+  int* flag;
+};
+struct MaskedRandnArgs {  // Q[:, j] = seeded Gaussian where mask[j] != 0
+  int64_t d, b, ldq;
+  const int* mask;
+  uint64_t seed;
+  void* Q;
+};
+struct RandnArgs { int64_t d, b, ldv; uint64_t seed; double* V; };
+struct Copy2dArgs { int64_t rows, cols, lds, ldd; const void* src; void* dst; };
+struct FillArgs { int64_t count; double v; double* dst; };
+struct FillI32Args { int64_t count; int v; int* dst; };
+struct SymArgs { int64_t m, ldh, ldt; const double* H; double* T; };
+struct RitzEstArgs {
+  int64_t m, b, cnt, lds, ldbm;
+  const double* w;
+  const double* S;
+  const double* Bm;
+  double* th;
+  double* res;
+};
+struct GatherArgs { int64_t m, cnt, lds, ldsd; const double* S; double* Sd; };
+struct SetDiagArgs { int64_t cnt, ldd; const double* v; double* D; };
+struct CouplingArgs {
+  int64_t m, b, kk, ldbm, ldsd, ldh;
+  const double* Bm;
+  const double* Sd;
+  double* Hn;
+};
+struct ResidArgs {
+  int64_t d, t, ldmy, ldy, ldr;
+  const double* MY;
+  const double* Y;
+  const double* theta;
+  double* R;
+  double* res;
+};
+struct DescArgs { int64_t cnt, n; const double* w; double* out; };
+struct SignArgs { int64_t d, t, ldx; double* X; };
+struct FlagArgs { int* flags; };
+struct SyevArgs {    // one symmetric eigenproblem, see launch_syev
+  int64_t n, lda, ldz, nvec;
+  const double* A;
+  double* w;
+  double* Z;
+  double* work;
+};
+
+// Kernel-side selection of the argument source of a multi launch.
+template <typename A>
+inline void pick(int count, const A* host, const A* dev, const A** arr, A* one) {
+  *arr = (count == 1) ? nullptr : dev;
+  *one = (count == 1) ? host[0] : A{};
+}
+
+hipError_t launch_tn_multi(int count, const TnArgs* host, const TnArgs* dev, DT adt, DT bdt,
+                           hipStream_t s);
+hipError_t launch_reduce_multi(int count, const ReduceArgs* host, const ReduceArgs* dev,
+                               hipStream_t s);
+hipError_t launch_nn_multi(int count, const NnArgs* host, const NnArgs* dev, DT adt, DT vdt,
+                           DT odt, hipStream_t s);
+hipError_t launch_chol_multi(int count, const CholArgs* host, const CholArgs* dev, hipStream_t s);
+hipError_t launch_pchol_multi(int count, const PcholArgs* host, const PcholArgs* dev,
+                              hipStream_t s);
+hipError_t launch_masked_randn_multi(int count, const MaskedRandnArgs* host,
+                                     const MaskedRandnArgs* dev, DT qdt, hipStream_t s);
+hipError_t launch_randn_multi(int count, const RandnArgs* host, const RandnArgs* dev,
+                              hipStream_t s);
+hipError_t launch_copy2d_multi(int count, const Copy2dArgs* host, const Copy2dArgs* dev, DT sdt,
+                               DT ddt, hipStream_t s);
+hipError_t launch_fill_multi(int count, const FillArgs* host, const FillArgs* dev, hipStream_t s);
+hipError_t launch_fill_i32_multi(int count, const FillI32Args* host, const FillI32Args* dev,
+                                 hipStream_t s);
+hipError_t launch_symmetrize_multi(int count, const SymArgs* host, const SymArgs* dev,
+                                   hipStream_t s);
+hipError_t launch_ritz_estimates_multi(int count, const RitzEstArgs* host, const RitzEstArgs* dev,
+                                       hipStream_t s);
+hipError_t launch_gather_desc_multi(int count, const GatherArgs* host, const GatherArgs* dev,
+                                    hipStream_t s);
+hipError_t launch_set_diag_multi(int count, const SetDiagArgs* host, const SetDiagArgs* dev,
+                                 hipStream_t s);
+hipError_t launch_restart_coupling_multi(int count, const CouplingArgs* host,
+                                         const CouplingArgs* dev, hipStream_t s);
+hipError_t launch_ritz_residual_multi(int count, const ResidArgs* host, const ResidArgs* dev,
+                                      hipStream_t s);
+hipError_t launch_desc_values_multi(int count, const DescArgs* host, const DescArgs* dev,
+                                    hipStream_t s);
+hipError_t launch_sign_fix_multi(int count, const SignArgs* host, const SignArgs* dev,
+                                 hipStream_t s);
+hipError_t launch_flag_fold_multi(int count, const FlagArgs* host, const FlagArgs* dev,
+                                  hipStream_t s);
+hipError_t launch_syev_multi(int count, const SyevArgs* host, const SyevArgs* dev,
+                             hipStream_t s);
+// Chunk count of a tn launch for one entry (the step count S is chosen from
+// the largest d and m of the launch, so pass those).
+int64_t tn_chunks_for(int64_t d, int64_t dmax, int64_t mmax);
+
 // k_basic.hip ---------------------------------------------------------------
 // H_W, H_B from class-contiguous samples (counts given as offsets[k+1] on device).
 hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int64_t ldx,

@@ -319,6 +319,10 @@ void eda_destroy(eda_handle h) {
     for (Buf* b : all) release(*b);
     for (auto& c : h->cores) release(c.buf);
     for (hipEvent_t e : h->op_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->prep_ev)
+      if (e != nullptr) (void)hipEventDestroy(e);
+    if (h->pin != nullptr) (void)hipHostFree(h->pin);
+    destroy_batch_state(h);
   }
   delete h;
 }
@@ -352,8 +356,12 @@ eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k, co
   return EDA_OK;
 }
 
-eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
-                       int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
+}  // extern "C"
+
+namespace eda {
+
+eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
+                         int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
   if (h == nullptr) return EDA_ERR_ARG;
   if (d < 2 || k < 2 || n < k) return fail(h, EDA_ERR_ARG, "need d>=2, k>=2, n>=k");
   if (n + k > 2048) return fail(h, EDA_ERR_ARG, "n+k=%lld exceeds 2048", (long long)(n + k));
@@ -368,10 +376,9 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const doub
   for (auto& c : h->cores) release(c.buf);
   h->cores.clear();
 
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, h->stream));
+  for (int q = 0; q < 2; ++q)
+    if (h->prep_ev[q] == nullptr) HIPCHK(hipEventCreate(&h->prep_ev[q]));
+  HIPCHK(hipEventRecord(h->prep_ev[0], h->stream));
 
   const int64_t N = n + k;
   h->d = d;
@@ -381,18 +388,29 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const doub
   h->storage = storage;
   h->ldp = round_up(d, 64);
 
+  // pinned scalars: [flag | normW | eig(G_BB) (k) | eig(G_WW) (n)]
+  const size_t pin_bytes = (size_t)(2 + k + n) * 8;
+  if (h->pin_cap < pin_bytes) {
+    if (h->pin != nullptr) {
+      HIPCHK(hipStreamSynchronize(h->stream));
+      (void)hipHostFree(h->pin);
+      h->pin = nullptr;
+      h->pin_cap = 0;
+    }
+    if (hipHostMalloc(&h->pin, pin_bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      h->pin = nullptr;
+      return fail(h, EDA_ERR_NOMEM, "pinned host allocation of %zu bytes failed", pin_bytes);
+    }
+    h->pin_cap = pin_bytes;
+  }
+  double* pin = (double*)h->pin;
+
   STCHK(ensure(h, h->flags, 64));
   HIPCHK(launch_fill_i32(16, 0, h->flags.i(), h->stream));
   HIPCHK(launch_nonfinite(d, n, H_W, ldw, h->flags.i(), h->stream));
   HIPCHK(launch_nonfinite(d, k, H_B, ldb, h->flags.i(), h->stream));
-  int bad = 0;
-  HIPCHK(hipMemcpyAsync(&bad, h->flags.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  if (bad) {
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return fail(h, EDA_ERR_NONFINITE, "NaN or Inf in H_W or H_B");
-  }
+  HIPCHK(hipMemcpyAsync(pin, h->flags.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
 
   // a1: factor ingest, P = [H_W H_B] in storage precision, plus a float64
   // master when the storage is narrower (Gram, cores and refinement use it)
@@ -419,6 +437,7 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const doub
   // eig(H_W^T H_W) + phi weights; both routes are exact up to rounding.
   const char* wc = std::getenv("EDA_WCORE");
   const bool w_by_eig = (wc != nullptr && std::strcmp(wc, "eig") == 0);
+  h->prep_wbyeig = w_by_eig;
   STCHK(ensure(h, h->eigW, (size_t)2 * n * 8));
   STCHK(ensure(h, h->eigZ, (size_t)2 * n * n * 8));
   STCHK(ensure(h, h->normbuf, 64));
@@ -430,33 +449,54 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const doub
     STCHK(ensure(h, h->syev_work, 2 * syev_work_bytes(n)));
     HIPCHK(launch_syev(2, n, h->nsbuf.i(), h->G.d(), N, n + n * N, h->eigW.d(), n, h->eigZ.d(),
                        n, n * n, 0, h->syev_work.d(), h->stream));
-    h->hwW.assign(n, 0.0);
-    HIPCHK(hipMemcpyAsync(h->hwW.data(), h->eigW.d(), n * 8, hipMemcpyDeviceToHost, h->stream));
-    h->w_eig = true;
+    HIPCHK(hipMemcpyAsync(pin + 2 + k, h->eigW.d(), n * 8, hipMemcpyDeviceToHost, h->stream));
   } else {
     STCHK(ensure(h, h->syev_work, syev_work_bytes(k)));
     HIPCHK(launch_syev(1, k, nullptr, h->G.d() + n + n * N, N, 0, h->eigW.d() + n, 0,
                        h->eigZ.d() + n * n, n, 0, 0, h->syev_work.d(), h->stream));
   }
   HIPCHK(launch_norm1(n, h->G.d(), N, h->normbuf.d(), h->stream));
-  h->hwB.assign(k, 0.0);
-  HIPCHK(hipMemcpyAsync(h->hwB.data(), h->eigW.d() + n, k * 8, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync(&h->normW, h->normbuf.d(), 8, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpyAsync(pin + 2, h->eigW.d() + n, k * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(pin + 1, h->normbuf.d(), 8, hipMemcpyDeviceToHost, h->stream));
+  return EDA_OK;
+}
+
+eda_status prepare_end(eda_handle h) {
+  const double* pin = (const double*)h->pin;
+  const int64_t n = h->n, k = h->k;
+  int bad = 0;
+  std::memcpy(&bad, pin, sizeof(int));
+  if (bad) return fail(h, EDA_ERR_NONFINITE, "NaN or Inf in H_W or H_B");
+  h->normW = pin[1];
+  h->hwB.assign(pin + 2, pin + 2 + k);
+  if (h->prep_wbyeig) {
+    h->hwW.assign(pin + 2 + k, pin + 2 + k + n);
+    h->w_eig = true;
+  }
   double lbmax = 0.0;
   for (double v : h->hwB) lbmax = std::max(lbmax, v);
   h->shiftB = lbmax;  // s = lambda_max(S_B): every factor e^{lambda - s} <= 1
   h->alphaB = std::exp(-h->shiftB);
-
   STCHK(build_composite_cores(h));
-  HIPCHK(hipEventRecord(e1, h->stream));
-  HIPCHK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  h->t_prepare_ms = ms;
+  HIPCHK(hipEventRecord(h->prep_ev[1], h->stream));
   h->prepared = true;
+  return EDA_OK;
+}
+
+}  // namespace eda
+
+extern "C" {
+
+eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
+                       int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
+  if (h == nullptr) return EDA_ERR_ARG;
+  STCHK(prepare_begin(h, d, n, k, H_W, ldw, H_B, ldb, storage));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  STCHK(prepare_end(h));
+  HIPCHK(hipEventSynchronize(h->prep_ev[1]));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, h->prep_ev[0], h->prep_ev[1]));
+  h->t_prepare_ms = ms;
   return EDA_OK;
 }
 

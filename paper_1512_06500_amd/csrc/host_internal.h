@@ -21,6 +21,8 @@ struct Buf {
   char* c() const { return (char*)p; }
 };
 
+struct BatchState;  // eda_solve_batched workspaces (eda_batched.cpp)
+
 struct CoreEntry {
   int which = -1;
   double c = 0.0;
@@ -52,6 +54,12 @@ struct eda_handle_s {
   bool w_eig = false;   // eigenpairs of H_W^T H_W available
   std::vector<double> hwW, hwB;
   double t_prepare_ms = 0.0;
+  // pinned host scalars of the preparation (non-finite flag, ||G_WW||_1,
+  // eigenvalues of G_BB and of G_WW), read back without a blocking copy
+  void* pin = nullptr;
+  size_t pin_cap = 0;
+  hipEvent_t prep_ev[2] = {nullptr, nullptr};
+  bool prep_wbyeig = false;
 
   // workspaces
   eda::Buf part, Ysm, Zsm, syev_work, offs, flags, mask;
@@ -59,6 +67,9 @@ struct eda_handle_s {
 
   // solver
   eda::Buf Q[2], H[2], Wb, T, wT, S, Sd, hz, Gs, Rinv, R1, Yb, MYb, dtheta, dres, refine;
+
+  // batched solver
+  eda::BatchState* batch = nullptr;
 };
 
 namespace eda {
@@ -75,6 +86,16 @@ inline DT dt_of(eda_dtype t) {
 }
 inline size_t dt_size(DT t) { return t == DT::F64 ? 8 : (t == DT::F32 ? 4 : 2); }
 inline int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
+
+// eda_prepare in two halves: prepare_begin validates and enqueues every
+// kernel up to the small eigensolves, with the scalars the host needs copied
+// asynchronously into pinned memory; after the stream has drained,
+// prepare_end reads them (non-finite check, spectral shift) and enqueues the
+// core construction.  Nothing in either half blocks the host.
+eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
+                         int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage);
+eda_status prepare_end(eda_handle h);
+void destroy_batch_state(eda_handle h);
 
 // Low-rank exponential apply on columns [c0, c0+Nc) of P (the storage copy,
 // or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.

@@ -76,8 +76,11 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(256) void randn_kernel(int64_t d, int64_t b, uint64_t seed,
-                                                    double* __restrict__ V, int64_t ldv) {
+__global__ __launch_bounds__(256) void randn_kernel(const RandnArgs* __restrict__ arr, RandnArgs one) {
+  const RandnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  const int64_t d = a.d, b = a.b, ldv = a.ldv;
+  const uint64_t seed = a.seed;
+  double* __restrict__ V = a.V;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= d * b) return;
   const int64_t c = e / d, r = e - c * d;
@@ -90,12 +93,12 @@ __global__ __launch_bounds__(256) void randn_kernel(int64_t d, int64_t b, uint64
 }
 
 template <typename TS, typename TD>
-__global__ __launch_bounds__(256) void copy2d_kernel(int64_t rows, const TS* __restrict__ S, int64_t lds,
-                                                     TD* __restrict__ D, int64_t ldd) {
+__global__ __launch_bounds__(256) void copy2d_kernel(const Copy2dArgs* __restrict__ arr, Copy2dArgs one) {
+  const Copy2dArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t c = blockIdx.y;
-  if (r >= rows) return;
-  D[r + c * ldd] = from_f64<TD>(to_f64<TS>(S[r + c * lds]));
+  if (r >= a.rows || c >= a.cols) return;
+  ((TD*)a.dst)[r + c * a.ldd] = from_f64<TD>(to_f64<TS>(((const TS*)a.src)[r + c * a.lds]));
 }
 
 // Weights of a core G = V diag(f) V^T of the exponential exp(c H H^T)
@@ -120,10 +123,13 @@ __global__ __launch_bounds__(256) void core_weights_kernel(int64_t n, const doub
 
 // One workgroup per column: make the largest-magnitude entry positive
 // (ties: the smallest row index).
-__global__ __launch_bounds__(256) void sign_fix_kernel(int64_t d, double* __restrict__ X, int64_t ldx) {
+__global__ __launch_bounds__(256) void sign_fix_kernel(const SignArgs* __restrict__ arr, SignArgs one) {
+  const SignArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if ((int64_t)blockIdx.x >= a.t) return;
+  const int64_t d = a.d;
   __shared__ double sv[256];
   __shared__ int64_t si[256];
-  double* x = X + blockIdx.x * ldx;
+  double* x = a.X + blockIdx.x * a.ldx;
   double best = -1.0;
   int64_t bi = 0;
   for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
@@ -149,32 +155,37 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(int64_t d, double* __rest
   for (int64_t r = threadIdx.x; r < d; r += blockDim.x) x[r] *= sg;
 }
 
-__global__ __launch_bounds__(256) void fill_kernel(int64_t count, double v, double* __restrict__ dst) {
+__global__ __launch_bounds__(256) void fill_kernel(const FillArgs* __restrict__ arr, FillArgs one) {
+  const FillArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e < count) dst[e] = v;
+  if (e < a.count) a.dst[e] = a.v;
 }
 
-__global__ __launch_bounds__(256) void fill_i32_kernel(int64_t count, int v, int* __restrict__ dst) {
+__global__ __launch_bounds__(256) void fill_i32_kernel(const FillI32Args* __restrict__ arr, FillI32Args one) {
+  const FillI32Args a = arr != nullptr ? arr[blockIdx.z] : one;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e < count) dst[e] = v;
+  if (e < a.count) a.dst[e] = a.v;
 }
 
-__global__ __launch_bounds__(256) void symmetrize_kernel(int64_t m, const double* __restrict__ H, int64_t ldh,
-                                                         double* __restrict__ T, int64_t ldt) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= m * m) return;
-  const int64_t c = e / m, r = e - c * m;
-  T[r + c * ldt] = 0.5 * (H[r + c * ldh] + H[c + r * ldh]);
+__global__ __launch_bounds__(256) void symmetrize_kernel(const SymArgs* __restrict__ arr, SymArgs one) {
+  const SymArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= a.m || c >= a.m) return;
+  a.T[r + c * a.ldt] = 0.5 * (a.H[r + c * a.ldh] + a.H[c + r * a.ldh]);
 }
 
-__global__ __launch_bounds__(64) void ritz_estimates_kernel(int64_t m, int64_t b, int64_t cnt,
-                                                            const double* __restrict__ w,
-                                                            const double* __restrict__ S, int64_t lds,
-                                                            const double* __restrict__ Bm, int64_t ldbm,
-                                                            double* __restrict__ th,
-                                                            double* __restrict__ res) {
+__global__ __launch_bounds__(64) void ritz_estimates_kernel(const RitzEstArgs* __restrict__ arr,
+                                                            RitzEstArgs one) {
+  const RitzEstArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  const int64_t m = a.m, b = a.b, lds = a.lds, ldbm = a.ldbm;
+  const double* __restrict__ w = a.w;
+  const double* __restrict__ S = a.S;
+  const double* __restrict__ Bm = a.Bm;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
+  if (i >= a.cnt) return;
+  double* __restrict__ th = a.th;
+  double* __restrict__ res = a.res;
   const int64_t col = m - 1 - i;
   double acc = 0.0;
   for (int64_t r = 0; r < b; ++r) {
@@ -186,16 +197,16 @@ __global__ __launch_bounds__(64) void ritz_estimates_kernel(int64_t m, int64_t b
   res[i] = sqrt(acc);
 }
 
-__global__ __launch_bounds__(256) void gather_desc_kernel(int64_t m, int64_t cnt, const double* __restrict__ S,
-                                                          int64_t lds, double* __restrict__ Sd,
-                                                          int64_t ldsd) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= m * cnt) return;
-  const int64_t i = e / m, r = e - i * m;
-  Sd[r * ldsd + i] = S[r + (m - 1 - i) * lds];
+__global__ __launch_bounds__(256) void gather_desc_kernel(const GatherArgs* __restrict__ arr, GatherArgs one) {
+  const GatherArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (r >= a.m || i >= a.cnt) return;
+  a.Sd[r * a.ldsd + i] = a.S[r + (a.m - 1 - i) * a.lds];
 }
 
-__global__ void flag_fold_kernel(int* flags) {
+__global__ void flag_fold_kernel(const FlagArgs* __restrict__ arr, FlagArgs one) {
+  int* flags = (arr != nullptr ? arr[blockIdx.z] : one).flags;
   if (threadIdx.x == 0) {
     flags[1] |= flags[0];
     flags[0] = 0;
@@ -204,14 +215,18 @@ __global__ void flag_fold_kernel(int* flags) {
 
 // R[:, c] = MY[:, c] - theta_c Y[:, c] (stored when R is not null) and
 // res[c] = ||R[:, c]||_2, one workgroup per column, fixed-order block sum.
-__global__ __launch_bounds__(256) void ritz_residual_kernel(int64_t d, const double* __restrict__ MY,
-                                                            int64_t ldmy, const double* __restrict__ Y,
-                                                            int64_t ldy,
-                                                            const double* __restrict__ theta,
-                                                            double* __restrict__ R, int64_t ldr,
-                                                            double* __restrict__ res) {
-  __shared__ double red[8];
+__global__ __launch_bounds__(256) void ritz_residual_kernel(const ResidArgs* __restrict__ arr,
+                                                            ResidArgs one) {
+  const ResidArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int64_t c = blockIdx.x;
+  if (c >= a.t) return;
+  const int64_t d = a.d, ldmy = a.ldmy, ldy = a.ldy, ldr = a.ldr;
+  const double* __restrict__ MY = a.MY;
+  const double* __restrict__ Y = a.Y;
+  const double* __restrict__ theta = a.theta;
+  double* __restrict__ R = a.R;
+  double* __restrict__ res = a.res;
+  __shared__ double red[8];
   const double th = theta[c];
   double acc = 0.0;
   for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
@@ -224,16 +239,19 @@ __global__ __launch_bounds__(256) void ritz_residual_kernel(int64_t d, const dou
 }
 
 // out[i] = w[n - 1 - i] for i < cnt (ascending eigenvalues to descending).
-__global__ __launch_bounds__(256) void desc_values_kernel(int64_t cnt, const double* __restrict__ w,
-                                                          int64_t n, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void desc_values_kernel(const DescArgs* __restrict__ arr, DescArgs one) {
+  const DescArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < cnt) out[i] = w[n - 1 - i];
+  if (i < a.cnt) a.out[i] = a.w[a.n - 1 - i];
 }
 
-__global__ __launch_bounds__(256) void restart_coupling_kernel(int64_t m, int64_t b, int64_t kk,
-                                                               const double* __restrict__ Bm, int64_t ldbm,
-                                                               const double* __restrict__ Sd, int64_t ldsd,
-                                                               double* __restrict__ Hn, int64_t ldh) {
+__global__ __launch_bounds__(256) void restart_coupling_kernel(const CouplingArgs* __restrict__ arr,
+                                                               CouplingArgs one) {
+  const CouplingArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  const int64_t m = a.m, b = a.b, kk = a.kk, ldbm = a.ldbm, ldsd = a.ldsd, ldh = a.ldh;
+  const double* __restrict__ Bm = a.Bm;
+  const double* __restrict__ Sd = a.Sd;
+  double* __restrict__ Hn = a.Hn;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= b * kk) return;
   const int64_t c = e / b, r = e - c * b;
@@ -252,10 +270,10 @@ __global__ __launch_bounds__(256) void copy_block_kernel(int64_t rows, int64_t c
   D[r + c * ldd] = alpha * (trans ? S[c + r * lds] : S[r + c * lds]);
 }
 
-__global__ __launch_bounds__(256) void set_diag_kernel(int64_t cnt, const double* __restrict__ v,
-                                                       double* __restrict__ D, int64_t ldd) {
+__global__ __launch_bounds__(256) void set_diag_kernel(const SetDiagArgs* __restrict__ arr, SetDiagArgs one) {
+  const SetDiagArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < cnt) D[i + i * ldd] = v[i];
+  if (i < a.cnt) a.D[i + i * a.ldd] = a.v[i];
 }
 
 __global__ __launch_bounds__(256) void norm1_kernel(int64_t n, const double* __restrict__ A,
@@ -317,12 +335,6 @@ hipError_t launch_copy_block(int64_t rows, int64_t cols, double alpha, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_set_diag(int64_t cnt, const double* v, double* dst, int64_t ldd, hipStream_t s) {
-  if (cnt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(set_diag_kernel, dim3(nblk(cnt)), dim3(256), 0, s, cnt, v, dst, ldd);
-  return hipGetLastError();
-}
-
 hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int64_t ldx,
                           const int64_t* offsets, double* H_W, int64_t ldw, double* H_B,
                           int64_t ldb, hipStream_t s) {
@@ -353,102 +365,257 @@ hipError_t launch_nonfinite(int64_t d, int64_t cols, const double* H, int64_t ld
   return hipGetLastError();
 }
 
-hipError_t launch_randn(int64_t d, int64_t b, uint64_t seed, double* V, int64_t ldv,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(randn_kernel, dim3(nblk(d * b)), dim3(256), 0, s, d, b, seed, V, ldv);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy2d(int64_t rows, int64_t cols, const void* src, DT sdt, int64_t lds,
-                         void* dst, DT ddt, int64_t ldd, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
-  dim3 g(nblk(rows), (unsigned)cols);
-  if (sdt == DT::F64 && ddt == DT::F64)
-    hipLaunchKernelGGL((copy2d_kernel<double, double>), g, dim3(256), 0, s, rows,
-                       (const double*)src, lds, (double*)dst, ldd);
-  else if (sdt == DT::F64 && ddt == DT::F32)
-    hipLaunchKernelGGL((copy2d_kernel<double, float>), g, dim3(256), 0, s, rows,
-                       (const double*)src, lds, (float*)dst, ldd);
-  else if (sdt == DT::F32 && ddt == DT::F64)
-    hipLaunchKernelGGL((copy2d_kernel<float, double>), g, dim3(256), 0, s, rows,
-                       (const float*)src, lds, (double*)dst, ldd);
-  else
-    hipLaunchKernelGGL((copy2d_kernel<float, float>), g, dim3(256), 0, s, rows,
-                       (const float*)src, lds, (float*)dst, ldd);
-  return hipGetLastError();
-}
-
 hipError_t launch_core_weights(int64_t n, const double* lam, double c, double shift, double* f,
                                hipStream_t s) {
   hipLaunchKernelGGL(core_weights_kernel, dim3(nblk(n)), dim3(256), 0, s, n, lam, c, shift, f);
   return hipGetLastError();
 }
 
+// ---- multi-problem launchers (count == 1: arguments by value) -------------
+
+hipError_t launch_randn_multi(int count, const RandnArgs* host, const RandnArgs* dev,
+                              hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, nblk(host[p].d * host[p].b));
+  if (x == 0) return hipSuccess;
+  const RandnArgs* arr;
+  RandnArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(randn_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2d_multi(int count, const Copy2dArgs* host, const Copy2dArgs* dev, DT sdt,
+                               DT ddt, hipStream_t s) {
+  int64_t x = 0, y = 0;
+  for (int p = 0; p < count; ++p) {
+    if (host[p].rows <= 0 || host[p].cols <= 0) continue;
+    x = std::max<int64_t>(x, nblk(host[p].rows));
+    y = std::max<int64_t>(y, host[p].cols);
+  }
+  if (x == 0) return hipSuccess;
+  const Copy2dArgs* arr;
+  Copy2dArgs one;
+  pick(count, host, dev, &arr, &one);
+  dim3 g((unsigned)x, (unsigned)y, (unsigned)count);
+  if (sdt == DT::F64 && ddt == DT::F64)
+    hipLaunchKernelGGL((copy2d_kernel<double, double>), g, dim3(256), 0, s, arr, one);
+  else if (sdt == DT::F64 && ddt == DT::F32)
+    hipLaunchKernelGGL((copy2d_kernel<double, float>), g, dim3(256), 0, s, arr, one);
+  else if (sdt == DT::F32 && ddt == DT::F64)
+    hipLaunchKernelGGL((copy2d_kernel<float, double>), g, dim3(256), 0, s, arr, one);
+  else if (sdt == DT::F32 && ddt == DT::F32)
+    hipLaunchKernelGGL((copy2d_kernel<float, float>), g, dim3(256), 0, s, arr, one);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_sign_fix_multi(int count, const SignArgs* host, const SignArgs* dev,
+                                 hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, host[p].t);
+  if (x == 0) return hipSuccess;
+  const SignArgs* arr;
+  SignArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_multi(int count, const FillArgs* host, const FillArgs* dev, hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, nblk(host[p].count));
+  if (x == 0) return hipSuccess;
+  const FillArgs* arr;
+  FillArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32_multi(int count, const FillI32Args* host, const FillI32Args* dev,
+                                 hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, nblk(host[p].count));
+  if (x == 0) return hipSuccess;
+  const FillI32Args* arr;
+  FillI32Args one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize_multi(int count, const SymArgs* host, const SymArgs* dev,
+                                   hipStream_t s) {
+  int64_t x = 0, y = 0;
+  for (int p = 0; p < count; ++p) {
+    x = std::max<int64_t>(x, nblk(host[p].m));
+    y = std::max<int64_t>(y, host[p].m);
+  }
+  if (x == 0) return hipSuccess;
+  const SymArgs* arr;
+  SymArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)x, (unsigned)y, (unsigned)count), dim3(256),
+                     0, s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_estimates_multi(int count, const RitzEstArgs* host, const RitzEstArgs* dev,
+                                       hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, nblk(host[p].cnt, 64));
+  if (x == 0) return hipSuccess;
+  const RitzEstArgs* arr;
+  RitzEstArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(ritz_estimates_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(64), 0, s,
+                     arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_desc_multi(int count, const GatherArgs* host, const GatherArgs* dev,
+                                    hipStream_t s) {
+  int64_t x = 0, y = 0;
+  for (int p = 0; p < count; ++p) {
+    x = std::max<int64_t>(x, nblk(host[p].m));
+    y = std::max<int64_t>(y, host[p].cnt);
+  }
+  if (x == 0 || y == 0) return hipSuccess;
+  const GatherArgs* arr;
+  GatherArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(gather_desc_kernel, dim3((unsigned)x, (unsigned)y, (unsigned)count), dim3(256),
+                     0, s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_fold_multi(int count, const FlagArgs* host, const FlagArgs* dev,
+                                  hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  const FlagArgs* arr;
+  FlagArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(flag_fold_kernel, dim3(1, 1, (unsigned)count), dim3(64), 0, s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_residual_multi(int count, const ResidArgs* host, const ResidArgs* dev,
+                                      hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, host[p].t);
+  if (x == 0) return hipSuccess;
+  const ResidArgs* arr;
+  ResidArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(ritz_residual_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s,
+                     arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_desc_values_multi(int count, const DescArgs* host, const DescArgs* dev,
+                                    hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, nblk(host[p].cnt));
+  if (x == 0) return hipSuccess;
+  const DescArgs* arr;
+  DescArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(desc_values_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s,
+                     arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_restart_coupling_multi(int count, const CouplingArgs* host,
+                                         const CouplingArgs* dev, hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, nblk(host[p].b * host[p].kk));
+  if (x == 0) return hipSuccess;
+  const CouplingArgs* arr;
+  CouplingArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(restart_coupling_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0,
+                     s, arr, one);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_diag_multi(int count, const SetDiagArgs* host, const SetDiagArgs* dev,
+                                 hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, nblk(host[p].cnt));
+  if (x == 0) return hipSuccess;
+  const SetDiagArgs* arr;
+  SetDiagArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(set_diag_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s, arr,
+                     one);
+  return hipGetLastError();
+}
+
+// ---- single-problem wrappers ------------------------------------------------
+hipError_t launch_randn(int64_t d, int64_t b, uint64_t seed, double* V, int64_t ldv,
+                        hipStream_t s) {
+  RandnArgs a{d, b, ldv, seed, V};
+  return launch_randn_multi(1, &a, nullptr, s);
+}
+hipError_t launch_copy2d(int64_t rows, int64_t cols, const void* src, DT sdt, int64_t lds,
+                         void* dst, DT ddt, int64_t ldd, hipStream_t s) {
+  Copy2dArgs a{rows, cols, lds, ldd, src, dst};
+  return launch_copy2d_multi(1, &a, nullptr, sdt, ddt, s);
+}
 hipError_t launch_sign_fix(int64_t d, int64_t t, double* X, int64_t ldx, hipStream_t s) {
-  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)t), dim3(256), 0, s, d, X, ldx);
-  return hipGetLastError();
+  SignArgs a{d, t, ldx, X};
+  return launch_sign_fix_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_fill(int64_t count, double value, double* dst, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk(count)), dim3(256), 0, s, count, value, dst);
-  return hipGetLastError();
+  FillArgs a{count, value, dst};
+  return launch_fill_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_fill_i32(int64_t count, int value, int* dst, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(count)), dim3(256), 0, s, count, value, dst);
-  return hipGetLastError();
+  FillI32Args a{count, value, dst};
+  return launch_fill_i32_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_symmetrize(int64_t m, const double* H, int64_t ldh, double* T, int64_t ldt,
                              hipStream_t s) {
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(m * m)), dim3(256), 0, s, m, H, ldh, T, ldt);
-  return hipGetLastError();
+  SymArgs a{m, ldh, ldt, H, T};
+  return launch_symmetrize_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_ritz_estimates(int64_t m, int64_t b, int64_t cnt, const double* w,
                                  const double* S, int64_t lds, const double* Bm, int64_t ldbm,
                                  double* out_theta, double* out_res, hipStream_t s) {
-  hipLaunchKernelGGL(ritz_estimates_kernel, dim3(nblk(cnt, 64)), dim3(64), 0, s, m, b, cnt, w, S,
-                     lds, Bm, ldbm, out_theta, out_res);
-  return hipGetLastError();
+  RitzEstArgs a{m, b, cnt, lds, ldbm, w, S, Bm, out_theta, out_res};
+  return launch_ritz_estimates_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_gather_desc(int64_t m, int64_t cnt, const double* S, int64_t lds, double* Sd,
                               int64_t ldsd, hipStream_t s) {
-  hipLaunchKernelGGL(gather_desc_kernel, dim3(nblk(m * cnt)), dim3(256), 0, s, m, cnt, S, lds,
-                     Sd, ldsd);
-  return hipGetLastError();
+  GatherArgs a{m, cnt, lds, ldsd, S, Sd};
+  return launch_gather_desc_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_flag_fold(int* flags, hipStream_t s) {
-  hipLaunchKernelGGL(flag_fold_kernel, dim3(1), dim3(64), 0, s, flags);
-  return hipGetLastError();
+  FlagArgs a{flags};
+  return launch_flag_fold_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_ritz_residual(int64_t d, int64_t t, const double* MY, int64_t ldmy,
                                 const double* Y, int64_t ldy, const double* theta, double* R,
                                 int64_t ldr, double* res, hipStream_t s) {
-  if (t <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ritz_residual_kernel, dim3((unsigned)t), dim3(256), 0, s, d, MY, ldmy, Y, ldy,
-                     theta, R, ldr, res);
-  return hipGetLastError();
+  ResidArgs a{d, t, ldmy, ldy, ldr, MY, Y, theta, R, res};
+  return launch_ritz_residual_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_desc_values(int64_t cnt, const double* w, int64_t n, double* out,
                               hipStream_t s) {
-  if (cnt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(desc_values_kernel, dim3(nblk(cnt)), dim3(256), 0, s, cnt, w, n, out);
-  return hipGetLastError();
+  DescArgs a{cnt, n, w, out};
+  return launch_desc_values_multi(1, &a, nullptr, s);
 }
-
 hipError_t launch_restart_coupling(int64_t m, int64_t b, int64_t kk, const double* Bm,
                                    int64_t ldbm, const double* Sd, int64_t ldsd, double* Hn,
                                    int64_t ldh, hipStream_t s) {
-  hipLaunchKernelGGL(restart_coupling_kernel, dim3(nblk(b * kk)), dim3(256), 0, s, m, b, kk, Bm,
-                     ldbm, Sd, ldsd, Hn, ldh);
-  return hipGetLastError();
+  CouplingArgs a{m, b, kk, ldbm, ldsd, ldh, Bm, Sd, Hn};
+  return launch_restart_coupling_multi(1, &a, nullptr, s);
+}
+hipError_t launch_set_diag(int64_t cnt, const double* v, double* dst, int64_t ldd, hipStream_t s) {
+  SetDiagArgs a{cnt, ldd, v, dst};
+  return launch_set_diag_multi(1, &a, nullptr, s);
 }
 
 }  // namespace eda

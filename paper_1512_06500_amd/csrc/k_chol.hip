@@ -18,14 +18,18 @@ namespace {
 
 constexpr int CH_MAX = 128;
 
-__global__ __launch_bounds__(256) void chol_kernel(int b, const double* __restrict__ G, int64_t ldg,
-                                                   double* __restrict__ Rinv, int64_t ldri,
-                                                   const double* __restrict__ Rprev, int64_t ldrp,
-                                                   double* __restrict__ Rout, int64_t ldro,
-                                                   const double* __restrict__ hcol, int64_t m,
-                                                   int64_t ldhc, double ratio, int* flag,
-                                                   const int* __restrict__ gate) {
-  if (gate != nullptr && *gate == 0) return;
+__global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ arr, CholArgs one) {
+  const CholArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  const int b = (int)a.b;
+  const double* __restrict__ G = a.G;
+  double* __restrict__ Rinv = a.Rinv;
+  const double* __restrict__ Rprev = a.Rprev;
+  double* __restrict__ Rout = a.Rout;
+  const double* __restrict__ hcol = a.hcol;
+  const int64_t ldg = a.ldg, ldri = a.ldri, ldrp = a.ldrp, ldro = a.ldro, m = a.m, ldhc = a.ldhc;
+  const double ratio = a.ratio;
+  int* flag = a.flag;
   __shared__ double L[CH_MAX * (CH_MAX + 1)];
   __shared__ double diag0[CH_MAX];
   __shared__ int sflag;
@@ -112,12 +116,18 @@ __global__ __launch_bounds__(256) void chol_kernel(int b, const double* __restri
 // Outputs: Z (row-major, W Z = [Q_1, 0]), R (col-major, W = [Q_1 Q_2] R with
 // rows >= r zero), mask[j] = 1 for deflated output columns j >= r, and
 // *flag = 1 if a column was deflated or kept less than `ratio` of its norm.
-__global__ __launch_bounds__(64) void pchol_kernel(int b, const double* __restrict__ G, int64_t ldg,
-                                                   const double* __restrict__ hcol, int64_t m,
-                                                   int64_t ldhc, double tau, double ratio,
-                                                   int equil, double* __restrict__ Z, int64_t ldz,
-                                                   double* __restrict__ R, int64_t ldr,
-                                                   int* __restrict__ mask, int* flag) {
+__global__ __launch_bounds__(64) void pchol_kernel(const PcholArgs* __restrict__ arr, PcholArgs one) {
+  const PcholArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  const int b = (int)a.b;
+  const double* __restrict__ G = a.G;
+  const double* __restrict__ hcol = a.hcol;
+  const int64_t ldg = a.ldg, m = a.m, ldhc = a.ldhc, ldz = a.ldz, ldr = a.ldr;
+  const double tau = a.tau, ratio = a.ratio;
+  const int equil = a.equil;
+  double* __restrict__ Z = a.Z;
+  double* __restrict__ R = a.R;
+  int* __restrict__ mask = a.mask;
+  int* flag = a.flag;
   constexpr int PB = 64;
   __shared__ double A[PB * (PB + 1)];
   __shared__ double nrm0[PB];
@@ -245,10 +255,13 @@ __global__ __launch_bounds__(64) void pchol_kernel(int b, const double* __restri
 
 // Q[:, j] = seeded Gaussian for every column j with mask[j] != 0.
 template <typename T>
-__global__ __launch_bounds__(256) void fill_masked_randn_kernel(int64_t d, int64_t b,
-                                                                const int* __restrict__ mask,
-                                                                uint64_t seed, T* Q,
-                                                                int64_t ldq) {
+__global__ __launch_bounds__(256) void fill_masked_randn_kernel(const MaskedRandnArgs* __restrict__ arr,
+                                                                MaskedRandnArgs one) {
+  const MaskedRandnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  const int64_t d = a.d, b = a.b, ldq = a.ldq;
+  const int* __restrict__ mask = a.mask;
+  const uint64_t seed = a.seed;
+  T* Q = (T*)a.Q;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= d * b) return;
   const int64_t c = e / d, r = e - c * d;
@@ -268,26 +281,57 @@ __global__ __launch_bounds__(256) void fill_masked_randn_kernel(int64_t d, int64
 
 }  // namespace
 
+hipError_t launch_pchol_multi(int count, const PcholArgs* host, const PcholArgs* dev,
+                              hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  for (int p = 0; p < count; ++p)
+    if (host[p].b < 1 || host[p].b > 64) return hipErrorInvalidValue;
+  const PcholArgs* arr;
+  PcholArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(pchol_kernel, dim3(1, 1, (unsigned)count), dim3(64), 0, s, arr, one);
+  return hipGetLastError();
+}
+
 hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
                         int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
                         double* R, int64_t ldr, int* mask, int* flag, hipStream_t s) {
-  if (b < 1 || b > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pchol_kernel, dim3(1), dim3(64), 0, s, (int)b, G, ldg, hcol, m, ldhc, tau,
-                     ratio, equil ? 1 : 0, Z, ldz, R, ldr, mask, flag);
+  PcholArgs a{b, ldg, m, ldhc, ldz, ldr, G, hcol, tau, ratio, equil ? 1 : 0, Z, R, mask, flag};
+  return launch_pchol_multi(1, &a, nullptr, s);
+}
+
+hipError_t launch_masked_randn_multi(int count, const MaskedRandnArgs* host,
+                                     const MaskedRandnArgs* dev, DT qdt, hipStream_t s) {
+  int64_t x = 0;
+  for (int p = 0; p < count; ++p) x = std::max<int64_t>(x, (host[p].d * host[p].b + 255) / 256);
+  if (x == 0) return hipSuccess;
+  const MaskedRandnArgs* arr;
+  MaskedRandnArgs one;
+  pick(count, host, dev, &arr, &one);
+  const dim3 g((unsigned)x, 1, (unsigned)count);
+  if (qdt == DT::F64)
+    hipLaunchKernelGGL(fill_masked_randn_kernel<double>, g, dim3(256), 0, s, arr, one);
+  else if (qdt == DT::F32)
+    hipLaunchKernelGGL(fill_masked_randn_kernel<float>, g, dim3(256), 0, s, arr, one);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
                                     void* Q, DT qdt, int64_t ldq, hipStream_t s) {
-  const dim3 g((unsigned)((d * b + 255) / 256));
-  if (qdt == DT::F64)
-    hipLaunchKernelGGL(fill_masked_randn_kernel<double>, g, dim3(256), 0, s, d, b, mask, seed,
-                       (double*)Q, ldq);
-  else if (qdt == DT::F32)
-    hipLaunchKernelGGL(fill_masked_randn_kernel<float>, g, dim3(256), 0, s, d, b, mask, seed,
-                       (float*)Q, ldq);
-  else
-    return hipErrorInvalidValue;
+  MaskedRandnArgs a{d, b, ldq, mask, seed, Q};
+  return launch_masked_randn_multi(1, &a, nullptr, qdt, s);
+}
+
+hipError_t launch_chol_multi(int count, const CholArgs* host, const CholArgs* dev, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  for (int p = 0; p < count; ++p)
+    if (host[p].b < 1 || host[p].b > CH_MAX) return hipErrorInvalidValue;
+  const CholArgs* arr;
+  CholArgs one;
+  pick(count, host, dev, &arr, &one);
+  hipLaunchKernelGGL(chol_kernel, dim3(1, 1, (unsigned)count), dim3(256), 0, s, arr, one);
   return hipGetLastError();
 }
 
@@ -295,10 +339,8 @@ hipError_t launch_chol(int64_t b, const double* G, int64_t ldg, double* Rinv, in
                        const double* Rprev, int64_t ldrp, double* Rout, int64_t ldro,
                        const double* hcol, int64_t m, int64_t ldhc, double ratio, int* flag,
                        const int* gate, hipStream_t s) {
-  if (b < 1 || b > CH_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, s, (int)b, G, ldg, Rinv, ldri, Rprev,
-                     ldrp, Rout, ldro, hcol, m, ldhc, ratio, flag, gate);
-  return hipGetLastError();
+  CholArgs a{b, ldg, ldri, ldrp, ldro, m, ldhc, G, Rinv, Rprev, Rout, hcol, ratio, flag, gate};
+  return launch_chol_multi(1, &a, nullptr, s);
 }
 
 }  // namespace eda

@@ -72,30 +72,25 @@ __device__ __forceinline__ double blk_min(double v, double* red) {
   return s;
 }
 
-// sum_k a[k*sa] b[k*sb], k < len: loads issued eight at a time into four
+// sum_k a[k*sa] b[k*sb], k < len: loads issued U at a time into four
 // accumulators (fixed order, so the result is reproducible).
+template <int U>
 __device__ __forceinline__ double dot_pipe(const double* __restrict__ a, int64_t sa,
                                            const double* __restrict__ b, int64_t sb, int len) {
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   int k = 0;
-  for (; k + 8 <= len; k += 8) {
-    double x[8], y[8];
+  for (; k + U <= len; k += U) {
+    double x[U], y[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       x[u] = a[(int64_t)(k + u) * sa];
       y[u] = b[(int64_t)(k + u) * sb];
     }
-    acc0 += x[0] * y[0];
-    acc1 += x[1] * y[1];
-    acc2 += x[2] * y[2];
-    acc3 += x[3] * y[3];
-    acc0 += x[4] * y[4];
-    acc1 += x[5] * y[5];
-    acc2 += x[6] * y[6];
-    acc3 += x[7] * y[7];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u & 3] += x[u] * y[u];
   }
-  for (; k < len; ++k) acc0 += a[(int64_t)k * sa] * b[(int64_t)k * sb];
-  return (acc0 + acc1) + (acc2 + acc3);
+  for (; k < len; ++k) acc[0] += a[(int64_t)k * sa] * b[(int64_t)k * sb];
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 __device__ __forceinline__ uint64_t hash64(uint64_t x) {
@@ -361,24 +356,48 @@ __device__ unsigned long long g_syev_cycles[8];
     }                                                                           \
   } while (0)
 
+// Matrix q of the launch: given by sarr[q] when sarr is not null (any
+// pointers, each with its own work area of syev_work_doubles(nmax, NT)),
+// else at the strided positions below.
 template <int NT>
-__global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restrict__ ns,
-                                                  const double* __restrict__ Ain, int64_t lda,
+__global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ sarr, int nfix,
+                                                  const int* __restrict__ ns,
+                                                  const double* __restrict__ Ain, int64_t lda_,
                                                   int64_t strideA, double* __restrict__ wout,
                                                   int64_t stridew, double* __restrict__ Zout,
-                                                  int64_t ldz, int64_t strideZ, int nvec_req,
+                                                  int64_t ldz_, int64_t strideZ, int nvec_,
                                                   double* __restrict__ work, int64_t nmax,
                                                   int lds_a, int timing) {
   constexpr int NW = NT / 64;
+  constexpr int DU = NT > 256 ? 4 : 8;  // dot-product unroll within the register budget
   extern __shared__ double smem[];
   const int q = blockIdx.x;
-  const int n = (ns != nullptr) ? ns[q] : nfix;
+  int n, nvec_req;
+  int64_t lda, ldz;
+  const double* Aq;
+  double *wq, *Zq, *wk;
+  if (sarr != nullptr) {
+    const SyevArgs a = sarr[q];
+    n = (int)a.n;
+    lda = a.lda;
+    ldz = a.ldz;
+    nvec_req = (int)a.nvec;
+    Aq = a.A;
+    wq = a.w;
+    Zq = a.Z;
+    wk = a.work;
+  } else {
+    n = (ns != nullptr) ? ns[q] : nfix;
+    lda = lda_;
+    ldz = ldz_;
+    nvec_req = nvec_;
+    Aq = Ain + q * strideA;
+    wq = wout + q * stridew;
+    Zq = Zout + q * strideZ;
+    wk = work + q * syev_work_doubles(nmax, NT);
+  }
   if (n <= 0) return;
   const int nv = (nvec_req <= 0 || nvec_req > n) ? n : nvec_req;
-  const double* Aq = Ain + q * strideA;
-  double* wq = wout + q * stridew;
-  double* Zq = Zout + q * strideZ;
-  double* wk = work + q * syev_work_doubles(nmax, NT);
   double* gA = wk;                   // n x n (global path)
   double* dd = gA + nmax * nmax;
   double* ee = dd + nmax;
@@ -449,7 +468,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
     // p = tau * A22 v (A22 symmetric: column r equals row r)
     if (lds_a) {
       for (int r = j + 1 + tid; r < n; r += NT)
-        sw[r] = tv * dot_pipe(A + (int64_t)r * ldA + j + 1, 1, sv + j + 1, 1, n - j - 1);
+        sw[r] = tv * dot_pipe<DU>(A + (int64_t)r * ldA + j + 1, 1, sv + j + 1, 1, n - j - 1);
     } else {
       for (int r = j + 1 + wid; r < n; r += NW) {
         const double* ac = A + (int64_t)r * ldA;
@@ -572,7 +591,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
             int i = 0;
             while ((i + 1) * (i + 2) / 2 <= p) ++i;
             const int jj = p - i * (i + 1) / 2;
-            Gc[i + jj * c] = dot_pipe(Zt + s0 + i, nv, Zt + s0 + jj, nv, n);
+            Gc[i + jj * c] = dot_pipe<DU>(Zt + s0 + i, nv, Zt + s0 + jj, nv, n);
           }
           __syncthreads();
           for (int jc = 0; jc < c; ++jc) {  // Cholesky G = L L^T, lower triangle
@@ -642,7 +661,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
       const double* v = A + (int64_t)j * ldA;  // v[j+1] = 1 implicit, v[r] for r > j+1
       for (int c = j + 1 + tid; c < n; c += NT) {
         const double* qc = A + (int64_t)c * ldA;
-        sw[c] = tj * (qc[j + 1] + dot_pipe(v + j + 2, 1, qc + j + 2, 1, n - j - 2));
+        sw[c] = tj * (qc[j + 1] + dot_pipe<DU>(v + j + 2, 1, qc + j + 2, 1, n - j - 2));
       }
       __syncthreads();
       for (int c = j + 1 + wid; c < n; c += NW) {
@@ -667,16 +686,17 @@ __global__ __launch_bounds__(NT) void syev_kernel(int nfix, const int* __restric
   for (int i = tid; i < n; i += NT) wq[i] = (zero_mat || i < n - nv) ? 0.0 : lamv[i];
   for (int slot = wid; slot < nv; slot += NW)
     for (int pos = lane; pos < n; pos += 64)
-      Zq[pos + (int64_t)(n0 + slot) * ldz] = dot_pipe(A + pos, ldA, Zt + slot, nv, n);
+      Zq[pos + (int64_t)(n0 + slot) * ldz] = dot_pipe<DU>(A + pos, ldA, Zt + slot, nv, n);
   SYEV_MARK(6);
 }
 
 bool syev_timing = false;
 
 template <int NT>
-hipError_t syev_launch_t(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
-                         int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
-                         int64_t strideZ, int64_t nvec, double* work, hipStream_t s) {
+hipError_t syev_launch_t(const SyevArgs* sarr, int64_t batch, int64_t n, const int* ns,
+                         const double* A, int64_t lda, int64_t strideA, double* w, int64_t stridew,
+                         double* Z, int64_t ldz, int64_t strideZ, int64_t nvec, double* work,
+                         hipStream_t s) {
   const bool lds_a = n <= kLdsMax;
   const size_t lds = (size_t)syev_lds_doubles(n, lds_a) * sizeof(double);
   static bool attr_set = false;
@@ -686,8 +706,8 @@ hipError_t syev_launch_t(int64_t batch, int64_t n, const int* ns, const double* 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(syev_kernel<NT>, dim3((unsigned)batch), dim3(NT), lds, s, (int)n, ns, A, lda,
-                     strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n, lds_a ? 1 : 0,
+  hipLaunchKernelGGL(syev_kernel<NT>, dim3((unsigned)batch), dim3(NT), lds, s, sarr, (int)n, ns, A,
+                     lda, strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n, lds_a ? 1 : 0,
                      syev_timing ? 1 : 0);
   return hipGetLastError();
 }
@@ -715,10 +735,32 @@ hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A,
                        int64_t strideZ, int64_t nvec, double* work, hipStream_t s) {
   if (n < 1 || n > SYEV_NMAX || batch < 1) return hipErrorInvalidValue;
   if (n <= 256)
-    return syev_launch_t<256>(batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ, nvec,
-                              work, s);
-  return syev_launch_t<1024>(batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ, nvec,
-                             work, s);
+    return syev_launch_t<256>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
+                              nvec, work, s);
+  return syev_launch_t<1024>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
+                             nvec, work, s);
+}
+
+// Several problems of different size: `dev` holds the count entries on the
+// device; every entry's work area must hold syev_work_bytes(max n).
+hipError_t launch_syev_multi(int count, const SyevArgs* host, const SyevArgs* dev,
+                             hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  int64_t nmax = 0;
+  for (int p = 0; p < count; ++p) {
+    if (host[p].n < 0 || host[p].n > SYEV_NMAX) return hipErrorInvalidValue;
+    nmax = std::max(nmax, host[p].n);
+  }
+  if (nmax == 0) return hipSuccess;
+  if (count == 1) {
+    const SyevArgs& a = host[0];
+    return launch_syev(1, a.n, nullptr, a.A, a.lda, 0, a.w, 0, a.Z, a.ldz, 0, a.nvec, a.work, s);
+  }
+  if (nmax <= 256)
+    return syev_launch_t<256>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
+                              0, nullptr, s);
+  return syev_launch_t<1024>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
+                             0, nullptr, s);
 }
 
 }  // namespace eda

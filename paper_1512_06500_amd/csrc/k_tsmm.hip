@@ -41,24 +41,28 @@ template <typename T> __device__ __forceinline__ double ld64(const T* p) { retur
 
 // A^T B partial over one row chunk and one 16-column tile of A, nb <= 16 per
 // z-tile.  part[(chunk * m + i) * nb + j].  S: 64-row steps per wave.
+// blockIdx.x: row chunk, blockIdx.y: column tile + ytiles * (nb tile),
+// blockIdx.z: problem.
 template <typename TA, typename TB, int S>
-__global__ __launch_bounds__(256) void tn_mfma_kernel(int64_t d, int m, int nb,
-                                                      const TA* __restrict__ A, int64_t lda,
-                                                      const TB* __restrict__ B, int64_t ldb,
-                                                      double* __restrict__ part,
-                                                      const int* __restrict__ gate) {
-  if (gate != nullptr && *gate == 0) return;
+__global__ __launch_bounds__(256) void tn_mfma_kernel(const TnArgs* __restrict__ arr, TnArgs one,
+                                                      int ytiles) {
+  const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  const int64_t chunk = blockIdx.x;
+  const int yt = blockIdx.y % ytiles, zt = blockIdx.y / ytiles;
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  if (chunk >= a.chunks || yt * 16 >= m || zt * 16 >= nb) return;
   __shared__ f64x4 red[3][64];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int64_t chunk = blockIdx.x;
-  const int c0 = blockIdx.y * 16;
-  const int j0 = blockIdx.z * 16;
+  const int c0 = yt * 16;
+  const int j0 = zt * 16;
   const int i = lane & 15, q = lane >> 4;
   const bool cok = (c0 + i) < m;
   const bool bok = (j0 + i) < nb;
-  const TA* ap = A + (int64_t)(cok ? c0 + i : c0) * lda;
-  const TB* bp = B + (int64_t)(bok ? j0 + i : j0) * ldb;
+  const TA* ap = (const TA*)a.A + (int64_t)(cok ? c0 + i : c0) * a.lda;
+  const TB* bp = (const TB*)a.B + (int64_t)(bok ? j0 + i : j0) * a.ldb;
   const int64_t r0 = chunk * (int64_t)(256 * S) + (int64_t)wid * (64 * S);
   const int64_t r1 = (r0 + 64 * S < d) ? r0 + 64 * S : d;
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -67,13 +71,13 @@ __global__ __launch_bounds__(256) void tn_mfma_kernel(int64_t d, int m, int nb,
     const int64_t rb = r0 + 64 * s;
     if (rb >= r1) break;
     const int64_t rs = rb + 16 * q;
-    double a[16], b[16];
+    double av[16], bv[16];
     if (rb + 64 <= r1) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const double x = ld64(ap + rs + e), y = ld64(bp + rs + e);
-        a[e] = cok ? x : 0.0;
-        b[e] = bok ? y : 0.0;
+        av[e] = cok ? x : 0.0;
+        bv[e] = bok ? y : 0.0;
       }
     } else {
 #pragma unroll
@@ -81,12 +85,12 @@ __global__ __launch_bounds__(256) void tn_mfma_kernel(int64_t d, int m, int nb,
         const bool ok = rs + e < r1;
         const int64_t rr = ok ? rs + e : rb;
         const double x = ld64(ap + rr), y = ld64(bp + rr);
-        a[e] = (cok && ok) ? x : 0.0;
-        b[e] = (bok && ok) ? y : 0.0;
+        av[e] = (cok && ok) ? x : 0.0;
+        bv[e] = (bok && ok) ? y : 0.0;
       }
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], acc, 0, 0, 0);
+    for (int e = 0; e < 16; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[e], acc, 0, 0, 0);
   }
   if (wid > 0) red[wid - 1][lane] = acc;
   __syncthreads();
@@ -98,24 +102,25 @@ __global__ __launch_bounds__(256) void tn_mfma_kernel(int64_t d, int m, int nb,
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int ii = 4 * v + ib;
-      if (c0 + ii < m && j0 + jj < nb) part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] = acc[v];
+      if (c0 + ii < m && j0 + jj < nb)
+        a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] = acc[v];
     }
   }
 }
 
 // Sum of the chunk partials, fixed order: wave w adds chunks w, w+4, ... of
 // 64 outputs, then the 4 wave sums are added in order.
-__global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t chunks, int64_t m, int64_t nb,
-                                                              const double* __restrict__ part,
-                                                              double alpha, double beta,
-                                                              double* __restrict__ C, int64_t ldc,
-                                                              double zalpha, double* __restrict__ Z,
-                                                              int64_t ldz, const int* __restrict__ gate) {
-  if (gate != nullptr && *gate == 0) return;
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const ReduceArgs* __restrict__ arr,
+                                                              ReduceArgs one) {
+  const ReduceArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  const int64_t mn = a.m * a.nb;
+  if (blockIdx.x * (int64_t)64 >= mn) return;
   __shared__ double red[3][64];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int64_t mn = m * nb;
+  const int64_t chunks = a.chunks;
+  const double* __restrict__ part = a.part;
   const int64_t e = blockIdx.x * (int64_t)64 + lane;
   const int64_t ee = e < mn ? e : mn - 1;
   double s = 0.0;
@@ -135,29 +140,30 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(int64_t chunks, in
   s += red[0][lane];
   s += red[1][lane];
   s += red[2][lane];
-  const int64_t i = e / nb, j = e - i * nb;
-  if (C != nullptr) {
-    double* cp = C + i + j * ldc;
-    *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * s;
+  const int64_t i = e / a.nb, j = e - i * a.nb;
+  if (a.C != nullptr) {
+    double* cp = a.C + i + j * a.ldc;
+    *cp = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * s;
   }
-  if (Z != nullptr) Z[i * ldz + j] = zalpha * s;
+  if (a.Z != nullptr) a.Z[i * a.ldz + j] = a.zalpha * s;
 }
 
 template <typename TA, typename TV, typename TO, typename ACC, int R, int BATCH>
-__global__ __launch_bounds__(256) void nn_kernel(int64_t d, int m, int nb, const TA* __restrict__ A,
-                                                 int64_t lda, const double* __restrict__ Z,
-                                                 int64_t ldz, double alpha, const TV* __restrict__ V,
-                                                 int64_t ldv, TO* __restrict__ Out, int64_t ldo,
-                                                 int out_row, const int* __restrict__ gate) {
-  if (gate != nullptr && *gate == 0) return;
+__global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
+  const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const int j0 = blockIdx.y * NN_NB;
+  if (blockIdx.x * (int64_t)R >= d || j0 >= nb) return;
   constexpr int G = 256 / R;
   __shared__ ACC zs[NN_ZT * NN_NB];
   __shared__ ACC red[256 * (NN_NB + 1)];
   const int tid = threadIdx.x;
   const int rl = tid % R, g = tid / R;
   const int64_t r = blockIdx.x * (int64_t)R + rl;
-  const int j0 = blockIdx.y * NN_NB;
-  const TA* ar = A + (r < d ? r : d - 1);  // rows past d read row d-1, never stored
+  const int64_t lda = a.lda;
+  const TA* ar = (const TA*)a.A + (r < d ? r : d - 1);  // rows past d read row d-1, never stored
   ACC acc[NN_NB];
 #pragma unroll
   for (int j = 0; j < NN_NB; ++j) acc[j] = ACC(0);
@@ -166,46 +172,48 @@ __global__ __launch_bounds__(256) void nn_kernel(int64_t d, int m, int nb, const
     __syncthreads();
     for (int e = tid; e < tn * NN_NB; e += 256) {
       const int i = e / NN_NB, j = e - i * NN_NB;
-      zs[e] = (j0 + j < nb) ? (ACC)Z[(int64_t)(t0 + i) * ldz + j0 + j] : ACC(0);
+      zs[e] = (j0 + j < nb) ? (ACC)a.Z[(int64_t)(t0 + i) * a.ldz + j0 + j] : ACC(0);
     }
     __syncthreads();
     int i = g;
     for (; i + (BATCH - 1) * G < tn; i += BATCH * G) {
-      ACC a[BATCH];
+      ACC av[BATCH];
 #pragma unroll
-      for (int u = 0; u < BATCH; ++u) a[u] = to_acc<ACC>(ar[(int64_t)(t0 + i + u * G) * lda]);
+      for (int u = 0; u < BATCH; ++u) av[u] = to_acc<ACC>(ar[(int64_t)(t0 + i + u * G) * lda]);
 #pragma unroll
       for (int u = 0; u < BATCH; ++u) {
         const ACC* zr = zs + (i + u * G) * NN_NB;
 #pragma unroll
-        for (int j = 0; j < NN_NB; ++j) acc[j] += a[u] * zr[j];
+        for (int j = 0; j < NN_NB; ++j) acc[j] += av[u] * zr[j];
       }
     }
     for (; i < tn; i += G) {
-      const ACC a = to_acc<ACC>(ar[(int64_t)(t0 + i) * lda]);
+      const ACC av = to_acc<ACC>(ar[(int64_t)(t0 + i) * lda]);
       const ACC* zr = zs + i * NN_NB;
 #pragma unroll
-      for (int j = 0; j < NN_NB; ++j) acc[j] += a * zr[j];
+      for (int j = 0; j < NN_NB; ++j) acc[j] += av * zr[j];
     }
   }
 #pragma unroll
   for (int j = 0; j < NN_NB; ++j) red[tid * (NN_NB + 1) + j] = acc[j];
   __syncthreads();
+  const TV* V = (const TV*)a.V;
+  TO* Out = (TO*)a.Out;
   for (int e = tid; e < R * NN_NB; e += 256) {
     const int rr = e % R, j = e / R;
     const int64_t row = blockIdx.x * (int64_t)R + rr;
     if (row >= d || j0 + j >= nb) continue;
-    ACC s = ACC(0);
-    for (int u = 0; u < G; ++u) s += red[(u * R + rr) * (NN_NB + 1) + j];
-    double o = (double)s;
-    if (alpha != 0.0) o += alpha * to_f64<TV>(V[row + (int64_t)(j0 + j) * ldv]);
-    const int64_t oi = out_row ? row * ldo + (j0 + j) : row + (int64_t)(j0 + j) * ldo;
+    ACC sacc = ACC(0);
+    for (int u = 0; u < G; ++u) sacc += red[(u * R + rr) * (NN_NB + 1) + j];
+    double o = (double)sacc;
+    if (a.alpha != 0.0) o += a.alpha * to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]);
+    const int64_t oi = a.out_row ? row * a.ldo + (j0 + j) : row + (int64_t)(j0 + j) * a.ldo;
     Out[oi] = from_f64<TO>(o);
   }
 }
 
 // 64 S rows per wave, 4 waves per workgroup: S = 4 when that still gives
-// 1024 workgroups, else 2, else 1.
+// 1024 workgroups, else 2, else 1 (chosen from the largest entry).
 int tn_steps(int64_t d, int64_t m) {
   const int64_t tiles = (m + 15) / 16;
   for (int S : {4, 2}) {
@@ -216,40 +224,59 @@ int tn_steps(int64_t d, int64_t m) {
 }
 
 template <typename TA, typename TB>
-hipError_t tn_launch_t(int64_t d, int64_t m, int64_t nb, const void* A, int64_t lda,
-                       const void* B, int64_t ldb, double* part, int64_t chunks,
-                       const int* gate, hipStream_t s) {
-  const int S = tn_steps(d, m);
-  if ((d + 256 * S - 1) / (256 * S) != chunks) return hipErrorInvalidValue;
-  dim3 g((unsigned)chunks, (unsigned)((m + 15) / 16), (unsigned)((nb + 15) / 16));
+hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStream_t s) {
+  int64_t dmax = 0, mmax = 0, cmax = 0, ymax = 0, zmax = 0;
+  for (int p = 0; p < count; ++p) {
+    dmax = std::max(dmax, host[p].d);
+    mmax = std::max(mmax, host[p].m);
+  }
+  const int S = tn_steps(dmax, mmax);
+  for (int p = 0; p < count; ++p) {
+    const TnArgs& a = host[p];
+    if (a.d <= 0 || a.m <= 0 || a.nb <= 0) continue;
+    if (a.chunks != (a.d + 256 * S - 1) / (256 * S)) return hipErrorInvalidValue;
+    cmax = std::max(cmax, a.chunks);
+    ymax = std::max(ymax, (a.m + 15) / 16);
+    zmax = std::max(zmax, (a.nb + 15) / 16);
+  }
+  if (cmax == 0) return hipSuccess;
+  const TnArgs one = (count == 1) ? host[0] : TnArgs{};
+  const TnArgs* arr = (count == 1) ? nullptr : dev;
+  dim3 g((unsigned)cmax, (unsigned)(ymax * zmax), (unsigned)count);
   if (S == 4)
-    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 4>), g, dim3(256), 0, s, d, (int)m, (int)nb,
-                       (const TA*)A, lda, (const TB*)B, ldb, part, gate);
+    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 4>), g, dim3(256), 0, s, arr, one, (int)ymax);
   else if (S == 2)
-    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 2>), g, dim3(256), 0, s, d, (int)m, (int)nb,
-                       (const TA*)A, lda, (const TB*)B, ldb, part, gate);
+    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 2>), g, dim3(256), 0, s, arr, one, (int)ymax);
   else
-    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 1>), g, dim3(256), 0, s, d, (int)m, (int)nb,
-                       (const TA*)A, lda, (const TB*)B, ldb, part, gate);
+    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 1>), g, dim3(256), 0, s, arr, one, (int)ymax);
   return hipGetLastError();
 }
 
 // Rows per nn workgroup: 64 when that still gives 384 workgroups (long
-// loops, little Z traffic), else 32, else 16 (more workgroups).
+// loops, little Z traffic), else 32, else 16 (more workgroups); chosen from
+// the largest entry.
 template <typename TA, typename TV, typename TO, typename ACC>
-hipError_t nn_launch_t(int64_t d, int64_t m, int64_t nb, const void* A, int64_t lda,
-                       const double* Z, int64_t ldz, double alpha, const void* V, int64_t ldv,
-                       void* Out, int64_t ldo, bool out_row, const int* gate, hipStream_t s) {
-  const unsigned gy = (unsigned)((nb + NN_NB - 1) / NN_NB);
-  const int orow = out_row ? 1 : 0;
+hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStream_t s) {
+  int64_t dmax = 0, ymax = 0;
+  for (int p = 0; p < count; ++p) {
+    const NnArgs& a = host[p];
+    if (a.d <= 0 || a.nb <= 0) continue;
+    if (a.m < 0) return hipErrorInvalidValue;
+    // In-place Out == A is only safe when one workgroup column covers all nb.
+    if (a.Out == a.A && a.nb > NN_NB) return hipErrorInvalidValue;
+    dmax = std::max(dmax, a.d);
+    ymax = std::max(ymax, (a.nb + NN_NB - 1) / NN_NB);
+  }
+  if (dmax == 0) return hipSuccess;
+  const NnArgs one = (count == 1) ? host[0] : NnArgs{};
+  const NnArgs* arr = (count == 1) ? nullptr : dev;
 #define NN_GO(R_, B_)                                                                          \
   hipLaunchKernelGGL((nn_kernel<TA, TV, TO, ACC, R_, B_>),                                     \
-                     dim3((unsigned)((d + R_ - 1) / R_), gy), dim3(256), 0, s, d, (int)m,     \
-                     (int)nb, (const TA*)A, lda, Z, ldz, alpha, (const TV*)V, ldv, (TO*)Out,  \
-                     ldo, orow, gate)
-  if (d / 64 >= 384)
+                     dim3((unsigned)((dmax + R_ - 1) / R_), (unsigned)ymax, (unsigned)count), \
+                     dim3(256), 0, s, arr, one)
+  if (dmax / 64 >= 384)
     NN_GO(64, 8);
-  else if (d / 32 >= 384)
+  else if (dmax / 32 >= 384)
     NN_GO(32, 8);
   else
     NN_GO(16, 4);
@@ -259,56 +286,65 @@ hipError_t nn_launch_t(int64_t d, int64_t m, int64_t nb, const void* A, int64_t 
 
 }  // namespace
 
+int64_t tn_chunks_for(int64_t d, int64_t dmax, int64_t mmax) {
+  const int S = tn_steps(dmax, mmax);
+  return (d + 256 * S - 1) / (256 * S);
+}
+
 int64_t tn_chunks(int64_t d, int64_t m, int64_t nb) {
   (void)nb;
-  const int S = tn_steps(d, m);
-  return (d + 256 * S - 1) / (256 * S);
+  return tn_chunks_for(d, d, m);
+}
+
+hipError_t launch_tn_multi(int count, const TnArgs* host, const TnArgs* dev, DT adt, DT bdt,
+                           hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  using bf = __hip_bfloat16;
+  if (adt == DT::F64 && bdt == DT::F64) return tn_launch_t<double, double>(count, host, dev, s);
+  if (adt == DT::F32 && bdt == DT::F32) return tn_launch_t<float, float>(count, host, dev, s);
+  if (adt == DT::F32 && bdt == DT::F64) return tn_launch_t<float, double>(count, host, dev, s);
+  if (adt == DT::F64 && bdt == DT::F32) return tn_launch_t<double, float>(count, host, dev, s);
+  if (adt == DT::BF16 && bdt == DT::F32) return tn_launch_t<bf, float>(count, host, dev, s);
+  if (adt == DT::BF16 && bdt == DT::F64) return tn_launch_t<bf, double>(count, host, dev, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT adt,
                              int64_t lda, const void* B, DT bdt, int64_t ldb, double* part,
                              int64_t chunks, const int* gate, hipStream_t s) {
   if (d <= 0 || m <= 0 || nb <= 0) return hipSuccess;
-  using bf = __hip_bfloat16;
-  if (adt == DT::F64 && bdt == DT::F64)
-    return tn_launch_t<double, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
-  if (adt == DT::F32 && bdt == DT::F32)
-    return tn_launch_t<float, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
-  if (adt == DT::F32 && bdt == DT::F64)
-    return tn_launch_t<float, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
-  if (adt == DT::F64 && bdt == DT::F32)
-    return tn_launch_t<double, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
-  if (adt == DT::BF16 && bdt == DT::F32)
-    return tn_launch_t<bf, float>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
-  if (adt == DT::BF16 && bdt == DT::F64)
-    return tn_launch_t<bf, double>(d, m, nb, A, lda, B, ldb, part, chunks, gate, s);
-  return hipErrorInvalidValue;
+  TnArgs a{d, m, nb, lda, ldb, chunks, A, B, part, gate};
+  return launch_tn_multi(1, &a, nullptr, adt, bdt, s);
+}
+
+hipError_t launch_reduce_multi(int count, const ReduceArgs* host, const ReduceArgs* dev,
+                               hipStream_t s) {
+  int64_t xmax = 0;
+  for (int p = 0; p < count; ++p) xmax = std::max(xmax, (host[p].m * host[p].nb + 63) / 64);
+  if (xmax == 0) return hipSuccess;
+  const ReduceArgs one = (count == 1) ? host[0] : ReduceArgs{};
+  const ReduceArgs* arr = (count == 1) ? nullptr : dev;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)xmax, 1, (unsigned)count), dim3(256),
+                     0, s, arr, one);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const double* part,
                                   double alpha, double beta, double* C_col, int64_t ldc,
                                   double zalpha, double* Z_row, int64_t ldz, const int* gate,
                                   hipStream_t s) {
-  const int64_t mn = m * nb;
-  if (mn <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((mn + 63) / 64)), dim3(256), 0, s,
-                     chunks, m, nb, part, alpha, beta, C_col, ldc, zalpha, Z_row, ldz, gate);
-  return hipGetLastError();
+  if (m * nb <= 0) return hipSuccess;
+  ReduceArgs a{chunks, m, nb, ldc, ldz, part, alpha, beta, zalpha, C_col, Z_row, gate};
+  return launch_reduce_multi(1, &a, nullptr, s);
 }
 
-hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
-                     const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
-                     int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
-                     hipStream_t s, bool out_row) {
-  if (d <= 0 || nb <= 0) return hipSuccess;
-  if (m < 0) return hipErrorInvalidValue;
-  // In-place Out == A is only safe when one workgroup column covers all nb.
-  if (Out == A && nb > NN_NB) return hipErrorInvalidValue;
+hipError_t launch_nn_multi(int count, const NnArgs* host, const NnArgs* dev, DT adt, DT vdt,
+                           DT odt, hipStream_t s) {
+  if (count < 1) return hipSuccess;
   using bf = __hip_bfloat16;
-#define NN_CASE(a, v, o, TA, TV, TO, ACC)                                                     \
-  if (adt == DT::a && vdt == DT::v && odt == DT::o)                                           \
-    return nn_launch_t<TA, TV, TO, ACC>(d, m, nb, A, lda, Z, ldz, alpha, V, ldv, Out, ldo,    \
-                                        out_row, gate, s);
+#define NN_CASE(a, v, o, TA, TV, TO, ACC)                                    \
+  if (adt == DT::a && vdt == DT::v && odt == DT::o)                          \
+    return nn_launch_t<TA, TV, TO, ACC>(count, host, dev, s);
   NN_CASE(F64, F64, F64, double, double, double, double)
   NN_CASE(F32, F32, F32, float, float, float, float)
   NN_CASE(F32, F64, F64, float, double, double, double)
@@ -318,6 +354,15 @@ hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, in
   NN_CASE(BF16, F64, F64, bf, double, double, double)
 #undef NN_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
+                     const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
+                     int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
+                     hipStream_t s, bool out_row) {
+  if (d <= 0 || nb <= 0) return hipSuccess;
+  NnArgs a{d, m, nb, lda, ldz, ldv, ldo, A, Z, alpha, V, Out, out_row ? 1 : 0, gate};
+  return launch_nn_multi(1, &a, nullptr, adt, vdt, odt, s);
 }
 
 }  // namespace eda

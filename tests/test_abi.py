@@ -119,3 +119,36 @@ def test_no_cpu_fallback_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(eda, "library_path", lambda: str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         eda.load_library()
+
+
+def _problem(eda, d=100, n=10, k=3, t=2, tol=1e-8):
+    arr = (eda.Problem * 1)()
+    r = (ctypes.c_double * 4)()
+    arr[0] = eda.Problem(d, n, k, 0x1000, d, 0x2000, d, t, tol, r, r, 0x3000, d, r)
+    return arr
+
+
+@pytest.mark.parametrize("field,value", [
+    ("d", 1), ("k", 1), ("n", 2), ("t", 0), ("t", 200), ("tol", 0.0), ("ldw", 5), ("ldx", 5),
+])
+def test_solve_batched_rejects_bad_problems(lib, handle, field, value):
+    arr = _problem(eda)
+    setattr(arr[0], field, value)
+    st = lib.eda_solve_batched(handle, 1, arr, 0, None, None, None)
+    assert st == eda.EDA_ERR_ARG
+    assert lib.eda_last_error(handle).decode()
+
+
+def test_solve_batched_rejects_bad_calls(lib, handle):
+    arr = _problem(eda)
+    assert lib.eda_solve_batched(handle, 0, arr, 0, None, None, None) == eda.EDA_ERR_ARG
+    assert lib.eda_solve_batched(handle, 1, None, 0, None, None, None) == eda.EDA_ERR_ARG
+    assert lib.eda_solve_batched(handle, 1, arr, 9, None, None, None) == eda.EDA_ERR_ARG
+    o = eda.SolveOpts()
+    o.start_block = 0x1000
+    o.ld_start = 100
+    assert lib.eda_solve_batched(handle, 1, arr, 0, ctypes.byref(o), None, None) == eda.EDA_ERR_ARG
+    o = eda.SolveOpts()
+    o.max_basis = 40
+    assert lib.eda_solve_batched(handle, 1, arr, 0, ctypes.byref(o), None, None) == eda.EDA_ERR_ARG
+    assert lib.eda_solve_batched(None, 1, arr, 0, None, None, None) == eda.EDA_ERR_ARG

@@ -456,3 +456,101 @@ def test_mixed_c3_full_size(torch, eda):
         assert ang <= ang_tol
         assert np.abs(X.T @ X - np.eye(p.t)).max() <= 1e-13
         h.close()
+
+
+# ---------------------------------------------------------------------------
+# a9: many problems solved together
+# ---------------------------------------------------------------------------
+
+def _small_batch():
+    """Uneven small problems: C1, the ragged case and four more shapes."""
+    cases = []
+    p = datagen.config("C1")
+    cases.append(Case("C1", p.X, p.counts, p.t))
+    counts = [2, 3, 4, 1, 5]
+    cases.append(Case("ragged", datagen.make_samples(333, counts, 12, seed=21), counts, 4))
+    rng = np.random.default_rng(77)
+    for q in range(4):
+        d = int(rng.choice([300, 700, 1500]))
+        k = int(rng.integers(3, 12))
+        cnt = rng.integers(2, 7, size=k).tolist()
+        cases.append(Case(f"s{q}", datagen.make_samples(d, cnt, 24, seed=500 + q), cnt, k - 1))
+    return cases
+
+
+@pytest.mark.parametrize("storage,basis", [("f64", "f64"), ("f32", "f32")])
+def test_batched_small_against_oracle(torch, eda, storage, basis):
+    """Each problem of a batch meets the float64 bounds of a single solve."""
+    log(f"batched solve of 6 uneven problems, storage={storage} basis={basis}")
+    cases = _small_batch()
+    h = eda.Handle()
+    probs = []
+    for c in cases:
+        HW, HB = h.scatter_factors(dev(torch, c.X), c.counts.tolist())
+        probs.append((HW, HB, c.t, 1e-10))
+    res, st = h.solve_batched(probs, storage=storage, krylov_dtype=basis, seed=11)
+    assert st == 0, res
+    for c, r in zip(cases, res):
+        red = O.eda_reduced(c.H_W, c.H_B, c.t)
+        log(f"  {c.name}: d={c.d} t={c.t}")
+        check_solution(r, red, c.t, red.lam_all, 1e-10)
+    h.close()
+
+
+def test_batched_agrees_with_single_solves(torch, eda):
+    """Same start blocks (seed + index) and the same kernels: the batch and
+    the one-by-one solves agree to rounding (the chunking of the row sums
+    may differ with the largest problem of a launch)."""
+    log("batched vs single solves")
+    cases = _small_batch()[:4]
+    h = eda.Handle()
+    probs, singles = [], []
+    for i, c in enumerate(cases):
+        HW, HB = h.scatter_factors(dev(torch, c.X), c.counts.tolist())
+        probs.append((HW, HB, c.t, 1e-10))
+        hs = eda.Handle()
+        hs.prepare(HW, HB)
+        singles.append(hs.solve(c.t, 1e-10, seed=5 + i))
+        hs.close()
+    res, st = h.solve_batched(probs, seed=5)
+    assert st == 0
+    for c, r, s in zip(cases, res, singles):
+        lam_b, lam_s = np.array(r.ritz), np.array(s.ritz)
+        rel = np.max(np.abs(lam_b - lam_s) / lam_s)
+        ang = O.sin_angle(host(s.X), host(r.X))
+        log(f"  {c.name}: lam rel diff {rel:.1e} sin {ang:.1e} iters {r.info['iters']} vs {s.info['iters']}")
+        assert rel <= 1e-11 and ang <= 1e-8
+    h.close()
+
+
+def test_batched_c4_sample(torch, eda):
+    """Twelve problems of the 64-problem workload (d in {1024, 4096, 10304},
+    k in [10, 68], n_j in [2, 20], float32 storage, tol 1e-6) in one batch,
+    each against the oracle's exact reduction.  Bounds as at C3: the
+    per-pair floors u lam_1/lam_i decide for the small pairs."""
+    log("batched C4 sample (12 problems, float32 storage)")
+    ps = datagen.batched_configs(12)
+    h = eda.Handle()
+    probs, cases = [], []
+    for p in ps:
+        c = Case(p.name, p.X, p.counts, p.t)
+        cases.append(c)
+        HW, HB = h.scatter_factors(dev(torch, c.X), c.counts.tolist())
+        probs.append((HW, HB, c.t, p.tol))
+    res, st = h.solve_batched(probs, storage="f32", krylov_dtype="f32", seed=4000)
+    assert st == 0, [r.status for r in res]
+    for c, r in zip(cases, res):
+        red = O.eda_reduced(c.H_W, c.H_B, c.t)
+        fl = O.accuracy_floor(red.lam_all, c.t)
+        lam = np.array(r.ritz)
+        relerr = np.abs(lam - red.lam) / red.lam
+        lam_tol = np.maximum(1e-5, 50 * U * red.lam[0] / red.lam)
+        X = host(r.X)
+        ang = O.sin_angle(red.X, X)
+        log(f"  {c.name}: d={c.d} N={c.H_W.shape[1] + c.H_B.shape[1]} t={c.t} "
+            f"iters={r.info['iters']} passes={r.info['refine_passes']} lam_err={relerr.max():.1e} "
+            f"sin={ang:.1e}")
+        assert np.all(relerr <= lam_tol)
+        assert ang <= max(1e-5, 50 * fl["span"])
+        assert np.abs(X.T @ X - np.eye(c.t)).max() <= 1e-13
+    h.close()
