@@ -21,6 +21,18 @@ timed solves.  Peak: MI355X HBM3E, 8 TB/s.
 
 `cpu_baseline` times the FP64 CPU oracle (exact (n+k)-dimensional reduction
 of the pencil, NumPy/SciPy on the host's cores) on the same workload.
+
+`mixed_vs_f64` (second half of the metric): solves/s of the d = 32256,
+k = 38, n = 1216, t = 37 workload at tol 1e-6, float64 end to end against
+bfloat16 factors + float32 basis + float64 refinement (prepare + solve each).
+
+`batched`: 64 independent problems of uneven shape (d in {1024, 4096,
+10304}, k in [10, 68], n_j in [2, 20], float32 factors, tol 1e-6) solved by
+one eda_solve_batched call, problems/s, against the same problems solved one
+after another.
+
+`--profile-op K`: only K exponential products (b = 8) on the headline
+workload plus one 256 MiB copy, for hardware-counter runs.
 """
 from __future__ import annotations
 
@@ -60,12 +72,125 @@ def cpu_baseline(p, budget_s: float = 15.0) -> dict:
                       f"dense pencil eig), {el:.1f} s"}
 
 
+def counter_traffic():
+    """HBM bytes per product from the committed counter summary, or None when
+    the streaming kernels have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "exp_op_c2_counters.md")
+    src = os.path.join(ROOT, "paper_1512_06500_amd", "csrc", "k_tsmm.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_op: ", "kernel_source_sha256: ")))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    return float(fields["traffic_bytes_per_op"])
+
+
+def profile_op(torch, eda, h, Xd, counts, reps):
+    """K products e^{-s} M V (b = 8) and one 256 MiB device copy."""
+    H_W, H_B = h.scatter_factors(Xd, counts)
+    h.prepare(H_W, H_B)
+    V = torch.randn(8, Xd.shape[0], dtype=torch.float64, device="cuda").t()
+    out = torch.empty_like(V.t()).t()
+    for _ in range(reps):
+        h.opmv("M", V, out=out)
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_op": reps, "copy_bytes": 2 * src.numel() * 8}), flush=True)
+
+
+def _upload(torch, X):
+    return torch.from_numpy(np.ascontiguousarray(X.T)).cuda().t()
+
+
+def mixed_vs_f64(torch, eda, reps: int = 3) -> dict:
+    import datagen
+    from tests.golden.make_golden import read as read_golden
+    p = datagen.config("C3")
+    g = read_golden("C3")
+    Xd = _upload(torch, p.X)
+    h = eda.Handle()
+    H_W, H_B = h.scatter_factors(Xd, p.counts.tolist())
+    out = {"workload": f"d={p.d}, k={p.k} x n_j={p.n // p.k} (n={p.n}), t={p.t}, "
+                       f"block 8, tol {p.tol:g}"}
+    for tag, storage, basis in (("f64", "f64", "f64"), ("mixed", "bf16", "f32")):
+        def one():
+            h.prepare(H_W, H_B, storage=storage)
+            return h.solve(p.t, p.tol, block=8, seed=p.seed, krylov_dtype=basis)
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = one()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        lam_err = np.abs(np.array(r.ritz) - g["lam"]) / g["lam"]
+        out[tag] = {"solves_per_s": 1.0 / el, "ms": 1e3 * el, "status": r.status,
+                    "storage": storage, "basis": basis, "iters": r.info["iters"],
+                    "refine_passes": r.info["refine_passes"],
+                    "krylov_ms": r.info["t_krylov_ms"], "refine_ms": r.info["t_refine_ms"],
+                    "resid_max": max(r.resid),
+                    "lam_rel_err_top": float(lam_err[0]),
+                    "lam_rel_err_max_over_floor": float(np.max(lam_err / np.maximum(
+                        1e-6, g["pair_floor"])))}
+    out["ratio_mixed_over_f64"] = out["mixed"]["solves_per_s"] / out["f64"]["solves_per_s"]
+    h.close()
+    return out
+
+
+def batched(torch, eda, count: int = 64, reps: int = 2) -> dict:
+    import datagen
+    ps = datagen.batched_configs(count)
+    h = eda.Handle()
+    probs = []
+    for p in ps:
+        HW, HB = h.scatter_factors(_upload(torch, p.X), p.counts.tolist())
+        probs.append((HW, HB, p.t, p.tol))
+    out = {"workload": f"{count} problems, d in {{1024, 4096, 10304}}, k in [10, 68], "
+                       f"n_j in [2, 20], t = k-1, tol 1e-6",
+           "P_bytes_f32_total": int(sum(p.d * (p.n + p.k) * 4 for p in ps))}
+    for tag, storage, basis in (("f32", "f32", "f32"), ("f64", "f64", "f64")):
+        h.solve_batched(probs, storage=storage, krylov_dtype=basis, seed=4000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res, st = h.solve_batched(probs, storage=storage, krylov_dtype=basis, seed=4000)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        out[tag] = {"problems_per_s": count / el, "ms_per_batch": 1e3 * el, "status": int(st),
+                    "ok": int(sum(r.status == 0 for r in res)),
+                    "max_iters": int(max(r.info["iters"] for r in res)),
+                    "max_refine_passes": int(max(r.info["refine_passes"] for r in res))}
+    # the same problems one after another (float32 factors, float32 basis)
+    hs = eda.Handle()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (HW, HB, t, tol) in enumerate(probs):
+        hs.prepare(HW, HB, storage="f32")
+        hs.solve(t, tol, block=8, seed=4000 + i, krylov_dtype="f32")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["one_by_one_f32"] = {"problems_per_s": count / el, "ms": 1e3 * el}
+    out["speedup_batched_over_one_by_one"] = out["f32"]["problems_per_s"] / (count / el)
+    hs.close()
+    h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mixed-precision and batched measurements")
+    ap.add_argument("--profile-op", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -82,6 +207,10 @@ def main():
     Xd = torch.from_numpy(np.ascontiguousarray(p.X.T)).cuda().t()
     counts = p.counts.tolist()
     h = eda.Handle()
+
+    if args.profile_op > 0:
+        profile_op(torch, eda, h, Xd, counts, args.profile_op)
+        return
 
     def step():
         H_W, H_B = h.scatter_factors(Xd, counts)
@@ -128,7 +257,8 @@ def main():
                    "d": p.d, "n": p.n, "k": p.k, "t": p.t, "block": b, "tol": tol,
                    "storage": "f64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": counter_traffic(),
                      "kernel": "exp-op e^{-s} M V (b=8): tn_partial + reduce + core gemm + nn",
                      "bytes_per_launch": op_bytes, "avg_launch_us": avg_op_s * 1e6,
                      "launches": op_calls},
@@ -140,9 +270,12 @@ def main():
         "solve": {"iters": res.info["iters"], "restarts": res.info["restarts"],
                   "resid_max": max(res.resid), "lam_max_rel_err_vs_stored_oracle": lam_err},
     }
+    h.close()
+    if not args.no_extra:
+        out["mixed_vs_f64"] = mixed_vs_f64(torch, eda)
+        out["batched"] = batched(torch, eda)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
-    h.close()
     print(json.dumps(out), flush=True)
 
 

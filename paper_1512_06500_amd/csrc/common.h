@@ -49,7 +49,7 @@ template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// Host-side launchers (implemented in the .hip files, called by eda_host.cpp).
+// Host-side launchers (implemented in the .hip files, called by the host sources).
 // All take the stream last and return hipError_t of the launch.
 // Shapes are validated by the caller; each launcher documents what it needs.
 // ---------------------------------------------------------------------------
