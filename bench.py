@@ -13,11 +13,12 @@ HBM: scatter factors -> factor ingest + Gram + small eigensolves + cores ->
 block Lanczos with Rayleigh-Ritz -> back-transform + orthonormalisation.
 `value` is solves per second over the timed steps.
 
-`roofline` covers the exp-op, the block product e^{-s} M V with two
-streaming passes over P = [H_W H_B] (d x 240 float64): its algorithmic bytes
-2 d N 8 + 3 d b 8 per product divided by its average duration, measured
-with HIP events on the library's stream around every product inside the
-timed solves.  Peak: MI355X HBM3E, 8 TB/s.
+`roofline` covers the exp-op, the block product e^{-s} M V (b = 8) with two
+streaming passes over P = [H_W H_B] (d x 240 float64): its algorithmic
+bytes 2 d N 8 + 3 d b 8 per product divided by its average duration,
+measured with HIP events on the library's stream around every product
+inside the timed solves (four launches: P^T V on the matrix cores, the
+chunk sum, the core product, alpha V + P Z).  Peak: MI355X HBM3E, 8 TB/s.
 
 `cpu_baseline` times the FP64 CPU oracle (exact (n+k)-dimensional reduction
 of the pencil, NumPy/SciPy on the host's cores) on the same workload.
@@ -259,7 +260,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": counter_traffic(),
-                     "kernel": "exp-op e^{-s} M V (b=8): tn_partial + reduce + core gemm + nn",
+                     "kernel": "exp-op e^{-s} M V (b=8): tn_mfma + reduce + core nn + nn",
                      "bytes_per_launch": op_bytes, "avg_launch_us": avg_op_s * 1e6,
                      "launches": op_calls},
         "breakdown_ms": {

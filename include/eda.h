@@ -88,7 +88,8 @@ typedef struct {
   uint64_t seed;            /* start-block seed when start_block is NULL             */
   const void* start_block;  /* device, d x b float64 start block, or NULL            */
   int64_t ld_start;         /* leading dimension of start_block                      */
-  int32_t check_every;      /* block steps between Rayleigh-Ritz checks (default 2)  */
+  int32_t check_every;      /* block steps between Rayleigh-Ritz checks; 0 (default):
+                               scheduled from the observed convergence rate        */
   int32_t max_refine;       /* float64 refinement passes after the Krylov phase:
                                0 = default (16 after a phase with a narrower operator
                                or basis, 2 after a float64 one); < 0 = none, and the

@@ -322,6 +322,12 @@ void eda_destroy(eda_handle h) {
     for (hipEvent_t e : h->prep_ev)
       if (e != nullptr) (void)hipEventDestroy(e);
     if (h->pin != nullptr) (void)hipHostFree(h->pin);
+    if (h->rr_pin != nullptr) (void)hipHostFree(h->rr_pin);
+    if (h->ev_main != nullptr) (void)hipEventDestroy(h->ev_main);
+    if (h->ev_rr != nullptr) (void)hipEventDestroy(h->ev_rr);
+    if (h->aux != nullptr) (void)hipStreamDestroy(h->aux);
+    release_graphs(h);
+    if (h->cap != nullptr) (void)hipStreamDestroy(h->cap);
     destroy_batch_state(h);
   }
   delete h;
@@ -360,6 +366,15 @@ eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k, co
 
 namespace eda {
 
+void release_graphs(eda_handle h) {
+  for (auto& g : h->graphs) {
+    if (g.op != nullptr) (void)hipGraphExecDestroy(g.op);
+    if (g.rest != nullptr) (void)hipGraphExecDestroy(g.rest);
+  }
+  h->graphs.clear();
+  h->graph_sig = 0;
+}
+
 eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
                          int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
   if (h == nullptr) return EDA_ERR_ARG;
@@ -373,6 +388,7 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
   STCHK(check_dev_ptr(h, H_W, "H_W"));
   STCHK(check_dev_ptr(h, H_B, "H_B"));
   h->prepared = false;
+  ++h->prep_gen;
   for (auto& c : h->cores) release(c.buf);
   h->cores.clear();
 

@@ -83,25 +83,24 @@ eda_status cgs_pass(eda_handle h, int64_t d, int64_t m, const void* Q, DT qdt, i
 
 // Block step: from the basis Q[:, 0:m+b] (current block Q[:, m:m+b]) build
 // Q[:, m+b:m+2b] and column block m of H.
-eda_status lanczos_step(Solver& S, int64_t m) {
+// W = e^{-s} M V_j in the Krylov-phase types.
+eda_status lanczos_op(Solver& S, int64_t m) {
+  eda_handle h = S.h;
+  return expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt, S.ldq,
+               h->Wb.p, S.qdt, S.ldq);
+}
+
+// The rest of the block step: orthonormalise W into the next block and
+// record its coefficients in H.
+eda_status lanczos_orth(Solver& S, int64_t m, bool repair) {
   eda_handle h = S.h;
   const int64_t d = S.d, b = S.b, ldq = S.ldq, ldh = S.ldh;
   const DT qdt = S.qdt;
   double* H = S.H();
   void* W = h->Wb.p;
-  int* flags = h->flags.i();
-  // W = e^{-s} M V_j in the Krylov-phase types, timed with a pair of events
-  if (h->op_used + 2 > h->op_ev.size()) {
-    for (int q = 0; q < 64; ++q) {
-      hipEvent_t e;
-      HIPCHK(hipEventCreate(&e));
-      h->op_ev.push_back(e);
-    }
-  }
-  HIPCHK(hipEventRecord(h->op_ev[h->op_used], h->stream));
-  STCHK(expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, b, S.Qc(m), qdt, ldq, W, qdt, ldq));
-  HIPCHK(hipEventRecord(h->op_ev[h->op_used + 1], h->stream));
-  h->op_used += 2;
+  // without the repair pass, a raised flag goes to the sticky slot 2 that
+  // the host reads at every check
+  int* flags = repair ? h->flags.i() : h->flags.i() + 2;
   // CGS2 against Q[:, 0:m+b]
   double* Hcol = H + m * ldh;
   STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, W, ldq, b, Hcol, ldh, 0.0, nullptr));
@@ -126,6 +125,7 @@ eda_status lanczos_step(Solver& S, int64_t m) {
   }
   STCHK(cholqr_pass(h, d, b, Qn, qdt, ldq, Qn, ldq, h->R1.d(), H + (m + b) + m * ldh, ldh,
                     nullptr, 0, 0, nullptr, flags));
+  if (!repair) return EDA_OK;
   // repair (only runs when the flag was raised): re-orthogonalise the new block
   STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, Qn, ldq, b, nullptr, 0, 0.0, flags));
   STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, Qn, ldq, b, nullptr, 0, 0.0, flags));
@@ -134,6 +134,72 @@ eda_status lanczos_step(Solver& S, int64_t m) {
   STCHK(cholqr_pass(h, d, b, Qn, qdt, ldq, Qn, ldq, nullptr, nullptr, 0, nullptr, 0, 0, flags,
                     nullptr));
   HIPCHK(launch_flag_fold(flags, h->stream));
+  return EDA_OK;
+}
+
+// Captures one call of f (launches on h->stream) into an executable graph,
+// recorded on the handle's capture stream.
+template <class F>
+eda_status capture(eda_handle h, F f, hipGraphExec_t* exec) {
+  if (h->cap == nullptr) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  hipStream_t keep = h->stream;
+  h->stream = h->cap;
+  hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    h->stream = keep;
+    return fail(h, EDA_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  const eda_status st = f();
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(h->cap, &g);
+  h->stream = keep;
+  if (st != EDA_OK) {
+    if (g != nullptr) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(h, EDA_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(h, EDA_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+  return EDA_OK;
+}
+
+// Block step m.  With graphs, the product and the orthonormalisation of a
+// given (m, basis buffer) are captured once per solver configuration and
+// replayed; the product stays bracketed by the timing events.
+eda_status lanczos_step(Solver& S, int64_t m, bool graphs, bool repair) {
+  eda_handle h = S.h;
+  if (h->op_used + 2 > h->op_ev.size()) {
+    for (int q = 0; q < 64; ++q) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      h->op_ev.push_back(e);
+    }
+  }
+  hipGraphExec_t gop = nullptr, grest = nullptr;
+  if (graphs) {
+    for (const auto& g : h->graphs)
+      if (g.m == m && g.cur == S.cur && g.repair == repair) {
+        gop = g.op;
+        grest = g.rest;
+      }
+    if (gop == nullptr) {
+      STCHK(capture(h, [&]() { return lanczos_op(S, m); }, &gop));
+      STCHK(capture(h, [&]() { return lanczos_orth(S, m, repair); }, &grest));
+      h->graphs.push_back(StepGraph{m, S.cur, repair, gop, grest});
+    }
+  }
+  HIPCHK(hipEventRecord(h->op_ev[h->op_used], h->stream));
+  if (graphs)
+    HIPCHK(hipGraphLaunch(gop, h->stream));
+  else
+    STCHK(lanczos_op(S, m));
+  HIPCHK(hipEventRecord(h->op_ev[h->op_used + 1], h->stream));
+  h->op_used += 2;
+  if (graphs)
+    HIPCHK(hipGraphLaunch(grest, h->stream));
+  else
+    STCHK(lanczos_orth(S, m, repair));
   return EDA_OK;
 }
 
@@ -148,7 +214,7 @@ void log_pairs(const char* tag, int64_t m, int64_t cnt, const double* theta, con
 // Rayleigh-Ritz on Q[:, 0:m]: eigenpairs of sym(H[0:m,0:m]); returns the top
 // `cnt` Ritz values (descending) and residual estimates on the host.
 eda_status rayleigh_ritz(Solver& S, int64_t m, int64_t nvec, int64_t cnt, double* theta,
-                         double* est) {
+                         double* est, int* flag0 = nullptr) {
   eda_handle h = S.h;
   const int64_t ldh = S.ldh, mm = S.mmax;
   HIPCHK(launch_symmetrize(m, S.H(), ldh, h->T.d(), mm, h->stream));
@@ -159,8 +225,45 @@ eda_status rayleigh_ritz(Solver& S, int64_t m, int64_t nvec, int64_t cnt, double
                                h->dres.d(), h->stream));
   HIPCHK(hipMemcpyAsync(theta, h->dtheta.d(), cnt * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(est, h->dres.d(), cnt * 8, hipMemcpyDeviceToHost, h->stream));
+  int f0 = 0;
+  HIPCHK(hipMemcpyAsync(&f0, h->flags.i() + 2, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  if (flag0 != nullptr) *flag0 = f0;
   if (std::getenv("EDA_LOG") != nullptr) log_pairs("rr", m, cnt, theta, est);
+  return EDA_OK;
+}
+
+// The same Rayleigh-Ritz, launched on the second stream after the work
+// enqueued so far on the main stream; its Ritz values and estimates land in
+// pinned memory and are read by rr_collect.  The block steps enqueued
+// meanwhile on the main stream write only columns >= m of H and of the
+// basis, which this reads nowhere.
+eda_status rr_launch_async(Solver& S, int64_t m, int64_t nvec, int64_t cnt) {
+  eda_handle h = S.h;
+  const int64_t ldh = S.ldh, mm = S.mmax;
+  hipStream_t a = h->aux;
+  HIPCHK(hipEventRecord(h->ev_main, h->stream));
+  HIPCHK(hipStreamWaitEvent(a, h->ev_main, 0));
+  HIPCHK(launch_symmetrize(m, S.H(), ldh, h->T.d(), mm, a));
+  HIPCHK(launch_syev(1, m, nullptr, h->T.d(), mm, 0, h->wT.d(), 0, h->S.d(), mm, 0, nvec,
+                     h->syev_work.d(), a));
+  const double* Bm = S.H() + m + (m - S.b) * ldh;
+  HIPCHK(launch_ritz_estimates(m, S.b, cnt, h->wT.d(), h->S.d(), mm, Bm, ldh, h->dtheta.d(),
+                               h->dres.d(), a));
+  HIPCHK(hipMemcpyAsync(h->rr_pin, h->dtheta.d(), cnt * 8, hipMemcpyDeviceToHost, a));
+  HIPCHK(hipMemcpyAsync(h->rr_pin + cnt, h->dres.d(), cnt * 8, hipMemcpyDeviceToHost, a));
+  HIPCHK(hipMemcpyAsync(h->rr_pin + 2 * cnt, h->flags.i() + 2, sizeof(int), hipMemcpyDeviceToHost, a));
+  HIPCHK(hipEventRecord(h->ev_rr, a));
+  return EDA_OK;
+}
+
+eda_status rr_collect(Solver& S, int64_t m, int64_t cnt, double* theta, double* est, int* flag0) {
+  eda_handle h = S.h;
+  HIPCHK(hipEventSynchronize(h->ev_rr));
+  std::memcpy(theta, h->rr_pin, cnt * 8);
+  std::memcpy(est, h->rr_pin + cnt, cnt * 8);
+  std::memcpy(flag0, h->rr_pin + 2 * cnt, sizeof(int));
+  if (std::getenv("EDA_LOG") != nullptr) log_pairs("rr-async", m, cnt, theta, est);
   return EDA_OK;
 }
 
@@ -222,7 +325,9 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     return fail(h, EDA_ERR_ARG, "max_basis=%lld must satisfy t+2b <= max_basis <= min(d, 2048-b)",
                 (long long)mmax);
   const int64_t max_iter = o.max_iter > 0 ? o.max_iter : 4000;
-  const int64_t check_every = o.check_every > 0 ? o.check_every : 2;
+  // check_every > 0: a Rayleigh-Ritz check every that many block steps;
+  // 0: checks scheduled from the observed convergence rate (below)
+  const int64_t check_every = o.check_every > 0 ? o.check_every : 0;
   if (o.start_block != nullptr && o.ld_start < d)
     return fail(h, EDA_ERR_ARG, "ld_start must be >= d");
   STCHK(need_device(h));
@@ -290,6 +395,32 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     STCHK(ensure(h, h->R1, (size_t)rb * rb * 8));
   }
 
+  // EDA_GRAPHS=1 replays the block steps from captured graphs (valid while
+  // every buffer, size and scalar they bake in is unchanged).  Measured
+  // slower than direct launches on this hardware, so off by default.
+  const char* genv = std::getenv("EDA_GRAPHS");
+  const bool use_graphs = genv != nullptr && std::strcmp(genv, "1") == 0;
+  {
+    const uint64_t parts[] = {
+        h->prep_gen, (uint64_t)d, (uint64_t)h->N, (uint64_t)b, (uint64_t)qdt, (uint64_t)ldq,
+        (uint64_t)ldh, (uint64_t)mmax, (uint64_t)h->storage, (uint64_t)(uintptr_t)h->Q[0].p,
+        (uint64_t)(uintptr_t)h->Q[1].p, (uint64_t)(uintptr_t)h->H[0].p,
+        (uint64_t)(uintptr_t)h->H[1].p, (uint64_t)(uintptr_t)h->Wb.p,
+        (uint64_t)(uintptr_t)h->part.p, (uint64_t)(uintptr_t)h->Ysm.p,
+        (uint64_t)(uintptr_t)h->Zsm.p, (uint64_t)(uintptr_t)h->hz.p,
+        (uint64_t)(uintptr_t)h->Gs.p, (uint64_t)(uintptr_t)h->Rinv.p,
+        (uint64_t)(uintptr_t)h->R1.p, (uint64_t)(uintptr_t)h->mask.p,
+        (uint64_t)(uintptr_t)h->flags.p, (uint64_t)(uintptr_t)h->CM.p,
+        (uint64_t)(uintptr_t)h->P.p};
+    uint64_t sig = 1469598103934665603ull;  // FNV-1a over the words
+    for (uint64_t w : parts)
+      for (int q = 0; q < 8; ++q) sig = (sig ^ ((w >> (8 * q)) & 0xff)) * 1099511628211ull;
+    if (sig != h->graph_sig) {
+      release_graphs(h);
+      h->graph_sig = sig;
+    }
+  }
+
   hipEvent_t e0, e1, e2;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -297,29 +428,6 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   HIPCHK(hipEventRecord(e0, h->stream));
   hipStream_t s = h->stream;
   h->op_used = 0;
-  HIPCHK(launch_fill_i32(16, 0, h->flags.i(), s));
-  HIPCHK(launch_fill(ldh * ldh, 0.0, h->H[0].d(), s));
-  HIPCHK(launch_fill(ldh * ldh, 0.0, h->H[1].d(), s));
-  S.cur = 0;
-
-  // start block -> Q[:, 0:b] (drawn in float64, then cast to the basis type)
-  void* Wst = h->Wb.p;
-  double* Wst64 = h->Yb.d();
-  if (o.start_block != nullptr)
-    HIPCHK(launch_copy2d(d, b, o.start_block, DT::F64, o.ld_start, Wst, qdt, ldq, s));
-  else {
-    HIPCHK(launch_randn(d, b, o.seed, Wst64, ldq, s));
-    HIPCHK(launch_copy2d(d, b, Wst64, DT::F64, ldq, Wst, qdt, ldq, s));
-  }
-  if (qdt == DT::F64)
-    HIPCHK(launch_fill(ldq * (mmax + b), 0.0, (double*)S.Q(), s));
-  else  // float32 zero has the bit pattern of int32 zero
-    HIPCHK(launch_fill_i32(ldq * (mmax + b), 0, (int*)S.Q(), s));
-  STCHK(cholqr_pass(h, d, b, Wst, qdt, ldq, S.Q(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
-                    nullptr, nullptr));
-  STCHK(cholqr_pass(h, d, b, S.Q(), qdt, ldq, S.Q(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
-                    nullptr, nullptr));
-
   const int64_t nvec = std::min<int64_t>(S.kk, mmax);
   std::vector<double> theta(S.kk + 8), est(S.kk + 8);
   int64_t m = 0;
@@ -331,30 +439,157 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   int64_t ops = 0;
   const double opbytes = 2.0 * d * h->N * dsize(h->storage) + 3.0 * d * b * qs;
   int64_t m_rr = 0;
+  auto finite_pairs = [&](int64_t cnt) {
+    for (int64_t i = 0; i < cnt; ++i)
+      if (!std::isfinite(theta[i]) || !std::isfinite(est[i])) return false;
+    return true;
+  };
+  // largest ratio residual / tolerance over the wanted pairs (<= 1: done)
+  auto worst_ratio = [&]() {
+    double w = 0.0;
+    const double th1 = theta[0];
+    for (int64_t i = 0; i < t; ++i) {
+      const double thi = theta[i];
+      if (!(thi > 0.0)) return (double)INFINITY;
+      const double tol_i = std::max(tol, 10.0 * u_lo * th1 / thi);
+      const double r = (o.resmode == EDA_RES_REL_THETA) ? est[i] / thi : est[i] / th1;
+      if (!(r <= INFINITY)) return (double)INFINITY;
+      w = std::max(w, r / tol_i);
+    }
+    return w;
+  };
+  auto phase_converged = [&]() { return worst_ratio() <= 1.0; };
+  // Check schedule without a fixed interval: after two checks, the ratio's
+  // decrease per block step predicts how many steps remain; the next check
+  // comes after that many (at least 1, at most 4), else after 2.
+  int64_t next_check = 0, prev_iter = -1;
+  double prev_ratio = -1.0;
+  auto schedule = [&](int64_t at_iter) {
+    const double w = worst_ratio();
+    int64_t gap = 2;
+    if (prev_ratio > 0.0 && w < prev_ratio && at_iter > prev_iter && std::isfinite(w)) {
+      const double rho = std::pow(w / prev_ratio, 1.0 / (double)(at_iter - prev_iter));
+      if (rho > 0.0 && rho < 1.0) {
+        const double k = std::ceil(std::log(w) / -std::log(rho));
+        gap = (int64_t)std::max(1.0, std::min(4.0, k));
+      }
+    }
+    prev_ratio = w;
+    prev_iter = at_iter;
+    next_check = at_iter + gap;
+  };
+  auto check_due = [&](bool can_check) {
+    if (!can_check) return false;
+    if (check_every > 0) return iters % check_every == 0;
+    return iters >= next_check;
+  };
+  // Checks that need no restart run on the second stream, overlapping the
+  // next block steps; the verdict is read when the next check is due (or
+  // earlier, once ready).  A convergence found that way discards the steps
+  // taken meanwhile.  EDA_SYNC_CHECKS=1 keeps every check synchronous.
+  const bool async_checks = std::getenv("EDA_SYNC_CHECKS") == nullptr;
+  if (async_checks) {
+    if (h->aux == nullptr) HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    if (h->ev_main == nullptr) HIPCHK(hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming));
+    if (h->ev_rr == nullptr) HIPCHK(hipEventCreateWithFlags(&h->ev_rr, hipEventDisableTiming));
+    const size_t need = (size_t)2 * (S.kk + 8) * 8;
+    if (h->rr_pin_cap < need) {
+      if (h->rr_pin != nullptr) (void)hipHostFree(h->rr_pin);
+      h->rr_pin = nullptr;
+      h->rr_pin_cap = 0;
+      if (hipHostMalloc((void**)&h->rr_pin, need, hipHostMallocDefault) != hipSuccess)
+        return fail(h, EDA_ERR_NOMEM, "pinned readback allocation failed");
+      h->rr_pin_cap = need;
+    }
+  }
+  bool pending = false;
+  int64_t pend_m = 0, pend_iter = 0;
 
   // ---- Krylov phase -------------------------------------------------------
+  // The repair pass (second re-orthogonalisation of a new block) is needed
+  // only when a block loses rank or most of its norm in the projection, which
+  // happens as the Krylov space nears its dimension bound rank(P) + b <=
+  // n - 1 + b.  Away from it the repair launches are left out; a flag raised
+  // there anyway lands in a sticky slot, is seen at the next check, and the
+  // Krylov phase is started again with the repair pass in every step.
+  const int64_t sat = h->n - 1 + b;
+  bool safe = std::getenv("EDA_ALWAYS_REPAIR") != nullptr;
+  for (int attempt = 0;; ++attempt) {
+  if (attempt > 0) {
+    m = 0;
+    iters = 0;
+    restarts = 0;
+    m_rr = 0;
+    kconv = false;
+    h->op_used = 0;
+    next_check = 0;
+    prev_iter = -1;
+    prev_ratio = -1.0;
+  }
+    HIPCHK(launch_fill_i32(16, 0, h->flags.i(), s));
+    HIPCHK(launch_fill(ldh * ldh, 0.0, h->H[0].d(), s));
+    HIPCHK(launch_fill(ldh * ldh, 0.0, h->H[1].d(), s));
+    S.cur = 0;
+
+    // start block -> Q[:, 0:b] (drawn in float64, then cast to the basis type)
+    void* Wst = h->Wb.p;
+    double* Wst64 = h->Yb.d();
+    if (o.start_block != nullptr)
+      HIPCHK(launch_copy2d(d, b, o.start_block, DT::F64, o.ld_start, Wst, qdt, ldq, s));
+    else {
+      HIPCHK(launch_randn(d, b, o.seed, Wst64, ldq, s));
+      HIPCHK(launch_copy2d(d, b, Wst64, DT::F64, ldq, Wst, qdt, ldq, s));
+    }
+    if (qdt == DT::F64)
+      HIPCHK(launch_fill(ldq * (mmax + b), 0.0, (double*)S.Q(), s));
+    else  // float32 zero has the bit pattern of int32 zero
+      HIPCHK(launch_fill_i32(ldq * (mmax + b), 0, (int*)S.Q(), s));
+    STCHK(cholqr_pass(h, d, b, Wst, qdt, ldq, S.Q(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                      nullptr, nullptr));
+    STCHK(cholqr_pass(h, d, b, S.Q(), qdt, ldq, S.Q(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+                      nullptr, nullptr));
+  bool redo = false;
   while (true) {
-    STCHK(lanczos_step(S, m));
+    const bool repair = safe || (m + 3 * b >= sat);
+    STCHK(lanczos_step(S, m, use_graphs, repair));
     m += b;
     ++iters;
     ops += b;
     bytes += opbytes;
     const bool need_restart = (m + b > mmax);
     const bool can_check = (m >= t + b) || need_restart;
-    if (can_check && (iters % check_every == 0 || need_restart || iters >= max_iter)) {
-      const int64_t cnt = need_restart ? S.kk : t;
-      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), cnt, theta.data(), est.data()));
-      m_rr = m;
-      bool ok = true;
-      const double th1 = theta[0];
-      for (int64_t i = 0; i < t; ++i) {
-        const double thi = theta[i];
-        if (!(thi > 0.0)) { ok = false; continue; }
-        const double tol_i = std::max(tol, 10.0 * u_lo * th1 / thi);
-        const double r = (o.resmode == EDA_RES_REL_THETA) ? est[i] / thi : est[i] / th1;
-        if (!(r <= tol_i)) ok = false;
+    const bool due = check_due(can_check) || need_restart || iters >= max_iter;
+    const bool must_sync = need_restart || iters >= max_iter;
+    if (pending && (due || must_sync || hipEventQuery(h->ev_rr) == hipSuccess)) {
+      int f2 = 0;
+      STCHK(rr_collect(S, pend_m, t, theta.data(), est.data(), &f2));
+      pending = false;
+      m_rr = pend_m;
+      if (f2 != 0 && !safe) { redo = true; break; }
+      if (!finite_pairs(t)) return fail(h, EDA_ERR_NONFINITE, "non-finite Ritz pair in the Krylov phase");
+      if (phase_converged()) {
+        kconv = true;
+        m = pend_m;  // the steps since then are not needed
+        break;
       }
-      if (ok) { kconv = true; break; }
+      schedule(pend_iter);
+    }
+    const bool due_now = check_due(can_check) || (can_check && must_sync);
+    if (due_now && async_checks && !must_sync) {
+      STCHK(rr_launch_async(S, m, std::min<int64_t>(nvec, m), t));
+      pending = true;
+      pend_m = m;
+      pend_iter = iters;
+      if (check_every == 0) next_check = iters + 2;  // refined when the verdict is read
+    } else if (due_now) {
+      const int64_t cnt = need_restart ? S.kk : t;
+      int f2 = 0;
+      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), cnt, theta.data(), est.data(), &f2));
+      m_rr = m;
+      if (f2 != 0 && !safe) { redo = true; break; }
+      if (!finite_pairs(cnt)) return fail(h, EDA_ERR_NONFINITE, "non-finite Ritz pair in the Krylov phase");
+      if (phase_converged()) { kconv = true; break; }
+      schedule(iters);
       if (iters >= max_iter) break;
       if (need_restart) {
         // thick restart: keep the kk leading Ritz vectors and the next block
@@ -375,11 +610,20 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
         ++restarts;
       }
     } else if (iters >= max_iter) {
+      int f2 = 0;
       STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), std::min<int64_t>(t, m), theta.data(),
-                          est.data()));
+                          est.data(), &f2));
       m_rr = m;
+      if (f2 != 0 && !safe) { redo = true; break; }
       break;
     }
+  }
+  if (!redo) break;
+  if (pending) {  // drain the second stream before the buffers are reused
+    HIPCHK(hipEventSynchronize(h->ev_rr));
+    pending = false;
+  }
+  safe = true;
   }
   if (m_rr != m || m < t) {
     if (m < t) return fail(h, EDA_ERR_NOCONV, "basis smaller than t at the iteration limit");

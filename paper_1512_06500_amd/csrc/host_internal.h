@@ -23,6 +23,13 @@ struct Buf {
 
 struct BatchState;  // eda_solve_batched workspaces (eda_batched.cpp)
 
+struct StepGraph {  // captured block step (product and orthonormalisation)
+  int64_t m;
+  int cur;
+  bool repair;
+  hipGraphExec_t op, rest;
+};
+
 struct CoreEntry {
   int which = -1;
   double c = 0.0;
@@ -68,6 +75,18 @@ struct eda_handle_s {
   // solver
   eda::Buf Q[2], H[2], Wb, T, wT, S, Sd, hz, Gs, Rinv, R1, Yb, MYb, dtheta, dres, refine;
 
+  // captured block steps of the current solver configuration
+  std::vector<eda::StepGraph> graphs;
+  uint64_t graph_sig = 0;
+  uint64_t prep_gen = 0;  // advanced by every preparation
+  hipStream_t cap = nullptr;
+
+  // second stream for Rayleigh-Ritz checks that overlap the next block steps
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_main = nullptr, ev_rr = nullptr;
+  double* rr_pin = nullptr;  // pinned readback of Ritz values and estimates
+  size_t rr_pin_cap = 0;
+
   // batched solver
   eda::BatchState* batch = nullptr;
 };
@@ -96,6 +115,7 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
                          int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage);
 eda_status prepare_end(eda_handle h);
 void destroy_batch_state(eda_handle h);
+void release_graphs(eda_handle h);
 
 // Low-rank exponential apply on columns [c0, c0+Nc) of P (the storage copy,
 // or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.

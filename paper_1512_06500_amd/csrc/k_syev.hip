@@ -369,7 +369,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
                                                   double* __restrict__ work, int64_t nmax,
                                                   int lds_a, int timing) {
   constexpr int NW = NT / 64;
-  constexpr int DU = NT > 256 ? 4 : 8;  // dot-product unroll within the register budget
+  constexpr int DU = NT > 512 ? 4 : 8;  // dot-product unroll within the register budget
   extern __shared__ double smem[];
   const int q = blockIdx.x;
   int n, nvec_req;
@@ -734,8 +734,12 @@ hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A,
                        int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
                        int64_t strideZ, int64_t nvec, double* work, hipStream_t s) {
   if (n < 1 || n > SYEV_NMAX || batch < 1) return hipErrorInvalidValue;
-  if (n <= 256)
+  // workgroup size by measurement: 256 threads up to n = 48, 512 up to 256
+  if (n <= 48)
     return syev_launch_t<256>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
+                              nvec, work, s);
+  if (n <= 256)
+    return syev_launch_t<512>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
                               nvec, work, s);
   return syev_launch_t<1024>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
                              nvec, work, s);
@@ -756,8 +760,11 @@ hipError_t launch_syev_multi(int count, const SyevArgs* host, const SyevArgs* de
     const SyevArgs& a = host[0];
     return launch_syev(1, a.n, nullptr, a.A, a.lda, 0, a.w, 0, a.Z, a.ldz, 0, a.nvec, a.work, s);
   }
-  if (nmax <= 256)
+  if (nmax <= 48)
     return syev_launch_t<256>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
+                              0, nullptr, s);
+  if (nmax <= 256)
+    return syev_launch_t<512>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
                               0, nullptr, s);
   return syev_launch_t<1024>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
                              0, nullptr, s);

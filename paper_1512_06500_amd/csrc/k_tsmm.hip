@@ -44,12 +44,7 @@ template <typename T> __device__ __forceinline__ double ld64(const T* p) { retur
 // blockIdx.x: row chunk, blockIdx.y: column tile + ytiles * (nb tile),
 // blockIdx.z: problem.
 template <typename TA, typename TB, int S>
-__global__ __launch_bounds__(256) void tn_mfma_kernel(const TnArgs* __restrict__ arr, TnArgs one,
-                                                      int ytiles) {
-  const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
-  if (a.gate != nullptr && *a.gate == 0) return;
-  const int64_t chunk = blockIdx.x;
-  const int yt = blockIdx.y % ytiles, zt = blockIdx.y / ytiles;
+__device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yt, int zt) {
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
   if (chunk >= a.chunks || yt * 16 >= m || zt * 16 >= nb) return;
@@ -106,22 +101,28 @@ __global__ __launch_bounds__(256) void tn_mfma_kernel(const TnArgs* __restrict__
         a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] = acc[v];
     }
   }
+  __syncthreads();  // red may be reused by a caller that loops over work items
+}
+
+template <typename TA, typename TB, int S>
+__global__ __launch_bounds__(256) void tn_mfma_kernel(const TnArgs* __restrict__ arr, TnArgs one,
+                                                      int ytiles) {
+  const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  tn_body<TA, TB, S>(a, blockIdx.x, blockIdx.y % ytiles, blockIdx.y / ytiles);
 }
 
 // Sum of the chunk partials, fixed order: wave w adds chunks w, w+4, ... of
 // 64 outputs, then the 4 wave sums are added in order.
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const ReduceArgs* __restrict__ arr,
-                                                              ReduceArgs one) {
-  const ReduceArgs a = arr != nullptr ? arr[blockIdx.z] : one;
-  if (a.gate != nullptr && *a.gate == 0) return;
+__device__ __forceinline__ void reduce_body(const ReduceArgs& a, int64_t bx) {
   const int64_t mn = a.m * a.nb;
-  if (blockIdx.x * (int64_t)64 >= mn) return;
+  if (bx * 64 >= mn) return;
   __shared__ double red[3][64];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int64_t chunks = a.chunks;
   const double* __restrict__ part = a.part;
-  const int64_t e = blockIdx.x * (int64_t)64 + lane;
+  const int64_t e = bx * 64 + lane;
   const int64_t ee = e < mn ? e : mn - 1;
   double s = 0.0;
   int64_t c = wid;
@@ -136,32 +137,39 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const ReduceArgs* 
   for (; c < chunks; c += 4) s += part[c * mn + ee];
   if (wid > 0) red[wid - 1][lane] = s;
   __syncthreads();
-  if (wid != 0 || e >= mn) return;
-  s += red[0][lane];
-  s += red[1][lane];
-  s += red[2][lane];
-  const int64_t i = e / a.nb, j = e - i * a.nb;
-  if (a.C != nullptr) {
-    double* cp = a.C + i + j * a.ldc;
-    *cp = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * s;
+  if (wid == 0 && e < mn) {
+    s += red[0][lane];
+    s += red[1][lane];
+    s += red[2][lane];
+    const int64_t i = e / a.nb, j = e - i * a.nb;
+    if (a.C != nullptr) {
+      double* cp = a.C + i + j * a.ldc;
+      *cp = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * s;
+    }
+    if (a.Z != nullptr) a.Z[i * a.ldz + j] = a.zalpha * s;
   }
-  if (a.Z != nullptr) a.Z[i * a.ldz + j] = a.zalpha * s;
+  __syncthreads();  // red may be reused by a caller that loops over work items
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const ReduceArgs* __restrict__ arr,
+                                                              ReduceArgs one) {
+  const ReduceArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  reduce_body(a, blockIdx.x);
 }
 
 template <typename TA, typename TV, typename TO, typename ACC, int R, int BATCH>
-__global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
-  const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
-  if (a.gate != nullptr && *a.gate == 0) return;
+__device__ __forceinline__ void nn_body(const NnArgs& a, int64_t bx, int by) {
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
-  const int j0 = blockIdx.y * NN_NB;
-  if (blockIdx.x * (int64_t)R >= d || j0 >= nb) return;
+  const int j0 = by * NN_NB;
+  if (bx * R >= d || j0 >= nb) return;
   constexpr int G = 256 / R;
   __shared__ ACC zs[NN_ZT * NN_NB];
   __shared__ ACC red[256 * (NN_NB + 1)];
   const int tid = threadIdx.x;
   const int rl = tid % R, g = tid / R;
-  const int64_t r = blockIdx.x * (int64_t)R + rl;
+  const int64_t r = bx * R + rl;
   const int64_t lda = a.lda;
   const TA* ar = (const TA*)a.A + (r < d ? r : d - 1);  // rows past d read row d-1, never stored
   ACC acc[NN_NB];
@@ -201,7 +209,7 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
   TO* Out = (TO*)a.Out;
   for (int e = tid; e < R * NN_NB; e += 256) {
     const int rr = e % R, j = e / R;
-    const int64_t row = blockIdx.x * (int64_t)R + rr;
+    const int64_t row = bx * R + rr;
     if (row >= d || j0 + j >= nb) continue;
     ACC sacc = ACC(0);
     for (int u = 0; u < G; ++u) sacc += red[(u * R + rr) * (NN_NB + 1) + j];
@@ -210,6 +218,14 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
     const int64_t oi = a.out_row ? row * a.ldo + (j0 + j) : row + (int64_t)(j0 + j) * a.ldo;
     Out[oi] = from_f64<TO>(o);
   }
+  __syncthreads();  // red and zs may be reused by a caller that loops over work items
+}
+
+template <typename TA, typename TV, typename TO, typename ACC, int R, int BATCH>
+__global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
+  const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  nn_body<TA, TV, TO, ACC, R, BATCH>(a, blockIdx.x, blockIdx.y);
 }
 
 // 64 S rows per wave, 4 waves per workgroup: S = 4 when that still gives

@@ -554,3 +554,40 @@ def test_batched_c4_sample(torch, eda):
         assert ang <= max(1e-5, 50 * fl["span"])
         assert np.abs(X.T @ X - np.eye(c.t)).max() <= 1e-13
     h.close()
+
+
+def test_solve_graph_replays_match_eager(torch, eda, c2, monkeypatch):
+    """Block steps replayed from captured graphs give the bitwise result of
+    direct launches, on every replay, with other work and synchronisations
+    of the program between the replays."""
+    log("graph replays vs direct launches (C2)")
+    h, _, _ = prepared(torch, eda, c2)
+    monkeypatch.setenv("EDA_GRAPHS", "0")
+    ref = h.solve(c2.t, 1e-10, seed=9)
+    X0 = host(ref.X).copy()
+    monkeypatch.setenv("EDA_GRAPHS", "1")
+    V = dev(torch, np.random.default_rng(1).standard_normal((c2.d, 4)))
+    for rep in range(3):
+        r = h.solve(c2.t, 1e-10, seed=9)
+        assert r.ritz == ref.ritz, f"replay {rep}"
+        assert np.array_equal(host(r.X), X0), f"replay {rep}"
+        h.expmv("W", -0.5, V)          # other work of the program in between
+        torch.cuda.synchronize()
+    h.close()
+
+
+def test_solve_repair_every_step_matches(torch, eda, c1, monkeypatch):
+    """The repair pass is left out away from the Krylov dimension bound; with
+    it forced into every step the solve must give the same pairs to
+    rounding (C1 reaches the bound, so both modes deflate)."""
+    log("repair pass in every step vs only near the bound (C1)")
+    ref = O.eda_dense(c1.H_W, c1.H_B, c1.t)
+    h, _, _ = prepared(torch, eda, c1)
+    a = h.solve(c1.t, 1e-10, seed=1)
+    monkeypatch.setenv("EDA_ALWAYS_REPAIR", "1")
+    b = h.solve(c1.t, 1e-10, seed=1)
+    for r in (a, b):
+        assert r.status == 0
+        assert np.max(np.abs(np.array(r.ritz) - ref.lam) / ref.lam) <= 1e-10
+        assert O.sin_angle(ref.X, host(r.X)) <= 1e-8
+    h.close()
