@@ -49,6 +49,39 @@ template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) {
 }
 
 // ---------------------------------------------------------------------------
+// Wave-level exchanges (wave64).
+// ---------------------------------------------------------------------------
+// Value of v in lane `lane` (the same lane for the whole wave).
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Lane exchanges within rows of 16 lanes (DPP): partner l^1, l^2 inside a
+// quad, the mirror inside 8 lanes (pairs the two quads) and inside 16
+// lanes (pairs the two halves).  Every pattern is an involution, so a
+// reduction built from them leaves the same bits in both partners.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppMirror8 = 0x141, kDppMirror16 = 0x140;
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes (all active); every lane gets the same bits.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppMirror8>(v);
+  v += dpp_f64<kDppMirror16>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers (implemented in the .hip files, called by the host sources).
 // All take the stream last and return hipError_t of the launch.
 // Shapes are validated by the caller; each launcher documents what it needs.
@@ -89,6 +122,7 @@ struct NnArgs {      // Out = alpha V + A Z
   void* Out;
   int out_row;
   const int* gate;
+  const double* alpha_p;  // when not null, alpha is read from here (device)
 };
 struct CholArgs {
   int64_t b, ldg, ldri, ldrp, ldro, m, ldhc;
@@ -285,7 +319,7 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
-                     hipStream_t s, bool out_row = false);
+                     hipStream_t s, bool out_row = false, const double* alpha_p = nullptr);
 
 // k_gemm.hip ----------------------------------------------------------------
 // C (m x n) = alpha * op(A) * diag(dk) * op(B) + beta * C, float64, col-major.

@@ -79,7 +79,7 @@ eda_status check_dev_ptr(eda_handle h, const void* p, const char* name) {
 //   Out = alpha V + P_c (C (P_c^T V)),  C: Nc x Nc (ldc).
 eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
                  int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
-                 void* Out, DT odt, int64_t ldo) {
+                 void* Out, DT odt, int64_t ldo, const double* alpha_p) {
   const bool use64 = master && h->storage != EDA_F64;
   const DT pdt = use64 ? DT::F64 : dt_of(h->storage);
   const char* base = use64 ? h->P64.c() : h->P.c();
@@ -97,7 +97,7 @@ eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double
   HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, h->Ysm.d(), b, 0.0, nullptr, DT::F64, 0,
                    h->Zsm.d(), DT::F64, b, nullptr, h->stream, true));
   HIPCHK(launch_nn(h->d, Nc, b, Pc, pdt, h->ldp, h->Zsm.d(), b, alpha, V, vdt, ldv, Out, odt,
-                   ldo, nullptr, h->stream));
+                   ldo, nullptr, h->stream, false, alpha_p));
   return EDA_OK;
 }
 
@@ -315,7 +315,7 @@ void eda_destroy(eda_handle h) {
                   &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part,
                   &h->Ysm, &h->Zsm, &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
-                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine};
+                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev};
     for (Buf* b : all) release(*b);
     for (auto& c : h->cores) release(c.buf);
     for (hipEvent_t e : h->op_ev) (void)hipEventDestroy(e);
@@ -388,7 +388,6 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
   STCHK(check_dev_ptr(h, H_W, "H_W"));
   STCHK(check_dev_ptr(h, H_B, "H_B"));
   h->prepared = false;
-  ++h->prep_gen;
   for (auto& c : h->cores) release(c.buf);
   h->cores.clear();
 
@@ -493,6 +492,8 @@ eda_status prepare_end(eda_handle h) {
   for (double v : h->hwB) lbmax = std::max(lbmax, v);
   h->shiftB = lbmax;  // s = lambda_max(S_B): every factor e^{lambda - s} <= 1
   h->alphaB = std::exp(-h->shiftB);
+  STCHK(ensure(h, h->alphaB_dev, 8));
+  HIPCHK(launch_fill(1, h->alphaB, h->alphaB_dev.d(), h->stream));
   STCHK(build_composite_cores(h));
   HIPCHK(hipEventRecord(h->prep_ev[1], h->stream));
   h->prepared = true;

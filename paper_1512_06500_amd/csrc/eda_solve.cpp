@@ -86,8 +86,10 @@ eda_status cgs_pass(eda_handle h, int64_t d, int64_t m, const void* Q, DT qdt, i
 // W = e^{-s} M V_j in the Krylov-phase types.
 eda_status lanczos_op(Solver& S, int64_t m) {
   eda_handle h = S.h;
+  // e^{-s} is read from the device, so a captured step stays valid when a
+  // later preparation changes the shift
   return expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt, S.ldq,
-               h->Wb.p, S.qdt, S.ldq);
+               h->Wb.p, S.qdt, S.ldq, h->alphaB_dev.d());
 }
 
 // The rest of the block step: orthonormalise W into the next block and
@@ -396,13 +398,12 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   }
 
   // EDA_GRAPHS=1 replays the block steps from captured graphs (valid while
-  // every buffer, size and scalar they bake in is unchanged).  Measured
-  // slower than direct launches on this hardware, so off by default.
+  // every buffer and size they bake in is unchanged).
   const char* genv = std::getenv("EDA_GRAPHS");
   const bool use_graphs = genv != nullptr && std::strcmp(genv, "1") == 0;
   {
     const uint64_t parts[] = {
-        h->prep_gen, (uint64_t)d, (uint64_t)h->N, (uint64_t)b, (uint64_t)qdt, (uint64_t)ldq,
+        (uint64_t)(uintptr_t)h->alphaB_dev.p, (uint64_t)d, (uint64_t)h->N, (uint64_t)b, (uint64_t)qdt, (uint64_t)ldq,
         (uint64_t)ldh, (uint64_t)mmax, (uint64_t)h->storage, (uint64_t)(uintptr_t)h->Q[0].p,
         (uint64_t)(uintptr_t)h->Q[1].p, (uint64_t)(uintptr_t)h->H[0].p,
         (uint64_t)(uintptr_t)h->H[1].p, (uint64_t)(uintptr_t)h->Wb.p,

@@ -57,6 +57,7 @@ struct eda_handle_s {
   eda::Buf P64;  // float64 master of P when storage is not float64
   eda::Buf G, eigW, eigZ, nsbuf, Gh, Gm, GBs, CM, CA, T1, T2, T3, T4, fw, polyws, normbuf;
   double shiftB = 0.0, alphaB = 1.0;
+  eda::Buf alphaB_dev;  // alphaB on the device, read by captured steps
   double normW = 0.0;   // ||H_W^T H_W||_1
   bool w_eig = false;   // eigenpairs of H_W^T H_W available
   std::vector<double> hwW, hwB;
@@ -78,7 +79,6 @@ struct eda_handle_s {
   // captured block steps of the current solver configuration
   std::vector<eda::StepGraph> graphs;
   uint64_t graph_sig = 0;
-  uint64_t prep_gen = 0;  // advanced by every preparation
   hipStream_t cap = nullptr;
 
   // second stream for Rayleigh-Ritz checks that overlap the next block steps
@@ -121,7 +121,7 @@ void release_graphs(eda_handle h);
 // or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.
 eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
                  int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
-                 void* Out, DT odt, int64_t ldo);
+                 void* Out, DT odt, int64_t ldo, const double* alpha_p = nullptr);
 
 }  // namespace eda
 

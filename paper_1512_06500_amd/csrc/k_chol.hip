@@ -18,6 +18,12 @@ namespace {
 
 constexpr int CH_MAX = 128;
 
+// LDS use of chol_kernel (one b x b array, ld = CH_MAX + 1):
+//   during the factorisation the lower triangle holds the trailing matrix
+//   and the strict upper triangle receives R = L^T row by row (diagonal in
+//   rd), so a step reads only what no thread of that step writes and needs
+//   one barrier; afterwards X = R^{-1} goes to the strict lower triangle
+//   (X[i][c] at (c, i)), diagonal in xd.
 __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ arr, CholArgs one) {
   const CholArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
@@ -31,76 +37,77 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
   const double ratio = a.ratio;
   int* flag = a.flag;
   __shared__ double L[CH_MAX * (CH_MAX + 1)];
-  __shared__ double diag0[CH_MAX];
+  __shared__ double rd[CH_MAX], xd[CH_MAX], hn[CH_MAX], d0[CH_MAX];
   __shared__ int sflag;
   const int ld = CH_MAX + 1;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   if (tid == 0) sflag = 0;
   for (int e = tid; e < b * b; e += blockDim.x) {
     const int c = e / b, r = e - c * b;
     if (r >= c) L[r + c * ld] = G[r + c * ldg];
+    if (r == c) d0[r] = G[r + c * ldg];
   }
-  __syncthreads();
-  for (int e = tid; e < b; e += blockDim.x) diag0[e] = L[e + e * ld];
+  // squared norms of the projection coefficients, one wave per column
+  if (hcol != nullptr)
+    for (int c = wid; c < b; c += nw) {
+      const double* hc = hcol + (int64_t)c * ldhc;
+      const double v0 = (lane < m) ? hc[lane] : 0.0;
+      const double v1 = (lane + 64 < m) ? hc[lane + 64] : 0.0;
+      double h2 = v0 * v0 + v1 * v1;
+      for (int64_t r = lane + 128; r < m; r += 64) h2 += hc[r] * hc[r];
+      h2 = wave_sum(h2);
+      if (lane == 0) hn[c] = h2;
+    }
   __syncthreads();
   for (int j = 0; j < b; ++j) {
-    if (tid == 0) {
-      double p = L[j + j * ld];
-      const double floor_ = 1e-28 * fabs(diag0[j]) + 1e-300;
-      if (!(p > floor_)) {  // also catches NaN
-        p = floor_;
-        sflag = 1;
-      }
-      L[j + j * ld] = sqrt(p);
+    double p = L[j + j * ld];
+    const double floor_ = 1e-28 * fabs(d0[j]) + 1e-300;
+    if (!(p > floor_)) {  // also catches NaN
+      p = floor_;
+      if (tid == 0) sflag = 1;
     }
-    __syncthreads();
-    const double piv = L[j + j * ld];
-    for (int i = j + 1 + tid; i < b; i += blockDim.x) L[i + j * ld] /= piv;
-    __syncthreads();
-    const int rem = b - j - 1;
-    for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int c = j + 1 + e / rem, r = j + 1 + e % rem;
-      if (r >= c) L[r + c * ld] -= L[r + j * ld] * L[c + j * ld];
+    const double piv = sqrt(p), inv = 1.0 / piv;
+    if (tid == 0) rd[j] = piv;
+    for (int i = j + 1 + tid; i < b; i += blockDim.x) L[j + i * ld] = L[i + j * ld] * inv;
+    for (int c = j + 1 + wid; c < b; c += nw) {
+      const double lc = L[c + j * ld] * inv;
+      for (int r = c + lane; r < b; r += 64) L[r + c * ld] -= (L[r + j * ld] * inv) * lc;
     }
     __syncthreads();
   }
-  // R = L^T.  Column c of X = R^{-1}: back substitution R X = I, one thread per column.
+  // X = R^{-1} by back substitution, one thread per column c:
+  //   X[i][c] = (delta_ic - sum_{q=i+1..c} R[i][q] X[q][c]) / R[i][i]
   for (int c = tid; c < b; c += blockDim.x) {
-    for (int i = b - 1; i >= 0; --i) {
-      double x;
-      if (i > c) {
-        x = 0.0;
-      } else {
-        double s = (i == c) ? 1.0 : 0.0;
-        for (int q = i + 1; q <= c; ++q) s -= L[q + i * ld] * Rinv[(int64_t)q * ldri + c];
-        x = s / L[i + i * ld];
-      }
-      Rinv[(int64_t)i * ldri + c] = x;
+    const double xcc = 1.0 / rd[c];
+    xd[c] = xcc;
+    for (int i = c - 1; i >= 0; --i) {
+      double s = -L[i + c * ld] * xcc;
+      for (int q = i + 1; q < c; ++q) s -= L[i + q * ld] * L[c + q * ld];
+      L[c + i * ld] = s / rd[i];
     }
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int i = e / b, c = e - i * b;
+    Rinv[(int64_t)i * ldri + c] = (i < c) ? L[c + i * ld] : (i == c ? xd[c] : 0.0);
   }
   if (Rout != nullptr) {
     for (int e = tid; e < b * b; e += blockDim.x) {
       const int c = e / b, r = e - c * b;
       double s = 0.0;
       if (Rprev == nullptr) {
-        s = (r <= c) ? L[c + r * ld] : 0.0;
+        s = (r < c) ? L[r + c * ld] : (r == c ? rd[r] : 0.0);
       } else {
         // (R * Rprev)[r, c] = sum_{q >= r} R[r, q] Rprev[q, c]  (R upper, Rprev general)
-        for (int q = r; q < b; ++q) s += L[q + r * ld] * Rprev[q + c * ldrp];
+        s = rd[r] * Rprev[r + c * ldrp];
+        for (int q = r + 1; q < b; ++q) s += L[r + q * ld] * Rprev[q + c * ldrp];
       }
       Rout[r + c * ldro] = s;
     }
   }
-  if (hcol != nullptr) {
-    for (int c = tid; c < b; c += blockDim.x) {
-      double h2 = 0.0;
-      for (int64_t r = 0; r < m; ++r) {
-        const double v = hcol[r + c * ldhc];
-        h2 += v * v;
-      }
-      const double rc = L[c + c * ld];
-      if (!(rc >= ratio * sqrt(h2 + rc * rc))) atomicOr(&sflag, 1);
-    }
+  if (hcol != nullptr && tid < b) {
+    const double rc = rd[tid];
+    if (!(rc >= ratio * sqrt(hn[tid] + rc * rc))) atomicOr(&sflag, 1);
   }
   __syncthreads();
   if (tid == 0 && flag != nullptr && sflag) *flag = 1;
@@ -145,13 +152,28 @@ __global__ __launch_bounds__(64) void pchol_kernel(const PcholArgs* __restrict__
     const int c = e / b, r = e - c * b;
     A[r + c * ld] = G[r + c * ldg] * dsc[r] * dsc[c];
   }
-  if (tid < b) {
-    double h2 = 0.0;
-    if (hcol != nullptr && !equil)
-      for (int64_t r = 0; r < m; ++r) {
-        const double v = hcol[r + tid * ldhc];
-        h2 += v * v;
+  // squared norms of the projection coefficients: the wave sums column c
+  // and lane c keeps it
+  double h2 = 0.0;
+  if (hcol != nullptr && !equil)
+    for (int c0 = 0; c0 < b; c0 += 8) {
+      double hs[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double* hc = hcol + (int64_t)(c0 + u < b ? c0 + u : 0) * ldhc;
+        const double v0 = (c0 + u < b && tid < m) ? hc[tid] : 0.0;
+        const double v1 = (c0 + u < b && tid + 64 < m) ? hc[tid + 64] : 0.0;
+        hs[u] = v0 * v0 + v1 * v1;
+        if (c0 + u < b)
+          for (int64_t r = tid + 128; r < m; r += 64) hs[u] += hc[r] * hc[r];
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double t = wave_sum(hs[u]);
+        if (tid == c0 + u) h2 = t;
+      }
+    }
+  if (tid < b) {
     nrm0[tid] = G[tid + tid * ldg] * dsc[tid] * dsc[tid] + h2;
     perm[tid] = tid;
   }
@@ -204,47 +226,46 @@ __global__ __launch_bounds__(64) void pchol_kernel(const PcholArgs* __restrict__
     __syncthreads();
     // update the whole (symmetric) trailing block: later pivot swaps read
     // both of its triangles
-    const int rem = b - j - 1;
-    for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int c = j + 1 + e / rem, r = j + 1 + e % rem;
-      A[r + c * ld] -= A[r + j * ld] * A[c + j * ld];
+    for (int c = j + 1; c < b; ++c) {
+      const double ac = A[c + j * ld];
+      if (tid > j && tid < b) A[tid + c * ld] -= A[tid + j * ld] * ac;
     }
     __syncthreads();
   }
   const int rk = s_rank;
-  // Z: zero, then R11^{-1} scattered to the original row positions.
-  for (int e = tid; e < b * b; e += blockDim.x) {
-    const int i = e / b, c = e - i * b;
-    Z[(int64_t)i * ldz + c] = 0.0;
-  }
-  __syncthreads();
-  // R11^{-1} (upper, R11[i, q] = L[q, i]) by back substitution, one thread per
-  // column c < rk, written straight into the rows perm[i] of Z.
+  __shared__ double xd[PB];
+  __shared__ int iperm[PB];
+  if (tid < b) iperm[perm[tid]] = tid;
+  // R11^{-1} (upper, R11[i][q] = L[q][i]) by back substitution, one thread
+  // per column c < rk; X[i][c] (i < c) goes to the strict upper triangle of
+  // A, which the factorisation no longer needs, the diagonal to xd.
   if (tid < rk) {
     const int c = tid;
-    for (int i = c; i >= 0; --i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int q = i + 1; q <= c; ++q) s -= A[q + i * ld] * Z[(int64_t)perm[q] * ldz + c];
-      Z[(int64_t)perm[i] * ldz + c] = s / A[i + i * ld];
+    const double xcc = 1.0 / A[c + c * ld];
+    xd[c] = xcc;
+    for (int i = c - 1; i >= 0; --i) {
+      double s = -A[c + i * ld] * xcc;
+      for (int q = i + 1; q < c; ++q) s -= A[q + i * ld] * A[q + c * ld];
+      A[i + c * ld] = s / A[i + i * ld];
     }
+  }
+  __syncthreads();
+  // Z[rho][c] = X[i][c] with perm[i] = rho (zero for i > c or c >= rk),
+  // times the column scaling of rho when equilibrated
+  for (int e = tid; e < b * b; e += blockDim.x) {
+    const int rho = e / b, c = e - rho * b;
+    const int i = iperm[rho];
+    double v = 0.0;
+    if (c < rk && i <= c) v = (i < c) ? A[i + c * ld] : xd[c];
+    Z[(int64_t)rho * ldz + c] = equil ? v * dsc[rho] : v;
   }
   // R[j, perm[i]] = L[i, j] for j < rk, i >= j; zero elsewhere.
   for (int e = tid; e < b * b; e += blockDim.x) {
     const int ci = e / b, j = e - ci * b;  // output column ci (original index), row j
-    double v = 0.0;
-    if (j < rk) {
-      int i = 0;
-      while (perm[i] != ci) ++i;
-      if (i >= j) v = A[i + j * ld] / dsc[ci];
-    }
+    const int i = iperm[ci];
+    const double v = (j < rk && i >= j) ? A[i + j * ld] / dsc[ci] : 0.0;
     R[j + (int64_t)ci * ldr] = v;
   }
-  __syncthreads();
-  if (equil)  // Z maps the unscaled block: fold the column scaling into its rows
-    for (int e = tid; e < b * b; e += blockDim.x) {
-      const int i = e / b, c = e - i * b;
-      Z[(int64_t)i * ldz + c] *= dsc[i];
-    }
   if (tid < b) {
     mask[tid] = (tid >= rk) ? 1 : 0;
     if (tid < rk && !(A[tid + tid * ld] >= ratio * sqrt(nrm0[perm[tid]]))) atomicOr(&s_flag, 1);

@@ -5,17 +5,22 @@
 // float64 throughout.
 //
 //   1. Householder reduction to tridiagonal form T = Q^T A Q.  The working
-//      matrix lives in LDS when it fits (n <= kLdsMax), else in global memory.
+//      matrix lives in LDS when it fits (n <= kLdsMax; two barriers per
+//      reflector), else in global memory.
 //   2. Eigenvalues of T by Sturm-count multisection: groups of g threads
-//      probe g points per step; the count uses the three-term recurrence of
-//      the leading principal minors (no divisions), rescaled by powers of 2.
+//      probe 4 g points per step; the count uses the three-term recurrence
+//      of the leading principal minors (no divisions) on T scaled by a power
+//      of two, rescaled by powers of 2 every four steps.
 //   3. Eigenvectors of T by inverse iteration, one thread per eigenvalue
-//      (LU with partial pivoting of T - lambda I, three solves with
+//      (LU with partial pivoting of T - lambda I, two solves with
 //      overflow-safe rescaling), then orthonormalisation inside clusters of
 //      close eigenvalues (Cholesky QR twice by the whole workgroup, or
 //      modified Gram-Schmidt for very large clusters).
-//   4. Back-transformation by the stored reflectors, one thread per vector.
+//   4. Back-transformation by the stored reflectors: applied straight to the
+//      eigenvectors of T held in registers (LDS path), or by forming Q
+//      (global path).
 #include <cstdio>
+#include <type_traits>
 
 #include "common.h"
 
@@ -27,11 +32,6 @@ constexpr int SYEV_NMAX = 2048;
 constexpr int kLdsMax = 112;      // largest n whose working matrix is kept in LDS
 constexpr int kStage = 8192;      // doubles of LDS for staged reflectors (global path)
 constexpr int kClusterMax = 64;   // clusters up to this size use Cholesky QR
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-  return v;
-}
 
 template <int NT>
 __device__ __forceinline__ double blk_sum(double v, double* red) {
@@ -100,58 +100,61 @@ __device__ __forceinline__ uint64_t hash64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// Number of eigenvalues of T below x: sign changes of the leading principal
-// minors p_k of T - xI, p_k = (d_k - x) p_{k-1} - e_{k-1}^2 p_{k-2}, kept in
-// range by exact power-of-two rescaling.  A zero minor is replaced by a tiny
-// value of the sign opposite to its predecessor (counted as a change), the
-// same convention as a zero pivot of the LDL^T form of the count.
-__device__ __forceinline__ int sturm_count(int n, const double* __restrict__ D,
-                                           const double* __restrict__ E2, double x) {
-  const double hi = 0x1.0p400, lo = 0x1.0p-400;
-  double pm2 = 1.0;        // p_{k-2}
-  double pm1 = D[0] - x;   // p_{k-1} = p_0
-  if (pm1 == 0.0) pm1 = -0x1.0p-1000;
-  int c = (pm1 < 0.0);
-  auto step = [&](double dk, double e2k) {
-    double p = (dk - x) * pm1 - e2k * pm2;
-    if (p == 0.0) p = (pm1 < 0.0) ? 0x1.0p-1000 : -0x1.0p-1000;
-    c += ((p < 0.0) != (pm1 < 0.0));
-    const double ap = fabs(p);
-    if (ap > hi) {
-      p *= lo;
-      pm1 *= lo;
-    } else if (ap < lo && fabs(pm1) < lo) {
-      p *= hi;
-      pm1 *= hi;
-    }
-    pm2 = pm1;
-    pm1 = p;
-  };
+// Counts for K points at once (K independent recurrences interleaved), for
+// a T scaled so that |d_k|, e_k^2 and |x| are at most 4: a minor grows by at
+// most 8x per step, so the power-of-two rescaling is checked every four
+// steps (thresholds 2^+-600).  A zero minor becomes -2^-60 times its
+// predecessor: tiny, of the opposite sign, counted as a change.
+template <int K>
+__device__ __forceinline__ void sturm_counts(int n, const double* __restrict__ D,
+                                             const double* __restrict__ E2, const double* x,
+                                             int* cnt) {
+  double pm2[K], pm1[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    pm2[q] = 1.0;
+    pm1[q] = D[0] - x[q];
+    if (pm1[q] == 0.0) pm1[q] = -0x1.0p-60;
+    cnt[q] = (pm1[q] < 0.0);
+  }
   int k = 1;
-  for (; k + 3 < n; k += 4) {  // loads of four steps issued together
-    const double d0 = D[k], d1 = D[k + 1], d2 = D[k + 2], d3 = D[k + 3];
-    const double f0 = E2[k - 1], f1 = E2[k], f2 = E2[k + 1], f3 = E2[k + 2];
-    step(d0, f0);
-    step(d1, f1);
-    step(d2, f2);
-    step(d3, f3);
+  for (; k + 3 < n; k += 4) {
+    double dk[4], fk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      dk[u] = D[k + u];
+      fk[u] = E2[k - 1 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        double p = fma(dk[u] - x[q], pm1[q], -fk[u] * pm2[q]);
+        p = (p == 0.0) ? -0x1.0p-60 * pm1[q] : p;
+        cnt[q] += ((p < 0.0) != (pm1[q] < 0.0));
+        pm2[q] = pm1[q];
+        pm1[q] = p;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const double mx = fmax(fabs(pm1[q]), fabs(pm2[q]));
+      const double f = (mx > 0x1.0p600) ? 0x1.0p-600 : ((mx < 0x1.0p-600) ? 0x1.0p600 : 1.0);
+      pm1[q] *= f;
+      pm2[q] *= f;
+    }
   }
   for (; k < n; ++k) {
-    double p = (D[k] - x) * pm1 - E2[k - 1] * pm2;
-    if (p == 0.0) p = (pm1 < 0.0) ? 0x1.0p-1000 : -0x1.0p-1000;
-    c += ((p < 0.0) != (pm1 < 0.0));
-    const double ap = fabs(p);
-    if (ap > hi) {
-      p *= lo;
-      pm1 *= lo;
-    } else if (ap < lo && fabs(pm1) < lo) {
-      p *= hi;
-      pm1 *= hi;
+    const double dv = D[k], fv = E2[k - 1];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      double p = fma(dv - x[q], pm1[q], -fv * pm2[q]);
+      p = (p == 0.0) ? -0x1.0p-60 * pm1[q] : p;
+      cnt[q] += ((p < 0.0) != (pm1[q] < 0.0));
+      pm2[q] = pm1[q];
+      pm1[q] = p;
     }
-    pm2 = pm1;
-    pm1 = p;
   }
-  return c;
 }
 
 // LU factorisation with partial pivoting of T - lam I (T tridiagonal: diagonal
@@ -436,6 +439,154 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
 
   SYEV_MARK(0);
   // ---- 1. Householder tridiagonalisation ---------------------------------
+  if (NT <= 512 && lds_a) {
+    // Working matrix in LDS, two barriers per reflector.  Lane l of every
+    // wave holds rows j+1+l and j+65+l of the trailing block; wave w takes
+    // the columns j+1+w, j+1+w+NW, ...  The wave partials of A v (and of
+    // v^T A v) meet in LDS at the first barrier; each thread then forms
+    // w = tau A v - (tau^2 v^T A v / 2) v for its rows and applies the
+    // rank-2 update to its columns, taking w of a column from the lane that
+    // holds that row.  The norm of the next column below its subdiagonal is
+    // summed by wave 0, which updates that column, so the next reflector
+    // needs no further reduction.  Reflector j is scaled into column j of A
+    // one step later, when nothing reads that column any more.
+    double* const AL = smem;     // the same matrix, addressed as LDS
+    double* pw = Gc;              // NW x 128 wave partials of A v
+    double* dw = Gc + NW * 128;   // NW wave partials of v^T A v
+    double* cn = red;             // next-column norms, alternating slots
+    const int wsu = __builtin_amdgcn_readfirstlane(wid);  // wave index, known uniform
+    if (wid == 0) {
+      double s0 = 0.0;
+      for (int r = 2 + lane; r < n; r += 64) s0 += AL[r] * AL[r];
+      s0 = wave_sum(s0);
+      if (lane == 0) cn[0] = s0;
+    }
+    __syncthreads();
+    double scale_prev = 0.0;
+    for (int j = 0; j < n - 2; ++j) {
+      const double* col = AL + (int64_t)j * ldA;
+      if (j > 0)
+        for (int r = j + 1 + tid; r < n; r += NT) AL[r + (int64_t)(j - 1) * ldA] *= scale_prev;
+      const double s = cn[j & 1];
+      const double alpha = col[j + 1];
+      double beta, tv, scale;
+      if (s == 0.0) {
+        tv = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        tv = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (tid == 0) {
+        dd[j] = col[j];
+        ee[j] = beta;
+        tau[j] = tv;
+      }
+      scale_prev = scale;
+      const int r0 = j + 1 + lane, r1 = r0 + 64;
+      if (tv == 0.0) {
+        if (wid == 0) {
+          const double* c1 = AL + (int64_t)(j + 1) * ldA;
+          double s1 = 0.0;
+          for (int r = j + 3 + lane; r < n; r += 64) s1 += c1[r] * c1[r];
+          s1 = wave_sum(s1);
+          if (lane == 0) cn[(j + 1) & 1] = s1;
+        }
+        __syncthreads();
+        continue;
+      }
+      const double y0 = col[r0], y1 = col[r1];  // rows past n: in-range LDS, masked
+      const double v0 = (r0 == j + 1) ? 1.0 : (r0 < n ? y0 * scale : 0.0);
+      const double v1 = (r1 < n) ? y1 * scale : 0.0;
+      // loads of four columns are issued together; rows past n read
+      // in-range LDS and are masked
+      double a0 = 0.0, a1 = 0.0;
+      int c = j + 1 + wsu;
+      for (; c + 3 * NW < n; c += 4 * NW) {
+        double vc[4], x0[4], x1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int cu = c + u * NW;
+          const double* ac = AL + (int64_t)cu * ldA;
+          vc[u] = col[cu];
+          x0[u] = ac[r0];
+          x1[u] = ac[r1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) vc[u] = (c + u * NW == j + 1) ? 1.0 : vc[u] * scale;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a0 += (r0 < n ? x0[u] : 0.0) * vc[u];
+          a1 += (r1 < n ? x1[u] : 0.0) * vc[u];
+        }
+      }
+      for (; c < n; c += NW) {
+        const double cv = col[c];
+        const double* ac = AL + (int64_t)c * ldA;
+        const double x0 = ac[r0], x1 = ac[r1];
+        const double vc = (c == j + 1) ? 1.0 : cv * scale;
+        a0 += (r0 < n ? x0 : 0.0) * vc;
+        a1 += (r1 < n ? x1 : 0.0) * vc;
+      }
+      const double dsum = wave_sum(v0 * a0 + v1 * a1);
+      pw[wid * 128 + lane] = a0;
+      pw[wid * 128 + 64 + lane] = a1;
+      if (lane == 0) dw[wid] = dsum;
+      __syncthreads();
+      double p0 = 0.0, p1 = 0.0, vav = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        p0 += pw[w * 128 + lane];
+        p1 += pw[w * 128 + 64 + lane];
+        vav += dw[w];
+      }
+      const double K = 0.5 * tv * tv * vav;
+      const double w0 = tv * p0 - K * v0, w1 = tv * p1 - K * v1;
+      c = j + 1 + wsu;
+      for (; c + 3 * NW < n; c += 4 * NW) {
+        double vc[4], wc[4], x0[4], x1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int cu = c + u * NW;
+          const int lc = cu - (j + 1);
+          const double* ac = AL + (int64_t)cu * ldA;
+          vc[u] = col[cu];
+          wc[u] = (lc < 64) ? readlane_f64(w0, lc) : readlane_f64(w1, lc - 64);
+          x0[u] = ac[r0];
+          x1[u] = ac[r1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) vc[u] = (c + u * NW == j + 1) ? 1.0 : vc[u] * scale;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          double* ac = AL + (int64_t)(c + u * NW) * ldA;
+          if (r0 < n) ac[r0] = x0[u] - (v0 * wc[u] + w0 * vc[u]);
+          if (r1 < n) ac[r1] = x1[u] - (v1 * wc[u] + w1 * vc[u]);
+        }
+      }
+      for (; c < n; c += NW) {
+        const int lc = c - (j + 1);
+        const double cv = col[c];
+        const double wc = (lc < 64) ? readlane_f64(w0, lc) : readlane_f64(w1, lc - 64);
+        double* ac = AL + (int64_t)c * ldA;
+        const double x0 = ac[r0], x1 = ac[r1];
+        const double vc = (c == j + 1) ? 1.0 : cv * scale;
+        if (r0 < n) ac[r0] = x0 - (v0 * wc + w0 * vc);
+        if (r1 < n) ac[r1] = x1 - (v1 * wc + w1 * vc);
+      }
+      if (wsu == 0) {  // wave 0 updated column j+1: its norm below row j+2
+        const double* c1 = AL + (int64_t)(j + 1) * ldA;
+        const double y0 = c1[r0], y1 = c1[r1];
+        double nrm = (r0 >= j + 3 && r0 < n) ? y0 * y0 : 0.0;
+        nrm += (r1 < n) ? y1 * y1 : 0.0;
+        nrm = wave_sum(nrm);
+        if (lane == 0) cn[(j + 1) & 1] = nrm;
+      }
+      __syncthreads();
+    }
+    if (n >= 3 && tid == 0) AL[(n - 1) + (int64_t)(n - 3) * ldA] *= scale_prev;
+  } else
   for (int j = 0; j < n - 2; ++j) {
     const int m1 = n - j - 1;
     double* col = A + (int64_t)j * ldA;
@@ -505,14 +656,16 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
 
   SYEV_MARK(1);
   // ---- 2. eigenvalues by multisection -------------------------------------
-  double* D = sv;
-  double* E2 = sw;
+  // Counts run on T scaled by a power of two (exact) to norm in [1, 2);
+  // each group of g lanes probes K g points of its eigenvalue's interval.
+  double* D = sv;    // diagonal, unscaled (eigenvector phase)
+  double* E2 = sw;   // squared off-diagonal, scaled
+  double* Ds = Gc;   // diagonal, scaled (Gc is free until the cluster phase)
   double lo_g = 1e308, hi_g = -1e308;
   for (int i = tid; i < n; i += NT) {
     D[i] = dd[i];
     const double el = (i > 0) ? fabs(ee[i - 1]) : 0.0;
     const double er = (i < n - 1) ? fabs(ee[i]) : 0.0;
-    if (i < n - 1) E2[i] = ee[i] * ee[i];
     lo_g = fmin(lo_g, dd[i] - el - er);
     hi_g = fmax(hi_g, dd[i] + el + er);
   }
@@ -521,24 +674,67 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   double tnorm = fmax(fabs(lo_g), fabs(hi_g));
   const bool zero_mat = !(tnorm > 0.0);
   if (zero_mat) tnorm = 1.0;
-  const double fudge = 4.0 * eps * tnorm;
-  const double atol = 0.5 * eps * tnorm;
-  // only the nv wanted (largest) eigenvalues are located
+  const int ex = ilogb(tnorm);
+  const double sc = ldexp(1.0, -ex), usc = ldexp(1.0, ex);
+  for (int i = tid; i < n; i += NT) {
+    Ds[i] = dd[i] * sc;
+    if (i < n - 1) {
+      const double es = ee[i] * sc;
+      E2[i] = es * es;
+    }
+  }
+  __syncthreads();
+  const double tn_s = tnorm * sc;
+  const double fudge = 4.0 * eps * tn_s;
+  const double atol = 0.5 * eps * tn_s;
+  const double lo0 = lo_g * sc - fudge, hi0 = hi_g * sc + fudge;
+  // only the nv wanted (largest) eigenvalues are located; K points per lane
+  // (1 when the groups fill at least half the workgroup, else 2 or 4: the
+  // recurrences of one lane are independent, so they overlap)
   int g = 1;
-  while (g < 64 && 2 * g * nv <= NT) g *= 2;
+  while (g < 64 && 2 * g * nv <= NT) g *= 2;  // g lanes per wanted eigenvalue
   const int groups = NT / g;
   const int gl = tid % g, gi = tid / g;
-  for (int base = n - nv; base < n; base += groups) {
-    const int i = base + gi;
-    if (i < n) {
-      double lo = lo_g - fudge, hi = hi_g + fudge;
+  const int busy = g * (nv < groups ? nv : groups);
+  auto locate = [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    const double inv_p = 1.0 / (double)(K * g + 1);
+    for (int base = n - nv; base < n; base += groups) {
+      const int i = base + gi;
+      if (i >= n) continue;
+      double lo = lo0, hi = hi0;
       for (int it = 0; it < 200; ++it) {
         if (hi - lo <= fmax(atol, 2.0 * eps * fmax(fabs(lo), fabs(hi)))) break;
-        const double x = lo + (double)(gl + 1) * ((hi - lo) / (double)(g + 1));
-        const int cnt = sturm_count(n, D, E2, x);
-        double nlo = (cnt <= i) ? x : lo;
-        double nhi = (cnt > i) ? x : hi;
-        for (int m = 1; m < g; m <<= 1) {
+        const double step = (hi - lo) * inv_p;
+        double x[K];
+        int cnt[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) x[q] = lo + (double)(gl * K + q + 1) * step;
+        sturm_counts<K>(n, Ds, E2, x, cnt);
+        double nlo = lo, nhi = hi;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          if (cnt[q] <= i) nlo = fmax(nlo, x[q]);
+          if (cnt[q] > i) nhi = fmin(nhi, x[q]);
+        }
+        // the g lanes of a group are aligned to g, so the exchanges stay inside it
+        if (g >= 2) {
+          nlo = fmax(nlo, dpp_f64<kDppXor1>(nlo));
+          nhi = fmin(nhi, dpp_f64<kDppXor1>(nhi));
+        }
+        if (g >= 4) {
+          nlo = fmax(nlo, dpp_f64<kDppXor2>(nlo));
+          nhi = fmin(nhi, dpp_f64<kDppXor2>(nhi));
+        }
+        if (g >= 8) {
+          nlo = fmax(nlo, dpp_f64<kDppMirror8>(nlo));
+          nhi = fmin(nhi, dpp_f64<kDppMirror8>(nhi));
+        }
+        if (g >= 16) {
+          nlo = fmax(nlo, dpp_f64<kDppMirror16>(nlo));
+          nhi = fmin(nhi, dpp_f64<kDppMirror16>(nhi));
+        }
+        for (int m = 16; m < g; m <<= 1) {
           nlo = fmax(nlo, __shfl_xor(nlo, m));
           nhi = fmin(nhi, __shfl_xor(nhi, m));
         }
@@ -546,9 +742,15 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
         lo = nlo;
         hi = nhi;
       }
-      if (gl == 0) lamv[i] = 0.5 * (lo + hi);
+      if (gl == 0) lamv[i] = (0.5 * (lo + hi)) * usc;
     }
-  }
+  };
+  if (2 * busy >= NT)
+    locate(std::integral_constant<int, 1>{});
+  else if (4 * busy >= NT)
+    locate(std::integral_constant<int, 2>{});
+  else
+    locate(std::integral_constant<int, 4>{});
   __syncthreads();
 
   SYEV_MARK(2);
@@ -564,7 +766,10 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
       tri_factor<NT>(n, D, ee, lamv[i], tiny, lu, nmax);
       double* y = Zt + slot;
       random_start(n, i, y, nv);
-      for (int it = 0; it < 3; ++it) {
+      // two solves from a random start: with lambda accurate to a few ulps of
+      // ||T|| the first leaves components outside the eigenvalue's cluster of
+      // relative size eps ||T|| / gap, the second squares that
+      for (int it = 0; it < 2; ++it) {
         tri_solve<NT>(n, lu, nmax, y, nv);
         normalize_serial(n, y, nv);
       }
@@ -643,6 +848,77 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   __syncthreads();
 
   SYEV_MARK(4);
+  if (NT <= 512 && lds_a) {
+    // ---- 4/5. Z = H_0 (H_1 ( ... (H_{n-3} Z_T))) --------------------------
+    // Each wanted vector is owned by 8 lanes, lane k holding positions
+    // k, k+8, ... in registers; a reflector costs those lanes one dot
+    // product (summed by three butterflies) and one axpy, with v read from
+    // LDS, so no barrier is needed.
+    constexpr int PL = (kLdsMax + 7) / 8;
+    const double* const AL = smem;
+    for (int i = tid; i < n; i += NT) sv[i] = (i < n - 2) ? tau[i] : 0.0;
+    for (int i = tid; i < n; i += NT) wq[i] = (zero_mat || i < n - nv) ? 0.0 : lamv[i];
+    __syncthreads();
+    const int k8 = tid & 7;
+    for (int slot0 = 0; slot0 < nv; slot0 += NT / 8) {
+      const int slot = slot0 + (tid >> 3);
+      const bool act = slot < nv;
+      double z[PL];
+#pragma unroll
+      for (int i = 0; i < PL; ++i) {
+        const int pos = k8 + 8 * i;
+        z[i] = (act && pos < n) ? Zt[(int64_t)pos * nv + slot] : 0.0;
+      }
+      // reflector j-1 is loaded while reflector j is applied
+      double vv[PL], tj = 0.0;
+#pragma unroll
+      for (int i = 0; i < PL; ++i) vv[i] = 0.0;
+      if (n >= 3) {
+        const double* v = AL + (int64_t)(n - 3) * ldA;
+        tj = sv[n - 3];
+#pragma unroll
+        for (int i = 0; i < PL; ++i) {
+          const int pos = k8 + 8 * i;
+          vv[i] = (pos >= n - 1 && pos < n) ? v[pos] : (pos == n - 2 ? 1.0 : 0.0);
+        }
+      }
+      for (int j = n - 3; j >= 0; --j) {
+        double vn[PL], tn = 0.0;
+        const int jn = j > 0 ? j - 1 : 0;
+        const double* v = AL + (int64_t)jn * ldA;
+#pragma unroll
+        for (int i = 0; i < PL; ++i) {
+          const int pos = k8 + 8 * i;
+          vn[i] = (pos >= jn + 2 && pos < n) ? v[pos] : (pos == jn + 1 ? 1.0 : 0.0);
+        }
+        tn = sv[jn];
+        if (tj != 0.0) {
+          double part = 0.0;
+#pragma unroll
+          for (int i = 0; i < PL; ++i) part += vv[i] * z[i];
+          part += dpp_f64<kDppXor1>(part);
+          part += dpp_f64<kDppXor2>(part);
+          part += dpp_f64<kDppMirror8>(part);
+          const double f = tj * part;
+#pragma unroll
+          for (int i = 0; i < PL; ++i) z[i] -= f * vv[i];
+        }
+#pragma unroll
+        for (int i = 0; i < PL; ++i) vv[i] = vn[i];
+        tj = tn;
+      }
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < PL; ++i) {
+          const int pos = k8 + 8 * i;
+          if (pos < n) Zq[pos + (int64_t)(n0 + slot) * ldz] = z[i];
+        }
+      }
+    }
+    SYEV_MARK(5);
+    SYEV_MARK(6);
+    return;
+  }
   // ---- 4. back-transformation ---------------------------------------------
   // Q = H_0 H_1 ... H_{n-3} is formed in place of the reflectors (backward
   // accumulation: Q_j = H_j Q_{j+1}, whose non-trivial block is rows and
@@ -697,7 +973,7 @@ hipError_t syev_launch_t(const SyevArgs* sarr, int64_t batch, int64_t n, const i
                          const double* A, int64_t lda, int64_t strideA, double* w, int64_t stridew,
                          double* Z, int64_t ldz, int64_t strideZ, int64_t nvec, double* work,
                          hipStream_t s) {
-  const bool lds_a = n <= kLdsMax;
+  const bool lds_a = n <= kLdsMax && NT <= 512;
   const size_t lds = (size_t)syev_lds_doubles(n, lds_a) * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {

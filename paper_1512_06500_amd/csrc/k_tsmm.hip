@@ -207,6 +207,7 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, int64_t bx, int by) {
   __syncthreads();
   const TV* V = (const TV*)a.V;
   TO* Out = (TO*)a.Out;
+  const double alpha = (a.alpha_p != nullptr) ? *a.alpha_p : a.alpha;
   for (int e = tid; e < R * NN_NB; e += 256) {
     const int rr = e % R, j = e / R;
     const int64_t row = bx * R + rr;
@@ -214,7 +215,7 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, int64_t bx, int by) {
     ACC sacc = ACC(0);
     for (int u = 0; u < G; ++u) sacc += red[(u * R + rr) * (NN_NB + 1) + j];
     double o = (double)sacc;
-    if (a.alpha != 0.0) o += a.alpha * to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]);
+    if (alpha != 0.0) o += alpha * to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]);
     const int64_t oi = a.out_row ? row * a.ldo + (j0 + j) : row + (int64_t)(j0 + j) * a.ldo;
     Out[oi] = from_f64<TO>(o);
   }
@@ -375,9 +376,9 @@ hipError_t launch_nn_multi(int count, const NnArgs* host, const NnArgs* dev, DT 
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
-                     hipStream_t s, bool out_row) {
+                     hipStream_t s, bool out_row, const double* alpha_p) {
   if (d <= 0 || nb <= 0) return hipSuccess;
-  NnArgs a{d, m, nb, lda, ldz, ldv, ldo, A, Z, alpha, V, Out, out_row ? 1 : 0, gate};
+  NnArgs a{d, m, nb, lda, ldz, ldv, ldo, A, Z, alpha, V, Out, out_row ? 1 : 0, gate, alpha_p};
   return launch_nn_multi(1, &a, nullptr, adt, vdt, odt, s);
 }
 
