@@ -119,7 +119,8 @@ def mixed_vs_f64(torch, eda, reps: int = 3) -> dict:
     H_W, H_B = h.scatter_factors(Xd, p.counts.tolist())
     out = {"workload": f"d={p.d}, k={p.k} x n_j={p.n // p.k} (n={p.n}), t={p.t}, "
                        f"block 8, tol {p.tol:g}"}
-    for tag, storage, basis in (("f64", "f64", "f64"), ("mixed", "bf16", "f32")):
+    for tag, storage, basis in (("f64", "f64", "f64"), ("mixed", "bf16", "f32"),
+                                ("fp8", "fp8", "f32")):
         def one():
             h.prepare(H_W, H_B, storage=storage)
             return h.solve(p.t, p.tol, block=8, seed=p.seed, krylov_dtype=basis)
@@ -140,6 +141,7 @@ def mixed_vs_f64(torch, eda, reps: int = 3) -> dict:
                     "lam_rel_err_max_over_floor": float(np.max(lam_err / np.maximum(
                         1e-6, g["pair_floor"])))}
     out["ratio_mixed_over_f64"] = out["mixed"]["solves_per_s"] / out["f64"]["solves_per_s"]
+    out["ratio_fp8_over_f64"] = out["fp8"]["solves_per_s"] / out["f64"]["solves_per_s"]
     h.close()
     return out
 

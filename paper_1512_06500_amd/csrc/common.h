@@ -48,6 +48,54 @@ template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) {
   return __float2bfloat16((float)x);
 }
 
+// FP8 E4M3 in the OCP layout (sign, 4 exponent bits with bias 7, 3 mantissa
+// bits; no infinities, S.1111.111 is NaN, largest finite 448).  Decoding is
+// exact; encoding rounds to nearest even and saturates at +-448.
+struct fp8e4m3 {
+  uint8_t b;
+};
+__host__ __device__ inline float fp8e4m3_decode(uint8_t b) {
+  const uint32_t s = (uint32_t)(b & 0x80u) << 24;
+  const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+  if (e == 0) {
+    const float v = (float)m * 0x1.0p-9f;  // subnormal: m/8 * 2^-6
+    return s ? -v : v;
+  }
+  if (e == 15 && m == 7) return __builtin_nanf("");
+  union {
+    uint32_t u;
+    float f;
+  } r;
+  r.u = s | ((e + 120u) << 23) | (m << 20);
+  return r.f;
+}
+__device__ inline uint8_t fp8e4m3_encode(double x) {
+  if (!(x == x)) return 0x7f;
+  const uint8_t s = (x < 0.0) ? 0x80 : 0x00;
+  const double a = fabs(x);
+  if (a >= 448.0) return s | 0x7e;
+  if (a < 0x1.0p-6) return s | (uint8_t)rint(a * 512.0);  // 8 is 2^-6 (exponent 1)
+  int e;
+  const double f = frexp(a, &e);                // a = f 2^e, f in [0.5, 1)
+  double q = rint((2.0 * f - 1.0) * 8.0);       // mantissa, 0 .. 8
+  int E = e + 6;                                // biased exponent of 2 f 2^(e-1)
+  if (q == 8.0) {
+    q = 0.0;
+    ++E;
+  }
+  if (E > 15 || (E == 15 && q > 6.0)) return s | 0x7e;
+  return s | (uint8_t)((E << 3) | (int)q);
+}
+template <> __device__ __forceinline__ double to_f64<fp8e4m3>(fp8e4m3 x) {
+  return (double)fp8e4m3_decode(x.b);
+}
+template <> __device__ __forceinline__ float to_acc<float, fp8e4m3>(fp8e4m3 x) {
+  return fp8e4m3_decode(x.b);
+}
+template <> __device__ __forceinline__ double to_acc<double, fp8e4m3>(fp8e4m3 x) {
+  return (double)fp8e4m3_decode(x.b);
+}
+
 // ---------------------------------------------------------------------------
 // Wave-level exchanges (wave64).
 // ---------------------------------------------------------------------------
@@ -87,7 +135,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Shapes are validated by the caller; each launcher documents what it needs.
 // ---------------------------------------------------------------------------
 
-enum class DT : int { F64 = 0, F32 = 1, BF16 = 2 };
+enum class DT : int { F64 = 0, F32 = 1, BF16 = 2, FP8 = 3 };
 
 // ---------------------------------------------------------------------------
 // Multi-problem launches.  Each kernel below exists once and takes its
@@ -104,6 +152,7 @@ struct TnArgs {      // part[(c * m + i) * nb + j] = sum over chunk c of A(r, i)
   const void* B;
   double* part;
   const int* gate;
+  const double* ascale;  // when not null, column i of A is scaled by ascale[i] (FP8 storage)
 };
 struct ReduceArgs {  // C = beta C + alpha sum_c part (col-major), Z = zalpha sum (row-major)
   int64_t chunks, m, nb, ldc, ldz;
@@ -123,6 +172,7 @@ struct NnArgs {      // Out = alpha V + A Z
   int out_row;
   const int* gate;
   const double* alpha_p;  // when not null, alpha is read from here (device)
+  const double* ascale;   // when not null, column i of A is scaled by ascale[i] (FP8 storage)
 };
 struct CholArgs {
   int64_t b, ldg, ldri, ldrp, ldro, m, ldhc;
@@ -247,6 +297,10 @@ hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int6
                           const int64_t* offsets, double* H_W, int64_t ldw, double* H_B,
                           int64_t ldb, hipStream_t s);
 // P[:, col0:col0+cols] = cast(H) for rows < d, zero for d <= row < ldp.
+// FP8 copy of the float64 matrix P64 (ld ldp, cols columns): scale[j] =
+// max |P64[:, j]| / 448, P8[r, j] = E4M3(P64[r, j] / scale[j]), rows d..ldp-1 zero.
+hipError_t launch_pack_fp8(int64_t d, int64_t ldp, int64_t cols, const double* P64,
+                           double* scale, void* P8, hipStream_t s);
 hipError_t launch_pack(int64_t d, int64_t ldp, int64_t cols, const double* H, int64_t ldh,
                        void* P, DT pdt, int64_t col0, hipStream_t s);
 // flag[0] |= 1 if any entry of the d x cols matrix is NaN/Inf.
@@ -307,7 +361,8 @@ hipError_t launch_restart_coupling(int64_t m, int64_t b, int64_t kk, const doubl
 int64_t tn_chunks(int64_t d, int64_t m, int64_t nb);
 hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT adt,
                              int64_t lda, const void* B, DT bdt, int64_t ldb, double* part,
-                             int64_t chunks, const int* gate, hipStream_t s);
+                             int64_t chunks, const int* gate, hipStream_t s,
+                             const double* ascale = nullptr);
 // C_col[i + j*ldc] = beta*C_col + alpha*sum_c part  (if C_col != null)
 // Z_row[i*ldz + j] = zalpha*sum_c part              (if Z_row != null)
 hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const double* part,
@@ -319,7 +374,8 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
-                     hipStream_t s, bool out_row = false, const double* alpha_p = nullptr);
+                     hipStream_t s, bool out_row = false, const double* alpha_p = nullptr,
+                     const double* ascale = nullptr);
 
 // k_gemm.hip ----------------------------------------------------------------
 // C (m x n) = alpha * op(A) * diag(dk) * op(B) + beta * C, float64, col-major.

@@ -88,8 +88,9 @@ eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double
   STCHK(ensure(h, h->part, (size_t)chunks * Nc * b * 8));
   STCHK(ensure(h, h->Ysm, (size_t)Nc * b * 8));
   STCHK(ensure(h, h->Zsm, (size_t)Nc * b * 8));
+  const double* sc = (pdt == DT::FP8) ? h->pscale.d() + c0 : nullptr;
   HIPCHK(launch_tn_partial(h->d, Nc, b, Pc, pdt, h->ldp, V, vdt, ldv, h->part.d(), chunks,
-                           nullptr, h->stream));
+                           nullptr, h->stream, sc));
   // Y = P_c^T V (row-major, leading dimension b), then Z = C Y (row-major) by
   // the same streaming kernel with C as the tall operand
   HIPCHK(launch_reduce_partials(chunks, Nc, b, h->part.d(), 0.0, 0.0, nullptr, 0, 1.0,
@@ -97,7 +98,7 @@ eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double
   HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, h->Ysm.d(), b, 0.0, nullptr, DT::F64, 0,
                    h->Zsm.d(), DT::F64, b, nullptr, h->stream, true));
   HIPCHK(launch_nn(h->d, Nc, b, Pc, pdt, h->ldp, h->Zsm.d(), b, alpha, V, vdt, ldv, Out, odt,
-                   ldo, nullptr, h->stream, false, alpha_p));
+                   ldo, nullptr, h->stream, false, alpha_p, sc));
   return EDA_OK;
 }
 
@@ -315,7 +316,7 @@ void eda_destroy(eda_handle h) {
                   &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part,
                   &h->Ysm, &h->Zsm, &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
-                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev};
+                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale};
     for (Buf* b : all) release(*b);
     for (auto& c : h->cores) release(c.buf);
     for (hipEvent_t e : h->op_ev) (void)hipEventDestroy(e);
@@ -382,8 +383,8 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
   if (n + k > 2048) return fail(h, EDA_ERR_ARG, "n+k=%lld exceeds 2048", (long long)(n + k));
   if (H_W == nullptr || H_B == nullptr) return fail(h, EDA_ERR_ARG, "null factor");
   if (ldw < d || ldb < d) return fail(h, EDA_ERR_ARG, "leading dimensions must be >= d");
-  if (storage != EDA_F64 && storage != EDA_F32 && storage != EDA_BF16)
-    return fail(h, EDA_ERR_ARG, "storage must be EDA_F64, EDA_F32 or EDA_BF16");
+  if (storage != EDA_F64 && storage != EDA_F32 && storage != EDA_BF16 && storage != EDA_FP8_E4M3)
+    return fail(h, EDA_ERR_ARG, "storage must be EDA_F64, EDA_F32, EDA_BF16 or EDA_FP8_E4M3");
   STCHK(need_device(h));
   STCHK(check_dev_ptr(h, H_W, "H_W"));
   STCHK(check_dev_ptr(h, H_B, "H_B"));
@@ -429,15 +430,22 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
 
   // a1: factor ingest, P = [H_W H_B] in storage precision, plus a float64
   // master when the storage is narrower (Gram, cores and refinement use it)
+  // (FP8: per-column scales from the master, then the scaled E4M3 copy)
   STCHK(ensure(h, h->P, (size_t)h->ldp * N * dsize(storage)));
-  HIPCHK(launch_pack(d, h->ldp, n, H_W, ldw, h->P.p, dt_of(storage), 0, h->stream));
-  HIPCHK(launch_pack(d, h->ldp, k, H_B, ldb, h->P.p, dt_of(storage), n, h->stream));
+  if (storage != EDA_FP8_E4M3) {
+    HIPCHK(launch_pack(d, h->ldp, n, H_W, ldw, h->P.p, dt_of(storage), 0, h->stream));
+    HIPCHK(launch_pack(d, h->ldp, k, H_B, ldb, h->P.p, dt_of(storage), n, h->stream));
+  }
   const void* Pm = h->P.p;
   if (storage != EDA_F64) {
     STCHK(ensure(h, h->P64, (size_t)h->ldp * N * 8));
     HIPCHK(launch_pack(d, h->ldp, n, H_W, ldw, h->P64.p, DT::F64, 0, h->stream));
     HIPCHK(launch_pack(d, h->ldp, k, H_B, ldb, h->P64.p, DT::F64, n, h->stream));
     Pm = h->P64.p;
+  }
+  if (storage == EDA_FP8_E4M3) {
+    STCHK(ensure(h, h->pscale, (size_t)N * 8));
+    HIPCHK(launch_pack_fp8(d, h->ldp, N, h->P64.d(), h->pscale.d(), h->P.p, h->stream));
   }
 
   // a2: Gram G = P^T P in float64 (from the float64 factors)

@@ -76,7 +76,8 @@ double unit_roundoff(DT t) {
   switch (t) {
     case DT::F64: return 0x1.0p-53;
     case DT::F32: return 0x1.0p-24;
-    default: return 0x1.0p-8;
+    case DT::BF16: return 0x1.0p-8;
+    default: return 0x1.0p-4;  // FP8 E4M3
   }
 }
 
@@ -405,7 +406,8 @@ eda_status m_expop(Engine& E, const std::vector<int>& ps, DT vdt, DT odt, F f) {
     const bool use64 = master && sb->storage != EDA_F64;
     const char* base = use64 ? sb->P64.c() : sb->P.c();
     const char* Pc = base + (size_t)s.c0 * sb->ldp * dt_size(pdt);
-    v.push_back(TnArgs{p.d, s.Nc, s.nb, sb->ldp, s.ldv, 0, Pc, s.V, p.part, nullptr});
+    const double* sc = (pdt == DT::FP8) ? sb->pscale.d() + s.c0 : nullptr;
+    v.push_back(TnArgs{p.d, s.Nc, s.nb, sb->ldp, s.ldv, 0, Pc, s.V, p.part, nullptr, sc});
     dmax = std::max(dmax, p.d);
     mmax = std::max(mmax, s.Nc);
   }
@@ -420,7 +422,7 @@ eda_status m_expop(Engine& E, const std::vector<int>& ps, DT vdt, DT odt, F f) {
     core.push_back(NnArgs{s.Nc, s.Nc, s.nb, s.ldc, s.nb, 0, s.nb, s.C, p.Ysm, 0.0, nullptr, p.Zsm,
                           1, nullptr});
     out.push_back(NnArgs{p.d, s.Nc, s.nb, p.sub->ldp, s.nb, s.ldv, s.ldo, v[q].A, p.Zsm, s.alpha,
-                         s.V, s.Out, 0, nullptr});
+                         s.V, s.Out, 0, nullptr, nullptr, v[q].ascale});
   }
   eda_handle h = E.h;
   hipStream_t st = h->stream;
@@ -633,8 +635,8 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
   if (o.resmode != EDA_RES_REL_THETA && o.resmode != EDA_RES_NORMWISE)
     return fail(h, EDA_ERR_ARG, "unknown residual mode");
   if (o.start_block != nullptr) return fail(h, EDA_ERR_ARG, "start_block is not used in batches");
-  if (storage != EDA_F64 && storage != EDA_F32 && storage != EDA_BF16)
-    return fail(h, EDA_ERR_ARG, "storage must be EDA_F64, EDA_F32 or EDA_BF16");
+  if (storage != EDA_F64 && storage != EDA_F32 && storage != EDA_BF16 && storage != EDA_FP8_E4M3)
+    return fail(h, EDA_ERR_ARG, "storage must be EDA_F64, EDA_F32, EDA_BF16 or EDA_FP8_E4M3");
   const int64_t b = o.block > 0 ? o.block : 8;
   if (b > 8) return fail(h, EDA_ERR_ARG, "block width must be in [1, 8]");
   if (o.max_basis > 0) return fail(h, EDA_ERR_ARG, "max_basis is chosen per problem in batches");

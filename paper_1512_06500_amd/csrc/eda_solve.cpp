@@ -29,7 +29,8 @@ double unit_roundoff(DT t) {
   switch (t) {
     case DT::F64: return 0x1.0p-53;
     case DT::F32: return 0x1.0p-24;
-    default: return 0x1.0p-8;  // bfloat16
+    case DT::BF16: return 0x1.0p-8;
+    default: return 0x1.0p-4;  // FP8 E4M3
   }
 }
 

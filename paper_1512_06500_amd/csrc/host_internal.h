@@ -58,6 +58,7 @@ struct eda_handle_s {
   eda::Buf G, eigW, eigZ, nsbuf, Gh, Gm, GBs, CM, CA, T1, T2, T3, T4, fw, polyws, normbuf;
   double shiftB = 0.0, alphaB = 1.0;
   eda::Buf alphaB_dev;  // alphaB on the device, read by captured steps
+  eda::Buf pscale;      // FP8 storage: column j of P is pscale[j] times its FP8 copy
   double normW = 0.0;   // ||H_W^T H_W||_1
   bool w_eig = false;   // eigenpairs of H_W^T H_W available
   std::vector<double> hwW, hwB;
@@ -99,11 +100,15 @@ void release(Buf& b);
 eda_status need_device(eda_handle h);
 eda_status check_dev_ptr(eda_handle h, const void* p, const char* name);
 
-inline size_t dsize(eda_dtype t) { return t == EDA_F64 ? 8 : (t == EDA_F32 ? 4 : 2); }
-inline DT dt_of(eda_dtype t) {
-  return t == EDA_F64 ? DT::F64 : (t == EDA_F32 ? DT::F32 : DT::BF16);
+inline size_t dsize(eda_dtype t) {
+  return t == EDA_F64 ? 8 : (t == EDA_F32 ? 4 : (t == EDA_BF16 ? 2 : 1));
 }
-inline size_t dt_size(DT t) { return t == DT::F64 ? 8 : (t == DT::F32 ? 4 : 2); }
+inline DT dt_of(eda_dtype t) {
+  return t == EDA_F64 ? DT::F64 : (t == EDA_F32 ? DT::F32 : (t == EDA_BF16 ? DT::BF16 : DT::FP8));
+}
+inline size_t dt_size(DT t) {
+  return t == DT::F64 ? 8 : (t == DT::F32 ? 4 : (t == DT::BF16 ? 2 : 1));
+}
 inline int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
 
 // eda_prepare in two halves: prepare_begin validates and enqueues every

@@ -55,6 +55,34 @@ __global__ __launch_bounds__(256) void pack_kernel(int64_t d, int64_t ldp, const
   P[r + (col0 + c) * ldp] = from_f64<TP>(v);
 }
 
+// FP8 storage: per-column scale max_r |P[r, j]| / 448 (1 for a zero
+// column), so that the largest entry of every column maps to the largest
+// finite E4M3 value.  One workgroup per column.
+__global__ __launch_bounds__(256) void fp8_scale_kernel(int64_t d, const double* __restrict__ P,
+                                                        int64_t ldp, double* __restrict__ scale) {
+  __shared__ double red[4];
+  const int64_t c = blockIdx.x;
+  double mx = 0.0;
+  for (int64_t r = threadIdx.x; r < d; r += 256) mx = fmax(mx, fabs(P[r + c * ldp]));
+  for (int m = 32; m >= 1; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    scale[c] = (t > 0.0) ? t / 448.0 : 1.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void pack_fp8_kernel(int64_t d, int64_t ldp,
+                                                       const double* __restrict__ P,
+                                                       const double* __restrict__ scale,
+                                                       uint8_t* __restrict__ P8) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= ldp) return;
+  P8[r + c * ldp] = (r < d) ? fp8e4m3_encode(P[r + c * ldp] / scale[c]) : (uint8_t)0;
+}
+
 __global__ __launch_bounds__(256) void nonfinite_kernel(int64_t d, int64_t cols, const double* __restrict__ H,
                                                         int64_t ldh, int* flag) {
   const int64_t total = d * cols;
@@ -353,6 +381,15 @@ hipError_t launch_pack(int64_t d, int64_t ldp, int64_t cols, const double* H, in
     hipLaunchKernelGGL(pack_kernel<float>, g, dim3(256), 0, s, d, ldp, H, ldh, (float*)P, col0);
   else
     hipLaunchKernelGGL(pack_kernel<bf16_t>, g, dim3(256), 0, s, d, ldp, H, ldh, (bf16_t*)P, col0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_fp8(int64_t d, int64_t ldp, int64_t cols, const double* P64,
+                           double* scale, void* P8, hipStream_t s) {
+  if (cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fp8_scale_kernel, dim3((unsigned)cols), dim3(256), 0, s, d, P64, ldp, scale);
+  hipLaunchKernelGGL(pack_fp8_kernel, dim3(nblk(ldp), (unsigned)cols), dim3(256), 0, s, d, ldp,
+                     P64, (const double*)scale, (uint8_t*)P8);
   return hipGetLastError();
 }
 

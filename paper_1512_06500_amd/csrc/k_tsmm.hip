@@ -68,11 +68,24 @@ __device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yt, 
     const int64_t rs = rb + 16 * q;
     double av[16], bv[16];
     if (rb + 64 <= r1) {
+      if constexpr (sizeof(TA) == 1) {  // FP8: the 16 bytes of a lane in one load
+        const uint4 w = *(const uint4*)((const uint8_t*)ap + rs);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const double x = ld64(ap + rs + e), y = ld64(bp + rs + e);
-        av[e] = cok ? x : 0.0;
-        bv[e] = bok ? y : 0.0;
+        for (int e = 0; e < 16; ++e)
+          av[e] = cok ? (double)fp8e4m3_decode((uint8_t)(ws[e >> 2] >> (8 * (e & 3)))) : 0.0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const double y = ld64(bp + rs + e);
+          bv[e] = bok ? y : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const double x = ld64(ap + rs + e), y = ld64(bp + rs + e);
+          av[e] = cok ? x : 0.0;
+          bv[e] = bok ? y : 0.0;
+        }
       }
     } else {
 #pragma unroll
@@ -98,7 +111,8 @@ __device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yt, 
     for (int v = 0; v < 4; ++v) {
       const int ii = 4 * v + ib;
       if (c0 + ii < m && j0 + jj < nb)
-        a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] = acc[v];
+        a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] =
+            (a.ascale != nullptr) ? acc[v] * a.ascale[c0 + ii] : acc[v];
     }
   }
   __syncthreads();  // red may be reused by a caller that loops over work items
@@ -180,7 +194,9 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, int64_t bx, int by) {
     __syncthreads();
     for (int e = tid; e < tn * NN_NB; e += 256) {
       const int i = e / NN_NB, j = e - i * NN_NB;
-      zs[e] = (j0 + j < nb) ? (ACC)a.Z[(int64_t)(t0 + i) * a.ldz + j0 + j] : ACC(0);
+      double z = (j0 + j < nb) ? a.Z[(int64_t)(t0 + i) * a.ldz + j0 + j] : 0.0;
+      if (a.ascale != nullptr) z *= a.ascale[t0 + i];
+      zs[e] = (ACC)z;
     }
     __syncthreads();
     int i = g;
@@ -323,14 +339,17 @@ hipError_t launch_tn_multi(int count, const TnArgs* host, const TnArgs* dev, DT 
   if (adt == DT::F64 && bdt == DT::F32) return tn_launch_t<double, float>(count, host, dev, s);
   if (adt == DT::BF16 && bdt == DT::F32) return tn_launch_t<bf, float>(count, host, dev, s);
   if (adt == DT::BF16 && bdt == DT::F64) return tn_launch_t<bf, double>(count, host, dev, s);
+  if (adt == DT::FP8 && bdt == DT::F32) return tn_launch_t<fp8e4m3, float>(count, host, dev, s);
+  if (adt == DT::FP8 && bdt == DT::F64) return tn_launch_t<fp8e4m3, double>(count, host, dev, s);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT adt,
                              int64_t lda, const void* B, DT bdt, int64_t ldb, double* part,
-                             int64_t chunks, const int* gate, hipStream_t s) {
+                             int64_t chunks, const int* gate, hipStream_t s,
+                             const double* ascale) {
   if (d <= 0 || m <= 0 || nb <= 0) return hipSuccess;
-  TnArgs a{d, m, nb, lda, ldb, chunks, A, B, part, gate};
+  TnArgs a{d, m, nb, lda, ldb, chunks, A, B, part, gate, ascale};
   return launch_tn_multi(1, &a, nullptr, adt, bdt, s);
 }
 
@@ -369,6 +388,8 @@ hipError_t launch_nn_multi(int count, const NnArgs* host, const NnArgs* dev, DT 
   NN_CASE(F64, F32, F32, double, float, float, double)
   NN_CASE(BF16, F32, F32, bf, float, float, float)
   NN_CASE(BF16, F64, F64, bf, double, double, double)
+  NN_CASE(FP8, F32, F32, fp8e4m3, float, float, float)
+  NN_CASE(FP8, F64, F64, fp8e4m3, double, double, double)
 #undef NN_CASE
   return hipErrorInvalidValue;
 }
@@ -376,9 +397,11 @@ hipError_t launch_nn_multi(int count, const NnArgs* host, const NnArgs* dev, DT 
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
-                     hipStream_t s, bool out_row, const double* alpha_p) {
+                     hipStream_t s, bool out_row, const double* alpha_p,
+                     const double* ascale) {
   if (d <= 0 || nb <= 0) return hipSuccess;
-  NnArgs a{d, m, nb, lda, ldz, ldv, ldo, A, Z, alpha, V, Out, out_row ? 1 : 0, gate, alpha_p};
+  NnArgs a{d, m, nb, lda, ldz, ldv, ldo, A, Z, alpha, V, Out, out_row ? 1 : 0, gate, alpha_p,
+           ascale};
   return launch_nn_multi(1, &a, nullptr, adt, vdt, odt, s);
 }
 

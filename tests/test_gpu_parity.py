@@ -214,6 +214,77 @@ def test_expmv_narrow_storage_c1(torch, eda, c1, storage, u):
     h.close()
 
 
+def _e4m3_factor(rng, d, cols, exps):
+    """Columns of exact E4M3 values times 2^exps[j], each holding +-448 once:
+    the per-column FP8 scale is then exactly 2^exps[j] and storage is lossless."""
+    from oracle.fp8 import e4m3_values
+    vals = e4m3_values()
+    H = rng.choice(vals, size=(d, cols)) * rng.choice([-1.0, 1.0], size=(d, cols))
+    H[rng.integers(0, d, size=cols), np.arange(cols)] = 448.0
+    return H * 2.0 ** np.asarray(exps, dtype=np.float64)
+
+
+def test_expmv_fp8_lossless_factor(torch, eda):
+    """FP8 storage of a factor whose entries are exact E4M3 values times a
+    power-of-two per column: the stored copy is exact, so both streaming
+    passes must reproduce the float64 exponential action to float64
+    accuracy.  Pins the decode, the per-column scales and where the passes
+    apply them."""
+    log("expmv FP8 storage, lossless factor")
+    rng = np.random.default_rng(11)
+    d, n, k = 700, 24, 5
+    H_W = _e4m3_factor(rng, d, n, rng.integers(-11, -8, size=n)) * 0.25
+    H_B = _e4m3_factor(rng, d, k, rng.integers(-11, -9, size=k))
+    h = eda.Handle()
+    h.prepare(dev(torch, H_W), dev(torch, H_B), storage="fp8")
+    V = rng.standard_normal((d, 8))
+    for vdt in ("f64", "f32"):
+        for which, H, c in (("W", H_W, -0.5), ("W", H_W, -1.0), ("B", H_B, 1.0)):
+            E = O.expm_sym(H @ H.T, c)
+            Vd = dev(torch, V)
+            if vdt == "f32":
+                Vd = Vd.float()
+            out, s = h.expmv(which, c, Vd, vdtype=vdt)
+            got = host(out).astype(np.float64) * np.exp(s)
+            ref = E @ (V.astype(np.float32).astype(np.float64) if vdt == "f32" else V)
+            err = rel_op_err(got, ref, np.linalg.norm(E, 2), V)
+            bound = 1e-13 if vdt == "f64" else 64 * 2.0 ** -24
+            log(f"  {which} c={c} vdtype={vdt} err={err:.2e} bound={bound:.1e}")
+            assert err <= bound
+    h.close()
+
+
+def test_expmv_fp8_rounding_c1(torch, eda, c1):
+    """FP8 storage of the C1 factors.  The two streaming passes read the
+    E4M3 copy (scaled per column, rounded to nearest even) while the core
+    phi_c(H^T H) comes from the float64 Gram, so the product equals
+    V + Hq G_c Hq^T V with Hq the reference rounding of H and G_c from the
+    SVD of H: compared at float64 accuracy, which pins the encoding of every
+    entry that feeds the product."""
+    from oracle.fp8 import fp8_columns
+    log("expmv C1 with FP8 storage against the reference rounding")
+    h = eda.Handle()
+    h.prepare(dev(torch, c1.H_W), dev(torch, c1.H_B), storage="fp8")
+    rng = np.random.default_rng(6)
+    V = rng.standard_normal((c1.d, 8))
+    for which, H, c in (("W", c1.H_W, -0.5), ("B", c1.H_B, 1.0)):
+        Hq, _ = fp8_columns(H)
+        _, sig, Vt = np.linalg.svd(H, full_matrices=False)
+        lam = sig ** 2
+        phi = np.where(lam > 0, np.expm1(c * lam) / np.where(lam > 0, lam, 1.0), c)
+        G = Vt.T @ (phi[:, None] * Vt)
+        ref = V + Hq @ (G @ (Hq.T @ V))
+        out, s = h.expmv(which, c, dev(torch, V))
+        got = host(out) * np.exp(s)
+        scale = np.linalg.norm(ref) + np.linalg.norm(V)
+        err = np.linalg.norm(got - ref) / scale
+        E = O.expm_sym(H @ H.T, c)
+        drift = rel_op_err(got, E @ V, np.linalg.norm(E, 2), V)
+        log(f"  {which} c={c} err vs rounded factor={err:.2e}  vs exact exp={drift:.2e}")
+        assert err <= 1e-12
+    h.close()
+
+
 @pytest.fixture(params=["poly", "eig"])
 def wcore(request, monkeypatch):
     """W-cores by the matrix polynomial (default) or by eig(H_W^T H_W)."""
@@ -396,7 +467,8 @@ def errors(res, ref):
 
 
 @pytest.mark.parametrize("storage,basis", [("f64", "f32"), ("f32", "f64"), ("f32", "f32"),
-                                           ("bf16", "f64"), ("bf16", "f32")])
+                                           ("bf16", "f64"), ("bf16", "f32"), ("fp8", "f32"),
+                                           ("fp8", "f64")])
 def test_mixed_refined_c2(torch, eda, c2, storage, basis):
     """The refined result meets the float64 bounds of the float64 solve.
     Before refinement (max_refine < 0) the errors are only reported: the paper

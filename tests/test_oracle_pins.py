@@ -392,3 +392,70 @@ def test_golden_values_match_oracle(name):
     # and the top of the stored values within Theorem 3.2's bounds in reduced form:
     # lam_1 <= exp(mu_1 - nu_d) = exp(sigma_B,max^2) since nu_d = 0 for d > n
     assert g["lam"][0] <= np.exp(g["sigma2_B_max"]) * (1 + 1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Reference E4M3 rounding of the FP8 storage tests (format facts, not paper)
+# ----------------------------------------------------------------------------
+
+def test_e4m3_codes():
+    """Known codes of the OCP E4M3 format: 1.0 = 0x38, 1.5 = 0x3c, the
+    largest finite 448 = 0x7e, the smallest normal 2^-6 = 0x08, the smallest
+    subnormal 2^-9 = 0x01, NaN = 0x7f, and 0x80 = -0."""
+    from oracle.fp8 import e4m3_decode, e4m3_values
+    assert e4m3_decode(0x38) == 1.0
+    assert e4m3_decode(0x3C) == 1.5
+    assert e4m3_decode(0x7E) == 448.0
+    assert e4m3_decode(0x08) == 2.0 ** -6
+    assert e4m3_decode(0x01) == 2.0 ** -9
+    assert np.isnan(e4m3_decode(0x7F))
+    assert e4m3_decode(0x80) == 0.0 and np.signbit(e4m3_decode(0x80))
+    v = e4m3_values()
+    assert len(v) == 127 and np.all(np.diff(v) > 0)          # monotone, no duplicates
+    # spacing: 2^-9 below 2^-5, then 8 values per binade
+    assert np.allclose(np.diff(v[:16]), 2.0 ** -9)
+    assert np.all(np.diff(v[v >= 1.0][:8]) == 0.125)
+
+
+def test_e4m3_rounding():
+    """Nearest with ties to even, saturation, subnormals, sign symmetry."""
+    from oracle.fp8 import e4m3_round
+    cases = {
+        1.0 + 1.0 / 16: 1.0,        # tie between 1.0 (m=0) and 1.125 (m=1): even
+        1.0 + 3.0 / 16: 1.25,       # tie between 1.125 (m=1) and 1.25 (m=2): even
+        1.0 + 1.0 / 15: 1.125,      # above the tie
+        500.0: 448.0,               # saturates
+        460.0: 448.0,
+        2.0 ** -10: 0.0,            # half the smallest subnormal: tie to 0
+        3 * 2.0 ** -10: 2.0 ** -8,  # 1.5 quanta: tie to 2 quanta
+        0.3: 0.3125,                # 0.3 = 1.2 * 2^-2 -> 1.25 * 2^-2
+    }
+    for x, want in cases.items():
+        assert e4m3_round(np.array([x]))[0] == want, x
+        assert e4m3_round(np.array([-x]))[0] == -want, -x
+    x = RNG.standard_normal(2000) * 10
+    r = e4m3_round(x)
+    small = np.abs(x) < 2.0 ** -6
+    rel_err = np.abs(r - x)[~small] / np.abs(x)[~small]
+    assert rel_err.max() <= 2.0 ** -4 * (1 + 1e-12)           # half an ulp of 3 bits
+    assert np.abs(r - x)[small].max(initial=0.0) <= 2.0 ** -10
+
+
+def test_fp8_columns_scale():
+    """Each column's largest entry maps to 448 exactly; zero columns keep
+    scale 1; exact E4M3 multiples of a power of two survive unchanged."""
+    from oracle.fp8 import fp8_columns, e4m3_values
+    P = RNG.standard_normal((50, 4))
+    P[:, 2] = 0.0
+    Q, s = fp8_columns(P)
+    assert s[2] == 1.0 and np.all(Q[:, 2] == 0.0)
+    for j in (0, 1, 3):
+        i = np.argmax(np.abs(P[:, j]))
+        assert np.isclose(abs(P[i, j]) / s[j], 448.0)
+        assert Q[i, j] == P[i, j] * (1 + 0.0) or np.isclose(Q[i, j], P[i, j], rtol=1e-15)
+    vals = e4m3_values()
+    E = RNG.choice(vals, size=(30, 3)) * RNG.choice([-1.0, 1.0], size=(30, 3))
+    E[0, :] = 448.0
+    E *= 2.0 ** np.array([-3, 0, 5])
+    Q, s = fp8_columns(E)
+    assert np.array_equal(Q, E) and np.array_equal(s, 2.0 ** np.array([-3, 0, 5]))
