@@ -129,6 +129,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// Standard normal sample for element e of a seeded stream: two SplitMix64
+// outputs (Steele, Lea, Flood 2014) turned into one Box-Muller deviate.
+__device__ __forceinline__ double masked_gauss(uint64_t seed, int64_t e) {
+  uint64_t z1 = (seed ^ 0x2545f4914f6cdd1dull) + 2ull * (uint64_t)e * 0x9e3779b97f4a7c15ull;
+  uint64_t z2 = z1 + 0x9e3779b97f4a7c15ull;
+  z1 = (z1 ^ (z1 >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z1 = (z1 ^ (z1 >> 27)) * 0x94d049bb133111ebull;
+  z1 ^= z1 >> 31;
+  z2 = (z2 ^ (z2 >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z2 = (z2 ^ (z2 >> 27)) * 0x94d049bb133111ebull;
+  z2 ^= z2 >> 31;
+  const double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (implemented in the .hip files, called by the host sources).
 // All take the stream last and return hipError_t of the launch.
@@ -173,6 +189,8 @@ struct NnArgs {      // Out = alpha V + A Z
   const int* gate;
   const double* alpha_p;  // when not null, alpha is read from here (device)
   const double* ascale;   // when not null, column i of A is scaled by ascale[i] (FP8 storage)
+  const int* mask;        // when not null, output columns j with mask[j] != 0 get
+  uint64_t seed;          //   masked_gauss(seed, j * d + row) instead of the product
 };
 struct CholArgs {
   int64_t b, ldg, ldri, ldrp, ldro, m, ldhc;
@@ -184,6 +202,8 @@ struct CholArgs {
   double ratio;
   int* flag;
   const int* gate;
+  const double* part;  // when not null, G = sum over `chunks` tn partials (layout of tn, m = nb = b)
+  int64_t chunks;
 };
 struct PcholArgs {
   int64_t b, ldg, m, ldhc, ldz, ldr;
@@ -195,6 +215,8 @@ struct PcholArgs {
   double* R;
   int* mask;
   int* flag;
+  const double* part;  // when not null, G = sum over `chunks` tn partials (layout of tn, m = nb = b)
+  int64_t chunks;
 };
 struct MaskedRandnArgs {  // Q[:, j] = seeded Gaussian where mask[j] != 0
   int64_t d, b, ldq;
@@ -375,7 +397,8 @@ hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, in
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
                      hipStream_t s, bool out_row = false, const double* alpha_p = nullptr,
-                     const double* ascale = nullptr);
+                     const double* ascale = nullptr, const int* mask = nullptr,
+                     uint64_t seed = 0);
 
 // k_gemm.hip ----------------------------------------------------------------
 // C (m x n) = alpha * op(A) * diag(dk) * op(B) + beta * C, float64, col-major.
@@ -395,17 +418,21 @@ hipError_t launch_gram_reduce(int64_t N, int64_t chunks, const double* part, dou
 // if Rout != null, Rout = R * Rprev (or R when Rprev is null), col-major.
 // If hcol != null, sets *flag = 1 when some column kept less than `ratio` of
 // its norm through the projection (hcol: m x b projection coefficients).
+// With part != null, G is the fixed-order sum of the `chunks` tn partials
+// part[(c*b + i)*b + j] (G and ldg unused).
 hipError_t launch_chol(int64_t b, const double* G, int64_t ldg, double* Rinv, int64_t ldri,
                        const double* Rprev, int64_t ldrp, double* Rout, int64_t ldro,
                        const double* hcol, int64_t m, int64_t ldhc, double ratio, int* flag,
-                       const int* gate, hipStream_t s);
+                       const int* gate, hipStream_t s, const double* part = nullptr,
+                       int64_t chunks = 0);
 
 // Rank-revealing pivoted Cholesky of a Lanczos block (b <= 64); see k_chol.hip.
 // With `equil`, the block is first scaled to unit column norms (hcol ignored)
 // and the scaling is folded back into Z and R.
 hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
                         int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
-                        double* R, int64_t ldr, int* mask, int* flag, hipStream_t s);
+                        double* R, int64_t ldr, int* mask, int* flag, hipStream_t s,
+                        const double* part = nullptr, int64_t chunks = 0);
 // Q[:, j] = seeded Gaussian for the columns with mask[j] != 0.
 hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
                                     void* Q, DT qdt, int64_t ldq, hipStream_t s);

@@ -54,12 +54,17 @@ eda_status cholqr_pass(eda_handle h, int64_t d, int64_t cols, const void* X, DT 
   STCHK(ensure(h, h->part, (size_t)chunks * cols * cols * 8));
   STCHK(ensure(h, h->Gs, (size_t)cols * cols * 8));
   STCHK(ensure(h, h->Rinv, (size_t)cols * cols * 8));
+  // for a narrow block the Cholesky kernel sums the chunk partials of
+  // X^T X itself; wider ones use the parallel reduction first
+  const bool fused = cols <= 16;
   HIPCHK(launch_tn_partial(d, cols, cols, X, xdt, ldx, X, xdt, ldx, h->part.d(), chunks, gate,
                            h->stream));
-  HIPCHK(launch_reduce_partials(chunks, cols, cols, h->part.d(), 1.0, 0.0, h->Gs.d(), cols, 0.0,
-                                nullptr, 0, gate, h->stream));
+  if (!fused)
+    HIPCHK(launch_reduce_partials(chunks, cols, cols, h->part.d(), 1.0, 0.0, h->Gs.d(), cols,
+                                  0.0, nullptr, 0, gate, h->stream));
   HIPCHK(launch_chol(cols, h->Gs.d(), cols, h->Rinv.d(), cols, Rprev, cols, Rout, ldro, hcol,
-                     mrows, ldhc, 1e-4, flag, gate, h->stream));
+                     mrows, ldhc, 1e-4, flag, gate, h->stream, fused ? h->part.d() : nullptr,
+                     chunks));
   HIPCHK(launch_nn(d, cols, cols, X, xdt, ldx, h->Rinv.d(), cols, 0.0, nullptr, xdt, ldx, Xout,
                    xdt, ldxo, gate, h->stream));
   return EDA_OK;
@@ -115,16 +120,20 @@ eda_status lanczos_orth(Solver& S, int64_t m, bool repair) {
   char* Qn = S.Qc(m + b);
   {
     const int64_t chunks = tn_chunks(d, b, b);
+    // (pchol sums the chunk partials; the product writes the random
+    // replacement columns)
     HIPCHK(launch_tn_partial(d, b, b, W, qdt, ldq, W, qdt, ldq, h->part.d(), chunks, nullptr,
                              h->stream));
-    HIPCHK(launch_reduce_partials(chunks, b, b, h->part.d(), 1.0, 0.0, h->Gs.d(), b, 0.0, nullptr,
-                                  0, nullptr, h->stream));
+    const bool fused = b <= 16;
+    if (!fused)
+      HIPCHK(launch_reduce_partials(chunks, b, b, h->part.d(), 1.0, 0.0, h->Gs.d(), b, 0.0,
+                                    nullptr, 0, nullptr, h->stream));
     HIPCHK(launch_pchol(b, h->Gs.d(), b, Hcol, m + b, ldh, 1e-13, 1e-4, false, h->Rinv.d(), b,
-                        h->R1.d(), b, h->mask.i(), flags, h->stream));
+                        h->R1.d(), b, h->mask.i(), flags, h->stream,
+                        fused ? h->part.d() : nullptr, chunks));
     HIPCHK(launch_nn(d, b, b, W, qdt, ldq, h->Rinv.d(), b, 0.0, nullptr, qdt, ldq, Qn, qdt, ldq,
-                     nullptr, h->stream));
-    HIPCHK(launch_fill_masked_randn(d, b, h->mask.i(), 0x5eed0000ull + (uint64_t)m, Qn, qdt, ldq,
-                                    h->stream));
+                     nullptr, h->stream, false, nullptr, nullptr, h->mask.i(),
+                     0x5eed0000ull + (uint64_t)m));
   }
   STCHK(cholqr_pass(h, d, b, Qn, qdt, ldq, Qn, ldq, h->R1.d(), H + (m + b) + m * ldh, ldh,
                     nullptr, 0, 0, nullptr, flags));
@@ -703,14 +712,16 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
       const int64_t chunks = tn_chunks(d, wz, wz);
       HIPCHK(launch_tn_partial(d, wz, wz, Z, DT::F64, ldq, Z, DT::F64, ldq, h->part.d(), chunks,
                                nullptr, s));
-      HIPCHK(launch_reduce_partials(chunks, wz, wz, h->part.d(), 1.0, 0.0, h->Gs.d(), wz, 0.0,
-                                    nullptr, 0, nullptr, s));
+      const bool fused = wz <= 16;
+      if (!fused)
+        HIPCHK(launch_reduce_partials(chunks, wz, wz, h->part.d(), 1.0, 0.0, h->Gs.d(), wz, 0.0,
+                                      nullptr, 0, nullptr, s));
       HIPCHK(launch_pchol(wz, h->Gs.d(), wz, nullptr, 0, 0, 1e-10, 1e-4, true, h->Rinv.d(), wz,
-                          h->R1.d(), wz, h->mask.i(), nullptr, s));
+                          h->R1.d(), wz, h->mask.i(), nullptr, s, fused ? h->part.d() : nullptr,
+                          chunks));
       HIPCHK(launch_nn(d, wz, wz, Z, DT::F64, ldq, h->Rinv.d(), wz, 0.0, nullptr, DT::F64, ldq, Zt,
-                       DT::F64, ldq, nullptr, s));
-      HIPCHK(launch_fill_masked_randn(d, wz, h->mask.i(), 0x7e41e000ull + (uint64_t)passes, Zt,
-                                      DT::F64, ldq, s));
+                       DT::F64, ldq, nullptr, s, false, nullptr, nullptr, h->mask.i(),
+                       0x7e41e000ull + (uint64_t)passes));
       STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
       STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
       STCHK(cholqr_pass(h, d, wz, Zt, DT::F64, ldq, Z, ldq, nullptr, nullptr, 0, nullptr, 0, 0,

@@ -18,6 +18,90 @@ namespace {
 
 constexpr int CH_MAX = 128;
 
+// Orders the LDS accesses of one wave (whose LDS instructions execute in
+// program order) without a workgroup barrier.
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// (largest value, smallest index among equals) over the 64 lanes; the same
+// result in every lane
+__device__ __forceinline__ void amax_take(double& v, int& i, double ov, int oi) {
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  amax_take(v, i, dpp_f64<kDppXor1>(v), dpp_i32<kDppXor1>(i));
+  amax_take(v, i, dpp_f64<kDppXor2>(v), dpp_i32<kDppXor2>(i));
+  amax_take(v, i, dpp_f64<kDppMirror8>(v), dpp_i32<kDppMirror8>(i));
+  amax_take(v, i, dpp_f64<kDppMirror16>(v), dpp_i32<kDppMirror16>(i));
+  double bv = readlane_f64(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
+  for (int row = 16; row < 64; row += 16)
+    amax_take(bv, bi, readlane_f64(v, row), __builtin_amdgcn_readlane(i, row));
+  v = bv;
+  i = bi;
+}
+
+// The b x b Gram matrix into LDS (A[r + c*ld], both triangles): copied from
+// G, or summed from `chunks` tn partials part[(ch*b + r)*b + c] in chunk
+// order.  When b*b is below the thread count, H threads share an entry
+// (chunks h, h+H, ...) and their sums are added in order of h through hs
+// (blockDim.x doubles).  Ends with a barrier.
+__device__ void gram_to_lds(const double* __restrict__ G, int64_t ldg,
+                            const double* __restrict__ part, int64_t chunks, int b,
+                            double* A, int ld, double* hs) {
+  const int nt = blockDim.x, tid = threadIdx.x, bb = b * b;
+  if (part == nullptr) {
+    for (int e = tid; e < bb; e += nt) {
+      const int c = e / b, r = e - c * b;
+      A[r + c * ld] = G[r + (int64_t)c * ldg];
+    }
+    __syncthreads();
+    return;
+  }
+  // H threads per entry, each summing chunks h, h+H, ... in batches of 16
+  // loads issued together
+  int H = 1;
+  while (2 * H * bb <= nt) H *= 2;
+  for (int e0 = 0; e0 < bb; e0 += nt / H) {
+    const int o = e0 + tid % (nt / H), h = tid / (nt / H);
+    double s = 0.0;
+    if (o < bb && h < H) {
+      const double* p = part + o;
+      for (int64_t base = h; base < chunks; base += 16 * (int64_t)H) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int64_t ch = base + (int64_t)u * H;
+          v[u] = (ch < chunks) ? p[ch * bb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) s += (v[u] + v[u + 1]) + (v[u + 2] + v[u + 3]);
+      }
+    }
+    if (H > 1) {
+      hs[tid] = s;
+      __syncthreads();
+      if (h == 0 && o < bb) {
+        double t = hs[tid];
+        for (int q = 1; q < H; ++q) t += hs[q * (nt / H) + tid];
+        s = t;
+      }
+    }
+    if (h == 0 && o < bb) {
+      const int r = o / b, c = o - r * b;
+      A[r + c * ld] = s;
+    }
+    if (H > 1) __syncthreads();
+  }
+  __syncthreads();
+}
+
 // LDS use of chol_kernel (one b x b array, ld = CH_MAX + 1):
 //   during the factorisation the lower triangle holds the trailing matrix
 //   and the strict upper triangle receives R = L^T row by row (diagonal in
@@ -37,16 +121,20 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
   const double ratio = a.ratio;
   int* flag = a.flag;
   __shared__ double L[CH_MAX * (CH_MAX + 1)];
-  __shared__ double rd[CH_MAX], xd[CH_MAX], hn[CH_MAX], d0[CH_MAX];
+  __shared__ double rd[CH_MAX], xd[CH_MAX], hn[CH_MAX], d0[CH_MAX], hs[256];
   __shared__ int sflag;
   const int ld = CH_MAX + 1;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   if (tid == 0) sflag = 0;
-  for (int e = tid; e < b * b; e += blockDim.x) {
-    const int c = e / b, r = e - c * b;
-    if (r >= c) L[r + c * ld] = G[r + c * ldg];
-    if (r == c) d0[r] = G[r + c * ldg];
-  }
+  // Rprev (b <= 64) staged in the unused second half of L
+  double* RP = (Rprev != nullptr && b <= 64) ? L + 64 * ld : nullptr;
+  if (RP != nullptr)
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int c = e / b, r = e - c * b;
+      RP[r + c * 64] = Rprev[r + c * ldrp];
+    }
+  gram_to_lds(G, ldg, a.part, a.chunks, b, L, ld, hs);
+  for (int r = tid; r < b; r += blockDim.x) d0[r] = L[r + r * ld];
   // squared norms of the projection coefficients, one wave per column
   if (hcol != nullptr)
     for (int c = wid; c < b; c += nw) {
@@ -59,31 +147,67 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
       if (lane == 0) hn[c] = h2;
     }
   __syncthreads();
-  for (int j = 0; j < b; ++j) {
-    double p = L[j + j * ld];
-    const double floor_ = 1e-28 * fabs(d0[j]) + 1e-300;
-    if (!(p > floor_)) {  // also catches NaN
-      p = floor_;
-      if (tid == 0) sflag = 1;
+  const bool one_wave = b <= 16;  // then wave 0 factorises and inverts alone, without barriers
+  if (one_wave) {
+    if (wid == 0) {
+      const int r = lane;
+      const bool live = r < b;
+      for (int j = 0; j < b; ++j) {
+        double p = L[j + j * ld];
+        const double floor_ = 1e-28 * fabs(d0[j]) + 1e-300;
+        if (!(p > floor_)) {  // also catches NaN
+          p = floor_;
+          if (lane == 0) sflag = 1;
+        }
+        const double piv = sqrt(p), inv = 1.0 / piv;
+        if (lane == 0) rd[j] = piv;
+        const double lr = (r > j && live) ? L[r + j * ld] * inv : 0.0;
+        if (r > j && live) L[j + r * ld] = lr;
+        for (int c = j + 1; c < b; ++c) {
+          const double lc = readlane_f64(lr, c);
+          if (r >= c && live) L[r + c * ld] -= lr * lc;
+        }
+        wave_fence();
+      }
     }
-    const double piv = sqrt(p), inv = 1.0 / piv;
-    if (tid == 0) rd[j] = piv;
-    for (int i = j + 1 + tid; i < b; i += blockDim.x) L[j + i * ld] = L[i + j * ld] * inv;
-    for (int c = j + 1 + wid; c < b; c += nw) {
-      const double lc = L[c + j * ld] * inv;
-      for (int r = c + lane; r < b; r += 64) L[r + c * ld] -= (L[r + j * ld] * inv) * lc;
+  } else {
+    for (int j = 0; j < b; ++j) {
+      double p = L[j + j * ld];
+      const double floor_ = 1e-28 * fabs(d0[j]) + 1e-300;
+      if (!(p > floor_)) {  // also catches NaN
+        p = floor_;
+        if (tid == 0) sflag = 1;
+      }
+      const double piv = sqrt(p), inv = 1.0 / piv;
+      if (tid == 0) rd[j] = piv;
+      for (int i = j + 1 + tid; i < b; i += blockDim.x) L[j + i * ld] = L[i + j * ld] * inv;
+      for (int c = j + 1 + wid; c < b; c += nw) {
+        const double lc = L[c + j * ld] * inv;
+        for (int r = c + lane; r < b; r += 64) L[r + c * ld] -= (L[r + j * ld] * inv) * lc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // X = R^{-1} by back substitution, one thread per column c:
-  //   X[i][c] = (delta_ic - sum_{q=i+1..c} R[i][q] X[q][c]) / R[i][i]
-  for (int c = tid; c < b; c += blockDim.x) {
-    const double xcc = 1.0 / rd[c];
-    xd[c] = xcc;
-    for (int i = c - 1; i >= 0; --i) {
-      double s = -L[i + c * ld] * xcc;
-      for (int q = i + 1; q < c; ++q) s -= L[i + q * ld] * L[c + q * ld];
-      L[c + i * ld] = s / rd[i];
+  // X = R^{-1}, rows i = b-1 .. 0 in turn, the entries of a row in parallel:
+  //   X[i][i] = 1 / R[i][i],  X[i][c] = -(sum_{q=i+1..c} R[i][q] X[q][c]) / R[i][i]
+  if (!one_wave || wid == 0) {
+    const int nth = one_wave ? 64 : (int)blockDim.x;
+    const int me = one_wave ? lane : tid;
+    for (int i = b - 1; i >= 0; --i) {
+      const double ri = rd[i];
+      for (int c = i + me; c < b; c += nth) {
+        if (c == i) {
+          xd[i] = 1.0 / ri;
+        } else {
+          double s = L[i + c * ld] * xd[c];
+          for (int q = i + 1; q < c; ++q) s += L[i + q * ld] * L[c + q * ld];
+          L[c + i * ld] = -s / ri;
+        }
+      }
+      if (one_wave)
+        wave_fence();
+      else
+        __syncthreads();
     }
   }
   __syncthreads();
@@ -99,8 +223,13 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
         s = (r < c) ? L[r + c * ld] : (r == c ? rd[r] : 0.0);
       } else {
         // (R * Rprev)[r, c] = sum_{q >= r} R[r, q] Rprev[q, c]  (R upper, Rprev general)
-        s = rd[r] * Rprev[r + c * ldrp];
-        for (int q = r + 1; q < b; ++q) s += L[r + q * ld] * Rprev[q + c * ldrp];
+        if (RP != nullptr) {
+          s = rd[r] * RP[r + c * 64];
+          for (int q = r + 1; q < b; ++q) s += L[r + q * ld] * RP[q + c * 64];
+        } else {
+          s = rd[r] * Rprev[r + c * ldrp];
+          for (int q = r + 1; q < b; ++q) s += L[r + q * ld] * Rprev[q + c * ldrp];
+        }
       }
       Rout[r + c * ldro] = s;
     }
@@ -123,7 +252,7 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
 // Outputs: Z (row-major, W Z = [Q_1, 0]), R (col-major, W = [Q_1 Q_2] R with
 // rows >= r zero), mask[j] = 1 for deflated output columns j >= r, and
 // *flag = 1 if a column was deflated or kept less than `ratio` of its norm.
-__global__ __launch_bounds__(64) void pchol_kernel(const PcholArgs* __restrict__ arr, PcholArgs one) {
+__global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict__ arr, PcholArgs one) {
   const PcholArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int b = (int)a.b;
   const double* __restrict__ G = a.G;
@@ -140,18 +269,22 @@ __global__ __launch_bounds__(64) void pchol_kernel(const PcholArgs* __restrict__
   __shared__ double nrm0[PB];
   __shared__ double dsc[PB];  // column scaling (1 unless equilibrated)
   __shared__ int perm[PB];
-  __shared__ int s_rank, s_q, s_flag;
+  __shared__ int s_rank, s_flag;
+  __shared__ double gd[PB], hs[256];
   const int ld = PB + 1;
   const int tid = threadIdx.x;
+  gram_to_lds(G, ldg, a.part, a.chunks, b, A, ld, hs);
   if (tid < b) {
-    const double g = G[tid + tid * ldg];
+    const double g = A[tid + tid * ld];
+    gd[tid] = g;
     dsc[tid] = (equil && g > 0.0) ? 1.0 / sqrt(g) : 1.0;
   }
   __syncthreads();
-  for (int e = tid; e < b * b; e += blockDim.x) {
-    const int c = e / b, r = e - c * b;
-    A[r + c * ld] = G[r + c * ldg] * dsc[r] * dsc[c];
-  }
+  if (equil)
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int c = e / b, r = e - c * b;
+      A[r + c * ld] *= dsc[r] * dsc[c];
+    }
   // squared norms of the projection coefficients: the wave sums column c
   // and lane c keeps it
   double h2 = 0.0;
@@ -174,7 +307,7 @@ __global__ __launch_bounds__(64) void pchol_kernel(const PcholArgs* __restrict__
       }
     }
   if (tid < b) {
-    nrm0[tid] = G[tid + tid * ldg] * dsc[tid] * dsc[tid] + h2;
+    nrm0[tid] = gd[tid] * dsc[tid] * dsc[tid] + h2;
     perm[tid] = tid;
   }
   if (tid == 0) {
@@ -185,53 +318,56 @@ __global__ __launch_bounds__(64) void pchol_kernel(const PcholArgs* __restrict__
   double scale2 = 0.0;
   for (int j = 0; j < b; ++j) scale2 = fmax(scale2, nrm0[j]);
   const double thr = tau * tau * scale2;
-  for (int j = 0; j < b; ++j) {
-    if (tid == 0) {
-      int q = j;
-      double best = A[j + j * ld];
-      for (int i = j + 1; i < b; ++i)
-        if (A[i + i * ld] > best) {
-          best = A[i + i * ld];
-          q = i;
+  // The factorisation runs in wave 0 alone (b <= 64: lane r owns row and
+  // column r), so its steps need no workgroup barrier.
+  if (tid < 64) {
+    const int r = tid;
+    const bool live = r < b;
+    int pr = r;  // perm entry of position r
+    int rank = b;
+    for (int j = 0; j < b; ++j) {
+      double v = (live && r >= j) ? A[r + r * ld] : -INFINITY;
+      int vi = r;
+      wave_argmax(v, vi);
+      if (!(v > thr)) {  // every remaining pivot is negligible: deflate them
+        rank = j;
+        break;
+      }
+      const int q = vi;
+      if (q != j) {
+        const int pj = __builtin_amdgcn_readlane(pr, j), pq = __builtin_amdgcn_readlane(pr, q);
+        if (r == j) pr = pq;
+        if (r == q) pr = pj;
+        if (live) {  // swap rows j and q
+          const double t = A[j + r * ld];
+          A[j + r * ld] = A[q + r * ld];
+          A[q + r * ld] = t;
         }
-      s_q = q;
-      if (!(best > thr)) {
-        s_rank = j;  // every remaining pivot is negligible: deflate them
-      } else {
-        const int t = perm[j];
-        perm[j] = perm[q];
-        perm[q] = t;
+        wave_fence();
+        if (live) {  // swap columns j and q
+          const double t = A[r + j * ld];
+          A[r + j * ld] = A[r + q * ld];
+          A[r + q * ld] = t;
+        }
+        wave_fence();
       }
-    }
-    __syncthreads();
-    if (s_rank == j) break;
-    const int q = s_q;
-    if (q != j) {
-      if (tid < b) {  // swap rows j and q
-        const double t = A[j + tid * ld];
-        A[j + tid * ld] = A[q + tid * ld];
-        A[q + tid * ld] = t;
+      const double piv = sqrt(A[j + j * ld]);
+      const double lr = (live && r > j) ? A[r + j * ld] / piv : 0.0;
+      wave_fence();
+      if (r == j) A[j + j * ld] = piv;
+      if (live && r > j) A[r + j * ld] = lr;
+      // update the whole (symmetric) trailing block: later pivot swaps read
+      // both of its triangles
+      for (int c = j + 1; c < b; ++c) {
+        const double lc = readlane_f64(lr, c);
+        if (live && r > j) A[r + c * ld] -= lr * lc;
       }
-      __syncthreads();
-      if (tid < b) {  // swap columns j and q
-        const double t = A[tid + j * ld];
-        A[tid + j * ld] = A[tid + q * ld];
-        A[tid + q * ld] = t;
-      }
-      __syncthreads();
+      wave_fence();
     }
-    if (tid == 0) A[j + j * ld] = sqrt(A[j + j * ld]);
-    __syncthreads();
-    if (tid > j && tid < b) A[tid + j * ld] /= A[j + j * ld];
-    __syncthreads();
-    // update the whole (symmetric) trailing block: later pivot swaps read
-    // both of its triangles
-    for (int c = j + 1; c < b; ++c) {
-      const double ac = A[c + j * ld];
-      if (tid > j && tid < b) A[tid + c * ld] -= A[tid + j * ld] * ac;
-    }
-    __syncthreads();
+    if (live) perm[r] = pr;
+    if (r == 0) s_rank = rank;
   }
+  __syncthreads();
   const int rk = s_rank;
   __shared__ double xd[PB];
   __shared__ int iperm[PB];
@@ -287,17 +423,7 @@ __global__ __launch_bounds__(256) void fill_masked_randn_kernel(const MaskedRand
   if (e >= d * b) return;
   const int64_t c = e / d, r = e - c * d;
   if (mask[c] == 0) return;
-  uint64_t z1 = (seed ^ 0x2545f4914f6cdd1dull) + 2ull * (uint64_t)e * 0x9e3779b97f4a7c15ull;
-  uint64_t z2 = z1 + 0x9e3779b97f4a7c15ull;
-  z1 = (z1 ^ (z1 >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z1 = (z1 ^ (z1 >> 27)) * 0x94d049bb133111ebull;
-  z1 ^= z1 >> 31;
-  z2 = (z2 ^ (z2 >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z2 = (z2 ^ (z2 >> 27)) * 0x94d049bb133111ebull;
-  z2 ^= z2 >> 31;
-  const double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;
-  const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
-  Q[r + c * ldq] = from_f64<T>(sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2));
+  Q[r + c * ldq] = from_f64<T>(masked_gauss(seed, e));
 }
 
 }  // namespace
@@ -310,14 +436,16 @@ hipError_t launch_pchol_multi(int count, const PcholArgs* host, const PcholArgs*
   const PcholArgs* arr;
   PcholArgs one;
   pick(count, host, dev, &arr, &one);
-  hipLaunchKernelGGL(pchol_kernel, dim3(1, 1, (unsigned)count), dim3(64), 0, s, arr, one);
+  hipLaunchKernelGGL(pchol_kernel, dim3(1, 1, (unsigned)count), dim3(256), 0, s, arr, one);
   return hipGetLastError();
 }
 
 hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
                         int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
-                        double* R, int64_t ldr, int* mask, int* flag, hipStream_t s) {
-  PcholArgs a{b, ldg, m, ldhc, ldz, ldr, G, hcol, tau, ratio, equil ? 1 : 0, Z, R, mask, flag};
+                        double* R, int64_t ldr, int* mask, int* flag, hipStream_t s,
+                        const double* part, int64_t chunks) {
+  PcholArgs a{b, ldg, m, ldhc, ldz, ldr, G, hcol, tau, ratio, equil ? 1 : 0, Z, R, mask, flag,
+              part, chunks};
   return launch_pchol_multi(1, &a, nullptr, s);
 }
 
@@ -359,8 +487,9 @@ hipError_t launch_chol_multi(int count, const CholArgs* host, const CholArgs* de
 hipError_t launch_chol(int64_t b, const double* G, int64_t ldg, double* Rinv, int64_t ldri,
                        const double* Rprev, int64_t ldrp, double* Rout, int64_t ldro,
                        const double* hcol, int64_t m, int64_t ldhc, double ratio, int* flag,
-                       const int* gate, hipStream_t s) {
-  CholArgs a{b, ldg, ldri, ldrp, ldro, m, ldhc, G, Rinv, Rprev, Rout, hcol, ratio, flag, gate};
+                       const int* gate, hipStream_t s, const double* part, int64_t chunks) {
+  CholArgs a{b, ldg, ldri, ldrp, ldro, m, ldhc, G, Rinv, Rprev, Rout, hcol, ratio, flag, gate,
+             part, chunks};
   return launch_chol_multi(1, &a, nullptr, s);
 }
 

@@ -232,6 +232,7 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, int64_t bx, int by) {
     for (int u = 0; u < G; ++u) sacc += red[(u * R + rr) * (NN_NB + 1) + j];
     double o = (double)sacc;
     if (alpha != 0.0) o += alpha * to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]);
+    if (a.mask != nullptr && a.mask[j0 + j] != 0) o = masked_gauss(a.seed, (int64_t)(j0 + j) * d + row);
     const int64_t oi = a.out_row ? row * a.ldo + (j0 + j) : row + (int64_t)(j0 + j) * a.ldo;
     Out[oi] = from_f64<TO>(o);
   }
@@ -398,10 +399,10 @@ hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, in
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,
                      hipStream_t s, bool out_row, const double* alpha_p,
-                     const double* ascale) {
+                     const double* ascale, const int* mask, uint64_t seed) {
   if (d <= 0 || nb <= 0) return hipSuccess;
   NnArgs a{d, m, nb, lda, ldz, ldv, ldo, A, Z, alpha, V, Out, out_row ? 1 : 0, gate, alpha_p,
-           ascale};
+           ascale, mask, seed};
   return launch_nn_multi(1, &a, nullptr, adt, vdt, odt, s);
 }
 
