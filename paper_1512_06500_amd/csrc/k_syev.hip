@@ -6,7 +6,7 @@
 //
 //   1. Householder reduction to tridiagonal form T = Q^T A Q.  The working
 //      matrix lives in LDS when it fits (n <= kLdsMax; two barriers per
-//      reflector), else in global memory.
+//      reflector), else in global memory (three barriers per reflector).
 //   2. Eigenvalues of T by Sturm-count multisection: groups of g threads
 //      probe 4 g points per step; the count uses the three-term recurrence
 //      of the leading principal minors (no divisions) on T scaled by a power
@@ -16,9 +16,9 @@
 //      overflow-safe rescaling), then orthonormalisation inside clusters of
 //      close eigenvalues (Cholesky QR twice by the whole workgroup, or
 //      modified Gram-Schmidt for very large clusters).
-//   4. Back-transformation by the stored reflectors: applied straight to the
-//      eigenvectors of T held in registers (LDS path), or by forming Q
-//      (global path).
+//   4. Back-transformation by the stored reflectors, applied straight to the
+//      eigenvectors of T: held in registers (LDS path) or in LDS panels with
+//      the reflectors staged in blocks (global path).
 #include <cstdio>
 #include <type_traits>
 
@@ -30,7 +30,7 @@ namespace {
 
 constexpr int SYEV_NMAX = 2048;
 constexpr int kLdsMax = 112;      // largest n whose working matrix is kept in LDS
-constexpr int kStage = 8192;      // doubles of LDS for staged reflectors (global path)
+constexpr int kLdsDoubles = 160 * 1024 / 8;  // all of a CU's LDS (global path)
 constexpr int kClusterMax = 64;   // clusters up to this size use Cholesky QR
 
 template <int NT>
@@ -342,9 +342,9 @@ __host__ __device__ inline int64_t syev_work_doubles(int64_t nmax, int nt) {
 
 // LDS layout (doubles):
 //   LDS path:    A [n (n+1)] | sv [n] | sw [n] | red [16] | Gc [kClusterMax^2]
-//   global path: sv [n] | sw [n] | stage [kStage] | red [16]   (Gc = stage)
+//   global path: sv [n] | sw [n] | red [32] | stage [rest of the 160 KB]  (Gc = stage)
 __host__ __device__ inline int64_t syev_lds_doubles(int64_t n, bool lds_a) {
-  return lds_a ? n * (n + 1) + 2 * n + 16 + kClusterMax * kClusterMax : 2 * n + kStage + 16;
+  return lds_a ? n * (n + 1) + 2 * n + 32 + kClusterMax * kClusterMax : kLdsDoubles;
 }
 
 // Optional per-phase cycle counters (matrix 0 of each launch), for profiling.
@@ -416,15 +416,15 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
     sv = smem + nmax * (nmax + 1);
     sw = sv + nmax;
     red = sw + nmax;
-    Gc = red + 16;
+    Gc = red + 32;
     stage = nullptr;
   } else {
     A = gA;
     ldA = nmax;
     sv = smem;
     sw = sv + nmax;
-    stage = sw + nmax;
-    red = stage + kStage;
+    red = sw + nmax;
+    stage = red + 32;
     Gc = stage;
   }
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -586,62 +586,135 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
       __syncthreads();
     }
     if (n >= 3 && tid == 0) AL[(n - 1) + (int64_t)(n - 3) * ldA] *= scale_prev;
-  } else
-  for (int j = 0; j < n - 2; ++j) {
-    const int m1 = n - j - 1;
-    double* col = A + (int64_t)j * ldA;
-    double s = 0.0;
-    for (int r = j + 2 + tid; r < n; r += NT) s += col[r] * col[r];
-    s = blk_sum<NT>(s, red);
-    const double alpha = col[j + 1];
-    double beta, tv, scale;
-    if (s == 0.0) {
-      tv = 0.0;
-      beta = alpha;
-      scale = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + s), alpha);
-      tv = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+  } else {
+    // Working matrix in global memory (L2-resident at these sizes), three
+    // barriers per reflector.  v lives in LDS (sv); wave w forms the entries
+    // p_r = (A v)_r of the rows r = j+1+w, j+1+w+NW, ... (lanes over the
+    // column of A that equals row r), keeping p in sw and its share of
+    // v^T A v in dw; the rank-2 update then takes w_c = tau p_c - K v_c on
+    // the fly, waves over columns and lanes over rows, and wave 0 sums the
+    // next column's norm while updating it.
+    double* const AG = gA;
+    double* dw = red + 2;  // NW <= 16 partials of v^T A v (red holds 16 + 2 doubles)
+    double* cn = red;
+    if (wid == 0) {
+      double s0 = 0.0;
+      for (int r = 2 + lane; r < n; r += 64) s0 += AG[r] * AG[r];
+      s0 = wave_sum(s0);
+      if (lane == 0) cn[0] = s0;
     }
-    for (int r = j + 1 + tid; r < n; r += NT) sv[r] = (r == j + 1) ? 1.0 : col[r] * scale;
     __syncthreads();
-    for (int r = j + 2 + tid; r < n; r += NT) col[r] = sv[r];
-    if (tid == 0) {
-      dd[j] = A[j + (int64_t)j * ldA];
-      ee[j] = beta;
-      tau[j] = tv;
-    }
-    if (tv == 0.0) {
-      __syncthreads();
-      continue;
-    }
-    // p = tau * A22 v (A22 symmetric: column r equals row r)
-    if (lds_a) {
-      for (int r = j + 1 + tid; r < n; r += NT)
-        sw[r] = tv * dot_pipe<DU>(A + (int64_t)r * ldA + j + 1, 1, sv + j + 1, 1, n - j - 1);
-    } else {
-      for (int r = j + 1 + wid; r < n; r += NW) {
-        const double* ac = A + (int64_t)r * ldA;
-        double acc = 0.0;
-        for (int c = j + 1 + lane; c < n; c += 64) acc += ac[c] * sv[c];
-        acc = wave_sum(acc);
-        if (lane == 0) sw[r] = tv * acc;
+    for (int j = 0; j < n - 2; ++j) {
+      double* col = AG + (int64_t)j * ldA;
+      const double s = cn[j & 1];
+      const double alpha = col[j + 1];
+      double beta, tv, scale;
+      if (s == 0.0) {
+        tv = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        tv = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
       }
+      if (tid == 0) {
+        dd[j] = col[j];
+        ee[j] = beta;
+        tau[j] = tv;
+      }
+      if (tv == 0.0) {
+        if (wid == 0) {
+          const double* c1 = AG + (int64_t)(j + 1) * ldA;
+          double s1 = 0.0;
+          for (int r = j + 3 + lane; r < n; r += 64) s1 += c1[r] * c1[r];
+          s1 = wave_sum(s1);
+          if (lane == 0) cn[(j + 1) & 1] = s1;
+        }
+        __syncthreads();
+        continue;
+      }
+      for (int r = j + 1 + tid; r < n; r += NT) {
+        const double v = (r == j + 1) ? 1.0 : col[r] * scale;
+        sv[r] = v;
+        if (r >= j + 2) col[r] = v;  // reflector j, kept for the back-transformation
+      }
+      __syncthreads();
+      // four rows per pass, their loads issued together
+      double dpart = 0.0;
+      for (int r0 = j + 1 + wid; r0 < n; r0 += 4 * NW) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = j + 1 + lane; c < n; c += 64) {
+          const double vc = sv[c];
+          double x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * NW;
+            x[u] = (r < n) ? AG[c + (int64_t)r * ldA] : 0.0;  // column r = row r
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] += x[u] * vc;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + u * NW;
+          const double p = wave_sum(acc[u]);
+          if (r < n) {
+            dpart += sv[r] * p;
+            if (lane == 0) sw[r] = p;
+          }
+        }
+      }
+      if (lane == 0) dw[wid] = dpart;
+      __syncthreads();
+      double vav = 0.0;
+      for (int w = 0; w < NW; ++w) vav += dw[w];
+      const double K = 0.5 * tv * tv * vav;
+      // four columns per pass; each lane loads up to four of its rows of
+      // them before storing any
+      for (int c0 = j + 1 + wid; c0 < n; c0 += 4 * NW) {
+        double vc[4], wc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u * NW;
+          vc[u] = (c < n) ? sv[c] : 0.0;
+          wc[u] = (c < n) ? tv * sw[c] - K * vc[u] : 0.0;
+        }
+        double nrm = 0.0;
+        for (int rb = j + 1 + lane; rb < n; rb += 256) {
+          double x[4][4], vr[4], wr[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = rb + 64 * q;
+            vr[q] = (r < n) ? sv[r] : 0.0;
+            wr[q] = (r < n) ? tv * sw[r] - K * vr[q] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int c = c0 + u * NW;
+              x[q][u] = (r < n && c < n) ? AG[r + (int64_t)c * ldA] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = rb + 64 * q;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int c = c0 + u * NW;
+              if (r < n && c < n) {
+                const double y = x[q][u] - (vr[q] * wc[u] + wr[q] * vc[u]);
+                AG[r + (int64_t)c * ldA] = y;
+                if (u == 0 && c == j + 1 && r >= j + 3) nrm += y * y;
+              }
+            }
+          }
+        }
+        if (c0 == j + 1) {  // wave 0: the next column, rows j+3 .. n-1
+          nrm = wave_sum(nrm);
+          if (lane == 0) cn[(j + 1) & 1] = nrm;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    double kk = 0.0;
-    for (int r = j + 1 + tid; r < n; r += NT) kk += sw[r] * sv[r];
-    kk = blk_sum<NT>(kk, red);
-    const double K = 0.5 * tv * kk;
-    for (int r = j + 1 + tid; r < n; r += NT) sw[r] -= K * sv[r];
-    __syncthreads();
-    for (int c = j + 1 + wid; c < n; c += NW) {
-      const double svc = sv[c], swc = sw[c];
-      for (int r = j + 1 + lane; r < n; r += 64)
-        A[r + (int64_t)c * ldA] -= sv[r] * swc + sw[r] * svc;
-    }
-    __syncthreads();
   }
   if (tid == 0) {
     if (n >= 2) {
@@ -919,51 +992,66 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
     SYEV_MARK(6);
     return;
   }
-  // ---- 4. back-transformation ---------------------------------------------
-  // Q = H_0 H_1 ... H_{n-3} is formed in place of the reflectors (backward
-  // accumulation: Q_j = H_j Q_{j+1}, whose non-trivial block is rows and
-  // columns >= j+1; reflector j sits in column j, outside that block), each
-  // reflector applied by the whole workgroup.  Then Z = Q Z_T.
-  if (tid == 0) A[(n - 1) + (int64_t)(n - 1) * ldA] = 1.0;
-  for (int j = n - 3; j >= 0; --j) {
-    for (int e = tid; e < n - j - 2; e += NT) {
-      A[(j + 1) + (int64_t)(j + 2 + e) * ldA] = 0.0;
-      A[(j + 2 + e) + (int64_t)(j + 1) * ldA] = 0.0;
-    }
-    if (tid == 0) A[(j + 1) + (int64_t)(j + 1) * ldA] = 1.0;
-    __syncthreads();
-    const double tj = tau[j];
-    if (tj != 0.0) {
-      const double* v = A + (int64_t)j * ldA;  // v[j+1] = 1 implicit, v[r] for r > j+1
-      for (int c = j + 1 + tid; c < n; c += NT) {
-        const double* qc = A + (int64_t)c * ldA;
-        sw[c] = tj * (qc[j + 1] + dot_pipe<DU>(v + j + 2, 1, qc + j + 2, 1, n - j - 2));
+  {
+    // ---- 4/5 (global path). Z = H_0 (H_1 ( ... (H_{n-3} Z_T))) on panels of
+    // the wanted vectors held in LDS, with blocks of RB reflectors staged in
+    // LDS (one barrier per block).  A vector is owned by g lanes of one wave
+    // (lane k: positions k, k+g, ...), so applying a reflector needs only an
+    // in-wave reduction and an in-order LDS update.
+    const int64_t stage_d = kLdsDoubles - 2 * nmax - 32;
+    const int RB = (int)std::min<int64_t>(16, std::max<int64_t>(1, stage_d / (4 * (int64_t)n)));
+    double* vb = stage;             // RB x n
+    double* zp = stage + RB * n;    // nvp x n
+    const int nvp = (int)std::min<int64_t>(nv, (stage_d - RB * (int64_t)n) / n);
+    for (int i = tid; i < n; i += NT) wq[i] = (zero_mat || i < n - nv) ? 0.0 : lamv[i];
+    for (int slot0 = 0; slot0 < nv; slot0 += nvp) {
+      const int cnt = std::min(nvp, nv - slot0);
+      for (int e = tid; e < cnt * n; e += NT) {
+        const int sl = e / n, pos = e - sl * n;
+        zp[e] = Zt[(int64_t)pos * nv + slot0 + sl];
       }
-      __syncthreads();
-      for (int c = j + 1 + wid; c < n; c += NW) {
-        const double swc = sw[c];
-        for (int r = j + 1 + lane; r < n; r += 64) {
-          const double vr = (r == j + 1) ? 1.0 : v[r];
-          A[r + (int64_t)c * ldA] -= vr * swc;
+      int g = 64;
+      while (g > 1 && g * cnt > NT) g >>= 1;
+      const int sl = tid / g, k = tid % g;
+      for (int jb = n - 3; jb >= 0; jb -= RB) {
+        const int j0 = jb - RB + 1 > 0 ? jb - RB + 1 : 0;
+        __syncthreads();  // the previous block is no longer read
+        for (int e = tid; e < (jb - j0 + 1) * n; e += NT) {
+          const int q = e / n, pos = e - q * n, j = j0 + q;
+          vb[e] = (pos < j + 1) ? 0.0 : (pos == j + 1 ? 1.0 : gA[pos + (int64_t)j * ldA]);
+        }
+        __syncthreads();
+        if (sl < cnt) {
+          double* z = zp + (int64_t)sl * n;
+          for (int j = jb; j >= j0; --j) {
+            const double tj = tau[j];
+            if (tj == 0.0) continue;
+            const double* v = vb + (int64_t)(j - j0) * n;
+            double part = 0.0;
+            for (int pos = j + 1 + k; pos < n; pos += g) part += v[pos] * z[pos];
+            if (g >= 2) part += dpp_f64<kDppXor1>(part);
+            if (g >= 4) part += dpp_f64<kDppXor2>(part);
+            if (g >= 8) part += dpp_f64<kDppMirror8>(part);
+            if (g >= 16) part += dpp_f64<kDppMirror16>(part);
+            if (g >= 32) part += __shfl_xor(part, 16);
+            if (g >= 64) part += __shfl_xor(part, 32);
+            const double f = tj * part;
+            for (int pos = j + 1 + k; pos < n; pos += g) z[pos] -= f * v[pos];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          }
         }
       }
       __syncthreads();
+      for (int e = tid; e < cnt * n; e += NT) {
+        const int s2 = e / n, pos = e - s2 * n;
+        Zq[pos + (int64_t)(n0 + slot0 + s2) * ldz] = zp[e];
+      }
+      __syncthreads();
     }
+    SYEV_MARK(5);
+    SYEV_MARK(6);
+    return;
   }
-  for (int e = tid; e < n - 1; e += NT) {
-    A[(int64_t)(e + 1) * ldA] = 0.0;  // row 0
-    A[e + 1] = 0.0;                   // column 0
-  }
-  if (tid == 0) A[0] = 1.0;
-  __syncthreads();
-
-  SYEV_MARK(5);
-  // ---- 5. outputs: eigenvalues, Z = Q Z_T ---------------------------------
-  for (int i = tid; i < n; i += NT) wq[i] = (zero_mat || i < n - nv) ? 0.0 : lamv[i];
-  for (int slot = wid; slot < nv; slot += NW)
-    for (int pos = lane; pos < n; pos += 64)
-      Zq[pos + (int64_t)(n0 + slot) * ldz] = dot_pipe<DU>(A + pos, ldA, Zt + slot, nv, n);
-  SYEV_MARK(6);
 }
 
 bool syev_timing = false;
@@ -1010,11 +1098,12 @@ hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A,
                        int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
                        int64_t strideZ, int64_t nvec, double* work, hipStream_t s) {
   if (n < 1 || n > SYEV_NMAX || batch < 1) return hipErrorInvalidValue;
-  // workgroup size by measurement: 256 threads up to n = 48, 512 up to 256
+  // workgroup size by measurement: 256 threads up to n = 48, 512 while the
+  // matrix fits in LDS, 1024 for the global-memory path
   if (n <= 48)
     return syev_launch_t<256>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
                               nvec, work, s);
-  if (n <= 256)
+  if (n <= kLdsMax)
     return syev_launch_t<512>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
                               nvec, work, s);
   return syev_launch_t<1024>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
@@ -1039,7 +1128,7 @@ hipError_t launch_syev_multi(int count, const SyevArgs* host, const SyevArgs* de
   if (nmax <= 48)
     return syev_launch_t<256>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
                               0, nullptr, s);
-  if (nmax <= 256)
+  if (nmax <= kLdsMax)
     return syev_launch_t<512>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
                               0, nullptr, s);
   return syev_launch_t<1024>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
