@@ -202,6 +202,19 @@ eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* 
                      double* ritz, double* ritz_log, double* X, int64_t ldx,
                      double* resid, eda_info* info);
 
+/* Reduced direct solve of eq. (1.7): the same outputs as eda_solve, computed
+ * without iteration.  Both exponentials are the identity plus a term in
+ * span P (Theorem 3.1), so e^{-s} M restricted to span P is the r x r
+ * matrix K = e^{-s} I + F^T C F (r = rank P; F from the eigendecomposition
+ * of the Gram matrix P^T P, C the core of the product e^{-s} M): one dense
+ * eigensolve of size n + k, one of size r, small GEMMs and three streaming
+ * passes.  Uses the float64 factors of the preparation.  resid[i] is
+ * ||e^{-s} M y_i - theta_i y_i|| / theta_i (one more product).  Requires
+ * 1 <= t <= min(128, rank P), t < d.  info: iters = 0; t_krylov_ms holds the
+ * time of the whole solve.  Synchronises. */
+eda_status eda_solve_direct(eda_handle h, int32_t t, double* ritz, double* ritz_log, double* X,
+                            int64_t ldx, double* resid, eda_info* info);
+
 /* One problem of a batch (eda_solve_batched).  H_W, H_B, X: device;
  * ritz, ritz_log, resid: host arrays of t entries. */
 typedef struct {

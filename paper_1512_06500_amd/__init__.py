@@ -35,7 +35,8 @@ _DTYPES = {"f64": EDA_F64, "f32": EDA_F32, "bf16": EDA_BF16, "fp8": EDA_FP8_E4M3
 
 EXPORTED_SYMBOLS = [
     "eda_create", "eda_destroy", "eda_strerror", "eda_last_error", "eda_scatter_factors",
-    "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_solve_batched", "eda_gram",
+    "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_solve_direct", "eda_solve_batched",
+    "eda_gram",
     "eda_syev",
 ]
 
@@ -123,6 +124,9 @@ def load_library():
                             ctypes.POINTER(dbl), vp, i64, ctypes.POINTER(dbl),
                             ctypes.POINTER(Info)]
     L.eda_solve.restype = ctypes.c_int
+    L.eda_solve_direct.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), vp, i64,
+                                   ctypes.POINTER(dbl), ctypes.POINTER(Info)]
+    L.eda_solve_direct.restype = ctypes.c_int
     L.eda_solve_batched.argtypes = [vp, i32, ctypes.POINTER(Problem), ctypes.c_int,
                                     ctypes.POINTER(SolveOpts), ctypes.POINTER(Info),
                                     ctypes.POINTER(ctypes.c_int)]
@@ -294,6 +298,22 @@ class Handle:
                                 X.data_ptr(), _ld(X), res, ctypes.byref(info))
         msg = self.lib.eda_last_error(self._h).decode() if st != EDA_OK else ""
         if st not in (EDA_OK, EDA_ERR_NOCONV) and raise_on_error:
+            raise EDAError(st, msg)
+        return SolveResult(list(ritz), list(rlog), X, list(res), info.as_dict(), st, msg)
+
+    def solve_direct(self, t: int, raise_on_error: bool = True, X=None) -> SolveResult:
+        """The t leading pairs by the reduced direct solve (eda_solve_direct)."""
+        torch = self._torch
+        if X is None:
+            X = _empty_cm(self.d, t, torch.float64, self.device)
+        ritz = (ctypes.c_double * t)()
+        rlog = (ctypes.c_double * t)()
+        res = (ctypes.c_double * t)()
+        info = Info()
+        st = self.lib.eda_solve_direct(self._h, t, ritz, rlog, X.data_ptr(), _ld(X), res,
+                                       ctypes.byref(info))
+        msg = self.lib.eda_last_error(self._h).decode() if st != EDA_OK else ""
+        if st != EDA_OK and raise_on_error:
             raise EDAError(st, msg)
         return SolveResult(list(ritz), list(rlog), X, list(res), info.as_dict(), st, msg)
 

@@ -346,6 +346,10 @@ hipError_t launch_norm1(int64_t n, const double* A, int64_t lda, double* out, hi
 hipError_t launch_lincomb(int64_t n, double a0, double a1, const double* X1, double a2,
                           const double* X2, double a3, const double* X3, int64_t ldx,
                           double* C, int64_t ldc, hipStream_t s);
+// dst[r + c*ldd] = src[r + c*lds] * w[c]^(p/2), p = +1 or -1 (columns scaled
+// by the square roots of w, or their reciprocals).
+hipError_t launch_scale_cols(int64_t rows, int64_t cols, const double* src, int64_t lds,
+                             const double* w, int p, double* dst, int64_t ldd, hipStream_t s);
 // dst[i + i*ldd] = v[i] for i < cnt (diagonal only).
 hipError_t launch_set_diag(int64_t cnt, const double* v, double* dst, int64_t ldd, hipStream_t s);
 // Column 2-norms / sign fix / scaling helpers.

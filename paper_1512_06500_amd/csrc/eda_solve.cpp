@@ -304,6 +304,26 @@ eda_status rr_block(eda_handle h, int64_t d, int64_t ld, int64_t w, int64_t t, i
 
 }  // namespace
 
+namespace eda {
+
+// x = exp(-S_W/2) y for the t Ritz vectors Y (float64, ld ldy), then
+// orthonormalised in column order by Cholesky QR run twice (scratch with
+// leading dimension ldw in h->Yb) and sign-fixed (eq. 3.14; Algorithm 3).
+eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy, double* X,
+                          int64_t ldx, int64_t ldw) {
+  const int64_t d = h->d;
+  STCHK(ensure(h, h->Yb, (size_t)ldw * t * 8));
+  STCHK(expop(h, true, 0, h->n, h->Gh.d(), h->n, 1.0, t, Y, DT::F64, ldy, X, DT::F64, ldx));
+  STCHK(cholqr_pass(h, d, t, X, DT::F64, ldx, h->Yb.d(), ldw, nullptr, nullptr, 0, nullptr, 0, 0,
+                    nullptr, nullptr));
+  STCHK(cholqr_pass(h, d, t, h->Yb.d(), DT::F64, ldw, X, ldx, nullptr, nullptr, 0, nullptr, 0, 0,
+                    nullptr, nullptr));
+  HIPCHK(launch_sign_fix(d, t, X, ldx, h->stream));
+  return EDA_OK;
+}
+
+}  // namespace eda
+
 extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* opt,
                                 double* ritz, double* ritz_log, double* X, int64_t ldx,
                                 double* resid, eda_info* info) {
@@ -749,12 +769,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   // back-transform x = exp(-S_W/2) y, orthonormalise in decreasing-lambda
   // order (Cholesky QR, twice), then fix signs
   double* Y = XB[cb];
-  STCHK(expop(h, true, 0, h->n, h->Gh.d(), h->n, 1.0, t, Y, DT::F64, ldq, X, DT::F64, ldx));
-  STCHK(cholqr_pass(h, d, t, X, DT::F64, ldx, h->Yb.d(), ldq, nullptr, nullptr, 0, nullptr, 0, 0,
-                    nullptr, nullptr));
-  STCHK(cholqr_pass(h, d, t, h->Yb.d(), DT::F64, ldq, X, ldx, nullptr, nullptr, 0, nullptr, 0, 0,
-                    nullptr, nullptr));
-  HIPCHK(launch_sign_fix(d, t, X, ldx, s));
+  STCHK(back_transform(h, t, Y, ldq, X, ldx, ldq));
   int fl[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(fl, h->flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -59,6 +59,7 @@ struct eda_handle_s {
   double shiftB = 0.0, alphaB = 1.0;
   eda::Buf alphaB_dev;  // alphaB on the device, read by captured steps
   eda::Buf pscale;      // FP8 storage: column j of P is pscale[j] times its FP8 copy
+  eda::Buf dir[10];     // workspaces of eda_solve_direct
   double normW = 0.0;   // ||H_W^T H_W||_1
   bool w_eig = false;   // eigenpairs of H_W^T H_W available
   std::vector<double> hwW, hwB;
@@ -124,6 +125,10 @@ void release_graphs(eda_handle h);
 
 // Low-rank exponential apply on columns [c0, c0+Nc) of P (the storage copy,
 // or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.
+// x = exp(-S_W/2) y for t columns, orthonormalised (Cholesky QR twice,
+// scratch ld ldw) and sign-fixed.
+eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy, double* X,
+                          int64_t ldx, int64_t ldw);
 eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
                  int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
                  void* Out, DT odt, int64_t ldo, const double* alpha_p = nullptr);

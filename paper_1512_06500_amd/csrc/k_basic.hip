@@ -393,6 +393,25 @@ hipError_t launch_pack_fp8(int64_t d, int64_t ldp, int64_t cols, const double* P
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void scale_cols_kernel(int64_t rows, const double* __restrict__ src,
+                                                         int64_t lds, const double* __restrict__ w,
+                                                         int p, double* __restrict__ dst,
+                                                         int64_t ldd) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= rows) return;
+  const double f = sqrt(w[c]);
+  dst[r + c * ldd] = (p > 0) ? src[r + c * lds] * f : src[r + c * lds] / f;
+}
+
+hipError_t launch_scale_cols(int64_t rows, int64_t cols, const double* src, int64_t lds,
+                             const double* w, int p, double* dst, int64_t ldd, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(nblk(rows), (unsigned)cols), dim3(256), 0, s, rows,
+                     src, lds, w, p, dst, ldd);
+  return hipGetLastError();
+}
+
 hipError_t launch_nonfinite(int64_t d, int64_t cols, const double* H, int64_t ldh, int* flag,
                             hipStream_t s) {
   int64_t total = d * cols;

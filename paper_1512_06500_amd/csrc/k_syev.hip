@@ -856,7 +856,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   // subspace; they are orthonormalised together, which mixes only vectors of
   // eigenvalues closer than ctol.
   {
-    int a = n0, cl = 0;
+    int a = n0;
     while (a < n) {
       int b = a + 1;
       while (b < n && (lamv[b] - lamv[b - 1]) <= ctol) ++b;
@@ -896,24 +896,37 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
           __syncthreads();
         }
       } else if (c > kClusterMax) {
-        if ((cl % NW) == wid) {
-          for (int pass = 0; pass < 2; ++pass) {
-            for (int i = a; i < b; ++i) {
-              double* y = Zt + (i - n0);
-              for (int k = a; k < i; ++k) {
-                const double* zk = Zt + (k - n0);
-                double dot = 0.0;
-                for (int pos = lane; pos < n; pos += 64)
-                  dot += zk[(int64_t)pos * nv] * y[(int64_t)pos * nv];
-                dot = wave_sum(dot);
-                for (int pos = lane; pos < n; pos += 64) y[(int64_t)pos * nv] -= dot * zk[(int64_t)pos * nv];
-              }
-              wave_normalize(n, y, nv, lane);
-              __threadfence_block();
+        // classical Gram-Schmidt run twice, vector by vector, by the whole
+        // workgroup: wave w forms the coefficients against vectors w, w+NW,
+        // ... of the cluster (Gc), then every thread updates its positions
+        const int s0 = a - n0;
+        for (int i = 0; i < c; ++i) {
+          double* y = Zt + s0 + i;
+          for (int pass = 0; pass < 2 && i > 0; ++pass) {
+            for (int q = wid; q < i; q += NW) {
+              const double* zq = Zt + s0 + q;
+              double dot = 0.0;
+              for (int pos = lane; pos < n; pos += 64)
+                dot += zq[(int64_t)pos * nv] * y[(int64_t)pos * nv];
+              dot = wave_sum(dot);
+              if (lane == 0) Gc[q] = dot;
             }
+            __syncthreads();
+            for (int pos = tid; pos < n; pos += NT) {
+              const double* zr = Zt + (int64_t)pos * nv + s0;
+              double acc = 0.0;
+              for (int q = 0; q < i; ++q) acc += Gc[q] * zr[q];
+              y[(int64_t)pos * nv] -= acc;
+            }
+            __syncthreads();
           }
+          double ss = 0.0;
+          for (int pos = tid; pos < n; pos += NT) ss += y[(int64_t)pos * nv] * y[(int64_t)pos * nv];
+          ss = blk_sum<NT>(ss, red);
+          const double sc = (ss > 0.0) ? 1.0 / sqrt(ss) : 0.0;
+          for (int pos = tid; pos < n; pos += NT) y[(int64_t)pos * nv] *= sc;
+          __syncthreads();
         }
-        ++cl;
       }
       a = b;
     }

@@ -80,6 +80,8 @@ def test_calls_before_prepare_report_state(lib, handle):
     info = eda.Info()
     assert lib.eda_solve(handle, 2, 1e-8, ctypes.byref(o), buf, buf, FAKE, 10, buf,
                          ctypes.byref(info)) == eda.EDA_ERR_STATE
+    assert lib.eda_solve_direct(handle, 2, buf, buf, FAKE, 10, buf,
+                                ctypes.byref(info)) == eda.EDA_ERR_STATE
 
 
 def test_expmv_rejects_bad_which_and_c(lib, handle):

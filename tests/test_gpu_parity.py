@@ -489,6 +489,36 @@ def test_mixed_refined_c2(torch, eda, c2, storage, basis):
     h.close()
 
 
+@pytest.mark.parametrize("cname", ["c1", "c2"])
+def test_direct_solve_against_oracle(torch, eda, cname, request):
+    """Reduced direct solve (row f2): the exact N x N reduction of the pencil
+    on the GPU.  Its pairs are exact up to rounding, so they meet the oracle's
+    exact reduction at the float64 bounds used for the converged Krylov
+    solve, and agree with that solve."""
+    case = request.getfixturevalue(cname)
+    log(f"direct solve {case.name}")
+    red = O.eda_reduced(case.H_W, case.H_B, case.t)
+    h, _, _ = prepared(torch, eda, case)
+    res = h.solve_direct(case.t)
+    log(f"  status={res.status} ms={res.info['t_krylov_ms']:.2f} resid_max={max(res.resid):.2e}")
+    check_solution(res, red, case.t, red.lam_all, 1e-12)
+    kry = h.solve(case.t, 1e-10, block=8, seed=2)
+    lam_d, lam_k = np.array(res.ritz), np.array(kry.ritz)
+    lam_tol = np.maximum(1e-10, 100 * U * red.lam_all[0] / red.lam)
+    assert np.all(np.abs(lam_d - lam_k) / lam_k <= lam_tol)
+    h.close()
+
+
+def test_direct_solve_rejects_t_above_rank(torch, eda, c1):
+    h, _, _ = prepared(torch, eda, c1)
+    N = c1.H_W.shape[1] + c1.H_B.shape[1]
+    r = np.linalg.matrix_rank(np.concatenate([c1.H_W, c1.H_B], axis=1))
+    assert r < N
+    res = h.solve_direct(min(r + 1, 128), raise_on_error=False)
+    assert res.status == eda.EDA_ERR_ARG and "rank" in res.message
+    h.close()
+
+
 def test_mixed_c1_agrees_per_column(torch, eda, c1):
     log("solve C1 with bfloat16 storage and float32 basis, refined")
     ref = O.eda_dense(c1.H_W, c1.H_B, c1.t)
