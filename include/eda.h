@@ -74,7 +74,7 @@ typedef enum {
 
 /* Solver options.  A zero-initialised struct selects every default. */
 typedef struct {
-  eda_form form;            /* only EDA_FORM_LANCZOS_M is solved at present          */
+  eda_form form;            /* EDA_FORM_LANCZOS_M (default) or EDA_FORM_ARNOLDI_A    */
   int32_t block;            /* block width b (default 8)                             */
   int32_t max_basis;        /* basis columns before a thick restart (default
                                max(2t+2b, t+6b) rounded up to a multiple of b,
@@ -197,7 +197,21 @@ eda_status eda_opmv(eda_handle h, eda_form form, int64_t b,
  * max(tol, 10 u64 theta_1/theta_i), refinement passes (Rayleigh-Ritz on the
  * Ritz block and its residual block), at most opts.max_refine of them.
  * EDA_ERR_NOCONV if max_iter or max_refine is exhausted (outputs still
- * written).  Synchronises. */
+ * written).
+ * With opts.form = EDA_FORM_ARNOLDI_A the eigenvectors of A = exp(-S_W)
+ * exp(S_B) (eq. 3.1) are computed directly, by block Lanczos in the
+ * exp(S_W) inner product (A is self-adjoint in it), keeping exp(S_W) V
+ * beside the basis V; each block step is one product with e^{-s} A (core
+ * C_A of eq. 3.2) and one with exp(S_W) (the H_W columns of P), about 1.5 to
+ * 2 times the traffic of a Lanczos step.  That form runs in float64 only
+ * (krylov_dtype EDA_F64; the float64 master of P is used whatever the
+ * storage type), has no refinement stage, needs ||H_W^T H_W||_1 <= 12 ln 10
+ * and t + 2b <= max_basis <= n - 1 - b (rounded down to a multiple of b; the
+ * default is capped there), and resid[i] is the exp(-S_W)-norm of
+ * e^{-s} exp(S_B) x_i - theta_i exp(S_W) x_i for exp(S_W)-normalised x_i,
+ * relative as in opts.resmode (equal to the Lanczos form's residual of the
+ * same pair).  EDA_ERR_NOCONV also when a block loses rank before the
+ * tolerance is met.  Synchronises. */
 eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* opt,
                      double* ritz, double* ritz_log, double* X, int64_t ldx,
                      double* resid, eda_info* info);

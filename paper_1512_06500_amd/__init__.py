@@ -271,10 +271,15 @@ class Handle:
     def solve(self, t: int, tol: float, block: int = 8, max_basis: int = 0, max_iter: int = 0,
               seed: int = 0, start_block=None, check_every: int = 0, resmode: str = "rel",
               krylov_dtype: str = "f64", max_refine: int = 0, raise_on_error: bool = True,
-              X=None) -> SolveResult:
+              X=None, form: str = "M") -> SolveResult:
+        """form 'M': block Lanczos on the symmetric e^{-s} M, then the
+        back-transform; form 'A': the eigenvectors of A = exp(-S_W) exp(S_B)
+        directly, by block Lanczos in the exp(S_W) inner product (float64)."""
         torch = self._torch
+        if form not in ("M", "A"):
+            raise ValueError("form must be 'M' or 'A'")
         o = SolveOpts()
-        o.form = EDA_FORM_LANCZOS_M
+        o.form = EDA_FORM_LANCZOS_M if form == "M" else EDA_FORM_ARNOLDI_A
         o.block = block
         o.max_basis = max_basis
         o.max_iter = max_iter

@@ -318,6 +318,7 @@ void eda_destroy(eda_handle h) {
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
                   &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale};
     for (Buf& b : h->dir) release(b);
+    for (Buf& b : h->af) release(b);
     for (Buf* b : all) release(*b);
     for (auto& c : h->cores) release(c.buf);
     for (hipEvent_t e : h->op_ev) (void)hipEventDestroy(e);
@@ -367,6 +368,11 @@ eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k, co
 }  // extern "C"
 
 namespace eda {
+
+eda_status build_w_core(eda_handle h, double c, double* out) {
+  if (c > 0.0) STCHK(ensure_w_eig(h));
+  return build_core(h, EDA_W, c, 0.0, out);
+}
 
 void release_graphs(eda_handle h) {
   for (auto& g : h->graphs) {

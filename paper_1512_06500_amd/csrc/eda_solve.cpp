@@ -311,9 +311,13 @@ namespace eda {
 // leading dimension ldw in h->Yb) and sign-fixed (eq. 3.14; Algorithm 3).
 eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy, double* X,
                           int64_t ldx, int64_t ldw) {
+  STCHK(expop(h, true, 0, h->n, h->Gh.d(), h->n, 1.0, t, Y, DT::F64, ldy, X, DT::F64, ldx));
+  return orthonormalise(h, t, X, ldx, ldw);
+}
+
+eda_status orthonormalise(eda_handle h, int64_t t, double* X, int64_t ldx, int64_t ldw) {
   const int64_t d = h->d;
   STCHK(ensure(h, h->Yb, (size_t)ldw * t * 8));
-  STCHK(expop(h, true, 0, h->n, h->Gh.d(), h->n, 1.0, t, Y, DT::F64, ldy, X, DT::F64, ldx));
   STCHK(cholqr_pass(h, d, t, X, DT::F64, ldx, h->Yb.d(), ldw, nullptr, nullptr, 0, nullptr, 0, 0,
                     nullptr, nullptr));
   STCHK(cholqr_pass(h, d, t, h->Yb.d(), DT::F64, ldw, X, ldx, nullptr, nullptr, 0, nullptr, 0, 0,
@@ -339,7 +343,8 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   if (ritz == nullptr || ritz_log == nullptr || X == nullptr || resid == nullptr)
     return fail(h, EDA_ERR_ARG, "null output pointer");
   if (ldx < d) return fail(h, EDA_ERR_ARG, "ldx must be >= d");
-  if (o.form != EDA_FORM_LANCZOS_M) return fail(h, EDA_ERR_ARG, "only the Lanczos form is solved");
+  if (o.form != EDA_FORM_LANCZOS_M && o.form != EDA_FORM_ARNOLDI_A)
+    return fail(h, EDA_ERR_ARG, "unknown form");
   if (o.krylov_dtype != EDA_F64 && o.krylov_dtype != EDA_F32)
     return fail(h, EDA_ERR_ARG, "krylov_dtype (basis type) must be EDA_F64 or EDA_F32");
   if (o.refine_dtype != EDA_F64) return fail(h, EDA_ERR_ARG, "refine_dtype must be EDA_F64");
@@ -365,6 +370,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   STCHK(need_device(h));
   STCHK(check_dev_ptr(h, X, "X"));
   if (o.start_block != nullptr) STCHK(check_dev_ptr(h, o.start_block, "start_block"));
+  if (o.form == EDA_FORM_ARNOLDI_A) return solve_aform(h, t, tol, o, ritz, ritz_log, X, ldx, resid, info);
 
   const DT qdt = o.krylov_dtype == EDA_F32 ? DT::F32 : DT::F64;
   const bool mixed = (h->storage != EDA_F64) || (qdt != DT::F64);

@@ -60,6 +60,7 @@ struct eda_handle_s {
   eda::Buf alphaB_dev;  // alphaB on the device, read by captured steps
   eda::Buf pscale;      // FP8 storage: column j of P is pscale[j] times its FP8 copy
   eda::Buf dir[10];     // workspaces of eda_solve_direct
+  eda::Buf af[10];      // workspaces of the Arnoldi-form solve
   double normW = 0.0;   // ||H_W^T H_W||_1
   bool w_eig = false;   // eigenpairs of H_W^T H_W available
   std::vector<double> hwW, hwB;
@@ -129,6 +130,15 @@ void release_graphs(eda_handle h);
 // scratch ld ldw) and sign-fixed.
 eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy, double* X,
                           int64_t ldx, int64_t ldw);
+// Columns of X (d x t) orthonormalised in column order by Cholesky QR run
+// twice (scratch with leading dimension ldw in h->Yb) and sign-fixed.
+eda_status orthonormalise(eda_handle h, int64_t t, double* X, int64_t ldx, int64_t ldw);
+// Core of exp(c S_W) without shift (exp(c S_W) = I + H_W C H_W^T), n x n.
+eda_status build_w_core(eda_handle h, double c, double* out);
+// eda_solve for the Arnoldi form (eda_aform.cpp); arguments already checked.
+eda_status solve_aform(eda_handle h, int32_t t, double tol, const eda_solve_opts& o,
+                       double* ritz, double* ritz_log, double* X, int64_t ldx, double* resid,
+                       eda_info* info);
 eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
                  int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
                  void* Out, DT odt, int64_t ldo, const double* alpha_p = nullptr);

@@ -251,7 +251,8 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
 //   W P = [Q_1 Q_2] [[R11 R12], [0, ~0]],   Q_1 = W P[:, :r] R11^{-1}.
 // Outputs: Z (row-major, W Z = [Q_1, 0]), R (col-major, W = [Q_1 Q_2] R with
 // rows >= r zero), mask[j] = 1 for deflated output columns j >= r, and
-// *flag = 1 if a column was deflated or kept less than `ratio` of its norm.
+// *flag = 1 if a column kept less than `ratio` of its norm, | 2 if a column
+// was deflated (nothing is written when neither happened).
 __global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict__ arr, PcholArgs one) {
   const PcholArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int b = (int)a.b;
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict_
     if (tid < rk && !(A[tid + tid * ld] >= ratio * sqrt(nrm0[perm[tid]]))) atomicOr(&s_flag, 1);
   }
   __syncthreads();
-  if (tid == 0 && flag != nullptr && (s_flag || rk < b)) *flag = 1;
+  if (tid == 0 && flag != nullptr && (s_flag || rk < b)) *flag = (s_flag ? 1 : 0) | (rk < b ? 2 : 0);
 }
 
 // Q[:, j] = seeded Gaussian for every column j with mask[j] != 0.

@@ -519,6 +519,48 @@ def test_direct_solve_rejects_t_above_rank(torch, eda, c1):
     h.close()
 
 
+@pytest.mark.parametrize("cname,block", [("c1", 8), ("c2", 8), ("ragged", 2)])
+def test_aform_solve_against_oracle(torch, eda, cname, block, request):
+    """Arnoldi form (row f1): eigenvectors of A = exp(-S_W) exp(S_B) by block
+    Lanczos in the exp(S_W) inner product, returned without back-transform.
+    Same bounds against the oracle as the Lanczos form, and the two forms
+    agree with each other."""
+    case = request.getfixturevalue(cname)
+    log(f"A-form solve {case.name} b={block}")
+    ref = O.eda_dense(case.H_W, case.H_B, case.t) if case.d <= 2000 else None
+    red = O.eda_reduced(case.H_W, case.H_B, case.t)
+    h, _, _ = prepared(torch, eda, case)
+    res = h.solve(case.t, 1e-10, block=block, seed=3, form="A")
+    check_solution(res, ref if ref is not None else red, case.t, red.lam_all, 1e-10)
+    kry = h.solve(case.t, 1e-10, block=block, seed=3)
+    lam_a, lam_m = np.array(res.ritz), np.array(kry.ritz)
+    lam_tol = np.maximum(1e-10, 100 * U * red.lam_all[0] / red.lam)
+    assert np.all(np.abs(lam_a - lam_m) / lam_m <= lam_tol)
+    fl = O.accuracy_floor(red.lam_all, case.t)
+    assert O.sin_angle(host(res.X), host(kry.X)) <= max(1e-8, 100 * fl["span"])
+    h.close()
+
+
+def test_aform_thick_restart_c2(torch, eda, c2):
+    log("A-form solve C2 with a small basis (thick restarts)")
+    red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
+    h, _, _ = prepared(torch, eda, c2)
+    res = h.solve(c2.t, 1e-10, block=8, max_basis=72, seed=4, max_iter=3000, form="A")
+    assert res.info["restarts"] >= 1
+    check_solution(res, red, c2.t, red.lam_all, 1e-10)
+    h.close()
+
+
+def test_aform_argument_checks(torch, eda, c1):
+    h, _, _ = prepared(torch, eda, c1)
+    r = h.solve(c1.t, 1e-10, form="A", krylov_dtype="f32", raise_on_error=False)
+    assert r.status == eda.EDA_ERR_ARG and "float64" in r.message
+    # the basis may not reach the dimension n - 1 + b of the invariant hull
+    r = h.solve(c1.t, 1e-10, form="A", max_basis=48, raise_on_error=False)
+    assert r.status == eda.EDA_ERR_ARG and "max_basis" in r.message
+    h.close()
+
+
 def test_mixed_c1_agrees_per_column(torch, eda, c1):
     log("solve C1 with bfloat16 storage and float32 basis, refined")
     ref = O.eda_dense(c1.H_W, c1.H_B, c1.t)
