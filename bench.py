@@ -146,9 +146,9 @@ def mixed_vs_f64(torch, eda, reps: int = 3) -> dict:
     return out
 
 
-def direct_vs_krylov(torch, eda, reps: int = 5) -> dict:
-    """Reduced direct solve against the Krylov solve, solve phase only (the
-    preparation is shared), at C1 and C2."""
+def solve_variants(torch, eda, reps: int = 5) -> dict:
+    """Lanczos-form Krylov solve, Arnoldi-form Krylov solve and reduced
+    direct solve, solve phase only (the preparation is shared), at C1 and C2."""
     import datagen
     out = {}
     for name in ("C1", "C2"):
@@ -156,8 +156,9 @@ def direct_vs_krylov(torch, eda, reps: int = 5) -> dict:
         h = eda.Handle()
         HW, HB = h.scatter_factors(_upload(torch, p.X), p.counts.tolist())
         h.prepare(HW, HB)
-        row = {"workload": f"d={p.d}, n={p.n}, k={p.k}, t={p.t}"}
-        for tag, fn in (("krylov", lambda: h.solve(p.t, p.tol, block=8, seed=p.seed)),
+        row = {"workload": f"d={p.d}, n={p.n}, k={p.k}, t={p.t}, tol={p.tol:g}"}
+        for tag, fn in (("lanczos", lambda: h.solve(p.t, p.tol, block=8, seed=p.seed)),
+                        ("arnoldi", lambda: h.solve(p.t, p.tol, block=8, seed=p.seed, form="A")),
                         ("direct", lambda: h.solve_direct(p.t))):
             r = fn()
             torch.cuda.synchronize()
@@ -167,10 +168,13 @@ def direct_vs_krylov(torch, eda, reps: int = 5) -> dict:
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) / reps
             row[tag] = {"solves_per_s": 1.0 / el, "ms": 1e3 * el, "status": r.status,
-                        "resid_max": max(r.resid), "lam": r.ritz}
-        lk, ld = np.array(row["krylov"].pop("lam")), np.array(row["direct"].pop("lam"))
-        row["lam_max_rel_diff"] = float(np.max(np.abs(lk - ld) / ld))
-        row["ratio_direct_over_krylov"] = row["direct"]["solves_per_s"] / row["krylov"]["solves_per_s"]
+                        "iters": r.info["iters"], "resid_max": max(r.resid), "lam": r.ritz}
+        lk = np.array(row["lanczos"].pop("lam"))
+        for tag in ("arnoldi", "direct"):
+            lv = np.array(row[tag].pop("lam"))
+            row[f"lam_max_rel_diff_{tag}"] = float(np.max(np.abs(lk - lv) / lv))
+            row[f"ratio_{tag}_over_lanczos"] = (row[tag]["solves_per_s"]
+                                                / row["lanczos"]["solves_per_s"])
         out[name] = row
         h.close()
     return out
@@ -306,7 +310,7 @@ def main():
     h.close()
     if not args.no_extra:
         out["mixed_vs_f64"] = mixed_vs_f64(torch, eda)
-        out["direct_vs_krylov"] = direct_vs_krylov(torch, eda)
+        out["solve_variants"] = solve_variants(torch, eda)
         out["batched"] = batched(torch, eda)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
