@@ -102,6 +102,136 @@ __device__ void gram_to_lds(const double* __restrict__ G, int64_t ldg,
   __syncthreads();
 }
 
+// Cholesky of a symmetric 8 x 8 matrix held by columns in lanes 0..7 of a
+// wave (lane c: col[r] = A(r, c)), in registers.  Step j takes the pivot
+// from lane j, which scales its column into L(:, j); every lane c > j then
+// subtracts L(:, j) L(c, j), reading L(r, j) from lane j.  A pivot not above
+// floor_[j] is clamped to it and counted in the return value.  On return
+// lane c holds L(r, c) for r >= c, and every lane invd[j] = 1 / L(j, j) and
+// pd[j] = the pivot before its square root.
+__device__ __forceinline__ int chol8_regs(double (&col)[8], int c, const double (&floor_)[8],
+                                          double (&invd)[8], double (&pd)[8]) {
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    double djj = readlane_f64(col[j], j);
+    pd[j] = djj;
+    if (!(djj > floor_[j])) {  // also catches NaN
+      djj = floor_[j];
+      bad = 1;
+    }
+    const double piv = sqrt(djj), inv = 1.0 / piv;
+    invd[j] = inv;
+    const double lcj = col[j] * inv;  // L(c, j) in lane c > j
+    if (c == j) {
+#pragma unroll
+      for (int r = j + 1; r < 8; ++r) col[r] *= inv;
+      col[j] = piv;
+    }
+#pragma unroll
+    for (int r = j + 1; r < 8; ++r) {
+      const double lrj = readlane_f64(col[r], j);
+      if (c > j) col[r] -= lrj * lcj;
+    }
+  }
+  return bad;
+}
+
+// Column c of L^{-1} (forward substitution on e_c) from the output of
+// chol8_regs; lane c gets y[r] = (L^{-1})(r, c), so (L^{-T})(c, q) = y[q]
+// is row c of R^{-1} for R = L^T.
+__device__ __forceinline__ void inv8_regs(const double (&col)[8], int c, const double (&invd)[8],
+                                          double (&y)[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    double sacc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < r; ++k) sacc -= readlane_f64(col[r], k) * y[k];
+    y[r] = sacc * invd[r];
+  }
+}
+
+// The inputs of a narrow block (b <= 16) with one memory round trip: every
+// thread issues all of its global loads (the gate, Rprev, the projection
+// coefficients, the Gram entries or their chunk partials) before it uses
+// any of them, then one barrier.  Results: A[r + c*ld] the Gram matrix (sums
+// in the order of gram_to_lds), hn[c] = sum_r hcol[r, c]^2 when hcol is
+// given (rows in a fixed order), RP[r + c*64] = Rprev when RP is given.
+// hs, hs2: blockDim.x doubles each.  Returns the gate's value (1 without a
+// gate); the buffers behind a closed gate are still valid, only stale.
+__device__ int stage_small(const double* __restrict__ G, int64_t ldg,
+                           const double* __restrict__ part, int64_t chunks, int b, double* A,
+                           int ld, double* hs, double* hs2, const double* __restrict__ hcol,
+                           int64_t m, int64_t ldhc, double* hn, const double* __restrict__ Rprev,
+                           int64_t ldrp, double* RP, const int* gate) {
+  const int nt = blockDim.x, tid = threadIdx.x, bb = b * b;
+  const int gv = (gate != nullptr) ? *gate : 1;
+  double rp = 0.0;
+  if (RP != nullptr && tid < bb) rp = Rprev[(tid % b) + (int64_t)(tid / b) * ldrp];
+  // projection coefficients: column tid % b, rows tid / b + k * per
+  const int per = nt / b;
+  double h2 = 0.0;
+  if (hcol != nullptr && tid < per * b) {
+    const double* hc = hcol + (int64_t)(tid % b) * ldhc;
+    for (int64_t r = tid / b; r < m; r += 8 * (int64_t)per) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t rr = r + (int64_t)u * per;
+        v[u] = (rr < m) ? hc[rr] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) h2 += v[u] * v[u];
+    }
+  }
+  // Gram entry o by H threads (chunks h, h+H, ...), as in gram_to_lds
+  int H = 1;
+  if (part != nullptr)
+    while (2 * H * bb <= nt) H *= 2;
+  const int st = nt / H;
+  const int o = tid % st, h = tid / st;
+  double g = 0.0;
+  if (o < bb && h < H) {
+    if (part == nullptr) {
+      g = G[(o % b) + (int64_t)(o / b) * ldg];
+    } else {
+      const double* p = part + o;
+      for (int64_t base = h; base < chunks; base += 16 * (int64_t)H) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int64_t ch = base + (int64_t)u * H;
+          v[u] = (ch < chunks) ? p[ch * bb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) g += (v[u] + v[u + 1]) + (v[u + 2] + v[u + 3]);
+      }
+    }
+  }
+  hs[tid] = g;
+  hs2[tid] = h2;
+  if (RP != nullptr && tid < bb) RP[(tid % b) + (tid / b) * 64] = rp;
+  __syncthreads();
+  if (tid < bb) {
+    double t = hs[tid];
+    if (part != nullptr) {
+      // entry tid: partial sums of threads tid + q st, q = 0..H-1, in order
+      for (int q = 1; q < H; ++q) t += hs[q * st + tid];
+      const int r = tid / b, c = tid - r * b;  // partials are row-major
+      A[r + c * ld] = t;
+    } else {
+      A[(tid % b) + (tid / b) * ld] = t;  // G is column-major
+    }
+  }
+  if (hcol != nullptr && tid < b) {
+    double t = 0.0;
+    for (int q = 0; q < per; ++q) t += hs2[tid + q * b];
+    hn[tid] = t;
+  }
+  __syncthreads();
+  return gv;
+}
+
 // LDS use of chol_kernel (one b x b array, ld = CH_MAX + 1):
 //   during the factorisation the lower triangle holds the trailing matrix
 //   and the strict upper triangle receives R = L^T row by row (diagonal in
@@ -110,7 +240,6 @@ __device__ void gram_to_lds(const double* __restrict__ G, int64_t ldg,
 //   (X[i][c] at (c, i)), diagonal in xd.
 __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ arr, CholArgs one) {
   const CholArgs a = arr != nullptr ? arr[blockIdx.z] : one;
-  if (a.gate != nullptr && *a.gate == 0) return;
   const int b = (int)a.b;
   const double* __restrict__ G = a.G;
   double* __restrict__ Rinv = a.Rinv;
@@ -121,32 +250,95 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
   const double ratio = a.ratio;
   int* flag = a.flag;
   __shared__ double L[CH_MAX * (CH_MAX + 1)];
-  __shared__ double rd[CH_MAX], xd[CH_MAX], hn[CH_MAX], d0[CH_MAX], hs[256];
+  __shared__ double rd[CH_MAX], xd[CH_MAX], hn[CH_MAX], d0[CH_MAX], hs[256], hs2[256];
   __shared__ int sflag;
   const int ld = CH_MAX + 1;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   if (tid == 0) sflag = 0;
   // Rprev (b <= 64) staged in the unused second half of L
   double* RP = (Rprev != nullptr && b <= 64) ? L + 64 * ld : nullptr;
-  if (RP != nullptr)
-    for (int e = tid; e < b * b; e += blockDim.x) {
-      const int c = e / b, r = e - c * b;
-      RP[r + c * 64] = Rprev[r + c * ldrp];
-    }
-  gram_to_lds(G, ldg, a.part, a.chunks, b, L, ld, hs);
+  if (b <= 16) {
+    // narrow blocks: every input in one memory round trip, the gate included
+    if (stage_small(G, ldg, a.part, a.chunks, b, L, ld, hs, hs2, hcol, m, ldhc, hn, Rprev, ldrp,
+                    RP, a.gate) == 0)
+      return;
+  } else {
+    if (a.gate != nullptr && *a.gate == 0) return;
+    if (RP != nullptr)
+      for (int e = tid; e < b * b; e += blockDim.x) {
+        const int c = e / b, r = e - c * b;
+        RP[r + c * 64] = Rprev[r + c * ldrp];
+      }
+    gram_to_lds(G, ldg, a.part, a.chunks, b, L, ld, hs);
+    // squared norms of the projection coefficients, one wave per column
+    if (hcol != nullptr)
+      for (int c = wid; c < b; c += nw) {
+        const double* hc = hcol + (int64_t)c * ldhc;
+        const double v0 = (lane < m) ? hc[lane] : 0.0;
+        const double v1 = (lane + 64 < m) ? hc[lane + 64] : 0.0;
+        double h2 = v0 * v0 + v1 * v1;
+        for (int64_t r = lane + 128; r < m; r += 64) h2 += hc[r] * hc[r];
+        h2 = wave_sum(h2);
+        if (lane == 0) hn[c] = h2;
+      }
+  }
   for (int r = tid; r < b; r += blockDim.x) d0[r] = L[r + r * ld];
-  // squared norms of the projection coefficients, one wave per column
-  if (hcol != nullptr)
-    for (int c = wid; c < b; c += nw) {
-      const double* hc = hcol + (int64_t)c * ldhc;
-      const double v0 = (lane < m) ? hc[lane] : 0.0;
-      const double v1 = (lane + 64 < m) ? hc[lane + 64] : 0.0;
-      double h2 = v0 * v0 + v1 * v1;
-      for (int64_t r = lane + 128; r < m; r += 64) h2 += hc[r] * hc[r];
-      h2 = wave_sum(h2);
-      if (lane == 0) hn[c] = h2;
-    }
   __syncthreads();
+  if (b <= 8) {
+    // Blocks of at most 8 columns: wave 0 factorises and inverts in
+    // registers (the matrix identity-padded to 8; only its lower triangle is
+    // read, so the copy in registers is exactly symmetric).
+    if (wid == 0) {
+      const int c = lane;
+      double col[8], fl[8], invd[8], pd[8], y[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const bool in = c < b && r < b;
+        const double g = in ? ((r >= c) ? L[r + c * ld] : L[c + r * ld]) : 0.0;
+        col[r] = in ? g : ((r == c) ? 1.0 : 0.0);
+        fl[r] = (r < b) ? 1e-28 * fabs(d0[r]) + 1e-300 : 0.0;
+      }
+      int bad = chol8_regs(col, c, fl, invd, pd);
+      inv8_regs(col, c, invd, y);
+      if (Rout != nullptr) {
+        // lane q: column q of R Rprev (or of R), R(i, k) = L(k, i):
+        //   (R Rprev)(i, q) = sum_{k >= i} L(k, i) Rprev(k, q)
+        double rq[8], o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          rq[k] = (Rprev != nullptr) ? ((c < b && k < b) ? RP[k + c * 64] : 0.0)
+                                     : ((k == c) ? 1.0 : 0.0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          double sacc = 0.0;
+#pragma unroll
+          for (int k = i; k < 8; ++k) sacc += readlane_f64(col[k], i) * rq[k];
+          o[i] = sacc;
+        }
+        if (c < b)
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i < b) Rout[i + (int64_t)c * ldro] = o[i];
+      }
+      if (c < b) {
+        // row c of R^{-1} (row-major)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < b) Rinv[(int64_t)c * ldri + q] = y[q];
+        if (hcol != nullptr) {
+          double rc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (k == c) rc = col[k];
+          if (!(rc >= ratio * sqrt(hn[c] + rc * rc))) bad = 1;
+        }
+      }
+      if (bad && c < 8) sflag = 1;
+    }
+    __syncthreads();
+    if (tid == 0 && flag != nullptr && sflag) *flag = 1;
+    return;
+  }
   const bool one_wave = b <= 16;  // then wave 0 factorises and inverts alone, without barriers
   if (one_wave) {
     if (wid == 0) {
@@ -271,10 +463,15 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict_
   __shared__ double dsc[PB];  // column scaling (1 unless equilibrated)
   __shared__ int perm[PB];
   __shared__ int s_rank, s_flag;
-  __shared__ double gd[PB], hs[256];
+  __shared__ double gd[PB], hs[256], hs2[256], hn[PB];
   const int ld = PB + 1;
   const int tid = threadIdx.x;
-  gram_to_lds(G, ldg, a.part, a.chunks, b, A, ld, hs);
+  const bool narrow = b <= 16;  // then every input arrives in one memory round trip
+  if (narrow)
+    stage_small(G, ldg, a.part, a.chunks, b, A, ld, hs, hs2, equil ? nullptr : hcol, m, ldhc, hn,
+                nullptr, 0, nullptr, nullptr);
+  else
+    gram_to_lds(G, ldg, a.part, a.chunks, b, A, ld, hs);
   if (tid < b) {
     const double g = A[tid + tid * ld];
     gd[tid] = g;
@@ -289,7 +486,9 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict_
   // squared norms of the projection coefficients: the wave sums column c
   // and lane c keeps it
   double h2 = 0.0;
-  if (hcol != nullptr && !equil)
+  if (hcol != nullptr && !equil && narrow) {
+    if (tid < b) h2 = hn[tid];
+  } else if (hcol != nullptr && !equil)
     for (int c0 = 0; c0 < b; c0 += 8) {
       double hs[8];
 #pragma unroll
@@ -319,6 +518,58 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict_
   double scale2 = 0.0;
   for (int j = 0; j < b; ++j) scale2 = fmax(scale2, nrm0[j]);
   const double thr = tau * tau * scale2;
+  if (b <= 8) {
+    // First the unpivoted factorisation in registers (as in chol_kernel).
+    // When every pivot keeps at least 1e-8 of its column's squared norm in
+    // the block (and is far above the deflation threshold), no column is
+    // near the span of the others and the identity is as good a pivot order
+    // as any: its outputs are final.  Otherwise the pivoted factorisation
+    // below runs on the untouched LDS copy.
+    __shared__ int s_fast;
+    if (tid < 64) {
+      const int c = tid;
+      double col[8], fl[8], invd[8], pd[8], y[8], g0[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const bool in = c < b && r < b;
+        const double g = in ? ((r >= c) ? A[r + c * ld] : A[c + r * ld]) : 0.0;
+        col[r] = in ? g : ((r == c) ? 1.0 : 0.0);
+        fl[r] = 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) g0[r] = readlane_f64(col[r], r);
+      int bad = chol8_regs(col, c, fl, invd, pd);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < b && !(pd[j] > fmax(1e-8 * g0[j], 1e6 * thr))) bad = 1;
+      if (!bad) {
+        inv8_regs(col, c, invd, y);
+        if (c < b) {
+          const double sc = dsc[c];
+          // row c of Z = R^{-1} (times the column scaling when equilibrated)
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (q < b) Z[(int64_t)c * ldz + q] = equil ? y[q] * sc : y[q];
+          // row c of R: R(c, k) = L(k, c) / dsc[k] for k >= c
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (k < b) R[c + (int64_t)k * ldr] = (k >= c) ? col[k] / dsc[k] : 0.0;
+          mask[c] = 0;
+          double rc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (k == c) rc = col[k];
+          if (!(rc >= ratio * sqrt(nrm0[c]))) s_flag = 1;
+        }
+      }
+      if (c == 0) s_fast = !bad;
+    }
+    __syncthreads();
+    if (s_fast) {
+      if (tid == 0 && flag != nullptr && s_flag) *flag = 1;
+      return;
+    }
+  }
   // The factorisation runs in wave 0 alone (b <= 64: lane r owns row and
   // column r), so its steps need no workgroup barrier.
   if (tid < 64) {

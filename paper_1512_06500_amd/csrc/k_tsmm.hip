@@ -138,28 +138,31 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a, int64_t bx) {
   const double* __restrict__ part = a.part;
   const int64_t e = bx * 64 + lane;
   const int64_t ee = e < mn ? e : mn - 1;
+  const int64_t i = e / a.nb, j = e - i * a.nb;
+  // the accumulated output is read before the partials, so that its memory
+  // round trip overlaps theirs
+  const double cprev =
+      (wid == 0 && e < mn && a.C != nullptr && a.beta != 0.0) ? a.C[i + j * a.ldc] : 0.0;
+  // 16 loads in flight per lane; chunks w, w+4, ... added in order
   double s = 0.0;
-  int64_t c = wid;
-  for (; c + 12 < chunks; c += 16) {
-    const double v0 = part[c * mn + ee], v1 = part[(c + 4) * mn + ee];
-    const double v2 = part[(c + 8) * mn + ee], v3 = part[(c + 12) * mn + ee];
-    s += v0;
-    s += v1;
-    s += v2;
-    s += v3;
+  for (int64_t c0 = wid; c0 < chunks; c0 += 64) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t c = c0 + 4 * u;
+      v[u] = (c < chunks) ? part[c * mn + ee] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (c0 + 4 * u < chunks) s += v[u];
   }
-  for (; c < chunks; c += 4) s += part[c * mn + ee];
   if (wid > 0) red[wid - 1][lane] = s;
   __syncthreads();
   if (wid == 0 && e < mn) {
     s += red[0][lane];
     s += red[1][lane];
     s += red[2][lane];
-    const int64_t i = e / a.nb, j = e - i * a.nb;
-    if (a.C != nullptr) {
-      double* cp = a.C + i + j * a.ldc;
-      *cp = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * s;
-    }
+    if (a.C != nullptr) a.C[i + j * a.ldc] = a.beta * cprev + a.alpha * s;
     if (a.Z != nullptr) a.Z[i * a.ldz + j] = a.zalpha * s;
   }
   __syncthreads();  // red may be reused by a caller that loops over work items
@@ -186,6 +189,24 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, int64_t bx, int by) {
   const int64_t r = bx * R + rl;
   const int64_t lda = a.lda;
   const TA* ar = (const TA*)a.A + (r < d ? r : d - 1);  // rows past d read row d-1, never stored
+  const TV* V = (const TV*)a.V;
+  TO* Out = (TO*)a.Out;
+  // the operands of the output step are loaded now, so that their memory
+  // round trip overlaps the main loop (each thread reads only the V entries
+  // it overwrites in Out, so V == Out is safe)
+  constexpr int NO = (R * NN_NB + 255) / 256;
+  const double alpha = (a.alpha_p != nullptr) ? *a.alpha_p : a.alpha;
+  double vpre[NO];
+  int mpre[NO];
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
+    const int e = tid + 256 * q;
+    const int rr = e % R, j = e / R;
+    const int64_t row = bx * R + rr;
+    const bool ok = e < R * NN_NB && row < d && j0 + j < nb;
+    vpre[q] = (ok && V != nullptr) ? to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]) : 0.0;
+    mpre[q] = (ok && a.mask != nullptr) ? a.mask[j0 + j] : 0;
+  }
   ACC acc[NN_NB];
 #pragma unroll
   for (int j = 0; j < NN_NB; ++j) acc[j] = ACC(0);
@@ -199,40 +220,41 @@ __device__ __forceinline__ void nn_body(const NnArgs& a, int64_t bx, int by) {
       zs[e] = (ACC)z;
     }
     __syncthreads();
-    int i = g;
-    for (; i + (BATCH - 1) * G < tn; i += BATCH * G) {
+    // BATCH loads issued together per step, the tail guarded (one memory
+    // round trip per BATCH columns of A)
+    for (int i = g; i < tn; i += BATCH * G) {
       ACC av[BATCH];
 #pragma unroll
-      for (int u = 0; u < BATCH; ++u) av[u] = to_acc<ACC>(ar[(int64_t)(t0 + i + u * G) * lda]);
+      for (int u = 0; u < BATCH; ++u) {
+        const int ii = i + u * G;
+        av[u] = (ii < tn) ? to_acc<ACC>(ar[(int64_t)(t0 + ii) * lda]) : ACC(0);
+      }
 #pragma unroll
       for (int u = 0; u < BATCH; ++u) {
-        const ACC* zr = zs + (i + u * G) * NN_NB;
+        const int ii = i + u * G;
+        if (ii < tn) {
+          const ACC* zr = zs + ii * NN_NB;
 #pragma unroll
-        for (int j = 0; j < NN_NB; ++j) acc[j] += av[u] * zr[j];
+          for (int j = 0; j < NN_NB; ++j) acc[j] += av[u] * zr[j];
+        }
       }
-    }
-    for (; i < tn; i += G) {
-      const ACC av = to_acc<ACC>(ar[(int64_t)(t0 + i) * lda]);
-      const ACC* zr = zs + i * NN_NB;
-#pragma unroll
-      for (int j = 0; j < NN_NB; ++j) acc[j] += av * zr[j];
     }
   }
 #pragma unroll
   for (int j = 0; j < NN_NB; ++j) red[tid * (NN_NB + 1) + j] = acc[j];
   __syncthreads();
-  const TV* V = (const TV*)a.V;
-  TO* Out = (TO*)a.Out;
-  const double alpha = (a.alpha_p != nullptr) ? *a.alpha_p : a.alpha;
-  for (int e = tid; e < R * NN_NB; e += 256) {
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
+    const int e = tid + 256 * q;
+    if (e >= R * NN_NB) continue;
     const int rr = e % R, j = e / R;
     const int64_t row = bx * R + rr;
     if (row >= d || j0 + j >= nb) continue;
     ACC sacc = ACC(0);
     for (int u = 0; u < G; ++u) sacc += red[(u * R + rr) * (NN_NB + 1) + j];
     double o = (double)sacc;
-    if (alpha != 0.0) o += alpha * to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]);
-    if (a.mask != nullptr && a.mask[j0 + j] != 0) o = masked_gauss(a.seed, (int64_t)(j0 + j) * d + row);
+    if (alpha != 0.0) o += alpha * vpre[q];
+    if (mpre[q] != 0) o = masked_gauss(a.seed, (int64_t)(j0 + j) * d + row);
     const int64_t oi = a.out_row ? row * a.ldo + (j0 + j) : row + (int64_t)(j0 + j) * a.ldo;
     Out[oi] = from_f64<TO>(o);
   }
@@ -288,7 +310,9 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
 
 // Rows per nn workgroup: 64 when that still gives 384 workgroups (long
 // loops, little Z traffic), else 32, else 16 (more workgroups); chosen from
-// the largest entry.
+// the largest entry.  Loads per batch: 16 for small d (few workgroups, so
+// one memory round trip per lane matters most), else 4 or 8 (measured
+// faster for the streaming passes over P).
 template <typename TA, typename TV, typename TO, typename ACC>
 hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStream_t s) {
   int64_t dmax = 0, ymax = 0;
@@ -312,8 +336,10 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
     NN_GO(64, 8);
   else if (dmax / 32 >= 384)
     NN_GO(32, 8);
-  else
+  else if (dmax > 4096)
     NN_GO(16, 4);
+  else  // few workgroups (core products): all loads of a lane in one batch
+    NN_GO(16, 16);
 #undef NN_GO
   return hipGetLastError();
 }
