@@ -262,6 +262,7 @@ struct SyevArgs {    // one symmetric eigenproblem, see launch_syev
   double* w;
   double* Z;
   double* work;
+  double ctol = 0.0;  // cluster gap relative to ||T|| (0: 1e-3)
 };
 
 // Kernel-side selection of the argument source of a multi launch.
@@ -451,8 +452,12 @@ hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint6
 size_t syev_work_bytes(int64_t nmax);
 void syev_timing_enable(bool on);
 void syev_timing_report(FILE* f);
+// Eigenvectors of eigenvalues closer than ctol ||T|| (ctol <= 0: 1e-3) are
+// orthonormalised together; a smaller ctol saves that work where the
+// vectors need not be orthogonal to better than about u / ctol.
 hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
                        int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
-                       int64_t strideZ, int64_t nvec, double* work, hipStream_t s);
+                       int64_t strideZ, int64_t nvec, double* work, hipStream_t s,
+                       double ctol = 0.0);
 
 }  // namespace eda

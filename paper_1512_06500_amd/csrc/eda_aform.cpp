@@ -169,13 +169,19 @@ eda_status step(const AForm& F, int64_t m, bool repair) {
 
 // Rayleigh-Ritz on the leading m x m block of H (synchronous): top `cnt`
 // Ritz values (descending) and residual estimates on the host, flags too.
+// With cnt < kk (no restart follows) only cnt eigenvectors are formed, and
+// those of eigenvalues closer than 1e-3 ||T|| are orthonormalised together
+// only when closer than 1e-8 ||T|| (the final vectors are orthonormalised
+// again).
 eda_status ritz(const AForm& F, int64_t m, int64_t cnt, double* theta, double* est, int* fl) {
   eda_handle h = F.h;
   hipStream_t s = h->stream;
   const int64_t mm = F.mm;
+  const bool keep = cnt >= F.kk;
   HIPCHK(launch_symmetrize(m, F.H(F.cur), F.ldh, h->T.d(), mm, s));
   HIPCHK(launch_syev(1, m, nullptr, h->T.d(), mm, 0, h->wT.d(), 0, h->S.d(), mm, 0,
-                     std::min<int64_t>(m, F.kk), h->syev_work.d(), s));
+                     std::min<int64_t>(m, keep ? F.kk : cnt), h->syev_work.d(), s,
+                     keep ? 0.0 : 1e-8));
   const double* Bm = F.H(F.cur) + m + (m - F.b) * F.ldh;
   HIPCHK(launch_ritz_estimates(m, F.b, cnt, h->wT.d(), h->S.d(), mm, Bm, F.ldh, h->dtheta.d(),
                                h->dres.d(), s));

@@ -223,15 +223,22 @@ void log_pairs(const char* tag, int64_t m, int64_t cnt, const double* theta, con
   std::fprintf(stderr, "\n");
 }
 
+// Cluster tolerance of the eigensolver for checks whose Ritz vectors are
+// not kept in a restarted basis: their vectors only give residual estimates
+// (or are orthonormalised again at the end), so eigenvectors of eigenvalues
+// closer than 1e-3 ||T|| need not be orthonormalised together, only those
+// closer than 1e-8 ||T|| (orthogonal to about u / 1e-8 otherwise).
+constexpr double kCheckCtol = 1e-8;
+
 // Rayleigh-Ritz on Q[:, 0:m]: eigenpairs of sym(H[0:m,0:m]); returns the top
 // `cnt` Ritz values (descending) and residual estimates on the host.
 eda_status rayleigh_ritz(Solver& S, int64_t m, int64_t nvec, int64_t cnt, double* theta,
-                         double* est, int* flag0 = nullptr) {
+                         double* est, int* flag0 = nullptr, double ctol = 0.0) {
   eda_handle h = S.h;
   const int64_t ldh = S.ldh, mm = S.mmax;
   HIPCHK(launch_symmetrize(m, S.H(), ldh, h->T.d(), mm, h->stream));
   HIPCHK(launch_syev(1, m, nullptr, h->T.d(), mm, 0, h->wT.d(), 0, h->S.d(), mm, 0, nvec,
-                     h->syev_work.d(), h->stream));
+                     h->syev_work.d(), h->stream, ctol));
   const double* Bm = S.H() + m + (m - S.b) * ldh;
   HIPCHK(launch_ritz_estimates(m, S.b, cnt, h->wT.d(), h->S.d(), mm, Bm, ldh, h->dtheta.d(),
                                h->dres.d(), h->stream));
@@ -258,7 +265,7 @@ eda_status rr_launch_async(Solver& S, int64_t m, int64_t nvec, int64_t cnt) {
   HIPCHK(hipStreamWaitEvent(a, h->ev_main, 0));
   HIPCHK(launch_symmetrize(m, S.H(), ldh, h->T.d(), mm, a));
   HIPCHK(launch_syev(1, m, nullptr, h->T.d(), mm, 0, h->wT.d(), 0, h->S.d(), mm, 0, nvec,
-                     h->syev_work.d(), a));
+                     h->syev_work.d(), a, kCheckCtol));
   const double* Bm = S.H() + m + (m - S.b) * ldh;
   HIPCHK(launch_ritz_estimates(m, S.b, cnt, h->wT.d(), h->S.d(), mm, Bm, ldh, h->dtheta.d(),
                                h->dres.d(), a));
@@ -613,15 +620,18 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     }
     const bool due_now = check_due(can_check) || (can_check && must_sync);
     if (due_now && async_checks && !must_sync) {
-      STCHK(rr_launch_async(S, m, std::min<int64_t>(nvec, m), t));
+      STCHK(rr_launch_async(S, m, std::min<int64_t>(t, m), t));
       pending = true;
       pend_m = m;
       pend_iter = iters;
       if (check_every == 0) next_check = iters + 2;  // refined when the verdict is read
     } else if (due_now) {
+      // a restart keeps kk Ritz vectors in the basis: those must be
+      // orthonormal (default cluster tolerance); a plain check needs t
       const int64_t cnt = need_restart ? S.kk : t;
       int f2 = 0;
-      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), cnt, theta.data(), est.data(), &f2));
+      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(need_restart ? nvec : t, m), cnt, theta.data(),
+                          est.data(), &f2, need_restart ? 0.0 : kCheckCtol));
       m_rr = m;
       if (f2 != 0 && !safe) { redo = true; break; }
       if (!finite_pairs(cnt)) return fail(h, EDA_ERR_NONFINITE, "non-finite Ritz pair in the Krylov phase");
@@ -648,8 +658,8 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
       }
     } else if (iters >= max_iter) {
       int f2 = 0;
-      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), std::min<int64_t>(t, m), theta.data(),
-                          est.data(), &f2));
+      STCHK(rayleigh_ritz(S, m, std::min<int64_t>(t, m), std::min<int64_t>(t, m), theta.data(),
+                          est.data(), &f2, kCheckCtol));
       m_rr = m;
       if (f2 != 0 && !safe) { redo = true; break; }
       break;
@@ -664,7 +674,8 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   }
   if (m_rr != m || m < t) {
     if (m < t) return fail(h, EDA_ERR_NOCONV, "basis smaller than t at the iteration limit");
-    STCHK(rayleigh_ritz(S, m, std::min<int64_t>(nvec, m), t, theta.data(), est.data()));
+    STCHK(rayleigh_ritz(S, m, std::min<int64_t>(t, m), t, theta.data(), est.data(), nullptr,
+                        kCheckCtol));
   }
 
   // Ritz vectors Y = Q S_t in float64 (theta in dtheta)

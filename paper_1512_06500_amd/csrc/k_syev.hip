@@ -175,7 +175,7 @@ __device__ void tri_factor(int n, const double* __restrict__ D, const double* __
   for (int k = 0; k < n - 1; ++k) {
     const double ek = ee[k];
     const double an = D[k + 1] - lam;
-    const double en = (k + 1 < n - 1) ? ee[k + 1] : 0.0;
+    const double en = (k + 1 < n - 1) ? ee[k + 1] : 0.0;  // (D and ee are in LDS)
     if (fabs(p) >= fabs(ek)) {
       if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
       const double inv = 1.0 / p;
@@ -220,20 +220,20 @@ __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
   const double* Pv = lu + 4 * nmax * NT;
 #define LU(arr, k) arr[(int64_t)(k) * NT]
 #define YV(k) y[(int64_t)(k) * ys]
-  // Loads are issued four steps at a time: each original entry is read once,
-  // before the step that overwrites it.
+  // Loads are issued eight steps at a time: each original entry is read
+  // once, before the step that overwrites it.
   double carry = YV(0);
   int k = 0;
-  for (; k + 4 <= n - 1; k += 4) {
-    double yb[4], pv[4], lm[4];
+  for (; k + 8 <= n - 1; k += 8) {
+    double yb[8], pv[8], lm[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       yb[q] = YV(k + 1 + q);
       pv[q] = LU(Pv, k + q);
       lm[q] = LU(Lm, k + q);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       double a = carry, b = yb[q];
       if (pv[q] != 0.0) {
         const double t = a;
@@ -258,22 +258,22 @@ __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
   const double big = 0x1.0p300, small = 0x1.0p-300;
   double x2 = 0.0, x1 = 0.0;  // x[k+2], x[k+1]
   k = n - 1;
-  for (; k >= 3; k -= 4) {
-    double yv[4], u1[4], u2[4], u3[4];
+  for (; k >= 7; k -= 8) {
+    double yv[8], u1[8], u2[8], u3[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       yv[q] = YV(k - q);
       u1[q] = LU(U1, k - q);
       u2[q] = LU(U2, k - q);
       u3[q] = LU(U3, k - q);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       double x = (yv[q] - u2[q] * x1 - u3[q] * x2) * u1[q];
       if (!(fabs(x) < big)) {
         for (int j = 0; j < n; ++j) YV(j) *= small;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) yv[r] *= small;
+        for (int r = 0; r < 8; ++r) yv[r] *= small;
         x1 *= small;
         x2 *= small;
         x = (yv[q] - u2[q] * x1 - u3[q] * x2) * u1[q];
@@ -306,17 +306,35 @@ __device__ void random_start(int n, int i, double* y, int64_t ys) {
   }
 }
 
+// y / ||y||, one thread; loads in batches of 8 so that each batch costs one
+// memory round trip (y lives in global memory).
 __device__ void normalize_serial(int n, double* y, int64_t ys) {
   double mx = 0.0;
-  for (int k = 0; k < n; ++k) mx = fmax(mx, fabs(y[(int64_t)k * ys]));
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (k0 + u < n) ? y[(int64_t)(k0 + u) * ys] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) mx = fmax(mx, fabs(v[u]));
+  }
   const double inv = (mx > 0.0) ? 1.0 / mx : 1.0;
   double nrm = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double v = y[(int64_t)k * ys] * inv;
-    nrm += v * v;
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (k0 + u < n) ? y[(int64_t)(k0 + u) * ys] * inv : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) nrm += v[u] * v[u];
   }
   const double sc = inv / sqrt(nrm);
-  for (int k = 0; k < n; ++k) y[(int64_t)k * ys] *= sc;
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (k0 + u < n) ? y[(int64_t)(k0 + u) * ys] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < n) y[(int64_t)(k0 + u) * ys] = v[u] * sc;
+  }
 }
 
 __device__ void wave_normalize(int n, double* y, int64_t ys, int lane) {
@@ -370,12 +388,13 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
                                                   int64_t stridew, double* __restrict__ Zout,
                                                   int64_t ldz_, int64_t strideZ, int nvec_,
                                                   double* __restrict__ work, int64_t nmax,
-                                                  int lds_a, int timing) {
+                                                  int lds_a, int timing, double ctol_) {
   constexpr int NW = NT / 64;
   constexpr int DU = NT > 512 ? 4 : 8;  // dot-product unroll within the register budget
   extern __shared__ double smem[];
   const int q = blockIdx.x;
   int n, nvec_req;
+  double ctol_rel = ctol_;
   int64_t lda, ldz;
   const double* Aq;
   double *wq, *Zq, *wk;
@@ -385,6 +404,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
     lda = a.lda;
     ldz = a.ldz;
     nvec_req = (int)a.nvec;
+    ctol_rel = a.ctol;
     Aq = a.A;
     wq = a.w;
     Zq = a.Z;
@@ -830,13 +850,18 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   // ---- 3. eigenvectors of T by inverse iteration ---------------------------
   const int n0 = n - nv;  // first computed eigenvalue index
   const double tiny = eps * tnorm;
-  const double ctol = 1e-3 * tnorm;
+  const double ctol = (ctol_rel > 0.0 ? ctol_rel : 1e-3) * tnorm;
+  // the off-diagonal into LDS (Gc is free between the eigenvalue and the
+  // cluster phases), so the factorisation's loop reads no global memory
+  double* EL = Gc;
+  for (int i = tid; i < n - 1; i += NT) EL[i] = ee[i];
+  __syncthreads();
   for (int slot0 = 0; slot0 < nv; slot0 += NT) {
     const int slot = slot0 + tid;
     if (slot < nv) {
       const int i = n0 + slot;
       double* lu = lub + tid;
-      tri_factor<NT>(n, D, ee, lamv[i], tiny, lu, nmax);
+      tri_factor<NT>(n, D, EL, lamv[i], tiny, lu, nmax);
       double* y = Zt + slot;
       random_start(n, i, y, nv);
       // two solves from a random start: with lambda accurate to a few ulps of
@@ -1073,7 +1098,7 @@ template <int NT>
 hipError_t syev_launch_t(const SyevArgs* sarr, int64_t batch, int64_t n, const int* ns,
                          const double* A, int64_t lda, int64_t strideA, double* w, int64_t stridew,
                          double* Z, int64_t ldz, int64_t strideZ, int64_t nvec, double* work,
-                         hipStream_t s) {
+                         hipStream_t s, double ctol) {
   const bool lds_a = n <= kLdsMax && NT <= 512;
   const size_t lds = (size_t)syev_lds_doubles(n, lds_a) * sizeof(double);
   static bool attr_set = false;
@@ -1085,7 +1110,7 @@ hipError_t syev_launch_t(const SyevArgs* sarr, int64_t batch, int64_t n, const i
   }
   hipLaunchKernelGGL(syev_kernel<NT>, dim3((unsigned)batch), dim3(NT), lds, s, sarr, (int)n, ns, A,
                      lda, strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n, lds_a ? 1 : 0,
-                     syev_timing ? 1 : 0);
+                     syev_timing ? 1 : 0, ctol);
   return hipGetLastError();
 }
 
@@ -1109,18 +1134,18 @@ size_t syev_work_bytes(int64_t nmax) {
 
 hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
                        int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
-                       int64_t strideZ, int64_t nvec, double* work, hipStream_t s) {
+                       int64_t strideZ, int64_t nvec, double* work, hipStream_t s, double ctol) {
   if (n < 1 || n > SYEV_NMAX || batch < 1) return hipErrorInvalidValue;
   // workgroup size by measurement: 256 threads up to n = 48, 512 while the
   // matrix fits in LDS, 1024 for the global-memory path
   if (n <= 48)
     return syev_launch_t<256>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
-                              nvec, work, s);
+                              nvec, work, s, ctol);
   if (n <= kLdsMax)
     return syev_launch_t<512>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
-                              nvec, work, s);
+                              nvec, work, s, ctol);
   return syev_launch_t<1024>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
-                             nvec, work, s);
+                             nvec, work, s, ctol);
 }
 
 // Several problems of different size: `dev` holds the count entries on the
@@ -1136,16 +1161,17 @@ hipError_t launch_syev_multi(int count, const SyevArgs* host, const SyevArgs* de
   if (nmax == 0) return hipSuccess;
   if (count == 1) {
     const SyevArgs& a = host[0];
-    return launch_syev(1, a.n, nullptr, a.A, a.lda, 0, a.w, 0, a.Z, a.ldz, 0, a.nvec, a.work, s);
+    return launch_syev(1, a.n, nullptr, a.A, a.lda, 0, a.w, 0, a.Z, a.ldz, 0, a.nvec, a.work, s,
+                       a.ctol);
   }
   if (nmax <= 48)
     return syev_launch_t<256>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
-                              0, nullptr, s);
+                              0, nullptr, s, 0.0);
   if (nmax <= kLdsMax)
     return syev_launch_t<512>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
-                              0, nullptr, s);
+                              0, nullptr, s, 0.0);
   return syev_launch_t<1024>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
-                             0, nullptr, s);
+                             0, nullptr, s, 0.0);
 }
 
 }  // namespace eda
