@@ -146,6 +146,57 @@ def mixed_vs_f64(torch, eda, reps: int = 3) -> dict:
     return out
 
 
+def large_fp8_vs_f64(torch, eda, reps: int = 3) -> dict:
+    """The large FP8 workload (d = 65536, n = 2000, k = 100, t = 99, tol
+    1e-6): float64 solve against FP8 E4M3 storage with a float32 basis and
+    float64 refinement (solve phase only, preparation shared per storage),
+    with the exponential product's bandwidth for each storage type."""
+    import datagen
+    from tests.golden.make_golden import read as read_golden
+    p = datagen.config("C5")
+    g = read_golden("C5")
+    h = eda.Handle()
+    H_W, H_B = h.scatter_factors(_upload(torch, p.X), p.counts.tolist())
+    N = p.n + p.k
+    out = {"workload": f"d={p.d}, k={p.k} x n_j={p.n // p.k} (n={p.n}), t={p.t}, block 8, "
+                       f"tol {p.tol:g}"}
+    for tag, storage, basis in (("f64", "f64", "f64"), ("fp8", "fp8", "f32")):
+        h.prepare(H_W, H_B, storage=storage)
+        V = torch.randn(8, p.d, dtype=torch.float64, device="cuda").t()
+        o = torch.empty_like(V.t()).t()
+        for _ in range(3):
+            h.opmv("M", V, out=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            h.opmv("M", V, out=o)
+        torch.cuda.synchronize()
+        op_s = (time.perf_counter() - t0) / 10
+        sp = {"f64": 8, "fp8": 1}[storage]
+        op_bytes = 2.0 * p.d * N * sp + 3.0 * p.d * 8 * 8
+        r = h.solve(p.t, p.tol, block=8, seed=p.seed, krylov_dtype=basis)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = h.solve(p.t, p.tol, block=8, seed=p.seed, krylov_dtype=basis)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        lam_err = np.abs(np.array(r.ritz) - g["lam"]) / np.array(g["lam"])
+        out[tag] = {"solves_per_s": 1.0 / el, "ms": 1e3 * el, "status": r.status,
+                    "storage": storage, "basis": basis, "iters": r.info["iters"],
+                    "refine_passes": r.info["refine_passes"],
+                    "krylov_ms": r.info["t_krylov_ms"], "refine_ms": r.info["t_refine_ms"],
+                    "resid_max": max(r.resid),
+                    "lam_rel_err_max_over_floor": float(np.max(lam_err / np.maximum(
+                        1e-6, g["pair_floor"]))),
+                    "exp_op": {"us": op_s * 1e6, "algorithmic_bytes": op_bytes,
+                               "GB_per_s": op_bytes / op_s / 1e9,
+                               "frac_of_hbm_peak": op_bytes / op_s / 1e9 / HBM_PEAK_GBPS}}
+    out["ratio_fp8_over_f64"] = out["fp8"]["solves_per_s"] / out["f64"]["solves_per_s"]
+    h.close()
+    return out
+
+
 def solve_variants(torch, eda, reps: int = 5) -> dict:
     """Lanczos-form Krylov solve, Arnoldi-form Krylov solve and reduced
     direct solve, solve phase only (the preparation is shared), at C1 and C2."""
@@ -311,6 +362,7 @@ def main():
     if not args.no_extra:
         out["mixed_vs_f64"] = mixed_vs_f64(torch, eda)
         out["solve_variants"] = solve_variants(torch, eda)
+        out["large_fp8_vs_f64"] = large_fp8_vs_f64(torch, eda)
         out["batched"] = batched(torch, eda)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)

@@ -148,10 +148,12 @@ eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k,
 
 /* Preprocessing of Algorithm 2 (steps 1-4), in Gram form.
  * H_W: device, d x n float64 (ldw >= d); H_B: device, d x k float64 (ldb >= d).
- * Requires d >= 2, k >= 2, n >= k.  The factors are copied into library
- * storage P = [H_W H_B] in `storage` precision (EDA_F64, EDA_F32 or
- * EDA_BF16; a narrower storage also keeps a float64 master copy, used for
- * the Gram matrix, the refinement stage of eda_solve and the back-transform),
+ * Requires d >= 2, 2 <= k <= n <= 2048.  The factors are copied into library
+ * storage P = [H_W H_B] in `storage` precision (EDA_F64, EDA_F32, EDA_BF16, or
+ * EDA_FP8_E4M3 with one float64 scale per column: column j is stored as
+ * E4M3(P(:, j) / s_j), s_j = max |P(:, j)| / 448; a narrower storage also
+ * keeps a float64 master copy, used for the Gram matrix, the refinement
+ * stage of eda_solve and the back-transform),
  * the Gram matrix P^T P is formed in float64, eig(H_B^T H_B) (and, when
  * requested, eig(H_W^T H_W)) are computed in float64, and the cores of the
  * exponentials are built.
@@ -224,7 +226,7 @@ eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* 
  * eigensolve of size n + k, one of size r, small GEMMs and three streaming
  * passes.  Uses the float64 factors of the preparation.  resid[i] is
  * ||e^{-s} M y_i - theta_i y_i|| / theta_i (one more product).  Requires
- * 1 <= t <= min(128, rank P), t < d.  info: iters = 0; t_krylov_ms holds the
+ * 1 <= t <= min(128, rank P), t < d, n + k <= 2048.  info: iters = 0; t_krylov_ms holds the
  * time of the whole solve.  Synchronises. */
 eda_status eda_solve_direct(eda_handle h, int32_t t, double* ritz, double* ritz_log, double* X,
                             int64_t ldx, double* resid, eda_info* info);

@@ -387,7 +387,8 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
                          int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
   if (h == nullptr) return EDA_ERR_ARG;
   if (d < 2 || k < 2 || n < k) return fail(h, EDA_ERR_ARG, "need d>=2, k>=2, n>=k");
-  if (n + k > 2048) return fail(h, EDA_ERR_ARG, "n+k=%lld exceeds 2048", (long long)(n + k));
+  // the dense eigensolves of the preparation are of sizes k and (on request) n
+  if (n > 2048) return fail(h, EDA_ERR_ARG, "n=%lld exceeds 2048", (long long)n);
   if (H_W == nullptr || H_B == nullptr) return fail(h, EDA_ERR_ARG, "null factor");
   if (ldw < d || ldb < d) return fail(h, EDA_ERR_ARG, "leading dimensions must be >= d");
   if (storage != EDA_F64 && storage != EDA_F32 && storage != EDA_BF16 && storage != EDA_FP8_E4M3)

@@ -39,6 +39,8 @@ extern "C" eda_status eda_solve_direct(eda_handle h, int32_t t, double* ritz, do
   const int64_t d = h->d, N = h->N;
   if (t < 1 || t >= d || t > N) return fail(h, EDA_ERR_ARG, "need 1 <= t < d and t <= n + k");
   if (t > 128) return fail(h, EDA_ERR_ARG, "t > 128 is not supported");
+  if (N > 2048) return fail(h, EDA_ERR_ARG, "n + k = %lld exceeds 2048 (dense eigensolve)",
+                            (long long)N);
   if (ritz == nullptr || ritz_log == nullptr || X == nullptr || resid == nullptr)
     return fail(h, EDA_ERR_ARG, "null output pointer");
   if (ldx < d) return fail(h, EDA_ERR_ARG, "ldx must be >= d");

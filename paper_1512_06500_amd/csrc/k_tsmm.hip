@@ -26,6 +26,8 @@
 // R rows x G = 256/R column groups (column j goes to group j mod G), so every
 // lane issues m/G independent loads in batches, reading rows of Z from an LDS
 // copy.  The G partial sums of a row are added in a fixed order through LDS.
+#include <type_traits>
+
 #include "common.h"
 
 namespace eda {
@@ -39,91 +41,108 @@ constexpr int NN_ZT = 512;  // rows of Z per LDS tile
 
 template <typename T> __device__ __forceinline__ double ld64(const T* p) { return to_f64<T>(*p); }
 
-// A^T B partial over one row chunk and one 16-column tile of A, nb <= 16 per
-// z-tile.  part[(chunk * m + i) * nb + j].  S: 64-row steps per wave.
-// blockIdx.x: row chunk, blockIdx.y: column tile + ytiles * (nb tile),
+// A^T B partial over one row chunk and CT consecutive 16-column tiles of A,
+// nb <= 16 per z-tile: part[(chunk * m + i) * nb + j].  S: 64-row steps per
+// wave.  The B rows of a step are loaded once and used for all CT tiles, so
+// a wide A (many columns) does not re-read B once per 16 columns.
+// blockIdx.x: row chunk, blockIdx.y: tile group + ygroups * (nb tile),
 // blockIdx.z: problem.
-template <typename TA, typename TB, int S>
-__device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yt, int zt) {
+template <typename TA, typename TB, int S, int CT>
+__device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yg, int zt) {
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
-  if (chunk >= a.chunks || yt * 16 >= m || zt * 16 >= nb) return;
-  __shared__ f64x4 red[3][64];
+  const int yt0 = yg * CT;
+  if (chunk >= a.chunks || yt0 * 16 >= m || zt * 16 >= nb) return;
+  __shared__ f64x4 red[3][CT][64];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int c0 = yt * 16;
   const int j0 = zt * 16;
   const int i = lane & 15, q = lane >> 4;
-  const bool cok = (c0 + i) < m;
   const bool bok = (j0 + i) < nb;
-  const TA* ap = (const TA*)a.A + (int64_t)(cok ? c0 + i : c0) * a.lda;
   const TB* bp = (const TB*)a.B + (int64_t)(bok ? j0 + i : j0) * a.ldb;
   const int64_t r0 = chunk * (int64_t)(256 * S) + (int64_t)wid * (64 * S);
   const int64_t r1 = (r0 + 64 * S < d) ? r0 + 64 * S : d;
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  f64x4 acc[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) acc[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int64_t rb = r0 + 64 * s;
     if (rb >= r1) break;
     const int64_t rs = rb + 16 * q;
-    double av[16], bv[16];
-    if (rb + 64 <= r1) {
-      if constexpr (sizeof(TA) == 1) {  // FP8: the 16 bytes of a lane in one load
-        const uint4 w = *(const uint4*)((const uint8_t*)ap + rs);
-        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    const bool full = rb + 64 <= r1;
+    double bv[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
-          av[e] = cok ? (double)fp8e4m3_decode((uint8_t)(ws[e >> 2] >> (8 * (e & 3)))) : 0.0;
+    for (int e = 0; e < 16; ++e) {
+      const bool ok = full || rs + e < r1;
+      const double y = ld64(bp + (ok ? rs + e : rb));
+      bv[e] = (bok && ok) ? y : 0.0;
+    }
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const double y = ld64(bp + rs + e);
-          bv[e] = bok ? y : 0.0;
+    for (int ct = 0; ct < CT; ++ct) {
+      const int c0 = (yt0 + ct) * 16;
+      if (c0 >= m) break;
+      const bool cok = (c0 + i) < m;
+      const TA* ap = (const TA*)a.A + (int64_t)(cok ? c0 + i : c0) * a.lda;
+      double av[16];
+      if (full) {
+        if constexpr (sizeof(TA) == 1) {  // FP8: the 16 bytes of a lane in one load
+          const uint4 w = *(const uint4*)((const uint8_t*)ap + rs);
+          const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int e = 0; e < 16; ++e)
+            av[e] = cok ? (double)fp8e4m3_decode((uint8_t)(ws[e >> 2] >> (8 * (e & 3)))) : 0.0;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const double x = ld64(ap + rs + e);
+            av[e] = cok ? x : 0.0;
+          }
         }
       } else {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const double x = ld64(ap + rs + e), y = ld64(bp + rs + e);
-          av[e] = cok ? x : 0.0;
-          bv[e] = bok ? y : 0.0;
+          const bool ok = rs + e < r1;
+          const double x = ld64(ap + (ok ? rs + e : rb));
+          av[e] = (cok && ok) ? x : 0.0;
         }
       }
-    } else {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const bool ok = rs + e < r1;
-        const int64_t rr = ok ? rs + e : rb;
-        const double x = ld64(ap + rr), y = ld64(bp + rr);
-        av[e] = (cok && ok) ? x : 0.0;
-        bv[e] = (bok && ok) ? y : 0.0;
-      }
+      for (int e = 0; e < 16; ++e)
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[e], acc[ct], 0, 0, 0);
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[e], acc, 0, 0, 0);
   }
-  if (wid > 0) red[wid - 1][lane] = acc;
+  if (wid > 0)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) red[wid - 1][ct][lane] = acc[ct];
   __syncthreads();
   if (wid == 0) {
-#pragma unroll
-    for (int w = 0; w < 3; ++w) acc += red[w][lane];
     // accumulator layout: lane l, element v holds row 4 v + l / 16, column l % 16
     const int jj = lane & 15, ib = lane >> 4;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int ii = 4 * v + ib;
-      if (c0 + ii < m && j0 + jj < nb)
-        a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] =
-            (a.ascale != nullptr) ? acc[v] * a.ascale[c0 + ii] : acc[v];
+    for (int ct = 0; ct < CT; ++ct) {
+      f64x4 t = acc[ct];
+#pragma unroll
+      for (int w = 0; w < 3; ++w) t += red[w][ct][lane];
+      const int c0 = (yt0 + ct) * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ii = 4 * v + ib;
+        if (c0 + ii < m && j0 + jj < nb)
+          a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] =
+              (a.ascale != nullptr) ? t[v] * a.ascale[c0 + ii] : t[v];
+      }
     }
   }
   __syncthreads();  // red may be reused by a caller that loops over work items
 }
 
-template <typename TA, typename TB, int S>
+template <typename TA, typename TB, int S, int CT>
 __global__ __launch_bounds__(256) void tn_mfma_kernel(const TnArgs* __restrict__ arr, TnArgs one,
-                                                      int ytiles) {
+                                                      int ygroups) {
   const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
-  tn_body<TA, TB, S>(a, blockIdx.x, blockIdx.y % ytiles, blockIdx.y / ytiles);
+  tn_body<TA, TB, S, CT>(a, blockIdx.x, blockIdx.y % ygroups, blockIdx.y / ygroups);
 }
 
 // Sum of the chunk partials, fixed order: wave w adds chunks w, w+4, ... of
@@ -268,6 +287,136 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
   nn_body<TA, TV, TO, ACC, R, BATCH>(a, blockIdx.x, blockIdx.y);
 }
 
+// nn for a narrow A (FP8 or bfloat16 entries).  A lane owns 8 consecutive
+// rows and reads them with one 8-byte (FP8) or 16-byte (bfloat16) load per
+// column: a wave instruction then moves 512 or 1024 contiguous bytes
+// instead of one entry per lane.  Lane (rl = l % 16, gq = l / 16) of wave w
+// takes rows 8 rl .. 8 rl + 7 of the workgroup's 128 and the columns
+// j = g mod 16, g = 4 w + gq; the 4 column groups of a wave are summed by
+// lane exchanges, the 4 waves through LDS, both in a fixed order.
+constexpr int NNN_R = 128;  // rows per workgroup of the narrow nn
+template <typename TA, typename TV, typename TO, typename ACC>
+__device__ __forceinline__ void nn_narrow_body(const NnArgs& a, int64_t bx, int by) {
+  constexpr int NR = 8, BATCH = 8, G = 16;
+  using RAW = typename std::conditional<sizeof(TA) == 1, uint2, uint4>::type;
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const int j0 = by * NN_NB;
+  if (bx * NNN_R >= d || j0 >= nb) return;
+  __shared__ ACC zs[NN_ZT * NN_NB];
+  __shared__ ACC red[4][NNN_R][NN_NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int rl = lane & 15, gq = lane >> 4, g = 4 * w + gq;
+  const int64_t row0 = bx * NNN_R + 8 * rl;
+  const bool rok = row0 < a.lda;  // rows d .. lda-1 of A are zero padding
+  const int64_t lda = a.lda;
+  const char* abase = (const char*)a.A + row0 * (int64_t)sizeof(TA);
+  const TV* V = (const TV*)a.V;
+  TO* Out = (TO*)a.Out;
+  constexpr int NO = (NNN_R * NN_NB + 255) / 256;
+  const double alpha = (a.alpha_p != nullptr) ? *a.alpha_p : a.alpha;
+  double vpre[NO];
+  int mpre[NO];
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
+    const int e = tid + 256 * q;
+    const int rr = e % NNN_R, j = e / NNN_R;
+    const int64_t row = bx * NNN_R + rr;
+    const bool ok = row < d && j0 + j < nb;
+    vpre[q] = (ok && V != nullptr) ? to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]) : 0.0;
+    mpre[q] = (ok && a.mask != nullptr) ? a.mask[j0 + j] : 0;
+  }
+  ACC acc[NR][NN_NB];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int j = 0; j < NN_NB; ++j) acc[r][j] = ACC(0);
+  for (int t0 = 0; t0 < m; t0 += NN_ZT) {
+    const int tn = (m - t0 < NN_ZT) ? m - t0 : NN_ZT;
+    __syncthreads();
+    for (int e = tid; e < tn * NN_NB; e += 256) {
+      const int i = e / NN_NB, j = e - i * NN_NB;
+      double z = (j0 + j < nb) ? a.Z[(int64_t)(t0 + i) * a.ldz + j0 + j] : 0.0;
+      if (a.ascale != nullptr) z *= a.ascale[t0 + i];
+      zs[e] = (ACC)z;
+    }
+    __syncthreads();
+    for (int i = g; i < tn; i += G * BATCH) {
+      RAW raw[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int ii = i + G * u;
+        if (ii < tn && rok)
+          raw[u] = *(const RAW*)(abase + (int64_t)(t0 + ii) * lda * (int64_t)sizeof(TA));
+        else
+          raw[u] = RAW{};
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int ii = i + G * u;
+        if (ii >= tn) continue;
+        ACC av[NR];
+        if constexpr (sizeof(TA) == 1) {
+          const uint32_t ws[2] = {raw[u].x, raw[u].y};
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            av[r] = (ACC)fp8e4m3_decode((uint8_t)(ws[r >> 2] >> (8 * (r & 3))));
+        } else {
+          const uint32_t ws[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const uint32_t h = (ws[r >> 1] >> (16 * (r & 1))) & 0xffffu;
+            av[r] = (ACC)__uint_as_float(h << 16);  // bfloat16 -> float, exact
+          }
+        }
+        const ACC* zr = zs + ii * NN_NB;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int j = 0; j < NN_NB; ++j) acc[r][j] += av[r] * zr[j];
+      }
+    }
+  }
+  // column groups gq = 0..3 of the wave hold the same rows: (0 + 1) + (2 + 3)
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int j = 0; j < NN_NB; ++j) {
+      ACC v = acc[r][j];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      acc[r][j] = v;
+    }
+  if (gq == 0)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < NN_NB; ++j) red[w][8 * rl + r][j] = acc[r][j];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
+    const int e = tid + 256 * q;
+    if (e >= NNN_R * NN_NB) continue;
+    const int rr = e % NNN_R, j = e / NNN_R;
+    const int64_t row = bx * NNN_R + rr;
+    if (row >= d || j0 + j >= nb) continue;
+    const ACC sacc = ((red[0][rr][j] + red[1][rr][j]) + red[2][rr][j]) + red[3][rr][j];
+    double o = (double)sacc;
+    if (alpha != 0.0) o += alpha * vpre[q];
+    if (mpre[q] != 0) o = masked_gauss(a.seed, (int64_t)(j0 + j) * d + row);
+    const int64_t oi = a.out_row ? row * a.ldo + (j0 + j) : row + (int64_t)(j0 + j) * a.ldo;
+    Out[oi] = from_f64<TO>(o);
+  }
+  __syncthreads();
+}
+
+template <typename TA, typename TV, typename TO, typename ACC>
+__global__ __launch_bounds__(256) void nn_narrow_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
+  const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  nn_narrow_body<TA, TV, TO, ACC>(a, blockIdx.x, blockIdx.y);
+}
+
 // 64 S rows per wave, 4 waves per workgroup: S = 4 when that still gives
 // 1024 workgroups, else 2, else 1 (chosen from the largest entry).
 int tn_steps(int64_t d, int64_t m) {
@@ -298,13 +447,30 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
   if (cmax == 0) return hipSuccess;
   const TnArgs one = (count == 1) ? host[0] : TnArgs{};
   const TnArgs* arr = (count == 1) ? nullptr : dev;
-  dim3 g((unsigned)cmax, (unsigned)(ymax * zmax), (unsigned)count);
-  if (S == 4)
-    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 4>), g, dim3(256), 0, s, arr, one, (int)ymax);
-  else if (S == 2)
-    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 2>), g, dim3(256), 0, s, arr, one, (int)ymax);
-  else
-    hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 1>), g, dim3(256), 0, s, arr, one, (int)ymax);
+  // column tiles per workgroup: doubled while the grid keeps 1024 workgroups
+  // (wide A: B is then read once per CT tiles instead of once per tile)
+  int CT = 1;
+  if (S == 4 && sizeof(TA) == 8)  // (narrow A is bound by its conversions, not by B)
+    while (CT < 8 && cmax * ((ymax + 2 * CT - 1) / (2 * CT)) * zmax * count >= 1024) CT *= 2;
+  const int64_t yg = (ymax + CT - 1) / CT;
+  dim3 g((unsigned)cmax, (unsigned)(yg * zmax), (unsigned)count);
+#define TN_GO(S_, CT_) \
+  hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, S_, CT_>), g, dim3(256), 0, s, arr, one, (int)yg)
+  if (S == 4) {
+    if (CT == 8)
+      TN_GO(4, 8);
+    else if (CT == 4)
+      TN_GO(4, 4);
+    else if (CT == 2)
+      TN_GO(4, 2);
+    else
+      TN_GO(4, 1);
+  } else if (S == 2) {
+    TN_GO(2, 1);
+  } else {
+    TN_GO(1, 1);
+  }
+#undef TN_GO
   return hipGetLastError();
 }
 
@@ -328,6 +494,19 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
   if (dmax == 0) return hipSuccess;
   const NnArgs one = (count == 1) ? host[0] : NnArgs{};
   const NnArgs* arr = (count == 1) ? nullptr : dev;
+  if constexpr (sizeof(TA) <= 2) {
+    // narrow A with 8-row-aligned columns (the padded storage of P): 8 rows
+    // per lane in one load
+    bool aligned = true;
+    for (int p = 0; p < count; ++p)
+      aligned = aligned && host[p].lda % 8 == 0 && ((uintptr_t)host[p].A % 16) == 0;
+    if (aligned) {
+      hipLaunchKernelGGL((nn_narrow_kernel<TA, TV, TO, ACC>),
+                         dim3((unsigned)((dmax + NNN_R - 1) / NNN_R), (unsigned)ymax, (unsigned)count),
+                         dim3(256), 0, s, arr, one);
+      return hipGetLastError();
+    }
+  }
 #define NN_GO(R_, B_)                                                                          \
   hipLaunchKernelGGL((nn_kernel<TA, TV, TO, ACC, R_, B_>),                                     \
                      dim3((unsigned)((dmax + R_ - 1) / R_), (unsigned)ymax, (unsigned)count), \

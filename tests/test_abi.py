@@ -58,7 +58,7 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     (100, 10, 3, 100, 50, 0),   # ldb < d
     (100, 10, 3, 100, 100, 9),  # unknown storage
     (100, 10, 3, 100, 100, 4),  # one past the last storage type
-    (4000, 2040, 10, 4000, 4000, 0),  # n + k > 2048
+    (5000, 2050, 10, 5000, 5000, 0),  # n > 2048
 ])
 def test_prepare_rejects_bad_arguments(lib, handle, d, n, k, ldw, ldb, storage):
     st = lib.eda_prepare(handle, d, n, k, FAKE, ldw, FAKE, ldb, storage)

@@ -602,6 +602,43 @@ def test_mixed_c3_full_size(torch, eda):
         h.close()
 
 
+def test_mixed_c5_fp8_full_size(torch, eda):
+    """d = 65536, k = 100, n = 2000, t = 99, tol 1e-6 (the large FP8
+    workload): FP8 E4M3 P with per-column scales, float32 basis, float64
+    refinement, against the oracle's exact reduction (and its stored values
+    in tests/golden) and the float64 GPU solve."""
+    from tests.golden.make_golden import read as read_golden
+    log("solve C5 full size: float64 and fp8+refinement (oracle reduction first)")
+    p = datagen.config("C5")
+    g = read_golden("C5")
+    case = Case("C5", p.X, p.counts, p.t)
+    red = O.eda_reduced(case.H_W, case.H_B, p.t)
+    # the stored values agree to the per-pair floor u lam_1 / lam_i (the
+    # reduced pencil is solved in a different summation order here)
+    assert np.all(np.abs(red.lam - g["lam"]) / red.lam
+                  <= np.maximum(1e-12, 10 * np.array(g["pair_floor"])))
+    fl = O.accuracy_floor(red.lam_all, p.t)
+    lam_tol = np.maximum(1e-5, 50 * U * red.lam[0] / red.lam)
+    ang_tol = max(1e-5, 50 * fl["span"])
+    log(f"  oracle done; span floor {fl['span']:.2e}")
+    for storage, basis in (("f64", "f64"), ("fp8", "f32")):
+        h, _, _ = prepared(torch, eda, case, storage=storage)
+        res = h.solve(p.t, p.tol, block=8, seed=3, krylov_dtype=basis)
+        lam = np.array(res.ritz)
+        relerr = np.abs(lam - red.lam) / red.lam
+        X = host(res.X)
+        ang = O.sin_angle(red.X, X)
+        log(f"  {storage}/{basis}: status={res.status} iters={res.info['iters']} "
+            f"restarts={res.info['restarts']} passes={res.info['refine_passes']} "
+            f"lam_err={relerr.max():.2e} sin={ang:.2e} krylov_ms={res.info['t_krylov_ms']:.1f} "
+            f"refine_ms={res.info['t_refine_ms']:.1f}")
+        assert res.status == 0, res.message
+        assert np.all(relerr <= lam_tol)
+        assert ang <= ang_tol
+        assert np.abs(X.T @ X - np.eye(p.t)).max() <= 1e-13
+        h.close()
+
+
 # ---------------------------------------------------------------------------
 # a9: many problems solved together
 # ---------------------------------------------------------------------------
