@@ -341,7 +341,7 @@ hipError_t launch_core_weights(int64_t n, const double* lam, double c, double sh
 // dst[r + c*ldd] = alpha * (trans ? src[c + r*lds] : src[r + c*lds]), rows x cols of dst.
 hipError_t launch_copy_block(int64_t rows, int64_t cols, double alpha, const double* src,
                              int64_t lds, bool trans, double* dst, int64_t ldd, hipStream_t s);
-// out[0] = max_j sum_i |A[i + j*lda]| (1-norm of an n x n matrix), one workgroup.
+// out[0] = max_j sum_i |A[i + j*lda]| (1-norm of an n x n matrix).
 hipError_t launch_norm1(int64_t n, const double* A, int64_t lda, double* out, hipStream_t s);
 // C = a0 I + a1 X1 + a2 X2 + a3 X3 (n x n; X2/X3 may be null when a2/a3 are 0).
 hipError_t launch_lincomb(int64_t n, double a0, double a1, const double* X1, double a2,

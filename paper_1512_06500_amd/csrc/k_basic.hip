@@ -304,22 +304,30 @@ __global__ __launch_bounds__(256) void set_diag_kernel(const SetDiagArgs* __rest
   if (i < a.cnt) a.D[i + i * a.ldd] = a.v[i];
 }
 
+// One wave per column (lanes over rows, coalesced), loads batched by eight;
+// the column sums meet in *out through an atomic maximum on their bit
+// patterns (non-negative doubles order like their unsigned 64-bit patterns).
+// *out must hold +0.0 before the launch.
 __global__ __launch_bounds__(256) void norm1_kernel(int64_t n, const double* __restrict__ A,
                                                     int64_t lda, double* __restrict__ out) {
-  __shared__ double red[256];
-  double best = 0.0;
-  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += fabs(A[i + j * lda]);
-    best = fmax(best, s);
+  const int lane = threadIdx.x & 63;
+  const int64_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const double* col = A + j * lda;
+  double s = 0.0;
+  for (int64_t i0 = lane; i0 < n; i0 += 64 * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + 64 * u;
+      v[u] = (i < n) ? fabs(col[i]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
   }
-  red[threadIdx.x] = best;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = red[0];
+  s = wave_sum(s);
+  if (lane == 0)
+    atomicMax((unsigned long long*)out, (unsigned long long)__double_as_longlong(s));
 }
 
 __global__ __launch_bounds__(256) void lincomb_kernel(int64_t n, double a0, double a1,
@@ -342,7 +350,10 @@ inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t
 }  // namespace
 
 hipError_t launch_norm1(int64_t n, const double* A, int64_t lda, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(norm1_kernel, dim3(1), dim3(256), 0, s, n, A, lda, out);
+  if (n <= 0) return hipSuccess;
+  const hipError_t e = launch_fill(1, 0.0, out, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(norm1_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, A, lda, out);
   return hipGetLastError();
 }
 

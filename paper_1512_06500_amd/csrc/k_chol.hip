@@ -232,12 +232,10 @@ __device__ int stage_small(const double* __restrict__ G, int64_t ldg,
   return gv;
 }
 
-// LDS use of chol_kernel (one b x b array, ld = CH_MAX + 1):
-//   during the factorisation the lower triangle holds the trailing matrix
-//   and the strict upper triangle receives R = L^T row by row (diagonal in
-//   rd), so a step reads only what no thread of that step writes and needs
-//   one barrier; afterwards X = R^{-1} goes to the strict lower triangle
-//   (X[i][c] at (c, i)), diagonal in xd.
+// LDS use of chol_kernel (one b x b array, ld = CH_MAX + 1): the Gram
+// matrix, then L in its lower triangle (diagonal also in rd); for b > 8 the
+// columns of L^{-1} go to the strict upper triangle (L^{-1}(r, c) at (c, r)),
+// their diagonal to xd.  Rprev (b <= 64) is staged in columns 64.. .
 __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ arr, CholArgs one) {
   const CholArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int b = (int)a.b;
@@ -339,91 +337,122 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
     if (tid == 0 && flag != nullptr && sflag) *flag = 1;
     return;
   }
-  const bool one_wave = b <= 16;  // then wave 0 factorises and inverts alone, without barriers
-  if (one_wave) {
+  // Wider blocks (8 < b <= 128): blocked right-looking factorisation with 8 x 8
+  // diagonal blocks, three barriers per block column.  Per block column
+  // kb: wave 0 factorises and inverts the diagonal block in registers (as
+  // above); every thread then takes rows of the panel below,
+  // L21 = A21 L11^{-T}; then the threads update the trailing lower
+  // triangle, A22 -= L21 L21^T.  L stays in the lower triangle of the LDS
+  // array, rd holds its diagonal.
+  __shared__ double Lis[CH_MAX / 8][64];  // L11^{-1} of every diagonal block, [kb][r * 8 + c]
+  const int nblk = (b + 7) / 8;
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = 8 * kb, kw = (b - k0 < 8) ? b - k0 : 8;
     if (wid == 0) {
-      const int r = lane;
-      const bool live = r < b;
-      for (int j = 0; j < b; ++j) {
-        double p = L[j + j * ld];
-        const double floor_ = 1e-28 * fabs(d0[j]) + 1e-300;
-        if (!(p > floor_)) {  // also catches NaN
-          p = floor_;
-          if (lane == 0) sflag = 1;
+      const int c = lane;
+      double col[8], fl[8], invd[8], pd[8], y[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const bool in = c < kw && r < kw;
+        const double g = in ? ((r >= c) ? L[(k0 + r) + (k0 + c) * ld] : L[(k0 + c) + (k0 + r) * ld])
+                            : 0.0;
+        col[r] = in ? g : ((r == c) ? 1.0 : 0.0);
+        fl[r] = (r < kw) ? 1e-28 * fabs(d0[k0 + r]) + 1e-300 : 0.0;
+      }
+      const int bad = chol8_regs(col, c, fl, invd, pd);
+      inv8_regs(col, c, invd, y);
+      if (c < kw) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          if (r >= c && r < kw) L[(k0 + r) + (k0 + c) * ld] = col[r];
+          if (r == c) rd[k0 + c] = col[r];
+          Lis[kb][r * 8 + c] = y[r];
         }
-        const double piv = sqrt(p), inv = 1.0 / piv;
-        if (lane == 0) rd[j] = piv;
-        const double lr = (r > j && live) ? L[r + j * ld] * inv : 0.0;
-        if (r > j && live) L[j + r * ld] = lr;
-        for (int c = j + 1; c < b; ++c) {
-          const double lc = readlane_f64(lr, c);
-          if (r >= c && live) L[r + c * ld] -= lr * lc;
-        }
-        wave_fence();
       }
+      if (bad && c < 8) sflag = 1;
     }
-  } else {
-    for (int j = 0; j < b; ++j) {
-      double p = L[j + j * ld];
-      const double floor_ = 1e-28 * fabs(d0[j]) + 1e-300;
-      if (!(p > floor_)) {  // also catches NaN
-        p = floor_;
-        if (tid == 0) sflag = 1;
+    __syncthreads();
+    const int p0 = k0 + kw;
+    // panel: L21[i][c] = sum_{q <= c} A21[i][q] (L11^{-1})[c][q]
+    for (int i = p0 + tid; i < b; i += blockDim.x) {
+      double av[8], o[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) av[q] = (q < kw) ? L[i + (k0 + q) * ld] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q <= c; ++q) sacc += av[q] * Lis[kb][c * 8 + q];
+        o[c] = sacc;
       }
-      const double piv = sqrt(p), inv = 1.0 / piv;
-      if (tid == 0) rd[j] = piv;
-      for (int i = j + 1 + tid; i < b; i += blockDim.x) L[j + i * ld] = L[i + j * ld] * inv;
-      for (int c = j + 1 + wid; c < b; c += nw) {
-        const double lc = L[c + j * ld] * inv;
-        for (int r = c + lane; r < b; r += 64) L[r + c * ld] -= (L[r + j * ld] * inv) * lc;
-      }
-      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < kw) L[i + (k0 + c) * ld] = o[c];
     }
+    __syncthreads();
+    // trailing lower triangle: A22 -= L21 L21^T
+    const int rem = b - p0;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int cc = e / rem, rr = e - cc * rem;
+      if (rr < cc) continue;
+      const int r = p0 + rr, c = p0 + cc;
+      double sacc = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < kw) sacc += L[r + (k0 + q) * ld] * L[c + (k0 + q) * ld];
+      L[r + c * ld] -= sacc;
+    }
+    __syncthreads();
   }
-  // X = R^{-1}, rows i = b-1 .. 0 in turn, the entries of a row in parallel:
-  //   X[i][i] = 1 / R[i][i],  X[i][c] = -(sum_{q=i+1..c} R[i][q] X[q][c]) / R[i][i]
-  if (!one_wave || wid == 0) {
-    const int nth = one_wave ? 64 : (int)blockDim.x;
-    const int me = one_wave ? lane : tid;
-    for (int i = b - 1; i >= 0; --i) {
-      const double ri = rd[i];
-      for (int c = i + me; c < b; c += nth) {
-        if (c == i) {
-          xd[i] = 1.0 / ri;
-        } else {
-          double s = L[i + c * ld] * xd[c];
-          for (int q = i + 1; q < c; ++q) s += L[i + q * ld] * L[c + q * ld];
-          L[c + i * ld] = -s / ri;
-        }
-      }
-      if (one_wave)
-        wave_fence();
-      else
-        __syncthreads();
+  // Y = L^{-1} by block rows I (rows r0 .. r0+kw-1), two barriers each:
+  //   T(r, c) = sum_{k=c}^{r0-1} L(r, k) Y(k, c)  for c < r0 (earlier block rows final),
+  //   Y(r, c) = -(L_II^{-1} T)(r, c),   Y_II = L_II^{-1}.
+  // Y(r, c), r > c, goes to the upper position (c, r), its diagonal to xd;
+  // then R^{-1} = Y^T: row i of R^{-1} is column i of Y.
+  __shared__ double Tb[8 * CH_MAX];
+  for (int I = 0; I < nblk; ++I) {
+    const int r0 = 8 * I, kw = (b - r0 < 8) ? b - r0 : 8;
+    for (int e = tid; e < kw * r0; e += blockDim.x) {
+      const int c = e / kw, j = e - c * kw;
+      double sacc = L[(r0 + j) + c * ld] * xd[c];
+      for (int k = c + 1; k < r0; ++k) sacc += L[(r0 + j) + k * ld] * L[c + k * ld];
+      Tb[j * CH_MAX + c] = sacc;
     }
+    __syncthreads();
+    for (int e = tid; e < kw * r0; e += blockDim.x) {
+      const int c = e / kw, j = e - c * kw;
+      double sacc = 0.0;
+      for (int q = 0; q <= j; ++q) sacc += Lis[I][j * 8 + q] * Tb[q * CH_MAX + c];
+      L[c + (r0 + j) * ld] = -sacc;
+    }
+    for (int e = tid; e < kw * kw; e += blockDim.x) {
+      const int j = e / kw, q = e - j * kw;
+      if (q < j)
+        L[(r0 + q) + (r0 + j) * ld] = Lis[I][j * 8 + q];
+      else if (q == j)
+        xd[r0 + j] = Lis[I][j * 8 + j];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int e = tid; e < b * b; e += blockDim.x) {
-    const int i = e / b, c = e - i * b;
-    Rinv[(int64_t)i * ldri + c] = (i < c) ? L[c + i * ld] : (i == c ? xd[c] : 0.0);
+    const int i = e / b, c = e - i * b;  // R^{-1}(i, c) = Y(c, i), zero for c < i
+    Rinv[(int64_t)i * ldri + c] = (c > i) ? L[i + c * ld] : (c == i ? xd[i] : 0.0);
   }
   if (Rout != nullptr) {
     for (int e = tid; e < b * b; e += blockDim.x) {
       const int c = e / b, r = e - c * b;
-      double s = 0.0;
+      // R(r, q) = L(q, r) for q >= r; (R Rprev)(r, c) = sum_{q >= r} R(r, q) Rprev(q, c)
+      double sacc = 0.0;
       if (Rprev == nullptr) {
-        s = (r < c) ? L[r + c * ld] : (r == c ? rd[r] : 0.0);
+        sacc = (r < c) ? L[c + r * ld] : (r == c ? rd[r] : 0.0);
+      } else if (RP != nullptr) {
+        sacc = rd[r] * RP[r + c * 64];
+        for (int q = r + 1; q < b; ++q) sacc += L[q + r * ld] * RP[q + c * 64];
       } else {
-        // (R * Rprev)[r, c] = sum_{q >= r} R[r, q] Rprev[q, c]  (R upper, Rprev general)
-        if (RP != nullptr) {
-          s = rd[r] * RP[r + c * 64];
-          for (int q = r + 1; q < b; ++q) s += L[r + q * ld] * RP[q + c * 64];
-        } else {
-          s = rd[r] * Rprev[r + c * ldrp];
-          for (int q = r + 1; q < b; ++q) s += L[r + q * ld] * Rprev[q + c * ldrp];
-        }
+        sacc = rd[r] * Rprev[r + c * ldrp];
+        for (int q = r + 1; q < b; ++q) sacc += L[q + r * ld] * Rprev[q + c * ldrp];
       }
-      Rout[r + c * ldro] = s;
+      Rout[r + c * ldro] = sacc;
     }
   }
   if (hcol != nullptr && tid < b) {
