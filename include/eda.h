@@ -218,6 +218,23 @@ eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* 
                      double* ritz, double* ritz_log, double* X, int64_t ldx,
                      double* resid, eda_info* info);
 
+/* Autotuner of the product passes (Theorem 3.1's two streaming passes over
+ * P, and every other tall-skinny product of the same shape class): measures
+ * each candidate launch shape for a d x N matrix stored as `storage` and a
+ * block of b float64 columns (1 <= b <= 16) on the handle's device, and
+ * records the fastest for the shape class (ceil(log2 d), ceil(log2 N),
+ * entry size) in a process-wide table used by every later launch; when the
+ * environment variable EDA_TUNE_CACHE names a file, the table is read from
+ * it once and rewritten after each tuning.  eda_solve_batched tunes the
+ * class of its largest problem by itself (EDA_AUTOTUNE=0 disables that).
+ * Outputs (host, each may be NULL): *tn_steps = 64-row steps per wave of the
+ * P^T V pass (1, 2 or 4); *nn_tile = configuration of the P Z pass (0..3,
+ * -1 for FP8/bfloat16 storage, which has one shape); us[0], us[1] = their
+ * measured times in microseconds.  Results of the products do not depend on
+ * the shapes beyond the order of partial sums.  Synchronises. */
+eda_status eda_autotune(eda_handle h, int64_t d, int64_t N, int32_t b, eda_dtype storage,
+                        int32_t* tn_steps, int32_t* nn_tile, double* us);
+
 /* Reduced direct solve of eq. (1.7): the same outputs as eda_solve, computed
  * without iteration.  Both exponentials are the identity plus a term in
  * span P (Theorem 3.1), so e^{-s} M restricted to span P is the r x r

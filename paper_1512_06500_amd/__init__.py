@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = [
     "eda_create", "eda_destroy", "eda_strerror", "eda_last_error", "eda_scatter_factors",
     "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_solve_direct", "eda_solve_batched",
     "eda_gram",
-    "eda_syev",
+    "eda_syev", "eda_autotune",
 ]
 
 
@@ -135,6 +135,9 @@ def load_library():
     L.eda_gram.restype = ctypes.c_int
     L.eda_syev.argtypes = [vp, i64, vp, i64, vp, vp, i64]
     L.eda_syev.restype = ctypes.c_int
+    L.eda_autotune.argtypes = [vp, i64, i64, i32, ctypes.c_int, ctypes.POINTER(i32),
+                               ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.eda_autotune.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -305,6 +308,15 @@ class Handle:
         if st not in (EDA_OK, EDA_ERR_NOCONV) and raise_on_error:
             raise EDAError(st, msg)
         return SolveResult(list(ritz), list(rlog), X, list(res), info.as_dict(), st, msg)
+
+    def autotune(self, d: int, N: int, b: int = 8, storage: str = "f64") -> dict:
+        """Measure and record the launch shapes of the product passes for a
+        d x N matrix in `storage` and b columns (eda_autotune)."""
+        tn, nn = ctypes.c_int32(), ctypes.c_int32()
+        us = (ctypes.c_double * 2)()
+        self._check(self.lib.eda_autotune(self._h, int(d), int(N), int(b), _DTYPES[storage],
+                                          ctypes.byref(tn), ctypes.byref(nn), us))
+        return {"tn_steps": tn.value, "nn_tile": nn.value, "tn_us": us[0], "nn_us": us[1]}
 
     def solve_direct(self, t: int, raise_on_error: bool = True, X=None) -> SolveResult:
         """The t leading pairs by the reduced direct solve (eda_solve_direct)."""

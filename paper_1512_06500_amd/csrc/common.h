@@ -382,6 +382,16 @@ hipError_t launch_restart_coupling(int64_t m, int64_t b, int64_t kk, const doubl
                                    int64_t ldbm, const double* Sd, int64_t ldsd, double* Hn,
                                    int64_t ldh, hipStream_t s);
 
+// Tile table (eda_tune.cpp): tuned launch shapes per shape class
+// (kind, ceil(log2 d), ceil(log2 m), entry bytes); -1 when not tuned.
+//   TnSteps: 64-row steps per wave of the tn kernel (1, 2 or 4), which fixes
+//            its chunk count (tn_chunks); NnTile: nn configuration index
+//            0 (16 rows, 4 loads per batch), 1 (16, 16), 2 (32, 8), 3 (64, 8).
+enum class TuneKind { TnSteps = 0, NnTile = 1 };
+constexpr int kNnConfigs = 4;
+int tune_get(TuneKind kind, int64_t d, int64_t m, int esize);
+void tune_set(TuneKind kind, int64_t d, int64_t m, int esize, int value);
+
 // k_tsmm.hip ----------------------------------------------------------------
 // Partial sums of A^T B over row chunks: part[(c*m + i)*nb + j], c < chunks.
 // Returns the number of chunks used through *chunks_out (computed from shape).

@@ -661,6 +661,19 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
   }
   STCHK(need_device(h));
   for (int32_t p = 0; p < count; ++p) STCHK(check_dev_ptr(h, probs[p].X, "X"));
+  {
+    // launch shapes of the product passes, measured once per shape class of
+    // the largest problem (EDA_AUTOTUNE=0 keeps the size heuristics)
+    int64_t dmax = 0, Nmax = 0;
+    for (int32_t p = 0; p < count; ++p) {
+      dmax = std::max<int64_t>(dmax, probs[p].d);
+      Nmax = std::max<int64_t>(Nmax, probs[p].n + probs[p].k);
+    }
+    const char* at = std::getenv("EDA_AUTOTUNE");
+    const bool tune = at == nullptr || std::strcmp(at, "0") != 0;
+    if (tune && tune_get(TuneKind::TnSteps, dmax, Nmax, 0) < 0)
+      STCHK(autotune_shapes(h, dmax, Nmax, b, storage, nullptr, nullptr, nullptr));
+  }
 
   if (h->batch == nullptr) h->batch = new BatchState();
   BatchState* Bs = h->batch;

@@ -135,6 +135,11 @@ eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy,
 eda_status orthonormalise(eda_handle h, int64_t t, double* X, int64_t ldx, int64_t ldw);
 // Core of exp(c S_W) without shift (exp(c S_W) = I + H_W C H_W^T), n x n.
 eda_status build_w_core(eda_handle h, double c, double* out);
+// Measures the candidate launch shapes of the product passes for a d x N
+// matrix in `storage` and b float64 columns and records the fastest
+// (eda_tune.cpp).  Outputs may be null.
+eda_status autotune_shapes(eda_handle h, int64_t d, int64_t N, int64_t b, eda_dtype storage,
+                           int32_t* tn_out, int32_t* nn_out, double* us_out);
 // eda_solve for the Arnoldi form (eda_aform.cpp); arguments already checked.
 eda_status solve_aform(eda_handle h, int32_t t, double tol, const eda_solve_opts& o,
                        double* ritz, double* ritz_log, double* X, int64_t ldx, double* resid,

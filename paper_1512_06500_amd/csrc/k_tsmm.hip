@@ -417,9 +417,12 @@ __global__ __launch_bounds__(256) void nn_narrow_kernel(const NnArgs* __restrict
   nn_narrow_body<TA, TV, TO, ACC>(a, blockIdx.x, blockIdx.y);
 }
 
-// 64 S rows per wave, 4 waves per workgroup: S = 4 when that still gives
-// 1024 workgroups, else 2, else 1 (chosen from the largest entry).
+// 64 S rows per wave, 4 waves per workgroup: the tuned value for this
+// shape class when there is one, else S = 4 when that still gives 1024
+// workgroups, else 2, else 1 (chosen from the largest entry).
 int tn_steps(int64_t d, int64_t m) {
+  const int tuned = tune_get(TuneKind::TnSteps, d, m, 0);
+  if (tuned == 1 || tuned == 2 || tuned == 4) return tuned;
   const int64_t tiles = (m + 15) / 16;
   for (int S : {4, 2}) {
     const int64_t chunks = (d + 256 * S - 1) / (256 * S);
@@ -511,11 +514,16 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
   hipLaunchKernelGGL((nn_kernel<TA, TV, TO, ACC, R_, B_>),                                     \
                      dim3((unsigned)((dmax + R_ - 1) / R_), (unsigned)ymax, (unsigned)count), \
                      dim3(256), 0, s, arr, one)
-  if (dmax / 64 >= 384)
+  int64_t mmax = 0;
+  for (int p = 0; p < count; ++p) mmax = std::max(mmax, host[p].m);
+  int cfg = tune_get(TuneKind::NnTile, dmax, mmax, (int)sizeof(TA));
+  if (cfg < 0 || cfg >= kNnConfigs)
+    cfg = (dmax / 64 >= 384) ? 3 : (dmax / 32 >= 384) ? 2 : (dmax > 4096) ? 0 : 1;
+  if (cfg == 3)
     NN_GO(64, 8);
-  else if (dmax / 32 >= 384)
+  else if (cfg == 2)
     NN_GO(32, 8);
-  else if (dmax > 4096)
+  else if (cfg == 0)
     NN_GO(16, 4);
   else  // few workgroups (core products): all loads of a lane in one batch
     NN_GO(16, 16);

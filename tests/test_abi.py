@@ -109,6 +109,18 @@ def test_scatter_rejects_bad_counts(lib, handle):
                                    10) == eda.EDA_ERR_ARG
 
 
+@pytest.mark.parametrize("d,N,b,storage", [
+    (0, 100, 8, 0),     # d < 1
+    (100, 0, 8, 0),     # N < 1
+    (100, 100, 0, 0),   # b < 1
+    (100, 100, 17, 0),  # b > 16
+    (100, 100, 8, 9),   # unknown storage
+])
+def test_autotune_rejects_bad_arguments(lib, handle, d, N, b, storage):
+    assert lib.eda_autotune(handle, d, N, b, storage, None, None, None) == eda.EDA_ERR_ARG
+    assert lib.eda_last_error(handle).decode()
+
+
 def test_null_handle(lib):
     assert lib.eda_prepare(None, 10, 4, 2, FAKE, 10, FAKE, 10, 0) == eda.EDA_ERR_ARG
     assert lib.eda_create(None, None) == eda.EDA_ERR_ARG

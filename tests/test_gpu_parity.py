@@ -639,6 +639,31 @@ def test_mixed_c5_fp8_full_size(torch, eda):
         h.close()
 
 
+def test_autotune_records_shapes_and_keeps_results(torch, eda, c2, tmp_path, monkeypatch):
+    """The autotuner (a9): valid shapes for the ORL-shaped class, written to
+    the cache file; the product and the solve after tuning still meet the
+    oracle's bounds."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("EDA_TUNE_CACHE", str(cache))
+    h, _, _ = prepared(torch, eda, c2)
+    V = dev(torch, datagen.start_block(c2.d, 8, 5))
+    before, _ = h.opmv("M", V)
+    before = host(before)
+    r = h.autotune(c2.d, c2.H_W.shape[1] + c2.H_B.shape[1], 8, "f64")
+    log(f"  autotune C2 class: {r}")
+    assert r["tn_steps"] in (1, 2, 4) and 0 <= r["nn_tile"] < 4
+    assert r["tn_us"] > 0 and r["nn_us"] > 0
+    lines = cache.read_text().split()
+    assert "tn" in lines and "nn" in lines
+    after, _ = h.opmv("M", V)
+    after = host(after)
+    assert np.abs(after - before).max() <= 1e-13 * np.abs(before).max()
+    red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
+    res = h.solve(c2.t, 1e-10, block=8, seed=2)
+    check_solution(res, red, c2.t, red.lam_all, 1e-10)
+    h.close()
+
+
 # ---------------------------------------------------------------------------
 # a9: many problems solved together
 # ---------------------------------------------------------------------------
