@@ -190,17 +190,12 @@ eda_status build_core(eda_handle h, int which, double c, double shift, double* o
   return EDA_OK;
 }
 
-eda_status build_composite_cores(eda_handle h) {
-  const int64_t n = h->n, k = h->k, N = h->N;
+// G_h = phi_{-1/2}(H_W^T H_W) and G_m = phi_{-1}(H_W^T H_W).
+eda_status build_w_cores(eda_handle h) {
+  const int64_t n = h->n, N = h->N;
   STCHK(ensure(h, h->Gh, (size_t)n * n * 8));
   STCHK(ensure(h, h->Gm, (size_t)n * n * 8));
-  STCHK(ensure(h, h->GBs, (size_t)k * k * 8));
   STCHK(ensure(h, h->CM, (size_t)N * N * 8));
-  STCHK(ensure(h, h->CA, (size_t)N * N * 8));
-  STCHK(ensure(h, h->T1, (size_t)n * k * 8));
-  STCHK(ensure(h, h->T2, (size_t)n * k * 8));
-  STCHK(ensure(h, h->T3, (size_t)n * k * 8));
-  STCHK(ensure(h, h->T4, (size_t)n * k * 8));
   STCHK(build_core(h, EDA_W, -0.5, 0.0, h->Gh.d()));
   if (h->w_eig) {
     STCHK(build_core(h, EDA_W, -1.0, 0.0, h->Gm.d()));
@@ -212,6 +207,20 @@ eda_status build_composite_cores(eda_handle h) {
     HIPCHK(launch_gemm(false, false, n, n, n, 1.0, h->Gh.d(), n, nullptr, h->CM.d(), n, 1.0,
                        h->Gm.d(), n, h->stream));
   }
+  return EDA_OK;
+}
+
+// G_B = e^{-s} phi_1(H_B^T H_B) and the composite cores C_M, C_A (after the
+// W-cores and the shift).
+eda_status build_composite_cores(eda_handle h) {
+  const int64_t n = h->n, k = h->k, N = h->N;
+  STCHK(ensure(h, h->GBs, (size_t)k * k * 8));
+  STCHK(ensure(h, h->CM, (size_t)N * N * 8));
+  STCHK(ensure(h, h->CA, (size_t)N * N * 8));
+  STCHK(ensure(h, h->T1, (size_t)n * k * 8));
+  STCHK(ensure(h, h->T2, (size_t)n * k * 8));
+  STCHK(ensure(h, h->T3, (size_t)n * k * 8));
+  STCHK(ensure(h, h->T4, (size_t)n * k * 8));
   STCHK(build_core(h, EDA_B, 1.0, h->shiftB, h->GBs.d()));
   const double* K = h->G.d() + n * N;  // H_W^T H_B, n x k, ld N
   hipStream_t s = h->stream;
@@ -384,7 +393,8 @@ void release_graphs(eda_handle h) {
 }
 
 eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
-                         int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
+                         int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage,
+                         bool overlap) {
   if (h == nullptr) return EDA_ERR_ARG;
   if (d < 2 || k < 2 || n < k) return fail(h, EDA_ERR_ARG, "need d>=2, k>=2, n>=k");
   // the dense eigensolves of the preparation are of sizes k and (on request) n
@@ -400,7 +410,7 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
   for (auto& c : h->cores) release(c.buf);
   h->cores.clear();
 
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < 4; ++q)
     if (h->prep_ev[q] == nullptr) HIPCHK(hipEventCreate(&h->prep_ev[q]));
   HIPCHK(hipEventRecord(h->prep_ev[0], h->stream));
 
@@ -473,6 +483,7 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
   STCHK(ensure(h, h->eigZ, (size_t)2 * n * n * 8));
   STCHK(ensure(h, h->normbuf, 64));
   h->w_eig = false;
+  h->prep_overlap = overlap && !w_by_eig;
   if (w_by_eig) {
     int hns[2] = {(int)n, (int)k};
     STCHK(ensure(h, h->nsbuf, 2 * sizeof(int)));
@@ -481,14 +492,26 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
     HIPCHK(launch_syev(2, n, h->nsbuf.i(), h->G.d(), N, n + n * N, h->eigW.d(), n, h->eigZ.d(),
                        n, n * n, 0, h->syev_work.d(), h->stream));
     HIPCHK(hipMemcpyAsync(pin + 2 + k, h->eigW.d(), n * 8, hipMemcpyDeviceToHost, h->stream));
-  } else {
-    STCHK(ensure(h, h->syev_work, syev_work_bytes(k)));
-    HIPCHK(launch_syev(1, k, nullptr, h->G.d() + n + n * N, N, 0, h->eigW.d() + n, 0,
-                       h->eigZ.d() + n * n, n, 0, 0, h->syev_work.d(), h->stream));
+    HIPCHK(launch_norm1(n, h->G.d(), N, h->normbuf.d(), h->stream));
+    HIPCHK(hipMemcpyAsync(pin + 2, h->eigW.d() + n, k * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(pin + 1, h->normbuf.d(), 8, hipMemcpyDeviceToHost, h->stream));
+    return EDA_OK;
   }
+  // ||H_W^T H_W||_1 first: the W-cores need nothing else
   HIPCHK(launch_norm1(n, h->G.d(), N, h->normbuf.d(), h->stream));
-  HIPCHK(hipMemcpyAsync(pin + 2, h->eigW.d() + n, k * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipMemcpyAsync(pin + 1, h->normbuf.d(), 8, hipMemcpyDeviceToHost, h->stream));
+  hipStream_t sb = h->stream;
+  if (h->prep_overlap) {
+    if (h->aux == nullptr) HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventRecord(h->prep_ev[2], h->stream));
+    HIPCHK(hipStreamWaitEvent(h->aux, h->prep_ev[2], 0));
+    sb = h->aux;
+  }
+  STCHK(ensure(h, h->syev_work, syev_work_bytes(k)));
+  HIPCHK(launch_syev(1, k, nullptr, h->G.d() + n + n * N, N, 0, h->eigW.d() + n, 0,
+                     h->eigZ.d() + n * n, n, 0, 0, h->syev_work.d(), sb));
+  HIPCHK(hipMemcpyAsync(pin + 2, h->eigW.d() + n, k * 8, hipMemcpyDeviceToHost, sb));
+  if (h->prep_overlap) HIPCHK(hipEventRecord(h->prep_ev[3], sb));
   return EDA_OK;
 }
 
@@ -497,8 +520,17 @@ eda_status prepare_end(eda_handle h) {
   const int64_t n = h->n, k = h->k;
   int bad = 0;
   std::memcpy(&bad, pin, sizeof(int));
-  if (bad) return fail(h, EDA_ERR_NONFINITE, "NaN or Inf in H_W or H_B");
+  if (bad) {
+    if (h->prep_overlap) (void)hipEventSynchronize(h->prep_ev[3]);
+    return fail(h, EDA_ERR_NONFINITE, "NaN or Inf in H_W or H_B");
+  }
   h->normW = pin[1];
+  if (h->prep_overlap) {
+    // the W-cores while eig(H_B^T H_B) runs on the second stream
+    STCHK(build_w_cores(h));
+    HIPCHK(hipEventSynchronize(h->prep_ev[3]));
+    HIPCHK(hipStreamWaitEvent(h->stream, h->prep_ev[3], 0));
+  }
   h->hwB.assign(pin + 2, pin + 2 + k);
   if (h->prep_wbyeig) {
     h->hwW.assign(pin + 2 + k, pin + 2 + k + n);
@@ -510,6 +542,7 @@ eda_status prepare_end(eda_handle h) {
   h->alphaB = std::exp(-h->shiftB);
   STCHK(ensure(h, h->alphaB_dev, 8));
   HIPCHK(launch_fill(1, h->alphaB, h->alphaB_dev.d(), h->stream));
+  if (!h->prep_overlap) STCHK(build_w_cores(h));
   STCHK(build_composite_cores(h));
   HIPCHK(hipEventRecord(h->prep_ev[1], h->stream));
   h->prepared = true;
@@ -523,7 +556,7 @@ extern "C" {
 eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
                        int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
   if (h == nullptr) return EDA_ERR_ARG;
-  STCHK(prepare_begin(h, d, n, k, H_W, ldw, H_B, ldb, storage));
+  STCHK(prepare_begin(h, d, n, k, H_W, ldw, H_B, ldb, storage, true));
   HIPCHK(hipStreamSynchronize(h->stream));
   STCHK(prepare_end(h));
   HIPCHK(hipEventSynchronize(h->prep_ev[1]));

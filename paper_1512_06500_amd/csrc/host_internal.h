@@ -69,8 +69,11 @@ struct eda_handle_s {
   // eigenvalues of G_BB and of G_WW), read back without a blocking copy
   void* pin = nullptr;
   size_t pin_cap = 0;
-  hipEvent_t prep_ev[2] = {nullptr, nullptr};
+  // prep_ev: [0] start, [1] end of the preparation, [2] Gram ready (the
+  // second stream starts eig(H_B^T H_B)), [3] that eigensolve copied out
+  hipEvent_t prep_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool prep_wbyeig = false;
+  bool prep_overlap = false;  // eig(H_B^T H_B) on the second stream beside the W-cores
 
   // workspaces
   eda::Buf part, Ysm, Zsm, syev_work, offs, flags, mask;
@@ -118,8 +121,13 @@ inline int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
 // asynchronously into pinned memory; after the stream has drained,
 // prepare_end reads them (non-finite check, spectral shift) and enqueues the
 // core construction.  Nothing in either half blocks the host.
+// With `overlap`, eig(H_B^T H_B) runs on the second stream so that
+// prepare_end can build the W-cores (which need only ||H_W^T H_W||_1) while
+// it runs; the caller then needs to drain only the main stream before
+// prepare_end.
 eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const double* H_W,
-                         int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage);
+                         int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage,
+                         bool overlap = false);
 eda_status prepare_end(eda_handle h);
 void destroy_batch_state(eda_handle h);
 void release_graphs(eda_handle h);
