@@ -77,29 +77,61 @@ eda_status check_dev_ptr(eda_handle h, const void* p, const char* name) {
 
 // Low-rank exponential apply on columns [c0, c0+Nc) of P:
 //   Out = alpha V + P_c (C (P_c^T V)),  C: Nc x Nc (ldc).
-eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
-                 int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
-                 void* Out, DT odt, int64_t ldo, const double* alpha_p) {
+namespace {
+const char* p_columns(eda_handle h, bool master, int64_t c0, DT* pdt) {
   const bool use64 = master && h->storage != EDA_F64;
-  const DT pdt = use64 ? DT::F64 : dt_of(h->storage);
+  *pdt = use64 ? DT::F64 : dt_of(h->storage);
   const char* base = use64 ? h->P64.c() : h->P.c();
-  const char* Pc = base + (size_t)c0 * h->ldp * dt_size(pdt);
+  return base + (size_t)c0 * h->ldp * dt_size(*pdt);
+}
+}  // namespace
+
+eda_status expop_first(eda_handle h, bool master, int64_t c0, int64_t Nc, int64_t b,
+                       const void* V, DT vdt, int64_t ldv, double* ysm, int64_t ldy) {
+  DT pdt;
+  const char* Pc = p_columns(h, master, c0, &pdt);
   const int64_t chunks = tn_chunks(h->d, Nc, b);
   STCHK(ensure(h, h->part, (size_t)chunks * Nc * b * 8));
-  STCHK(ensure(h, h->Ysm, (size_t)Nc * b * 8));
-  STCHK(ensure(h, h->Zsm, (size_t)Nc * b * 8));
+  if (ysm == nullptr) {
+    STCHK(ensure(h, h->Ysm, (size_t)Nc * b * 8));
+    ysm = h->Ysm.d();
+    ldy = b;
+  }
   const double* sc = (pdt == DT::FP8) ? h->pscale.d() + c0 : nullptr;
   HIPCHK(launch_tn_partial(h->d, Nc, b, Pc, pdt, h->ldp, V, vdt, ldv, h->part.d(), chunks,
                            nullptr, h->stream, sc));
-  // Y = P_c^T V (row-major, leading dimension b), then Z = C Y (row-major) by
-  // the same streaming kernel with C as the tall operand
-  HIPCHK(launch_reduce_partials(chunks, Nc, b, h->part.d(), 0.0, 0.0, nullptr, 0, 1.0,
-                                h->Ysm.d(), b, nullptr, h->stream));
-  HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, h->Ysm.d(), b, 0.0, nullptr, DT::F64, 0,
-                   h->Zsm.d(), DT::F64, b, nullptr, h->stream, true));
+  // Y = P_c^T V (row-major)
+  HIPCHK(launch_reduce_partials(chunks, Nc, b, h->part.d(), 0.0, 0.0, nullptr, 0, 1.0, ysm, ldy,
+                                nullptr, h->stream));
+  return EDA_OK;
+}
+
+eda_status expop_second(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
+                        int64_t ldc, double alpha, int64_t b, const void* V, DT vdt,
+                        int64_t ldv, void* Out, DT odt, int64_t ldo, const double* alpha_p,
+                        const double* ysm, int64_t ldy) {
+  DT pdt;
+  const char* Pc = p_columns(h, master, c0, &pdt);
+  STCHK(ensure(h, h->Zsm, (size_t)Nc * b * 8));
+  if (ysm == nullptr) {
+    ysm = h->Ysm.d();
+    ldy = b;
+  }
+  const double* sc = (pdt == DT::FP8) ? h->pscale.d() + c0 : nullptr;
+  // Z = C Y (row-major) by the same streaming kernel with C as the tall
+  // operand, then Out = alpha V + P_c Z
+  HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, ysm, ldy, 0.0, nullptr, DT::F64, 0, h->Zsm.d(),
+                   DT::F64, b, nullptr, h->stream, true));
   HIPCHK(launch_nn(h->d, Nc, b, Pc, pdt, h->ldp, h->Zsm.d(), b, alpha, V, vdt, ldv, Out, odt,
                    ldo, nullptr, h->stream, false, alpha_p, sc));
   return EDA_OK;
+}
+
+eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
+                 int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
+                 void* Out, DT odt, int64_t ldo, const double* alpha_p) {
+  STCHK(expop_first(h, master, c0, Nc, b, V, vdt, ldv));
+  return expop_second(h, master, c0, Nc, C, ldc, alpha, b, V, vdt, ldv, Out, odt, ldo, alpha_p);
 }
 
 }  // namespace eda
@@ -323,7 +355,7 @@ void eda_destroy(eda_handle h) {
     Buf* all[] = {&h->polyws, &h->normbuf,
                   &h->P,  &h->G,  &h->eigW, &h->eigZ, &h->nsbuf, &h->Gh,  &h->Gm,  &h->GBs,
                   &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part,
-                  &h->Ysm, &h->Zsm, &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
+                  &h->Ysm, &h->Zsm, &h->PQ[0], &h->PQ[1], &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
                   &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale};
     for (Buf& b : h->dir) release(b);

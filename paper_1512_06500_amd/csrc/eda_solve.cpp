@@ -39,6 +39,9 @@ struct Solver {
   int64_t d, ldq, b, mmax, ldh, t, kk;
   DT qdt;       // basis type of the Krylov phase
   int cur = 0;  // which of the two basis/H buffers is live
+  // float64 P: the products keep P^T Q (h->PQ[cur], row-major, ld ldpq)
+  bool track = false;
+  int64_t ldpq = 0;
   char* Q() const { return h->Q[cur].c(); }
   char* Qc(int64_t j) const { return Q() + (size_t)j * ldq * dt_size(qdt); }
   double* H() const { return h->H[cur].d(); }
@@ -94,8 +97,14 @@ eda_status lanczos_op(Solver& S, int64_t m) {
   eda_handle h = S.h;
   // e^{-s} is read from the device, so a captured step stays valid when a
   // later preparation changes the shift
-  return expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt, S.ldq,
-               h->Wb.p, S.qdt, S.ldq, h->alphaB_dev.d());
+  if (!S.track)
+    return expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt, S.ldq,
+                 h->Wb.p, S.qdt, S.ldq, h->alphaB_dev.d());
+  // P^T V_m goes to columns m .. m+b of P^T Q
+  double* pq = h->PQ[S.cur].d() + m;
+  STCHK(expop_first(h, false, 0, h->N, S.b, S.Qc(m), S.qdt, S.ldq, pq, S.ldpq));
+  return expop_second(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt,
+                      S.ldq, h->Wb.p, S.qdt, S.ldq, h->alphaB_dev.d(), pq, S.ldpq);
 }
 
 // The rest of the block step: orthonormalise W into the next block and
@@ -317,8 +326,11 @@ namespace eda {
 // orthonormalised in column order by Cholesky QR run twice (scratch with
 // leading dimension ldw in h->Yb) and sign-fixed (eq. 3.14; Algorithm 3).
 eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy, double* X,
-                          int64_t ldx, int64_t ldw) {
-  STCHK(expop(h, true, 0, h->n, h->Gh.d(), h->n, 1.0, t, Y, DT::F64, ldy, X, DT::F64, ldx));
+                          int64_t ldx, int64_t ldw, bool ysm_ready) {
+  // H_W is the leading n columns of P, so H_W^T Y is the leading n rows of P^T Y
+  if (!ysm_ready) STCHK(expop_first(h, true, 0, h->n, t, Y, DT::F64, ldy));
+  STCHK(expop_second(h, true, 0, h->n, h->Gh.d(), h->n, 1.0, t, Y, DT::F64, ldy, X, DT::F64,
+                     ldx));
   return orthonormalise(h, t, X, ldx, ldw);
 }
 
@@ -408,6 +420,12 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     STCHK(ensure(h, h->Q[q], (size_t)ldq * (mmax + b) * qs));
     STCHK(ensure(h, h->H[q], (size_t)ldh * ldh * 8));
   }
+  // With float64 P, P^T y of the final Ritz block follows from P^T Q by a
+  // small product instead of a pass over P
+  S.track = (h->storage == EDA_F64);
+  S.ldpq = mmax + b;
+  if (S.track)
+    for (int q = 0; q < 2; ++q) STCHK(ensure(h, h->PQ[q], (size_t)h->N * S.ldpq * 8));
   STCHK(ensure(h, h->Wb, (size_t)ldq * b * qs));
   STCHK(ensure(h, h->T, (size_t)mm * mm * 8));
   STCHK(ensure(h, h->wT, (size_t)mm * 8));
@@ -455,7 +473,8 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
         (uint64_t)(uintptr_t)h->Gs.p, (uint64_t)(uintptr_t)h->Rinv.p,
         (uint64_t)(uintptr_t)h->R1.p, (uint64_t)(uintptr_t)h->mask.p,
         (uint64_t)(uintptr_t)h->flags.p, (uint64_t)(uintptr_t)h->CM.p,
-        (uint64_t)(uintptr_t)h->P.p};
+        (uint64_t)(uintptr_t)h->P.p, (uint64_t)(uintptr_t)h->PQ[0].p,
+        (uint64_t)(uintptr_t)h->PQ[1].p, (uint64_t)S.track};
     uint64_t sig = 1469598103934665603ull;  // FNV-1a over the words
     for (uint64_t w : parts)
       for (int q = 0; q < 8; ++q) sig = (sig ^ ((w >> (8 * q)) & 0xff)) * 1099511628211ull;
@@ -648,6 +667,11 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
         HIPCHK(launch_nn(d, m, kk, S.Q(), qdt, ldq, h->Sd.d(), kk, 0.0, nullptr, qdt, ldq, Qn, qdt,
                          ldq, nullptr, s));
         HIPCHK(launch_copy2d(d, b, S.Qc(m), qdt, ldq, Qn + (size_t)kk * ldq * qs, qdt, ldq, s));
+        // P^T of the kept Ritz vectors: (P^T Q) S_kk, row-major (the next
+        // product fills the columns of the residual block)
+        if (S.track)
+          HIPCHK(launch_gemm(false, false, kk, h->N, m, 1.0, h->Sd.d(), kk, nullptr,
+                             h->PQ[S.cur].d(), S.ldpq, 0.0, h->PQ[nxt].d(), S.ldpq, s));
         HIPCHK(launch_fill(ldh * ldh, 0.0, Hn, s));
         HIPCHK(launch_set_diag(kk, h->dtheta.d(), Hn, ldh, s));
         HIPCHK(launch_restart_coupling(m, b, kk, S.H() + m + (m - b) * ldh, ldh, h->Sd.d(), kk, Hn,
@@ -704,12 +728,22 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     bytes += opbytes_t;
     STCHK(rr_block(h, d, ldq, t, t, mm, XB[0], MB[0], XB[1], MB[1]));
     cb = 1;
+  } else if (S.track) {
+    // P^T Y = (P^T Q) S_t (row-major N x t), then the second pass only
+    HIPCHK(launch_gemm(false, false, t, h->N, m, 1.0, h->Sd.d(), t, nullptr, h->PQ[S.cur].d(),
+                       S.ldpq, 0.0, h->Ysm.d(), t, s));
+    STCHK(expop_second(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, t, XB[0], DT::F64, ldq,
+                       MB[0], DT::F64, ldq));
+    ops += t;
+    bytes += opbytes_t;
   } else {
     STCHK(expop(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, t, XB[0], DT::F64, ldq, MB[0],
                 DT::F64, ldq));
     ops += t;
     bytes += opbytes_t;
   }
+  // h->Ysm holds P^T y for these Ritz vectors until the next product
+  const double* ysm_of = (mixed && max_refine >= 0) ? nullptr : XB[0];
   std::vector<double> res(t);
   bool converged = false, floor_limited = false;
   int64_t passes = 0;
@@ -732,7 +766,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     if (speculate) {
       // x = exp(-S_W/2) y, orthonormalised in decreasing-lambda order
       // (Cholesky QR, twice), signs fixed
-      STCHK(back_transform(h, t, Y, ldq, X, ldx, ldq));
+      STCHK(back_transform(h, t, Y, ldq, X, ldx, ldq, Y == ysm_of));
       x_done = true;
     }
     HIPCHK(hipMemcpyAsync(fl, h->flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -791,6 +825,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     HIPCHK(launch_copy2d(d, wz, Zt, DT::F64, ldq, Z, DT::F64, ldq, s));
     STCHK(expop(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, wz, Z, DT::F64, ldq,
                 MY + (size_t)t * ldq, DT::F64, ldq));
+    ysm_of = nullptr;
     ops += wz;
     bytes += opbytes_z;
     STCHK(rr_block(h, d, ldq, t + wz, t, mm, Y, MY, XB[1 - cb], MB[1 - cb]));

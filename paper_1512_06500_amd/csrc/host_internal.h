@@ -81,6 +81,9 @@ struct eda_handle_s {
 
   // solver
   eda::Buf Q[2], H[2], Wb, T, wT, S, Sd, hz, Gs, Rinv, R1, Yb, MYb, dtheta, dres, refine;
+  // P^T Q of the live basis (row-major N x (mmax + b)), float64 storage only:
+  // filled block by block by the products of the Krylov phase
+  eda::Buf PQ[2];
 
   // captured block steps of the current solver configuration
   std::vector<eda::StepGraph> graphs;
@@ -132,12 +135,12 @@ eda_status prepare_end(eda_handle h);
 void destroy_batch_state(eda_handle h);
 void release_graphs(eda_handle h);
 
-// Low-rank exponential apply on columns [c0, c0+Nc) of P (the storage copy,
-// or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.
 // x = exp(-S_W/2) y for t columns, orthonormalised (Cholesky QR twice,
-// scratch ld ldw) and sign-fixed.
+// scratch ld ldw) and sign-fixed.  With `ysm_ready`, h->Ysm already holds
+// P^T Y from the product just taken of the same Y (float64 master), and
+// only the second pass runs.
 eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy, double* X,
-                          int64_t ldx, int64_t ldw);
+                          int64_t ldx, int64_t ldw, bool ysm_ready = false);
 // Columns of X (d x t) orthonormalised in column order by Cholesky QR run
 // twice (scratch with leading dimension ldw in h->Yb) and sign-fixed.
 eda_status orthonormalise(eda_handle h, int64_t t, double* X, int64_t ldx, int64_t ldw);
@@ -152,9 +155,23 @@ eda_status autotune_shapes(eda_handle h, int64_t d, int64_t N, int64_t b, eda_dt
 eda_status solve_aform(eda_handle h, int32_t t, double tol, const eda_solve_opts& o,
                        double* ritz, double* ritz_log, double* X, int64_t ldx, double* resid,
                        eda_info* info);
+// Low-rank exponential apply on columns [c0, c0+Nc) of P (the storage copy,
+// or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.
 eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
                  int64_t ldc, double alpha, int64_t b, const void* V, DT vdt, int64_t ldv,
                  void* Out, DT odt, int64_t ldo, const double* alpha_p = nullptr);
+// Its two halves: h->Ysm = P_c^T V (row-major, Nc x b), then
+// Out = alpha V + P_c (C Ysm).  The second half may take a leading block of
+// columns of an earlier first half (Nc no larger, same b, same V).
+// (ysm, ldy): where P_c^T V goes (row-major), h->Ysm with ld b by default.
+eda_status expop_first(eda_handle h, bool master, int64_t c0, int64_t Nc, int64_t b,
+                       const void* V, DT vdt, int64_t ldv, double* ysm = nullptr,
+                       int64_t ldy = 0);
+eda_status expop_second(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
+                        int64_t ldc, double alpha, int64_t b, const void* V, DT vdt,
+                        int64_t ldv, void* Out, DT odt, int64_t ldo,
+                        const double* alpha_p = nullptr, const double* ysm = nullptr,
+                        int64_t ldy = 0);
 
 }  // namespace eda
 

@@ -151,18 +151,25 @@ __global__ __launch_bounds__(256) void core_weights_kernel(int64_t n, const doub
 
 // One workgroup per column: make the largest-magnitude entry positive
 // (ties: the smallest row index).
-__global__ __launch_bounds__(256) void sign_fix_kernel(const SignArgs* __restrict__ arr, SignArgs one) {
+__global__ __launch_bounds__(1024) void sign_fix_kernel(const SignArgs* __restrict__ arr, SignArgs one) {
   const SignArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if ((int64_t)blockIdx.x >= a.t) return;
   const int64_t d = a.d;
-  __shared__ double sv[256];
-  __shared__ int64_t si[256];
+  __shared__ double sv[1024];
+  __shared__ int64_t si[1024];
   double* x = a.X + blockIdx.x * a.ldx;
   double best = -1.0;
   int64_t bi = 0;
-  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
-    const double a = fabs(x[r]);
-    if (a > best) { best = a; bi = r; }
+  const int64_t nt = blockDim.x;
+  // eight loads in flight per thread; each thread visits its rows in
+  // increasing order, so ties keep the smallest index
+  for (int64_t r0 = threadIdx.x; r0 < d; r0 += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (r0 + u * nt < d) ? fabs(x[r0 + u * nt]) : -1.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (v[u] > best) { best = v[u]; bi = r0 + u * nt; }
   }
   sv[threadIdx.x] = best;
   si[threadIdx.x] = bi;
@@ -178,9 +185,17 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(const SignArgs* __restric
     }
     __syncthreads();
   }
-  const double sg = (x[si[0]] < 0.0) ? -1.0 : 1.0;
-  __syncthreads();
-  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) x[r] *= sg;
+  const bool flip = x[si[0]] < 0.0;  // uniform across the workgroup
+  __syncthreads();  // every thread has read the pivot before any entry changes
+  if (!flip) return;
+  for (int64_t r0 = threadIdx.x; r0 < d; r0 += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (r0 + u * nt < d) ? x[r0 + u * nt] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r0 + u * nt < d) x[r0 + u * nt] = -v[u];
+  }
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(const FillArgs* __restrict__ arr, FillArgs one) {
@@ -486,7 +501,7 @@ hipError_t launch_sign_fix_multi(int count, const SignArgs* host, const SignArgs
   const SignArgs* arr;
   SignArgs one;
   pick(count, host, dev, &arr, &one);
-  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s, arr, one);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(1024), 0, s, arr, one);
   return hipGetLastError();
 }
 

@@ -161,7 +161,7 @@ __device__ __forceinline__ void sturm_counts(int n, const double* __restrict__ D
 // D, off-diagonal ee).  Stored per position k with stride NT: 1/U(k,k),
 // U(k,k+1), U(k,k+2), the multiplier and the interchange flag.
 template <int NT>
-__device__ void tri_factor(int n, const double* __restrict__ D, const double* __restrict__ ee,
+__device__ __forceinline__ void tri_factor(int n, const double* __restrict__ D, const double* __restrict__ ee,
                            double lam, double tiny, double* __restrict__ lu, int64_t nmax) {
   double* U1 = lu;
   double* U2 = lu + nmax * NT;
@@ -211,7 +211,7 @@ __device__ void tri_factor(int n, const double* __restrict__ D, const double* __
 // rescales the whole system whenever the solution grows past 2^300, so chains
 // of tiny pivots (split matrices, multiple eigenvalues) cannot overflow.
 template <int NT>
-__device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
+__device__ __forceinline__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
                           double* __restrict__ y, int64_t ys) {
   const double* U1 = lu;
   const double* U2 = lu + nmax * NT;
@@ -299,7 +299,7 @@ __device__ void tri_solve(int n, const double* __restrict__ lu, int64_t nmax,
 #undef LU
 }
 
-__device__ void random_start(int n, int i, double* y, int64_t ys) {
+__device__ __forceinline__ void random_start(int n, int i, double* y, int64_t ys) {
   for (int k = 0; k < n; ++k) {
     const uint64_t h = hash64(((uint64_t)(i + 1) << 32) ^ (uint64_t)k ^ 0x5bd1e995ull);
     y[(int64_t)k * ys] = ((double)(h >> 11) * 0x1.0p-53) * 2.0 - 1.0;
@@ -308,7 +308,7 @@ __device__ void random_start(int n, int i, double* y, int64_t ys) {
 
 // y / ||y||, one thread; loads in batches of 8 so that each batch costs one
 // memory round trip (y lives in global memory).
-__device__ void normalize_serial(int n, double* y, int64_t ys) {
+__device__ __forceinline__ void normalize_serial(int n, double* y, int64_t ys) {
   double mx = 0.0;
   for (int k0 = 0; k0 < n; k0 += 8) {
     double v[8];
@@ -360,9 +360,15 @@ __host__ __device__ inline int64_t syev_work_doubles(int64_t nmax, int nt) {
 
 // LDS layout (doubles):
 //   LDS path:    A [n (n+1)] | sv [n] | sw [n] | red [16] | Gc [kClusterMax^2]
+//                | Zt [n nvec] (when it fits)
 //   global path: sv [n] | sw [n] | red [32] | stage [rest of the 160 KB]  (Gc = stage)
 __host__ __device__ inline int64_t syev_lds_doubles(int64_t n, bool lds_a) {
   return lds_a ? n * (n + 1) + 2 * n + 32 + kClusterMax * kClusterMax : kLdsDoubles;
+}
+// LDS path: the eigenvectors of T (n x nvec) follow when they fit in 160 KB.
+inline int64_t syev_lds_alloc(int64_t nmax, int64_t nvmax, bool lds_a) {
+  const int64_t base = syev_lds_doubles(nmax, lds_a);
+  return (lds_a && base + nmax * nvmax <= kLdsDoubles) ? base + nmax * nvmax : base;
 }
 
 // Optional per-phase cycle counters (matrix 0 of each launch), for profiling.
@@ -388,7 +394,8 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
                                                   int64_t stridew, double* __restrict__ Zout,
                                                   int64_t ldz_, int64_t strideZ, int nvec_,
                                                   double* __restrict__ work, int64_t nmax,
-                                                  int lds_a, int timing, double ctol_) {
+                                                  int lds_a, int timing, double ctol_,
+                                                  int64_t lds_cap) {
   constexpr int NW = NT / 64;
   constexpr int DU = NT > 512 ? 4 : 8;  // dot-product unroll within the register budget
   extern __shared__ double smem[];
@@ -426,8 +433,11 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   double* ee = dd + nmax;
   double* tau = ee + nmax;
   double* lamv = tau + nmax;
-  double* Zt = lamv + nmax;          // [pos][slot]
-  double* lub = Zt + nmax * nmax;    // LU arrays, [array][pos][thread]
+  double* ZtG = lamv + nmax;         // [pos][slot] (work area)
+  double* lub = ZtG + nmax * nmax;   // LU arrays, [array][pos][thread]
+  // [pos][slot] in LDS when the launch reserved n nv doubles past the rest
+  double* ZtL = smem + syev_lds_doubles(nmax, true);
+  const bool zt_lds = lds_a && syev_lds_doubles(nmax, true) + (int64_t)n * nv <= lds_cap;
   double *A, *sv, *sw, *red, *stage, *Gc;
   int64_t ldA;
   if (lds_a) {
@@ -856,6 +866,11 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   double* EL = Gc;
   for (int i = tid; i < n - 1; i += NT) EL[i] = ee[i];
   __syncthreads();
+  // The eigenvectors of T (Zt) live in LDS past the working matrix when the
+  // launch reserved room for them, else in the work area; the two phases
+  // below are instantiated for each, so that LDS accesses compile to LDS
+  // instructions.
+  auto vectors_of_t = [&](double* __restrict__ Zt) __attribute__((always_inline)) {
   for (int slot0 = 0; slot0 < nv; slot0 += NT) {
     const int slot = slot0 + tid;
     if (slot < nv) {
@@ -957,6 +972,12 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
     }
   }
   __syncthreads();
+  };
+  if (zt_lds)
+    vectors_of_t(ZtL);
+  else
+    vectors_of_t(ZtG);
+  double* const Zt = zt_lds ? ZtL : ZtG;
 
   SYEV_MARK(4);
   if (NT <= 512 && lds_a) {
@@ -1098,9 +1119,10 @@ template <int NT>
 hipError_t syev_launch_t(const SyevArgs* sarr, int64_t batch, int64_t n, const int* ns,
                          const double* A, int64_t lda, int64_t strideA, double* w, int64_t stridew,
                          double* Z, int64_t ldz, int64_t strideZ, int64_t nvec, double* work,
-                         hipStream_t s, double ctol) {
+                         hipStream_t s, double ctol, int64_t nvmax) {
   const bool lds_a = n <= kLdsMax && NT <= 512;
-  const size_t lds = (size_t)syev_lds_doubles(n, lds_a) * sizeof(double);
+  const int64_t lds_cap = syev_lds_alloc(n, nvmax, lds_a);
+  const size_t lds = (size_t)lds_cap * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)syev_kernel<NT>,
@@ -1110,7 +1132,7 @@ hipError_t syev_launch_t(const SyevArgs* sarr, int64_t batch, int64_t n, const i
   }
   hipLaunchKernelGGL(syev_kernel<NT>, dim3((unsigned)batch), dim3(NT), lds, s, sarr, (int)n, ns, A,
                      lda, strideA, w, stridew, Z, ldz, strideZ, (int)nvec, work, n, lds_a ? 1 : 0,
-                     syev_timing ? 1 : 0, ctol);
+                     syev_timing ? 1 : 0, ctol, lds_cap);
   return hipGetLastError();
 }
 
@@ -1138,14 +1160,15 @@ hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A,
   if (n < 1 || n > SYEV_NMAX || batch < 1) return hipErrorInvalidValue;
   // workgroup size by measurement: 256 threads up to n = 48, 512 while the
   // matrix fits in LDS, 1024 for the global-memory path
+  const int64_t nvmax = (nvec <= 0 || nvec > n) ? n : nvec;
   if (n <= 48)
     return syev_launch_t<256>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
-                              nvec, work, s, ctol);
+                              nvec, work, s, ctol, nvmax);
   if (n <= kLdsMax)
     return syev_launch_t<512>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
-                              nvec, work, s, ctol);
+                              nvec, work, s, ctol, nvmax);
   return syev_launch_t<1024>(nullptr, batch, n, ns, A, lda, strideA, w, stridew, Z, ldz, strideZ,
-                             nvec, work, s, ctol);
+                             nvec, work, s, ctol, nvmax);
 }
 
 // Several problems of different size: `dev` holds the count entries on the
@@ -1153,10 +1176,12 @@ hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A,
 hipError_t launch_syev_multi(int count, const SyevArgs* host, const SyevArgs* dev,
                              hipStream_t s) {
   if (count < 1) return hipSuccess;
-  int64_t nmax = 0;
+  int64_t nmax = 0, nvmax = 0;
   for (int p = 0; p < count; ++p) {
     if (host[p].n < 0 || host[p].n > SYEV_NMAX) return hipErrorInvalidValue;
     nmax = std::max(nmax, host[p].n);
+    const int64_t nv = (host[p].nvec <= 0 || host[p].nvec > host[p].n) ? host[p].n : host[p].nvec;
+    nvmax = std::max(nvmax, nv);
   }
   if (nmax == 0) return hipSuccess;
   if (count == 1) {
@@ -1166,12 +1191,12 @@ hipError_t launch_syev_multi(int count, const SyevArgs* host, const SyevArgs* de
   }
   if (nmax <= 48)
     return syev_launch_t<256>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
-                              0, nullptr, s, 0.0);
+                              0, nullptr, s, 0.0, nvmax);
   if (nmax <= kLdsMax)
     return syev_launch_t<512>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
-                              0, nullptr, s, 0.0);
+                              0, nullptr, s, 0.0, nvmax);
   return syev_launch_t<1024>(dev, count, nmax, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, 0, 0,
-                             0, nullptr, s, 0.0);
+                             0, nullptr, s, 0.0, nvmax);
 }
 
 }  // namespace eda

@@ -47,37 +47,46 @@ template <typename T> __device__ __forceinline__ double ld64(const T* p) { retur
 // a wide A (many columns) does not re-read B once per 16 columns.
 // blockIdx.x: row chunk, blockIdx.y: tile group + ygroups * (nb tile),
 // blockIdx.z: problem.
-template <typename TA, typename TB, int S, int CT>
-__device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yg, int zt) {
+template <typename TA, typename TB, int S, int CT, int ZT>
+__device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yg, int zg) {
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
-  const int yt0 = yg * CT;
-  if (chunk >= a.chunks || yt0 * 16 >= m || zt * 16 >= nb) return;
-  __shared__ f64x4 red[3][CT][64];
+  const int yt0 = yg * CT, zt0 = zg * ZT;
+  if (chunk >= a.chunks || yt0 * 16 >= m || zt0 * 16 >= nb) return;
+  __shared__ f64x4 red[3][CT * ZT][64];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int j0 = zt * 16;
   const int i = lane & 15, q = lane >> 4;
-  const bool bok = (j0 + i) < nb;
-  const TB* bp = (const TB*)a.B + (int64_t)(bok ? j0 + i : j0) * a.ldb;
+  // B columns of the ZT tiles; a lane whose column is past nb reads column 0
+  // (always valid) and contributes zeros
+  const TB* bp[ZT];
+  bool bok[ZT];
+#pragma unroll
+  for (int z = 0; z < ZT; ++z) {
+    const int jz = (zt0 + z) * 16 + i;
+    bok[z] = jz < nb;
+    bp[z] = (const TB*)a.B + (int64_t)(bok[z] ? jz : 0) * a.ldb;
+  }
   const int64_t r0 = chunk * (int64_t)(256 * S) + (int64_t)wid * (64 * S);
   const int64_t r1 = (r0 + 64 * S < d) ? r0 + 64 * S : d;
-  f64x4 acc[CT];
+  f64x4 acc[CT * ZT];
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) acc[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < CT * ZT; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int64_t rb = r0 + 64 * s;
     if (rb >= r1) break;
     const int64_t rs = rb + 16 * q;
     const bool full = rb + 64 <= r1;
-    double bv[16];
+    double bv[ZT][16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const bool ok = full || rs + e < r1;
-      const double y = ld64(bp + (ok ? rs + e : rb));
-      bv[e] = (bok && ok) ? y : 0.0;
-    }
+    for (int z = 0; z < ZT; ++z)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const bool ok = full || rs + e < r1;
+        const double y = ld64(bp[z] + (ok ? rs + e : rb));
+        bv[z][e] = (bok[z] && ok) ? y : 0.0;
+      }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int c0 = (yt0 + ct) * 16;
@@ -108,41 +117,49 @@ __device__ __forceinline__ void tn_body(const TnArgs& a, int64_t chunk, int yg, 
         }
       }
 #pragma unroll
-      for (int e = 0; e < 16; ++e)
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[e], acc[ct], 0, 0, 0);
+      for (int z = 0; z < ZT; ++z) {
+        if ((zt0 + z) * 16 >= nb) break;  // uniform
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          acc[ct * ZT + z] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[z][e], acc[ct * ZT + z], 0, 0, 0);
+      }
     }
   }
   if (wid > 0)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) red[wid - 1][ct][lane] = acc[ct];
+    for (int c = 0; c < CT * ZT; ++c) red[wid - 1][c][lane] = acc[c];
   __syncthreads();
   if (wid == 0) {
     // accumulator layout: lane l, element v holds row 4 v + l / 16, column l % 16
     const int jj = lane & 15, ib = lane >> 4;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      f64x4 t = acc[ct];
 #pragma unroll
-      for (int w = 0; w < 3; ++w) t += red[w][ct][lane];
-      const int c0 = (yt0 + ct) * 16;
+      for (int z = 0; z < ZT; ++z) {
+        f64x4 t = acc[ct * ZT + z];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ii = 4 * v + ib;
-        if (c0 + ii < m && j0 + jj < nb)
-          a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] =
-              (a.ascale != nullptr) ? t[v] * a.ascale[c0 + ii] : t[v];
+        for (int w = 0; w < 3; ++w) t += red[w][ct * ZT + z][lane];
+        const int c0 = (yt0 + ct) * 16, j0 = (zt0 + z) * 16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ii = 4 * v + ib;
+          if (c0 + ii < m && j0 + jj < nb)
+            a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + (j0 + jj)] =
+                (a.ascale != nullptr) ? t[v] * a.ascale[c0 + ii] : t[v];
+        }
       }
     }
   }
   __syncthreads();  // red may be reused by a caller that loops over work items
 }
 
-template <typename TA, typename TB, int S, int CT>
+template <typename TA, typename TB, int S, int CT, int ZT>
 __global__ __launch_bounds__(256) void tn_mfma_kernel(const TnArgs* __restrict__ arr, TnArgs one,
                                                       int ygroups) {
   const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
-  tn_body<TA, TB, S, CT>(a, blockIdx.x, blockIdx.y % ygroups, blockIdx.y / ygroups);
+  tn_body<TA, TB, S, CT, ZT>(a, blockIdx.x, blockIdx.y % ygroups, blockIdx.y / ygroups);
 }
 
 // Sum of the chunk partials, fixed order: wave w adds chunks w, w+4, ... of
@@ -285,6 +302,177 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
   const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
   nn_body<TA, TV, TO, ACC, R, BATCH>(a, blockIdx.x, blockIdx.y);
+}
+
+// nn for wide outputs (nb > 8): NNW_NB output columns per workgroup, so that
+// A streams once per 40 columns instead of once per 8 (the Ritz blocks of
+// the final stage, restarts and orthonormalisation of t columns).  Z tiles
+// of NNW_ZT rows in LDS; the partial sums of the G = 256 / R column groups
+// meet in LDS eight output columns at a time, in a fixed order.
+constexpr int NNW_NB = 40;
+constexpr int NNW_ZT = 96;
+template <typename TA, typename TV, typename TO, typename ACC, int R, int BATCH>
+__device__ __forceinline__ void nn_wide_body(const NnArgs& a, int64_t bx, int by) {
+  static_assert(R == 32 || R == 64, "an 8-column chunk must fill whole output slots");
+  constexpr int NB = NNW_NB, G = 256 / R, QC = 8 * R / 256, NO = R * NB / 256;
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const int j0 = by * NB;
+  if (bx * R >= d || j0 >= nb) return;
+  __shared__ ACC zs[NNW_ZT * NB];
+  __shared__ ACC red[256 * 9];
+  const int tid = threadIdx.x;
+  const int rl = tid % R, g = tid / R;
+  const int64_t r = bx * R + rl;
+  const int64_t lda = a.lda;
+  const TA* ar = (const TA*)a.A + (r < d ? r : d - 1);  // rows past d read row d-1, never stored
+  const TV* V = (const TV*)a.V;
+  TO* Out = (TO*)a.Out;
+  // output slot q of a thread: e = tid + 256 q, row e % R, column e / R;
+  // each thread reads only the V entries it overwrites, so V == Out is safe
+  const double alpha = (a.alpha_p != nullptr) ? *a.alpha_p : a.alpha;
+  double vpre[NO];
+  int mpre[NO];
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
+    const int e = tid + 256 * q;
+    const int rr = e % R, j = e / R;
+    const int64_t row = bx * R + rr;
+    const bool ok = row < d && j0 + j < nb;
+    vpre[q] = (ok && V != nullptr) ? to_f64<TV>(V[row + (int64_t)(j0 + j) * a.ldv]) : 0.0;
+    mpre[q] = (ok && a.mask != nullptr) ? a.mask[j0 + j] : 0;
+  }
+  ACC acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = ACC(0);
+  for (int t0 = 0; t0 < m; t0 += NNW_ZT) {
+    const int tn = (m - t0 < NNW_ZT) ? m - t0 : NNW_ZT;
+    __syncthreads();
+    for (int e = tid; e < tn * NB; e += 256) {
+      const int i = e / NB, j = e - i * NB;
+      double z = (j0 + j < nb) ? a.Z[(int64_t)(t0 + i) * a.ldz + j0 + j] : 0.0;
+      if (a.ascale != nullptr) z *= a.ascale[t0 + i];
+      zs[e] = (ACC)z;
+    }
+    __syncthreads();
+    for (int i = g; i < tn; i += BATCH * G) {
+      ACC av[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int ii = i + u * G;
+        av[u] = (ii < tn) ? to_acc<ACC>(ar[(int64_t)(t0 + ii) * lda]) : ACC(0);
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int ii = i + u * G;
+        if (ii < tn) {
+          const ACC* zr = zs + ii * NB;
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc[j] += av[u] * zr[j];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c8 = 0; c8 < NB / 8; ++c8) {
+    __syncthreads();  // the previous chunk has been read
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[tid * 9 + j] = acc[8 * c8 + j];
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < QC; ++qq) {
+      const int q = c8 * QC + qq;
+      const int e = tid + 256 * q;
+      const int rr = e % R, j = e / R;  // 8 c8 <= j < 8 c8 + 8
+      const int64_t row = bx * R + rr;
+      if (row >= d || j0 + j >= nb) continue;
+      ACC sacc = ACC(0);
+      for (int u = 0; u < G; ++u) sacc += red[(u * R + rr) * 9 + (j - 8 * c8)];
+      double o = (double)sacc;
+      if (alpha != 0.0) o += alpha * vpre[q];
+      if (mpre[q] != 0) o = masked_gauss(a.seed, (int64_t)(j0 + j) * d + row);
+      const int64_t oi = a.out_row ? row * a.ldo + (j0 + j) : row + (int64_t)(j0 + j) * a.ldo;
+      Out[oi] = from_f64<TO>(o);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename TA, typename TV, typename TO, typename ACC, int R, int BATCH>
+__global__ __launch_bounds__(256) void nn_wide_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
+  const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  nn_wide_body<TA, TV, TO, ACC, R, BATCH>(a, blockIdx.x, blockIdx.y);
+}
+
+// nn for wide outputs over a long float64 A on the matrix cores: a wave owns
+// 16 rows of A and CTN 16-column tiles of the output, a workgroup 64 rows;
+// Z is staged in LDS in tiles of NNM_KT rows shared by the four waves, and
+// each A entry, loaded once, feeds CTN v_mfma_f64_16x16x4f64.  Operand
+// layout: A(i, k) at lane i + 16 k, Z(k, j) at lane j + 16 k; accumulator
+// element v of lane l is Out(4 v + l / 16, l % 16).  For Out = alpha V + A Z
+// without mask, column scales or row-major output.
+constexpr int NNM_KT = 32;
+template <int CTN>
+__global__ __launch_bounds__(256) void nn_mfma_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
+  const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 16 * CTN;
+  if (row0 >= d || j0 >= nb) return;
+  constexpr int ZW = 16 * CTN;  // Z columns staged per tile
+  __shared__ double zs[NNM_KT * ZW];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r = row0 + wid * 16 + li;
+  const double* ar = (const double*)a.A + (r < d ? r : d - 1);  // rows past d: never stored
+  const int64_t lda = a.lda;
+  f64x4 acc[CTN];
+#pragma unroll
+  for (int c = 0; c < CTN; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += NNM_KT) {
+    // this tile's A entries first, so that their round trip overlaps the
+    // staging of Z
+    double av[NNM_KT / 4];
+#pragma unroll
+    for (int q = 0; q < NNM_KT / 4; ++q) {
+      const int k = k0 + 4 * q + lk;
+      av[q] = (k < m) ? ar[(int64_t)k * lda] : 0.0;
+    }
+    __syncthreads();  // the previous tile has been read
+    for (int e = tid; e < NNM_KT * ZW; e += 256) {
+      const int kk = e / ZW, j = e - kk * ZW;
+      const int k = k0 + kk;
+      zs[e] = (k < m && j0 + j < nb) ? a.Z[(int64_t)k * a.ldz + j0 + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NNM_KT / 4; ++q) {
+      const double* zr = zs + (4 * q + lk) * ZW + li;
+#pragma unroll
+      for (int c = 0; c < CTN; ++c)
+        if (j0 + 16 * c < nb)  // uniform
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], zr[16 * c], acc[c], 0, 0, 0);
+    }
+  }
+  const double alpha = (a.alpha_p != nullptr) ? *a.alpha_p : a.alpha;
+  const double* V = (const double*)a.V;
+  double* Out = (double*)a.Out;
+#pragma unroll
+  for (int c = 0; c < CTN; ++c) {
+    const int j = j0 + 16 * c + li;
+    if (j >= nb) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row0 + wid * 16 + 4 * v + lk;
+      if (row >= d) continue;
+      double o = acc[c][v];
+      if (alpha != 0.0 && V != nullptr) o += alpha * V[row + (int64_t)j * a.ldv];
+      Out[row + (int64_t)j * a.ldo] = o;
+    }
+  }
 }
 
 // nn for a narrow A (FP8 or bfloat16 entries).  A lane owns 8 consecutive
@@ -453,13 +641,31 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
   // column tiles per workgroup: doubled while the grid keeps 1024 workgroups
   // (wide A: B is then read once per CT tiles instead of once per tile)
   int CT = 1;
+  // wide B (more than one 16-column tile): three B tiles per workgroup, so
+  // that A is read once per 48 columns of B, while that still leaves 1024
+  // workgroups
+  const int ZT = (zmax >= 2 && cmax * ymax * ((zmax + 2) / 3) * count >= 1024) ? 3 : 1;
+  const int64_t zgs = (zmax + ZT - 1) / ZT;
+  const int ctmax = (ZT == 1) ? 8 : 2;  // (register budget with three B tiles)
   if (S == 4 && sizeof(TA) == 8)  // (narrow A is bound by its conversions, not by B)
-    while (CT < 8 && cmax * ((ymax + 2 * CT - 1) / (2 * CT)) * zmax * count >= 1024) CT *= 2;
+    while (CT < ctmax && cmax * ((ymax + 2 * CT - 1) / (2 * CT)) * zgs * count >= 1024) CT *= 2;
   const int64_t yg = (ymax + CT - 1) / CT;
-  dim3 g((unsigned)cmax, (unsigned)(yg * zmax), (unsigned)count);
+  const int64_t zg = (zmax + ZT - 1) / ZT;
+  dim3 g((unsigned)cmax, (unsigned)(yg * zg), (unsigned)count);
 #define TN_GO(S_, CT_) \
-  hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, S_, CT_>), g, dim3(256), 0, s, arr, one, (int)yg)
-  if (S == 4) {
+  hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, S_, CT_, 1>), g, dim3(256), 0, s, arr, one, (int)yg)
+#define TN_GOW(S_) \
+  hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, S_, 1, 3>), g, dim3(256), 0, s, arr, one, (int)yg)
+  if (ZT == 3) {
+    if (S == 4 && CT == 2)
+      hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 4, 2, 3>), g, dim3(256), 0, s, arr, one, (int)yg);
+    else if (S == 4)
+      TN_GOW(4);
+    else if (S == 2)
+      TN_GOW(2);
+    else
+      TN_GOW(1);
+  } else if (S == 4) {
     if (CT == 8)
       TN_GO(4, 8);
     else if (CT == 4)
@@ -474,6 +680,7 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
     TN_GO(1, 1);
   }
 #undef TN_GO
+#undef TN_GOW
   return hipGetLastError();
 }
 
@@ -484,7 +691,7 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
 // faster for the streaming passes over P).
 template <typename TA, typename TV, typename TO, typename ACC>
 hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStream_t s) {
-  int64_t dmax = 0, ymax = 0;
+  int64_t dmax = 0, ymax = 0, nbmax = 0;
   for (int p = 0; p < count; ++p) {
     const NnArgs& a = host[p];
     if (a.d <= 0 || a.nb <= 0) continue;
@@ -493,6 +700,7 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
     if (a.Out == a.A && a.nb > NN_NB) return hipErrorInvalidValue;
     dmax = std::max(dmax, a.d);
     ymax = std::max(ymax, (a.nb + NN_NB - 1) / NN_NB);
+    nbmax = std::max(nbmax, a.nb);
   }
   if (dmax == 0) return hipSuccess;
   const NnArgs one = (count == 1) ? host[0] : NnArgs{};
@@ -509,6 +717,45 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
                          dim3(256), 0, s, arr, one);
       return hipGetLastError();
     }
+  }
+  if constexpr (std::is_same<TA, double>::value && std::is_same<TV, double>::value &&
+                std::is_same<TO, double>::value) {
+    bool plain = nbmax > NN_NB && dmax >= 8192;
+    for (int p = 0; p < count && plain; ++p)
+      plain = host[p].mask == nullptr && host[p].ascale == nullptr && host[p].out_row == 0 &&
+              host[p].Out != host[p].A;
+    if (plain) {
+      // matrix cores: CTN output tiles per workgroup, as many as leave 512
+      // workgroups (A is then read once per 16 CTN columns)
+      const int64_t rb = (dmax + 63) / 64;
+      int ctn = 8;
+      while (ctn > 1 && rb * ((nbmax + 16 * ctn - 1) / (16 * ctn)) * count < 512) ctn /= 2;
+      const dim3 g((unsigned)rb, (unsigned)((nbmax + 16 * ctn - 1) / (16 * ctn)), (unsigned)count);
+      if (ctn == 8)
+        hipLaunchKernelGGL(nn_mfma_kernel<8>, g, dim3(256), 0, s, arr, one);
+      else if (ctn == 4)
+        hipLaunchKernelGGL(nn_mfma_kernel<4>, g, dim3(256), 0, s, arr, one);
+      else if (ctn == 2)
+        hipLaunchKernelGGL(nn_mfma_kernel<2>, g, dim3(256), 0, s, arr, one);
+      else
+        hipLaunchKernelGGL(nn_mfma_kernel<1>, g, dim3(256), 0, s, arr, one);
+      return hipGetLastError();
+    }
+  }
+  if (nbmax > NN_NB && dmax >= 8192) {
+    // wide outputs over a long A: A streams once per NNW_NB columns (short
+    // operands, such as the cores, keep the many small workgroups of the
+    // 8-column kernel)
+    const unsigned yw = (unsigned)((nbmax + NNW_NB - 1) / NNW_NB);
+    if (dmax / 64 >= 256)
+      hipLaunchKernelGGL((nn_wide_kernel<TA, TV, TO, ACC, 64, 8>),
+                         dim3((unsigned)((dmax + 63) / 64), yw, (unsigned)count), dim3(256), 0, s,
+                         arr, one);
+    else
+      hipLaunchKernelGGL((nn_wide_kernel<TA, TV, TO, ACC, 32, 8>),
+                         dim3((unsigned)((dmax + 31) / 32), yw, (unsigned)count), dim3(256), 0, s,
+                         arr, one);
+    return hipGetLastError();
   }
 #define NN_GO(R_, B_)                                                                          \
   hipLaunchKernelGGL((nn_kernel<TA, TV, TO, ACC, R_, B_>),                                     \
