@@ -15,13 +15,16 @@ constexpr int GK = 16;   // K slice
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MT = 32;  // output tile edge of the matrix-core GEMM
-constexpr int MK = 16;  // K slice
+constexpr int MK = 64;  // K slice
 
 // C = alpha op(A) diag(dk) op(B) + beta C on the matrix cores: a 256-thread
 // workgroup owns a 32 x 32 tile of C, each wave one 16 x 16 block of it,
-// accumulated by v_mfma_f64_16x16x4f64 over K slices of 16 staged in LDS.
-// Operand lane layout: A(i, k) at lane i + 16 k, B(k, j) at lane j + 16 k;
-// accumulator element v of lane l is C(4 v + l / 16, l % 16).
+// accumulated by v_mfma_f64_16x16x4f64 over K slices of 64 staged in LDS.
+// The next slice is loaded into registers while the current one is
+// multiplied, so a slice costs one memory round trip at most (the products
+// of the cores have K = n or k, a few slices).  Operand lane layout:
+// A(i, k) at lane i + 16 k, B(k, j) at lane j + 16 k; accumulator element v
+// of lane l is C(4 v + l / 16, l % 16).
 __global__ __launch_bounds__(256) void gemm_kernel(bool ta, bool tb, int64_t m, int64_t n, int64_t k,
                                                    double alpha, const double* __restrict__ A,
                                                    int64_t lda, const double* __restrict__ dk,
@@ -30,39 +33,61 @@ __global__ __launch_bounds__(256) void gemm_kernel(bool ta, bool tb, int64_t m, 
                                                    int64_t ldc) {
   __shared__ double As[MT][MK + 1];  // op(A)(i, k)
   __shared__ double Bs[MK][MT + 1];  // op(B)(k, j)
+  constexpr int NL = MT * MK / 256;  // elements of each tile per thread
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int64_t i0 = blockIdx.x * (int64_t)MT, j0 = blockIdx.y * (int64_t)MT;
   const int bi = (wid >> 1) * 16, bj = (wid & 1) * 16;
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = 0; k0 < k; k0 += MK) {
+  // element q of this thread: (ii, kk) of op(A) and (kb, jj) of op(B), with
+  // consecutive threads on consecutive addresses
+  auto a_pos = [&](int q, int& ii, int& kk) {
+    const int e = tid + q * 256;
+    if (!ta) { ii = e & (MT - 1); kk = e / MT; } else { kk = e & (MK - 1); ii = e / MK; }
+  };
+  auto b_pos = [&](int q, int& kb, int& jj) {
+    const int e = tid + q * 256;
+    if (!tb) { kb = e & (MK - 1); jj = e / MK; } else { jj = e & (MT - 1); kb = e / MT; }
+  };
+  double ra[NL], rb[NL];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = tid + q * 256;  // 512 elements of each tile
-      int ii, kk;
-      if (!ta) { ii = e & 31; kk = e >> 5; } else { kk = e & 15; ii = e >> 4; }
-      const int64_t gi = i0 + ii, gk = k0 + kk;
-      double v = 0.0;
+    for (int q = 0; q < NL; ++q) {
+      int ii, kk, kb, jj;
+      a_pos(q, ii, kk);
+      b_pos(q, kb, jj);
+      const int64_t gi = i0 + ii, gk = k0 + kk, gj = j0 + jj, gk2 = k0 + kb;
+      double v = 0.0, w = 0.0;
       if (gi < m && gk < k) {
         v = ta ? A[gk + gi * lda] : A[gi + gk * lda];
         if (dk != nullptr) v *= dk[gk];
       }
-      As[ii][kk] = v;
-      int jj, kb;
-      if (!tb) { kb = e & 15; jj = e >> 4; } else { jj = e & 31; kb = e >> 5; }
-      const int64_t gj = j0 + jj, gk2 = k0 + kb;
-      double w = 0.0;
       if (gj < n && gk2 < k) w = tb ? B[gj + gk2 * ldb] : B[gk2 + gj * ldb];
-      Bs[kb][jj] = w;
+      ra[q] = v;
+      rb[q] = w;
+    }
+  };
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  if (k > 0) load(0);
+  for (int64_t k0 = 0; k0 < k; k0 += MK) {
+    __syncthreads();  // the previous slice has been read
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      int ii, kk, kb, jj;
+      a_pos(q, ii, kk);
+      b_pos(q, kb, jj);
+      As[ii][kk] = ra[q];
+      Bs[kb][jj] = rb[q];
     }
     __syncthreads();
+    if (k0 + MK < k) load(k0 + MK);  // in flight during the products below
+    const int kl = (k - k0 < MK) ? (int)(k - k0) : MK;
 #pragma unroll
     for (int ks = 0; ks < MK; ks += 4) {
+      if (ks >= kl) break;  // uniform
       const double a = As[bi + (lane & 15)][ks + (lane >> 4)];
       const double b = Bs[ks + (lane >> 4)][bj + (lane & 15)];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
-    __syncthreads();
   }
   const int64_t gj = j0 + bj + (lane & 15);
 #pragma unroll
