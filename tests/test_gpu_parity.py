@@ -333,6 +333,35 @@ def test_expmv_opmv_c2_full_size(torch, eda, c2, wcore):
     h.close()
 
 
+@pytest.mark.parametrize("b,storage", [(39, "f64"), (99, "f64"), (39, "f32")])
+def test_expmv_opmv_c2_wide_blocks(torch, eda, c2, b, storage):
+    """Blocks as wide as the Ritz blocks of the final stage (t = 39 at this
+    size, 99 for the large workload), on the full-size factor: the wide
+    launch shapes of both passes (matrix-core P Z for float64, the
+    40-column vector kernel for float32, three B tiles per workgroup in
+    P^T V).  Oracle: the closed form of Theorem 3.1; the float32 bound is
+    the storage-rounding bound of the narrow-storage test."""
+    log(f"expmv/opmv C2 full size, b={b}, {storage} storage")
+    h, _, _ = prepared(torch, eda, c2, storage=storage)
+    V = np.random.default_rng(b).standard_normal((c2.d, b))
+    sB = np.linalg.svd(c2.H_B, compute_uv=False) ** 2
+    u = 2.0 ** -24 if storage == "f32" else 0.0
+    for which, H, c, En in (("W", c2.H_W, -0.5, 1.0), ("B", c2.H_B, 1.0, np.exp(sB[0]))):
+        out, s = h.expmv(which, c, dev(torch, V))
+        ref = O.exp_action_thm31(H, c, V)
+        err = rel_op_err(host(out) * np.exp(s), ref, En, V)
+        bound = max(1e-13, 4 * abs(c) * u * np.linalg.norm(H, 2) * np.linalg.norm(H))
+        log(f"  {which} c={c} err={err:.2e} bound={bound:.2e}")
+        assert err <= bound
+    if storage == "f64":
+        out, s = h.opmv("M", dev(torch, V))
+        ref = O.lanczos_action_thm31(c2.H_W, c2.H_B, V)
+        err = rel_op_err(host(out) * np.exp(s), ref, np.exp(sB[0]), V)
+        log(f"  M err={err:.2e}")
+        assert err <= 1e-13
+    h.close()
+
+
 # ---------------------------------------------------------------------------
 # a5-a7: block Lanczos solve, Rayleigh-Ritz, back-transform + orth
 # ---------------------------------------------------------------------------
