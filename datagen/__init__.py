@@ -30,6 +30,7 @@ import numpy as np
 __all__ = [
     "Problem",
     "make_samples",
+    "make_split",
     "start_block",
     "config",
     "batched_configs",
@@ -85,6 +86,40 @@ def make_samples(d: int, counts: Sequence[int], r: int, seed: int,
         X[:, col:col + nj] = Xj
         col += nj
     return X
+
+
+def make_split(d: int, counts: Sequence[int], test_counts: Sequence[int], r: int, seed: int,
+               signal: float = 0.5, noise: float = 0.05):
+    """Training and testing samples of the same classes: X_train equals
+    make_samples(d, counts, r, seed); the testing samples (test_counts[j]
+    per class, same U and class codes) are drawn after all of it, class by
+    class, an m_j x r block of g followed by an m_j x d block of eps.
+    Returns (X_train, X_test, test_labels)."""
+    counts = np.asarray(counts, dtype=np.int64)
+    test_counts = np.asarray(test_counts, dtype=np.int64)
+    k = counts.size
+    if test_counts.size != k:
+        raise ValueError("one test count per class")
+    rng = np.random.default_rng(seed)
+    U = np.linalg.qr(rng.standard_normal((d, r)))[0]
+    A = rng.standard_normal((k, r))
+
+    def draw(cs):
+        out = np.empty((d, int(cs.sum())), dtype=np.float64, order="F")
+        col = 0
+        for j in range(k):
+            nj = int(cs[j])
+            G = rng.standard_normal((nj, r))
+            E = rng.standard_normal((nj, d))
+            Xj = U @ (A[j][None, :] + signal * G).T + noise * E.T
+            Xj /= np.linalg.norm(Xj, axis=0, keepdims=True)
+            out[:, col:col + nj] = Xj
+            col += nj
+        return out
+
+    X_train = draw(counts)
+    X_test = draw(test_counts)
+    return X_train, X_test, np.repeat(np.arange(k, dtype=np.int32), test_counts)
 
 
 def start_block(d: int, b: int, seed: int) -> np.ndarray:
