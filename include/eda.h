@@ -294,6 +294,24 @@ eda_status eda_gram(eda_handle h, double* G, int64_t ldg);
 eda_status eda_syev(eda_handle h, int64_t n, const double* A, int64_t lda,
                     double* w, double* Z, int64_t ldz);
 
+/* Nearest-neighbour classification in the EDA subspace (Section 3.3): the
+ * distance between training sample x_i and testing sample y_j is
+ * d_ij = ||X^T (x_i - y_j)||_2 for the orthonormal d x t matrix X (as
+ * returned by eda_solve), and testing sample j takes the label of the
+ * training sample with the smallest d_ij (1-NN; on equal distances the
+ * smallest index, a choice the paper leaves open).  X (ldx >= d), train
+ * (d x n_train, ldtr >= d), test (d x n_test, ldte >= d): float64, device,
+ * column-major; train_labels: device int32 [n_train].  Outputs (device):
+ * pred[n_test] = train_labels[nn_index[j]], nn_index[n_test], nn_dist[n_test]
+ * = min_i d_ij.  1 <= t <= min(d, 1024), n_train, n_test >= 1.  Independent
+ * of the preparation; uses the handle's stream and workspaces; stream-ordered
+ * (no synchronisation).  A testing sample whose distances are all NaN gets
+ * index and label -1 and distance NaN. */
+eda_status eda_nn_classify(eda_handle h, int64_t d, int64_t t, const double* X, int64_t ldx,
+                           int64_t n_train, const double* train, int64_t ldtr,
+                           const int32_t* train_labels, int64_t n_test, const double* test,
+                           int64_t ldte, int32_t* pred, int64_t* nn_index, double* nn_dist);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = [
     "eda_create", "eda_destroy", "eda_strerror", "eda_last_error", "eda_scatter_factors",
     "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_solve_direct", "eda_solve_batched",
     "eda_gram",
-    "eda_syev", "eda_autotune",
+    "eda_syev", "eda_autotune", "eda_nn_classify",
 ]
 
 
@@ -138,6 +138,9 @@ def load_library():
     L.eda_autotune.argtypes = [vp, i64, i64, i32, ctypes.c_int, ctypes.POINTER(i32),
                                ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.eda_autotune.restype = ctypes.c_int
+    L.eda_nn_classify.argtypes = [vp, i64, i64, vp, i64, i64, vp, i64, vp, i64, vp, i64, vp, vp,
+                                  vp]
+    L.eda_nn_classify.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -387,6 +390,31 @@ class Handle:
         G = _empty_cm(N, N, self._torch.float64, self.device)
         self._check(self.lib.eda_gram(self._h, G.data_ptr(), _ld(G)))
         return G
+
+    def nn_classify(self, X, train, train_labels, test):
+        """1-NN classification in span X (Section 3.3): for every column of
+        `test`, the label and index of the training column nearest in the
+        distance ||X^T (x_i - y_j)||_2, and that distance (ties: smallest
+        index).  X: d x t orthonormal; train: d x n_train; test: d x n_test
+        (float64 CUDA); train_labels: int32 CUDA tensor of n_train entries."""
+        torch = self._torch
+        X, train, test = self._f64(X), self._f64(train), self._f64(test)
+        if train_labels.dtype != torch.int32 or train_labels.device.type != "cuda":
+            raise TypeError("train_labels: expected an int32 CUDA tensor")
+        train_labels = train_labels.contiguous()
+        d, t = X.shape
+        n_tr, n_te = train.shape[1], test.shape[1]
+        if train.shape[0] != d or test.shape[0] != d or train_labels.numel() != n_tr:
+            raise ValueError("shapes of X, train, train_labels and test do not agree")
+        pred = torch.empty(n_te, dtype=torch.int32, device=X.device)
+        idx = torch.empty(n_te, dtype=torch.int64, device=X.device)
+        dist = torch.empty(n_te, dtype=torch.float64, device=X.device)
+        self._check(self.lib.eda_nn_classify(self._h, d, t, X.data_ptr(), _ld(X), n_tr,
+                                             train.data_ptr(), _ld(train),
+                                             train_labels.data_ptr(), n_te, test.data_ptr(),
+                                             _ld(test), pred.data_ptr(), idx.data_ptr(),
+                                             dist.data_ptr()))
+        return pred, idx, dist
 
     def syev(self, A):
         A = self._f64(A)

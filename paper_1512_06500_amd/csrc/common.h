@@ -355,6 +355,12 @@ hipError_t launch_scale_cols(int64_t rows, int64_t cols, const double* src, int6
 hipError_t launch_set_diag(int64_t cnt, const double* v, double* dst, int64_t ldd, hipStream_t s);
 // Column 2-norms / sign fix / scaling helpers.
 hipError_t launch_sign_fix(int64_t d, int64_t t, double* X, int64_t ldx, hipStream_t s);
+// 1-NN in a t-dimensional projection: for every testing row j of Pte
+// (row-major n_test x t) the training row i of Ptr (row-major n_train x t)
+// with the smallest ||Ptr_i - Pte_j||_2 (ties: the smallest i).
+hipError_t launch_nn_classify(int64_t n_train, int64_t n_test, int64_t t, const double* Ptr,
+                              const double* Pte, const int32_t* labels, int32_t* pred,
+                              int64_t* idx, double* dist, hipStream_t s);
 hipError_t launch_fill(int64_t count, double value, double* dst, hipStream_t s);
 hipError_t launch_fill_i32(int64_t count, int value, int* dst, hipStream_t s);
 // Symmetrised copy T = (H[0:m,0:m] + H[0:m,0:m]^T)/2.

@@ -360,6 +360,7 @@ void eda_destroy(eda_handle h) {
                   &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale};
     for (Buf& b : h->dir) release(b);
     for (Buf& b : h->af) release(b);
+    for (Buf& b : h->nnp) release(b);
     for (Buf* b : all) release(*b);
     for (auto& c : h->cores) release(c.buf);
     for (hipEvent_t e : h->op_ev) (void)hipEventDestroy(e);

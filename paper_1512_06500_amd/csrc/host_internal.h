@@ -61,6 +61,7 @@ struct eda_handle_s {
   eda::Buf pscale;      // FP8 storage: column j of P is pscale[j] times its FP8 copy
   eda::Buf dir[10];     // workspaces of eda_solve_direct
   eda::Buf af[10];      // workspaces of the Arnoldi-form solve
+  eda::Buf nnp[2];      // projections of the classifier (training, testing)
   double normW = 0.0;   // ||H_W^T H_W||_1
   bool w_eig = false;   // eigenpairs of H_W^T H_W available
   std::vector<double> hwW, hwB;

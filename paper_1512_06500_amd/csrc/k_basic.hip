@@ -646,6 +646,83 @@ hipError_t launch_copy2d(int64_t rows, int64_t cols, const void* src, DT sdt, in
   Copy2dArgs a{rows, cols, lds, ldd, src, dst};
   return launch_copy2d_multi(1, &a, nullptr, sdt, ddt, s);
 }
+namespace {
+
+// One workgroup per testing sample: its projection in LDS, the training
+// projections split over the threads (each keeps its first minimum, rows in
+// increasing order), then a fixed-order reduction that keeps the smaller
+// index on equal distances.
+constexpr int NNC_TMAX = 1024;
+__global__ __launch_bounds__(256) void nn_classify_kernel(int64_t n_train, int64_t t,
+                                                          const double* __restrict__ Ptr,
+                                                          const double* __restrict__ Pte,
+                                                          const int32_t* __restrict__ labels,
+                                                          int32_t* __restrict__ pred,
+                                                          int64_t* __restrict__ idx,
+                                                          double* __restrict__ dist) {
+  __shared__ double q[NNC_TMAX];
+  __shared__ double bd[256];
+  __shared__ int64_t bi[256];
+  const int64_t j = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int64_t k = tid; k < t; k += 256) q[k] = Pte[j * t + k];
+  __syncthreads();
+  double best = INFINITY;
+  int64_t besti = -1;
+  for (int64_t i = tid; i < n_train; i += 256) {
+    const double* p = Ptr + i * t;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t k = 0;
+    for (; k + 4 <= t; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double df = p[k + u] - q[k + u];
+        acc[u] = fma(df, df, acc[u]);
+      }
+    }
+    for (; k < t; ++k) {
+      const double df = p[k] - q[k];
+      acc[0] = fma(df, df, acc[0]);
+    }
+    const double d2 = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if (d2 < best) {
+      best = d2;
+      besti = i;
+    }
+  }
+  bd[tid] = best;
+  bi[tid] = besti;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      const double o = bd[tid + h];
+      const int64_t oi = bi[tid + h];
+      if (oi >= 0 && (bi[tid] < 0 || o < bd[tid] || (o == bd[tid] && oi < bi[tid]))) {
+        bd[tid] = o;
+        bi[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {  // (no index: every distance was NaN)
+    const int64_t b = bi[0];
+    idx[j] = b;
+    pred[j] = (b >= 0) ? labels[b] : -1;
+    dist[j] = (b >= 0) ? sqrt(bd[0]) : NAN;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_nn_classify(int64_t n_train, int64_t n_test, int64_t t, const double* Ptr,
+                              const double* Pte, const int32_t* labels, int32_t* pred,
+                              int64_t* idx, double* dist, hipStream_t s) {
+  if (n_train < 1 || n_test < 1 || t < 1 || t > NNC_TMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nn_classify_kernel, dim3((unsigned)n_test), dim3(256), 0, s, n_train, t,
+                     Ptr, Pte, labels, pred, idx, dist);
+  return hipGetLastError();
+}
+
 hipError_t launch_sign_fix(int64_t d, int64_t t, double* X, int64_t ldx, hipStream_t s) {
   SignArgs a{d, t, ldx, X};
   return launch_sign_fix_multi(1, &a, nullptr, s);

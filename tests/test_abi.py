@@ -121,6 +121,26 @@ def test_autotune_rejects_bad_arguments(lib, handle, d, N, b, storage):
     assert lib.eda_last_error(handle).decode()
 
 
+@pytest.mark.parametrize("d,t,ntr,nte,ldx,ldtr,ldte", [
+    (0, 1, 4, 4, 1, 1, 1),        # d < 1
+    (10, 0, 4, 4, 10, 10, 10),    # t < 1
+    (10, 11, 4, 4, 10, 10, 10),   # t > d
+    (2000, 1025, 4, 4, 2000, 2000, 2000),  # t > 1024
+    (10, 2, 0, 4, 10, 10, 10),    # no training samples
+    (10, 2, 4, 0, 10, 10, 10),    # no testing samples
+    (10, 2, 4, 4, 9, 10, 10),     # ldx < d
+    (10, 2, 4, 4, 10, 9, 10),     # ldtr < d
+    (10, 2, 4, 4, 10, 10, 9),     # ldte < d
+])
+def test_nn_classify_rejects_bad_arguments(lib, handle, d, t, ntr, nte, ldx, ldtr, ldte):
+    st = lib.eda_nn_classify(handle, d, t, FAKE, ldx, ntr, FAKE, ldtr, FAKE, nte, FAKE, ldte,
+                             FAKE, FAKE, FAKE)
+    assert st == eda.EDA_ERR_ARG
+    assert lib.eda_last_error(handle).decode()
+    assert lib.eda_nn_classify(handle, 10, 2, None, 10, 4, FAKE, 10, FAKE, 4, FAKE, 10, FAKE,
+                               FAKE, FAKE) == eda.EDA_ERR_ARG
+
+
 def test_null_handle(lib):
     assert lib.eda_prepare(None, 10, 4, 2, FAKE, 10, FAKE, 10, 0) == eda.EDA_ERR_ARG
     assert lib.eda_create(None, None) == eda.EDA_ERR_ARG

@@ -363,6 +363,85 @@ def test_expmv_opmv_c2_wide_blocks(torch, eda, c2, b, storage):
 
 
 # ---------------------------------------------------------------------------
+# f3: nearest-neighbour classification in the EDA subspace (Section 3.3)
+# ---------------------------------------------------------------------------
+
+def _classify(torch, h, V, train, labels, test):
+    pred, idx, dist = h.nn_classify(dev(torch, V), dev(torch, train),
+                                    torch.as_tensor(np.asarray(labels, dtype=np.int32)).cuda(),
+                                    dev(torch, test))
+    return host(pred), host(idx), host(dist)
+
+
+def test_nn_classify_hand_example_and_ties(torch, eda):
+    """The hand-computed example of the oracle pins: exact distances, labels,
+    and the smallest index on a three-way tie."""
+    log("nn_classify hand example")
+    h = eda.Handle()
+    train = np.array([[1.0, 0.0, 0.0, 0.6], [0.0, 1.0, 0.0, 0.8], [0.0, 0.0, 1.0, 0.0]])
+    test = np.array([[0.9, 0.5, 0.0], [0.1, 0.7, 0.0], [0.4, 0.5, 1.0]])
+    pred, idx, dist = _classify(torch, h, np.eye(3)[:, :2], train, [10, 11, 12, 13], test)
+    assert idx.tolist() == [0, 3, 2] and pred.tolist() == [10, 13, 12]
+    np.testing.assert_allclose(dist, [np.sqrt(0.02), np.sqrt(0.02), 0.0], rtol=0, atol=1e-15)
+    pred, idx, dist = _classify(torch, h, np.eye(3)[:, 2:3], train, [5, 6, 7, 8],
+                                np.array([[0.6], [0.8], [0.0]]))
+    assert idx.tolist() == [0] and pred.tolist() == [5] and dist.tolist() == [0.0]
+    h.close()
+
+
+@pytest.mark.parametrize("n_test_per_class", [5, 1])
+def test_nn_classify_c2_against_oracle(torch, eda, n_test_per_class):
+    """C2-sized split (d = 10304, 200 training samples, 40 classes): the
+    oracle's EDA solution on both sides; the nearest index must agree wherever
+    the oracle's nearest distance is unique (second nearest more than 1e-10
+    away), else be one of the near-tied; distances to 1e-12."""
+    p = datagen.config("C2", with_data=False)
+    Xtr, Xte, lte = datagen.make_split(p.d, p.counts, np.full(p.k, n_test_per_class), p.r, p.seed)
+    log(f"nn_classify C2 split, {Xte.shape[1]} testing samples")
+    H_W, H_B = O.scatter_factors(Xtr, p.counts)
+    V = O.eda_reduced(H_W, H_B, p.t).X
+    lab_o, idx_o, dist_o = O.nn.nn_classify(V, Xtr, p.labels(), Xte)
+    D = O.nn.nn_distances(V, Xtr, Xte)
+    h = eda.Handle()
+    pred, idx, dist = _classify(torch, h, V, Xtr, p.labels(), Xte)
+    h.close()
+    np.testing.assert_allclose(dist, dist_o, rtol=0, atol=1e-12)
+    Ds = np.sort(D, axis=0)
+    unique = (Ds[1] - Ds[0]) > 1e-10
+    log(f"  unique nearest: {int(unique.sum())}/{unique.size}, accuracy {np.mean(pred == lte):.3f}")
+    assert np.array_equal(idx[unique], idx_o[unique])
+    near = D[idx, np.arange(D.shape[1])] <= Ds[0] + 1e-10
+    assert near.all()
+    assert np.array_equal(pred, p.labels()[idx])
+
+
+def test_nn_distances_within_thm38_bounds(torch, eda):
+    """Theorem 3.8 on a solution computed to tol 1e-4: the nearest distances
+    measured with it stay within the bounds around those of the exact
+    subspace (the oracle's), with sin and cos of the angle between them."""
+    p = datagen.config("C2", with_data=False)
+    Xtr, Xte, lte = datagen.make_split(p.d, p.counts, np.full(p.k, 2), p.r, p.seed)
+    log("nn distances vs Theorem 3.8, tol 1e-4")
+    H_W, H_B = O.scatter_factors(Xtr, p.counts)
+    V = O.eda_reduced(H_W, H_B, p.t).X
+    _, _, d_exact = O.nn.nn_classify(V, Xtr, p.labels(), Xte)
+    h = eda.Handle()
+    Xd = dev(torch, Xtr)
+    H_Wd, H_Bd = h.scatter_factors(Xd, p.counts.tolist())
+    h.prepare(H_Wd, H_Bd)
+    res = h.solve(p.t, 1e-4, block=8, seed=p.seed)
+    assert res.status == 0
+    Xt = host(res.X)
+    pred, idx, d_approx = _classify(torch, h, Xt, Xtr, p.labels(), Xte)
+    h.close()
+    s, c = O.sin_angle(V, Xt), O.nn.cos_angle(V, Xt)
+    lo, hi = O.nn.thm38_bounds(d_approx, s, c)
+    log(f"  sin={s:.2e} cos={c:.6f} max|d~-d|={np.max(np.abs(d_approx - d_exact)):.2e} "
+        f"accuracy {np.mean(pred == lte):.3f}")
+    assert np.all(lo <= d_exact + 1e-12) and np.all(d_exact <= hi + 1e-12)
+
+
+# ---------------------------------------------------------------------------
 # a5-a7: block Lanczos solve, Rayleigh-Ritz, back-transform + orth
 # ---------------------------------------------------------------------------
 
