@@ -27,6 +27,11 @@ of the pencil, NumPy/SciPy on the host's cores) on the same workload.
 k = 38, n = 1216, t = 37 workload at tol 1e-6, float64 end to end against
 bfloat16 factors + float32 basis + float64 refinement (prepare + solve each).
 
+`nn_tol_sweep`: Section 3.3 on a split of the headline workload (200
+training, 200 testing samples): 1-NN accuracy, angle to the tol-1e-10
+subspace and the Theorem 3.8 check for tol 1e-2 ... 1e-10, and the time of
+one eda_nn_classify call.
+
 `batched`: 64 independent problems of uneven shape (d in {1024, 4096,
 10304}, k in [10, 68], n_j in [2, 20], float32 factors, tol 1e-6) solved by
 one eda_solve_batched call, problems/s, against the same problems solved one
@@ -231,6 +236,59 @@ def solve_variants(torch, eda, reps: int = 5) -> dict:
     return out
 
 
+def nn_tol_sweep(torch, eda, reps: int = 20) -> dict:
+    """Section 3.3 on the headline-shaped split (d = 10304, 200 training
+    samples of 40 classes, 5 testing samples per class from the same class
+    model): solve to each tolerance, classify the testing samples by 1-NN in
+    the solution's subspace, and compare with the tightest solution: the
+    accuracy, sin of the angle, the largest change of a nearest distance and
+    whether Theorem 3.8's bounds hold.  Also the classification call itself
+    (projections of all samples + distances): time and the bytes of the
+    samples it streams."""
+    import datagen
+    p = datagen.config("C2", with_data=False)
+    Xtr, Xte, lte = datagen.make_split(p.d, p.counts, np.full(p.k, 5), p.r, p.seed)
+    h = eda.Handle()
+    tr, te = _upload(torch, Xtr), _upload(torch, Xte)
+    labels = torch.as_tensor(p.labels()).cuda()
+    HW, HB = h.scatter_factors(tr, p.counts.tolist())
+    h.prepare(HW, HB)
+    sols = {}
+    for tol in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10):
+        r = h.solve(p.t, tol, block=8, seed=p.seed)
+        pred, idx, dist = h.nn_classify(r.X, tr, labels, te)
+        torch.cuda.synchronize()
+        sols[tol] = (r, r.X.cpu().numpy(), pred.cpu().numpy(), dist.cpu().numpy())
+    Vref = sols[1e-10][1]
+    dref = sols[1e-10][3]
+    rows = []
+    for tol, (r, X, pred, dist) in sols.items():
+        # sin = ||(I - Vref Vref^T) X||_2, cos = ||Vref^T X||_2 (Theorem 3.8)
+        sin = float(np.linalg.norm(X - Vref @ (Vref.T @ X), 2))
+        cos = float(np.linalg.norm(Vref.T @ X, 2))
+        lo, hi = (dist - 2 * sin) / cos, dist * cos + 2 * sin
+        rows.append({"tol": tol, "status": r.status, "iters": r.info["iters"],
+                     "accuracy": float(np.mean(pred == lte)), "sin_angle_vs_1e-10": sin,
+                     "max_nn_dist_change": float(np.max(np.abs(dist - dref))),
+                     "thm38_holds": bool(np.all(lo <= dref + 1e-12) and np.all(dref <= hi + 1e-12))})
+    X = sols[1e-8][0].X
+    for _ in range(3):
+        h.nn_classify(X, tr, labels, te)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        h.nn_classify(X, tr, labels, te)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    nbytes = 8.0 * p.d * (Xtr.shape[1] + Xte.shape[1] + p.t)
+    h.close()
+    return {"workload": f"d={p.d}, {Xtr.shape[1]} training / {Xte.shape[1]} testing samples, "
+                        f"k={p.k}, t={p.t}",
+            "sweep": rows,
+            "classify": {"us": 1e6 * el, "sample_bytes": nbytes, "GB_per_s": nbytes / el / 1e9,
+                         "testing_samples_per_s": Xte.shape[1] / el}}
+
+
 def batched(torch, eda, count: int = 64, reps: int = 2) -> dict:
     import datagen
     ps = datagen.batched_configs(count)
@@ -362,6 +420,7 @@ def main():
     if not args.no_extra:
         out["mixed_vs_f64"] = mixed_vs_f64(torch, eda)
         out["solve_variants"] = solve_variants(torch, eda)
+        out["nn_tol_sweep"] = nn_tol_sweep(torch, eda)
         out["large_fp8_vs_f64"] = large_fp8_vs_f64(torch, eda)
         out["batched"] = batched(torch, eda)
     if not args.no_cpu_baseline:
