@@ -177,6 +177,9 @@ struct ReduceArgs {  // C = beta C + alpha sum_c part (col-major), Z = zalpha su
   double* C;
   double* Z;
   const int* gate;
+  // when mc >= 0, rows i >= mc go to C2[(i - mc) + j*ldc2] (plain sum) instead of C
+  int64_t mc = -1, ldc2 = 0;
+  double* C2 = nullptr;
 };
 struct NnArgs {      // Out = alpha V + A Z
   int64_t d, m, nb, lda, ldz, ldv, ldo;
@@ -217,6 +220,9 @@ struct PcholArgs {
   int* flag;
   const double* part;  // when not null, G = sum over `chunks` tn partials (layout of tn, m = nb = b)
   int64_t chunks;
+  // when not null, G -= corr^T corr (corr row-major mcorr x b, mcorr b <= 2048)
+  const double* corr = nullptr;
+  int64_t mcorr = 0;
 };
 struct MaskedRandnArgs {  // Q[:, j] = seeded Gaussian where mask[j] != 0
   int64_t d, b, ldq;
@@ -408,10 +414,12 @@ hipError_t launch_tn_partial(int64_t d, int64_t m, int64_t nb, const void* A, DT
                              const double* ascale = nullptr);
 // C_col[i + j*ldc] = beta*C_col + alpha*sum_c part  (if C_col != null)
 // Z_row[i*ldz + j] = zalpha*sum_c part              (if Z_row != null)
+// (with mc >= 0: rows i >= mc go to C2[(i - mc) + j*ldc2] = sum_c part instead)
 hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const double* part,
                                   double alpha, double beta, double* C_col, int64_t ldc,
                                   double zalpha, double* Z_row, int64_t ldz, const int* gate,
-                                  hipStream_t s);
+                                  hipStream_t s, int64_t mc = -1, double* C2 = nullptr,
+                                  int64_t ldc2 = 0);
 // Out = alpha * V + A * Z, Z row-major (Z[i*ldz + j]) float64, m columns of A.
 // Out column-major (Out[r + j*ldo]) or, with out_row, row-major (Out[r*ldo + j]).
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
@@ -453,7 +461,8 @@ hipError_t launch_chol(int64_t b, const double* G, int64_t ldg, double* Rinv, in
 hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
                         int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
                         double* R, int64_t ldr, int* mask, int* flag, hipStream_t s,
-                        const double* part = nullptr, int64_t chunks = 0);
+                        const double* part = nullptr, int64_t chunks = 0,
+                        const double* corr = nullptr, int64_t mcorr = 0);
 // Q[:, j] = seeded Gaussian for the columns with mask[j] != 0.
 hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint64_t seed,
                                     void* Q, DT qdt, int64_t ldq, hipStream_t s);

@@ -97,14 +97,16 @@ eda_status lanczos_op(Solver& S, int64_t m) {
   eda_handle h = S.h;
   // e^{-s} is read from the device, so a captured step stays valid when a
   // later preparation changes the shift
+  // W goes straight into the slot of the next block, Q[:, m+b:m+2b]
+  void* W = S.Qc(m + S.b);
   if (!S.track)
-    return expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt, S.ldq,
-                 h->Wb.p, S.qdt, S.ldq, h->alphaB_dev.d());
+    return expop(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt, S.ldq, W,
+                 S.qdt, S.ldq, h->alphaB_dev.d());
   // P^T V_m goes to columns m .. m+b of P^T Q
   double* pq = h->PQ[S.cur].d() + m;
   STCHK(expop_first(h, false, 0, h->N, S.b, S.Qc(m), S.qdt, S.ldq, pq, S.ldpq));
   return expop_second(h, false, 0, h->N, h->CM.d(), h->N, h->alphaB, S.b, S.Qc(m), S.qdt,
-                      S.ldq, h->Wb.p, S.qdt, S.ldq, h->alphaB_dev.d(), pq, S.ldpq);
+                      S.ldq, W, S.qdt, S.ldq, h->alphaB_dev.d(), pq, S.ldpq);
 }
 
 // The rest of the block step: orthonormalise W into the next block and
@@ -114,36 +116,42 @@ eda_status lanczos_orth(Solver& S, int64_t m, bool repair) {
   const int64_t d = S.d, b = S.b, ldq = S.ldq, ldh = S.ldh;
   const DT qdt = S.qdt;
   double* H = S.H();
-  void* W = h->Wb.p;
+  // W (the product) already sits in the slot of the next block
+  char* Qn = S.Qc(m + b);
+  void* W = Qn;
   // without the repair pass, a raised flag goes to the sticky slot 2 that
   // the host reads at every check
   int* flags = repair ? h->flags.i() : h->flags.i() + 2;
-  // CGS2 against Q[:, 0:m+b]
+  // CGS2 against Q[:, 0:m+b], first pass
   double* Hcol = H + m * ldh;
   STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, W, ldq, b, Hcol, ldh, 0.0, nullptr));
-  STCHK(cgs_pass(h, d, m + b, S.Q(), qdt, ldq, W, ldq, b, Hcol, ldh, 1.0, nullptr));
+  // Second pass and the Gram matrix of its result from one product:
+  // [Q W]^T W = [h2; W^T W] (W adjacent to Q), h2 added to H, and
+  // (W - Q h2)^T (W - Q h2) = W^T W - h2^T h2 for orthonormal Q, formed by
+  // the Cholesky kernel (h2 is of the order of the rounding of the first
+  // pass, so the difference loses nothing).
+  {
+    const int64_t chunks = tn_chunks(d, m + 2 * b, b);
+    HIPCHK(launch_tn_partial(d, m + 2 * b, b, S.Q(), qdt, ldq, W, qdt, ldq, h->part.d(), chunks,
+                             nullptr, h->stream));
+    HIPCHK(launch_reduce_partials(chunks, m + 2 * b, b, h->part.d(), 1.0, 1.0, Hcol, ldh, -1.0,
+                                  h->hz.d(), b, nullptr, h->stream, m + b, h->Gs.d(), b));
+    HIPCHK(launch_nn(d, m + b, b, S.Q(), qdt, ldq, h->hz.d(), b, 1.0, W, qdt, ldq, W, qdt, ldq,
+                     nullptr, h->stream));
+  }
   // Block orthonormalisation, R = R2 R1 going to H[m+b:m+2b, m:m+b].
   // Pass 1 is rank revealing: directions along which the Krylov space has
   // become invariant are deflated and replaced by fresh random directions
   // with zero coupling (their rows of R1 are zero).
-  char* Qn = S.Qc(m + b);
-  {
-    const int64_t chunks = tn_chunks(d, b, b);
-    // (pchol sums the chunk partials; the product writes the random
-    // replacement columns)
-    HIPCHK(launch_tn_partial(d, b, b, W, qdt, ldq, W, qdt, ldq, h->part.d(), chunks, nullptr,
-                             h->stream));
-    const bool fused = b <= 16;
-    if (!fused)
-      HIPCHK(launch_reduce_partials(chunks, b, b, h->part.d(), 1.0, 0.0, h->Gs.d(), b, 0.0,
-                                    nullptr, 0, nullptr, h->stream));
-    HIPCHK(launch_pchol(b, h->Gs.d(), b, Hcol, m + b, ldh, 1e-13, 1e-4, false, h->Rinv.d(), b,
-                        h->R1.d(), b, h->mask.i(), flags, h->stream,
-                        fused ? h->part.d() : nullptr, chunks));
-    HIPCHK(launch_nn(d, b, b, W, qdt, ldq, h->Rinv.d(), b, 0.0, nullptr, qdt, ldq, Qn, qdt, ldq,
-                     nullptr, h->stream, false, nullptr, nullptr, h->mask.i(),
-                     0x5eed0000ull + (uint64_t)m));
-  }
+  HIPCHK(launch_pchol(b, h->Gs.d(), b, Hcol, m + b, ldh, 1e-13, 1e-4, false, h->Rinv.d(), b,
+                      h->R1.d(), b, h->mask.i(), flags, h->stream, nullptr, 0, h->hz.d(),
+                      m + b));
+  // Q_n = W R1^{-1} in place (b <= 8 columns: one workgroup column reads all
+  // of a row before writing it); the product writes the random replacement
+  // columns
+  HIPCHK(launch_nn(d, b, b, W, qdt, ldq, h->Rinv.d(), b, 0.0, nullptr, qdt, ldq, Qn, qdt, ldq,
+                   nullptr, h->stream, false, nullptr, nullptr, h->mask.i(),
+                   0x5eed0000ull + (uint64_t)m));
   STCHK(cholqr_pass(h, d, b, Qn, qdt, ldq, Qn, ldq, h->R1.d(), H + (m + b) + m * ldh, ldh,
                     nullptr, 0, 0, nullptr, flags));
   if (!repair) return EDA_OK;

@@ -526,6 +526,25 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict_
                 nullptr, 0, nullptr, nullptr);
   else
     gram_to_lds(G, ldg, a.part, a.chunks, b, A, ld, hs);
+  if (a.corr != nullptr) {
+    // G -= corr^T corr: the Gram matrix of W - Q h from that of W and the
+    // coefficients h = Q^T W (Q orthonormal); corr staged in one round trip
+    __shared__ double cs[2048];
+    const int64_t nc = a.mcorr * b;
+    for (int64_t e = tid; e < nc; e += blockDim.x) cs[e] = a.corr[e];
+    __syncthreads();
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int c = e / b, r = e - c * b;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int64_t k = 0;
+      for (; k + 4 <= a.mcorr; k += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(cs[(k + u) * b + r], cs[(k + u) * b + c], acc[u]);
+      for (; k < a.mcorr; ++k) acc[0] = fma(cs[k * b + r], cs[k * b + c], acc[0]);
+      A[r + c * ld] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
+    __syncthreads();
+  }
   if (tid < b) {
     const double g = A[tid + tid * ld];
     gd[tid] = g;
@@ -749,9 +768,12 @@ hipError_t launch_pchol_multi(int count, const PcholArgs* host, const PcholArgs*
 hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* hcol, int64_t m,
                         int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
                         double* R, int64_t ldr, int* mask, int* flag, hipStream_t s,
-                        const double* part, int64_t chunks) {
+                        const double* part, int64_t chunks, const double* corr, int64_t mcorr) {
+  if (corr != nullptr && (mcorr < 0 || mcorr * b > 2048)) return hipErrorInvalidValue;
   PcholArgs a{b, ldg, m, ldhc, ldz, ldr, G, hcol, tau, ratio, equil ? 1 : 0, Z, R, mask, flag,
               part, chunks};
+  a.corr = corr;
+  a.mcorr = mcorr;
   return launch_pchol_multi(1, &a, nullptr, s);
 }
 

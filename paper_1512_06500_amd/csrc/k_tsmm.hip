@@ -177,8 +177,10 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a, int64_t bx) {
   const int64_t i = e / a.nb, j = e - i * a.nb;
   // the accumulated output is read before the partials, so that its memory
   // round trip overlaps theirs
-  const double cprev =
-      (wid == 0 && e < mn && a.C != nullptr && a.beta != 0.0) ? a.C[i + j * a.ldc] : 0.0;
+  const bool toc2 = a.mc >= 0 && i >= a.mc;
+  const double cprev = (wid == 0 && e < mn && a.C != nullptr && !toc2 && a.beta != 0.0)
+                           ? a.C[i + j * a.ldc]
+                           : 0.0;
   // 16 loads in flight per lane; chunks w, w+4, ... added in order
   double s = 0.0;
   for (int64_t c0 = wid; c0 < chunks; c0 += 64) {
@@ -198,7 +200,10 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a, int64_t bx) {
     s += red[0][lane];
     s += red[1][lane];
     s += red[2][lane];
-    if (a.C != nullptr) a.C[i + j * a.ldc] = a.beta * cprev + a.alpha * s;
+    if (toc2)
+      a.C2[(i - a.mc) + j * a.ldc2] = s;
+    else if (a.C != nullptr)
+      a.C[i + j * a.ldc] = a.beta * cprev + a.alpha * s;
     if (a.Z != nullptr) a.Z[i * a.ldz + j] = a.zalpha * s;
   }
   __syncthreads();  // red may be reused by a caller that loops over work items
@@ -829,9 +834,13 @@ hipError_t launch_reduce_multi(int count, const ReduceArgs* host, const ReduceAr
 hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const double* part,
                                   double alpha, double beta, double* C_col, int64_t ldc,
                                   double zalpha, double* Z_row, int64_t ldz, const int* gate,
-                                  hipStream_t s) {
+                                  hipStream_t s, int64_t mc, double* C2, int64_t ldc2) {
   if (m * nb <= 0) return hipSuccess;
+  if (mc >= 0 && C2 == nullptr) return hipErrorInvalidValue;
   ReduceArgs a{chunks, m, nb, ldc, ldz, part, alpha, beta, zalpha, C_col, Z_row, gate};
+  a.mc = mc;
+  a.C2 = C2;
+  a.ldc2 = ldc2;
   return launch_reduce_multi(1, &a, nullptr, s);
 }
 
