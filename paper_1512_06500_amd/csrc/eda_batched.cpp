@@ -450,34 +450,51 @@ eda_status lanczos_step(Engine& E, const std::vector<int>& ps, hipEvent_t e_op0,
   const DT qdt = E.qdt;
   const size_t qs = E.qs;
   STCHK(push_op(h, [h, e_op0]() { return hipEventRecord(e_op0, h->stream); }));
+  // W goes straight into the slot of the next block, Q[:, m+b:m+2b]
   STCHK(m_expop(E, ps, qdt, qdt, [&](BP& p) {
-    return OpSite{false, 0, p.N, p.sub->CM.d(), p.N, p.sub->alphaB, b, p.Qc(p.m, qs), p.ldq, p.W,
-                  p.ldq};
+    return OpSite{false, 0, p.N, p.sub->CM.d(), p.N, p.sub->alphaB, b, p.Qc(p.m, qs), p.ldq,
+                  p.Qc(p.m + b, qs), p.ldq};
   }));
   STCHK(push_op(h, [h, e_op1]() { return hipEventRecord(e_op1, h->stream); }));
-  for (int pass = 0; pass < 2; ++pass)
-    STCHK(m_cgs(E, ps, qdt, [&](BP& p) {
-      return CGSSite{p.Q[p.cur], p.ldq, p.m + b, p.W, p.ldq, b, p.H[p.cur] + p.m * p.ldh, p.ldh,
-                     pass == 0 ? 0.0 : 1.0, nullptr};
-    }));
-  // rank-revealing first orthonormalisation (deflated directions replaced)
-  STCHK(m_tn(E, ps, qdt, qdt, [&](BP& p) {
-    return TnArgs{p.d, b, b, p.ldq, p.ldq, 0, p.W, p.W, p.part, nullptr};
+  STCHK(m_cgs(E, ps, qdt, [&](BP& p) {
+    return CGSSite{p.Q[p.cur], p.ldq, p.m + b, p.Qc(p.m + b, qs), p.ldq, b,
+                   p.H[p.cur] + p.m * p.ldh, p.ldh, 0.0, nullptr};
   }));
+  // second pass and the Gram matrix of its result from one product:
+  // [Q W]^T W = [h2; W^T W]; the Cholesky kernel forms W^T W - h2^T h2
   {
-    int64_t dmax = 0;
-    for (int i : ps) dmax = std::max(dmax, E.P[i].d);
+    int64_t dmax = 0, mmax = 0;
+    for (int i : ps) {
+      dmax = std::max(dmax, E.P[i].d);
+      mmax = std::max(mmax, E.P[i].m + 2 * b);
+    }
+    STCHK(m_tn(E, ps, qdt, qdt, [&](BP& p) {
+      return TnArgs{p.d, p.m + 2 * b, b, p.ldq, p.ldq, 0, p.Q[p.cur], p.Qc(p.m + b, qs), p.part,
+                    nullptr};
+    }));
     STCHK(m_reduce(E, ps, [&](BP& p) {
-      return ReduceArgs{tn_chunks_for(p.d, dmax, b), b, b, b, 0, p.part, 1.0, 0.0, 0.0, p.Gs,
-                        nullptr, nullptr};
+      ReduceArgs r{tn_chunks_for(p.d, dmax, mmax), p.m + 2 * b, b, p.ldh, b, p.part, 1.0, 1.0,
+                   -1.0, p.H[p.cur] + p.m * p.ldh, p.hz, nullptr};
+      r.mc = p.m + b;
+      r.C2 = p.Gs;
+      r.ldc2 = b;
+      return r;
+    }));
+    STCHK(m_nn(E, ps, qdt, qdt, qdt, [&](BP& p) {
+      return NnArgs{p.d, p.m + b, b, p.ldq, b, p.ldq, p.ldq, p.Q[p.cur], p.hz, 1.0,
+                    p.Qc(p.m + b, qs), p.Qc(p.m + b, qs), 0, nullptr};
     }));
   }
+  // rank-revealing first orthonormalisation (deflated directions replaced)
   STCHK(m_pchol(E, ps, [&](BP& p) {
-    return PcholArgs{b, b, p.m + b, p.ldh, b, b, p.Gs, p.H[p.cur] + p.m * p.ldh, 1e-13, 1e-4, 0,
-                     p.Rinv, p.R1, p.mask, p.flags};
+    PcholArgs a{b, b, p.m + b, p.ldh, b, b, p.Gs, p.H[p.cur] + p.m * p.ldh, 1e-13, 1e-4, 0,
+                p.Rinv, p.R1, p.mask, p.flags};
+    a.corr = p.hz;
+    a.mcorr = p.m + b;
+    return a;
   }));
   STCHK(m_nn(E, ps, qdt, qdt, qdt, [&](BP& p) {
-    return NnArgs{p.d, b, b, p.ldq, b, p.ldq, p.ldq, p.W, p.Rinv, 0.0, nullptr,
+    return NnArgs{p.d, b, b, p.ldq, b, p.ldq, p.ldq, p.Qc(p.m + b, qs), p.Rinv, 0.0, nullptr,
                   p.Qc(p.m + b, qs), 0, nullptr};
   }));
   STCHK(m_mrandn(E, ps, qdt, [&](BP& p) {
