@@ -303,7 +303,7 @@ eda_status eda_syev(eda_handle h, int64_t n, const double* A, int64_t lda,
  * (d x n_train, ldtr >= d), test (d x n_test, ldte >= d): float64, device,
  * column-major; train_labels: device int32 [n_train].  Outputs (device):
  * pred[n_test] = train_labels[nn_index[j]], nn_index[n_test], nn_dist[n_test]
- * = min_i d_ij.  1 <= t <= min(d, 1024), n_train, n_test >= 1.  Independent
+ * = min_i d_ij.  1 <= t <= min(d, 1024), n_train >= 1, 1 <= n_test < 2^31.  Independent
  * of the preparation; uses the handle's stream and workspaces; stream-ordered
  * (no synchronisation).  A testing sample whose distances are all NaN gets
  * index and label -1 and distance NaN. */

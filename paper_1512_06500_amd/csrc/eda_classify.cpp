@@ -40,6 +40,7 @@ extern "C" eda_status eda_nn_classify(eda_handle h, int64_t d, int64_t t, const 
     return fail(h, EDA_ERR_ARG, "need 1 <= t <= min(d, 1024), got d=%lld t=%lld", (long long)d,
                 (long long)t);
   if (n_train < 1 || n_test < 1) return fail(h, EDA_ERR_ARG, "need n_train >= 1 and n_test >= 1");
+  if (n_test > INT32_MAX) return fail(h, EDA_ERR_ARG, "n_test exceeds 2^31 - 1");
   if (ldx < d || ldtr < d || ldte < d) return fail(h, EDA_ERR_ARG, "leading dimensions must be >= d");
   if (X == nullptr || train == nullptr || train_labels == nullptr || test == nullptr ||
       pred == nullptr || nn_index == nullptr || nn_dist == nullptr)

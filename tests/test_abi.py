@@ -131,6 +131,7 @@ def test_autotune_rejects_bad_arguments(lib, handle, d, N, b, storage):
     (10, 2, 4, 4, 9, 10, 10),     # ldx < d
     (10, 2, 4, 4, 10, 9, 10),     # ldtr < d
     (10, 2, 4, 4, 10, 10, 9),     # ldte < d
+    (10, 2, 4, 2 ** 31, 10, 10, 10),  # more testing samples than workgroups
 ])
 def test_nn_classify_rejects_bad_arguments(lib, handle, d, t, ntr, nte, ldx, ldtr, ldte):
     st = lib.eda_nn_classify(handle, d, t, FAKE, ldx, ntr, FAKE, ldtr, FAKE, nte, FAKE, ldte,
