@@ -203,6 +203,7 @@ eda_status solve_aform(eda_handle h, int32_t t, double tol, const eda_solve_opts
   if (h->normW > 12.0 * std::log(10.0))
     return fail(h, EDA_ERR_ARG,
                 "||S_W|| = %.3g: exp(S_W) is too ill-conditioned for the Arnoldi form", h->normW);
+  STCHK(ensure_arnoldi_core(h));
   AForm F;
   F.h = h;
   F.d = h->d;

@@ -248,16 +248,13 @@ eda_status build_composite_cores(eda_handle h) {
   const int64_t n = h->n, k = h->k, N = h->N;
   STCHK(ensure(h, h->GBs, (size_t)k * k * 8));
   STCHK(ensure(h, h->CM, (size_t)N * N * 8));
-  STCHK(ensure(h, h->CA, (size_t)N * N * 8));
   STCHK(ensure(h, h->T1, (size_t)n * k * 8));
   STCHK(ensure(h, h->T2, (size_t)n * k * 8));
-  STCHK(ensure(h, h->T3, (size_t)n * k * 8));
-  STCHK(ensure(h, h->T4, (size_t)n * k * 8));
   STCHK(build_core(h, EDA_B, 1.0, h->shiftB, h->GBs.d()));
   const double* K = h->G.d() + n * N;  // H_W^T H_B, n x k, ld N
   hipStream_t s = h->stream;
   double* CM = h->CM.d();
-  double* CA = h->CA.d();
+  h->ca_ready = false;
   // Lanczos core: [[a Gm + Gh K GB K^T Gh, Gh K GB], [GB K^T Gh, GB]]
   HIPCHK(launch_gemm(false, false, n, k, n, 1.0, h->Gh.d(), n, nullptr, K, N, 0.0, h->T1.d(), n, s));
   HIPCHK(launch_gemm(false, false, n, k, k, 1.0, h->T1.d(), n, nullptr, h->GBs.d(), k, 0.0,
@@ -267,7 +264,23 @@ eda_status build_composite_cores(eda_handle h) {
   HIPCHK(launch_copy_block(n, k, 1.0, h->T2.d(), n, false, CM + n * N, N, s));
   HIPCHK(launch_copy_block(k, n, 1.0, h->T2.d(), n, true, CM + n, N, s));
   HIPCHK(launch_copy_block(k, k, 1.0, h->GBs.d(), k, false, CM + n + n * N, N, s));
-  // Arnoldi core: [[a Gm, Gm K GB], [0, GB]]
+  return EDA_OK;
+}
+
+}  // namespace
+
+namespace eda {
+
+// Arnoldi core: [[a Gm, Gm K GB], [0, GB]]
+eda_status ensure_arnoldi_core(eda_handle h) {
+  if (h->ca_ready) return EDA_OK;
+  const int64_t n = h->n, k = h->k, N = h->N;
+  STCHK(ensure(h, h->CA, (size_t)N * N * 8));
+  STCHK(ensure(h, h->T3, (size_t)n * k * 8));
+  STCHK(ensure(h, h->T4, (size_t)n * k * 8));
+  const double* K = h->G.d() + n * N;  // H_W^T H_B, n x k, ld N
+  hipStream_t s = h->stream;
+  double* CA = h->CA.d();
   HIPCHK(launch_gemm(false, false, n, k, n, 1.0, h->Gm.d(), n, nullptr, K, N, 0.0, h->T3.d(), n, s));
   HIPCHK(launch_gemm(false, false, n, k, k, 1.0, h->T3.d(), n, nullptr, h->GBs.d(), k, 0.0,
                      h->T4.d(), n, s));
@@ -275,8 +288,13 @@ eda_status build_composite_cores(eda_handle h) {
   HIPCHK(launch_copy_block(n, k, 1.0, h->T4.d(), n, false, CA + n * N, N, s));
   HIPCHK(launch_copy_block(k, n, 0.0, h->T4.d(), n, true, CA + n, N, s));
   HIPCHK(launch_copy_block(k, k, 1.0, h->GBs.d(), k, false, CA + n + n * N, N, s));
+  h->ca_ready = true;
   return EDA_OK;
 }
+
+}  // namespace eda
+
+namespace {
 
 eda_status validate_block(eda_handle h, int64_t b, const void* V, int64_t ldv, const void* Out,
                           int64_t ldo, eda_dtype vdtype) {
@@ -649,6 +667,7 @@ eda_status eda_opmv(eda_handle h, eda_form form, int64_t b, const void* V, int64
   STCHK(need_device(h));
   STCHK(check_dev_ptr(h, V, "V"));
   STCHK(check_dev_ptr(h, Out, "Out"));
+  if (form == EDA_FORM_ARNOLDI_A) STCHK(ensure_arnoldi_core(h));
   const double* C = form == EDA_FORM_LANCZOS_M ? h->CM.d() : h->CA.d();
   STCHK(expop(h, false, 0, h->N, C, h->N, h->alphaB, b, V, dt_of(vdtype), ldv, Out, dt_of(vdtype), ldo));
   if (log_scale != nullptr) *log_scale = h->shiftB;

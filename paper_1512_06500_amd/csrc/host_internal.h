@@ -64,6 +64,7 @@ struct eda_handle_s {
   eda::Buf nnp[2];      // projections of the classifier (training, testing)
   double normW = 0.0;   // ||H_W^T H_W||_1
   bool w_eig = false;   // eigenpairs of H_W^T H_W available
+  bool ca_ready = false;  // Arnoldi core C_A built for the current preparation
   std::vector<double> hwW, hwB;
   double t_prepare_ms = 0.0;
   // pinned host scalars of the preparation (non-finite flag, ||G_WW||_1,
@@ -145,6 +146,9 @@ eda_status back_transform(eda_handle h, int64_t t, const double* Y, int64_t ldy,
 // Columns of X (d x t) orthonormalised in column order by Cholesky QR run
 // twice (scratch with leading dimension ldw in h->Yb) and sign-fixed.
 eda_status orthonormalise(eda_handle h, int64_t t, double* X, int64_t ldx, int64_t ldw);
+// The Arnoldi core C_A of the current preparation, built on first use (the
+// Lanczos form does not need it).
+eda_status ensure_arnoldi_core(eda_handle h);
 // Core of exp(c S_W) without shift (exp(c S_W) = I + H_W C H_W^T), n x n.
 eda_status build_w_core(eda_handle h, double c, double* out);
 // Measures the candidate launch shapes of the product passes for a d x N
