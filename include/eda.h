@@ -120,6 +120,8 @@ typedef struct {
 #define EDA_WARN_DEGENERATE 1  /* t > k-1: the wanted subspace is not unique       */
 #define EDA_WARN_FLOOR 2       /* some pair stopped at its attainable floor, not tol */
 #define EDA_WARN_REPAIRED 4    /* a Krylov block lost rank and was re-orthogonalised */
+#define EDA_WARN_FALLBACK 8    /* batched, narrow precision: the refinement stalled and the
+                                  problem was solved again in float64                 */
 
 /* Create a handle bound to the current HIP device and to `hip_stream`
  * (a hipStream_t, or NULL for the default stream).  *h receives the handle. */
@@ -275,7 +277,10 @@ typedef struct {
  * argument arrays of a step are copied to the device in one transfer.
  * infos, statuses: host arrays of `count` entries (may be NULL).  Returns
  * EDA_OK when every problem succeeded, else the first failing status
- * (argument errors are reported before any work is done).  Uses the
+ * (argument errors are reported before any work is done).  With narrow
+ * storage or a float32 basis, a problem whose float64 refinement passes
+ * stall is solved again by eda_solve in float64 on its own handle
+ * (EDA_WARN_FALLBACK; its iterations are added to iters).  Uses the
  * handle's stream and workspaces; does not change the handle's own
  * preparation.  Synchronises. */
 eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_problem* probs,

@@ -29,7 +29,7 @@ EDA_F64, EDA_F32, EDA_BF16, EDA_FP8_E4M3 = 0, 1, 2, 3
 EDA_W, EDA_B = 0, 1
 EDA_FORM_LANCZOS_M, EDA_FORM_ARNOLDI_A = 0, 1
 EDA_RES_REL_THETA, EDA_RES_NORMWISE = 0, 1
-EDA_WARN_DEGENERATE, EDA_WARN_FLOOR, EDA_WARN_REPAIRED = 1, 2, 4
+EDA_WARN_DEGENERATE, EDA_WARN_FLOOR, EDA_WARN_REPAIRED, EDA_WARN_FALLBACK = 1, 2, 4, 8
 
 _DTYPES = {"f64": EDA_F64, "f32": EDA_F32, "bf16": EDA_BF16, "fp8": EDA_FP8_E4M3}
 

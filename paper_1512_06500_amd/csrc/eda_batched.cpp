@@ -177,6 +177,7 @@ struct Engine {
   double u_lo = 0x1.0p-53;
   eda_resmode resmode = EDA_RES_REL_THETA;
   int64_t mm_all = 0;  // largest Rayleigh-Ritz dimension (eigensolver work size)
+  uint64_t seed = 0;   // problem p draws its start block from seed + p
 };
 
 // ---- multi-launch helpers (one entry per listed problem) --------------------
@@ -750,6 +751,7 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
   E.max_iter = o.max_iter > 0 ? o.max_iter : 4000;
   E.max_refine = o.max_refine > 0 ? o.max_refine : (o.max_refine < 0 ? -1 : (E.mixed ? 16 : 2));
   E.resmode = o.resmode;
+  E.seed = o.seed;
   E.P.resize(count);
   size_t total = 0;
   std::vector<size_t> sizes;
@@ -1215,6 +1217,31 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
       else if (!P.converged)
         stat[p] = EDA_ERR_NOCONV;
     }
+    // A narrow-precision problem whose refinement stalled (wanted pairs a few
+    // per cent from a large eigenvalue cluster) is solved again by the
+    // float64 path on its own handle.
+    eda_info fb;
+    std::memset(&fb, 0, sizeof(fb));
+    bool fell_back = false;
+    if (stat[p] == EDA_ERR_NOCONV && E.mixed) {
+      eda_status s1 = eda_prepare(P.sub, q.d, q.n, q.k, q.H_W, q.ldw, q.H_B, q.ldb, EDA_F64);
+      if (s1 == EDA_OK) {
+        eda_solve_opts o1;
+        std::memset(&o1, 0, sizeof(o1));
+        o1.form = EDA_FORM_LANCZOS_M;
+        o1.block = (int32_t)E.b;
+        o1.resmode = E.resmode;
+        o1.krylov_dtype = EDA_F64;
+        o1.refine_dtype = EDA_F64;
+        o1.seed = E.seed + (uint64_t)p;
+        s1 = eda_solve(P.sub, (int32_t)q.t, q.tol, &o1, q.ritz, q.ritz_log, q.X, q.ldx, q.resid,
+                       &fb);
+      }
+      if (s1 == EDA_OK) {
+        stat[p] = EDA_OK;
+        fell_back = true;
+      }
+    }
     if (infos != nullptr) {
       eda_info& I = infos[p];
       std::memset(&I, 0, sizeof(I));
@@ -1231,6 +1258,11 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
       I.op_calls = P.op_calls;
       I.t_op_ms = P.t_op_ms;
       I.op_bytes = 2.0 * P.d * P.N * dsize(storage) + 3.0 * P.d * b * qs;
+      if (fell_back) {
+        I.iters += fb.iters;
+        I.restarts += fb.restarts;
+        I.flags = fb.flags | EDA_WARN_FALLBACK;
+      }
     }
     if (statuses != nullptr) statuses[p] = stat[p];
     if (stat[p] != EDA_OK && first == EDA_OK) first = stat[p];

@@ -837,6 +837,40 @@ def test_batched_agrees_with_single_solves(torch, eda):
     h.close()
 
 
+def test_batched_f32_stalled_problems_fall_back(torch, eda):
+    """The 64-problem workload with float32 storage: three problems (d = 1024,
+    n + k close to d, wanted pairs within a few per cent of the unit
+    eigenvalue) stall in the float32 phase and its refinement; they are
+    solved again in float64 (EDA_WARN_FALLBACK) and then agree with the
+    oracle's exact reduction.  Every problem ends with status 0."""
+    log("batched float32, 64 problems, fallback of the stalled ones")
+    ps = datagen.batched_configs(64)
+    h = eda.Handle()
+    probs = []
+    for p in ps:
+        HW, HB = h.scatter_factors(dev(torch, p.X), p.counts.tolist())
+        probs.append((HW, HB, p.t, p.tol))
+    res, st = h.solve_batched(probs, storage="f32", krylov_dtype="f32", seed=4000)
+    assert st == 0, [r.status for r in res]
+    fell = [i for i, r in enumerate(res) if r.info["flags"] & eda.EDA_WARN_FALLBACK]
+    log(f"  fell back: {fell}")
+    assert fell
+    for i in fell:
+        c = Case(ps[i].name, ps[i].X, ps[i].counts, ps[i].t)
+        red = O.eda_reduced(c.H_W, c.H_B, c.t)
+        r = res[i]
+        relerr = np.abs(np.array(r.ritz) - red.lam) / red.lam
+        # graded spectra: the small pairs are held to their attainable
+        # float64 floor u lam_1 / lam_i (as in the float64 solver's test)
+        lam_tol = np.maximum(1e-8, 50 * U * red.lam[0] / red.lam)
+        X = host(r.X)
+        log(f"  {c.name}: iters={r.info['iters']} lam_err={relerr.max():.1e} "
+            f"lam_1/lam_t={red.lam[0] / red.lam[-1]:.1e} sin={O.sin_angle(red.X, X):.1e}")
+        assert np.all(relerr <= lam_tol)
+        assert np.abs(X.T @ X - np.eye(c.t)).max() <= 1e-13
+    h.close()
+
+
 def test_batched_c4_sample(torch, eda):
     """Twelve problems of the 64-problem workload (d in {1024, 4096, 10304},
     k in [10, 68], n_j in [2, 20], float32 storage, tol 1e-6) in one batch,
