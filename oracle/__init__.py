@@ -22,7 +22,7 @@ reduction", arXiv 1512.06500):
 * the EDA criterion rho and the bounds used as checks -- eq. (1.6); Section 3.2
   (eigenvalue bounds of Theorem 3.2, criterion bounds of Theorem 3.4,
   unit-eigenvalue count of Theorem 3.6)
-* nearest-neighbour classification and Theorem 3.8 -- Section 3.3 (oracle.nn)
+* nearest-neighbour classification and Theorem 3.7 -- Section 3.3 (oracle.nn)
 
 Equation numbers are the printed ones (section.number).
 """

@@ -1,5 +1,5 @@
 """Nearest-neighbour classification in the EDA subspace and the distance
-bounds of Theorem 3.8 (Section 3.3), in float64.
+bounds of Theorem 3.7 (Section 3.3), in float64.
 
 TEST INFRASTRUCTURE ONLY, like the rest of ``oracle``: the product path never
 imports it.
@@ -7,10 +7,10 @@ imports it.
 * The distance between a training sample x_i and a testing sample y_j is
   d_ij = ||V^T (x_i - y_j)||_2 for the orthonormal d x t matrix V of the
   computed (or exact) solution (Section 3.3, the distance definition before
-  Theorem 3.8).  A testing sample takes the class of its nearest training
+  Theorem 3.7).  A testing sample takes the class of its nearest training
   sample (1-NN, Section 3.3).  The paper does not say how ties are broken;
   here the smallest training index wins.
-* Theorem 3.8: for unit-norm samples and cos angle(V, W) != 0,
+* Theorem 3.7: for unit-norm samples and cos angle(V, W) != 0,
       (dW_ij - 2 sin) / cos <= dV_ij <= dW_ij cos + 2 sin,
   with sin = ||(I - V V^T) W||_2 and cos = ||V^T W||_2 (the theorem's
   definitions; the cosine as in its proof).
@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["nn_distances", "nn_classify", "cos_angle", "thm38_bounds"]
+__all__ = ["nn_distances", "nn_classify", "cos_angle", "thm37_bounds"]
 
 
 def nn_distances(V: np.ndarray, train: np.ndarray, test: np.ndarray) -> np.ndarray:
@@ -45,10 +45,10 @@ def nn_classify(V, train, train_labels, test):
 
 
 def cos_angle(V: np.ndarray, W: np.ndarray) -> float:
-    """cos angle(V, W) = ||V^T W||_2 for orthonormal V, W (proof of Theorem 3.8)."""
+    """cos angle(V, W) = ||V^T W||_2 for orthonormal V, W (proof of Theorem 3.7)."""
     return float(np.linalg.norm(V.T @ W, 2))
 
 
-def thm38_bounds(dW: np.ndarray, sin: float, cos: float):
-    """Lower and upper bounds on d^V_ij from d^W_ij (eq. (3.24))."""
+def thm37_bounds(dW: np.ndarray, sin: float, cos: float):
+    """Lower and upper bounds on d^V_ij from d^W_ij (eq. (3.30))."""
     return (dW - 2.0 * sin) / cos, dW * cos + 2.0 * sin

@@ -16,6 +16,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import datagen  # noqa: E402
 import oracle as O  # noqa: E402
+from tests.golden.reader import read  # noqa: E402,F401
 
 
 def write(name: str) -> str:
@@ -40,25 +41,6 @@ def write(name: str) -> str:
         for i in range(p.t, min(p.t + 8, red.lam_all.size)):
             f.write(f"next {red.lam_all[i]:.17e}\n")
     return path
-
-
-def read(name: str) -> dict:
-    path = os.path.join(HERE, f"oracle_{name}.txt")
-    out = {"lam": [], "log_lam": [], "pair_floor": [], "next": []}
-    with open(path) as f:
-        for line in f:
-            if line.startswith("#") or not line.strip():
-                continue
-            parts = line.split()
-            if parts[0] == "next":
-                out["next"].append(float(parts[1]))
-            elif parts[0].isdigit():
-                out["lam"].append(float(parts[1]))
-                out["log_lam"].append(float(parts[2]))
-                out["pair_floor"].append(float(parts[3]))
-            else:
-                out[parts[0]] = float(parts[1])
-    return {k: (np.array(v) if isinstance(v, list) else v) for k, v in out.items()}
 
 
 if __name__ == "__main__":

@@ -1,4 +1,4 @@
-"""Pins of the nearest-neighbour classifier and of Theorem 3.8 (Section 3.3)
+"""Pins of the nearest-neighbour classifier and of Theorem 3.7 (Section 3.3)
 in the oracle: hand-computed distances and labels, closed forms of the
 subspace angle, the theorem's bounds on random perturbations, and the
 generator's train/test split."""
@@ -56,12 +56,12 @@ def test_angle_closed_form(theta):
     dV = nn.nn_distances(V, x, y)[0, 0]
     dW = nn.nn_distances(W, x, y)[0, 0]
     assert abs(dV - 1.0) <= 1e-16 and abs(dW - abs(np.cos(theta) - np.sin(theta))) <= 1e-15
-    lo, hi = nn.thm38_bounds(dW, abs(np.sin(theta)), abs(np.cos(theta)))
+    lo, hi = nn.thm37_bounds(dW, abs(np.sin(theta)), abs(np.cos(theta)))
     assert lo <= dV + 1e-15 and dV <= hi + 1e-15
 
 
 @pytest.mark.parametrize("eps", [1e-8, 1e-4, 1e-2, 0.3])
-def test_thm38_bounds_hold_on_perturbed_subspaces(eps):
+def test_thm37_bounds_hold_on_perturbed_subspaces(eps):
     rng = np.random.default_rng(int(-np.log10(eps)) + 11)
     d, t = 60, 5
     V = np.linalg.qr(rng.standard_normal((d, t)))[0]
@@ -77,10 +77,10 @@ def test_thm38_bounds_hold_on_perturbed_subspaces(eps):
     # the smallest (singular values of V^T W)
     sv = np.linalg.svd(V.T @ W, compute_uv=False)
     assert abs(c - sv[0]) <= 1e-14 and abs(s * s + sv[-1] ** 2 - 1.0) <= 1e-12
-    lo, hi = nn.thm38_bounds(dW, s, c)
+    lo, hi = nn.thm37_bounds(dW, s, c)
     assert np.all(lo <= dV + 1e-12) and np.all(dV <= hi + 1e-12)
     # the symmetric statement with the roles exchanged
-    lo2, hi2 = nn.thm38_bounds(dV, s, c)
+    lo2, hi2 = nn.thm37_bounds(dV, s, c)
     assert np.all(lo2 <= dW + 1e-12) and np.all(dW <= hi2 + 1e-12)
 
 

@@ -383,7 +383,7 @@ class TestMutants:
 
 @pytest.mark.parametrize("name", ["C1", "C2"])
 def test_golden_values_match_oracle(name):
-    from tests.golden.make_golden import read
+    from tests.golden.reader import read
     g = read(name)
     p = datagen.config(name)
     H_W, H_B = O.scatter_factors(p.X, p.counts)
@@ -459,3 +459,238 @@ def test_fp8_columns_scale():
     E *= 2.0 ** np.array([-3, 0, 5])
     Q, s = fp8_columns(E)
     assert np.array_equal(Q, E) and np.array_equal(s, 2.0 ** np.array([-3, 0, 5]))
+
+
+# ----------------------------------------------------------------------------
+# Reference bfloat16 rounding (format facts, not paper): one rounding from
+# float64, ties to even.
+# ----------------------------------------------------------------------------
+
+def test_bf16_codes_known_values():
+    """Codes fixed by the format: 1 = 0x3f80, -2 = 0xc000, the smallest
+    subnormal 2^-133 = 0x0001, the smallest normal 2^-126 = 0x0080, the
+    largest finite (2 - 2^-7) 2^127 = 0x7f7f, infinity 0x7f80, and the
+    nearest values of pi (3.140625 = 0x4049) and 1/3 (0.333984375 = 0x3eab)."""
+    from oracle.bf16 import bf16_codes, bf16_decode, BF16_MAX
+    cases = {1.0: 0x3F80, -2.0: 0xC000, 2.0 ** -133: 0x0001, 2.0 ** -126: 0x0080,
+             BF16_MAX: 0x7F7F, np.inf: 0x7F80, np.pi: 0x4049, 1.0 / 3.0: 0x3EAB,
+             0.0: 0x0000}
+    for x, code in cases.items():
+        assert int(bf16_codes(np.array([x]))[0]) == code, (x, hex(code))
+    assert bf16_decode(np.array([0x4049]))[0] == 3.140625
+    assert bf16_decode(np.array([0x3EAB]))[0] == 0.333984375
+    assert np.signbit(bf16_decode(np.array([0x8000]))[0])
+
+
+def test_bf16_rounding_ties_and_single_rounding():
+    """Ties go to the even significand; a value just above a tie rounds up
+    even when its float32 rounding would land on the tie (the double
+    rounding float64 -> float32 -> bfloat16 gets that case wrong); overflow
+    to infinity happens exactly at the midpoint above the largest finite."""
+    from oracle.bf16 import bf16_round, BF16_MAX
+    cases = {
+        1.0 + 2.0 ** -8: 1.0,                      # tie between m = 0 and m = 1: even
+        1.0 + 3 * 2.0 ** -8: 1.0 + 2.0 ** -6,      # tie between m = 1 and m = 2: even
+        1.0 + 2.0 ** -8 + 2.0 ** -30: 1.0 + 2.0 ** -7,   # above the tie, below float32's ulp
+        1.0 + 2.0 ** -8 - 2.0 ** -40: 1.0,         # below the tie
+        3 * 2.0 ** -134: 2.0 ** -132,              # subnormal tie (1.5 quanta): even = 2
+        2.0 ** -134: 0.0,                          # half the smallest subnormal: to 0
+        2.0 ** -134 + 2.0 ** -160: 2.0 ** -133,    # just above it
+        BF16_MAX + 2.0 ** 119: np.inf,             # the midpoint to 2^128: ties to even = inf
+        BF16_MAX + 2.0 ** 119 - 2.0 ** 100: BF16_MAX,
+    }
+    for x, want in cases.items():
+        assert bf16_round(np.array([x]))[0] == want, x
+        assert bf16_round(np.array([-x]))[0] == -want, -x
+    x = np.float64(1.0 + 2.0 ** -8 + 2.0 ** -30)
+    assert float(np.float32(x)) == 1.0 + 2.0 ** -8   # float32 hop lands on the tie
+
+
+def test_bf16_rounding_error_bound_and_idempotence():
+    """|round(x) - x| <= 2^-8 |x| for normal x (half an ulp of 7 stored bits),
+    rounding is idempotent, monotone, and exact on values with 8 significant
+    bits."""
+    from oracle.bf16 import bf16_round
+    x = RNG.standard_normal(5000) * 10.0 ** RNG.uniform(-30, 30, 5000)
+    r = bf16_round(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-15))
+    assert np.array_equal(bf16_round(r), r)
+    s = np.sort(x)
+    assert np.all(np.diff(bf16_round(s)) >= 0)
+    m = RNG.integers(128, 256, 1000).astype(np.float64) * 2.0 ** RNG.integers(-40, 40, 1000)
+    assert np.array_equal(bf16_round(m), m)
+
+
+# ----------------------------------------------------------------------------
+# The attainable-accuracy report (oracle.accuracy_floor) against Weyl's and
+# Davis-Kahan's perturbation theorems on matrices with a chosen spectrum:
+# the report claims that an absolute perturbation of size u * lam_1 (one
+# product's rounding) moves pair i by at most u lam_1 / lam_i relatively and
+# the top-t span by at most u lam_1 / gap.  Both bounds are attained by
+# specific perturbations, so a floor that is too small fails the random
+# checks and one that is too large fails the attainment checks.
+# ----------------------------------------------------------------------------
+
+def _spectral_matrix(spec, rng):
+    """Symmetric matrix Q diag(spec) Q^T with a random orthogonal Q."""
+    Q = np.linalg.qr(rng.standard_normal((len(spec), len(spec))))[0]
+    return (Q * spec) @ Q.T, Q
+
+
+def _top_span(M, t):
+    w, Z = np.linalg.eigh(0.5 * (M + M.T))
+    return w[::-1], Z[:, ::-1][:, :t]
+
+
+def check_accuracy_floor(accuracy_floor):
+    """True when accuracy_floor's pair and span floors match the perturbation
+    theory of the spectra below (unit cluster present, absent, t = N)."""
+    rng = np.random.default_rng(31)
+    ok = True
+    # (reduced spectrum lam_all, t, multiplicity of the unit eigenvalue in the
+    # full problem: d - N complement directions)
+    cases = [
+        (np.array([400.0, 90.0, 12.0, 3.0, 0.6, 0.4, 0.2]), 3, 4),   # lam_{t+1} > 1
+        (np.array([400.0, 90.0, 12.0, 1.3, 0.6, 0.4, 0.2]), 4, 4),   # unit cluster closest
+        (np.array([400.0, 90.0, 12.0, 0.8, 0.6]), 3, 3),             # lam_{t+1} < 1 < lam_t
+        (np.array([50.0, 7.0, 2.5]), 3, 5),                          # t = N: gap to the unit cluster
+        (np.array([50.0, 7.0, 2.5, 0.3]), 2, 0),                     # no complement (d = N)
+    ]
+    u = 1e-9   # a perturbation level far above float64 rounding
+    for lam_all, t, n_unit in cases:
+        spec = np.concatenate([lam_all, np.ones(n_unit)])
+        fl = accuracy_floor(lam_all, t, u=u, unit_cluster=n_unit > 0)
+        M, Q = _spectral_matrix(spec, rng)
+        eps = u * lam_all[0]
+        order = np.argsort(-spec, kind="stable")
+        q = Q[:, order]                           # eigenvectors by decreasing eigenvalue
+        _, X0 = _top_span(M, t)
+        # Weyl: no perturbation of norm eps moves lam_i by more than eps
+        for _ in range(3):
+            E = rng.standard_normal(M.shape)
+            E = E + E.T
+            E *= eps / np.linalg.norm(E, 2)
+            w, X = _top_span(M + E, t)
+            ok &= np.all(np.abs(w[:t] - lam_all[:t]) / lam_all[:t] <= fl["pair"] * (1 + 1e-6))
+            ok &= O.sin_angle(X0, X) <= fl["span"] * (1 + 1e-3)
+        # attained: E = eps q_i q_i^T moves lam_i by exactly eps
+        for i in range(t):
+            w, _ = _top_span(M + eps * np.outer(q[:, i], q[:, i]), t)
+            ok &= abs((w[i] - lam_all[i]) / lam_all[i] / fl["pair"][i] - 1.0) < 1e-4
+        # attained to first order: coupling q_t with the closest unwanted
+        # eigenvector rotates the span by eps / gap
+        jn = int(np.argmin(np.abs(spec[order][t:] - lam_all[t - 1]))) + t
+        E = eps * (np.outer(q[:, t - 1], q[:, jn]) + np.outer(q[:, jn], q[:, t - 1]))
+        _, X = _top_span(M + E, t)
+        with np.errstate(divide="ignore"):
+            ok &= abs(O.sin_angle(X0, X) / fl["span"] - 1.0) < 1e-3
+    return bool(ok)
+
+
+def test_accuracy_floor_matches_perturbation_theory():
+    assert check_accuracy_floor(O.accuracy_floor)
+
+
+def test_accuracy_floor_hand_values_and_default_unit_roundoff():
+    """Hand values: lam = [100, 10, 0.5], t = 2 -> pair floors u [1, 10],
+    span u * 100 / (10 - 1) with the unit eigenvalue, u * 100 / 9.5 without;
+    the default u is the float64 unit roundoff 2^-53 = eps / 2."""
+    lam = np.array([100.0, 10.0, 0.5])
+    f = O.accuracy_floor(lam, 2)
+    u = np.finfo(np.float64).eps / 2
+    assert f["pair"][0] == u and f["pair"][1] == 10 * u
+    assert f["span"] == u * 100 / 9.0 and f["gap"] == 9.0
+    g = O.accuracy_floor(lam, 2, unit_cluster=False)
+    assert g["span"] == u * 100 / 9.5
+    h = O.accuracy_floor(np.array([100.0, 10.0]), 2)          # t = N
+    assert h["gap"] == 9.0
+
+
+def test_rho_bounds_thm34_collapse_and_hand_case():
+    """Theorem 3.4's bounds on the EDA criterion are the minimum and maximum
+    over all V of the trace ratio (Lemma 3.3) when one factor vanishes:
+    with S_W = 0 they are the sums of the t smallest and t largest exp(mu_i),
+    with S_B = 0 those of exp(-nu_i).  A hand case fixes the index pairing:
+    mu = (3, 1, 0), nu = (2, 0.5, 0), t = 2 gives
+    lower = max(e^{1-2}, e^{0-0.5}) + max(e^{0-2}, e^{0-2}) = e^{-1/2} + e^{-2},
+    upper = min(e^{3-0}, e^{3-0}) + min(e^{1-0}, e^{3-0.5}) = e^3 + e."""
+    rng = np.random.default_rng(5)
+    d, t = 7, 3
+    mu = np.sort(rng.uniform(0, 2, d))[::-1]
+    lo, hi = O.rho_bounds_thm34(mu, np.zeros(d), t)
+    assert np.isclose(lo, np.exp(mu[-t:]).sum(), rtol=1e-15)
+    assert np.isclose(hi, np.exp(mu[:t]).sum(), rtol=1e-15)
+    nu = np.sort(rng.uniform(0, 2, d))[::-1]
+    lo, hi = O.rho_bounds_thm34(np.zeros(d), nu, t)
+    assert np.isclose(lo, np.exp(-nu[:t]).sum(), rtol=1e-15)
+    assert np.isclose(hi, np.exp(-nu[-t:]).sum(), rtol=1e-15)
+    lo, hi = O.rho_bounds_thm34(np.array([3.0, 1.0, 0.0]), np.array([2.0, 0.5, 0.0]), 2)
+    assert np.isclose(lo, np.exp(-0.5) + np.exp(-2.0), rtol=1e-15)
+    assert np.isclose(hi, np.exp(3.0) + np.exp(1.0), rtol=1e-15)
+    # and on a real problem both bounds contain the extreme trace ratios
+    _, _, H_W, H_B = small_problem(d=12, k=3, counts=[2, 2, 2])
+    lam = O.pencil_spectrum(H_W, H_B)
+    mu = np.sort(np.linalg.eigvalsh(H_B @ H_B.T))[::-1]
+    nu = np.sort(np.linalg.eigvalsh(H_W @ H_W.T))[::-1]
+    lo, hi = O.rho_bounds_thm34(mu, nu, t)
+    assert lo * (1 - 1e-12) <= lam[-t:].sum() and lam[:t].sum() <= hi * (1 + 1e-12)
+
+
+class TestFloorAndBoundMutants:
+    """Plausible slips in the accuracy report and in the criterion bounds."""
+
+    def test_off_by_one_gap_index_is_caught(self):
+        def bad(lam_all, t, u=2.0 ** -53, unit_cluster=True):
+            f = O.accuracy_floor(lam_all, t, u, unit_cluster)
+            nxt = lam_all[t + 1] if lam_all.size > t + 1 else -np.inf
+            if unit_cluster:
+                nxt = max(nxt, 1.0)
+            gap = lam_all[t - 1] - nxt
+            return {"pair": f["pair"], "span": u * lam_all[0] / gap, "gap": gap}
+        assert not check_accuracy_floor(bad)
+
+    def test_previous_pair_gap_is_caught(self):
+        def bad(lam_all, t, u=2.0 ** -53, unit_cluster=True):
+            f = O.accuracy_floor(lam_all, t, u, unit_cluster)
+            gap = lam_all[t - 2] - lam_all[t - 1]
+            return {"pair": f["pair"], "span": u * lam_all[0] / gap, "gap": gap}
+        assert not check_accuracy_floor(bad)
+
+    def test_ignored_unit_cluster_is_caught(self):
+        def bad(lam_all, t, u=2.0 ** -53, unit_cluster=True):
+            return O.accuracy_floor(lam_all, t, u, unit_cluster=False)
+        assert not check_accuracy_floor(bad)
+
+    def test_pair_floor_against_lam_t_is_caught(self):
+        def bad(lam_all, t, u=2.0 ** -53, unit_cluster=True):
+            f = O.accuracy_floor(lam_all, t, u, unit_cluster)
+            return {"pair": u * lam_all[0] / lam_all[t - 1] * np.ones(t), "span": f["span"],
+                    "gap": f["gap"]}
+        assert not check_accuracy_floor(bad)
+
+    def test_wrong_unit_roundoff_is_caught(self):
+        import inspect
+        default_u = inspect.signature(O.accuracy_floor).parameters["u"].default
+        assert default_u == np.finfo(np.float64).eps / 2      # 2^-52 would fail here
+        assert 2.0 ** -52 != np.finfo(np.float64).eps / 2
+
+    def test_shifted_mu_index_in_rho_lower_bound_is_caught(self):
+        def bad(mu, nu, t):
+            d = mu.size
+            i = np.arange(1, t + 1)
+            lo = np.maximum(np.exp(mu[np.minimum(d - t + i, d - 1)] - nu[0]),
+                            np.exp(mu[d - 1] - nu[t - i]))
+            return float(lo.sum()), O.rho_bounds_thm34(mu, nu, t)[1]
+        mu = np.sort(RNG.uniform(0, 2, 7))[::-1]
+        lo, _ = bad(mu, np.zeros(7), 3)
+        assert not np.isclose(lo, np.exp(mu[-3:]).sum(), rtol=1e-12)
+
+    def test_reversed_nu_index_in_rho_upper_bound_is_caught(self):
+        def bad(mu, nu, t):
+            d = mu.size
+            i = np.arange(1, t + 1)
+            hi = np.minimum(np.exp(mu[i - 1] - nu[d - 1]), np.exp(mu[0] - nu[i - 1]))
+            return O.rho_bounds_thm34(mu, nu, t)[0], float(hi.sum())
+        nu = np.sort(RNG.uniform(0, 2, 7))[::-1]
+        _, hi = bad(np.zeros(7), nu, 3)
+        assert not np.isclose(hi, np.exp(-nu[-3:]).sum(), rtol=1e-12)
