@@ -29,7 +29,7 @@ bfloat16 factors + float32 basis + float64 refinement (prepare + solve each).
 
 `nn_tol_sweep`: Section 3.3 on a split of the headline workload (200
 training, 200 testing samples): 1-NN accuracy, angle to the tol-1e-10
-subspace and the Theorem 3.8 check for tol 1e-2 ... 1e-10, and the time of
+subspace and the Theorem 3.7 check for tol 1e-2 ... 1e-10, and the time of
 one eda_nn_classify call.
 
 `batched`: 64 independent problems of uneven shape (d in {1024, 4096,
@@ -116,7 +116,7 @@ def _upload(torch, X):
 
 def mixed_vs_f64(torch, eda, reps: int = 3) -> dict:
     import datagen
-    from tests.golden.make_golden import read as read_golden
+    from tests.golden.reader import read as read_golden
     p = datagen.config("C3")
     g = read_golden("C3")
     Xd = _upload(torch, p.X)
@@ -157,7 +157,7 @@ def large_fp8_vs_f64(torch, eda, reps: int = 3) -> dict:
     float64 refinement (solve phase only, preparation shared per storage),
     with the exponential product's bandwidth for each storage type."""
     import datagen
-    from tests.golden.make_golden import read as read_golden
+    from tests.golden.reader import read as read_golden
     p = datagen.config("C5")
     g = read_golden("C5")
     h = eda.Handle()
@@ -242,7 +242,7 @@ def nn_tol_sweep(torch, eda, reps: int = 20) -> dict:
     model): solve to each tolerance, classify the testing samples by 1-NN in
     the solution's subspace, and compare with the tightest solution: the
     accuracy, sin of the angle, the largest change of a nearest distance and
-    whether Theorem 3.8's bounds hold.  Also the classification call itself
+    whether Theorem 3.7's bounds hold.  Also the classification call itself
     (projections of all samples + distances): time and the bytes of the
     samples it streams."""
     import datagen
@@ -263,14 +263,14 @@ def nn_tol_sweep(torch, eda, reps: int = 20) -> dict:
     dref = sols[1e-10][3]
     rows = []
     for tol, (r, X, pred, dist) in sols.items():
-        # sin = ||(I - Vref Vref^T) X||_2, cos = ||Vref^T X||_2 (Theorem 3.8)
+        # sin = ||(I - Vref Vref^T) X||_2, cos = ||Vref^T X||_2 (Theorem 3.7)
         sin = float(np.linalg.norm(X - Vref @ (Vref.T @ X), 2))
         cos = float(np.linalg.norm(Vref.T @ X, 2))
         lo, hi = (dist - 2 * sin) / cos, dist * cos + 2 * sin
         rows.append({"tol": tol, "status": r.status, "iters": r.info["iters"],
                      "accuracy": float(np.mean(pred == lte)), "sin_angle_vs_1e-10": sin,
                      "max_nn_dist_change": float(np.max(np.abs(dist - dref))),
-                     "thm38_holds": bool(np.all(lo <= dref + 1e-12) and np.all(dref <= hi + 1e-12))})
+                     "thm37_holds": bool(np.all(lo <= dref + 1e-12) and np.all(dref <= hi + 1e-12))})
     X = sols[1e-8][0].X
     for _ in range(3):
         h.nn_classify(X, tr, labels, te)
@@ -381,7 +381,7 @@ def main():
     avg_op_s = op_ms / op_calls / 1e3
     achieved = op_bytes / avg_op_s / 1e9
     # sanity against the stored oracle values (text file, no oracle import)
-    from tests.golden.make_golden import read as read_golden
+    from tests.golden.reader import read as read_golden
     g = read_golden("C2")
     lam_err = float(np.max(np.abs(np.array(res.ritz) - g["lam"]) / g["lam"]))
 

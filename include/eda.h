@@ -291,6 +291,15 @@ eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_problem* pro
  * N = n + k, P = [H_W H_B]); G: device out (ldg >= N).  Stream-ordered. */
 eda_status eda_gram(eda_handle h, double* G, int64_t ldg);
 
+/* The stored factor P = [H_W H_B] of the current preparation (factor
+ * ingest, eqs. (1.1)-(1.2) in the storage encoding of eda_prepare), for
+ * checks of the byte-level encoding: out (device, ld ldo >= d) receives the
+ * d x (n + k) entries column-major in the storage type (float64, float32,
+ * bfloat16 codes as uint16, E4M3 codes as uint8); for EDA_FP8_E4M3, scales
+ * (device, n + k float64, may be NULL) receives the per-column scales, so
+ * that P(:, j) ~ scales[j] * decode(out(:, j)).  Stream-ordered. */
+eda_status eda_factor_codes(eda_handle h, void* out, int64_t ldo, double* scales);
+
 /* Symmetric eigensolver used for the Gram and Rayleigh-Ritz matrices:
  * A = Z diag(w) Z^T for symmetric A (n x n float64, device, lda >= n, only
  * the lower triangle is read; A is not modified).  w: device out [n]

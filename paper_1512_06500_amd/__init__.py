@@ -36,7 +36,7 @@ _DTYPES = {"f64": EDA_F64, "f32": EDA_F32, "bf16": EDA_BF16, "fp8": EDA_FP8_E4M3
 EXPORTED_SYMBOLS = [
     "eda_create", "eda_destroy", "eda_strerror", "eda_last_error", "eda_scatter_factors",
     "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_solve_direct", "eda_solve_batched",
-    "eda_gram",
+    "eda_gram", "eda_factor_codes",
     "eda_syev", "eda_autotune", "eda_nn_classify",
 ]
 
@@ -133,6 +133,8 @@ def load_library():
     L.eda_solve_batched.restype = ctypes.c_int
     L.eda_gram.argtypes = [vp, vp, i64]
     L.eda_gram.restype = ctypes.c_int
+    L.eda_factor_codes.argtypes = [vp, vp, i64, vp]
+    L.eda_factor_codes.restype = ctypes.c_int
     L.eda_syev.argtypes = [vp, i64, vp, i64, vp, vp, i64]
     L.eda_syev.restype = ctypes.c_int
     L.eda_autotune.argtypes = [vp, i64, i64, i32, ctypes.c_int, ctypes.POINTER(i32),
@@ -390,6 +392,21 @@ class Handle:
         G = _empty_cm(N, N, self._torch.float64, self.device)
         self._check(self.lib.eda_gram(self._h, G.data_ptr(), _ld(G)))
         return G
+
+    def factor_codes(self):
+        """The stored factor P = [H_W H_B] in its storage encoding: a d x (n+k)
+        column-major tensor of float64 / float32 / int16 (bfloat16 codes) /
+        uint8 (E4M3 codes), and for E4M3 storage the per-column scales."""
+        torch = self._torch
+        N = self.n + self.k
+        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.int16,
+              "fp8": torch.uint8}[self.storage]
+        P = _empty_cm(self.d, N, dt, self.device)
+        sc = torch.empty(N, dtype=torch.float64, device=self.device) if self.storage == "fp8" \
+            else None
+        self._check(self.lib.eda_factor_codes(self._h, P.data_ptr(), _ld(P),
+                                              sc.data_ptr() if sc is not None else None))
+        return P, sc
 
     def nn_classify(self, X, train, train_labels, test):
         """1-NN classification in span X (Section 3.3): for every column of

@@ -33,8 +33,28 @@ template <typename T> __device__ __forceinline__ T from_f64(double x);
 template <> __device__ __forceinline__ double from_f64<double>(double x) { return x; }
 template <> __device__ __forceinline__ float from_f64<float>(double x) { return (float)x; }
 
-// bfloat16 (round to nearest even from float).
+// bfloat16: 8 exponent bits (bias 127), 7 stored mantissa bits.
 using bf16_t = __hip_bfloat16;
+
+// Code of the bfloat16 value nearest to x, rounded once from float64 (ties
+// to the even significand).  The spacing of bfloat16 values around |x| is a
+// power of two 2^qe (2^-133 among the subnormals), so |x| 2^-qe is exact in
+// float64 and rint rounds it; magnitudes that round to 2^128 become
+// infinity.  (Converting to float first would round twice: a value just
+// above a bfloat16 tie can land on the tie in float32 and then go to even.)
+__device__ inline uint16_t bf16_bits_rne(double x) {
+  if (x != x) return 0x7fc0;
+  const uint16_t s = signbit(x) ? 0x8000 : 0;
+  const double a = fabs(x);
+  if (a == 0.0) return s;
+  if (a >= 0x1.0p128) return s | 0x7f80;
+  int e;
+  (void)frexp(a, &e);  // a in [2^(e-1), 2^e)
+  const int qe = ((e - 1 > -126) ? e - 1 : -126) - 7;
+  const double r = ldexp(rint(ldexp(a, -qe)), qe);
+  if (r >= 0x1.0p128) return s | 0x7f80;
+  return s | (uint16_t)(__float_as_uint((float)r) >> 16);  // r is exact in float
+}
 template <> __device__ __forceinline__ double to_f64<bf16_t>(bf16_t x) {
   return (double)__bfloat162float(x);
 }
@@ -45,7 +65,7 @@ template <> __device__ __forceinline__ double to_acc<double, bf16_t>(bf16_t x) {
   return (double)__bfloat162float(x);
 }
 template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) {
-  return __float2bfloat16((float)x);
+  return __ushort_as_bfloat16(bf16_bits_rne(x));
 }
 
 // FP8 E4M3 in the OCP layout (sign, 4 exponent bits with bias 7, 3 mantissa

@@ -684,6 +684,23 @@ eda_status eda_gram(eda_handle h, double* G, int64_t ldg) {
   return EDA_OK;
 }
 
+eda_status eda_factor_codes(eda_handle h, void* out, int64_t ldo, double* scales) {
+  if (h == nullptr) return EDA_ERR_ARG;
+  if (!h->prepared) return fail(h, EDA_ERR_STATE, "eda_prepare has not succeeded");
+  if (out == nullptr || ldo < h->d) return fail(h, EDA_ERR_ARG, "out null or ldo < d");
+  STCHK(need_device(h));
+  STCHK(check_dev_ptr(h, out, "out"));
+  const size_t es = dsize(h->storage);
+  HIPCHK(hipMemcpy2DAsync(out, (size_t)ldo * es, h->P.p, (size_t)h->ldp * es, (size_t)h->d * es,
+                          (size_t)h->N, hipMemcpyDeviceToDevice, h->stream));
+  if (scales != nullptr && h->storage == EDA_FP8_E4M3) {
+    STCHK(check_dev_ptr(h, scales, "scales"));
+    HIPCHK(hipMemcpyAsync(scales, h->pscale.p, (size_t)h->N * 8, hipMemcpyDeviceToDevice,
+                          h->stream));
+  }
+  return EDA_OK;
+}
+
 eda_status eda_syev(eda_handle h, int64_t n, const double* A, int64_t lda, double* w, double* Z,
                     int64_t ldz) {
   if (h == nullptr) return EDA_ERR_ARG;
