@@ -140,7 +140,7 @@ const char* eda_last_error(eda_handle h);
 /* Scatter factors of eqs. (1.1)-(1.2).
  * X: device, d x n float64, ld ldx >= d, samples as columns, classes stored
  *    contiguously (class j occupies counts[j] consecutive columns).
- * counts: host, k entries, each >= 1, summing to n.
+ * counts: host, k entries (1 <= k <= 65535), each >= 1, summing to n.
  * H_W: device out, d x n (ld ldw >= d): X_j - mu_j e^T per class.
  * H_B: device out, d x k (ld ldb >= d): sqrt(n_j) (mu_j - mu), mu the mean of
  *      all n samples.  Stream-ordered, no synchronisation. */
@@ -230,7 +230,7 @@ eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* 
  * it once and rewritten after each tuning.  eda_solve_batched tunes the
  * class of its largest problem by itself (EDA_AUTOTUNE=0 disables that).
  * Outputs (host, each may be NULL): *tn_steps = 64-row steps per wave of the
- * P^T V pass (1, 2 or 4); *nn_tile = configuration of the P Z pass (0..3,
+ * P^T V pass (1, 2, 4 or 8); *nn_tile = configuration of the P Z pass (0..3,
  * -1 for FP8/bfloat16 storage, which has one shape); us[0], us[1] = their
  * measured times in microseconds.  Results of the products do not depend on
  * the shapes beyond the order of partial sums.  Synchronises. */

@@ -214,6 +214,9 @@ struct NnArgs {      // Out = alpha V + A Z
   const double* ascale;   // when not null, column i of A is scaled by ascale[i] (FP8 storage)
   const int* mask;        // when not null, output columns j with mask[j] != 0 get
   uint64_t seed;          //   masked_gauss(seed, j * d + row) instead of the product
+  // when > 0: column groups of kcols columns, each writing its partial
+  // product row-major to Out + group * d * nb (streaming kernel only)
+  int64_t kcols = 0;
 };
 struct CholArgs {
   int64_t b, ldg, ldri, ldrp, ldro, m, ldhc;
@@ -416,7 +419,7 @@ hipError_t launch_restart_coupling(int64_t m, int64_t b, int64_t kk, const doubl
 
 // Tile table (eda_tune.cpp): tuned launch shapes per shape class
 // (kind, ceil(log2 d), ceil(log2 m), entry bytes); -1 when not tuned.
-//   TnSteps: 64-row steps per wave of the tn kernel (1, 2 or 4), which fixes
+//   TnSteps: 64-row steps per wave of the tn kernel (1, 2, 4 or 8), which fixes
 //            its chunk count (tn_chunks); NnTile: nn configuration index
 //            0 (16 rows, 4 loads per batch), 1 (16, 16), 2 (32, 8), 3 (64, 8).
 enum class TuneKind { TnSteps = 0, NnTile = 1 };
@@ -442,6 +445,15 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
                                   int64_t ldc2 = 0);
 // Out = alpha * V + A * Z, Z row-major (Z[i*ldz + j]) float64, m columns of A.
 // Out column-major (Out[r + j*ldo]) or, with out_row, row-major (Out[r*ldo + j]).
+// Z = C Y for a square float64 C (m x m, column-major ldc) and a row-major
+// float64 Y (m x nb, nb <= 8, ld ldy): the columns of C are split into
+// groups whose partial products are written to `part` (at least
+// nn_split_groups(m) * m * nb doubles) and summed in a fixed order into Z
+// (row-major, ld ldz).  Returns hipErrorInvalidValue when the shape does not
+// suit the split (the caller then uses launch_nn).
+int64_t nn_split_groups(int64_t m);
+hipError_t launch_nn_split(int64_t m, int64_t nb, const double* C, int64_t ldc, const double* Y,
+                           int64_t ldy, double* part, double* Z, int64_t ldz, hipStream_t s);
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
                      const double* Z, int64_t ldz, double alpha, const void* V, DT vdt,
                      int64_t ldv, void* Out, DT odt, int64_t ldo, const int* gate,

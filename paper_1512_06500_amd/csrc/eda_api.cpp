@@ -119,9 +119,17 @@ eda_status expop_second(eda_handle h, bool master, int64_t c0, int64_t Nc, const
   }
   const double* sc = (pdt == DT::FP8) ? h->pscale.d() + c0 : nullptr;
   // Z = C Y (row-major) by the same streaming kernel with C as the tall
-  // operand, then Out = alpha V + P_c Z
-  HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, ysm, ldy, 0.0, nullptr, DT::F64, 0, h->Zsm.d(),
-                   DT::F64, b, nullptr, h->stream, true));
+  // operand (split over column groups of C when it is large), then
+  // Out = alpha V + P_c Z
+  bool done = false;
+  if (Nc >= 1024 && b <= 8 && ldc % 2 == 0 && (uintptr_t)C % 16 == 0) {
+    STCHK(ensure(h, h->zpart, (size_t)nn_split_groups(Nc) * Nc * b * 8));
+    HIPCHK(launch_nn_split(Nc, b, C, ldc, ysm, ldy, h->zpart.d(), h->Zsm.d(), b, h->stream));
+    done = true;
+  }
+  if (!done)
+    HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, ysm, ldy, 0.0, nullptr, DT::F64, 0, h->Zsm.d(),
+                     DT::F64, b, nullptr, h->stream, true));
   HIPCHK(launch_nn(h->d, Nc, b, Pc, pdt, h->ldp, h->Zsm.d(), b, alpha, V, vdt, ldv, Out, odt,
                    ldo, nullptr, h->stream, false, alpha_p, sc));
   return EDA_OK;
@@ -372,7 +380,7 @@ void eda_destroy(eda_handle h) {
     (void)hipStreamSynchronize(h->stream);
     Buf* all[] = {&h->polyws, &h->normbuf,
                   &h->P,  &h->G,  &h->eigW, &h->eigZ, &h->nsbuf, &h->Gh,  &h->Gm,  &h->GBs,
-                  &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part,
+                  &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part, &h->zpart,
                   &h->Ysm, &h->Zsm, &h->PQ[0], &h->PQ[1], &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
                   &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale};
@@ -401,6 +409,7 @@ eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k, co
                                double* H_B, int64_t ldb) {
   if (h == nullptr) return EDA_ERR_ARG;
   if (d < 1 || n < 1 || k < 1 || k > n) return fail(h, EDA_ERR_ARG, "need d>=1, 1<=k<=n");
+  if (k > 65535) return fail(h, EDA_ERR_ARG, "k=%lld exceeds 65535 classes", (long long)k);
   if (X == nullptr || counts == nullptr || H_W == nullptr || H_B == nullptr)
     return fail(h, EDA_ERR_ARG, "null pointer argument");
   if (ldx < d || ldw < d || ldb < d) return fail(h, EDA_ERR_ARG, "leading dimensions must be >= d");

@@ -53,7 +53,7 @@ void load_locked() {
   while (std::fscanf(f, "%7s %d %d %d %d", kind, &dl, &ml, &es, &v) == 5) {
     const bool tn = std::strcmp(kind, "tn") == 0, nn = std::strcmp(kind, "nn") == 0;
     if ((!tn && !nn) || dl < 0 || dl > 62 || ml < 0 || ml > 62 || es < 0 || es > 8) continue;
-    if (tn && v != 1 && v != 2 && v != 4) continue;
+    if (tn && v != 1 && v != 2 && v != 4 && v != 8) continue;
     if (nn && (v < 0 || v >= kNnConfigs)) continue;
     g_table[make_key(tn ? 0 : 1, dl, ml, es)] = v;
   }
@@ -142,7 +142,7 @@ eda_status autotune_shapes(eda_handle h, int64_t d, int64_t N, int64_t b, eda_dt
   // tn: 64-row steps per wave
   int best_s = -1;
   double best_tn = 1e30;
-  for (int S : {1, 2, 4}) {
+  for (int S : {1, 2, 4, 8}) {
     if (e != hipSuccess) break;
     tune_set(TuneKind::TnSteps, d, N, 0, S);
     const int64_t chunks = tn_chunks(d, N, b);

@@ -19,29 +19,40 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// Scatter factors, Section 1, eqs. (1.1)-(1.2).  One thread per feature row.
+// Scatter factors, Section 1, eqs. (1.1)-(1.2), in two launches.  First one
+// workgroup per (256 feature rows, class j): each thread sums its row over
+// the class's samples, writes the centred samples to H_W and the class sum
+// s_j to H_B (column j).  Then one thread per row: mu = (sum_j s_j) / n (the
+// sample-weighted global centroid) and H_B(:, j) = sqrt(n_j) (s_j / n_j - mu).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void scatter_kernel(int64_t d, int64_t n, int64_t k,
-                                                      const double* __restrict__ X, int64_t ldx,
-                                                      const int64_t* __restrict__ offs,
-                                                      double* __restrict__ HW, int64_t ldw,
-                                                      double* __restrict__ HB, int64_t ldb) {
+__global__ __launch_bounds__(256) void scatter_class_kernel(int64_t d, const double* __restrict__ X,
+                                                            int64_t ldx,
+                                                            const int64_t* __restrict__ offs,
+                                                            double* __restrict__ HW, int64_t ldw,
+                                                            double* __restrict__ HB, int64_t ldb) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= d) return;
+  const int64_t c0 = offs[j], c1 = offs[j + 1];
+  double s = 0.0;
+  for (int64_t c = c0; c < c1; ++c) s += X[i + c * ldx];
+  const double mj = s / (double)(c1 - c0);
+  for (int64_t c = c0; c < c1; ++c) HW[i + c * ldw] = X[i + c * ldx] - mj;
+  HB[i + j * ldb] = s;
+}
+
+__global__ __launch_bounds__(256) void scatter_between_kernel(int64_t d, int64_t n, int64_t k,
+                                                              const int64_t* __restrict__ offs,
+                                                              double* __restrict__ HB,
+                                                              int64_t ldb) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= d) return;
   double total = 0.0;
-  for (int64_t j = 0; j < k; ++j) {
-    const int64_t c0 = offs[j], c1 = offs[j + 1];
-    double s = 0.0;
-    for (int64_t c = c0; c < c1; ++c) s += X[i + c * ldx];
-    total += s;
-    const double mj = s / (double)(c1 - c0);
-    for (int64_t c = c0; c < c1; ++c) HW[i + c * ldw] = X[i + c * ldx] - mj;
-    HB[i + j * ldb] = mj;
-  }
+  for (int64_t j = 0; j < k; ++j) total += HB[i + j * ldb];
   const double mu = total / (double)n;  // sample-weighted global centroid
   for (int64_t j = 0; j < k; ++j) {
     const double nj = (double)(offs[j + 1] - offs[j]);
-    HB[i + j * ldb] = sqrt(nj) * (HB[i + j * ldb] - mu);
+    HB[i + j * ldb] = sqrt(nj) * (HB[i + j * ldb] / nj - mu);
   }
 }
 
@@ -392,8 +403,10 @@ hipError_t launch_copy_block(int64_t rows, int64_t cols, double alpha, const dou
 hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int64_t ldx,
                           const int64_t* offsets, double* H_W, int64_t ldw, double* H_B,
                           int64_t ldb, hipStream_t s) {
-  hipLaunchKernelGGL(scatter_kernel, dim3(nblk(d)), dim3(256), 0, s, d, n, k, X, ldx, offsets,
-                     H_W, ldw, H_B, ldb);
+  hipLaunchKernelGGL(scatter_class_kernel, dim3(nblk(d), (unsigned)k), dim3(256), 0, s, d, X, ldx,
+                     offsets, H_W, ldw, H_B, ldb);
+  hipLaunchKernelGGL(scatter_between_kernel, dim3(nblk(d)), dim3(256), 0, s, d, n, k, offsets, H_B,
+                     ldb);
   return hipGetLastError();
 }
 

@@ -1,8 +1,7 @@
-// Small dense FP64 products: general GEMM for the cores (n x n and n x k
-// factors of the exponentials) on the matrix cores, and the Gram matrix
-// P^T P of the scatter factors (register-tiled FMA kernel: 64 x 64 output
-// tiles, 256 threads, 4 x 4 outputs per thread, K staged through LDS in
-// slices of 16).
+// Dense FP64 products: general GEMM for the cores (n x n and n x k factors
+// of the exponentials) and the Gram matrix P^T P of the scatter factors, on
+// the matrix cores (128 x 128 tiles for large shapes, 32 x 32 for small
+// ones), plus a register-tiled FMA Gram kernel for narrow factors.
 #include "common.h"
 
 namespace eda {
@@ -99,6 +98,200 @@ __global__ __launch_bounds__(256) void gemm_kernel(bool ta, bool tb, int64_t m, 
   }
 }
 
+// Large products on the matrix cores: C (M x N) = alpha op(A) diag(dk) op(B)
+// (+ beta C), or, for the Gram matrix, partial tiles of P^T P over row
+// chunks.  A workgroup owns a BT x BT tile of C (BT = 128): its 4 waves a
+// 2 x 2 grid of 64 x 64 quadrants, 16 v_mfma_f64_16x16x4f64 accumulators
+// each, so every A or B fragment read from LDS feeds 4 products.  K is
+// staged through LDS in slices of BK = 16, op(A) and op(B) both k-major
+// (As[k][i], Bs[k][j]: the 16 lanes of a fragment read 128 contiguous bytes),
+// and the next slice is loaded into registers with 16-byte loads while the
+// current one is multiplied.  Global loads run along whichever index is
+// contiguous in memory (i for op(A) = A, k for op(A) = A^T; likewise for B).
+// Requires even leading dimensions and 16-byte aligned operands (the
+// launcher falls back to gemm_kernel otherwise).
+constexpr int BT = 128;  // tile edge of the Gram kernel (and of large GEMMs)
+constexpr int BK = 16;
+
+// LDS row stride (doubles) for a tile edge T: T + 18 for 128, T + 2 for 64,
+// both = 2 (mod 16), which keeps the transposing stores (8 lanes on rows 0,
+// 2, .., 14 of one column) on distinct banks while the 4 k groups of a
+// fragment read nearly disjoint bank ranges
+template <int T> struct BigStride { static constexpr int v = (T == 128) ? 146 : 66; };
+
+struct BigGemmArgs {
+  int64_t M, N, K, lda, ldb, ldc;
+  const double* A;
+  const double* B;
+  const double* dk;
+  double* C;
+  double alpha, beta;
+  int ta, tb;
+  // Gram mode: lower-triangle tiles (blockIdx.x enumerates them), K split
+  // into chunks of kchunk rows (blockIdx.y), partial tile written to
+  // part + chunk * N * N (column-major N x N, only the tile's entries)
+  int gram;
+  int64_t kchunk;
+  double* part;
+};
+
+// Loads of one BK slice of op(X) (rows: the T-edge tile index, k: the
+// slice), T BK / 512 pairs of doubles per thread.  trans == false: X(i, k)
+// at X[i + k ld] (pairs along i); trans: X(i, k) at X[k + i ld] (pairs
+// along k).
+template <int T>
+__device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t ld, bool trans,
+                                         int64_t i0, int64_t nI, int64_t k0, int64_t kend,
+                                         double2 (&r)[T * BK / 512]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < T * BK / 512; ++q) {
+    const int e = tid + 256 * q;
+    int ii, kk;
+    if (!trans) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
+    else { kk = 2 * (e % (BK / 2)); ii = e / (BK / 2); }
+    const int64_t gi = i0 + ii, gk = k0 + kk;
+    double2 v = {0.0, 0.0};
+    if (!trans) {
+      if (gk < kend) {
+        const double* p = X + gi + gk * ld;
+        if (gi + 1 < nI) v = *(const double2*)p;
+        else if (gi < nI) v.x = p[0];
+      }
+    } else {
+      if (gi < nI) {
+        const double* p = X + gk + gi * ld;
+        if (gk + 1 < kend) v = *(const double2*)p;
+        else if (gk < kend) v.x = p[0];
+      }
+    }
+    r[q] = v;
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v], bool trans,
+                                          const double2 (&r)[T * BK / 512],
+                                          const double* __restrict__ dk, int64_t k0,
+                                          int64_t kend) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < T * BK / 512; ++q) {
+    const int e = tid + 256 * q;
+    int ii, kk;
+    if (!trans) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
+    else { kk = 2 * (e % (BK / 2)); ii = e / (BK / 2); }
+    double x = r[q].x, y = r[q].y;
+    if (!trans) {
+      if (dk != nullptr && k0 + kk < kend) { const double f = dk[k0 + kk]; x *= f; y *= f; }
+      S[kk][ii] = x;
+      S[kk][ii + 1] = y;
+    } else {
+      if (dk != nullptr) {
+        if (k0 + kk < kend) x *= dk[k0 + kk];
+        if (k0 + kk + 1 < kend) y *= dk[k0 + kk + 1];
+      }
+      S[kk][ii] = x;
+      S[kk + 1][ii] = y;
+    }
+  }
+}
+
+// T x T tile per workgroup; wave quadrants of (T/2) x (T/2) = QB x QB MFMA blocks.
+template <int T>
+__global__ __launch_bounds__(256) void big_gemm_kernel(BigGemmArgs a) {
+  constexpr int LS = BigStride<T>::v;
+  constexpr int QB = T / 32;  // 16 x 16 blocks per quadrant edge
+  constexpr int NP = T * BK / 512;
+  __shared__ double As[BK][LS];
+  __shared__ double Bs[BK][LS];
+  int64_t ti, tj, kbeg, kend;
+  if (a.gram) {
+    int64_t t = blockIdx.x;
+    ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    tj = t - ti * (ti + 1) / 2;
+    kbeg = (int64_t)blockIdx.y * a.kchunk;
+    kend = min(a.K, kbeg + a.kchunk);
+  } else {
+    ti = blockIdx.x;
+    tj = blockIdx.y;
+    kbeg = 0;
+    kend = a.K;
+  }
+  const int64_t i0 = ti * T, j0 = tj * T;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int qi = (wid >> 1) * (T / 2), qj = (wid & 1) * (T / 2);  // quadrant of the wave
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[QB][QB];
+#pragma unroll
+  for (int x = 0; x < QB; ++x)
+#pragma unroll
+    for (int y = 0; y < QB; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // op(B)(k, j) = B(k, j) (tb == 0: contiguous along k) or B(j, k) (tb:
+  // contiguous along j): loaded as X(j, k) that is "trans" exactly when tb == 0
+  double2 ra[NP], rb[NP];
+  if (kbeg < kend) {
+    big_load<T>(a.A, a.lda, a.ta != 0, i0, a.M, kbeg, kend, ra);
+    big_load<T>(a.B, a.ldb, a.tb == 0, j0, a.N, kbeg, kend, rb);
+  }
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();  // the previous slice has been read
+    big_store<T>(As, a.ta != 0, ra, a.dk, k0, kend);
+    big_store<T>(Bs, a.tb == 0, rb, nullptr, k0, kend);
+    __syncthreads();
+    if (k0 + BK < kend) {
+      big_load<T>(a.A, a.lda, a.ta != 0, i0, a.M, k0 + BK, kend, ra);
+      big_load<T>(a.B, a.ldb, a.tb == 0, j0, a.N, k0 + BK, kend, rb);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double fa[QB], fb[QB];
+#pragma unroll
+      for (int x = 0; x < QB; ++x) fa[x] = As[ks + lk][qi + 16 * x + li];
+#pragma unroll
+      for (int y = 0; y < QB; ++y) fb[y] = Bs[ks + lk][qj + 16 * y + li];
+#pragma unroll
+      for (int x = 0; x < QB; ++x)
+#pragma unroll
+        for (int y = 0; y < QB; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[x], fb[y], acc[x][y], 0, 0, 0);
+    }
+  }
+  // accumulator element v of lane l: row 4 v + l / 16, column l % 16 of the block
+#pragma unroll
+  for (int x = 0; x < QB; ++x)
+#pragma unroll
+    for (int y = 0; y < QB; ++y) {
+      const int64_t gj = j0 + qj + 16 * y + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = i0 + qi + 16 * x + 4 * v + lk;
+        if (gi >= a.M || gj >= a.N) continue;
+        if (a.gram) {
+          a.part[(int64_t)blockIdx.y * a.N * a.N + gi + gj * a.N] = acc[x][y][v];
+        } else {
+          double* cp = a.C + gi + gj * a.ldc;
+          *cp = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * acc[x][y][v];
+        }
+      }
+    }
+}
+
+// Sum of the Gram partials of big_gemm_kernel (tiles of BT), mirrored.
+__global__ __launch_bounds__(256) void big_gram_reduce_kernel(int64_t N, int64_t chunks,
+                                                              const double* __restrict__ part,
+                                                              double* __restrict__ G, int64_t ldg) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  const int64_t j = e / N, i = e - j * N;
+  const bool lower = (i / BT) >= (j / BT);
+  const int64_t src = lower ? (i + j * N) : (j + i * N);
+  double s = 0.0;
+  for (int64_t c = 0; c < chunks; ++c) s += part[c * N * N + src];
+  G[i + j * ldg] = s;
+}
+
 // Gram partials over one row chunk for one lower-triangle tile (ti >= tj).
 template <typename TP>
 __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t d, int64_t N,
@@ -188,27 +381,81 @@ void gram_geometry(int64_t d, int64_t N, int64_t* chunks, int64_t* rows) {
   *chunks = (d + rp - 1) / rp;
 }
 
+// Row chunks of the matrix-core Gram: enough lower-triangle tiles x chunks
+// to fill whole rounds of 512 resident workgroups (two per compute unit),
+// chunks of at least 256 rows, a multiple of BK.
+void big_gram_geometry(int64_t d, int64_t N, int64_t* chunks, int64_t* rows) {
+  const int64_t T = (N + BT - 1) / BT;
+  const int64_t tiles = T * (T + 1) / 2;
+  int64_t best = 1;
+  double best_eff = 0.0;
+  for (int64_t c = 1; c <= 16; ++c) {
+    if (c > 1 && (d + c - 1) / c < 256) break;
+    const int64_t wg = tiles * c;
+    const int64_t rounds = (wg + 511) / 512;
+    const double eff = (double)wg / (double)(rounds * 512);
+    if (eff > best_eff + 1e-9) { best_eff = eff; best = c; }
+  }
+  int64_t rp = (d + best - 1) / best;
+  rp = ((rp + BK - 1) / BK) * BK;
+  *rows = rp;
+  *chunks = (d + rp - 1) / rp;
+}
+
+bool big_ok(const double* p, int64_t ld) { return ld % 2 == 0 && ((uintptr_t)p % 16) == 0; }
+
 }  // namespace
 
 hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha,
                        const double* A, int64_t lda, const double* dk, const double* B,
                        int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (m >= 512 && n >= 512 && k >= 64 && big_ok(A, lda) && big_ok(B, ldb)) {
+    BigGemmArgs a{m, n, k, lda, ldb, ldc, A, B, dk, C, alpha, beta, ta ? 1 : 0, tb ? 1 : 0,
+                  0, 0, nullptr};
+    // 128 x 128 tiles while they give 512 workgroups, else 64 x 64
+    if (((m + 127) / 128) * ((n + 127) / 128) >= 512) {
+      dim3 g((unsigned)((m + 127) / 128), (unsigned)((n + 127) / 128));
+      hipLaunchKernelGGL(big_gemm_kernel<128>, g, dim3(256), 0, s, a);
+    } else {
+      dim3 g((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
+      hipLaunchKernelGGL(big_gemm_kernel<64>, g, dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+  }
   dim3 g((unsigned)((m + MT - 1) / MT), (unsigned)((n + MT - 1) / MT));
   hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, dk, B, ldb,
                      beta, C, ldc);
   return hipGetLastError();
 }
 
+// The matrix-core Gram serves float64 factors with at least 256 columns
+// (enough tiles); the register-tiled kernel everything else.
+static bool gram_big(int64_t N, DT pdt) { return pdt == DT::F64 && N >= 256; }
+
 int64_t gram_chunks(int64_t d, int64_t N) {
   int64_t c, r;
-  gram_geometry(d, N, &c, &r);
+  if (gram_big(N, DT::F64))
+    big_gram_geometry(d, N, &c, &r);
+  else
+    gram_geometry(d, N, &c, &r);
   return c;
 }
 
 hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int64_t ldp,
                                double* part, int64_t chunks, hipStream_t s) {
   int64_t c, rows;
+  if (gram_big(N, pdt) && big_ok((const double*)P, ldp)) {
+    big_gram_geometry(d, N, &c, &rows);
+    if (c != chunks) return hipErrorInvalidValue;
+    const int64_t T = (N + BT - 1) / BT;
+    BigGemmArgs a{N, N, d, ldp, ldp, N, (const double*)P, (const double*)P, nullptr, nullptr,
+                  1.0, 0.0, 1, 0, 1, rows, part};
+    hipLaunchKernelGGL(big_gemm_kernel<BT>, dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks),
+                       dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (gram_big(N, pdt)) return hipErrorInvalidValue;  // chunks were sized for the big kernel
   gram_geometry(d, N, &c, &rows);
   if (c != chunks) return hipErrorInvalidValue;
   const int64_t T = (N + GT - 1) / GT;
@@ -224,6 +471,11 @@ hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int6
 
 hipError_t launch_gram_reduce(int64_t N, int64_t chunks, const double* part, double* G,
                               int64_t ldg, hipStream_t s) {
+  if (gram_big(N, DT::F64)) {
+    hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0,
+                       s, N, chunks, part, G, ldg);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, N,
                      chunks, part, G, ldg);
   return hipGetLastError();

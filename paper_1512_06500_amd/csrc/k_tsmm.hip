@@ -26,6 +26,7 @@
 // R rows x G = 256/R column groups (column j goes to group j mod G), so every
 // lane issues m/G independent loads in batches, reading rows of Z from an LDS
 // copy.  The G partial sums of a row are added in a fixed order through LDS.
+#include <cstdlib>
 #include <type_traits>
 
 #include "common.h"
@@ -160,6 +161,255 @@ __global__ __launch_bounds__(256) void tn_mfma_kernel(const TnArgs* __restrict__
   const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
   tn_body<TA, TB, S, CT, ZT>(a, blockIdx.x, blockIdx.y % ygroups, blockIdx.y / ygroups);
+}
+
+// Streaming variant of tn for a narrow B (nb <= 16) and a float64/float32 A
+// whose columns start on 16-byte boundaries: one 16-column tile of A per
+// workgroup, the 4 waves on consecutive 64 S-row ranges.  Every load is a
+// 16-byte vector load, arranged so that the 4 lanes of one column read
+// consecutive 16-byte pieces (a wave instruction touches 16 column segments
+// of 64 bytes), and the loads of step s + 1 are issued before the matrix-core
+// products of step s, so a wave always has a step in flight.  The k slot of
+// MFMA number (l, h) in lane (i, q) is row rb + 4 VW l + VW q + h (VW = 16 /
+// sizeof(TA) rows per vector), the same for A and B, which is all a sum over
+// rows needs.  Partial layout and chunking are those of tn_body.
+template <typename T> struct Vec16 {
+  static constexpr int VW = 16 / (int)sizeof(T);
+  typedef T type __attribute__((ext_vector_type(VW)));
+};
+
+template <typename TA, typename TB, int S>
+__device__ __forceinline__ void tn_stream_body(const TnArgs& a, int64_t chunk, int tile) {
+  constexpr int VW = Vec16<TA>::VW;   // rows per A vector load (2 or 4)
+  constexpr int NL = 16 / VW;         // vector loads per lane and step
+  typedef typename Vec16<TA>::type VA;
+  typedef TB VB __attribute__((ext_vector_type(VW)));
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const int c0 = tile * 16;
+  if (chunk >= a.chunks || c0 >= m) return;
+  __shared__ f64x4 red[3][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const bool cok = c0 + i < m, bok = i < nb;
+  const TA* ap = (const TA*)a.A + (int64_t)(cok ? c0 + i : c0) * a.lda;
+  const TB* bp = (const TB*)a.B + (int64_t)(bok ? i : 0) * a.ldb;
+  const int64_t r0 = chunk * (int64_t)(256 * S) + (int64_t)wid * (64 * S);
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  double av[2][16], bv[2][16];
+  // loads of step s into buffer u: element 2 l + h... (VW l + h) is row
+  // rb + 4 VW l + VW q + h
+  auto load = [&](int s, int u) {
+    const int64_t rb = r0 + 64 * s;
+    if (rb + 64 <= d) {
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const int64_t r = rb + 4 * VW * l + VW * q;
+        const VA x = *(const VA*)(ap + r);
+#pragma unroll
+        for (int h = 0; h < VW; ++h) av[u][VW * l + h] = cok ? (double)x[h] : 0.0;
+      }
+      // only the lanes of B's nb columns load (the others hold zeros)
+      if (bok) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const int64_t r = rb + 4 * VW * l + VW * q;
+          const VB y = *(const VB*)(bp + r);
+#pragma unroll
+          for (int h = 0; h < VW; ++h) bv[u][VW * l + h] = (double)y[h];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) bv[u][e] = 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+#pragma unroll
+        for (int h = 0; h < VW; ++h) {
+          const int64_t r = rb + 4 * VW * l + VW * q + h;
+          const bool ok = r < d;
+          const double x = (double)ap[ok ? r : 0];
+          const double y = (double)bp[ok ? r : 0];
+          av[u][VW * l + h] = (cok && ok) ? x : 0.0;
+          bv[u][VW * l + h] = (bok && ok) ? y : 0.0;
+        }
+    }
+  };
+  if (r0 < d) load(0, 0);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    if (r0 + 64 * s >= d) break;
+    if (s + 1 < S && r0 + 64 * (s + 1) < d) load(s + 1, (s + 1) & 1);
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s & 1][e], bv[s & 1][e], acc, 0, 0, 0);
+  }
+  if (wid > 0) red[wid - 1][lane] = acc;
+  __syncthreads();
+  if (wid == 0) {
+    // accumulator layout: lane l, element v holds row 4 v + l / 16, column l % 16
+    f64x4 t = acc;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) t += red[w][lane];
+    const int jj = lane & 15, ib = lane >> 4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ii = 4 * v + ib;
+      if (c0 + ii < m && jj < nb)
+        a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + jj] =
+            (a.ascale != nullptr) ? t[v] * a.ascale[c0 + ii] : t[v];
+    }
+  }
+}
+
+// tn for a float64 A and B (nb <= 8) staged through LDS: per slab of 256
+// rows the workgroup loads its 16 columns of A and the nb columns of B with
+// whole-wave 1 KB loads (64 lanes x 16 bytes down one column), stores them
+// column-major in LDS (column stride TL_S doubles = 2 (mod 32), so the 16
+// lanes of an MFMA fragment hit distinct banks), and each wave multiplies 64
+// of the slab's rows on the matrix cores; the next slab is loaded into
+// registers while the current one is multiplied.  Same partial layout and
+// chunking (256 S rows) as tn_body.
+constexpr int TL_S = 258;
+template <int S>
+__device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int tile) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const int c0 = tile * 16;
+  if (chunk >= a.chunks || c0 >= m) return;
+  __shared__ __attribute__((aligned(32))) double As[16 * TL_S];
+  __shared__ __attribute__((aligned(16))) double Bs[8 * TL_S];
+  typedef const __attribute__((address_space(1))) d2* G2;
+  typedef const __attribute__((address_space(1))) double* G1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
+  const double* A = (const double*)a.A;
+  const double* B = (const double*)a.B;
+  const int64_t R0 = chunk * (int64_t)(256 * S);
+  // this wave loads A columns c0 + wid + 4 u (u < 4) and B columns 2 wid, 2 wid + 1,
+  // rows 2 lane + 128 h of the slab (h < 2); columns past m (nb) read a valid
+  // column and are zeroed by a select, so no load sits behind a branch
+  d2 ra[4][2], rb[2][2];
+  const double* acol[4];
+  bool aok[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = c0 + wid + 4 * u;
+    aok[u] = c < m;
+    acol[u] = A + (int64_t)(aok[u] ? c : c0) * a.lda;
+  }
+  const double* bcol[2];
+  bool bok2[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = 2 * wid + u;
+    bok2[u] = j < nb;
+    bcol[u] = B + (int64_t)(bok2[u] ? j : 0) * a.ldb;
+  }
+  auto load = [&](int s) {
+    const int64_t r0 = R0 + 256 * s;
+    const d2 zero = {0.0, 0.0};
+    if (r0 + 256 <= d) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          ra[u][h] = *(G2)(acol[u] + r0 + 2 * lane + 128 * h);
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          rb[u][h] = *(G2)(bcol[u] + r0 + 2 * lane + 128 * h);
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t r = r0 + 2 * lane + 128 * h;
+          d2 v = zero;
+          if (r < d) v[0] = ((G1)acol[u])[r];
+          if (r + 1 < d) v[1] = ((G1)acol[u])[r + 1];
+          ra[u][h] = v;
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t r = r0 + 2 * lane + 128 * h;
+          d2 v = zero;
+          if (r < d) v[0] = ((G1)bcol[u])[r];
+          if (r + 1 < d) v[1] = ((G1)bcol[u])[r + 1];
+          rb[u][h] = v;
+        }
+    }
+  };
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int i = lane & 15, q = lane >> 4;
+  int ns = 0;  // slabs of this chunk that hold rows < d
+  while (ns < S && R0 + 256 * ns < d) ++ns;
+  if (ns > 0) load(0);
+  for (int s = 0; s < ns; ++s) {
+    __syncthreads();  // the previous slab has been read
+    // (columns past m or nb become zeros here, when their loads have landed)
+    const d2 zero = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        *(d2*)(As + (wid + 4 * u) * TL_S + 2 * lane + 128 * h) = aok[u] ? ra[u][h] : zero;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        *(d2*)(Bs + (2 * wid + u) * TL_S + 2 * lane + 128 * h) = bok2[u] ? rb[u][h] : zero;
+    __syncthreads();
+    if (s + 1 < ns) load(s + 1);
+    const double* ac = As + i * TL_S + 64 * wid + q;
+    const double* bc = Bs + (i < 8 ? i : 0) * TL_S + 64 * wid + q;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const double x = ac[4 * e];
+      const double y = (i < nb) ? bc[4 * e] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+    }
+  }
+  // the 4 waves' sums (each over its quarter of every slab) meet in LDS
+  __syncthreads();
+  f64x4* red = (f64x4*)As;
+  if (wid > 0) red[(wid - 1) * 64 + lane] = acc;
+  __syncthreads();
+  if (wid == 0) {
+    f64x4 t = acc;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) t += red[w * 64 + lane];
+    const int jj = lane & 15, ib = lane >> 4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ii = 4 * v + ib;
+      if (c0 + ii < m && jj < nb)
+        a.part[(chunk * m + (c0 + ii)) * (int64_t)nb + jj] =
+            (a.ascale != nullptr) ? t[v] * a.ascale[c0 + ii] : t[v];
+    }
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void tn_lds_kernel(const TnArgs* __restrict__ arr, TnArgs one) {
+  const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  tn_lds_body<S>(a, blockIdx.x, blockIdx.y);
+}
+
+template <typename TA, typename TB, int S>
+__global__ __launch_bounds__(256) void tn_stream_kernel(const TnArgs* __restrict__ arr,
+                                                        TnArgs one) {
+  const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  tn_stream_body<TA, TB, S>(a, blockIdx.x, blockIdx.y);
 }
 
 // Sum of the chunk partials, fixed order: wave w adds chunks w, w+4, ... of
@@ -307,6 +557,139 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
   const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
   nn_body<TA, TV, TO, ACC, R, BATCH>(a, blockIdx.x, blockIdx.y);
+}
+
+// Streaming variant of nn for a long A (float64 or float32) with 16-byte
+// aligned columns and at most 8 output columns per blockIdx.y group: a
+// workgroup owns 32 VW rows (VW = 16 / sizeof(TA): each lane reads VW
+// consecutive rows of a column with one 16-byte load, so a wave instruction
+// moves 1 KB of one column), its 4 waves take the columns j = w mod 4.  Z is
+// staged in LDS in tiles of NS_ZT rows; each wave keeps two batches of NS_B
+// column loads in flight (the next batch is issued before the current one is
+// multiplied).  The 4 waves' sums meet in LDS in a fixed order.
+// With kcols > 0 the columns are split into groups of kcols (blockIdx.y =
+// group) and every group writes its partial product, row-major, to
+// Out + group * d * nb (ldo = nb, no V term): a fixed-order reduction over
+// the groups finishes it.
+constexpr int NS_ZT = 1024;
+constexpr int NS_B = 8;
+
+// Columns [t0, t0 + tn) of A times the staged Z tile, accumulated into acc:
+// wave w takes the columns t0 + w + 4 u, NS_B loads per batch issued before
+// the batch's products.  FULL: every row of the workgroup is < d (plain
+// vector loads); else rows >= d read as zero.
+template <typename TA, bool FULL>
+__device__ __forceinline__ void nn_stream_tile(const TA* __restrict__ ar, int64_t lda, int64_t row0,
+                                               int64_t d, int t0, int tn, int w,
+                                               const double* __restrict__ zs,
+                                               double (&acc)[Vec16<TA>::VW][NN_NB]) {
+  constexpr int VW = Vec16<TA>::VW;
+  typedef typename Vec16<TA>::type VA;
+  typedef const __attribute__((address_space(1))) VA* GVA;
+  typedef const __attribute__((address_space(1))) TA* GTA;
+  const int nloc = (tn - w + 3) / 4;  // columns of this wave in the tile (uniform)
+  for (int c = 0; c < nloc; c += NS_B) {
+    // loads of the batch first (columns past the wave's last are clamped to
+    // its first and weighted by zero), then the products
+    VA raw[NS_B];
+#pragma unroll
+    for (int u = 0; u < NS_B; ++u) {
+      const int cc = (c + u < nloc) ? c + u : 0;
+      const TA* colp = ar + (int64_t)(t0 + w + 4 * cc) * lda;
+      if constexpr (FULL) {
+        raw[u] = *(GVA)colp;
+      } else {
+#pragma unroll
+        for (int h = 0; h < VW; ++h) raw[u][h] = (row0 + h < d) ? ((GTA)colp)[h] : (TA)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NS_B; ++u) {
+      const bool live = c + u < nloc;
+      const double* zr = zs + (w + 4 * (live ? c + u : 0)) * NN_NB;
+      const double f = live ? 1.0 : 0.0;
+#pragma unroll
+      for (int h = 0; h < VW; ++h) {
+        const double x = (double)raw[u][h] * f;
+#pragma unroll
+        for (int j = 0; j < NN_NB; ++j) acc[h][j] += x * zr[j];
+      }
+    }
+  }
+}
+
+template <typename TA, typename TV, typename TO>
+__device__ __forceinline__ void nn_stream_body(const NnArgs& a, int64_t bx, int by) {
+  constexpr int VW = Vec16<TA>::VW;
+  constexpr int R = 64 * VW;  // rows per workgroup
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const bool split = a.kcols > 0;
+  const int k0 = split ? by * (int)a.kcols : 0;
+  const int k1 = split ? min(m, k0 + (int)a.kcols) : m;
+  if (bx * R >= d || k0 >= k1) return;
+  __shared__ double zs[NS_ZT * NN_NB];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
+  const int64_t row0 = bx * R + (int64_t)lane * VW;  // first of this lane's VW rows
+  const bool full = bx * R + R <= d;                  // every row of the workgroup < d
+  const TA* ar = (const TA*)a.A + (row0 < d ? row0 : 0);
+  double acc[VW][NN_NB];
+#pragma unroll
+  for (int h = 0; h < VW; ++h)
+#pragma unroll
+    for (int j = 0; j < NN_NB; ++j) acc[h][j] = 0.0;
+  for (int t0 = k0; t0 < k1; t0 += NS_ZT) {
+    const int tn = (k1 - t0 < NS_ZT) ? k1 - t0 : NS_ZT;
+    __syncthreads();
+    for (int e = tid; e < tn * NN_NB; e += 256) {
+      const int i = e / NN_NB, j = e - i * NN_NB;
+      double z = (j < nb) ? a.Z[(int64_t)(t0 + i) * a.ldz + j] : 0.0;
+      if (a.ascale != nullptr) z *= a.ascale[t0 + i];
+      zs[e] = z;
+    }
+    __syncthreads();
+    if (full)
+      nn_stream_tile<TA, true>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
+    else
+      nn_stream_tile<TA, false>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
+  }
+  // the 4 waves' sums meet in LDS (zs reused: 4 x R x 8 doubles <= its size)
+  static_assert(4 * R * NN_NB <= NS_ZT * NN_NB, "reduction buffer must fit in zs");
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < VW; ++h)
+#pragma unroll
+    for (int j = 0; j < NN_NB; ++j) zs[(w * R + lane * VW + h) * NN_NB + j] = acc[h][j];
+  __syncthreads();
+  const double alpha = split ? 0.0 : ((a.alpha_p != nullptr) ? *a.alpha_p : a.alpha);
+  const TV* V = (const TV*)a.V;
+  TO* Out = (TO*)a.Out;
+  if (split) Out += (int64_t)by * d * nb;
+  // output element e = tid + 256 q: row e % R of the workgroup, column e / R
+  constexpr int NO = R * NN_NB / 256;
+#pragma unroll
+  for (int qq = 0; qq < NO; ++qq) {
+    const int e = tid + 256 * qq;
+    const int rr = e % R, j = e / R;
+    const int64_t row = bx * R + rr;
+    if (row >= d || j >= nb) continue;
+    double o = ((zs[(0 * R + rr) * NN_NB + j] + zs[(1 * R + rr) * NN_NB + j]) +
+                zs[(2 * R + rr) * NN_NB + j]) + zs[(3 * R + rr) * NN_NB + j];
+    if (alpha != 0.0 && V != nullptr) o += alpha * to_f64<TV>(V[row + (int64_t)j * a.ldv]);
+    if (!split && a.mask != nullptr && a.mask[j] != 0)
+      o = masked_gauss(a.seed, (int64_t)j * d + row);
+    const int64_t oi = (split || a.out_row) ? row * (split ? nb : a.ldo) + j
+                                            : row + (int64_t)j * a.ldo;
+    Out[oi] = from_f64<TO>(o);
+  }
+}
+
+template <typename TA, typename TV, typename TO>
+__global__ __launch_bounds__(256) void nn_stream_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
+  const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  nn_stream_body<TA, TV, TO>(a, blockIdx.x, blockIdx.y);
 }
 
 // nn for wide outputs (nb > 8): NNW_NB output columns per workgroup, so that
@@ -611,12 +994,14 @@ __global__ __launch_bounds__(256) void nn_narrow_kernel(const NnArgs* __restrict
 }
 
 // 64 S rows per wave, 4 waves per workgroup: the tuned value for this
-// shape class when there is one, else S = 4 when that still gives 1024
-// workgroups, else 2, else 1 (chosen from the largest entry).
+// shape class when there is one, else S = 8 when that still gives 4096
+// workgroups (long factors: fewer partial sums), else S = 4 when that still
+// gives 1024 workgroups, else 2, else 1 (chosen from the largest entry).
 int tn_steps(int64_t d, int64_t m) {
   const int tuned = tune_get(TuneKind::TnSteps, d, m, 0);
-  if (tuned == 1 || tuned == 2 || tuned == 4) return tuned;
+  if (tuned == 1 || tuned == 2 || tuned == 4 || tuned == 8) return tuned;
   const int64_t tiles = (m + 15) / 16;
+  if (((d + 2047) / 2048) * tiles >= 4096) return 8;
   for (int S : {4, 2}) {
     const int64_t chunks = (d + 256 * S - 1) / (256 * S);
     if (chunks * tiles >= 1024) return S;
@@ -643,6 +1028,45 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
   if (cmax == 0) return hipSuccess;
   const TnArgs one = (count == 1) ? host[0] : TnArgs{};
   const TnArgs* arr = (count == 1) ? nullptr : dev;
+  if constexpr (sizeof(TA) >= 4) {
+    // narrow B, 16-byte aligned columns of A and VW-element aligned columns
+    // of B: the streaming kernel with vector loads
+    constexpr int VW = 16 / (int)sizeof(TA);
+    bool vec = zmax == 1;
+    for (int p = 0; p < count && vec; ++p) {
+      const TnArgs& a = host[p];
+      vec = ((a.lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)a.A % 16 == 0) &&
+            (a.ldb % VW == 0) && ((uintptr_t)a.B % (VW * sizeof(TB)) == 0);
+    }
+    if (vec) {
+      dim3 g((unsigned)cmax, (unsigned)ymax, (unsigned)count);
+      // EDA_TN_DIRECT=1 selects the direct-load kernel (for comparisons)
+      static const bool direct = std::getenv("EDA_TN_DIRECT") != nullptr;
+      bool lds = std::is_same<TA, double>::value && std::is_same<TB, double>::value && !direct;
+      for (int p = 0; p < count && lds; ++p)
+        lds = host[p].nb <= 8 && host[p].ldb % 2 == 0 && ((uintptr_t)host[p].B % 16) == 0;
+      if (lds) {
+        if (S == 8)
+          hipLaunchKernelGGL(tn_lds_kernel<8>, g, dim3(256), 0, s, arr, one);
+        else if (S == 4)
+          hipLaunchKernelGGL(tn_lds_kernel<4>, g, dim3(256), 0, s, arr, one);
+        else if (S == 2)
+          hipLaunchKernelGGL(tn_lds_kernel<2>, g, dim3(256), 0, s, arr, one);
+        else
+          hipLaunchKernelGGL(tn_lds_kernel<1>, g, dim3(256), 0, s, arr, one);
+        return hipGetLastError();
+      }
+      if (S == 8)
+        hipLaunchKernelGGL((tn_stream_kernel<TA, TB, 8>), g, dim3(256), 0, s, arr, one);
+      else if (S == 4)
+        hipLaunchKernelGGL((tn_stream_kernel<TA, TB, 4>), g, dim3(256), 0, s, arr, one);
+      else if (S == 2)
+        hipLaunchKernelGGL((tn_stream_kernel<TA, TB, 2>), g, dim3(256), 0, s, arr, one);
+      else
+        hipLaunchKernelGGL((tn_stream_kernel<TA, TB, 1>), g, dim3(256), 0, s, arr, one);
+      return hipGetLastError();
+    }
+  }
   // column tiles per workgroup: doubled while the grid keeps 1024 workgroups
   // (wide A: B is then read once per CT tiles instead of once per tile)
   int CT = 1;
@@ -662,7 +1086,9 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
 #define TN_GOW(S_) \
   hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, S_, 1, 3>), g, dim3(256), 0, s, arr, one, (int)yg)
   if (ZT == 3) {
-    if (S == 4 && CT == 2)
+    if (S == 8)
+      TN_GOW(8);
+    else if (S == 4 && CT == 2)
       hipLaunchKernelGGL((tn_mfma_kernel<TA, TB, 4, 2, 3>), g, dim3(256), 0, s, arr, one, (int)yg);
     else if (S == 4)
       TN_GOW(4);
@@ -670,6 +1096,8 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
       TN_GOW(2);
     else
       TN_GOW(1);
+  } else if (S == 8) {
+    TN_GO(8, 1);
   } else if (S == 4) {
     if (CT == 8)
       TN_GO(4, 8);
@@ -710,6 +1138,29 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
   if (dmax == 0) return hipSuccess;
   const NnArgs one = (count == 1) ? host[0] : NnArgs{};
   const NnArgs* arr = (count == 1) ? nullptr : dev;
+  if constexpr (sizeof(TA) >= 4) {
+    // long A with 16-byte aligned columns and at most 8 output columns: the
+    // streaming kernel, when it still gets 256 workgroups (or the launch is
+    // a column-split one, which only it implements)
+    constexpr int R = 64 * Vec16<TA>::VW;
+    bool split = false, stream = nbmax <= NN_NB;
+    for (int p = 0; p < count && stream; ++p) {
+      const NnArgs& a = host[p];
+      split = split || a.kcols > 0;
+      stream = ((a.lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)a.A % 16 == 0) &&
+               a.Out != a.A;
+    }
+    if (split && (!stream || count != 1)) return hipErrorInvalidValue;
+    if (stream && (split || (dmax + R - 1) / R >= 256)) {
+      const int64_t groups = split ? (host[0].m + host[0].kcols - 1) / host[0].kcols : 1;
+      hipLaunchKernelGGL((nn_stream_kernel<TA, TV, TO>),
+                         dim3((unsigned)((dmax + R - 1) / R), (unsigned)groups, (unsigned)count),
+                         dim3(256), 0, s, arr, one);
+      return hipGetLastError();
+    }
+  }
+  for (int p = 0; p < count; ++p)
+    if (host[p].kcols > 0) return hipErrorInvalidValue;
   if constexpr (sizeof(TA) <= 2) {
     // narrow A with 8-row-aligned columns (the padded storage of P): 8 rows
     // per lane in one load
@@ -862,6 +1313,30 @@ hipError_t launch_nn_multi(int count, const NnArgs* host, const NnArgs* dev, DT 
   NN_CASE(FP8, F64, F64, fp8e4m3, double, double, double)
 #undef NN_CASE
   return hipErrorInvalidValue;
+}
+
+int64_t nn_split_groups(int64_t m) {
+  // 128-row workgroups; column groups of at least 64 columns, as many as
+  // give about 512 workgroups
+  const int64_t rb = (m + 127) / 128;
+  int64_t g = (512 + rb - 1) / rb;
+  g = std::max<int64_t>(1, std::min(g, (m + 63) / 64));
+  const int64_t kc = (m + g - 1) / g;
+  return (m + kc - 1) / kc;
+}
+
+hipError_t launch_nn_split(int64_t m, int64_t nb, const double* C, int64_t ldc, const double* Y,
+                           int64_t ldy, double* part, double* Z, int64_t ldz, hipStream_t s) {
+  if (m <= 0 || nb <= 0) return hipSuccess;
+  if (nb > NN_NB || (ldc * 8) % 16 != 0 || (uintptr_t)C % 16 != 0) return hipErrorInvalidValue;
+  const int64_t groups = nn_split_groups(m);
+  const int64_t kc = (m + groups - 1) / groups;
+  NnArgs a{m, m, nb, ldc, ldy, 0, nb, C, Y, 0.0, nullptr, part, 1, nullptr, nullptr, nullptr,
+           nullptr, 0};
+  a.kcols = kc;
+  hipError_t e = nn_launch_t<double, double, double, double>(1, &a, nullptr, s);
+  if (e != hipSuccess) return e;
+  return launch_reduce_partials(groups, m, nb, part, 0.0, 0.0, nullptr, 0, 1.0, Z, ldz, nullptr, s);
 }
 
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,
