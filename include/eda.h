@@ -183,6 +183,21 @@ eda_status eda_opmv(eda_handle h, eda_form form, int64_t b,
                     const void* V, int64_t ldv, void* Out, int64_t ldo, eda_dtype vdtype,
                     double* log_scale);
 
+/* eda_opmv without any device allocation, for callers that cannot allocate
+ * (work under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and stream ordering as eda_opmv, the
+ * same launches in the same order (identical bits).  The product's scratch
+ * (partial sums, P^T V and the core product) is a static 32 MiB device
+ * array per device, shared by every call on that device: calls that overlap
+ * on one device race.  EDA_ERR_ARG when a product needs more scratch than
+ * that (8 (n + k) b (c + g + 2) bytes, c the row chunks of P^T V, about
+ * d / 2048 for long factors, g <= 33 the column groups of the core product:
+ * with b = 8 and n + k = 2048 up to d of about 450 000); EDA_ERR_STATE for
+ * the Arnoldi form before its core exists (eda_opmv with EDA_FORM_ARNOLDI_A
+ * builds it). */
+eda_status eda_opmv_noalloc(eda_handle h, eda_form form, int64_t b, const void* V, int64_t ldv,
+                            void* Out, int64_t ldo, eda_dtype vdtype, double* log_scale);
+
 /* Algorithm 3: t dominant eigenpairs of eq. (1.7).
  * ritz:     host out [t], lambda_i in decreasing order (+inf if > DBL_MAX).
  * ritz_log: host out [t], log lambda_i.

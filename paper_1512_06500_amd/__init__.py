@@ -36,7 +36,7 @@ _DTYPES = {"f64": EDA_F64, "f32": EDA_F32, "bf16": EDA_BF16, "fp8": EDA_FP8_E4M3
 EXPORTED_SYMBOLS = [
     "eda_create", "eda_destroy", "eda_strerror", "eda_last_error", "eda_scatter_factors",
     "eda_prepare", "eda_expmv", "eda_opmv", "eda_solve", "eda_solve_direct", "eda_solve_batched",
-    "eda_gram", "eda_factor_codes",
+    "eda_gram", "eda_factor_codes", "eda_opmv_noalloc",
     "eda_syev", "eda_autotune", "eda_nn_classify",
 ]
 
@@ -135,6 +135,9 @@ def load_library():
     L.eda_gram.restype = ctypes.c_int
     L.eda_factor_codes.argtypes = [vp, vp, i64, vp]
     L.eda_factor_codes.restype = ctypes.c_int
+    L.eda_opmv_noalloc.argtypes = [vp, ctypes.c_int, i64, vp, i64, vp, i64, ctypes.c_int,
+                                   ctypes.POINTER(dbl)]
+    L.eda_opmv_noalloc.restype = ctypes.c_int
     L.eda_syev.argtypes = [vp, i64, vp, i64, vp, vp, i64]
     L.eda_syev.restype = ctypes.c_int
     L.eda_autotune.argtypes = [vp, i64, i64, i32, ctypes.c_int, ctypes.POINTER(i32),
@@ -275,6 +278,19 @@ class Handle:
         self._check(self.lib.eda_opmv(self._h, f, b, V.data_ptr(), _ld(V), out.data_ptr(),
                                       _ld(out), _DTYPES[vdtype], ctypes.byref(ls)))
         return out, ls.value
+
+    def opmv_noalloc(self, form: str, V, out, vdtype: str = "f64"):
+        """eda_opmv_noalloc: the product of opmv with the library's static
+        scratch instead of allocated workspaces; `out` must be given.
+        Returns s (Out = e^{-s} M V or e^{-s} A V)."""
+        V = self._vblock(V, vdtype)
+        d, b = V.shape
+        ls = ctypes.c_double()
+        f = EDA_FORM_LANCZOS_M if form == "M" else EDA_FORM_ARNOLDI_A
+        self._check(self.lib.eda_opmv_noalloc(self._h, f, b, V.data_ptr(), _ld(V),
+                                              out.data_ptr(), _ld(out), _DTYPES[vdtype],
+                                              ctypes.byref(ls)))
+        return ls.value
 
     def solve(self, t: int, tol: float, block: int = 8, max_basis: int = 0, max_iter: int = 0,
               seed: int = 0, start_block=None, check_every: int = 0, resmode: str = "rel",

@@ -122,7 +122,7 @@ eda_status expop_second(eda_handle h, bool master, int64_t c0, int64_t Nc, const
   // operand (split over column groups of C when it is large), then
   // Out = alpha V + P_c Z
   bool done = false;
-  if (Nc >= 1024 && b <= 8 && ldc % 2 == 0 && (uintptr_t)C % 16 == 0) {
+  if (core_split(Nc, b, C, ldc)) {
     STCHK(ensure(h, h->zpart, (size_t)nn_split_groups(Nc) * Nc * b * 8));
     HIPCHK(launch_nn_split(Nc, b, C, ldc, ysm, ldy, h->zpart.d(), h->Zsm.d(), b, h->stream));
     done = true;
@@ -302,7 +302,7 @@ eda_status ensure_arnoldi_core(eda_handle h) {
 
 }  // namespace eda
 
-namespace {
+namespace eda {
 
 eda_status validate_block(eda_handle h, int64_t b, const void* V, int64_t ldv, const void* Out,
                           int64_t ldo, eda_dtype vdtype) {
@@ -320,7 +320,7 @@ eda_status validate_block(eda_handle h, int64_t b, const void* V, int64_t ldv, c
   return EDA_OK;
 }
 
-}  // namespace
+}  // namespace eda
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -367,6 +367,9 @@ eda_status eda_create(eda_handle* out, void* hip_stream) {
   }
   h->device = dev;
   if (std::getenv("EDA_SYEV_TIMERS") != nullptr) syev_timing_enable(true);
+  // device address of the allocation-free entry point's scratch array on
+  // this device (a failure is reported by that entry point, not here)
+  (void)noalloc_init_device(dev);
   return EDA_OK;
 }
 

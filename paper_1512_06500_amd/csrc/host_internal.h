@@ -161,6 +161,18 @@ eda_status autotune_shapes(eda_handle h, int64_t d, int64_t N, int64_t b, eda_dt
 eda_status solve_aform(eda_handle h, int32_t t, double tol, const eda_solve_opts& o,
                        double* ritz, double* ritz_log, double* X, int64_t ldx, double* resid,
                        eda_info* info);
+// Checks of an operand block V and output block Out of b columns (eda_expmv,
+// eda_opmv): shapes, types, leading dimensions, no overlap.
+eda_status validate_block(eda_handle h, int64_t b, const void* V, int64_t ldv, const void* Out,
+                          int64_t ldo, eda_dtype vdtype);
+// Whether the core product Z = C Y of a product over Nc columns is split
+// over column groups of C (launch_nn_split) rather than one streaming launch.
+inline bool core_split(int64_t Nc, int64_t b, const double* C, int64_t ldc) {
+  return Nc >= 1024 && b <= 8 && ldc % 2 == 0 && ((uintptr_t)C % 16) == 0;
+}
+// Looks up, once per device, the device address of the scratch array of
+// eda_opmv_noalloc (eda_noalloc.hip); the device must be current.
+hipError_t noalloc_init_device(int device);
 // Low-rank exponential apply on columns [c0, c0+Nc) of P (the storage copy,
 // or the float64 master when `master`):  Out = alpha V + P_c C P_c^T V.
 eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double* C,
