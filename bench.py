@@ -1,12 +1,12 @@
 """Benchmark: end-to-end EDA solves on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extra]
 
-Workload (the configuration the metric is quoted on): d = 10304 (112 x 92
-images), k = 40 classes x n_j = 5 samples (n = 200), t = 39 dominant
-eigenpairs, block width 8, tol 1e-8, float64 throughout.  Synthetic samples
-(unit-norm columns, 128-dim class signal, 5% noise) stand in for the ORL
-face images, which are not available.
+Workload (the largest configuration that fits one GPU): d = 65536 (256 x 256
+images), k = 100 classes x n_j = 20 samples (n = 2000), t = 99 dominant
+eigenpairs, block width 8, tol 1e-6 (per-pair floors u lam_1 / lam_i),
+float64 throughout.  Synthetic samples (unit-norm columns, 512-dim class
+signal, 5% noise) stand in for face images, which are not available.
 
 One step = the whole hot path on one batch of samples already resident in
 HBM: scatter factors -> factor ingest + Gram + small eigensolves + cores ->
@@ -14,31 +14,29 @@ block Lanczos with Rayleigh-Ritz -> back-transform + orthonormalisation.
 `value` is solves per second over the timed steps.
 
 `roofline` covers the exp-op, the block product e^{-s} M V (b = 8) with two
-streaming passes over P = [H_W H_B] (d x 240 float64): its algorithmic
-bytes 2 d N 8 + 3 d b 8 per product divided by its average duration,
-measured with HIP events on the library's stream around every product
-inside the timed solves (four launches: P^T V on the matrix cores, the
-chunk sum, the core product, alpha V + P Z).  Peak: MI355X HBM3E, 8 TB/s.
+streaming passes over P = [H_W H_B] (d x 2100 float64, 1.1 GB, far larger
+than the 256 MB Infinity Cache): its algorithmic bytes 2 d N 8 + 3 d b 8 per
+product divided by its average duration, measured with HIP events on the
+library's stream around every product inside the timed solves (P^T V on the
+matrix cores, the chunk sum, the core product and its column-group sum,
+alpha V + P Z).  Peak: MI355X HBM3E, 8 TB/s.  `traffic` is the
+counter-measured HBM bytes per product from the committed rocprofv3 summary
+(while the streaming kernels are unchanged since it was taken).
 
 `cpu_baseline` times the FP64 CPU oracle (exact (n+k)-dimensional reduction
-of the pencil, NumPy/SciPy on the host's cores) on the same workload.
+of the pencil, NumPy/SciPy) on one full solve of the same workload with all
+host threads; `cpu_baseline_1thread` the same with one thread.
 
-`mixed_vs_f64` (second half of the metric): solves/s of the d = 32256,
-k = 38, n = 1216, t = 37 workload at tol 1e-6, float64 end to end against
-bfloat16 factors + float32 basis + float64 refinement (prepare + solve each).
+Extras (--no-extra skips them): the C5 step with FP8 storage + float32 basis
++ float64 refinement against the float64 step (preparation included); the
+d = 32256 workload in float64, bfloat16 and FP8 storage; the ORL-shaped
+d = 10304 workload (its 19.8 MB factor sits in the Infinity Cache, so its
+"HBM" bandwidth is effective cache bandwidth); the Lanczos form, Arnoldi
+form and direct solve side by side; the Section 3.3 tolerance sweep; the
+64-problem batch against the float64 and float32 one-by-one loops.
 
-`nn_tol_sweep`: Section 3.3 on a split of the headline workload (200
-training, 200 testing samples): 1-NN accuracy, angle to the tol-1e-10
-subspace and the Theorem 3.7 check for tol 1e-2 ... 1e-10, and the time of
-one eda_nn_classify call.
-
-`batched`: 64 independent problems of uneven shape (d in {1024, 4096,
-10304}, k in [10, 68], n_j in [2, 20], float32 factors, tol 1e-6) solved by
-one eda_solve_batched call, problems/s, against the same problems solved one
-after another.
-
-`--profile-op K`: only K exponential products (b = 8) on the headline
-workload plus one 256 MiB copy, for hardware-counter runs.
+`--profile-op K [--workload C5|C2]`: only K exponential products (b = 8)
+plus one 1 GiB copy, for hardware-counter runs.
 """
 from __future__ import annotations
 
@@ -57,32 +55,40 @@ METRIC = "exp(S)·V HBM GB/s vs peak; EDA solves/s mixed vs FP64 at residual 1e-
 HBM_PEAK_GBPS = 8000.0
 
 
-def cpu_baseline(p, budget_s: float = 15.0) -> dict:
-    import oracle
+def _cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_info
-        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    reps, t0 = 0, time.perf_counter()
-    while True:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, threads=None) -> dict:
+    """One full solve by the oracle's exact reduction (scatter factors,
+    Householder QR of [H_W H_B], dense pencil eigenproblem) with `threads`
+    BLAS threads (None: all the host offers)."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    with threadpool_limits(threads):
+        used = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+        t0 = time.perf_counter()
         H_W, H_B = oracle.scatter_factors(p.X, p.counts)
         oracle.eda_reduced(H_W, H_B, p.t)
-        reps += 1
-        if time.perf_counter() - t0 > budget_s or reps >= 50:
-            break
-    el = time.perf_counter() - t0
-    return {"value": reps / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{reps} full solves of the same workload by the oracle's exact "
-                      f"(n+k)-dim reduction (scatter factors, Householder QR of [H_W H_B], "
-                      f"dense pencil eig), {el:.1f} s"}
+        el = time.perf_counter() - t0
+    return {"value": 1.0 / el, "unit": "solves/s", "cores": int(used), "kind": "oracle",
+            "sample": f"1 full solve of the same workload by the oracle's exact (n+k)-dim "
+                      f"reduction (scatter factors, Householder QR of [H_W H_B], dense pencil "
+                      f"eig), {el:.1f} s",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def counter_traffic():
     """HBM bytes per product from the committed counter summary, or None when
     the streaming kernels have changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "exp_op_c2_counters.md")
+    path = os.path.join(ROOT, "profiles", "exp_op_c5_counters.md")
     src = os.path.join(ROOT, "paper_1512_06500_amd", "csrc", "k_tsmm.hip")
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
@@ -96,14 +102,14 @@ def counter_traffic():
 
 
 def profile_op(torch, eda, h, Xd, counts, reps):
-    """K products e^{-s} M V (b = 8) and one 256 MiB device copy."""
+    """K products e^{-s} M V (b = 8) and one 1 GiB device copy."""
     H_W, H_B = h.scatter_factors(Xd, counts)
     h.prepare(H_W, H_B)
     V = torch.randn(8, Xd.shape[0], dtype=torch.float64, device="cuda").t()
     out = torch.empty_like(V.t()).t()
     for _ in range(reps):
         h.opmv("M", V, out=out)
-    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    src = torch.ones(128 << 20, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
@@ -151,55 +157,87 @@ def mixed_vs_f64(torch, eda, reps: int = 3) -> dict:
     return out
 
 
-def large_fp8_vs_f64(torch, eda, reps: int = 3) -> dict:
-    """The large FP8 workload (d = 65536, n = 2000, k = 100, t = 99, tol
-    1e-6): float64 solve against FP8 E4M3 storage with a float32 basis and
-    float64 refinement (solve phase only, preparation shared per storage),
-    with the exponential product's bandwidth for each storage type."""
-    import datagen
+def large_fp8_vs_f64(torch, eda, p, Xd, reps: int = 3) -> dict:
+    """The headline step (scatter -> prepare -> solve at d = 65536, n = 2000,
+    k = 100, t = 99, tol 1e-6) with FP8 E4M3 storage, a float32 Krylov basis
+    and float64 refinement, against the float64 step; preparation included.
+    Also the exponential product's bandwidth for each storage type (its
+    algorithmic bytes over the event-timed products inside the solves)."""
     from tests.golden.reader import read as read_golden
-    p = datagen.config("C5")
     g = read_golden("C5")
     h = eda.Handle()
-    H_W, H_B = h.scatter_factors(_upload(torch, p.X), p.counts.tolist())
-    N = p.n + p.k
+    counts = p.counts.tolist()
     out = {"workload": f"d={p.d}, k={p.k} x n_j={p.n // p.k} (n={p.n}), t={p.t}, block 8, "
-                       f"tol {p.tol:g}"}
+                       f"tol {p.tol:g}, prepare + solve"}
     for tag, storage, basis in (("f64", "f64", "f64"), ("fp8", "fp8", "f32")):
-        h.prepare(H_W, H_B, storage=storage)
-        V = torch.randn(8, p.d, dtype=torch.float64, device="cuda").t()
-        o = torch.empty_like(V.t()).t()
-        for _ in range(3):
-            h.opmv("M", V, out=o)
+        def one():
+            H_W, H_B = h.scatter_factors(Xd, counts)
+            h.prepare(H_W, H_B, storage=storage)
+            return h.solve(p.t, p.tol, block=8, seed=p.seed, krylov_dtype=basis)
+        one()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(10):
-            h.opmv("M", V, out=o)
-        torch.cuda.synchronize()
-        op_s = (time.perf_counter() - t0) / 10
-        sp = {"f64": 8, "fp8": 1}[storage]
-        op_bytes = 2.0 * p.d * N * sp + 3.0 * p.d * 8 * 8
-        r = h.solve(p.t, p.tol, block=8, seed=p.seed, krylov_dtype=basis)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        infos = []
         for _ in range(reps):
-            r = h.solve(p.t, p.tol, block=8, seed=p.seed, krylov_dtype=basis)
+            r = one()
+            infos.append(r.info)
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / reps
         lam_err = np.abs(np.array(r.ritz) - g["lam"]) / np.array(g["lam"])
+        op_calls = sum(i["op_calls"] for i in infos)
+        op_s = sum(i["t_op_ms"] for i in infos) / max(op_calls, 1) / 1e3
+        op_bytes = infos[-1]["op_bytes"]
         out[tag] = {"solves_per_s": 1.0 / el, "ms": 1e3 * el, "status": r.status,
                     "storage": storage, "basis": basis, "iters": r.info["iters"],
                     "refine_passes": r.info["refine_passes"],
+                    "prepare_ms": r.info["t_prepare_ms"],
                     "krylov_ms": r.info["t_krylov_ms"], "refine_ms": r.info["t_refine_ms"],
                     "resid_max": max(r.resid),
                     "lam_rel_err_max_over_floor": float(np.max(lam_err / np.maximum(
                         1e-6, g["pair_floor"]))),
                     "exp_op": {"us": op_s * 1e6, "algorithmic_bytes": op_bytes,
-                               "GB_per_s": op_bytes / op_s / 1e9,
-                               "frac_of_hbm_peak": op_bytes / op_s / 1e9 / HBM_PEAK_GBPS}}
+                               "GB_per_s": op_bytes / op_s / 1e9 if op_calls else None,
+                               "frac_of_hbm_peak": op_bytes / op_s / 1e9 / HBM_PEAK_GBPS
+                               if op_calls else None, "products": op_calls}}
     out["ratio_fp8_over_f64"] = out["fp8"]["solves_per_s"] / out["f64"]["solves_per_s"]
     h.close()
     return out
+
+
+def orl_mall_resident(torch, eda, reps: int = 20) -> dict:
+    """The ORL-shaped workload (d = 10304, n = 200, k = 40, t = 39, tol 1e-8,
+    float64): prepare + solve per second and its product bandwidth.  Its
+    19.8 MB factor stays in the 256 MB Infinity Cache between products, so
+    the bandwidth is effective cache bandwidth, not an HBM fraction."""
+    import datagen
+    p = datagen.config("C2")
+    h = eda.Handle()
+    Xd = _upload(torch, p.X)
+    counts = p.counts.tolist()
+
+    def one():
+        H_W, H_B = h.scatter_factors(Xd, counts)
+        h.prepare(H_W, H_B)
+        return h.solve(p.t, p.tol, block=8, seed=p.seed)
+    for _ in range(3):
+        one()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = one()
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    op_calls = sum(i["op_calls"] for i in infos)
+    op_s = sum(i["t_op_ms"] for i in infos) / op_calls / 1e3
+    h.close()
+    return {"workload": f"d={p.d}, k={p.k} x n_j=5 (n={p.n}), t={p.t}, block 8, tol {p.tol:g}, "
+                        "float64, prepare + solve",
+            "solves_per_s": 1.0 / el, "ms": 1e3 * el, "status": r.status,
+            "iters": r.info["iters"],
+            "exp_op": {"us": op_s * 1e6, "effective_GB_per_s": infos[-1]["op_bytes"] / op_s / 1e9,
+                       "note": "Infinity-Cache resident factor: effective, not HBM, bandwidth"}}
 
 
 def solve_variants(torch, eda, reps: int = 5) -> dict:
@@ -312,17 +350,22 @@ def batched(torch, eda, count: int = 64, reps: int = 2) -> dict:
                     "ok": int(sum(r.status == 0 for r in res)),
                     "max_iters": int(max(r.info["iters"] for r in res)),
                     "max_refine_passes": int(max(r.info["refine_passes"] for r in res))}
-    # the same problems one after another (float32 factors, float32 basis)
+    # the same problems one after another: float64 (the plain single-problem
+    # solve) and float32 factors with a float32 basis
     hs = eda.Handle()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i, (HW, HB, t, tol) in enumerate(probs):
-        hs.prepare(HW, HB, storage="f32")
-        hs.solve(t, tol, block=8, seed=4000 + i, krylov_dtype="f32")
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    out["one_by_one_f32"] = {"problems_per_s": count / el, "ms": 1e3 * el}
-    out["speedup_batched_over_one_by_one"] = out["f32"]["problems_per_s"] / (count / el)
+    for tag, storage, basis in (("f64", "f64", "f64"), ("f32", "f32", "f32")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, (HW, HB, t, tol) in enumerate(probs):
+            hs.prepare(HW, HB, storage=storage)
+            hs.solve(t, tol, block=8, seed=4000 + i, krylov_dtype=basis)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"one_by_one_{tag}"] = {"problems_per_s": count / el, "ms": 1e3 * el}
+    out["speedup_batched_f64_over_one_by_one_f64"] = (out["f64"]["problems_per_s"]
+                                                      / out["one_by_one_f64"]["problems_per_s"])
+    out["speedup_batched_f32_over_one_by_one_f64"] = (out["f32"]["problems_per_s"]
+                                                      / out["one_by_one_f64"]["problems_per_s"])
     hs.close()
     h.close()
     return out
@@ -335,8 +378,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the mixed-precision and batched measurements")
+                    help="skip the measurements beside the headline step")
     ap.add_argument("--profile-op", type=int, default=0)
+    ap.add_argument("--workload", default="C5", choices=["C5", "C2"],
+                    help="workload of --profile-op")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -348,9 +393,9 @@ def main():
     import paper_1512_06500_amd as eda
 
     torch.cuda.set_device(0)
-    p = datagen.config("C2")
+    p = datagen.config(args.workload if args.profile_op > 0 else "C5")
     b, tol = 8, p.tol
-    Xd = torch.from_numpy(np.ascontiguousarray(p.X.T)).cuda().t()
+    Xd = _upload(torch, p.X)
     counts = p.counts.tolist()
     h = eda.Handle()
 
@@ -382,8 +427,8 @@ def main():
     achieved = op_bytes / avg_op_s / 1e9
     # sanity against the stored oracle values (text file, no oracle import)
     from tests.golden.reader import read as read_golden
-    g = read_golden("C2")
-    lam_err = float(np.max(np.abs(np.array(res.ritz) - g["lam"]) / g["lam"]))
+    g = read_golden("C5")
+    lam_err = np.abs(np.array(res.ritz) - g["lam"]) / g["lam"]
 
     out = {
         "metric": METRIC,
@@ -398,33 +443,41 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "ORL-shaped EDA solve: d=10304, k=40 x n_j=5 (n=200), "
-                               "t=39, block 8, tol 1e-8, float64",
+        "config": {"workload": "large EDA solve: d=65536 (256x256), k=100 x n_j=20 (n=2000), "
+                               "t=99, block 8, tol 1e-6 (per-pair floors), float64, "
+                               "scatter -> prepare -> solve",
                    "d": p.d, "n": p.n, "k": p.k, "t": p.t, "block": b, "tol": tol,
                    "storage": "f64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": counter_traffic(),
-                     "kernel": "exp-op e^{-s} M V (b=8): tn_mfma + reduce + core nn + nn",
+                     "kernel": "exp-op e^{-s} M V (b=8) over the 1.1 GB factor: tn_lds + reduce "
+                               "+ split core product + reduce + nn_stream",
                      "bytes_per_launch": op_bytes, "avg_launch_us": avg_op_s * 1e6,
                      "launches": op_calls},
         "breakdown_ms": {
             "prepare": float(np.mean([i["t_prepare_ms"] for i in infos])),
             "krylov": float(np.mean([i["t_krylov_ms"] for i in infos])),
+            "refine_and_final": float(np.mean([i["t_refine_ms"] for i in infos])),
             "op_total": op_ms / args.steps,
         },
         "solve": {"iters": res.info["iters"], "restarts": res.info["restarts"],
-                  "resid_max": max(res.resid), "lam_max_rel_err_vs_stored_oracle": lam_err},
+                  "resid_max": max(res.resid),
+                  "lam_max_rel_err_vs_stored_oracle": float(lam_err.max()),
+                  "lam_rel_err_max_over_pair_floor": float(np.max(
+                      lam_err / np.maximum(1e-6, g["pair_floor"])))},
     }
     h.close()
     if not args.no_extra:
+        out["large_fp8_vs_f64"] = large_fp8_vs_f64(torch, eda, p, Xd)
+        out["orl_mall_resident"] = orl_mall_resident(torch, eda)
         out["mixed_vs_f64"] = mixed_vs_f64(torch, eda)
         out["solve_variants"] = solve_variants(torch, eda)
         out["nn_tol_sweep"] = nn_tol_sweep(torch, eda)
-        out["large_fp8_vs_f64"] = large_fp8_vs_f64(torch, eda)
         out["batched"] = batched(torch, eda)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
+        out["cpu_baseline_1thread"] = cpu_baseline(p, threads=1)
     print(json.dumps(out), flush=True)
 
 

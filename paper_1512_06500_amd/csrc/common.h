@@ -467,6 +467,13 @@ hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, in
 hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha,
                        const double* A, int64_t lda, const double* dk, const double* B,
                        int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s);
+// The same for an n x n product the caller knows to be symmetric (with
+// beta != 0, C symmetric too): only the lower triangle is computed, then
+// mirrored, so the result is exactly symmetric (large n; small n falls back
+// to launch_gemm).
+hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha, const double* A,
+                           int64_t lda, const double* dk, const double* B, int64_t ldb,
+                           double beta, double* C, int64_t ldc, hipStream_t s);
 // Gram partials: part[c][i][j] over lower-triangle tiles; finalised by launch_gram_reduce.
 int64_t gram_chunks(int64_t d, int64_t N);
 hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int64_t ldp,

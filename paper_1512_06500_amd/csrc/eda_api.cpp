@@ -177,20 +177,22 @@ eda_status poly_core_W(eda_handle h, double c, double* out) {
     a[j] = 1.0 / f;  // 1/(j+1)!
   }
   HIPCHK(launch_copy_block(n, n, sc, h->G.d(), N, false, X, n, s));
-  HIPCHK(launch_gemm(false, false, n, n, n, 1.0, X, n, nullptr, X, n, 0.0, A2, n, s));
-  HIPCHK(launch_gemm(false, false, n, n, n, 1.0, A2, n, nullptr, X, n, 0.0, A3, n, s));
-  HIPCHK(launch_gemm(false, false, n, n, n, 1.0, A2, n, nullptr, A2, n, 0.0, A4, n, s));
+  // every product below is of commuting symmetric polynomials in X, hence
+  // symmetric: only lower triangles are computed (and mirrored)
+  HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, X, n, nullptr, X, n, 0.0, A2, n, s));
+  HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, A2, n, nullptr, X, n, 0.0, A3, n, s));
+  HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, A2, n, nullptr, A2, n, 0.0, A4, n, s));
   HIPCHK(launch_lincomb(n, a[16], a[17], X, 0.0, nullptr, 0.0, nullptr, n, P, n, s));
   for (int kb = 3; kb >= 0; --kb) {
     HIPCHK(launch_lincomb(n, a[4 * kb], a[4 * kb + 1], X, a[4 * kb + 2], A2, a[4 * kb + 3], A3,
                           n, T, n, s));
-    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, A4, n, nullptr, P, n, 1.0, T, n, s));
+    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, A4, n, nullptr, P, n, 1.0, T, n, s));
     std::swap(P, T);
   }
   for (int i = 0; i < q; ++i) {
-    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, X, n, nullptr, P, n, 0.0, U, n, s));
+    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, X, n, nullptr, P, n, 0.0, U, n, s));
     HIPCHK(launch_copy_block(n, n, 1.0, P, n, false, T, n, s));
-    HIPCHK(launch_gemm(false, false, n, n, n, 0.5, P, n, nullptr, U, n, 1.0, T, n, s));
+    HIPCHK(launch_gemm_sym(false, false, n, n, 0.5, P, n, nullptr, U, n, 1.0, T, n, s));
     std::swap(P, T);
     HIPCHK(launch_copy_block(n, n, 2.0, X, n, false, X, n, s));
   }
@@ -225,7 +227,7 @@ eda_status build_core(eda_handle h, int which, double c, double shift, double* o
   const int64_t ldz = h->n;
   STCHK(ensure(h, h->fw, (size_t)(h->N + 8) * 8));
   HIPCHK(launch_core_weights(Nw, lam, c, shift, h->fw.d(), h->stream));
-  HIPCHK(launch_gemm(false, true, Nw, Nw, Nw, 1.0, Z, ldz, h->fw.d(), Z, ldz, 0.0, out, Nw,
+  HIPCHK(launch_gemm_sym(false, true, Nw, Nw, 1.0, Z, ldz, h->fw.d(), Z, ldz, 0.0, out, Nw,
                      h->stream));
   return EDA_OK;
 }
@@ -241,10 +243,10 @@ eda_status build_w_cores(eda_handle h) {
     STCHK(build_core(h, EDA_W, -1.0, 0.0, h->Gm.d()));
   } else {
     // exp(-S_W) = exp(-S_W/2)^2 gives G_m = 2 G_h + G_h (H_W^T H_W) G_h
-    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, h->G.d(), N, nullptr, h->Gh.d(), n, 0.0,
+    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, h->G.d(), N, nullptr, h->Gh.d(), n, 0.0,
                        h->CM.d(), n, h->stream));
     HIPCHK(launch_copy_block(n, n, 2.0, h->Gh.d(), n, false, h->Gm.d(), n, h->stream));
-    HIPCHK(launch_gemm(false, false, n, n, n, 1.0, h->Gh.d(), n, nullptr, h->CM.d(), n, 1.0,
+    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, h->Gh.d(), n, nullptr, h->CM.d(), n, 1.0,
                        h->Gm.d(), n, h->stream));
   }
   return EDA_OK;
@@ -268,7 +270,7 @@ eda_status build_composite_cores(eda_handle h) {
   HIPCHK(launch_gemm(false, false, n, k, k, 1.0, h->T1.d(), n, nullptr, h->GBs.d(), k, 0.0,
                      h->T2.d(), n, s));
   HIPCHK(launch_copy_block(n, n, h->alphaB, h->Gm.d(), n, false, CM, N, s));
-  HIPCHK(launch_gemm(false, true, n, n, k, 1.0, h->T2.d(), n, nullptr, h->T1.d(), n, 1.0, CM, N, s));
+  HIPCHK(launch_gemm_sym(false, true, n, k, 1.0, h->T2.d(), n, nullptr, h->T1.d(), n, 1.0, CM, N, s));
   HIPCHK(launch_copy_block(n, k, 1.0, h->T2.d(), n, false, CM + n * N, N, s));
   HIPCHK(launch_copy_block(k, n, 1.0, h->T2.d(), n, true, CM + n, N, s));
   HIPCHK(launch_copy_block(k, k, 1.0, h->GBs.d(), k, false, CM + n + n * N, N, s));

@@ -133,6 +133,11 @@ struct BigGemmArgs {
   int gram;
   int64_t kchunk;
   double* part;
+  // symmetric mode (M == N, the caller guarantees a symmetric result and,
+  // with beta != 0, a symmetric C): lower-triangle tiles only (blockIdx.x
+  // enumerates them), full K, every entry i >= j written to C(i, j) and
+  // C(j, i), so the result is exactly symmetric
+  int sym = 0;
 };
 
 // Loads of one BK slice of op(X) (rows: the T-edge tile index, k: the
@@ -199,20 +204,20 @@ __device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v], bool tra
 
 // T x T tile per workgroup; wave quadrants of (T/2) x (T/2) = QB x QB MFMA blocks.
 template <int T>
-__global__ __launch_bounds__(256) void big_gemm_kernel(BigGemmArgs a) {
+__global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
   constexpr int LS = BigStride<T>::v;
   constexpr int QB = T / 32;  // 16 x 16 blocks per quadrant edge
   constexpr int NP = T * BK / 512;
   __shared__ double As[BK][LS];
   __shared__ double Bs[BK][LS];
   int64_t ti, tj, kbeg, kend;
-  if (a.gram) {
+  if (a.gram || a.sym) {
     int64_t t = blockIdx.x;
     ti = 0;
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     tj = t - ti * (ti + 1) / 2;
-    kbeg = (int64_t)blockIdx.y * a.kchunk;
-    kend = min(a.K, kbeg + a.kchunk);
+    kbeg = a.gram ? (int64_t)blockIdx.y * a.kchunk : 0;
+    kend = a.gram ? min(a.K, kbeg + a.kchunk) : a.K;
   } else {
     ti = blockIdx.x;
     tj = blockIdx.y;
@@ -244,18 +249,26 @@ __global__ __launch_bounds__(256) void big_gemm_kernel(BigGemmArgs a) {
       big_load<T>(a.A, a.lda, a.ta != 0, i0, a.M, k0 + BK, kend, ra);
       big_load<T>(a.B, a.ldb, a.tb == 0, j0, a.N, k0 + BK, kend, rb);
     }
+    // fragments of step ks + 4 are read from LDS while step ks multiplies
+    double fa[2][QB], fb[2][QB];
+#pragma unroll
+    for (int x = 0; x < QB; ++x) fa[0][x] = As[lk][qi + 16 * x + li];
+#pragma unroll
+    for (int y = 0; y < QB; ++y) fb[0][y] = Bs[lk][qj + 16 * y + li];
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double fa[QB], fb[QB];
+      const int cb = (ks / 4) & 1;
+      if (ks + 4 < BK) {
 #pragma unroll
-      for (int x = 0; x < QB; ++x) fa[x] = As[ks + lk][qi + 16 * x + li];
+        for (int x = 0; x < QB; ++x) fa[cb ^ 1][x] = As[ks + 4 + lk][qi + 16 * x + li];
 #pragma unroll
-      for (int y = 0; y < QB; ++y) fb[y] = Bs[ks + lk][qj + 16 * y + li];
+        for (int y = 0; y < QB; ++y) fb[cb ^ 1][y] = Bs[ks + 4 + lk][qj + 16 * y + li];
+      }
 #pragma unroll
       for (int x = 0; x < QB; ++x)
 #pragma unroll
         for (int y = 0; y < QB; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[x], fb[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][x], fb[cb][y], acc[x][y], 0, 0, 0);
     }
   }
   // accumulator element v of lane l: row 4 v + l / 16, column l % 16 of the block
@@ -270,6 +283,12 @@ __global__ __launch_bounds__(256) void big_gemm_kernel(BigGemmArgs a) {
         if (gi >= a.M || gj >= a.N) continue;
         if (a.gram) {
           a.part[(int64_t)blockIdx.y * a.N * a.N + gi + gj * a.N] = acc[x][y][v];
+        } else if (a.sym) {
+          if (gi < gj) continue;
+          double* cp = a.C + gi + gj * a.ldc;
+          const double o = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * acc[x][y][v];
+          *cp = o;
+          a.C[gj + gi * a.ldc] = o;
         } else {
           double* cp = a.C + gi + gj * a.ldc;
           *cp = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * acc[x][y][v];
@@ -432,6 +451,21 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
 // The matrix-core Gram serves float64 factors with at least 256 columns
 // (enough tiles); the register-tiled kernel everything else.
 static bool gram_big(int64_t N, DT pdt) { return pdt == DT::F64 && N >= 256; }
+
+hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha, const double* A,
+                           int64_t lda, const double* dk, const double* B, int64_t ldb,
+                           double beta, double* C, int64_t ldc, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n >= 512 && k >= 64 && big_ok(A, lda) && big_ok(B, ldb)) {
+    BigGemmArgs a{n, n, k, lda, ldb, ldc, A, B, dk, C, alpha, beta, ta ? 1 : 0, tb ? 1 : 0,
+                  0, 0, nullptr};
+    a.sym = 1;
+    const int64_t T = (n + 63) / 64;
+    hipLaunchKernelGGL(big_gemm_kernel<64>, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  return launch_gemm(ta, tb, n, n, k, alpha, A, lda, dk, B, ldb, beta, C, ldc, s);
+}
 
 int64_t gram_chunks(int64_t d, int64_t N) {
   int64_t c, r;

@@ -36,6 +36,7 @@ namespace eda {
 namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int NN_NB = 8;    // output columns per workgroup (grid.y tiles the rest)
 constexpr int NN_ZT = 512;  // rows of Z per LDS tile
@@ -395,6 +396,206 @@ __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int 
             (a.ascale != nullptr) ? t[v] * a.ascale[c0 + ii] : t[v];
     }
   }
+}
+
+// tn for a narrow A (FP8 E4M3 or bfloat16 codes) and a float32 B (nb <= 8)
+// on the bfloat16 matrix cores.  A workgroup owns 64 columns of A (4 tiles
+// of 16) and one row chunk of 256 S rows; slabs of 32 KB of A are staged
+// through LDS with whole-wave 16-byte loads (32 lanes down each column), and
+// each wave multiplies a quarter of every slab's rows for all 4 tiles.  FP8
+// codes are widened by the hardware E4M3 -> float32 conversion (exact) and
+// truncated to bfloat16 (exact: E4M3 values have 4 significant bits); B's
+// float32 values are split into three bfloat16 terms hi + mid + lo (exact to
+// float32's precision), so every product of v_mfma_f32_16x16x32_bf16 is
+// exact and each 32-row step is accumulated in float32 from zero and then
+// added into float64 accumulators.  The 4 waves' sums meet in LDS in a fixed
+// order, scaled by the per-column scales on output (tn_body's layout).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 bf16_of_bits(uint16_t u) {
+  __bf16 r;
+  __builtin_memcpy(&r, &u, 2);
+  return r;
+}
+// float32 -> bfloat16 with round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_rne_f32(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+// 8 E4M3 codes (two words) -> 8 bfloat16 values, exact
+__device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint32_t w0, uint32_t w1) {
+  bf16x8 r;
+  const uint32_t ws[2] = {w0, w1};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)ws[q], false);
+    const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)ws[q], true);
+    r[4 * q + 0] = bf16_of_bits((uint16_t)(__float_as_uint(lo.x) >> 16));
+    r[4 * q + 1] = bf16_of_bits((uint16_t)(__float_as_uint(lo.y) >> 16));
+    r[4 * q + 2] = bf16_of_bits((uint16_t)(__float_as_uint(hi.x) >> 16));
+    r[4 * q + 3] = bf16_of_bits((uint16_t)(__float_as_uint(hi.y) >> 16));
+  }
+  return r;
+}
+
+template <typename TA, int S>
+__device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, int grp) {
+  constexpr int SZ = (int)sizeof(TA);
+  constexpr int SR = 32768 / (64 * SZ);      // rows per slab: 512 (FP8), 256 (bfloat16)
+  constexpr int CB = SR * SZ;                // bytes per column per slab (512)
+  constexpr int CS = CB + 16;                // LDS column stride (bytes)
+  constexpr int NSL = 256 * S / SR;          // slabs per chunk
+  constexpr int WR = SR / 4;                 // rows per wave per slab
+  constexpr int NKS = WR / 32;               // 32-row MFMA steps per wave per slab
+  static_assert(NSL >= 1 && (256 * S) % SR == 0, "a chunk must hold whole slabs");
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) u32x4* G4;
+  const int64_t d = a.d;
+  const int m = (int)a.m, nb = (int)a.nb;
+  const int c0 = grp * 64;
+  if (chunk >= a.chunks || c0 >= m) return;
+  __shared__ __attribute__((aligned(16))) uint8_t As[64 * CS];
+  static_assert(3 * 4 * 4 * 64 * 8 <= 64 * CS, "the wave sums must fit in the slab buffer");
+  double(*red)[4][4][64] = (double(*)[4][4][64])As;  // reused after the last slab
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = lane & 15, kq = lane >> 4;
+  const uint8_t* A = (const uint8_t*)a.A;
+  const float* B = (const float*)a.B;
+  const int64_t lda_b = a.lda * SZ;
+  const int64_t R0 = chunk * (int64_t)(256 * S);
+  // loads of a slab: element e = tid + 256 u (u < 8) is column e / 32,
+  // bytes 16 (e % 32) .. + 15 of that column's CB
+  u32x4 ra[8];
+  const u32x4 z4 = {0u, 0u, 0u, 0u};
+  auto load = [&](int sl) {
+    const int64_t r0 = R0 + (int64_t)sl * SR;
+    const bool full = r0 + SR <= d;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      const int cl = e >> 5, off = (e & 31) * 16;
+      const int c = c0 + cl;
+      const uint8_t* p = A + (int64_t)(c < m ? c : c0) * lda_b + r0 * SZ + off;
+      if (full) {
+        ra[u] = *(G4)p;
+      } else {
+        // pieces wholly past d read as zero; the piece holding row d - 1 is
+        // read byte by byte up to it
+        const int64_t rfirst = r0 + off / SZ;
+        u32x4 v = z4;
+        if (rfirst + 16 / SZ <= d) {
+          v = *(G4)p;
+        } else if (rfirst < d) {
+          const int keep = (int)((d - rfirst) * SZ);  // bytes of rows < d in this piece
+          uint8_t bytes[16];
+          for (int q = 0; q < 16; ++q)
+            bytes[q] = (q < keep) ? ((const __attribute__((address_space(1))) uint8_t*)p)[q] : 0;
+          __builtin_memcpy(&v, bytes, 16);
+        }
+        ra[u] = v;
+      }
+    }
+  };
+  double acc[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[t][v] = 0.0;
+  const bool bok = i < nb;
+  const float* bcol = B + (int64_t)(bok ? i : 0) * a.ldb;
+  int nsl = 0;
+  while (nsl < NSL && R0 + (int64_t)nsl * SR < d) ++nsl;
+  if (nsl > 0) load(0);
+  for (int sl = 0; sl < nsl; ++sl) {
+    __syncthreads();  // the previous slab has been read
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = tid + 256 * u;
+      const int cl = e >> 5, off = (e & 31) * 16;
+      *(u32x4*)(As + cl * CS + off) = (c0 + cl < m) ? ra[u] : z4;
+    }
+    __syncthreads();
+    if (sl + 1 < nsl) load(sl + 1);
+    const int64_t r0 = R0 + (int64_t)sl * SR;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int rl = wid * WR + 32 * ks + 8 * kq;  // first of this lane's 8 rows in the slab
+      // B: rows r0 + rl .. + 7 of column i, split into three bfloat16 terms
+      float bv[8];
+      const int64_t rb = r0 + rl;
+      if (bok && rb + 8 <= d) {
+        const f32x4 x0 = *(const __attribute__((address_space(1))) f32x4*)(bcol + rb);
+        const f32x4 x1 = *(const __attribute__((address_space(1))) f32x4*)(bcol + rb + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { bv[e] = x0[e]; bv[4 + e] = x1[e]; }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bv[e] = (bok && rb + e < d) ? bcol[rb + e] : 0.0f;
+      }
+      bf16x8 bh, bm, bl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint16_t h = bf16_rne_f32(bv[e]);
+        const float r1 = bv[e] - __uint_as_float((uint32_t)h << 16);
+        const uint16_t mm = bf16_rne_f32(r1);
+        const float r2 = r1 - __uint_as_float((uint32_t)mm << 16);
+        bh[e] = bf16_of_bits(h);
+        bm[e] = bf16_of_bits(mm);
+        bl[e] = bf16_of_bits(bf16_rne_f32(r2));
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint8_t* ap = As + (16 * t + i) * CS + rl * SZ;
+        bf16x8 av;
+        if constexpr (SZ == 1) {
+          const uint2 w = *(const uint2*)ap;
+          av = fp8x8_to_bf16(w.x, w.y);
+        } else {
+          const u32x4 w = *(const u32x4*)ap;
+          __builtin_memcpy(&av, &w, 16);
+        }
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bm, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, c, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t][v] += (double)c[v];
+      }
+    }
+  }
+  // fixed-order sum of the 4 waves (each over its quarter of every slab)
+  __syncthreads();  // the last slab has been read
+  if (wid > 0)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wid - 1][t][v][lane] = acc[t][v];
+  __syncthreads();
+  if (wid == 0) {
+    // accumulator element v of lane l: row 4 (l / 16) + v of the tile, column l % 16
+    const int jj = lane & 15, ib = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double sum = ((acc[t][v] + red[0][t][v][lane]) + red[1][t][v][lane]) +
+                           red[2][t][v][lane];
+        const int col = c0 + 16 * t + 4 * ib + v;
+        if (col < m && jj < nb)
+          a.part[(chunk * m + col) * (int64_t)nb + jj] =
+              (a.ascale != nullptr) ? sum * a.ascale[col] : sum;
+      }
+  }
+}
+
+template <typename TA, int S>
+__global__ __launch_bounds__(256) void tn_narrow_kernel(const TnArgs* __restrict__ arr,
+                                                        TnArgs one) {
+  const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
+  if (a.gate != nullptr && *a.gate == 0) return;
+  tn_narrow_body<TA, S>(a, blockIdx.x, blockIdx.y);
 }
 
 template <int S>
@@ -933,10 +1134,17 @@ __device__ __forceinline__ void nn_narrow_body(const NnArgs& a, int64_t bx, int 
         if (ii >= tn) continue;
         ACC av[NR];
         if constexpr (sizeof(TA) == 1) {
+          // hardware E4M3 -> float32 conversion (exact), two codes at a time
           const uint32_t ws[2] = {raw[u].x, raw[u].y};
 #pragma unroll
-          for (int r = 0; r < NR; ++r)
-            av[r] = (ACC)fp8e4m3_decode((uint8_t)(ws[r >> 2] >> (8 * (r & 3))));
+          for (int q = 0; q < 2; ++q) {
+            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)ws[q], false);
+            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)ws[q], true);
+            av[4 * q + 0] = (ACC)lo.x;
+            av[4 * q + 1] = (ACC)lo.y;
+            av[4 * q + 2] = (ACC)hi.x;
+            av[4 * q + 3] = (ACC)hi.y;
+          }
         } else {
           const uint32_t ws[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
 #pragma unroll
@@ -1028,6 +1236,30 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
   if (cmax == 0) return hipSuccess;
   const TnArgs one = (count == 1) ? host[0] : TnArgs{};
   const TnArgs* arr = (count == 1) ? nullptr : dev;
+  if constexpr (sizeof(TA) <= 2 && std::is_same<TB, float>::value) {
+    // narrow A, float32 B of at most 8 columns, 16-byte aligned columns:
+    // the bfloat16 matrix cores (chunks of whole 32 KB slabs)
+    constexpr int SR = 32768 / (64 * (int)sizeof(TA));
+    static const bool off = std::getenv("EDA_NARROW_F64") != nullptr;
+    bool ok = !off && (256 * S) % SR == 0;
+    for (int p = 0; p < count && ok; ++p) {
+      const TnArgs& a = host[p];
+      ok = a.nb <= 8 && ((a.lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)a.A % 16 == 0) &&
+           (a.ldb % 4 == 0) && ((uintptr_t)a.B % 16 == 0);
+    }
+    if (ok) {
+      dim3 g((unsigned)cmax, (unsigned)((mmax + 63) / 64), (unsigned)count);
+      if (S == 8)
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, 8>), g, dim3(256), 0, s, arr, one);
+      else if (S == 4)
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, 4>), g, dim3(256), 0, s, arr, one);
+      else if (S == 2)
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, 2>), g, dim3(256), 0, s, arr, one);
+      else if constexpr (sizeof(TA) == 2)
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, 1>), g, dim3(256), 0, s, arr, one);
+      return hipGetLastError();
+    }
+  }
   if constexpr (sizeof(TA) >= 4) {
     // narrow B, 16-byte aligned columns of A and VW-element aligned columns
     // of B: the streaming kernel with vector loads

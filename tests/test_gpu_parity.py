@@ -275,6 +275,39 @@ def test_expmv_fp8_lossless_factor(torch, eda):
     h.close()
 
 
+@pytest.mark.parametrize("storage", ["fp8", "bf16"])
+@pytest.mark.parametrize("d,n,k,b", [(3001, 150, 7, 8), (20011, 333, 40, 3), (40000, 1216, 38, 8)])
+def test_expmv_narrow_lossless_float32_blocks(torch, eda, storage, d, n, k, b):
+    """Float32 blocks against FP8 / bfloat16 copies that hold the factor
+    exactly (E4M3 values times a power of two per column, or bfloat16
+    values): the float32 pass over the narrow copy must give the exact
+    exponential action of the float32-rounded block to float32 accuracy.
+    The shapes span several 64-column groups with a ragged last group, row
+    chunks of several slabs and a ragged row tail."""
+    from oracle.bf16 import bf16_round
+    log(f"expmv {storage} lossless d={d} n={n} k={k} b={b} float32 block")
+    rng = np.random.default_rng(d + n)
+    if storage == "fp8":
+        H_W = _e4m3_factor(rng, d, n, rng.integers(-13, -10, size=n))
+        H_B = _e4m3_factor(rng, d, k, rng.integers(-13, -11, size=k))
+    else:
+        H_W = bf16_round(rng.standard_normal((d, n)) * 2.0 ** -5)
+        H_B = bf16_round(rng.standard_normal((d, k)) * 2.0 ** -6)
+    h = eda.Handle()
+    h.prepare(dev(torch, H_W), dev(torch, H_B), storage=storage)
+    V = rng.standard_normal((d, b)).astype(np.float32).astype(np.float64)
+    for which, H, c in (("W", H_W, -0.5), ("B", H_B, 1.0)):
+        out, s = h.expmv(which, c, dev(torch, V).float(), vdtype="f32")
+        got = host(out).astype(np.float64) * np.exp(s)
+        ref = O.exp_action_thm31(H, c, V)
+        E_norm = np.exp(max(0.0, c * np.linalg.norm(H, 2) ** 2))
+        err = rel_op_err(got, ref, E_norm, V)
+        bound = 64 * 2.0 ** -24
+        log(f"  {which} c={c} err={err:.2e} bound={bound:.1e}")
+        assert err <= bound
+    h.close()
+
+
 def test_expmv_fp8_rounding_c1(torch, eda, c1):
     """FP8 storage of the C1 factors.  The two streaming passes read the
     E4M3 copy (scaled per column, rounded to nearest even) while the core
