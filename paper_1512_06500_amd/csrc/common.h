@@ -291,7 +291,7 @@ struct SyevArgs {    // one symmetric eigenproblem, see launch_syev
   double* w;
   double* Z;
   double* work;
-  double ctol = 0.0;  // cluster gap relative to ||T|| (0: 1e-3)
+  double ctol = 0.0;  // cluster gap relative to ||T|| (0: orthonormal, see launch_syev)
 };
 
 // Kernel-side selection of the argument source of a multi launch.
@@ -471,6 +471,13 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
 // beta != 0, C symmetric too): only the lower triangle is computed, then
 // mirrored, so the result is exactly symmetric (large n; small n falls back
 // to launch_gemm).
+// C = A Z + gv V (gv from gv_p when not null; V may be null) on the matrix
+// cores in 64 x 64 tiles: A m x k column-major, Z k x n row-major (Z(r, j) at
+// Z[r ldz + j]), V and C m x n column-major.  Requires k >= 16, an even lda
+// and a 16-byte aligned A (hipErrorInvalidValue otherwise).
+hipError_t launch_gemm_av(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                          const double* Z, int64_t ldz, double gv, const double* gv_p,
+                          const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
 hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha, const double* A,
                            int64_t lda, const double* dk, const double* B, int64_t ldb,
                            double beta, double* C, int64_t ldc, hipStream_t s);
@@ -516,9 +523,11 @@ hipError_t launch_fill_masked_randn(int64_t d, int64_t b, const int* mask, uint6
 size_t syev_work_bytes(int64_t nmax);
 void syev_timing_enable(bool on);
 void syev_timing_report(FILE* f);
-// Eigenvectors of eigenvalues closer than ctol ||T|| (ctol <= 0: 1e-3) are
-// orthonormalised together; a smaller ctol saves that work where the
-// vectors need not be orthogonal to better than about u / ctol.
+// ctol <= 0: eigenvectors orthonormal to working accuracy (clusters of gaps
+// up to 1e-8 ||T|| orthonormalised together, then a correction of the whole
+// block).  ctol > 0: only clusters of gaps up to ctol ||T|| are
+// orthonormalised, for callers that need the vectors orthogonal to no better
+// than about u / ctol.
 hipError_t launch_syev(int64_t batch, int64_t n, const int* ns, const double* A, int64_t lda,
                        int64_t strideA, double* w, int64_t stridew, double* Z, int64_t ldz,
                        int64_t strideZ, int64_t nvec, double* work, hipStream_t s,

@@ -138,6 +138,14 @@ struct BigGemmArgs {
   // enumerates them), full K, every entry i >= j written to C(i, j) and
   // C(j, i), so the result is exactly symmetric
   int sym = 0;
+  // general mode with V: C = alpha op(A) op(B) + gv V (V column-major, ldv;
+  // gv read from gv_p when that is not null); beta is then unused
+  const double* V = nullptr;
+  int64_t ldv = 0;
+  double gv = 0.0;
+  const double* gv_p = nullptr;
+  // 0: B is read one double at a time (odd ldb or 8-byte aligned B)
+  int b_pairs = 1;
 };
 
 // Loads of one BK slice of op(X) (rows: the T-edge tile index, k: the
@@ -145,7 +153,7 @@ struct BigGemmArgs {
 // at X[i + k ld] (pairs along i); trans: X(i, k) at X[k + i ld] (pairs
 // along k).
 template <int T>
-__device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t ld, bool trans,
+__device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t ld, bool trans, bool pairs,
                                          int64_t i0, int64_t nI, int64_t k0, int64_t kend,
                                          double2 (&r)[T * BK / 512]) {
   const int tid = threadIdx.x;
@@ -160,14 +168,22 @@ __device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t l
     if (!trans) {
       if (gk < kend) {
         const double* p = X + gi + gk * ld;
-        if (gi + 1 < nI) v = *(const double2*)p;
-        else if (gi < nI) v.x = p[0];
+        if (gi + 1 < nI) {
+          if (pairs) v = *(const double2*)p;
+          else { v.x = p[0]; v.y = p[1]; }
+        } else if (gi < nI) {
+          v.x = p[0];
+        }
       }
     } else {
       if (gi < nI) {
         const double* p = X + gk + gi * ld;
-        if (gk + 1 < kend) v = *(const double2*)p;
-        else if (gk < kend) v.x = p[0];
+        if (gk + 1 < kend) {
+          if (pairs) v = *(const double2*)p;
+          else { v.x = p[0]; v.y = p[1]; }
+        } else if (gk < kend) {
+          v.x = p[0];
+        }
       }
     }
     r[q] = v;
@@ -237,8 +253,8 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
   // contiguous along j): loaded as X(j, k) that is "trans" exactly when tb == 0
   double2 ra[NP], rb[NP];
   if (kbeg < kend) {
-    big_load<T>(a.A, a.lda, a.ta != 0, i0, a.M, kbeg, kend, ra);
-    big_load<T>(a.B, a.ldb, a.tb == 0, j0, a.N, kbeg, kend, rb);
+    big_load<T>(a.A, a.lda, a.ta != 0, true, i0, a.M, kbeg, kend, ra);
+    big_load<T>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, kbeg, kend, rb);
   }
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();  // the previous slice has been read
@@ -246,8 +262,8 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
     big_store<T>(Bs, a.tb == 0, rb, nullptr, k0, kend);
     __syncthreads();
     if (k0 + BK < kend) {
-      big_load<T>(a.A, a.lda, a.ta != 0, i0, a.M, k0 + BK, kend, ra);
-      big_load<T>(a.B, a.ldb, a.tb == 0, j0, a.N, k0 + BK, kend, rb);
+      big_load<T>(a.A, a.lda, a.ta != 0, true, i0, a.M, k0 + BK, kend, ra);
+      big_load<T>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, k0 + BK, kend, rb);
     }
     // fragments of step ks + 4 are read from LDS while step ks multiplies
     double fa[2][QB], fb[2][QB];
@@ -289,6 +305,10 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
           const double o = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * acc[x][y][v];
           *cp = o;
           a.C[gj + gi * a.ldc] = o;
+        } else if (a.V != nullptr) {
+          const double g = (a.gv_p != nullptr) ? *a.gv_p : a.gv;
+          const double o = a.alpha * acc[x][y][v];
+          a.C[gi + gj * a.ldc] = (g == 0.0) ? o : o + g * a.V[gi + gj * a.ldv];
         } else {
           double* cp = a.C + gi + gj * a.ldc;
           *cp = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * acc[x][y][v];
@@ -445,6 +465,22 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
   dim3 g((unsigned)((m + MT - 1) / MT), (unsigned)((n + MT - 1) / MT));
   hipLaunchKernelGGL(gemm_kernel, g, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, dk, B, ldb,
                      beta, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_av(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                          const double* Z, int64_t ldz, double gv, const double* gv_p,
+                          const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (k < BK || !big_ok(A, lda)) return hipErrorInvalidValue;
+  BigGemmArgs a{m, n, k, lda, ldz, ldc, A, Z, nullptr, C, 1.0, 0.0, 0, 1, 0, 0, nullptr};
+  a.b_pairs = big_ok(Z, ldz) ? 1 : 0;
+  a.V = V;
+  a.ldv = ldv;
+  a.gv = gv;
+  a.gv_p = gv_p;
+  dim3 g((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
+  hipLaunchKernelGGL(big_gemm_kernel<64>, g, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -15,7 +15,10 @@
 //      (LU with partial pivoting of T - lambda I, two solves with
 //      overflow-safe rescaling), then orthonormalisation inside clusters of
 //      close eigenvalues (Cholesky QR twice by the whole workgroup, or
-//      modified Gram-Schmidt for very large clusters).
+//      classical Gram-Schmidt twice for very large clusters).  By default
+//      the clusters are tight (gaps up to 1e-8 ||T||) and a first-order
+//      correction of the whole block, Z <- Z (I - (Z^T Z - I) / 2), then
+//      removes the small overlaps between clusters.
 //   4. Back-transformation by the stored reflectors, applied straight to the
 //      eigenvectors of T: held in registers (LDS path) or in LDS panels with
 //      the reflectors staged in blocks (global path).
@@ -334,6 +337,97 @@ __device__ __forceinline__ void normalize_serial(int n, double* y, int64_t ys) {
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (k0 + u < n) y[(int64_t)(k0 + u) * ys] = v[u] * sc;
+  }
+}
+
+// Orthogonality correction of the nv columns of Z (n x nv, row stride nv) by
+// the whole workgroup: with E = Z^T Z - I, Z <- Z (I - E / 2), which leaves
+// Z^T Z = I - 3 E^2 / 4 + O(E^3); repeated (at most three times) until
+// max |E_ij| <= 16 u.  Meant for columns whose pairwise products are already
+// small (inverse-iteration vectors of eigenvalues separated by g, which
+// overlap by about u ||T|| / g): column j then moves by sum_i E_ij z_i, and
+// its residual by about sum_i |E_ij| |lambda_i - lambda_j| = O(u ||T||).
+// E lives in Eg (nv x nv), the updated block in Zn (n x nv) before it is
+// copied back; both are global scratch.
+template <int NT>
+__device__ __forceinline__ void wg_orth_correct(int n, int nv, double* __restrict__ Z,
+                                                double* __restrict__ Eg, double* __restrict__ Zn,
+                                                double* red) {
+  const int tid = threadIdx.x;
+  const int nb4 = (nv + 3) >> 2, nr4 = (n + 3) >> 2;
+  const int L = nb4 * (nb4 + 1) / 2;
+  for (int pass = 0; pass < 3; ++pass) {
+    double emax = 0.0;
+    for (int p = tid; p < L; p += NT) {
+      int bi = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+      while ((bi + 1) * (bi + 2) / 2 <= p) ++bi;
+      while (bi * (bi + 1) / 2 > p) --bi;
+      const int bj = p - bi * (bi + 1) / 2;
+      const int i0 = 4 * bi, j0 = 4 * bj;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int pos = 0; pos < n; ++pos) {
+        const double* zr = Z + (int64_t)pos * nv;
+        double zi[4], zj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          zi[a] = (i0 + a < nv) ? zr[i0 + a] : 0.0;
+          zj[a] = (j0 + a < nv) ? zr[j0 + a] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(zi[a], zj[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = i0 + a, j = j0 + b;
+          if (i < nv && j <= i) {
+            const double e = acc[a][b] - (i == j ? 1.0 : 0.0);
+            Eg[(int64_t)i * nv + j] = e;
+            Eg[(int64_t)j * nv + i] = e;
+            emax = fmax(emax, fabs(e));
+          }
+        }
+    }
+    emax = blk_max<NT>(emax, red);  // its barriers publish E
+    if (!(emax > 16.0 * 0x1.0p-53)) break;
+    for (int p = tid; p < nr4 * nb4; p += NT) {
+      const int r0 = 4 * (p / nb4), j0 = 4 * (p % nb4);
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int q = 0; q < nv; ++q) {
+        double zq[4], eq[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          zq[a] = (r0 + a < n) ? Z[(int64_t)(r0 + a) * nv + q] : 0.0;
+          eq[a] = (j0 + a < nv) ? Eg[(int64_t)q * nv + j0 + a] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(zq[a], eq[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int r = r0 + a, j = j0 + b;
+          if (r < n && j < nv)
+            Zn[(int64_t)r * nv + j] = fma(-0.5, acc[a][b], Z[(int64_t)r * nv + j]);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * nv; e += NT) Z[e] = Zn[e];
+    __syncthreads();
   }
 }
 
@@ -860,7 +954,11 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   // ---- 3. eigenvectors of T by inverse iteration ---------------------------
   const int n0 = n - nv;  // first computed eigenvalue index
   const double tiny = eps * tnorm;
-  const double ctol = (ctol_rel > 0.0 ? ctol_rel : 1e-3) * tnorm;
+  // clusters: consecutive gaps within ctol ||T|| (the caller's, else 1e-8;
+  // in the default mode a whole-block correction follows, which needs the
+  // vectors of separate clusters to overlap by no more than about 1e-8)
+  const bool correct_all = !(ctol_rel > 0.0);
+  const double ctol = (ctol_rel > 0.0 ? ctol_rel : 1e-8) * tnorm;
   // the off-diagonal into LDS (Gc is free between the eigenvalue and the
   // cluster phases), so the factorisation's loop reads no global memory
   double* EL = Gc;
@@ -972,6 +1070,8 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
     }
   }
   __syncthreads();
+  // the LU arrays are free once every vector has been iterated
+  if (correct_all && nv > 1) wg_orth_correct<NT>(n, nv, Zt, lub, lub + (int64_t)nv * nv, red);
   };
   if (zt_lds)
     vectors_of_t(ZtL);

@@ -445,17 +445,22 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
   constexpr int SR = 32768 / (64 * SZ);      // rows per slab: 512 (FP8), 256 (bfloat16)
   constexpr int CB = SR * SZ;                // bytes per column per slab (512)
   constexpr int CS = CB + 16;                // LDS column stride (bytes)
+  constexpr int BS = SR + 4;                 // LDS column stride of B (floats)
   constexpr int NSL = 256 * S / SR;          // slabs per chunk
   constexpr int WR = SR / 4;                 // rows per wave per slab
   constexpr int NKS = WR / 32;               // 32-row MFMA steps per wave per slab
+  constexpr int NBL = SR * 8 / 4 / 256;      // float4 loads of B per thread per slab
   static_assert(NSL >= 1 && (256 * S) % SR == 0, "a chunk must hold whole slabs");
+  static_assert(NBL >= 1 && (SR * 8 / 4) % 256 == 0, "B slab split over the workgroup");
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   typedef const __attribute__((address_space(1))) u32x4* G4;
+  typedef const __attribute__((address_space(1))) f32x4* GF4;
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
   const int c0 = grp * 64;
   if (chunk >= a.chunks || c0 >= m) return;
   __shared__ __attribute__((aligned(16))) uint8_t As[64 * CS];
+  __shared__ __attribute__((aligned(16))) float Bs[8 * BS];
   static_assert(3 * 4 * 4 * 64 * 8 <= 64 * CS, "the wave sums must fit in the slab buffer");
   double(*red)[4][4][64] = (double(*)[4][4][64])As;  // reused after the last slab
   const int tid = threadIdx.x, lane = tid & 63;
@@ -465,10 +470,13 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
   const float* B = (const float*)a.B;
   const int64_t lda_b = a.lda * SZ;
   const int64_t R0 = chunk * (int64_t)(256 * S);
-  // loads of a slab: element e = tid + 256 u (u < 8) is column e / 32,
-  // bytes 16 (e % 32) .. + 15 of that column's CB
+  // loads of a slab: A element e = tid + 256 u (u < 8) is column e / 32,
+  // bytes 16 (e % 32) .. + 15 of that column's CB; B group g = tid + 256 u
+  // (u < NBL) is column g / (SR / 4), rows 4 (g % (SR / 4)) .. + 3
   u32x4 ra[8];
+  f32x4 rbv[NBL];
   const u32x4 z4 = {0u, 0u, 0u, 0u};
+  const f32x4 zf4 = {0.f, 0.f, 0.f, 0.f};
   auto load = [&](int sl) {
     const int64_t r0 = R0 + (int64_t)sl * SR;
     const bool full = r0 + SR <= d;
@@ -497,14 +505,28 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
         ra[u] = v;
       }
     }
+#pragma unroll
+    for (int u = 0; u < NBL; ++u) {
+      const int g = tid + 256 * u;
+      const int col = g / (SR / 4), rr = 4 * (g % (SR / 4));
+      const int cc = col < nb ? col : 0;
+      const float* p = B + (int64_t)cc * a.ldb + r0 + rr;
+      if (full && ((a.ldb & 3) == 0)) {
+        rbv[u] = *(GF4)p;
+      } else {
+        f32x4 v = zf4;
+        for (int q = 0; q < 4; ++q)
+          if (r0 + rr + q < d) v[q] = ((const __attribute__((address_space(1))) float*)p)[q];
+        rbv[u] = v;
+      }
+      if (col >= nb) rbv[u] = zf4;
+    }
   };
   double acc[4][4];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[t][v] = 0.0;
-  const bool bok = i < nb;
-  const float* bcol = B + (int64_t)(bok ? i : 0) * a.ldb;
   int nsl = 0;
   while (nsl < NSL && R0 + (int64_t)nsl * SR < d) ++nsl;
   if (nsl > 0) load(0);
@@ -516,23 +538,29 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
       const int cl = e >> 5, off = (e & 31) * 16;
       *(u32x4*)(As + cl * CS + off) = (c0 + cl < m) ? ra[u] : z4;
     }
+#pragma unroll
+    for (int u = 0; u < NBL; ++u) {
+      const int g = tid + 256 * u;
+      const int col = g / (SR / 4), rr = 4 * (g % (SR / 4));
+      *(f32x4*)(Bs + col * BS + rr) = rbv[u];
+    }
     __syncthreads();
     if (sl + 1 < nsl) load(sl + 1);
-    const int64_t r0 = R0 + (int64_t)sl * SR;
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int rl = wid * WR + 32 * ks + 8 * kq;  // first of this lane's 8 rows in the slab
-      // B: rows r0 + rl .. + 7 of column i, split into three bfloat16 terms
+      // B: rows rl .. + 7 of column i (zero past nb and past d), split into
+      // three bfloat16 terms
       float bv[8];
-      const int64_t rb = r0 + rl;
-      if (bok && rb + 8 <= d) {
-        const f32x4 x0 = *(const __attribute__((address_space(1))) f32x4*)(bcol + rb);
-        const f32x4 x1 = *(const __attribute__((address_space(1))) f32x4*)(bcol + rb + 4);
+      {
+        const float* bp = Bs + (i < 8 ? i : 0) * BS + rl;
+        const f32x4 x0 = *(const f32x4*)bp;
+        const f32x4 x1 = *(const f32x4*)(bp + 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { bv[e] = x0[e]; bv[4 + e] = x1[e]; }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = (bok && rb + e < d) ? bcol[rb + e] : 0.0f;
+        for (int e = 0; e < 4; ++e) {
+          bv[e] = i < 8 ? x0[e] : 0.0f;
+          bv[4 + e] = i < 8 ? x1[e] : 0.0f;
+        }
       }
       bf16x8 bh, bm, bl;
 #pragma unroll
@@ -1412,6 +1440,15 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
     for (int p = 0; p < count && plain; ++p)
       plain = host[p].mask == nullptr && host[p].ascale == nullptr && host[p].out_row == 0 &&
               host[p].Out != host[p].A;
+    if (plain && count == 1) {
+      // a single wide product with a long inner dimension: the LDS-tiled
+      // matrix-core GEMM (64 x 64 output tiles, double-buffered slices)
+      const NnArgs& a = host[0];
+      const bool al = a.lda % 2 == 0 && ((uintptr_t)a.A % 16) == 0;
+      if (al && a.gate == nullptr && a.nb >= 48 && a.m >= 64)
+        return launch_gemm_av(a.d, a.nb, a.m, (const double*)a.A, a.lda, a.Z, a.ldz, a.alpha,
+                              a.alpha_p, (const double*)a.V, a.ldv, (double*)a.Out, a.ldo, s);
+    }
     if (plain) {
       // matrix cores: CTN output tiles per workgroup, as many as leave 512
       // workgroups (A is then read once per 16 CTN columns)
