@@ -100,9 +100,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(bool ta, bool tb, int64_t m, 
 
 // Large products on the matrix cores: C (M x N) = alpha op(A) diag(dk) op(B)
 // (+ beta C), or, for the Gram matrix, partial tiles of P^T P over row
-// chunks.  A workgroup owns a BT x BT tile of C (BT = 128): its 4 waves a
-// 2 x 2 grid of 64 x 64 quadrants, 16 v_mfma_f64_16x16x4f64 accumulators
-// each, so every A or B fragment read from LDS feeds 4 products.  K is
+// chunks.  A workgroup owns a BT x BT tile of C (BT = 64): its 4 waves a
+// 2 x 2 grid of 32 x 32 quadrants, 4 v_mfma_f64_16x16x4f64 accumulators
+// each, so every A or B fragment read from LDS feeds 2 products (128-edge
+// tiles, 16 accumulators a wave, need more registers than two waves per
+// SIMD leave and spill).  K is
 // staged through LDS in slices of BK = 16, op(A) and op(B) both k-major
 // (As[k][i], Bs[k][j]: the 16 lanes of a fragment read 128 contiguous bytes),
 // and the next slice is loaded into registers with 16-byte loads while the
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(bool ta, bool tb, int64_t m, 
 // contiguous in memory (i for op(A) = A, k for op(A) = A^T; likewise for B).
 // Requires even leading dimensions and 16-byte aligned operands (the
 // launcher falls back to gemm_kernel otherwise).
-constexpr int BT = 128;  // tile edge of the Gram kernel (and of large GEMMs)
+constexpr int BT = 64;  // tile edge of the Gram kernel and of large GEMMs
 constexpr int BK = 16;
 
 // LDS row stride (doubles) for a tile edge T: T + 18 for 128, T + 2 for 64,
@@ -227,12 +229,13 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
   __shared__ double As[BK][LS];
   __shared__ double Bs[BK][LS];
   int64_t ti, tj, kbeg, kend;
+  int64_t chunk = blockIdx.y;
   if (a.gram || a.sym) {
     int64_t t = blockIdx.x;
     ti = 0;
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     tj = t - ti * (ti + 1) / 2;
-    kbeg = a.gram ? (int64_t)blockIdx.y * a.kchunk : 0;
+    kbeg = a.gram ? chunk * a.kchunk : 0;
     kend = a.gram ? min(a.K, kbeg + a.kchunk) : a.K;
   } else {
     ti = blockIdx.x;
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
         const int64_t gi = i0 + qi + 16 * x + 4 * v + lk;
         if (gi >= a.M || gj >= a.N) continue;
         if (a.gram) {
-          a.part[(int64_t)blockIdx.y * a.N * a.N + gi + gj * a.N] = acc[x][y][v];
+          a.part[chunk * a.N * a.N + gi + gj * a.N] = acc[x][y][v];
         } else if (a.sym) {
           if (gi < gj) continue;
           double* cp = a.C + gi + gj * a.ldc;
@@ -318,13 +321,13 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
 }
 
 // Sum of the Gram partials of big_gemm_kernel (tiles of BT), mirrored.
-__global__ __launch_bounds__(256) void big_gram_reduce_kernel(int64_t N, int64_t chunks,
+__global__ __launch_bounds__(256) void big_gram_reduce_kernel(int64_t N, int64_t chunks, int bt,
                                                               const double* __restrict__ part,
                                                               double* __restrict__ G, int64_t ldg) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= N * N) return;
   const int64_t j = e / N, i = e - j * N;
-  const bool lower = (i / BT) >= (j / BT);
+  const bool lower = (i / bt) >= (j / bt);
   const int64_t src = lower ? (i + j * N) : (j + i * N);
   double s = 0.0;
   for (int64_t c = 0; c < chunks; ++c) s += part[c * N * N + src];
@@ -452,14 +455,8 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
   if (m >= 512 && n >= 512 && k >= 64 && big_ok(A, lda) && big_ok(B, ldb)) {
     BigGemmArgs a{m, n, k, lda, ldb, ldc, A, B, dk, C, alpha, beta, ta ? 1 : 0, tb ? 1 : 0,
                   0, 0, nullptr};
-    // 128 x 128 tiles while they give 512 workgroups, else 64 x 64
-    if (((m + 127) / 128) * ((n + 127) / 128) >= 512) {
-      dim3 g((unsigned)((m + 127) / 128), (unsigned)((n + 127) / 128));
-      hipLaunchKernelGGL(big_gemm_kernel<128>, g, dim3(256), 0, s, a);
-    } else {
-      dim3 g((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
-      hipLaunchKernelGGL(big_gemm_kernel<64>, g, dim3(256), 0, s, a);
-    }
+    dim3 g((unsigned)((m + BT - 1) / BT), (unsigned)((n + BT - 1) / BT));
+    hipLaunchKernelGGL(big_gemm_kernel<BT>, g, dim3(256), 0, s, a);
     return hipGetLastError();
   }
   dim3 g((unsigned)((m + MT - 1) / MT), (unsigned)((n + MT - 1) / MT));
@@ -543,7 +540,7 @@ hipError_t launch_gram_reduce(int64_t N, int64_t chunks, const double* part, dou
                               int64_t ldg, hipStream_t s) {
   if (gram_big(N, DT::F64)) {
     hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0,
-                       s, N, chunks, part, G, ldg);
+                       s, N, chunks, BT, part, G, ldg);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, N,
