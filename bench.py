@@ -349,7 +349,9 @@ def batched(torch, eda, count: int = 64, reps: int = 2) -> dict:
         out[tag] = {"problems_per_s": count / el, "ms_per_batch": 1e3 * el, "status": int(st),
                     "ok": int(sum(r.status == 0 for r in res)),
                     "max_iters": int(max(r.info["iters"] for r in res)),
-                    "max_refine_passes": int(max(r.info["refine_passes"] for r in res))}
+                    "max_refine_passes": int(max(r.info["refine_passes"] for r in res)),
+                    "float64_continuations": int(sum(bool(r.info["flags"] & eda.EDA_WARN_FALLBACK)
+                                                     for r in res))}
     # the same problems one after another: float64 (the plain single-problem
     # solve) and float32 factors with a float32 basis
     hs = eda.Handle()

@@ -121,7 +121,8 @@ typedef struct {
 #define EDA_WARN_FLOOR 2       /* some pair stopped at its attainable floor, not tol */
 #define EDA_WARN_REPAIRED 4    /* a Krylov block lost rank and was re-orthogonalised */
 #define EDA_WARN_FALLBACK 8    /* batched, narrow precision: the refinement stalled and the
-                                  problem was solved again in float64                 */
+                                  problem continued as a float64 block Lanczos solve
+                                  started from its refined Ritz block                  */
 
 /* Create a handle bound to the current HIP device and to `hip_stream`
  * (a hipStream_t, or NULL for the default stream).  *h receives the handle. */
@@ -294,8 +295,10 @@ typedef struct {
  * EDA_OK when every problem succeeded, else the first failing status
  * (argument errors are reported before any work is done).  With narrow
  * storage or a float32 basis, a problem whose float64 refinement passes
- * stall is solved again by eda_solve in float64 on its own handle
- * (EDA_WARN_FALLBACK; its iterations are added to iters).  Uses the
+ * stall continues by eda_solve in float64 on its own handle, with its
+ * float64 master as the storage (no new Gram or cores) and a start block
+ * mixed from its refined Ritz block (EDA_WARN_FALLBACK; its iterations are
+ * added to iters).  Uses the
  * handle's stream and workspaces; does not change the handle's own
  * preparation.  Synchronises. */
 eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_problem* probs,

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "host_internal.h"
@@ -282,6 +283,48 @@ eda_status build_composite_cores(eda_handle h) {
 namespace eda {
 
 // Arnoldi core: [[a Gm, Gm K GB], [0, GB]]
+eda_status promote_storage_f64(eda_handle h) {
+  if (!h->prepared) return fail(h, EDA_ERR_STATE, "no preparation to promote");
+  if (h->storage == EDA_F64) return EDA_OK;
+  std::swap(h->P, h->P64);
+  release(h->P64);
+  h->storage = EDA_F64;
+  release_graphs(h);  // captured steps read the narrow copy
+  return EDA_OK;
+}
+
+eda_status warm_start_block(eda_handle h, int64_t d, int64_t t, int64_t b, const double* Y,
+                            int64_t ldy, uint64_t seed, double** V, int64_t* ldv) {
+  STCHK(ensure(h, h->warm, (size_t)(d * b + t * b) * 8));
+  double* Vd = h->warm.d();
+  hipStream_t s = h->stream;
+  if (t >= b) {
+    // G: t x b with entries +-1 from a SplitMix64 stream (Steele, Lea and
+    // Flood 2014), scaled by 1/sqrt(t); every column of Y G mixes all pairs
+    std::vector<double> G((size_t)t * b);
+    uint64_t x = seed ^ 0x243f6a8885a308d3ull;
+    const double sc = 1.0 / std::sqrt((double)t);
+    for (auto& g : G) {
+      x += 0x9e3779b97f4a7c15ull;
+      uint64_t z = x;
+      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+      z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+      z ^= z >> 31;
+      g = (z >> 63) ? sc : -sc;
+    }
+    double* Gd = Vd + d * b;
+    HIPCHK(hipMemcpyAsync(Gd, G.data(), G.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_gemm(false, false, d, b, t, 1.0, Y, ldy, nullptr, Gd, t, 0.0, Vd, d, s));
+    HIPCHK(hipStreamSynchronize(s));  // G is a host temporary
+  } else {
+    HIPCHK(launch_copy2d(d, t, Y, DT::F64, ldy, Vd, DT::F64, d, s));
+    HIPCHK(launch_randn(d, b - t, seed, Vd + d * t, d, s));
+  }
+  *V = Vd;
+  *ldv = d;
+  return EDA_OK;
+}
+
 eda_status ensure_arnoldi_core(eda_handle h) {
   if (h->ca_ready) return EDA_OK;
   const int64_t n = h->n, k = h->k, N = h->N;
@@ -388,7 +431,7 @@ void eda_destroy(eda_handle h) {
                   &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part, &h->zpart,
                   &h->Ysm, &h->Zsm, &h->PQ[0], &h->PQ[1], &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
-                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale};
+                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale, &h->warm};
     for (Buf& b : h->dir) release(b);
     for (Buf& b : h->af) release(b);
     for (Buf& b : h->nnp) release(b);

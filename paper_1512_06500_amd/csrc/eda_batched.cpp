@@ -1218,13 +1218,20 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
         stat[p] = EDA_ERR_NOCONV;
     }
     // A narrow-precision problem whose refinement stalled (wanted pairs a few
-    // per cent from a large eigenvalue cluster) is solved again by the
-    // float64 path on its own handle.
+    // per cent from a large eigenvalue cluster) continues in float64 on its
+    // own handle: its float64 master becomes the storage (Gram and cores are
+    // kept) and block Lanczos starts from the refined Ritz block mixed down
+    // to b columns, so the Krylov space begins inside the wanted subspace.
     eda_info fb;
     std::memset(&fb, 0, sizeof(fb));
     bool fell_back = false;
     if (stat[p] == EDA_ERR_NOCONV && E.mixed) {
-      eda_status s1 = eda_prepare(P.sub, q.d, q.n, q.k, q.H_W, q.ldw, q.H_B, q.ldb, EDA_F64);
+      eda_status s1 = promote_storage_f64(P.sub);
+      double* V1 = nullptr;
+      int64_t ld1 = 0;
+      if (s1 == EDA_OK)
+        s1 = warm_start_block(P.sub, P.d, P.t, E.b, P.XB[P.cb], P.ldq, E.seed + (uint64_t)p, &V1,
+                              &ld1);
       if (s1 == EDA_OK) {
         eda_solve_opts o1;
         std::memset(&o1, 0, sizeof(o1));
@@ -1234,6 +1241,8 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
         o1.krylov_dtype = EDA_F64;
         o1.refine_dtype = EDA_F64;
         o1.seed = E.seed + (uint64_t)p;
+        o1.start_block = V1;
+        o1.ld_start = ld1;
         s1 = eda_solve(P.sub, (int32_t)q.t, q.tol, &o1, q.ritz, q.ritz_log, q.X, q.ldx, q.resid,
                        &fb);
       }

@@ -60,6 +60,7 @@ struct eda_handle_s {
   eda::Buf alphaB_dev;  // alphaB on the device, read by captured steps
   eda::Buf pscale;      // FP8 storage: column j of P is pscale[j] times its FP8 copy
   eda::Buf dir[10];     // workspaces of eda_solve_direct
+  eda::Buf warm;        // start block of a float64 continuation (and its mixing matrix)
   eda::Buf af[10];      // workspaces of the Arnoldi-form solve
   eda::Buf nnp[2];      // projections of the classifier (training, testing)
   double normW = 0.0;   // ||H_W^T H_W||_1
@@ -170,6 +171,15 @@ eda_status validate_block(eda_handle h, int64_t b, const void* V, int64_t ldv, c
 inline bool core_split(int64_t Nc, int64_t b, const double* C, int64_t ldc) {
   return Nc >= 1024 && b <= 8 && ldc % 2 == 0 && ((uintptr_t)C % 16) == 0;
 }
+// Makes the float64 master the storage copy of a narrow preparation (the
+// Gram and the cores already come from the float64 factors, so nothing is
+// rebuilt); a float64 preparation is left as it is.
+eda_status promote_storage_f64(eda_handle h);
+// Start block of a float64 continuation from a Ritz block Y (d x t, ld ldy):
+// Y G with a fixed pseudo-random t x b mixing G when t >= b, else Y followed
+// by b - t Gaussian columns.  Written to h->warm (d x b, ld d).
+eda_status warm_start_block(eda_handle h, int64_t d, int64_t t, int64_t b, const double* Y,
+                            int64_t ldy, uint64_t seed, double** V, int64_t* ldv);
 // Looks up, once per device, the device address of the scratch array of
 // eda_opmv_noalloc (eda_noalloc.hip); the device must be current.
 hipError_t noalloc_init_device(int device);

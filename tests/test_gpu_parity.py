@@ -121,8 +121,8 @@ def test_gram(torch, eda, cname, request):
 
 @pytest.mark.parametrize("d,n,k", [(5003, 677, 100), (20000, 1500, 37)])
 def test_gram_large_matrix_cores(torch, eda, d, n, k):
-    """Gram matrices with N = n + k >= 256 take the matrix-core kernel (128 x
-    128 tiles, row chunks, ragged last tile and chunk): exactly symmetric and
+    """Gram matrices with N = n + k >= 256 take the matrix-core kernel (64 x
+    64 tiles, row chunks, ragged last tile and chunk): exactly symmetric and
     normwise within 1e-14 of P^T P in float64."""
     log(f"gram (matrix cores) d={d} N={n + k}")
     rng = np.random.default_rng(d)
@@ -953,8 +953,8 @@ def test_batched_c4_all_problems(torch, eda, c4_batch, storage, basis):
     the oracle's exact reduction: residuals, Ritz values and span as for the
     single floored solves (graded spectra: the small pairs are held to their
     attainable float64 floors u lam_1 / lam_i).  With float32 storage, the
-    problems whose float32 phase and refinement stall are solved again in
-    float64 (EDA_WARN_FALLBACK) and meet the same bounds."""
+    problems whose float32 phase and refinement stall continue in float64
+    (EDA_WARN_FALLBACK) and meet the same bounds."""
     ps, cases, reds = c4_batch
     log(f"batched C4, 64 problems, storage={storage} basis={basis}")
     h = eda.Handle()
@@ -973,6 +973,34 @@ def test_batched_c4_all_problems(torch, eda, c4_batch, storage, basis):
                                f"{c.name} d={c.d} N={c.H_W.shape[1] + c.H_B.shape[1]} "
                                f"t={c.t}{' (fallback)' if i in fell else ''}",
                                nu1=nu_max(c.H_W))
+    h.close()
+
+
+def test_batched_float64_continuation(torch, eda, c4_batch):
+    """Narrow problems with the float64 refinement switched off stall after
+    their bfloat16 phase and continue as float64 block Lanczos solves started
+    from their Ritz blocks, on their float64 masters: every one meets the
+    floored float64 bounds against the oracle, and none needs more
+    iterations than a float64 solve from a random start."""
+    ps, cases, reds = c4_batch
+    sel = list(range(0, 64, 8))
+    log(f"batched float64 continuation, problems {sel}")
+    h = eda.Handle()
+    probs = []
+    for i in sel:
+        HW, HB = h.scatter_factors(dev(torch, cases[i].X), cases[i].counts.tolist())
+        probs.append((HW, HB, cases[i].t, ps[i].tol))
+    res, st = h.solve_batched(probs, storage="bf16", krylov_dtype="f32", seed=4100, max_refine=-1)
+    assert st == 0, [r.status for r in res]
+    cold, st2 = h.solve_batched(probs, storage="f64", krylov_dtype="f64", seed=4100)
+    assert st2 == 0
+    fell = [j for j, r in enumerate(res) if r.info["flags"] & eda.EDA_WARN_FALLBACK]
+    log(f"  continued in float64: {fell}")
+    assert fell, "no problem stalled without refinement"
+    for j, i in enumerate(sel):
+        r = res[j]
+        check_floored_solution(r, reds[i], cases[i].t, ps[i].tol,
+                               f"{cases[i].name} continuation={j in fell}", nu1=nu_max(cases[i].H_W))
     h.close()
 
 
