@@ -253,6 +253,8 @@ def solve_variants(torch, eda, reps: int = 5) -> dict:
         row = {"workload": f"d={p.d}, n={p.n}, k={p.k}, t={p.t}, tol={p.tol:g}"}
         for tag, fn in (("lanczos", lambda: h.solve(p.t, p.tol, block=8, seed=p.seed)),
                         ("arnoldi", lambda: h.solve(p.t, p.tol, block=8, seed=p.seed, form="A")),
+                        ("jacobi_davidson", lambda: h.solve(p.t, p.tol, block=8, seed=p.seed,
+                                                            form="JD")),
                         ("direct", lambda: h.solve_direct(p.t))):
             r = fn()
             torch.cuda.synchronize()
@@ -264,7 +266,7 @@ def solve_variants(torch, eda, reps: int = 5) -> dict:
             row[tag] = {"solves_per_s": 1.0 / el, "ms": 1e3 * el, "status": r.status,
                         "iters": r.info["iters"], "resid_max": max(r.resid), "lam": r.ritz}
         lk = np.array(row["lanczos"].pop("lam"))
-        for tag in ("arnoldi", "direct"):
+        for tag in ("arnoldi", "jacobi_davidson", "direct"):
             lv = np.array(row[tag].pop("lam"))
             row[f"lam_max_rel_diff_{tag}"] = float(np.max(np.abs(lk - lv) / lv))
             row[f"ratio_{tag}_over_lanczos"] = (row[tag]["solves_per_s"]

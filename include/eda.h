@@ -63,7 +63,8 @@ typedef enum { EDA_W = 0, EDA_B = 1 } eda_which;
 /* Operator forms of Section 3.1. */
 typedef enum {
   EDA_FORM_LANCZOS_M = 0,  /* M = exp(-S_W/2) exp(S_B) exp(-S_W/2), eq. (3.15), product (3.16) */
-  EDA_FORM_ARNOLDI_A = 1   /* A = exp(-S_W) exp(S_B), eq. (3.1), product (3.2)                 */
+  EDA_FORM_ARNOLDI_A = 1,  /* A = exp(-S_W) exp(S_B), eq. (3.1), product (3.2)                 */
+  EDA_FORM_JD_M = 2        /* M of eq. (3.15) solved by block Jacobi-Davidson (Section 5)       */
 } eda_form;
 
 /* Residual measure used by the stopping test of eda_solve. */
@@ -74,7 +75,8 @@ typedef enum {
 
 /* Solver options.  A zero-initialised struct selects every default. */
 typedef struct {
-  eda_form form;            /* EDA_FORM_LANCZOS_M (default) or EDA_FORM_ARNOLDI_A    */
+  eda_form form;            /* EDA_FORM_LANCZOS_M (default), EDA_FORM_ARNOLDI_A or
+                               EDA_FORM_JD_M                                         */
   int32_t block;            /* block width b (default 8)                             */
   int32_t max_basis;        /* basis columns before a thick restart (default
                                max(2t+2b, t+6b) rounded up to a multiple of b,
@@ -231,7 +233,18 @@ eda_status eda_opmv_noalloc(eda_handle h, eda_form form, int64_t b, const void* 
  * e^{-s} exp(S_B) x_i - theta_i exp(S_W) x_i for exp(S_W)-normalised x_i,
  * relative as in opts.resmode (equal to the Lanczos form's residual of the
  * same pair).  EDA_ERR_NOCONV also when a block loses rank before the
- * tolerance is met.  Synchronises. */
+ * tolerance is met.
+ * With opts.form = EDA_FORM_JD_M the same pairs of e^{-s} M come from block
+ * Jacobi-Davidson (one of the further solvers named in Section 5): every
+ * outer step takes the Rayleigh-Ritz pairs of the search space, solves the
+ * projected correction equation (I - Y Y^T)(e^{-s} M - theta_i I)(I - Y Y^T)
+ * z_i = -r_i for up to b unconverged pairs by 4 GMRES steps (one block
+ * product each), and restarts to the t + b leading Ritz vectors plus the
+ * corrections.  Float64 only (krylov_dtype EDA_F64; the float64 master of P
+ * is used whatever the storage type), max_iter counts outer steps (default
+ * 1000), max_basis is unused (the search space holds t + 2b columns, t + 2b
+ * <= d), no refinement stage; stopping test, back-transform, outputs and
+ * resid as for the Lanczos form.  Synchronises. */
 eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_solve_opts* opt,
                      double* ritz, double* ritz_log, double* X, int64_t ldx,
                      double* resid, eda_info* info);

@@ -27,7 +27,7 @@ EDA_OK, EDA_ERR_ARG, EDA_ERR_NOMEM, EDA_ERR_HIP = 0, 1, 2, 3
 EDA_ERR_NOCONV, EDA_ERR_RANGE, EDA_ERR_NONFINITE, EDA_ERR_STATE = 4, 5, 6, 7
 EDA_F64, EDA_F32, EDA_BF16, EDA_FP8_E4M3 = 0, 1, 2, 3
 EDA_W, EDA_B = 0, 1
-EDA_FORM_LANCZOS_M, EDA_FORM_ARNOLDI_A = 0, 1
+EDA_FORM_LANCZOS_M, EDA_FORM_ARNOLDI_A, EDA_FORM_JD_M = 0, 1, 2
 EDA_RES_REL_THETA, EDA_RES_NORMWISE = 0, 1
 EDA_WARN_DEGENERATE, EDA_WARN_FLOOR, EDA_WARN_REPAIRED, EDA_WARN_FALLBACK = 1, 2, 4, 8
 
@@ -298,12 +298,14 @@ class Handle:
               X=None, form: str = "M") -> SolveResult:
         """form 'M': block Lanczos on the symmetric e^{-s} M, then the
         back-transform; form 'A': the eigenvectors of A = exp(-S_W) exp(S_B)
-        directly, by block Lanczos in the exp(S_W) inner product (float64)."""
+        directly, by block Lanczos in the exp(S_W) inner product (float64);
+        form 'JD': the pairs of e^{-s} M by block Jacobi-Davidson (float64)."""
         torch = self._torch
-        if form not in ("M", "A"):
-            raise ValueError("form must be 'M' or 'A'")
+        forms = {"M": EDA_FORM_LANCZOS_M, "A": EDA_FORM_ARNOLDI_A, "JD": EDA_FORM_JD_M}
+        if form not in forms:
+            raise ValueError("form must be 'M', 'A' or 'JD'")
         o = SolveOpts()
-        o.form = EDA_FORM_LANCZOS_M if form == "M" else EDA_FORM_ARNOLDI_A
+        o.form = forms[form]
         o.block = block
         o.max_basis = max_basis
         o.max_iter = max_iter

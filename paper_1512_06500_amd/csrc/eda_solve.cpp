@@ -47,8 +47,10 @@ struct Solver {
   double* H() const { return h->H[cur].d(); }
 };
 
-// One Cholesky QR pass: G = X^T X, Xout = X R^{-1}.  Optionally records R
-// (combined with Rprev) and raises the repair flag.
+}  // namespace
+
+namespace eda {
+
 eda_status cholqr_pass(eda_handle h, int64_t d, int64_t cols, const void* X, DT xdt, int64_t ldx,
                        void* Xout, int64_t ldxo, const double* Rprev, double* Rout, int64_t ldro,
                        const double* hcol, int64_t mrows, int64_t ldhc, const int* gate,
@@ -73,8 +75,6 @@ eda_status cholqr_pass(eda_handle h, int64_t d, int64_t cols, const void* X, DT 
   return EDA_OK;
 }
 
-// One classical Gram-Schmidt pass of W (b columns) against Q[:, 0:m]:
-//   h = Q^T W (accumulated into Hcol when given),  W -= Q h.
 eda_status cgs_pass(eda_handle h, int64_t d, int64_t m, const void* Q, DT qdt, int64_t ldq,
                     void* W, int64_t ldw, int64_t b, double* Hcol, int64_t ldh, double beta,
                     const int* gate) {
@@ -89,6 +89,10 @@ eda_status cgs_pass(eda_handle h, int64_t d, int64_t m, const void* Q, DT qdt, i
                    h->stream));
   return EDA_OK;
 }
+
+}  // namespace eda
+
+namespace {
 
 // Block step: from the basis Q[:, 0:m+b] (current block Q[:, m:m+b]) build
 // Q[:, m+b:m+2b] and column block m of H.
@@ -303,9 +307,10 @@ eda_status rr_collect(Solver& S, int64_t m, int64_t cnt, double* theta, double* 
   return EDA_OK;
 }
 
-// float64 Rayleigh-Ritz on the w columns of B (with MB = M B): the top t
-// Ritz vectors go to Y = B S_t and MY = MB S_t, the Ritz values (descending)
-// to dtheta.  Uses the workspaces T, S, wT, Sd with leading dimension mm.
+}  // namespace
+
+namespace eda {
+
 eda_status rr_block(eda_handle h, int64_t d, int64_t ld, int64_t w, int64_t t, int64_t mm,
                     const double* B, const double* MB, double* Y, double* MY) {
   hipStream_t s = h->stream;
@@ -326,7 +331,7 @@ eda_status rr_block(eda_handle h, int64_t d, int64_t ld, int64_t w, int64_t t, i
   return EDA_OK;
 }
 
-}  // namespace
+}  // namespace eda
 
 namespace eda {
 
@@ -370,7 +375,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   if (ritz == nullptr || ritz_log == nullptr || X == nullptr || resid == nullptr)
     return fail(h, EDA_ERR_ARG, "null output pointer");
   if (ldx < d) return fail(h, EDA_ERR_ARG, "ldx must be >= d");
-  if (o.form != EDA_FORM_LANCZOS_M && o.form != EDA_FORM_ARNOLDI_A)
+  if (o.form != EDA_FORM_LANCZOS_M && o.form != EDA_FORM_ARNOLDI_A && o.form != EDA_FORM_JD_M)
     return fail(h, EDA_ERR_ARG, "unknown form");
   if (o.krylov_dtype != EDA_F64 && o.krylov_dtype != EDA_F32)
     return fail(h, EDA_ERR_ARG, "krylov_dtype (basis type) must be EDA_F64 or EDA_F32");
@@ -398,6 +403,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   STCHK(check_dev_ptr(h, X, "X"));
   if (o.start_block != nullptr) STCHK(check_dev_ptr(h, o.start_block, "start_block"));
   if (o.form == EDA_FORM_ARNOLDI_A) return solve_aform(h, t, tol, o, ritz, ritz_log, X, ldx, resid, info);
+  if (o.form == EDA_FORM_JD_M) return solve_jd(h, t, tol, o, ritz, ritz_log, X, ldx, resid, info);
 
   const DT qdt = o.krylov_dtype == EDA_F32 ? DT::F32 : DT::F64;
   const bool mixed = (h->storage != EDA_F64) || (qdt != DT::F64);

@@ -180,6 +180,25 @@ eda_status promote_storage_f64(eda_handle h);
 // by b - t Gaussian columns.  Written to h->warm (d x b, ld d).
 eda_status warm_start_block(eda_handle h, int64_t d, int64_t t, int64_t b, const double* Y,
                             int64_t ldy, uint64_t seed, double** V, int64_t* ldv);
+// One Cholesky QR pass: G = X^T X, Xout = X R^{-1}.  Optionally records R
+// (combined with Rprev) and raises the repair flag.
+eda_status cholqr_pass(eda_handle h, int64_t d, int64_t cols, const void* X, DT xdt, int64_t ldx,
+                       void* Xout, int64_t ldxo, const double* Rprev, double* Rout, int64_t ldro,
+                       const double* hcol, int64_t mrows, int64_t ldhc, const int* gate,
+                       int* flag);
+// One classical Gram-Schmidt pass of W (b columns) against Q[:, 0:m]:
+//   h = Q^T W (accumulated into Hcol when given),  W -= Q h.
+eda_status cgs_pass(eda_handle h, int64_t d, int64_t m, const void* Q, DT qdt, int64_t ldq,
+                    void* W, int64_t ldw, int64_t b, double* Hcol, int64_t ldh, double beta,
+                    const int* gate);
+// float64 Rayleigh-Ritz on the w columns of B (with MB = M B): the top t
+// Ritz vectors go to Y = B S_t and MY = MB S_t, the Ritz values (descending)
+// to dtheta.  Uses the workspaces T, S, wT, Sd with leading dimension mm.
+eda_status rr_block(eda_handle h, int64_t d, int64_t ld, int64_t w, int64_t t, int64_t mm,
+                    const double* B, const double* MB, double* Y, double* MY);
+// eda_solve by block Jacobi-Davidson (eda_jd.cpp); arguments already checked.
+eda_status solve_jd(eda_handle h, int32_t t, double tol, const eda_solve_opts& o, double* ritz,
+                    double* ritz_log, double* X, int64_t ldx, double* resid, eda_info* info);
 // Looks up, once per device, the device address of the scratch array of
 // eda_opmv_noalloc (eda_noalloc.hip); the device must be current.
 hipError_t noalloc_init_device(int device);

@@ -770,6 +770,42 @@ def test_aform_solve_against_oracle(torch, eda, cname, block, request):
     h.close()
 
 
+@pytest.mark.parametrize("cname,block", [("c1", 8), ("c2", 8), ("ragged", 3), ("c2", 4)])
+def test_jd_solve_against_oracle(torch, eda, cname, block, request):
+    """Block Jacobi-Davidson (row f4): the same pairs of e^{-s} M by
+    Rayleigh-Ritz, projected correction equations solved by GMRES, and
+    restarts to the t + b leading Ritz vectors.  Same bounds against the
+    oracle as the Lanczos form, and the two solvers agree."""
+    case = request.getfixturevalue(cname)
+    log(f"JD solve {case.name} b={block}")
+    ref = O.eda_dense(case.H_W, case.H_B, case.t) if case.d <= 2000 else None
+    red = O.eda_reduced(case.H_W, case.H_B, case.t)
+    h, _, _ = prepared(torch, eda, case)
+    res = h.solve(case.t, 1e-10, block=block, seed=5, form="JD")
+    check_solution(res, ref if ref is not None else red, case.t, red.lam_all, 1e-10)
+    kry = h.solve(case.t, 1e-10, block=block, seed=5)
+    lam_j, lam_m = np.array(res.ritz), np.array(kry.ritz)
+    lam_tol = np.maximum(1e-10, 100 * U * red.lam_all[0] / red.lam)
+    assert np.all(np.abs(lam_j - lam_m) / lam_m <= lam_tol)
+    fl = O.accuracy_floor(red.lam_all, case.t)
+    assert O.sin_angle(host(res.X), host(kry.X)) <= max(1e-8, 100 * fl["span"])
+    h.close()
+
+
+def test_jd_argument_checks_and_iteration_limit(torch, eda, c1):
+    """The Jacobi-Davidson form refuses a float32 basis and reports
+    EDA_ERR_NOCONV (outputs still written) when max_iter outer steps do not
+    reach the tolerance."""
+    h, _, _ = prepared(torch, eda, c1)
+    r = h.solve(c1.t, 1e-10, form="JD", krylov_dtype="f32", raise_on_error=False)
+    assert r.status == eda.EDA_ERR_ARG
+    r = h.solve(c1.t, 1e-14, form="JD", max_iter=1, raise_on_error=False)
+    assert r.status == eda.EDA_ERR_NOCONV
+    assert r.info["iters"] == 1
+    assert np.all(np.isfinite(np.array(r.ritz)))
+    h.close()
+
+
 def test_aform_thick_restart_c2(torch, eda, c2):
     log("A-form solve C2 with a small basis (thick restarts)")
     red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
