@@ -171,7 +171,9 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k,
  *     Out = e^{-s} exp(c S_which) V,   s = max(0, c * lambda_max(S_which)),
  * with s written to *log_scale (host) so that exp(c S) V = e^{s} Out.
  * V: device d x b (ldv >= d); Out: device d x b (ldo >= d), must not overlap V.
- * vdtype: EDA_F64 (V and Out float64) or EDA_F32 (float32); the factor is
+ * vdtype: EDA_F64 (V and Out float64), EDA_F32 (float32) or, with bfloat16
+ * or FP8 storage, EDA_BF16 (bfloat16; products exact, sums in float32 per
+ * 32 rows and float64 beyond, Out rounded once to bfloat16); the factor is
  * read in the storage type of eda_prepare.
  * Stream-ordered; synchronises only when a core for a new c must be built. */
 eda_status eda_expmv(eda_handle h, eda_which which, double c, int64_t b,

@@ -250,7 +250,8 @@ class Handle:
 
     def _vblock(self, V, vdtype):
         V = colmajor(V)
-        want = self._torch.float64 if vdtype == "f64" else self._torch.float32
+        want = {"f64": self._torch.float64, "f32": self._torch.float32,
+                "bf16": self._torch.bfloat16}[vdtype]
         if V.dtype != want or V.device.type != "cuda":
             raise TypeError(f"expected a {want} CUDA tensor")
         return V

@@ -353,8 +353,10 @@ eda_status validate_block(eda_handle h, int64_t b, const void* V, int64_t ldv, c
                           int64_t ldo, eda_dtype vdtype) {
   if (b < 1 || b > (1 << 20)) return fail(h, EDA_ERR_ARG, "block width b=%lld out of range", (long long)b);
   if (V == nullptr || Out == nullptr) return fail(h, EDA_ERR_ARG, "null V or Out");
-  if (vdtype != EDA_F64 && vdtype != EDA_F32)
-    return fail(h, EDA_ERR_ARG, "vdtype must be EDA_F64 or EDA_F32");
+  if (vdtype != EDA_F64 && vdtype != EDA_F32 && vdtype != EDA_BF16)
+    return fail(h, EDA_ERR_ARG, "vdtype must be EDA_F64, EDA_F32 or EDA_BF16");
+  if (vdtype == EDA_BF16 && h->storage != EDA_BF16 && h->storage != EDA_FP8_E4M3)
+    return fail(h, EDA_ERR_ARG, "a bfloat16 block needs bfloat16 or FP8 storage");
   if (ldv < h->d || ldo < h->d) return fail(h, EDA_ERR_ARG, "ldv/ldo must be >= d");
   const size_t es = dsize(vdtype);
   const char* v0 = (const char*)V;

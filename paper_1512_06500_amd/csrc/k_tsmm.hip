@@ -398,17 +398,18 @@ __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int 
   }
 }
 
-// tn for a narrow A (FP8 E4M3 or bfloat16 codes) and a float32 B (nb <= 8)
-// on the bfloat16 matrix cores.  A workgroup owns 64 columns of A (4 tiles
-// of 16) and one row chunk of 256 S rows; slabs of 32 KB of A are staged
-// through LDS with whole-wave 16-byte loads (32 lanes down each column), and
-// each wave multiplies a quarter of every slab's rows for all 4 tiles.  FP8
-// codes are widened by the hardware E4M3 -> float32 conversion (exact) and
-// truncated to bfloat16 (exact: E4M3 values have 4 significant bits); B's
-// float32 values are split into three bfloat16 terms hi + mid + lo (exact to
-// float32's precision), so every product of v_mfma_f32_16x16x32_bf16 is
-// exact and each 32-row step is accumulated in float32 from zero and then
-// added into float64 accumulators.  The 4 waves' sums meet in LDS in a fixed
+// tn for a narrow A (FP8 E4M3 or bfloat16 codes) and a float32 or bfloat16
+// B (nb <= 8) on the bfloat16 matrix cores.  A workgroup owns 64 columns of
+// A (4 tiles of 16) and one row chunk of 256 S rows; slabs of 32 KB of A
+// (and the matching rows of B) are staged through LDS with whole-wave
+// 16-byte loads (32 lanes down each column), and each wave multiplies a
+// quarter of every slab's rows for all 4 tiles.  FP8 codes are widened by
+// the hardware E4M3 -> float32 conversion (exact) and truncated to bfloat16
+// (exact: E4M3 values have 4 significant bits); a float32 B is split into
+// three bfloat16 terms hi + mid + lo (exact to float32's precision), a
+// bfloat16 B is used as it is, so every product of
+// v_mfma_f32_16x16x32_bf16 is exact and each 32-row step is accumulated in
+// float32 from zero and then added into float64 accumulators.  The 4 waves' sums meet in LDS in a fixed
 // order, scaled by the per-column scales on output (tn_body's layout).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -439,44 +440,47 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint32_t w0, uint32_t w1) {
   return r;
 }
 
-template <typename TA, int S>
+template <typename TA, typename TB, int S>
 __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, int grp) {
   constexpr int SZ = (int)sizeof(TA);
+  constexpr int BZ = (int)sizeof(TB);        // 4 (float32 block) or 2 (bfloat16 block)
   constexpr int SR = 32768 / (64 * SZ);      // rows per slab: 512 (FP8), 256 (bfloat16)
   constexpr int CB = SR * SZ;                // bytes per column per slab (512)
   constexpr int CS = CB + 16;                // LDS column stride (bytes)
-  constexpr int BS = SR + 4;                 // LDS column stride of B (floats)
+  constexpr int BCB = SR * BZ;               // bytes per column of B per slab
+  constexpr int BS = BCB + 16;               // LDS column stride of B (bytes)
   constexpr int NSL = 256 * S / SR;          // slabs per chunk
   constexpr int WR = SR / 4;                 // rows per wave per slab
   constexpr int NKS = WR / 32;               // 32-row MFMA steps per wave per slab
-  constexpr int NBL = SR * 8 / 4 / 256;      // float4 loads of B per thread per slab
+  constexpr int BPC = BCB / 16;              // 16-byte pieces of B per column per slab
+  constexpr int NBL = 8 * BPC / 256;         // 16-byte loads of B per thread per slab
   static_assert(NSL >= 1 && (256 * S) % SR == 0, "a chunk must hold whole slabs");
-  static_assert(NBL >= 1 && (SR * 8 / 4) % 256 == 0, "B slab split over the workgroup");
+  static_assert(NBL >= 1 && (8 * BPC) % 256 == 0, "B slab split over the workgroup");
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   typedef const __attribute__((address_space(1))) u32x4* G4;
-  typedef const __attribute__((address_space(1))) f32x4* GF4;
+
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
   const int c0 = grp * 64;
   if (chunk >= a.chunks || c0 >= m) return;
   __shared__ __attribute__((aligned(16))) uint8_t As[64 * CS];
-  __shared__ __attribute__((aligned(16))) float Bs[8 * BS];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[8 * BS];
   static_assert(3 * 4 * 4 * 64 * 8 <= 64 * CS, "the wave sums must fit in the slab buffer");
   double(*red)[4][4][64] = (double(*)[4][4][64])As;  // reused after the last slab
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = lane & 15, kq = lane >> 4;
   const uint8_t* A = (const uint8_t*)a.A;
-  const float* B = (const float*)a.B;
+  const uint8_t* B = (const uint8_t*)a.B;
+  const int64_t ldb_b = a.ldb * BZ;
   const int64_t lda_b = a.lda * SZ;
   const int64_t R0 = chunk * (int64_t)(256 * S);
   // loads of a slab: A element e = tid + 256 u (u < 8) is column e / 32,
-  // bytes 16 (e % 32) .. + 15 of that column's CB; B group g = tid + 256 u
-  // (u < NBL) is column g / (SR / 4), rows 4 (g % (SR / 4)) .. + 3
+  // bytes 16 (e % 32) .. + 15 of that column's CB; B piece g = tid + 256 u
+  // (u < NBL) is column g / BPC, bytes 16 (g % BPC) .. + 15 of its BCB
   u32x4 ra[8];
-  f32x4 rbv[NBL];
+  u32x4 rbv[NBL];
   const u32x4 z4 = {0u, 0u, 0u, 0u};
-  const f32x4 zf4 = {0.f, 0.f, 0.f, 0.f};
   auto load = [&](int sl) {
     const int64_t r0 = R0 + (int64_t)sl * SR;
     const bool full = r0 + SR <= d;
@@ -508,18 +512,21 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
 #pragma unroll
     for (int u = 0; u < NBL; ++u) {
       const int g = tid + 256 * u;
-      const int col = g / (SR / 4), rr = 4 * (g % (SR / 4));
+      const int col = g / BPC, off = (g % BPC) * 16;
       const int cc = col < nb ? col : 0;
-      const float* p = B + (int64_t)cc * a.ldb + r0 + rr;
-      if (full && ((a.ldb & 3) == 0)) {
-        rbv[u] = *(GF4)p;
-      } else {
-        f32x4 v = zf4;
-        for (int q = 0; q < 4; ++q)
-          if (r0 + rr + q < d) v[q] = ((const __attribute__((address_space(1))) float*)p)[q];
-        rbv[u] = v;
+      const uint8_t* p = B + (int64_t)cc * ldb_b + r0 * BZ + off;
+      u32x4 v = z4;
+      const int64_t rfirst = r0 + off / BZ;
+      if (full || rfirst + 16 / BZ <= d) {
+        v = *(G4)p;
+      } else if (rfirst < d) {
+        const int keep = (int)((d - rfirst) * BZ);  // bytes of rows < d in this piece
+        uint8_t bytes[16];
+        for (int q = 0; q < 16; ++q)
+          bytes[q] = (q < keep) ? ((const __attribute__((address_space(1))) uint8_t*)p)[q] : 0;
+        __builtin_memcpy(&v, bytes, 16);
       }
-      if (col >= nb) rbv[u] = zf4;
+      rbv[u] = (col < nb) ? v : z4;
     }
   };
   double acc[4][4];
@@ -541,37 +548,43 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
 #pragma unroll
     for (int u = 0; u < NBL; ++u) {
       const int g = tid + 256 * u;
-      const int col = g / (SR / 4), rr = 4 * (g % (SR / 4));
-      *(f32x4*)(Bs + col * BS + rr) = rbv[u];
+      const int col = g / BPC, off = (g % BPC) * 16;
+      *(u32x4*)(Bs + col * BS + off) = rbv[u];
     }
     __syncthreads();
     if (sl + 1 < nsl) load(sl + 1);
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int rl = wid * WR + 32 * ks + 8 * kq;  // first of this lane's 8 rows in the slab
-      // B: rows rl .. + 7 of column i (zero past nb and past d), split into
-      // three bfloat16 terms
-      float bv[8];
+      // B: rows rl .. + 7 of column i (zero past nb and past d); a float32
+      // block is split into three bfloat16 terms, a bfloat16 one is used as is
+      constexpr int NT = (BZ == 4) ? 3 : 1;
+      bf16x8 bt[NT];
       {
-        const float* bp = Bs + (i < 8 ? i : 0) * BS + rl;
-        const f32x4 x0 = *(const f32x4*)bp;
-        const f32x4 x1 = *(const f32x4*)(bp + 4);
+        const uint8_t* bp = Bs + (i < 8 ? i : 0) * BS + rl * BZ;
+        if constexpr (BZ == 4) {
+          const f32x4 x0 = *(const f32x4*)bp;
+          const f32x4 x1 = *(const f32x4*)(bp + 16);
+          float bv[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          bv[e] = i < 8 ? x0[e] : 0.0f;
-          bv[4 + e] = i < 8 ? x1[e] : 0.0f;
+          for (int e = 0; e < 4; ++e) {
+            bv[e] = i < 8 ? x0[e] : 0.0f;
+            bv[4 + e] = i < 8 ? x1[e] : 0.0f;
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint16_t hb = bf16_rne_f32(bv[e]);
+            const float r1 = bv[e] - __uint_as_float((uint32_t)hb << 16);
+            const uint16_t mb = bf16_rne_f32(r1);
+            const float r2 = r1 - __uint_as_float((uint32_t)mb << 16);
+            bt[0][e] = bf16_of_bits(hb);
+            bt[NT - 2][e] = bf16_of_bits(mb);
+            bt[NT - 1][e] = bf16_of_bits(bf16_rne_f32(r2));
+          }
+        } else {
+          const u32x4 w = i < 8 ? *(const u32x4*)bp : z4;
+          __builtin_memcpy(&bt[0], &w, 16);
         }
-      }
-      bf16x8 bh, bm, bl;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint16_t h = bf16_rne_f32(bv[e]);
-        const float r1 = bv[e] - __uint_as_float((uint32_t)h << 16);
-        const uint16_t mm = bf16_rne_f32(r1);
-        const float r2 = r1 - __uint_as_float((uint32_t)mm << 16);
-        bh[e] = bf16_of_bits(h);
-        bm[e] = bf16_of_bits(mm);
-        bl[e] = bf16_of_bits(bf16_rne_f32(r2));
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -585,9 +598,9 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
           __builtin_memcpy(&av, &w, 16);
         }
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bm, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, c, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bt[q], c, 0, 0, 0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[t][v] += (double)c[v];
       }
@@ -618,12 +631,12 @@ __device__ __forceinline__ void tn_narrow_body(const TnArgs& a, int64_t chunk, i
   }
 }
 
-template <typename TA, int S>
+template <typename TA, typename TB, int S>
 __global__ __launch_bounds__(256) void tn_narrow_kernel(const TnArgs* __restrict__ arr,
                                                         TnArgs one) {
   const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
-  tn_narrow_body<TA, S>(a, blockIdx.x, blockIdx.y);
+  tn_narrow_body<TA, TB, S>(a, blockIdx.x, blockIdx.y);
 }
 
 template <int S>
@@ -1264,27 +1277,27 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
   if (cmax == 0) return hipSuccess;
   const TnArgs one = (count == 1) ? host[0] : TnArgs{};
   const TnArgs* arr = (count == 1) ? nullptr : dev;
-  if constexpr (sizeof(TA) <= 2 && std::is_same<TB, float>::value) {
-    // narrow A, float32 B of at most 8 columns, 16-byte aligned columns:
-    // the bfloat16 matrix cores (chunks of whole 32 KB slabs)
+  if constexpr (sizeof(TA) <= 2 && (std::is_same<TB, float>::value || sizeof(TB) == 2)) {
+    // narrow A, float32 or bfloat16 B of at most 8 columns, 16-byte aligned
+    // columns: the bfloat16 matrix cores (chunks of whole 32 KB slabs)
     constexpr int SR = 32768 / (64 * (int)sizeof(TA));
     static const bool off = std::getenv("EDA_NARROW_F64") != nullptr;
     bool ok = !off && (256 * S) % SR == 0;
     for (int p = 0; p < count && ok; ++p) {
       const TnArgs& a = host[p];
       ok = a.nb <= 8 && ((a.lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)a.A % 16 == 0) &&
-           (a.ldb % 4 == 0) && ((uintptr_t)a.B % 16 == 0);
+           ((a.ldb * (int64_t)sizeof(TB)) % 16 == 0) && ((uintptr_t)a.B % 16 == 0);
     }
     if (ok) {
       dim3 g((unsigned)cmax, (unsigned)((mmax + 63) / 64), (unsigned)count);
       if (S == 8)
-        hipLaunchKernelGGL((tn_narrow_kernel<TA, 8>), g, dim3(256), 0, s, arr, one);
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, TB, 8>), g, dim3(256), 0, s, arr, one);
       else if (S == 4)
-        hipLaunchKernelGGL((tn_narrow_kernel<TA, 4>), g, dim3(256), 0, s, arr, one);
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, TB, 4>), g, dim3(256), 0, s, arr, one);
       else if (S == 2)
-        hipLaunchKernelGGL((tn_narrow_kernel<TA, 2>), g, dim3(256), 0, s, arr, one);
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, TB, 2>), g, dim3(256), 0, s, arr, one);
       else if constexpr (sizeof(TA) == 2)
-        hipLaunchKernelGGL((tn_narrow_kernel<TA, 1>), g, dim3(256), 0, s, arr, one);
+        hipLaunchKernelGGL((tn_narrow_kernel<TA, TB, 1>), g, dim3(256), 0, s, arr, one);
       return hipGetLastError();
     }
   }
@@ -1527,6 +1540,8 @@ hipError_t launch_tn_multi(int count, const TnArgs* host, const TnArgs* dev, DT 
   if (adt == DT::BF16 && bdt == DT::F64) return tn_launch_t<bf, double>(count, host, dev, s);
   if (adt == DT::FP8 && bdt == DT::F32) return tn_launch_t<fp8e4m3, float>(count, host, dev, s);
   if (adt == DT::FP8 && bdt == DT::F64) return tn_launch_t<fp8e4m3, double>(count, host, dev, s);
+  if (adt == DT::BF16 && bdt == DT::BF16) return tn_launch_t<bf, bf>(count, host, dev, s);
+  if (adt == DT::FP8 && bdt == DT::BF16) return tn_launch_t<fp8e4m3, bf>(count, host, dev, s);
   return hipErrorInvalidValue;
 }
 
@@ -1580,6 +1595,8 @@ hipError_t launch_nn_multi(int count, const NnArgs* host, const NnArgs* dev, DT 
   NN_CASE(BF16, F64, F64, bf, double, double, double)
   NN_CASE(FP8, F32, F32, fp8e4m3, float, float, float)
   NN_CASE(FP8, F64, F64, fp8e4m3, double, double, double)
+  NN_CASE(BF16, BF16, BF16, bf, bf, bf, float)
+  NN_CASE(FP8, BF16, BF16, fp8e4m3, bf, bf, float)
 #undef NN_CASE
   return hipErrorInvalidValue;
 }

@@ -308,6 +308,50 @@ def test_expmv_narrow_lossless_float32_blocks(torch, eda, storage, d, n, k, b):
     h.close()
 
 
+@pytest.mark.parametrize("storage", ["fp8", "bf16"])
+@pytest.mark.parametrize("d,n,k,b", [(3001, 150, 7, 8), (20011, 333, 40, 3)])
+def test_expmv_narrow_bfloat16_blocks(torch, eda, storage, d, n, k, b):
+    """bfloat16 blocks against lossless FP8 / bfloat16 copies: the products
+    are exact and the sums run in float32 over 32 rows, then float64, so the
+    result is the exact exponential action of the block, rounded once to
+    bfloat16: within 2^-8 of the oracle normwise, and within one bfloat16
+    ulp of the float32-block result rounded to bfloat16, entry by entry."""
+    from oracle.bf16 import bf16_round
+    log(f"expmv {storage} lossless d={d} n={n} k={k} b={b} bfloat16 block")
+    rng = np.random.default_rng(d + 7 * n)
+    if storage == "fp8":
+        H_W = _e4m3_factor(rng, d, n, rng.integers(-13, -10, size=n))
+        H_B = _e4m3_factor(rng, d, k, rng.integers(-13, -11, size=k))
+    else:
+        H_W = bf16_round(rng.standard_normal((d, n)) * 2.0 ** -5)
+        H_B = bf16_round(rng.standard_normal((d, k)) * 2.0 ** -6)
+    h = eda.Handle()
+    h.prepare(dev(torch, H_W), dev(torch, H_B), storage=storage)
+    V = bf16_round(rng.standard_normal((d, b)))
+    for which, H, c in (("W", H_W, -0.5), ("B", H_B, 1.0)):
+        out, s = h.expmv(which, c, dev(torch, V).to(torch.bfloat16), vdtype="bf16")
+        o16 = host(out.float()).astype(np.float64)
+        out32, s32 = h.expmv(which, c, dev(torch, V).float(), vdtype="f32")
+        assert s == s32
+        o32 = bf16_round(host(out32).astype(np.float64))
+        ulp = np.abs(o32) * 2.0 ** -7 + 2.0 ** -133
+        assert np.all(np.abs(o16 - o32) <= ulp), np.abs(o16 - o32).max()
+        ref = O.exp_action_thm31(H, c, V)
+        E_norm = np.exp(max(0.0, c * np.linalg.norm(H, 2) ** 2))
+        err = rel_op_err(o16 * np.exp(s), ref, E_norm, V)
+        log(f"  {which} c={c} err={err:.2e}")
+        assert err <= 2.0 ** -8
+    h.close()
+
+
+def test_bfloat16_block_needs_narrow_storage(torch, eda, c1):
+    h, _, _ = prepared(torch, eda, c1)
+    V = torch.zeros(8, c1.d, dtype=torch.bfloat16, device="cuda").t()
+    with pytest.raises(eda.EDAError):
+        h.expmv("W", -0.5, V, vdtype="bf16")
+    h.close()
+
+
 def test_expmv_fp8_rounding_c1(torch, eda, c1):
     """FP8 storage of the C1 factors.  The two streaming passes read the
     E4M3 copy (scaled per column, rounded to nearest even) while the core
