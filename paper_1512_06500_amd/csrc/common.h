@@ -452,6 +452,20 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
 // (row-major, ld ldz).  Returns hipErrorInvalidValue when the shape does not
 // suit the split (the caller then uses launch_nn).
 int64_t nn_split_groups(int64_t m);
+// Out = alpha V + A Z for a narrow A (bfloat16 or FP8 codes, d x m, lda a
+// multiple of 8, column scales ascale or null) and nb <= 8: column groups
+// of A write float32 partial rows to `part` (at least
+// nn_narrow_split_groups(d, m) * d * 8 floats, 16-byte aligned), summed in a
+// fixed order by a second kernel that adds alpha V (alpha from alpha_p when
+// not null) and rounds to odt (== vdt, float32 or bfloat16: the sums are
+// float32).  hipErrorInvalidValue when the shape does not suit it (the
+// caller then uses launch_nn).
+int64_t nn_narrow_split_groups(int64_t d, int64_t m);
+hipError_t launch_nn_narrow_split(int64_t d, int64_t m, int64_t nb, const void* A, DT adt,
+                                  int64_t lda, const double* Z, int64_t ldz, double alpha,
+                                  const double* alpha_p, const void* V, DT vdt, int64_t ldv,
+                                  void* Out, DT odt, int64_t ldo, const double* ascale,
+                                  float* part, hipStream_t s);
 hipError_t launch_nn_split(int64_t m, int64_t nb, const double* C, int64_t ldc, const double* Y,
                            int64_t ldy, double* part, double* Z, int64_t ldz, hipStream_t s);
 hipError_t launch_nn(int64_t d, int64_t m, int64_t nb, const void* A, DT adt, int64_t lda,

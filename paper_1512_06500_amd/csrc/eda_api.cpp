@@ -131,6 +131,18 @@ eda_status expop_second(eda_handle h, bool master, int64_t c0, int64_t Nc, const
   if (!done)
     HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, ysm, ldy, 0.0, nullptr, DT::F64, 0, h->Zsm.d(),
                      DT::F64, b, nullptr, h->stream, true));
+  if ((pdt == DT::BF16 || pdt == DT::FP8) && (vdt == DT::F32 || vdt == DT::BF16) && b <= 8 &&
+      vdt == odt && h->ldp % 8 == 0) {
+    // narrow factor and block: column groups of P, float32 partial rows,
+    // fixed-order sum (a float64 block keeps float64 sums below)
+    STCHK(ensure(h, h->npart, (size_t)nn_narrow_split_groups(h->d, Nc) * h->d * 8 * 4));
+    const hipError_t e = launch_nn_narrow_split(h->d, Nc, b, Pc, pdt, h->ldp, h->Zsm.d(), b, alpha,
+                                                alpha_p, V, vdt, ldv, Out, odt, ldo, sc,
+                                                (float*)h->npart.p, h->stream);
+    if (e == hipSuccess) return EDA_OK;
+    if (e != hipErrorInvalidValue)
+      return fail(h, EDA_ERR_HIP, "launch_nn_narrow_split failed: %s", hipGetErrorString(e));
+  }
   HIPCHK(launch_nn(h->d, Nc, b, Pc, pdt, h->ldp, h->Zsm.d(), b, alpha, V, vdt, ldv, Out, odt,
                    ldo, nullptr, h->stream, false, alpha_p, sc));
   return EDA_OK;
@@ -433,7 +445,7 @@ void eda_destroy(eda_handle h) {
                   &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part, &h->zpart,
                   &h->Ysm, &h->Zsm, &h->PQ[0], &h->PQ[1], &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
-                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale, &h->warm};
+                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale, &h->warm, &h->npart};
     for (Buf& b : h->dir) release(b);
     for (Buf& b : h->af) release(b);
     for (Buf& b : h->nnp) release(b);

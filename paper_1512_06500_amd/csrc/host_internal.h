@@ -81,6 +81,7 @@ struct eda_handle_s {
   // workspaces
   eda::Buf part, Ysm, Zsm, syev_work, offs, flags, mask;
   eda::Buf zpart;  // column-group partials of the split core product Z = C Y
+  eda::Buf npart;  // float32 column-group partials of the narrow second pass
   std::vector<eda::CoreEntry> cores;
 
   // solver

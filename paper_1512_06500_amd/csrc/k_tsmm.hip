@@ -1242,6 +1242,169 @@ __global__ __launch_bounds__(256) void nn_narrow_kernel(const NnArgs* __restrict
   nn_narrow_body<TA, TV, TO, ACC>(a, blockIdx.x, blockIdx.y);
 }
 
+// Column-split nn for a narrow A (FP8 or bfloat16), nb <= 8: a workgroup
+// owns 512 rows (8 per lane, read with one 8- or 16-byte load per column, so
+// a wave instruction moves 512 or 1024 contiguous bytes) and one group of at
+// most NNS_KC columns of A; its 4 waves take every fourth column of the
+// group, 8 loads in flight each.  Z (scaled by the FP8 column scales) sits in
+// LDS as float32; products and sums are float32.  The waves' sums meet in
+// LDS in the fixed order (w0 + w1) + (w2 + w3), and each group writes its
+// partial rows (8 floats per row) to part + group * d * 8; nn_nsplit_finish
+// adds the groups in order, alpha V, and rounds to the output type.
+constexpr int NNS_R = 512;
+constexpr int NNS_KC = 1024;
+template <typename TA>
+__global__ __launch_bounds__(256) void nn_nsplit_kernel(int64_t d, int64_t m, int nb,
+                                                        const TA* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ Z, int64_t ldz,
+                                                        const double* __restrict__ ascale,
+                                                        int64_t kc, float* __restrict__ part) {
+  constexpr int NR = 8, BATCH = 8, LS = 68;  // LS: LDS floats per lane in the exchange
+  typedef uint32_t u32v2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t u32v4 __attribute__((ext_vector_type(4)));
+  using RAW = typename std::conditional<sizeof(TA) == 1, u32v2, u32v4>::type;
+  constexpr int ZN = (NNS_KC * 8 > 2 * 64 * LS) ? NNS_KC * 8 : 2 * 64 * LS;
+  __shared__ __attribute__((aligned(16))) float zs[ZN];  // Z, then the exchange
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t c0 = (int64_t)blockIdx.y * kc;
+  const int64_t c1 = (c0 + kc < m) ? c0 + kc : m;
+  const int tn = (int)(c1 - c0);
+  const int64_t row0 = (int64_t)blockIdx.x * NNS_R + 8 * lane;
+  for (int e = tid; e < tn * 8; e += 256) {
+    const int i = e >> 3, j = e & 7;
+    double z = (j < nb) ? Z[(c0 + i) * ldz + j] : 0.0;
+    if (ascale != nullptr) z *= ascale[c0 + i];
+    zs[e] = (float)z;
+  }
+  __syncthreads();
+  float acc[NR][8];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[r][j] = 0.0f;
+  if (row0 < lda) {  // rows d .. lda - 1 of A are zero padding
+    const char* abase = (const char*)A + row0 * (int64_t)sizeof(TA);
+    for (int i0 = w; i0 < tn; i0 += 4 * BATCH) {
+      RAW raw[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int ii = i0 + 4 * u;
+        const int ic = ii < tn ? ii : w;  // columns past the group: a valid column, weight 0
+        raw[u] = *(const __attribute__((address_space(1))) RAW*)(
+            abase + (c0 + ic) * lda * (int64_t)sizeof(TA));
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int ii = i0 + 4 * u;
+        float av[NR];
+        if constexpr (sizeof(TA) == 1) {
+          const uint32_t ws[2] = {raw[u].x, raw[u].y};
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)ws[q], false);
+            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)ws[q], true);
+            av[4 * q + 0] = lo.x;
+            av[4 * q + 1] = lo.y;
+            av[4 * q + 2] = hi.x;
+            av[4 * q + 3] = hi.y;
+          }
+        } else {
+          const uint32_t ws[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            av[r] = __uint_as_float(((ws[r >> 1] >> (16 * (r & 1))) & 0xffffu) << 16);
+        }
+        const float wgt = ii < tn ? 1.0f : 0.0f;
+        const f32x4 z0 = *(const f32x4*)(zs + 8 * (ii < tn ? ii : 0));
+        const f32x4 z1 = *(const f32x4*)(zs + 8 * (ii < tn ? ii : 0) + 4);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const float x = av[r] * wgt;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc[r][j] = fmaf(x, z0[j], acc[r][j]);
+            acc[r][4 + j] = fmaf(x, z1[j], acc[r][4 + j]);
+          }
+        }
+      }
+    }
+  }
+  // (w0 + w1) + (w2 + w3) through LDS (the Z buffer is free once all waves
+  // are past their columns)
+  __syncthreads();
+  float* xb = zs + (size_t)lane * LS;
+  if (w == 1 || w == 3) {
+    float* dst = xb + (w == 3 ? 64 * LS : 0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[8 * r + j] = acc[r][j];
+  }
+  __syncthreads();
+  if (w == 0 || w == 2) {
+    const float* src = xb + (w == 2 ? 64 * LS : 0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[r][j] += src[8 * r + j];
+  }
+  __syncthreads();
+  if (w == 2)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xb[8 * r + j] = acc[r][j];
+  __syncthreads();
+  if (w == 0) {
+    float* out = part + ((int64_t)blockIdx.y * d + row0) * 8;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (row0 + r >= d) break;
+      f32x4 o0, o1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        o0[j] = acc[r][j] + xb[8 * r + j];
+        o1[j] = acc[r][4 + j] + xb[8 * r + 4 + j];
+      }
+      *(f32x4*)(out + 8 * r) = o0;
+      *(f32x4*)(out + 8 * r + 4) = o1;
+    }
+  }
+}
+
+// Out(row, j) = alpha V(row, j) + sum over the groups, in group order.
+template <typename TV, typename TO>
+__global__ __launch_bounds__(256) void nn_nsplit_finish(int64_t d, int nb, int64_t groups,
+                                                        const float* __restrict__ part,
+                                                        double alpha,
+                                                        const double* __restrict__ alpha_p,
+                                                        const TV* __restrict__ V, int64_t ldv,
+                                                        TO* __restrict__ Out, int64_t ldo) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= d) return;
+  const double al = (alpha_p != nullptr) ? *alpha_p : alpha;
+  double sacc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) sacc[j] = 0.0;
+  for (int64_t g = 0; g < groups; ++g) {
+    const f32x4 p0 = *(const f32x4*)(part + (g * d + row) * 8);
+    const f32x4 p1 = *(const f32x4*)(part + (g * d + row) * 8 + 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      sacc[j] += (double)p0[j];
+      sacc[4 + j] += (double)p1[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (j >= nb) break;
+    double o = sacc[j];
+    if (al != 0.0 && V != nullptr) o += al * to_f64<TV>(V[row + (int64_t)j * ldv]);
+    Out[row + (int64_t)j * ldo] = from_f64<TO>(o);
+  }
+}
+
 // 64 S rows per wave, 4 waves per workgroup: the tuned value for this
 // shape class when there is one, else S = 8 when that still gives 4096
 // workgroups (long factors: fewer partial sums), else S = 4 when that still
@@ -1609,6 +1772,51 @@ int64_t nn_split_groups(int64_t m) {
   g = std::max<int64_t>(1, std::min(g, (m + 63) / 64));
   const int64_t kc = (m + g - 1) / g;
   return (m + kc - 1) / kc;
+}
+
+int64_t nn_narrow_split_groups(int64_t d, int64_t m) {
+  // about 512 workgroups, column groups of at least 64 and at most NNS_KC
+  // (the pass is bound by its float32 FMAs, 8 per factor entry, so more
+  // groups only add partial rows)
+  const int64_t rb = (d + NNS_R - 1) / NNS_R;
+  int64_t g = (512 + rb - 1) / rb;
+  g = std::max<int64_t>(g, (m + NNS_KC - 1) / NNS_KC);
+  g = std::min<int64_t>(g, std::max<int64_t>(1, (m + 63) / 64));
+  g = std::max<int64_t>(g, (m + NNS_KC - 1) / NNS_KC);
+  const int64_t kc = (m + g - 1) / g;
+  return (m + kc - 1) / kc;
+}
+
+hipError_t launch_nn_narrow_split(int64_t d, int64_t m, int64_t nb, const void* A, DT adt,
+                                  int64_t lda, const double* Z, int64_t ldz, double alpha,
+                                  const double* alpha_p, const void* V, DT vdt, int64_t ldv,
+                                  void* Out, DT odt, int64_t ldo, const double* ascale,
+                                  float* part, hipStream_t s) {
+  if (d <= 0 || nb <= 0) return hipSuccess;
+  if (m <= 0 || nb > 8 || (adt != DT::BF16 && adt != DT::FP8) || vdt != odt || vdt == DT::F64 ||
+      (lda % 8) != 0 || ((uintptr_t)A % 16) != 0 || ((uintptr_t)part % 16) != 0)
+    return hipErrorInvalidValue;
+  const int64_t groups = nn_narrow_split_groups(d, m);
+  const int64_t kc = (m + groups - 1) / groups;
+  if (kc > NNS_KC) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((d + NNS_R - 1) / NNS_R), (unsigned)groups);
+  if (adt == DT::FP8)
+    hipLaunchKernelGGL(nn_nsplit_kernel<fp8e4m3>, g, dim3(256), 0, s, d, m, (int)nb,
+                       (const fp8e4m3*)A, lda, Z, ldz, ascale, kc, part);
+  else
+    hipLaunchKernelGGL(nn_nsplit_kernel<__hip_bfloat16>, g, dim3(256), 0, s, d, m, (int)nb,
+                       (const __hip_bfloat16*)A, lda, Z, ldz, ascale, kc, part);
+  const dim3 gf((unsigned)((d + 255) / 256));
+  using bf = __hip_bfloat16;
+  if (odt == DT::F32)
+    hipLaunchKernelGGL((nn_nsplit_finish<float, float>), gf, dim3(256), 0, s, d, (int)nb, groups,
+                       part, alpha, alpha_p, (const float*)V, ldv, (float*)Out, ldo);
+  else if (odt == DT::BF16)
+    hipLaunchKernelGGL((nn_nsplit_finish<bf, bf>), gf, dim3(256), 0, s, d, (int)nb, groups, part,
+                       alpha, alpha_p, (const bf*)V, ldv, (bf*)Out, ldo);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_nn_split(int64_t m, int64_t nb, const double* C, int64_t ldc, const double* Y,
