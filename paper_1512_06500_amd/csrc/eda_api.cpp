@@ -131,8 +131,7 @@ eda_status expop_second(eda_handle h, bool master, int64_t c0, int64_t Nc, const
   if (!done)
     HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, ysm, ldy, 0.0, nullptr, DT::F64, 0, h->Zsm.d(),
                      DT::F64, b, nullptr, h->stream, true));
-  if ((pdt == DT::BF16 || pdt == DT::FP8) && (vdt == DT::F32 || vdt == DT::BF16) && b <= 8 &&
-      vdt == odt && h->ldp % 8 == 0) {
+  if (narrow_split(pdt, vdt, odt, b, h->ldp)) {
     // narrow factor and block: column groups of P, float32 partial rows,
     // fixed-order sum (a float64 block keeps float64 sums below)
     STCHK(ensure(h, h->npart, (size_t)nn_narrow_split_groups(h->d, Nc) * h->d * 8 * 4));

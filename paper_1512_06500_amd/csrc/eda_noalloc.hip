@@ -92,7 +92,9 @@ extern "C" eda_status eda_opmv_noalloc(eda_handle h, eda_form form, int64_t b, c
   const size_t y_b = align256((size_t)N * b * 8);
   const size_t z_b = align256((size_t)N * b * 8);
   const size_t zp_b = split ? align256((size_t)nn_split_groups(N) * N * b * 8) : 0;
-  const size_t need = part_b + y_b + z_b + zp_b;
+  const bool nsplit = narrow_split(pdt, vdt, vdt, b, h->ldp);
+  const size_t np_b = nsplit ? align256((size_t)nn_narrow_split_groups(d, N) * d * 8 * 4) : 0;
+  const size_t need = part_b + y_b + z_b + zp_b + np_b;
   if (need > kScratchBytes)
     return fail(h, EDA_ERR_ARG,
                 "this product needs %zu bytes of scratch, more than the %zu of eda_opmv_noalloc "
@@ -103,6 +105,7 @@ extern "C" eda_status eda_opmv_noalloc(eda_handle h, eda_form form, int64_t b, c
   double* ysm = (double*)(sp + part_b);
   double* zsm = (double*)(sp + part_b + y_b);
   double* zpart = (double*)(sp + part_b + y_b + z_b);
+  float* npart = (float*)(sp + part_b + y_b + z_b + zp_b);
   const double* sc = (pdt == DT::FP8) ? h->pscale.d() : nullptr;
   hipStream_t s = h->stream;
   HIPCHK(launch_tn_partial(d, N, b, h->P.p, pdt, h->ldp, V, vdt, ldv, part, chunks, nullptr, s, sc));
@@ -112,8 +115,16 @@ extern "C" eda_status eda_opmv_noalloc(eda_handle h, eda_form form, int64_t b, c
   else
     HIPCHK(launch_nn(N, N, b, C, DT::F64, N, ysm, b, 0.0, nullptr, DT::F64, 0, zsm, DT::F64, b,
                      nullptr, s, true));
-  HIPCHK(launch_nn(d, N, b, h->P.p, pdt, h->ldp, zsm, b, h->alphaB, V, vdt, ldv, Out, vdt, ldo,
-                   nullptr, s, false, nullptr, sc));
+  // the second pass as eda_opmv takes it
+  hipError_t e2 = hipErrorInvalidValue;
+  if (nsplit)
+    e2 = launch_nn_narrow_split(d, N, b, h->P.p, pdt, h->ldp, zsm, b, h->alphaB, nullptr, V, vdt,
+                                ldv, Out, vdt, ldo, sc, npart, s);
+  if (e2 == hipErrorInvalidValue)
+    HIPCHK(launch_nn(d, N, b, h->P.p, pdt, h->ldp, zsm, b, h->alphaB, V, vdt, ldv, Out, vdt, ldo,
+                     nullptr, s, false, nullptr, sc));
+  else if (e2 != hipSuccess)
+    return fail(h, EDA_ERR_HIP, "launch_nn_narrow_split failed: %s", hipGetErrorString(e2));
   if (log_scale != nullptr) *log_scale = h->shiftB;
   return EDA_OK;
 }

@@ -200,6 +200,12 @@ eda_status rr_block(eda_handle h, int64_t d, int64_t ld, int64_t w, int64_t t, i
 // eda_solve by block Jacobi-Davidson (eda_jd.cpp); arguments already checked.
 eda_status solve_jd(eda_handle h, int32_t t, double tol, const eda_solve_opts& o, double* ritz,
                     double* ritz_log, double* X, int64_t ldx, double* resid, eda_info* info);
+// Whether the second pass of a product over a narrow factor takes the
+// column-split kernel (launch_nn_narrow_split) with float32 partial rows.
+inline bool narrow_split(DT pdt, DT vdt, DT odt, int64_t b, int64_t ldp) {
+  return (pdt == DT::BF16 || pdt == DT::FP8) && (vdt == DT::F32 || vdt == DT::BF16) && b <= 8 &&
+         vdt == odt && ldp % 8 == 0;
+}
 // Looks up, once per device, the device address of the scratch array of
 // eda_opmv_noalloc (eda_noalloc.hip); the device must be current.
 hipError_t noalloc_init_device(int device);

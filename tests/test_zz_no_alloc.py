@@ -1,7 +1,8 @@
 """The allocation-free product entry point (eda_opmv_noalloc) against
 eda_opmv, through the C ABI: identical bits on two calls in a row (the
 second with a smaller block), on a second, smaller problem, in both
-operator forms and with float32 blocks; oversized products are refused."""
+operator forms, with float32 and bfloat16 blocks and with narrow factors;
+oversized products are refused."""
 import sys
 
 import numpy as np
@@ -33,12 +34,12 @@ def eda(torch):
     return m
 
 
-def _prepared(torch, eda, name):
+def _prepared(torch, eda, name, storage="f64"):
     p = datagen.config(name)
     h = eda.Handle()
     Xd = torch.from_numpy(np.ascontiguousarray(p.X.T)).cuda().t()
     HW, HB = h.scatter_factors(Xd, p.counts.tolist())
-    h.prepare(HW, HB)
+    h.prepare(HW, HB, storage=storage)
     return h, p
 
 
@@ -69,6 +70,18 @@ def test_noalloc_matches_opmv_two_calls_then_smaller(torch, eda):
     log(f"no-alloc product on the smaller d={p1.d} N={p1.n + p1.k}: b=2")
     _compare(torch, h1, "M", _block(torch, p1.d, 2, 6, torch.float64), "f64")
     h1.close()
+
+
+@pytest.mark.parametrize("storage,vdtype", [("bf16", "f32"), ("fp8", "bf16"), ("fp8", "f64")])
+def test_noalloc_matches_opmv_narrow_storage(torch, eda, storage, vdtype):
+    """Narrow factors: the second pass of both entry points takes the same
+    kernel (column-split with float32 partials for narrow blocks)."""
+    h, p = _prepared(torch, eda, "C3", storage)
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}[vdtype]
+    log(f"no-alloc product, {storage} factor d={p.d} N={p.n + p.k}, {vdtype} blocks b=8 then b=5")
+    _compare(torch, h, "M", _block(torch, p.d, 8, 11, torch.float32).to(dt), vdtype)
+    _compare(torch, h, "M", _block(torch, p.d, 5, 12, torch.float32).to(dt), vdtype)
+    h.close()
 
 
 def test_noalloc_refuses_oversized_and_unbuilt_core(torch, eda):
