@@ -312,8 +312,9 @@ typedef struct {
  * storage or a float32 basis, a problem whose float64 refinement passes
  * stall continues by eda_solve in float64 on its own handle, with its
  * float64 master as the storage (no new Gram or cores) and a start block
- * mixed from its refined Ritz block (EDA_WARN_FALLBACK; its iterations are
- * added to iters).  Uses the
+ * mixed from its refined Ritz block (EDA_WARN_FALLBACK; its block steps,
+ * restarts, passes, products, bytes and times are added to the problem's
+ * info).  Uses the
  * handle's stream and workspaces; does not change the handle's own
  * preparation.  Synchronises. */
 eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_problem* probs,

@@ -1267,10 +1267,17 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
       I.op_calls = P.op_calls;
       I.t_op_ms = P.t_op_ms;
       I.op_bytes = 2.0 * P.d * P.N * dsize(storage) + 3.0 * P.d * b * qs;
-      if (fell_back) {
+      if (fell_back) {  // the float64 continuation's work is part of this problem's
         I.iters += fb.iters;
         I.restarts += fb.restarts;
+        I.refine_passes += fb.refine_passes;
         I.flags = fb.flags | EDA_WARN_FALLBACK;
+        I.ops += fb.ops;
+        I.bytes_moved += fb.bytes_moved;
+        I.t_krylov_ms += fb.t_krylov_ms;
+        I.t_refine_ms += fb.t_refine_ms;
+        I.op_calls += fb.op_calls;
+        I.t_op_ms += fb.t_op_ms;
       }
     }
     if (statuses != nullptr) statuses[p] = stat[p];
