@@ -452,6 +452,14 @@ hipError_t launch_reduce_partials(int64_t chunks, int64_t m, int64_t nb, const d
 // (row-major, ld ldz).  Returns hipErrorInvalidValue when the shape does not
 // suit the split (the caller then uses launch_nn).
 int64_t nn_split_groups(int64_t m);
+// k_jd.hip: the lockstep GMRES of the Jacobi-Davidson inner solve (c <= 64
+// columns, k <= 8 steps; H: c Hessenberg matrices of (k+1) x k, see there).
+hipError_t launch_jd_gs_coeffs(int blocks, int c, int k, int l, const double* G, double* D,
+                               double* H, hipStream_t s);
+hipError_t launch_jd_norms(int c, int k, int l, const double* G, double tiny, double* S,
+                           double* H, hipStream_t s);
+hipError_t launch_jd_gmres_ls(int c, int k, const double* H, const double* beta, double* Y,
+                              hipStream_t s);
 // Out = alpha V + A Z for a narrow A (bfloat16 or FP8 codes, d x m, lda a
 // multiple of 8, column scales ascale or null) and nb <= 8: column groups
 // of A write float32 partial rows to `part` (at least

@@ -29,108 +29,16 @@ namespace {
 
 constexpr int kInner = 4;  // GMRES steps per correction
 
-// Column-wise Gram-Schmidt of W (c columns) against blocks U_0 .. U_{blocks-1}
-// of c columns each (column j of every block belongs to column j of W):
-// g[p c + j] = U_p(:, j)^T W(:, j) is added to acc (host) and W(:, j) -=
-// sum_p g[p c + j] U_p(:, j).  Gd, Dd: device scratch of blocks c^2 doubles.
-eda_status colwise_gs(eda_handle h, int64_t d, int64_t ldq, const double* U, int64_t blocks,
-                      int64_t c, double* W, double* acc, double* Gd, double* Dd) {
-  hipStream_t s = h->stream;
-  const int64_t m = blocks * c;
-  const int64_t chunks = tn_chunks(d, m, c);
-  STCHK(ensure(h, h->part, (size_t)chunks * m * c * 8));
-  HIPCHK(launch_tn_partial(d, m, c, U, DT::F64, ldq, W, DT::F64, ldq, h->part.d(), chunks, nullptr,
-                           s));
-  HIPCHK(launch_reduce_partials(chunks, m, c, h->part.d(), 1.0, 0.0, Gd, m, 0.0, nullptr, 0,
-                                nullptr, s));
-  std::vector<double> G((size_t)m * c), D((size_t)m * c, 0.0);
-  HIPCHK(hipMemcpyAsync(G.data(), Gd, G.size() * 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (int64_t p = 0; p < blocks; ++p)
-    for (int64_t j = 0; j < c; ++j) {
-      const double g = G[(size_t)(p * c + j) + (size_t)j * m];
-      D[(size_t)(p * c + j) * c + j] = -g;
-      acc[p * c + j] += g;
-    }
-  HIPCHK(hipMemcpyAsync(Dd, D.data(), D.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(launch_nn(d, m, c, U, DT::F64, ldq, Dd, c, 1.0, W, DT::F64, ldq, W, DT::F64, ldq, nullptr,
-                   s));
-  HIPCHK(hipStreamSynchronize(s));  // D is a host temporary
+// Gram block X^T Y (rows x c, column-major, leading dimension rows) into G.
+eda_status gram_block(eda_handle h, int64_t d, int64_t ldq, const double* X, int64_t rows,
+                      const double* Y, int64_t c, double* G) {
+  const int64_t chunks = tn_chunks(d, rows, c);
+  STCHK(ensure(h, h->part, (size_t)chunks * rows * c * 8));
+  HIPCHK(launch_tn_partial(d, rows, c, X, DT::F64, ldq, Y, DT::F64, ldq, h->part.d(), chunks,
+                           nullptr, h->stream));
+  HIPCHK(launch_reduce_partials(chunks, rows, c, h->part.d(), 1.0, 0.0, G, rows, 0.0, nullptr, 0,
+                                nullptr, h->stream));
   return EDA_OK;
-}
-
-// Column norms of W (c columns) on the host.
-eda_status col_norms(eda_handle h, int64_t d, int64_t ldq, const double* W, int64_t c, double* Gd,
-                     double* out) {
-  hipStream_t s = h->stream;
-  const int64_t chunks = tn_chunks(d, c, c);
-  STCHK(ensure(h, h->part, (size_t)chunks * c * c * 8));
-  HIPCHK(launch_tn_partial(d, c, c, W, DT::F64, ldq, W, DT::F64, ldq, h->part.d(), chunks, nullptr,
-                           s));
-  HIPCHK(launch_reduce_partials(chunks, c, c, h->part.d(), 1.0, 0.0, Gd, c, 0.0, nullptr, 0,
-                                nullptr, s));
-  std::vector<double> G((size_t)c * c);
-  HIPCHK(hipMemcpyAsync(G.data(), Gd, G.size() * 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (int64_t j = 0; j < c; ++j) out[j] = std::sqrt(std::max(G[(size_t)j * c + j], 0.0));
-  return EDA_OK;
-}
-
-// Out(:, j) = sum_q A(:, q) Dm(q, j) with a host matrix Dm (rows x c,
-// row-major), copied to the device scratch Dd.
-eda_status combine(eda_handle h, int64_t d, int64_t ldq, const double* A, int64_t rows, int64_t c,
-                   const std::vector<double>& Dm, double* Dd, double alpha, const double* V,
-                   double* Out) {
-  hipStream_t s = h->stream;
-  HIPCHK(hipMemcpyAsync(Dd, Dm.data(), Dm.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(launch_nn(d, rows, c, A, DT::F64, ldq, Dd, c, alpha, V, DT::F64, ldq, Out, DT::F64, ldq,
-                   nullptr, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return EDA_OK;
-}
-
-// min || beta e_1 - H y || over y in R^k for the (k+1) x k Hessenberg H
-// (column-major, leading dimension ldh) by Givens rotations; columns from
-// the first zero subdiagonal entry on are dropped (the Krylov space became
-// invariant there and the system is solved).
-void gmres_ls(int k, const double* H, int ldh, double beta, double* y) {
-  std::vector<double> R((size_t)(k + 1) * k, 0.0);
-  for (int l = 0; l < k; ++l)
-    for (int p = 0; p <= l + 1; ++p) R[(size_t)l * (k + 1) + p] = H[(size_t)l * ldh + p];
-  std::vector<double> g(k + 1, 0.0), cs(k, 1.0), sn(k, 0.0);
-  g[0] = beta;
-  int kk = k;
-  for (int l = 0; l < k; ++l) {
-    double* col = R.data() + (size_t)l * (k + 1);
-    for (int p = 0; p < l; ++p) {
-      const double a = col[p], b2 = col[p + 1];
-      col[p] = cs[p] * a + sn[p] * b2;
-      col[p + 1] = -sn[p] * a + cs[p] * b2;
-    }
-    const double a = col[l], b2 = col[l + 1];
-    const double r = std::hypot(a, b2);
-    if (!(r > 0.0)) {
-      kk = l;
-      break;
-    }
-    cs[l] = a / r;
-    sn[l] = b2 / r;
-    col[l] = r;
-    col[l + 1] = 0.0;
-    const double g0 = g[l];
-    g[l] = cs[l] * g0;
-    g[l + 1] = -sn[l] * g0;
-    if (b2 == 0.0) {
-      kk = l + 1;
-      break;
-    }
-  }
-  for (int l = 0; l < k; ++l) y[l] = 0.0;
-  for (int l = kk - 1; l >= 0; --l) {
-    double sacc = g[l];
-    for (int q = l + 1; q < kk; ++q) sacc -= R[(size_t)q * (k + 1) + l] * y[q];
-    y[l] = sacc / R[(size_t)l * (k + 1) + l];
-  }
 }
 
 }  // namespace
@@ -159,7 +67,11 @@ eda_status solve_jd(eda_handle h, int32_t t, double tol, const eda_solve_opts& o
   STCHK(ensure(h, h->af[3], (size_t)ldq * wmax * 8));
   STCHK(ensure(h, h->af[4], (size_t)ldq * nk * 8));
   STCHK(ensure(h, h->af[5], (size_t)ldq * (KC + b) * 8));
-  STCHK(ensure(h, h->af[6], (size_t)(2 * KC * b + 4 * wmax * wmax) * 8));
+  // device scratch: Gram blocks, update and scale matrices, the Hessenberg
+  // matrices of the c columns, and the per-step inputs (U_0 mixing, -theta,
+  // beta) uploaded from pinned memory once per outer step
+  const int64_t nstage = nk * b + b * b + b;
+  STCHK(ensure(h, h->af[6], (size_t)(2 * KC * b + b * b + b * (kInner + 1) * kInner + nstage) * 8));
   double* Bv[2] = {h->af[0].d(), h->af[2].d()};
   double* MBv[2] = {h->af[1].d(), h->af[3].d()};
   double* R = h->af[4].d();
@@ -167,6 +79,18 @@ eda_status solve_jd(eda_handle h, int32_t t, double tol, const eda_solve_opts& o
   double* W = U + (size_t)ldq * KC;
   double* Gd = h->af[6].d();
   double* Dd = Gd + KC * b;
+  double* Sg = Dd + KC * b;
+  double* Hd = Sg + b * b;
+  double* stage_d = Hd + b * (kInner + 1) * kInner;
+  double* stage_h = nullptr;
+  if (hipHostMalloc((void**)&stage_h, (size_t)nstage * 8, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, EDA_ERR_NOMEM, "pinned staging of %lld doubles failed", (long long)nstage);
+  }
+  struct PinGuard {
+    double* p;
+    ~PinGuard() { (void)hipHostFree(p); }
+  } pin_guard{stage_h};
   STCHK(ensure(h, h->T, (size_t)mm * mm * 8));
   STCHK(ensure(h, h->wT, (size_t)mm * 8));
   STCHK(ensure(h, h->S, (size_t)mm * mm * 8));
@@ -251,56 +175,56 @@ eda_status solve_jd(eda_handle h, int32_t t, double tol, const eda_solve_opts& o
     ++iters;
     // 2. corrections for the first c open pairs
     const int64_t c = std::min<int64_t>(b, (int64_t)open.size());
-    // U_0 = -r_i / ||r_i||
+    // per-step inputs: U_0 = -r_i / ||r_i|| as a mixing of the residuals,
+    // -theta_i on a diagonal, beta_i = ||r_i||
     {
-      std::vector<double> Dm((size_t)kept * c, 0.0);
+      double* mix = stage_h;
+      double* mth = stage_h + kept * c;
+      double* beta = mth + c * c;
+      std::fill(stage_h, stage_h + kept * c + c * c + c, 0.0);
       for (int64_t j = 0; j < c; ++j) {
         const int64_t i = open[j];
-        Dm[(size_t)i * c + j] = res[i] > 0.0 ? -1.0 / res[i] : 0.0;
+        mix[i * c + j] = res[i] > 0.0 ? -1.0 / res[i] : 0.0;
+        mth[j * c + j] = -theta[i];
+        beta[j] = res[i];
       }
-      STCHK(combine(h, d, ldq, R, kept, c, Dm, Dd, 0.0, nullptr, U));
+      HIPCHK(hipMemcpyAsync(stage_d, stage_h, (size_t)(kept * c + c * c + c) * 8,
+                            hipMemcpyHostToDevice, s));
     }
-    std::vector<double> Hh((size_t)c * (kInner + 1) * kInner, 0.0);  // per column (k+1) x k
-    std::vector<double> nrm(c), acc((size_t)(kInner + 1) * c);
-    std::vector<double> mth((size_t)c * c, 0.0);
-    for (int64_t j = 0; j < c; ++j) mth[(size_t)j * c + j] = -theta[open[j]];
-    int steps = 0;
+    const double* mix_d = stage_d;
+    const double* mth_d = stage_d + kept * c;
+    const double* beta_d = mth_d + c * c;
+    HIPCHK(launch_nn(d, kept, c, R, DT::F64, ldq, mix_d, c, 0.0, nullptr, DT::F64, ldq, U, DT::F64,
+                     ldq, nullptr, s));
+    HIPCHK(launch_fill(c * (kInner + 1) * kInner, 0.0, Hd, s));
+    const double tiny = 1e-14 * std::fabs(theta[0]);
     for (int l = 0; l < kInner; ++l) {
       double* Ul = U + (size_t)l * c * ldq;
       // W = (e^{-s} M - theta I) U_l, projected against the kept Ritz vectors
       STCHK(expop(h, true, 0, N, h->CM.d(), N, h->alphaB, c, Ul, DT::F64, ldq, W, DT::F64, ldq));
       ops += c;
-      STCHK(combine(h, d, ldq, Ul, c, c, mth, Dd, 1.0, W, W));
+      HIPCHK(launch_nn(d, c, c, Ul, DT::F64, ldq, mth_d, c, 1.0, W, DT::F64, ldq, W, DT::F64, ldq,
+                       nullptr, s));
       STCHK(cgs_pass(h, d, kept, Y, DT::F64, ldq, W, ldq, c, nullptr, 0, 0.0, nullptr));
-      // Arnoldi coefficients against U_0 .. U_l (classical Gram-Schmidt, twice)
-      std::fill(acc.begin(), acc.end(), 0.0);
-      STCHK(colwise_gs(h, d, ldq, U, l + 1, c, W, acc.data(), Gd, Dd));
-      STCHK(colwise_gs(h, d, ldq, U, l + 1, c, W, acc.data(), Gd, Dd));
-      STCHK(col_norms(h, d, ldq, W, c, Gd, nrm.data()));
-      std::vector<double> sc((size_t)c * c, 0.0);
-      for (int64_t j = 0; j < c; ++j) {
-        double* Hj = Hh.data() + (size_t)j * (kInner + 1) * kInner;
-        for (int p = 0; p <= l; ++p) Hj[(size_t)l * (kInner + 1) + p] = acc[(size_t)p * c + j];
-        // a column whose Krylov space became invariant stops (zero next vector)
-        const bool stop = !(nrm[j] > 1e-14 * std::fabs(theta[0]));
-        Hj[(size_t)l * (kInner + 1) + l + 1] = stop ? 0.0 : nrm[j];
-        sc[(size_t)j * c + j] = stop ? 0.0 : 1.0 / nrm[j];
+      // Arnoldi coefficients against U_0 .. U_l (column-wise classical
+      // Gram-Schmidt, twice), the norm and the next basis block
+      for (int pass = 0; pass < 2; ++pass) {
+        STCHK(gram_block(h, d, ldq, U, (l + 1) * c, W, c, Gd));
+        HIPCHK(launch_jd_gs_coeffs(l + 1, (int)c, kInner, l, Gd, Dd, Hd, s));
+        HIPCHK(launch_nn(d, (l + 1) * c, c, U, DT::F64, ldq, Dd, c, 1.0, W, DT::F64, ldq, W,
+                         DT::F64, ldq, nullptr, s));
       }
-      STCHK(combine(h, d, ldq, W, c, c, sc, Dd, 0.0, nullptr, U + (size_t)(l + 1) * c * ldq));
-      steps = l + 1;
+      STCHK(gram_block(h, d, ldq, W, c, W, c, Gd));
+      HIPCHK(launch_jd_norms((int)c, kInner, l, Gd, tiny, Sg, Hd, s));
+      HIPCHK(launch_nn(d, c, c, W, DT::F64, ldq, Sg, c, 0.0, nullptr, DT::F64, ldq,
+                       U + (size_t)(l + 1) * c * ldq, DT::F64, ldq, nullptr, s));
     }
     // z_j = sum_l y_j[l] U_l(:, j), y_j from the small least-squares problems
-    // (right-hand side ||-r_j|| e_1 in the basis U_0 = -r_j / ||r_j||)
-    {
-      std::vector<double> Dm((size_t)steps * c * c, 0.0), y(kInner);
-      for (int64_t j = 0; j < c; ++j) {
-        gmres_ls(steps, Hh.data() + (size_t)j * (kInner + 1) * kInner, kInner + 1, res[open[j]],
-                 y.data());
-        for (int l = 0; l < steps; ++l) Dm[(size_t)(l * c + j) * c + j] = y[l];
-      }
-      // the corrections go to the search-space slots after the kept vectors
-      STCHK(combine(h, d, ldq, U, steps * c, c, Dm, Dd, 0.0, nullptr, Y + (size_t)kept * ldq));
-    }
+    // (right-hand side ||r_j|| e_1 in the basis U_0 = -r_j / ||r_j||); the
+    // corrections go to the search-space slots after the kept vectors
+    HIPCHK(launch_jd_gmres_ls((int)c, kInner, Hd, beta_d, Dd, s));
+    HIPCHK(launch_nn(d, kInner * c, c, U, DT::F64, ldq, Dd, c, 0.0, nullptr, DT::F64, ldq,
+                     Y + (size_t)kept * ldq, DT::F64, ldq, nullptr, s));
     // 3. orthonormalise the corrections against the kept Ritz vectors and
     // among themselves (rank revealing: a correction already inside the
     // space is replaced by a random direction), then their image

@@ -803,7 +803,7 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
 
 // Streaming variant of nn for a long A (float64 or float32) with 16-byte
 // aligned columns and at most 8 output columns per blockIdx.y group: a
-// workgroup owns 32 VW rows (VW = 16 / sizeof(TA): each lane reads VW
+// workgroup owns 64 VW rows (VW = 16 / sizeof(TA): each lane reads VW
 // consecutive rows of a column with one 16-byte load, so a wave instruction
 // moves 1 KB of one column), its 4 waves take the columns j = w mod 4.  Z is
 // staged in LDS in tiles of NS_ZT rows; each wave keeps two batches of NS_B
