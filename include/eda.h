@@ -77,7 +77,9 @@ typedef enum {
 typedef struct {
   eda_form form;            /* EDA_FORM_LANCZOS_M (default), EDA_FORM_ARNOLDI_A or
                                EDA_FORM_JD_M                                         */
-  int32_t block;            /* block width b (default 8)                             */
+  int32_t block;            /* block width b (default 8): 1 .. 16 for the Lanczos
+                               form, 1 .. 8 for the Arnoldi and Jacobi-Davidson
+                               forms and for eda_solve_batched                       */
   int32_t max_basis;        /* basis columns before a thick restart (default
                                max(2t+2b, t+6b) rounded up to a multiple of b,
                                capped by d)                                          */

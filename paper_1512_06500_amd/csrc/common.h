@@ -243,7 +243,7 @@ struct PcholArgs {
   int* flag;
   const double* part;  // when not null, G = sum over `chunks` tn partials (layout of tn, m = nb = b)
   int64_t chunks;
-  // when not null, G -= corr^T corr (corr row-major mcorr x b, mcorr b <= 2048)
+  // when not null, G -= corr^T corr (corr row-major mcorr x b)
   const double* corr = nullptr;
   int64_t mcorr = 0;
 };

@@ -51,6 +51,7 @@ eda_status solve_jd(eda_handle h, int32_t t, double tol, const eda_solve_opts& o
     return fail(h, EDA_ERR_ARG, "the Jacobi-Davidson form runs in float64 (krylov_dtype EDA_F64)");
   const int64_t d = h->d, N = h->N, ldq = h->ldp;
   const int64_t b = o.block > 0 ? o.block : 8;
+  if (b > 8) return fail(h, EDA_ERR_ARG, "the Jacobi-Davidson form takes block widths in [1, 8]");
   const int64_t nk = t + b;                   // Ritz vectors kept at every restart
   const int64_t wmax = nk + b;                // search space columns
   if (wmax > d) return fail(h, EDA_ERR_ARG, "Jacobi-Davidson needs t + 2b <= d");

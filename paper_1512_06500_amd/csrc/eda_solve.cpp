@@ -150,9 +150,9 @@ eda_status lanczos_orth(Solver& S, int64_t m, bool repair) {
   HIPCHK(launch_pchol(b, h->Gs.d(), b, Hcol, m + b, ldh, 1e-13, 1e-4, false, h->Rinv.d(), b,
                       h->R1.d(), b, h->mask.i(), flags, h->stream, nullptr, 0, h->hz.d(),
                       m + b));
-  // Q_n = W R1^{-1} in place (b <= 8 columns: one workgroup column reads all
-  // of a row before writing it); the product writes the random replacement
-  // columns
+  // Q_n = W R1^{-1} in place (b <= 16 columns: one workgroup column reads
+  // all of a row before writing it); the product writes the random
+  // replacement columns
   HIPCHK(launch_nn(d, b, b, W, qdt, ldq, h->Rinv.d(), b, 0.0, nullptr, qdt, ldq, Qn, qdt, ldq,
                    nullptr, h->stream, false, nullptr, nullptr, h->mask.i(),
                    0x5eed0000ull + (uint64_t)m));
@@ -383,7 +383,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
   if (o.resmode != EDA_RES_REL_THETA && o.resmode != EDA_RES_NORMWISE)
     return fail(h, EDA_ERR_ARG, "unknown residual mode");
   const int64_t b = o.block > 0 ? o.block : 8;
-  if (b > 8) return fail(h, EDA_ERR_ARG, "block width must be in [1, 8]");
+  if (b > 16) return fail(h, EDA_ERR_ARG, "block width must be in [1, 16]");
   int64_t mmax = o.max_basis;
   if (mmax <= 0) {
     mmax = std::max<int64_t>(2 * t + 2 * b, t + 6 * b);

@@ -170,7 +170,7 @@ eda_status validate_block(eda_handle h, int64_t b, const void* V, int64_t ldv, c
 // Whether the core product Z = C Y of a product over Nc columns is split
 // over column groups of C (launch_nn_split) rather than one streaming launch.
 inline bool core_split(int64_t Nc, int64_t b, const double* C, int64_t ldc) {
-  return Nc >= 1024 && b <= 8 && ldc % 2 == 0 && ((uintptr_t)C % 16) == 0;
+  return Nc >= 1024 && b <= 16 && ldc % 2 == 0 && ((uintptr_t)C % 16) == 0;
 }
 // Makes the float64 master the storage copy of a narrow preparation (the
 // Gram and the cores already come from the float64 factors, so nothing is

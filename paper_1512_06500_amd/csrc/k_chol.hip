@@ -528,20 +528,25 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholArgs* __restrict_
     gram_to_lds(G, ldg, a.part, a.chunks, b, A, ld, hs);
   if (a.corr != nullptr) {
     // G -= corr^T corr: the Gram matrix of W - Q h from that of W and the
-    // coefficients h = Q^T W (Q orthonormal); corr staged in one round trip
+    // coefficients h = Q^T W (Q orthonormal, h row-major mcorr x b); h is
+    // staged in tiles of 2048 / b rows, one memory round trip per tile
     __shared__ double cs[2048];
-    const int64_t nc = a.mcorr * b;
-    for (int64_t e = tid; e < nc; e += blockDim.x) cs[e] = a.corr[e];
-    __syncthreads();
-    for (int e = tid; e < b * b; e += blockDim.x) {
-      const int c = e / b, r = e - c * b;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      int64_t k = 0;
-      for (; k + 4 <= a.mcorr; k += 4)
+    const int64_t kt = 2048 / b;
+    for (int64_t k0 = 0; k0 < a.mcorr; k0 += kt) {
+      const int64_t kn = (a.mcorr - k0 < kt) ? a.mcorr - k0 : kt;
+      __syncthreads();  // the previous tile has been read
+      for (int64_t e = tid; e < kn * b; e += blockDim.x) cs[e] = a.corr[k0 * b + e];
+      __syncthreads();
+      for (int e = tid; e < b * b; e += blockDim.x) {
+        const int c = e / b, r = e - c * b;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int64_t k = 0;
+        for (; k + 4 <= kn; k += 4)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = fma(cs[(k + u) * b + r], cs[(k + u) * b + c], acc[u]);
-      for (; k < a.mcorr; ++k) acc[0] = fma(cs[k * b + r], cs[k * b + c], acc[0]);
-      A[r + c * ld] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+          for (int u = 0; u < 4; ++u) acc[u] = fma(cs[(k + u) * b + r], cs[(k + u) * b + c], acc[u]);
+        for (; k < kn; ++k) acc[0] = fma(cs[k * b + r], cs[k * b + c], acc[0]);
+        A[r + c * ld] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      }
     }
     __syncthreads();
   }
@@ -769,7 +774,7 @@ hipError_t launch_pchol(int64_t b, const double* G, int64_t ldg, const double* h
                         int64_t ldhc, double tau, double ratio, bool equil, double* Z, int64_t ldz,
                         double* R, int64_t ldr, int* mask, int* flag, hipStream_t s,
                         const double* part, int64_t chunks, const double* corr, int64_t mcorr) {
-  if (corr != nullptr && (mcorr < 0 || mcorr * b > 2048)) return hipErrorInvalidValue;
+  if (corr != nullptr && mcorr < 0) return hipErrorInvalidValue;
   PcholArgs a{b, ldg, m, ldhc, ldz, ldr, G, hcol, tau, ratio, equil ? 1 : 0, Z, R, mask, flag,
               part, chunks};
   a.corr = corr;

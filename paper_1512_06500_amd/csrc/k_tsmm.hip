@@ -264,8 +264,9 @@ __device__ __forceinline__ void tn_stream_body(const TnArgs& a, int64_t chunk, i
   }
 }
 
-// tn for a float64 A and B (nb <= 8) staged through LDS: per slab of 256
-// rows the workgroup loads its 16 columns of A and the nb columns of B with
+// tn for a float64 A and B (nb <= NB, NB = 8 or 16) staged through LDS: per
+// slab of 256 rows the workgroup loads its 16 columns of A and the nb columns
+// of B with
 // whole-wave 1 KB loads (64 lanes x 16 bytes down one column), stores them
 // column-major in LDS (column stride TL_S doubles = 2 (mod 32), so the 16
 // lanes of an MFMA fragment hit distinct banks), and each wave multiplies 64
@@ -273,15 +274,17 @@ __device__ __forceinline__ void tn_stream_body(const TnArgs& a, int64_t chunk, i
 // registers while the current one is multiplied.  Same partial layout and
 // chunking (256 S rows) as tn_body.
 constexpr int TL_S = 258;
-template <int S>
+template <int S, int NB>
 __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int tile) {
+  static_assert(NB == 8 || NB == 16, "B staged as 8 or 16 columns");
+  constexpr int BU = NB / 4;  // B columns loaded per wave
   typedef double d2 __attribute__((ext_vector_type(2)));
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
   const int c0 = tile * 16;
   if (chunk >= a.chunks || c0 >= m) return;
   __shared__ __attribute__((aligned(32))) double As[16 * TL_S];
-  __shared__ __attribute__((aligned(16))) double Bs[8 * TL_S];
+  __shared__ __attribute__((aligned(16))) double Bs[NB * TL_S];
   typedef const __attribute__((address_space(1))) d2* G2;
   typedef const __attribute__((address_space(1))) double* G1;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -289,10 +292,11 @@ __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int 
   const double* A = (const double*)a.A;
   const double* B = (const double*)a.B;
   const int64_t R0 = chunk * (int64_t)(256 * S);
-  // this wave loads A columns c0 + wid + 4 u (u < 4) and B columns 2 wid, 2 wid + 1,
-  // rows 2 lane + 128 h of the slab (h < 2); columns past m (nb) read a valid
-  // column and are zeroed by a select, so no load sits behind a branch
-  d2 ra[4][2], rb[2][2];
+  // this wave loads A columns c0 + wid + 4 u (u < 4) and B columns
+  // BU wid + u (u < BU), rows 2 lane + 128 h of the slab (h < 2); columns
+  // past m (nb) read a valid column and are zeroed by a select, so no load
+  // sits behind a branch
+  d2 ra[4][2], rb[BU][2];
   const double* acol[4];
   bool aok[4];
 #pragma unroll
@@ -301,11 +305,11 @@ __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int 
     aok[u] = c < m;
     acol[u] = A + (int64_t)(aok[u] ? c : c0) * a.lda;
   }
-  const double* bcol[2];
-  bool bok2[2];
+  const double* bcol[BU];
+  bool bok2[BU];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int j = 2 * wid + u;
+  for (int u = 0; u < BU; ++u) {
+    const int j = BU * wid + u;
     bok2[u] = j < nb;
     bcol[u] = B + (int64_t)(bok2[u] ? j : 0) * a.ldb;
   }
@@ -320,7 +324,7 @@ __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int 
           ra[u][h] = *(G2)(acol[u] + r0 + 2 * lane + 128 * h);
         }
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < BU; ++u)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           rb[u][h] = *(G2)(bcol[u] + r0 + 2 * lane + 128 * h);
@@ -337,7 +341,7 @@ __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int 
           ra[u][h] = v;
         }
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < BU; ++u)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int64_t r = r0 + 2 * lane + 128 * h;
@@ -363,14 +367,14 @@ __device__ __forceinline__ void tn_lds_body(const TnArgs& a, int64_t chunk, int 
       for (int h = 0; h < 2; ++h)
         *(d2*)(As + (wid + 4 * u) * TL_S + 2 * lane + 128 * h) = aok[u] ? ra[u][h] : zero;
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < BU; ++u)
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        *(d2*)(Bs + (2 * wid + u) * TL_S + 2 * lane + 128 * h) = bok2[u] ? rb[u][h] : zero;
+        *(d2*)(Bs + (BU * wid + u) * TL_S + 2 * lane + 128 * h) = bok2[u] ? rb[u][h] : zero;
     __syncthreads();
     if (s + 1 < ns) load(s + 1);
     const double* ac = As + i * TL_S + 64 * wid + q;
-    const double* bc = Bs + (i < 8 ? i : 0) * TL_S + 64 * wid + q;
+    const double* bc = Bs + (i < NB ? i : 0) * TL_S + 64 * wid + q;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const double x = ac[4 * e];
@@ -639,11 +643,11 @@ __global__ __launch_bounds__(256) void tn_narrow_kernel(const TnArgs* __restrict
   tn_narrow_body<TA, TB, S>(a, blockIdx.x, blockIdx.y);
 }
 
-template <int S>
+template <int S, int NB>
 __global__ __launch_bounds__(256) void tn_lds_kernel(const TnArgs* __restrict__ arr, TnArgs one) {
   const TnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
-  tn_lds_body<S>(a, blockIdx.x, blockIdx.y);
+  tn_lds_body<S, NB>(a, blockIdx.x, blockIdx.y);
 }
 
 template <typename TA, typename TB, int S>
@@ -802,29 +806,36 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
 }
 
 // Streaming variant of nn for a long A (float64 or float32) with 16-byte
-// aligned columns and at most 8 output columns per blockIdx.y group: a
+// aligned columns and at most NB output columns (NB = 8 or 16), all in one
+// workgroup column: a
 // workgroup owns 64 VW rows (VW = 16 / sizeof(TA): each lane reads VW
 // consecutive rows of a column with one 16-byte load, so a wave instruction
 // moves 1 KB of one column), its 4 waves take the columns j = w mod 4.  Z is
-// staged in LDS in tiles of NS_ZT rows; each wave keeps two batches of NS_B
+// staged in LDS in tiles of ns_zt<NB>() rows; each wave keeps two batches of NS_B
 // column loads in flight (the next batch is issued before the current one is
-// multiplied).  The 4 waves' sums meet in LDS in a fixed order.
+// multiplied).  The 4 waves' sums meet in LDS in a fixed order.  Every
+// workgroup reads all of A's columns for its rows before it writes those
+// rows, so Out may be A itself (columns 0 .. nb, same leading dimension).
 // With kcols > 0 the columns are split into groups of kcols (blockIdx.y =
 // group) and every group writes its partial product, row-major, to
 // Out + group * d * nb (ldo = nb, no V term): a fixed-order reduction over
 // the groups finishes it.
-constexpr int NS_ZT = 1024;
 constexpr int NS_B = 8;
+// Z tile rows: 1024 for 8 columns, 512 for 16 (64 KB of LDS either way)
+template <int NB>
+constexpr int ns_zt() {
+  return NB == 8 ? 1024 : 512;
+}
 
 // Columns [t0, t0 + tn) of A times the staged Z tile, accumulated into acc:
 // wave w takes the columns t0 + w + 4 u, NS_B loads per batch issued before
 // the batch's products.  FULL: every row of the workgroup is < d (plain
 // vector loads); else rows >= d read as zero.
-template <typename TA, bool FULL>
+template <typename TA, int NB, bool FULL>
 __device__ __forceinline__ void nn_stream_tile(const TA* __restrict__ ar, int64_t lda, int64_t row0,
                                                int64_t d, int t0, int tn, int w,
                                                const double* __restrict__ zs,
-                                               double (&acc)[Vec16<TA>::VW][NN_NB]) {
+                                               double (&acc)[Vec16<TA>::VW][NB]) {
   constexpr int VW = Vec16<TA>::VW;
   typedef typename Vec16<TA>::type VA;
   typedef const __attribute__((address_space(1))) VA* GVA;
@@ -848,90 +859,95 @@ __device__ __forceinline__ void nn_stream_tile(const TA* __restrict__ ar, int64_
 #pragma unroll
     for (int u = 0; u < NS_B; ++u) {
       const bool live = c + u < nloc;
-      const double* zr = zs + (w + 4 * (live ? c + u : 0)) * NN_NB;
+      const double* zr = zs + (w + 4 * (live ? c + u : 0)) * NB;
       const double f = live ? 1.0 : 0.0;
 #pragma unroll
       for (int h = 0; h < VW; ++h) {
         const double x = (double)raw[u][h] * f;
 #pragma unroll
-        for (int j = 0; j < NN_NB; ++j) acc[h][j] += x * zr[j];
+        for (int j = 0; j < NB; ++j) acc[h][j] += x * zr[j];
       }
     }
   }
 }
 
-template <typename TA, typename TV, typename TO>
+template <typename TA, typename TV, typename TO, int NB>
 __device__ __forceinline__ void nn_stream_body(const NnArgs& a, int64_t bx, int by) {
   constexpr int VW = Vec16<TA>::VW;
   constexpr int R = 64 * VW;  // rows per workgroup
+  constexpr int ZT = ns_zt<NB>();
   const int64_t d = a.d;
   const int m = (int)a.m, nb = (int)a.nb;
   const bool split = a.kcols > 0;
   const int k0 = split ? by * (int)a.kcols : 0;
   const int k1 = split ? min(m, k0 + (int)a.kcols) : m;
   if (bx * R >= d || k0 >= k1) return;
-  __shared__ double zs[NS_ZT * NN_NB];
+  __shared__ double zs[ZT * NB];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
   const int64_t row0 = bx * R + (int64_t)lane * VW;  // first of this lane's VW rows
   const bool full = bx * R + R <= d;                  // every row of the workgroup < d
   const TA* ar = (const TA*)a.A + (row0 < d ? row0 : 0);
-  double acc[VW][NN_NB];
+  double acc[VW][NB];
 #pragma unroll
   for (int h = 0; h < VW; ++h)
 #pragma unroll
-    for (int j = 0; j < NN_NB; ++j) acc[h][j] = 0.0;
-  for (int t0 = k0; t0 < k1; t0 += NS_ZT) {
-    const int tn = (k1 - t0 < NS_ZT) ? k1 - t0 : NS_ZT;
+    for (int j = 0; j < NB; ++j) acc[h][j] = 0.0;
+  for (int t0 = k0; t0 < k1; t0 += ZT) {
+    const int tn = (k1 - t0 < ZT) ? k1 - t0 : ZT;
     __syncthreads();
-    for (int e = tid; e < tn * NN_NB; e += 256) {
-      const int i = e / NN_NB, j = e - i * NN_NB;
+    for (int e = tid; e < tn * NB; e += 256) {
+      const int i = e / NB, j = e - i * NB;
       double z = (j < nb) ? a.Z[(int64_t)(t0 + i) * a.ldz + j] : 0.0;
       if (a.ascale != nullptr) z *= a.ascale[t0 + i];
       zs[e] = z;
     }
     __syncthreads();
     if (full)
-      nn_stream_tile<TA, true>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
+      nn_stream_tile<TA, NB, true>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
     else
-      nn_stream_tile<TA, false>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
+      nn_stream_tile<TA, NB, false>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
   }
-  // the 4 waves' sums meet in LDS (zs reused: 4 x R x 8 doubles <= its size)
-  static_assert(4 * R * NN_NB <= NS_ZT * NN_NB, "reduction buffer must fit in zs");
-  __syncthreads();
-#pragma unroll
-  for (int h = 0; h < VW; ++h)
-#pragma unroll
-    for (int j = 0; j < NN_NB; ++j) zs[(w * R + lane * VW + h) * NN_NB + j] = acc[h][j];
-  __syncthreads();
+  // the 4 waves' sums meet in LDS (zs reused), JP columns at a time
+  constexpr int JP = (ZT * NB / (4 * R) < NB) ? ZT * NB / (4 * R) : NB;
+  static_assert(JP >= 1 && NB % JP == 0 && (R * JP) % 256 == 0, "reduction passes");
   const double alpha = split ? 0.0 : ((a.alpha_p != nullptr) ? *a.alpha_p : a.alpha);
   const TV* V = (const TV*)a.V;
   TO* Out = (TO*)a.Out;
   if (split) Out += (int64_t)by * d * nb;
-  // output element e = tid + 256 q: row e % R of the workgroup, column e / R
-  constexpr int NO = R * NN_NB / 256;
 #pragma unroll
-  for (int qq = 0; qq < NO; ++qq) {
-    const int e = tid + 256 * qq;
-    const int rr = e % R, j = e / R;
-    const int64_t row = bx * R + rr;
-    if (row >= d || j >= nb) continue;
-    double o = ((zs[(0 * R + rr) * NN_NB + j] + zs[(1 * R + rr) * NN_NB + j]) +
-                zs[(2 * R + rr) * NN_NB + j]) + zs[(3 * R + rr) * NN_NB + j];
-    if (alpha != 0.0 && V != nullptr) o += alpha * to_f64<TV>(V[row + (int64_t)j * a.ldv]);
-    if (!split && a.mask != nullptr && a.mask[j] != 0)
-      o = masked_gauss(a.seed, (int64_t)j * d + row);
-    const int64_t oi = (split || a.out_row) ? row * (split ? nb : a.ldo) + j
-                                            : row + (int64_t)j * a.ldo;
-    Out[oi] = from_f64<TO>(o);
+  for (int jp = 0; jp < NB; jp += JP) {
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < VW; ++h)
+#pragma unroll
+      for (int j = 0; j < JP; ++j) zs[(w * R + lane * VW + h) * JP + j] = acc[h][jp + j];
+    __syncthreads();
+    // output element e = tid + 256 q: row e % R of the workgroup, column jp + e / R
+    constexpr int NO = R * JP / 256;
+#pragma unroll
+    for (int qq = 0; qq < NO; ++qq) {
+      const int e = tid + 256 * qq;
+      const int rr = e % R, jl = e / R, j = jp + jl;
+      const int64_t row = bx * R + rr;
+      if (row >= d || j >= nb) continue;
+      double o = ((zs[(0 * R + rr) * JP + jl] + zs[(1 * R + rr) * JP + jl]) +
+                  zs[(2 * R + rr) * JP + jl]) + zs[(3 * R + rr) * JP + jl];
+      if (alpha != 0.0 && V != nullptr) o += alpha * to_f64<TV>(V[row + (int64_t)j * a.ldv]);
+      if (!split && a.mask != nullptr && a.mask[j] != 0)
+        o = masked_gauss(a.seed, (int64_t)j * d + row);
+      const int64_t oi = (split || a.out_row) ? row * (split ? nb : a.ldo) + j
+                                              : row + (int64_t)j * a.ldo;
+      Out[oi] = from_f64<TO>(o);
+    }
   }
 }
 
-template <typename TA, typename TV, typename TO>
+template <typename TA, typename TV, typename TO, int NB>
 __global__ __launch_bounds__(256) void nn_stream_kernel(const NnArgs* __restrict__ arr, NnArgs one) {
   const NnArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   if (a.gate != nullptr && *a.gate == 0) return;
-  nn_stream_body<TA, TV, TO>(a, blockIdx.x, blockIdx.y);
+  nn_stream_body<TA, TV, TO, NB>(a, blockIdx.x, blockIdx.y);
 }
 
 // nn for wide outputs (nb > 8): NNW_NB output columns per workgroup, so that
@@ -1479,17 +1495,29 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
       // EDA_TN_DIRECT=1 selects the direct-load kernel (for comparisons)
       static const bool direct = std::getenv("EDA_TN_DIRECT") != nullptr;
       bool lds = std::is_same<TA, double>::value && std::is_same<TB, double>::value && !direct;
-      for (int p = 0; p < count && lds; ++p)
-        lds = host[p].nb <= 8 && host[p].ldb % 2 == 0 && ((uintptr_t)host[p].B % 16) == 0;
+      int64_t nbmax = 0;
+      for (int p = 0; p < count && lds; ++p) {
+        lds = host[p].nb <= 16 && host[p].ldb % 2 == 0 && ((uintptr_t)host[p].B % 16) == 0;
+        nbmax = std::max(nbmax, host[p].nb);
+      }
       if (lds) {
+        // B staged as 8 columns when every problem has at most 8 (less LDS,
+        // more resident workgroups), else as 16
+        const bool w16 = nbmax > 8;
+#define EDA_TN_LDS(SS)                                                      \
+  if (w16)                                                                  \
+    hipLaunchKernelGGL((tn_lds_kernel<SS, 16>), g, dim3(256), 0, s, arr, one); \
+  else                                                                      \
+    hipLaunchKernelGGL((tn_lds_kernel<SS, 8>), g, dim3(256), 0, s, arr, one)
         if (S == 8)
-          hipLaunchKernelGGL(tn_lds_kernel<8>, g, dim3(256), 0, s, arr, one);
+          EDA_TN_LDS(8);
         else if (S == 4)
-          hipLaunchKernelGGL(tn_lds_kernel<4>, g, dim3(256), 0, s, arr, one);
+          EDA_TN_LDS(4);
         else if (S == 2)
-          hipLaunchKernelGGL(tn_lds_kernel<2>, g, dim3(256), 0, s, arr, one);
+          EDA_TN_LDS(2);
         else
-          hipLaunchKernelGGL(tn_lds_kernel<1>, g, dim3(256), 0, s, arr, one);
+          EDA_TN_LDS(1);
+#undef EDA_TN_LDS
         return hipGetLastError();
       }
       if (S == 8)
@@ -1561,12 +1589,14 @@ hipError_t tn_launch_t(int count, const TnArgs* host, const TnArgs* dev, hipStre
 template <typename TA, typename TV, typename TO, typename ACC>
 hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStream_t s) {
   int64_t dmax = 0, ymax = 0, nbmax = 0;
+  bool wide_in_place = false;
   for (int p = 0; p < count; ++p) {
     const NnArgs& a = host[p];
     if (a.d <= 0 || a.nb <= 0) continue;
     if (a.m < 0) return hipErrorInvalidValue;
-    // In-place Out == A is only safe when one workgroup column covers all nb.
-    if (a.Out == a.A && a.nb > NN_NB) return hipErrorInvalidValue;
+    // In-place Out == A is only safe when one workgroup column covers all
+    // nb: up to 8 columns in every kernel, up to 16 in the streaming one.
+    if (a.Out == a.A && a.nb > NN_NB) wide_in_place = true;
     dmax = std::max(dmax, a.d);
     ymax = std::max(ymax, (a.nb + NN_NB - 1) / NN_NB);
     nbmax = std::max(nbmax, a.nb);
@@ -1575,26 +1605,34 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
   const NnArgs one = (count == 1) ? host[0] : NnArgs{};
   const NnArgs* arr = (count == 1) ? nullptr : dev;
   if constexpr (sizeof(TA) >= 4) {
-    // long A with 16-byte aligned columns and at most 8 output columns: the
-    // streaming kernel, when it still gets 256 workgroups (or the launch is
-    // a column-split one, which only it implements)
+    // long A with 16-byte aligned columns and at most 16 output columns: the
+    // streaming kernel, when it still gets 256
+    // workgroups (or the launch is a column-split one or an in-place one of
+    // more than 8 columns, which only it implements)
     constexpr int R = 64 * Vec16<TA>::VW;
-    bool split = false, stream = nbmax <= NN_NB;
+    constexpr int NBS = 16;
+    bool split = false, stream = nbmax <= NBS;
     for (int p = 0; p < count && stream; ++p) {
       const NnArgs& a = host[p];
       split = split || a.kcols > 0;
       stream = ((a.lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)a.A % 16 == 0) &&
-               a.Out != a.A;
+               (a.Out != a.A || (a.kcols == 0 && a.out_row == 0 && a.ldo == a.lda &&
+                                 std::is_same<TO, TA>::value));
     }
     if (split && (!stream || count != 1)) return hipErrorInvalidValue;
-    if (stream && (split || (dmax + R - 1) / R >= 256)) {
+    if (wide_in_place && !stream) return hipErrorInvalidValue;
+    if (stream && (split || wide_in_place || (dmax + R - 1) / R >= 256)) {
       const int64_t groups = split ? (host[0].m + host[0].kcols - 1) / host[0].kcols : 1;
-      hipLaunchKernelGGL((nn_stream_kernel<TA, TV, TO>),
-                         dim3((unsigned)((dmax + R - 1) / R), (unsigned)groups, (unsigned)count),
-                         dim3(256), 0, s, arr, one);
+      const dim3 g((unsigned)((dmax + R - 1) / R), (unsigned)groups, (unsigned)count);
+      if (nbmax > NN_NB) {
+        hipLaunchKernelGGL((nn_stream_kernel<TA, TV, TO, 16>), g, dim3(256), 0, s, arr, one);
+      } else {
+        hipLaunchKernelGGL((nn_stream_kernel<TA, TV, TO, 8>), g, dim3(256), 0, s, arr, one);
+      }
       return hipGetLastError();
     }
   }
+  if (wide_in_place) return hipErrorInvalidValue;
   for (int p = 0; p < count; ++p)
     if (host[p].kcols > 0) return hipErrorInvalidValue;
   if constexpr (sizeof(TA) <= 2) {
@@ -1822,7 +1860,7 @@ hipError_t launch_nn_narrow_split(int64_t d, int64_t m, int64_t nb, const void* 
 hipError_t launch_nn_split(int64_t m, int64_t nb, const double* C, int64_t ldc, const double* Y,
                            int64_t ldy, double* part, double* Z, int64_t ldz, hipStream_t s) {
   if (m <= 0 || nb <= 0) return hipSuccess;
-  if (nb > NN_NB || (ldc * 8) % 16 != 0 || (uintptr_t)C % 16 != 0) return hipErrorInvalidValue;
+  if (nb > 16 || (ldc * 8) % 16 != 0 || (uintptr_t)C % 16 != 0) return hipErrorInvalidValue;
   const int64_t groups = nn_split_groups(m);
   const int64_t kc = (m + groups - 1) / groups;
   NnArgs a{m, m, nb, ldc, ldy, 0, nb, C, Y, 0.0, nullptr, part, 1, nullptr, nullptr, nullptr,

@@ -460,6 +460,76 @@ def test_expmv_opmv_c2_wide_blocks(torch, eda, c2, b, storage):
     h.close()
 
 
+@pytest.fixture(scope="module")
+def tall():
+    """A factor long enough (d = 40000) for the streaming passes to take
+    their 16-column forms, with few columns so that the oracle stays cheap."""
+    counts = [25] * 12
+    X = datagen.make_samples(40000, counts, 40, seed=31)
+    return Case("tall", X, counts, 11)
+
+
+@pytest.mark.parametrize("b", [12, 16])
+def test_expmv_opmv_blocks_of_9_to_16_columns(torch, eda, c2, tall, b):
+    """Blocks of 9 to 16 columns: P^T V staged as 16 columns, the 16-column
+    streaming P Z (d = 40000) and the column-split core product.  Oracle:
+    the closed form of Theorem 3.1."""
+    for case in (c2, tall):
+        log(f"expmv/opmv {case.name} b={b}")
+        h, _, _ = prepared(torch, eda, case)
+        V = np.random.default_rng(100 + b).standard_normal((case.d, b))
+        sB = np.linalg.svd(case.H_B, compute_uv=False) ** 2
+        for which, H, c, En in (("W", case.H_W, -0.5, 1.0), ("B", case.H_B, 1.0, np.exp(sB[0]))):
+            out, s = h.expmv(which, c, dev(torch, V))
+            ref = O.exp_action_thm31(H, c, V)
+            err = rel_op_err(host(out) * np.exp(s), ref, En, V)
+            log(f"  {which} c={c} err={err:.2e}")
+            assert err <= 1e-13
+        out, s = h.opmv("M", dev(torch, V))
+        ref = O.lanczos_action_thm31(case.H_W, case.H_B, V)
+        err = rel_op_err(host(out) * np.exp(s), ref, np.exp(sB[0]), V)
+        log(f"  M err={err:.2e}")
+        assert err <= 1e-13
+        h.close()
+
+
+@pytest.mark.parametrize("b,max_basis", [(16, 0), (12, 72), (16, 80)])
+def test_solve_c2_blocks_above_8(torch, eda, c2, b, max_basis):
+    """Block Lanczos with 12 and 16 columns: the full default basis (the
+    pivoted Cholesky's correction then spans more rows than one staged
+    tile) and small bases with thick restarts.  Oracle: the reduced
+    direct solve."""
+    log(f"solve C2 b={b} max_basis={max_basis}")
+    red = O.eda_reduced(c2.H_W, c2.H_B, c2.t)
+    h, _, _ = prepared(torch, eda, c2)
+    res = h.solve(c2.t, 1e-10, block=b, max_basis=max_basis, seed=6, max_iter=3000)
+    if max_basis:
+        assert res.info["restarts"] >= 1
+    check_solution(res, red, c2.t, red.lam_all, 1e-10)
+    h.close()
+
+
+def test_solve_tall_block_16(torch, eda, tall):
+    """b = 16 at d = 40000: the new block is normalised in place by the
+    16-column streaming product.  Oracle: the reduced direct solve."""
+    log("solve tall d=40000 t=11 b=16")
+    red = O.eda_reduced(tall.H_W, tall.H_B, tall.t)
+    h, _, _ = prepared(torch, eda, tall)
+    res = h.solve(tall.t, 1e-10, block=16, seed=7)
+    check_solution(res, red, tall.t, red.lam_all, 1e-10)
+    h.close()
+
+
+def test_block_width_limits_per_form(torch, eda, c1):
+    """Block widths above 16 are rejected; the Arnoldi and Jacobi-Davidson
+    forms take at most 8."""
+    h, _, _ = prepared(torch, eda, c1)
+    for form, b in (("M", 17), ("A", 9), ("JD", 9)):
+        res = h.solve(c1.t, 1e-8, block=b, seed=1, form=form, raise_on_error=False)
+        assert res.status == 1, (form, b, res.status, res.message)
+    h.close()
+
+
 # ---------------------------------------------------------------------------
 # f3: nearest-neighbour classification in the EDA subspace (Section 3.3)
 # ---------------------------------------------------------------------------
