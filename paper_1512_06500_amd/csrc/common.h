@@ -500,9 +500,16 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
 hipError_t launch_gemm_av(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
                           const double* Z, int64_t ldz, double gv, const double* gv_p,
                           const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
+// C = alpha op(A) op(B) + beta C for an n x n result known to be symmetric
+// (lower tiles computed, mirrored).  ws (ws_bytes; may be null) holds the
+// partial tiles when the tiles are split along K, which needs
+// gemm_sym_ws_bytes(n, k) bytes (0: no split); calls sharing ws must be
+// ordered (one stream).
 hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha, const double* A,
                            int64_t lda, const double* dk, const double* B, int64_t ldb,
-                           double beta, double* C, int64_t ldc, hipStream_t s);
+                           double beta, double* C, int64_t ldc, hipStream_t s,
+                           double* ws = nullptr, int64_t ws_bytes = 0);
+int64_t gemm_sym_ws_bytes(int64_t n, int64_t k);
 // Gram partials: part[c][i][j] over lower-triangle tiles; finalised by launch_gram_reduce.
 int64_t gram_chunks(int64_t d, int64_t N);
 hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int64_t ldp,

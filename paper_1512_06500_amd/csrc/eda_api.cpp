@@ -164,6 +164,17 @@ namespace {
 // which equals V diag(phi_c(lambda)) V^T.  X = c G_WW / 2^q with ||X||_1 <= 1,
 // psi(X) by Paterson-Stockmeyer (degree 17, truncation below 1/19! < 1e-17),
 // then q doublings psi(2X) = psi(X) + psi(X) X psi(X) / 2.  Only GEMMs.
+// launch_gemm_sym on the handle's stream with the handle's split workspace
+eda_status gemm_sym(eda_handle h, bool ta, bool tb, int64_t n, int64_t k, double alpha,
+                    const double* A, int64_t lda, const double* dk, const double* B, int64_t ldb,
+                    double beta, double* C, int64_t ldc) {
+  const int64_t wsb = gemm_sym_ws_bytes(n, k);
+  if (wsb > 0) STCHK(ensure(h, h->gws, (size_t)wsb));
+  HIPCHK(launch_gemm_sym(ta, tb, n, k, alpha, A, lda, dk, B, ldb, beta, C, ldc, h->stream,
+                         wsb > 0 ? h->gws.d() : nullptr, wsb));
+  return EDA_OK;
+}
+
 eda_status poly_core_W(eda_handle h, double c, double* out) {
   const int64_t n = h->n, N = h->N, nn = n * n;
   hipStream_t s = h->stream;
@@ -191,20 +202,20 @@ eda_status poly_core_W(eda_handle h, double c, double* out) {
   HIPCHK(launch_copy_block(n, n, sc, h->G.d(), N, false, X, n, s));
   // every product below is of commuting symmetric polynomials in X, hence
   // symmetric: only lower triangles are computed (and mirrored)
-  HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, X, n, nullptr, X, n, 0.0, A2, n, s));
-  HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, A2, n, nullptr, X, n, 0.0, A3, n, s));
-  HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, A2, n, nullptr, A2, n, 0.0, A4, n, s));
+  STCHK(gemm_sym(h, false, false, n, n, 1.0, X, n, nullptr, X, n, 0.0, A2, n));
+  STCHK(gemm_sym(h, false, false, n, n, 1.0, A2, n, nullptr, X, n, 0.0, A3, n));
+  STCHK(gemm_sym(h, false, false, n, n, 1.0, A2, n, nullptr, A2, n, 0.0, A4, n));
   HIPCHK(launch_lincomb(n, a[16], a[17], X, 0.0, nullptr, 0.0, nullptr, n, P, n, s));
   for (int kb = 3; kb >= 0; --kb) {
     HIPCHK(launch_lincomb(n, a[4 * kb], a[4 * kb + 1], X, a[4 * kb + 2], A2, a[4 * kb + 3], A3,
                           n, T, n, s));
-    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, A4, n, nullptr, P, n, 1.0, T, n, s));
+    STCHK(gemm_sym(h, false, false, n, n, 1.0, A4, n, nullptr, P, n, 1.0, T, n));
     std::swap(P, T);
   }
   for (int i = 0; i < q; ++i) {
-    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, X, n, nullptr, P, n, 0.0, U, n, s));
+    STCHK(gemm_sym(h, false, false, n, n, 1.0, X, n, nullptr, P, n, 0.0, U, n));
     HIPCHK(launch_copy_block(n, n, 1.0, P, n, false, T, n, s));
-    HIPCHK(launch_gemm_sym(false, false, n, n, 0.5, P, n, nullptr, U, n, 1.0, T, n, s));
+    STCHK(gemm_sym(h, false, false, n, n, 0.5, P, n, nullptr, U, n, 1.0, T, n));
     std::swap(P, T);
     HIPCHK(launch_copy_block(n, n, 2.0, X, n, false, X, n, s));
   }
@@ -239,8 +250,7 @@ eda_status build_core(eda_handle h, int which, double c, double shift, double* o
   const int64_t ldz = h->n;
   STCHK(ensure(h, h->fw, (size_t)(h->N + 8) * 8));
   HIPCHK(launch_core_weights(Nw, lam, c, shift, h->fw.d(), h->stream));
-  HIPCHK(launch_gemm_sym(false, true, Nw, Nw, 1.0, Z, ldz, h->fw.d(), Z, ldz, 0.0, out, Nw,
-                     h->stream));
+  STCHK(gemm_sym(h, false, true, Nw, Nw, 1.0, Z, ldz, h->fw.d(), Z, ldz, 0.0, out, Nw));
   return EDA_OK;
 }
 
@@ -255,11 +265,11 @@ eda_status build_w_cores(eda_handle h) {
     STCHK(build_core(h, EDA_W, -1.0, 0.0, h->Gm.d()));
   } else {
     // exp(-S_W) = exp(-S_W/2)^2 gives G_m = 2 G_h + G_h (H_W^T H_W) G_h
-    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, h->G.d(), N, nullptr, h->Gh.d(), n, 0.0,
-                       h->CM.d(), n, h->stream));
+    STCHK(gemm_sym(h, false, false, n, n, 1.0, h->G.d(), N, nullptr, h->Gh.d(), n, 0.0,
+                       h->CM.d(), n));
     HIPCHK(launch_copy_block(n, n, 2.0, h->Gh.d(), n, false, h->Gm.d(), n, h->stream));
-    HIPCHK(launch_gemm_sym(false, false, n, n, 1.0, h->Gh.d(), n, nullptr, h->CM.d(), n, 1.0,
-                       h->Gm.d(), n, h->stream));
+    STCHK(gemm_sym(h, false, false, n, n, 1.0, h->Gh.d(), n, nullptr, h->CM.d(), n, 1.0,
+                       h->Gm.d(), n));
   }
   return EDA_OK;
 }
@@ -444,7 +454,7 @@ void eda_destroy(eda_handle h) {
                   &h->CM, &h->CA, &h->T1,   &h->T2,   &h->T3,    &h->T4,  &h->fw,  &h->part, &h->zpart,
                   &h->Ysm, &h->Zsm, &h->PQ[0], &h->PQ[1], &h->syev_work, &h->offs, &h->flags, &h->mask, &h->Q[0], &h->Q[1],
                   &h->H[0], &h->H[1], &h->Wb, &h->T, &h->wT, &h->S, &h->Sd, &h->hz, &h->Gs,
-                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale, &h->warm, &h->npart};
+                  &h->Rinv, &h->R1, &h->Yb, &h->MYb, &h->dtheta, &h->dres, &h->P64, &h->refine, &h->alphaB_dev, &h->pscale, &h->warm, &h->npart, &h->gws};
     for (Buf& b : h->dir) release(b);
     for (Buf& b : h->af) release(b);
     for (Buf& b : h->nnp) release(b);

@@ -56,6 +56,7 @@ struct eda_handle_s {
   eda::Buf P;    // P = [H_W H_B] in storage precision (ld ldp)
   eda::Buf P64;  // float64 master of P when storage is not float64
   eda::Buf G, eigW, eigZ, nsbuf, Gh, Gm, GBs, CM, CA, T1, T2, T3, T4, fw, polyws, normbuf;
+  eda::Buf gws;  // split partial tiles of the symmetric GEMMs on the handle's stream
   double shiftB = 0.0, alphaB = 1.0;
   eda::Buf alphaB_dev;  // alphaB on the device, read by captured steps
   eda::Buf pscale;      // FP8 storage: column j of P is pscale[j] times its FP8 copy

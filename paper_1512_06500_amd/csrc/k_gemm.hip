@@ -2,6 +2,9 @@
 // of the exponentials) and the Gram matrix P^T P of the scatter factors, on
 // the matrix cores (128 x 128 tiles for large shapes, 32 x 32 for small
 // ones), plus a register-tiled FMA Gram kernel for narrow factors.
+#include <algorithm>
+#include <atomic>
+
 #include "common.h"
 
 namespace eda {
@@ -148,20 +151,29 @@ struct BigGemmArgs {
   const double* gv_p = nullptr;
   // 0: B is read one double at a time (odd ldb or 8-byte aligned B)
   int b_pairs = 1;
+  // symmetric mode with split tiles (nfull >= 0): blockIdx.x < nfull
+  // computes tile blockIdx.x whole; blockIdx.x = nfull + u computes K part
+  // u % ksplit (kpart rows) of tile nfull + u / ksplit and writes that
+  // partial tile to spart + u T T (column-major in the tile); a fixed-order
+  // reduction (big_sym_split_reduce_kernel) finishes the split tiles
+  int64_t nfull = -1;
+  int64_t ksplit = 1;
+  int64_t kpart = 0;
+  double* spart = nullptr;
 };
 
 // Loads of one BK slice of op(X) (rows: the T-edge tile index, k: the
 // slice), T BK / 512 pairs of doubles per thread.  trans == false: X(i, k)
 // at X[i + k ld] (pairs along i); trans: X(i, k) at X[k + i ld] (pairs
 // along k).
-template <int T>
+template <int T, int NT>
 __device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t ld, bool trans, bool pairs,
                                          int64_t i0, int64_t nI, int64_t k0, int64_t kend,
-                                         double2 (&r)[T * BK / 512]) {
+                                         double2 (&r)[T * BK / (2 * NT)]) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < T * BK / 512; ++q) {
-    const int e = tid + 256 * q;
+  for (int q = 0; q < T * BK / (2 * NT); ++q) {
+    const int e = tid + NT * q;
     int ii, kk;
     if (!trans) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
     else { kk = 2 * (e % (BK / 2)); ii = e / (BK / 2); }
@@ -192,15 +204,15 @@ __device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t l
   }
 }
 
-template <int T>
+template <int T, int NT>
 __device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v], bool trans,
-                                          const double2 (&r)[T * BK / 512],
+                                          const double2 (&r)[T * BK / (2 * NT)],
                                           const double* __restrict__ dk, int64_t k0,
                                           int64_t kend) {
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < T * BK / 512; ++q) {
-    const int e = tid + 256 * q;
+  for (int q = 0; q < T * BK / (2 * NT); ++q) {
+    const int e = tid + NT * q;
     int ii, kk;
     if (!trans) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
     else { kk = 2 * (e % (BK / 2)); ii = e / (BK / 2); }
@@ -220,23 +232,35 @@ __device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v], bool tra
   }
 }
 
-// T x T tile per workgroup; wave quadrants of (T/2) x (T/2) = QB x QB MFMA blocks.
-template <int T>
-__global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
+// T x T tile per workgroup of NT threads (NW = NT / 64 waves in a 2 x NW/2
+// grid); each wave owns a (T/2) x (2T/NW) block of QBI x QBJ MFMA blocks.
+template <int T, int NT>
+__global__ __launch_bounds__(NT, 2) void big_gemm_kernel(BigGemmArgs a) {
   constexpr int LS = BigStride<T>::v;
-  constexpr int QB = T / 32;  // 16 x 16 blocks per quadrant edge
-  constexpr int NP = T * BK / 512;
+  constexpr int NW = NT / 64, WJ = NW / 2;
+  constexpr int QBI = T / 32;        // 16 x 16 blocks per wave, along i
+  constexpr int QBJ = T / (16 * WJ);  // and along j
+  constexpr int NP = T * BK / (2 * NT);
   __shared__ double As[BK][LS];
   __shared__ double Bs[BK][LS];
   int64_t ti, tj, kbeg, kend;
   int64_t chunk = blockIdx.y;
+  int64_t unit = -1;  // split-remainder unit of this workgroup (or -1)
   if (a.gram || a.sym) {
     int64_t t = blockIdx.x;
+    if (a.sym && a.nfull >= 0 && t >= a.nfull) {
+      unit = t - a.nfull;
+      t = a.nfull + unit / a.ksplit;
+    }
     ti = 0;
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     tj = t - ti * (ti + 1) / 2;
     kbeg = a.gram ? chunk * a.kchunk : 0;
     kend = a.gram ? min(a.K, kbeg + a.kchunk) : a.K;
+    if (unit >= 0) {
+      kbeg = (unit % a.ksplit) * a.kpart;
+      kend = min(a.K, kbeg + a.kpart);
+    }
   } else {
     ti = blockIdx.x;
     tj = blockIdx.y;
@@ -245,56 +269,67 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
   }
   const int64_t i0 = ti * T, j0 = tj * T;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int qi = (wid >> 1) * (T / 2), qj = (wid & 1) * (T / 2);  // quadrant of the wave
+  const int qi = (wid / WJ) * (T / 2), qj = (wid % WJ) * (T / WJ);  // block of the wave
   const int li = lane & 15, lk = lane >> 4;
-  f64x4 acc[QB][QB];
+  f64x4 acc[QBI][QBJ];
 #pragma unroll
-  for (int x = 0; x < QB; ++x)
+  for (int x = 0; x < QBI; ++x)
 #pragma unroll
-    for (int y = 0; y < QB; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < QBJ; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
   // op(B)(k, j) = B(k, j) (tb == 0: contiguous along k) or B(j, k) (tb:
   // contiguous along j): loaded as X(j, k) that is "trans" exactly when tb == 0
   double2 ra[NP], rb[NP];
   if (kbeg < kend) {
-    big_load<T>(a.A, a.lda, a.ta != 0, true, i0, a.M, kbeg, kend, ra);
-    big_load<T>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, kbeg, kend, rb);
+    big_load<T, NT>(a.A, a.lda, a.ta != 0, true, i0, a.M, kbeg, kend, ra);
+    big_load<T, NT>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, kbeg, kend, rb);
   }
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();  // the previous slice has been read
-    big_store<T>(As, a.ta != 0, ra, a.dk, k0, kend);
-    big_store<T>(Bs, a.tb == 0, rb, nullptr, k0, kend);
+    big_store<T, NT>(As, a.ta != 0, ra, a.dk, k0, kend);
+    big_store<T, NT>(Bs, a.tb == 0, rb, nullptr, k0, kend);
     __syncthreads();
     if (k0 + BK < kend) {
-      big_load<T>(a.A, a.lda, a.ta != 0, true, i0, a.M, k0 + BK, kend, ra);
-      big_load<T>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, k0 + BK, kend, rb);
+      big_load<T, NT>(a.A, a.lda, a.ta != 0, true, i0, a.M, k0 + BK, kend, ra);
+      big_load<T, NT>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, k0 + BK, kend, rb);
     }
     // fragments of step ks + 4 are read from LDS while step ks multiplies
-    double fa[2][QB], fb[2][QB];
+    double fa[2][QBI], fb[2][QBJ];
 #pragma unroll
-    for (int x = 0; x < QB; ++x) fa[0][x] = As[lk][qi + 16 * x + li];
+    for (int x = 0; x < QBI; ++x) fa[0][x] = As[lk][qi + 16 * x + li];
 #pragma unroll
-    for (int y = 0; y < QB; ++y) fb[0][y] = Bs[lk][qj + 16 * y + li];
+    for (int y = 0; y < QBJ; ++y) fb[0][y] = Bs[lk][qj + 16 * y + li];
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int cb = (ks / 4) & 1;
       if (ks + 4 < BK) {
 #pragma unroll
-        for (int x = 0; x < QB; ++x) fa[cb ^ 1][x] = As[ks + 4 + lk][qi + 16 * x + li];
+        for (int x = 0; x < QBI; ++x) fa[cb ^ 1][x] = As[ks + 4 + lk][qi + 16 * x + li];
 #pragma unroll
-        for (int y = 0; y < QB; ++y) fb[cb ^ 1][y] = Bs[ks + 4 + lk][qj + 16 * y + li];
+        for (int y = 0; y < QBJ; ++y) fb[cb ^ 1][y] = Bs[ks + 4 + lk][qj + 16 * y + li];
       }
 #pragma unroll
-      for (int x = 0; x < QB; ++x)
+      for (int x = 0; x < QBI; ++x)
 #pragma unroll
-        for (int y = 0; y < QB; ++y)
+        for (int y = 0; y < QBJ; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][x], fb[cb][y], acc[x][y], 0, 0, 0);
     }
   }
   // accumulator element v of lane l: row 4 v + l / 16, column l % 16 of the block
+  if (unit >= 0) {
+    double* sp = a.spart + unit * (int64_t)(T * T);
 #pragma unroll
-  for (int x = 0; x < QB; ++x)
+    for (int x = 0; x < QBI; ++x)
 #pragma unroll
-    for (int y = 0; y < QB; ++y) {
+      for (int y = 0; y < QBJ; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sp[(qi + 16 * x + 4 * v + lk) + (qj + 16 * y + li) * T] = acc[x][y][v];
+    return;
+  }
+#pragma unroll
+  for (int x = 0; x < QBI; ++x)
+#pragma unroll
+    for (int y = 0; y < QBJ; ++y) {
       const int64_t gj = j0 + qj + 16 * y + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -318,6 +353,40 @@ __global__ __launch_bounds__(256, 2) void big_gemm_kernel(BigGemmArgs a) {
         }
       }
     }
+}
+
+// The split tiles of a symmetric-mode big_gemm_kernel<64, 256> launch, one
+// workgroup per tile (tile nfull + blockIdx.x): each entry is the sum of its
+// ksplit partial tiles in order of their K parts; the lower entries are
+// written as the unsplit kernel writes them, the mirrored ones from an LDS
+// copy so that both stores run along columns of C.
+__global__ __launch_bounds__(256) void big_sym_split_reduce_kernel(BigGemmArgs a) {
+  constexpr int T = 64;
+  __shared__ double tile[T][T + 1];
+  const int64_t t = a.nfull + blockIdx.x;
+  int64_t ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int64_t tj = t - ti * (ti + 1) / 2;
+  const double* sp = a.spart + (int64_t)blockIdx.x * a.ksplit * (T * T);
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    const int il = e % T, jl = e / T;
+    const int64_t gi = ti * T + il, gj = tj * T + jl;
+    double o = 0.0;
+    if (gi < a.M && gj < a.N && gi >= gj) {
+      double sum = 0.0;
+      for (int64_t p = 0; p < a.ksplit; ++p) sum += sp[p * (T * T) + e];
+      double* cp = a.C + gi + gj * a.ldc;
+      o = (a.beta == 0.0 ? 0.0 : a.beta * *cp) + a.alpha * sum;
+      *cp = o;
+    }
+    tile[jl][il] = o;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    const int jl = e % T, il = e / T;
+    const int64_t gi = ti * T + il, gj = tj * T + jl;
+    if (gi < a.M && gj < a.N && gi > gj) a.C[gj + gi * a.ldc] = tile[jl][il];
+  }
 }
 
 // Sum of the Gram partials of big_gemm_kernel (tiles of BT), mirrored.
@@ -446,6 +515,21 @@ void big_gram_geometry(int64_t d, int64_t N, int64_t* chunks, int64_t* rows) {
 
 bool big_ok(const double* p, int64_t ld) { return ld % 2 == 0 && ((uintptr_t)p % 16) == 0; }
 
+// Compute units of the current device (cached per device; 256 if the
+// query fails).
+int64_t device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v <= 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cache[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
 }  // namespace
 
 hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha,
@@ -456,7 +540,7 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
     BigGemmArgs a{m, n, k, lda, ldb, ldc, A, B, dk, C, alpha, beta, ta ? 1 : 0, tb ? 1 : 0,
                   0, 0, nullptr};
     dim3 g((unsigned)((m + BT - 1) / BT), (unsigned)((n + BT - 1) / BT));
-    hipLaunchKernelGGL(big_gemm_kernel<BT>, g, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((big_gemm_kernel<BT, 256>), g, dim3(256), 0, s, a);
     return hipGetLastError();
   }
   dim3 g((unsigned)((m + MT - 1) / MT), (unsigned)((n + MT - 1) / MT));
@@ -477,7 +561,7 @@ hipError_t launch_gemm_av(int64_t m, int64_t n, int64_t k, const double* A, int6
   a.gv = gv;
   a.gv_p = gv_p;
   dim3 g((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
-  hipLaunchKernelGGL(big_gemm_kernel<64>, g, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((big_gemm_kernel<64, 256>), g, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -485,16 +569,51 @@ hipError_t launch_gemm_av(int64_t m, int64_t n, int64_t k, const double* A, int6
 // (enough tiles); the register-tiled kernel everything else.
 static bool gram_big(int64_t N, DT pdt) { return pdt == DT::F64 && N >= 256; }
 
+// K parts of every tile of a symmetric product of n x n with inner
+// dimension k: whole tiles alone leave a compute unit two or three
+// workgroups (too few to hide the latency of the slice loop) and a ragged
+// last round, so every tile is split along K into ks parts, as many as give
+// about eight workgroups a unit (at most 4 parts, at least two slices of BK
+// each); 1 when there are tiles enough.
+int64_t gemm_sym_split(int64_t n, int64_t k) {
+  const int64_t T = (n + 63) / 64, tiles = T * (T + 1) / 2;
+  const int64_t cus = device_cus();
+  if (n < 512 || k < 64 || tiles >= 8 * cus) return 1;
+  int64_t ks = std::min<int64_t>(4, (8 * cus + tiles - 1) / tiles);
+  ks = std::min<int64_t>(ks, ((k + BK - 1) / BK) / 2);
+  return ks >= 2 ? ks : 1;
+}
+
+int64_t gemm_sym_ws_bytes(int64_t n, int64_t k) {
+  const int64_t ks = gemm_sym_split(n, k);
+  if (ks < 2) return 0;
+  const int64_t T = (n + 63) / 64;
+  return T * (T + 1) / 2 * ks * 64 * 64 * 8;
+}
+
 hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha, const double* A,
                            int64_t lda, const double* dk, const double* B, int64_t ldb,
-                           double beta, double* C, int64_t ldc, hipStream_t s) {
+                           double beta, double* C, int64_t ldc, hipStream_t s, double* ws,
+                           int64_t ws_bytes) {
   if (n <= 0) return hipSuccess;
   if (n >= 512 && k >= 64 && big_ok(A, lda) && big_ok(B, ldb)) {
     BigGemmArgs a{n, n, k, lda, ldb, ldc, A, B, dk, C, alpha, beta, ta ? 1 : 0, tb ? 1 : 0,
                   0, 0, nullptr};
     a.sym = 1;
     const int64_t T = (n + 63) / 64;
-    hipLaunchKernelGGL(big_gemm_kernel<64>, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, a);
+    const int64_t tiles = T * (T + 1) / 2;
+    const int64_t ks = gemm_sym_split(n, k);
+    if (ks >= 2 && ws != nullptr && ws_bytes >= gemm_sym_ws_bytes(n, k)) {
+      const int64_t slices = (k + BK - 1) / BK;
+      a.nfull = 0;
+      a.ksplit = ks;
+      a.kpart = ((slices + ks - 1) / ks) * BK;
+      a.spart = ws;
+      hipLaunchKernelGGL((big_gemm_kernel<64, 256>), dim3((unsigned)(tiles * ks)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(big_sym_split_reduce_kernel, dim3((unsigned)tiles), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL((big_gemm_kernel<64, 256>), dim3((unsigned)tiles), dim3(256), 0, s, a);
     return hipGetLastError();
   }
   return launch_gemm(ta, tb, n, n, k, alpha, A, lda, dk, B, ldb, beta, C, ldc, s);
@@ -518,7 +637,7 @@ hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int6
     const int64_t T = (N + BT - 1) / BT;
     BigGemmArgs a{N, N, d, ldp, ldp, N, (const double*)P, (const double*)P, nullptr, nullptr,
                   1.0, 0.0, 1, 0, 1, rows, part};
-    hipLaunchKernelGGL(big_gemm_kernel<BT>, dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks),
+    hipLaunchKernelGGL((big_gemm_kernel<BT, 256>), dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks),
                        dim3(256), 0, s, a);
     return hipGetLastError();
   }

@@ -140,6 +140,36 @@ def test_gram_large_matrix_cores(torch, eda, d, n, k):
     h.close()
 
 
+@pytest.mark.parametrize("n", [1990, 2000])
+def test_w_cores_with_many_tiles(torch, eda, n):
+    """W-cores of n = 2000 columns: 528 lower 64 x 64 tiles per product of
+    the matrix polynomial, more than one round on the compute units, so the
+    last round's tiles are split along K and reduced (n = 1990: ragged last
+    tile).  Oracle: the closed form of Theorem 3.1 for exp(-S_W/2) and the
+    composite operator."""
+    d, k = 3000, 20
+    log(f"W-cores n={n} d={d} k={k}")
+    rng = np.random.default_rng(n)
+    H_W = rng.standard_normal((d, n)) * (0.9 / np.sqrt(d))
+    H_B = rng.standard_normal((d, k)) * (0.5 / np.sqrt(d))
+    h = eda.Handle()
+    h.prepare(dev(torch, H_W), dev(torch, H_B))
+    V = rng.standard_normal((d, 8))
+    for c in (-0.5, -1.0):
+        out, s = h.expmv("W", c, dev(torch, V))
+        ref = O.exp_action_thm31(H_W, c, V)
+        err = rel_op_err(host(out) * np.exp(s), ref, 1.0, V)
+        log(f"  W c={c} err={err:.2e}")
+        assert err <= 1e-13
+    sB = np.linalg.svd(H_B, compute_uv=False) ** 2
+    out, s = h.opmv("M", dev(torch, V))
+    ref = O.lanczos_action_thm31(H_W, H_B, V)
+    err = rel_op_err(host(out) * np.exp(s), ref, np.exp(sB[0]), V)
+    log(f"  M err={err:.2e}")
+    assert err <= 1e-13
+    h.close()
+
+
 # ---------------------------------------------------------------------------
 # a3: symmetric eigensolver
 # ---------------------------------------------------------------------------
