@@ -353,8 +353,10 @@ hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int6
 // max |P64[:, j]| / 448, P8[r, j] = E4M3(P64[r, j] / scale[j]), rows d..ldp-1 zero.
 hipError_t launch_pack_fp8(int64_t d, int64_t ldp, int64_t cols, const double* P64,
                            double* scale, void* P8, hipStream_t s);
+// P[:, col0 .. col0 + cols) (ld ldp, rows d .. ldp-1 zero) = H in type pdt;
+// with a flag, flag[0] |= 1 if any entry of H is NaN/Inf.
 hipError_t launch_pack(int64_t d, int64_t ldp, int64_t cols, const double* H, int64_t ldh,
-                       void* P, DT pdt, int64_t col0, hipStream_t s);
+                       void* P, DT pdt, int64_t col0, hipStream_t s, int* flag = nullptr);
 // flag[0] |= 1 if any entry of the d x cols matrix is NaN/Inf.
 hipError_t launch_nonfinite(int64_t d, int64_t cols, const double* H, int64_t ldh, int* flag,
                             hipStream_t s);

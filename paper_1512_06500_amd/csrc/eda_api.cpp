@@ -573,25 +573,26 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
 
   STCHK(ensure(h, h->flags, 64));
   HIPCHK(launch_fill_i32(16, 0, h->flags.i(), h->stream));
-  HIPCHK(launch_nonfinite(d, n, H_W, ldw, h->flags.i(), h->stream));
-  HIPCHK(launch_nonfinite(d, k, H_B, ldb, h->flags.i(), h->stream));
-  HIPCHK(hipMemcpyAsync(pin, h->flags.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
 
   // a1: factor ingest, P = [H_W H_B] in storage precision, plus a float64
   // master when the storage is narrower (Gram, cores and refinement use it)
-  // (FP8: per-column scales from the master, then the scaled E4M3 copy)
+  // (FP8: per-column scales from the master, then the scaled E4M3 copy).
+  // The float64 copy also flags non-finite entries of the factors.
+  int* nf = h->flags.i();
   STCHK(ensure(h, h->P, (size_t)h->ldp * N * dsize(storage)));
   if (storage != EDA_FP8_E4M3) {
-    HIPCHK(launch_pack(d, h->ldp, n, H_W, ldw, h->P.p, dt_of(storage), 0, h->stream));
-    HIPCHK(launch_pack(d, h->ldp, k, H_B, ldb, h->P.p, dt_of(storage), n, h->stream));
+    int* f = (storage == EDA_F64) ? nf : nullptr;
+    HIPCHK(launch_pack(d, h->ldp, n, H_W, ldw, h->P.p, dt_of(storage), 0, h->stream, f));
+    HIPCHK(launch_pack(d, h->ldp, k, H_B, ldb, h->P.p, dt_of(storage), n, h->stream, f));
   }
   const void* Pm = h->P.p;
   if (storage != EDA_F64) {
     STCHK(ensure(h, h->P64, (size_t)h->ldp * N * 8));
-    HIPCHK(launch_pack(d, h->ldp, n, H_W, ldw, h->P64.p, DT::F64, 0, h->stream));
-    HIPCHK(launch_pack(d, h->ldp, k, H_B, ldb, h->P64.p, DT::F64, n, h->stream));
+    HIPCHK(launch_pack(d, h->ldp, n, H_W, ldw, h->P64.p, DT::F64, 0, h->stream, nf));
+    HIPCHK(launch_pack(d, h->ldp, k, H_B, ldb, h->P64.p, DT::F64, n, h->stream, nf));
     Pm = h->P64.p;
   }
+  HIPCHK(hipMemcpyAsync(pin, h->flags.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   if (storage == EDA_FP8_E4M3) {
     STCHK(ensure(h, h->pscale, (size_t)N * 8));
     HIPCHK(launch_pack_fp8(d, h->ldp, N, h->P64.d(), h->pscale.d(), h->P.p, h->stream));

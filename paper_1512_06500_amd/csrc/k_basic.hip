@@ -56,13 +56,17 @@ __global__ __launch_bounds__(256) void scatter_between_kernel(int64_t d, int64_t
   }
 }
 
+// With a flag, flag[0] |= 1 when an entry read is NaN or Inf (the pass that
+// copies the factor also checks it).
 template <typename TP>
 __global__ __launch_bounds__(256) void pack_kernel(int64_t d, int64_t ldp, const double* __restrict__ H,
-                                                   int64_t ldh, TP* __restrict__ P, int64_t col0) {
+                                                   int64_t ldh, TP* __restrict__ P, int64_t col0,
+                                                   int* flag) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t c = blockIdx.y;
-  if (r >= ldp) return;
   const double v = (r < d) ? H[r + c * ldh] : 0.0;
+  if (flag != nullptr && __any(!isfinite(v)) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+  if (r >= ldp) return;
   P[r + (col0 + c) * ldp] = from_f64<TP>(v);
 }
 
@@ -411,15 +415,18 @@ hipError_t launch_scatter(int64_t d, int64_t n, int64_t k, const double* X, int6
 }
 
 hipError_t launch_pack(int64_t d, int64_t ldp, int64_t cols, const double* H, int64_t ldh,
-                       void* P, DT pdt, int64_t col0, hipStream_t s) {
+                       void* P, DT pdt, int64_t col0, hipStream_t s, int* flag) {
   if (cols <= 0) return hipSuccess;
   dim3 g(nblk(ldp), (unsigned)cols);
   if (pdt == DT::F64)
-    hipLaunchKernelGGL(pack_kernel<double>, g, dim3(256), 0, s, d, ldp, H, ldh, (double*)P, col0);
+    hipLaunchKernelGGL(pack_kernel<double>, g, dim3(256), 0, s, d, ldp, H, ldh, (double*)P, col0,
+                       flag);
   else if (pdt == DT::F32)
-    hipLaunchKernelGGL(pack_kernel<float>, g, dim3(256), 0, s, d, ldp, H, ldh, (float*)P, col0);
+    hipLaunchKernelGGL(pack_kernel<float>, g, dim3(256), 0, s, d, ldp, H, ldh, (float*)P, col0,
+                       flag);
   else
-    hipLaunchKernelGGL(pack_kernel<bf16_t>, g, dim3(256), 0, s, d, ldp, H, ldh, (bf16_t*)P, col0);
+    hipLaunchKernelGGL(pack_kernel<bf16_t>, g, dim3(256), 0, s, d, ldp, H, ldh, (bf16_t*)P, col0,
+                       flag);
   return hipGetLastError();
 }
 

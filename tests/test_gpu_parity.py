@@ -785,15 +785,22 @@ def test_degenerate_t_flag(torch, eda, ragged):
     h.close()
 
 
-def test_nonfinite_input_rejected(torch, eda, ragged):
-    log("NaN in H_W")
-    h = eda.Handle()
-    HW = ragged.H_W.copy()
-    HW[5, 3] = np.nan
-    with pytest.raises(eda.EDAError) as ei:
-        h.prepare(dev(torch, HW), dev(torch, ragged.H_B))
-    assert ei.value.status == eda.EDA_ERR_NONFINITE
-    h.close()
+@pytest.mark.parametrize("storage", ["f64", "f32", "fp8"])
+@pytest.mark.parametrize("where", ["W", "B"])
+def test_nonfinite_input_rejected(torch, eda, ragged, storage, where):
+    """A NaN or Inf anywhere in either factor (checked by the pass that
+    copies the factor) makes the preparation fail with EDA_ERR_NONFINITE;
+    the same handle then prepares the clean factors."""
+    for r, c, v in ((5, 3, np.nan), (ragged.d - 1, -1, np.inf), (0, 0, -np.inf)):
+        log(f"{v} in H_{where}[{r}, {c}], {storage} storage")
+        h = eda.Handle()
+        HW, HB = ragged.H_W.copy(), ragged.H_B.copy()
+        (HW if where == "W" else HB)[r, c] = v
+        with pytest.raises(eda.EDAError) as ei:
+            h.prepare(dev(torch, HW), dev(torch, HB), storage=storage)
+        assert ei.value.status == eda.EDA_ERR_NONFINITE
+        h.prepare(dev(torch, ragged.H_W), dev(torch, ragged.H_B), storage=storage)
+        h.close()
 
 
 def test_fp32_storage_c2(torch, eda, c2):
