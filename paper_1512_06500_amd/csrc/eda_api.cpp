@@ -158,12 +158,6 @@ eda_status expop(eda_handle h, bool master, int64_t c0, int64_t Nc, const double
 
 namespace {
 
-// Core V diag(f) V^T of exp(c H H^T) e^{-shift} for the factor `which`.
-// W-core by a matrix polynomial instead of an eigendecomposition:
-//   G_c = c psi(c G_WW),  psi(X) = sum_{j>=0} X^j / (j+1)!  (psi(z) = (e^z - 1)/z),
-// which equals V diag(phi_c(lambda)) V^T.  X = c G_WW / 2^q with ||X||_1 <= 1,
-// psi(X) by Paterson-Stockmeyer (degree 17, truncation below 1/19! < 1e-17),
-// then q doublings psi(2X) = psi(X) + psi(X) X psi(X) / 2.  Only GEMMs.
 // launch_gemm_sym on the handle's stream with the handle's split workspace
 eda_status gemm_sym(eda_handle h, bool ta, bool tb, int64_t n, int64_t k, double alpha,
                     const double* A, int64_t lda, const double* dk, const double* B, int64_t ldb,
@@ -175,10 +169,23 @@ eda_status gemm_sym(eda_handle h, bool ta, bool tb, int64_t n, int64_t k, double
   return EDA_OK;
 }
 
+// Core V diag(f) V^T of exp(c H H^T) e^{-shift} for the factor `which`.
+// W-core by a matrix polynomial instead of an eigendecomposition:
+//   G_c = c psi(c G_WW),  psi(X) = sum_{j>=0} X^j / (j+1)!  (psi(z) = (e^z - 1)/z),
+// which equals V diag(phi_c(lambda)) V^T.  X = c G_WW has its spectrum in
+// [-rho, 0] (c <= 0), and rho <= ||X^p||_1^{1/p} for every p, so the 1-norms
+// of X, X^2 and X^4 (the last two are powers the evaluation needs anyway)
+// bound it; with the scale f = 2^-q that brings the bound to at most 2,
+// psi(f X) is the Taylor polynomial of degree 23 (alternating remainder
+// below 2^24 / 25! < 1.1e-18, terms at most 1 against psi(-2) = 0.43),
+// evaluated by Paterson-Stockmeyer on the powers of X with the powers of f
+// folded into the coefficients, then q doublings
+// psi(2Y) = psi(Y) + psi(Y) Y psi(Y) / 2.  Only GEMMs.
 eda_status poly_core_W(eda_handle h, double c, double* out) {
   const int64_t n = h->n, N = h->N, nn = n * n;
   hipStream_t s = h->stream;
   STCHK(ensure(h, h->polyws, (size_t)7 * nn * 8));
+  STCHK(ensure(h, h->normbuf, 64));
   double* X = h->polyws.d();
   double* A2 = X + nn;
   double* A3 = A2 + nn;
@@ -186,32 +193,46 @@ eda_status poly_core_W(eda_handle h, double c, double* out) {
   double* P = A4 + nn;
   double* T = P + nn;
   double* U = T + nn;
-  double nrm = std::fabs(c) * h->normW;
-  int q = 0;
-  while (nrm > 1.0 && q < 60) {
-    nrm *= 0.5;
-    ++q;
+  constexpr int kDeg = 23;            // degree of the Taylor polynomial
+  constexpr int kChunks = (kDeg + 1) / 4;
+  double a[kDeg + 1];
+  double fct = 1.0;
+  for (int j = 0; j <= kDeg; ++j) {
+    fct *= (double)(j + 1);
+    a[j] = 1.0 / fct;  // 1/(j+1)!
   }
-  const double sc = c * std::ldexp(1.0, -q);
-  double a[18];
-  double f = 1.0;
-  for (int j = 0; j < 18; ++j) {
-    f *= (double)(j + 1);
-    a[j] = 1.0 / f;  // 1/(j+1)!
-  }
-  HIPCHK(launch_copy_block(n, n, sc, h->G.d(), N, false, X, n, s));
   // every product below is of commuting symmetric polynomials in X, hence
   // symmetric: only lower triangles are computed (and mirrored)
+  HIPCHK(launch_copy_block(n, n, c, h->G.d(), N, false, X, n, s));
   STCHK(gemm_sym(h, false, false, n, n, 1.0, X, n, nullptr, X, n, 0.0, A2, n));
-  STCHK(gemm_sym(h, false, false, n, n, 1.0, A2, n, nullptr, X, n, 0.0, A3, n));
   STCHK(gemm_sym(h, false, false, n, n, 1.0, A2, n, nullptr, A2, n, 0.0, A4, n));
-  HIPCHK(launch_lincomb(n, a[16], a[17], X, 0.0, nullptr, 0.0, nullptr, n, P, n, s));
-  for (int kb = 3; kb >= 0; --kb) {
-    HIPCHK(launch_lincomb(n, a[4 * kb], a[4 * kb + 1], X, a[4 * kb + 2], A2, a[4 * kb + 3], A3,
-                          n, T, n, s));
-    STCHK(gemm_sym(h, false, false, n, n, 1.0, A4, n, nullptr, P, n, 1.0, T, n));
+  HIPCHK(launch_norm1(n, A2, n, h->normbuf.d() + 1, s));
+  HIPCHK(launch_norm1(n, A4, n, h->normbuf.d() + 2, s));
+  double nrm[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(nrm, h->normbuf.d() + 1, sizeof(nrm), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double rho = std::fabs(c) * h->normW;
+  if (std::isfinite(nrm[0])) rho = std::min(rho, std::sqrt(nrm[0]));
+  if (std::isfinite(nrm[1])) rho = std::min(rho, std::sqrt(std::sqrt(nrm[1])));
+  int q = 0;
+  while (rho > 2.0 && q < 60) {
+    rho *= 0.5;
+    ++q;
+  }
+  const double f = std::ldexp(1.0, -q), f2 = f * f, f3 = f2 * f, f4 = f2 * f2;
+  // A3 = (f X)^3; chunk k of the polynomial in Y = f X is
+  // a_{4k} I + a_{4k+1} Y + a_{4k+2} Y^2 + a_{4k+3} Y^3, and P <- chunk + Y^4 P
+  STCHK(gemm_sym(h, false, false, n, n, f3, A2, n, nullptr, X, n, 0.0, A3, n));
+  int kb = kChunks - 1;
+  HIPCHK(launch_lincomb(n, a[4 * kb], a[4 * kb + 1] * f, X, a[4 * kb + 2] * f2, A2,
+                        a[4 * kb + 3], A3, n, P, n, s));
+  for (kb = kChunks - 2; kb >= 0; --kb) {
+    HIPCHK(launch_lincomb(n, a[4 * kb], a[4 * kb + 1] * f, X, a[4 * kb + 2] * f2, A2,
+                          a[4 * kb + 3], A3, n, T, n, s));
+    STCHK(gemm_sym(h, false, false, n, n, f4, A4, n, nullptr, P, n, 1.0, T, n));
     std::swap(P, T);
   }
+  if (q > 0) HIPCHK(launch_copy_block(n, n, f, X, n, false, X, n, s));  // X <- Y
   for (int i = 0; i < q; ++i) {
     STCHK(gemm_sym(h, false, false, n, n, 1.0, X, n, nullptr, P, n, 0.0, U, n));
     HIPCHK(launch_copy_block(n, n, 1.0, P, n, false, T, n, s));

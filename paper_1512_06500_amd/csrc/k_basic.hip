@@ -272,28 +272,58 @@ __global__ void flag_fold_kernel(const FlagArgs* __restrict__ arr, FlagArgs one)
 }
 
 // R[:, c] = MY[:, c] - theta_c Y[:, c] (stored when R is not null) and
-// res[c] = ||R[:, c]||_2, one workgroup per column, fixed-order block sum.
-__global__ __launch_bounds__(256) void ritz_residual_kernel(const ResidArgs* __restrict__ arr,
-                                                            ResidArgs one) {
+// res[c] = ||R[:, c]||_2, one workgroup of 1024 threads per column.  With
+// 16-byte aligned columns each thread takes four row pairs a round, all
+// loads issued before the arithmetic, so that a compute unit keeps enough
+// loads in flight; fixed-order block sum.
+__global__ __launch_bounds__(1024) void ritz_residual_kernel(const ResidArgs* __restrict__ arr,
+                                                             ResidArgs one) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
   const ResidArgs a = arr != nullptr ? arr[blockIdx.z] : one;
   const int64_t c = blockIdx.x;
   if (c >= a.t) return;
-  const int64_t d = a.d, ldmy = a.ldmy, ldy = a.ldy, ldr = a.ldr;
-  const double* __restrict__ MY = a.MY;
-  const double* __restrict__ Y = a.Y;
-  const double* __restrict__ theta = a.theta;
-  double* __restrict__ R = a.R;
-  double* __restrict__ res = a.res;
-  __shared__ double red[8];
-  const double th = theta[c];
+  const int64_t d = a.d;
+  const double* __restrict__ my = a.MY + c * a.ldmy;
+  const double* __restrict__ y = a.Y + c * a.ldy;
+  double* __restrict__ rr = (a.R != nullptr) ? a.R + c * a.ldr : nullptr;
+  __shared__ double red[16];
+  const double th = a.theta[c];
+  const bool vec = ((uintptr_t)my % 16 == 0) && ((uintptr_t)y % 16 == 0) &&
+                   (rr == nullptr || (uintptr_t)rr % 16 == 0);
   double acc = 0.0;
-  for (int64_t r = threadIdx.x; r < d; r += blockDim.x) {
-    const double v = MY[r + c * ldmy] - th * Y[r + c * ldy];
-    if (R != nullptr) R[r + c * ldr] = v;
+  int64_t r0 = 0;
+  if (vec) {
+    const int64_t np = d / 2;
+    for (int64_t p0 = 0; p0 < np; p0 += 4 * 1024) {
+      d2 xm[4], xy[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t p = p0 + threadIdx.x + 1024 * u;
+        const int64_t pc = (p < np) ? p : 0;
+        xm[u] = *(const d2*)(my + 2 * pc);
+        xy[u] = *(const d2*)(y + 2 * pc);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t p = p0 + threadIdx.x + 1024 * u;
+        if (p < np) {
+          d2 v;
+          v.x = xm[u].x - th * xy[u].x;
+          v.y = xm[u].y - th * xy[u].y;
+          if (rr != nullptr) *(d2*)(rr + 2 * p) = v;
+          acc += v.x * v.x + v.y * v.y;
+        }
+      }
+    }
+    r0 = 2 * np;
+  }
+  for (int64_t r = r0 + threadIdx.x; r < d; r += blockDim.x) {
+    const double v = my[r] - th * y[r];
+    if (rr != nullptr) rr[r] = v;
     acc += v * v;
   }
   acc = block_sum(acc, red);
-  if (threadIdx.x == 0) res[c] = sqrt(acc);
+  if (threadIdx.x == 0) a.res[c] = sqrt(acc);
 }
 
 // out[i] = w[n - 1 - i] for i < cnt (ascending eigenvalues to descending).
@@ -611,7 +641,7 @@ hipError_t launch_ritz_residual_multi(int count, const ResidArgs* host, const Re
   const ResidArgs* arr;
   ResidArgs one;
   pick(count, host, dev, &arr, &one);
-  hipLaunchKernelGGL(ritz_residual_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(256), 0, s,
+  hipLaunchKernelGGL(ritz_residual_kernel, dim3((unsigned)x, 1, (unsigned)count), dim3(1024), 0, s,
                      arr, one);
   return hipGetLastError();
 }

@@ -140,17 +140,17 @@ def test_gram_large_matrix_cores(torch, eda, d, n, k):
     h.close()
 
 
-@pytest.mark.parametrize("n", [1990, 2000])
-def test_w_cores_with_many_tiles(torch, eda, n):
+@pytest.mark.parametrize("n,scale", [(1990, 4.0), (2000, 0.9)])
+def test_w_cores_with_many_tiles(torch, eda, n, scale):
     """W-cores of n = 2000 columns: 528 lower 64 x 64 tiles per product of
-    the matrix polynomial, more than one round on the compute units, so the
-    last round's tiles are split along K and reduced (n = 1990: ragged last
-    tile).  Oracle: the closed form of Theorem 3.1 for exp(-S_W/2) and the
-    composite operator."""
+    the matrix polynomial, every tile split along K and reduced (n = 1990:
+    ragged last tile).  The scales put the spectral bound of c S_W at about
+    2 (no or one doubling) and about 50 (several doublings).  Oracle: the
+    closed form of Theorem 3.1 for exp(c S_W) and the composite operator."""
     d, k = 3000, 20
-    log(f"W-cores n={n} d={d} k={k}")
+    log(f"W-cores n={n} d={d} k={k} scale={scale}")
     rng = np.random.default_rng(n)
-    H_W = rng.standard_normal((d, n)) * (0.9 / np.sqrt(d))
+    H_W = rng.standard_normal((d, n)) * (scale / np.sqrt(d))
     H_B = rng.standard_normal((d, k)) * (0.5 / np.sqrt(d))
     h = eda.Handle()
     h.prepare(dev(torch, H_W), dev(torch, H_B))
