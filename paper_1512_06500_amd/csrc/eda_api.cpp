@@ -127,6 +127,12 @@ eda_status expop_second(eda_handle h, bool master, int64_t c0, int64_t Nc, const
     STCHK(ensure(h, h->zpart, (size_t)nn_split_groups(Nc) * Nc * b * 8));
     HIPCHK(launch_nn_split(Nc, b, C, ldc, ysm, ldy, h->zpart.d(), h->Zsm.d(), b, h->stream));
     done = true;
+  } else if (b > 16 && Nc >= 256) {
+    // a wide block (Ritz blocks of the final stage): Z^T = Y^T C^T on the
+    // matrix cores, Y^T and Z^T being the row-major Y and Z read column-major
+    HIPCHK(launch_gemm(false, true, b, Nc, Nc, 1.0, ysm, ldy, nullptr, C, ldc, 0.0, h->Zsm.d(), b,
+                       h->stream));
+    done = true;
   }
   if (!done)
     HIPCHK(launch_nn(Nc, Nc, b, C, DT::F64, ldc, ysm, ldy, 0.0, nullptr, DT::F64, 0, h->Zsm.d(),

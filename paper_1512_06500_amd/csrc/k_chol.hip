@@ -439,9 +439,19 @@ __global__ __launch_bounds__(256) void chol_kernel(const CholArgs* __restrict__ 
     const int r0 = 8 * I, kw = (b - r0 < 8) ? b - r0 : 8;
     for (int e = tid; e < kw * r0; e += blockDim.x) {
       const int c = e / kw, j = e - c * kw;
-      double sacc = L[(r0 + j) + c * ld] * xd[c];
-      for (int k = c + 1; k < r0; ++k) sacc += L[(r0 + j) + k * ld] * L[c + k * ld];
-      Tb[j * CH_MAX + c] = sacc;
+      // four independent partial sums (LDS loads of four k in flight), added
+      // in a fixed order
+      const double* lr = L + (r0 + j);
+      double s0 = lr[c * ld] * xd[c], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int k = c + 1;
+      for (; k + 3 < r0; k += 4) {
+        s0 += lr[k * ld] * L[c + k * ld];
+        s1 += lr[(k + 1) * ld] * L[c + (k + 1) * ld];
+        s2 += lr[(k + 2) * ld] * L[c + (k + 2) * ld];
+        s3 += lr[(k + 3) * ld] * L[c + (k + 3) * ld];
+      }
+      for (; k < r0; ++k) s0 += lr[k * ld] * L[c + k * ld];
+      Tb[j * CH_MAX + c] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     for (int e = tid; e < kw * r0; e += blockDim.x) {
