@@ -166,20 +166,34 @@ struct BigGemmArgs {
 // slice), T BK / 512 pairs of doubles per thread.  trans == false: X(i, k)
 // at X[i + k ld] (pairs along i); trans: X(i, k) at X[k + i ld] (pairs
 // along k).
-template <int T, int NT>
-__device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t ld, bool trans, bool pairs,
+template <int T, int NT, bool TRANS>
+__device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t ld, bool pairs,
                                          int64_t i0, int64_t nI, int64_t k0, int64_t kend,
                                          double2 (&r)[T * BK / (2 * NT)]) {
   const int tid = threadIdx.x;
+  // a slice inside the matrix with 16-byte pairs (wave-uniform test): plain
+  // loads, no per-element bounds
+  if (pairs && i0 + T <= nI && k0 + BK <= kend) {
+#pragma unroll
+    for (int q = 0; q < T * BK / (2 * NT); ++q) {
+      const int e = tid + NT * q;
+      int ii, kk;
+      if (!TRANS) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
+      else { kk = 2 * (e % (BK / 2)); ii = e / (BK / 2); }
+      const double* p = TRANS ? X + (k0 + kk) + (i0 + ii) * ld : X + (i0 + ii) + (k0 + kk) * ld;
+      r[q] = *(const double2*)p;
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < T * BK / (2 * NT); ++q) {
     const int e = tid + NT * q;
     int ii, kk;
-    if (!trans) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
+    if (!TRANS) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
     else { kk = 2 * (e % (BK / 2)); ii = e / (BK / 2); }
     const int64_t gi = i0 + ii, gk = k0 + kk;
     double2 v = {0.0, 0.0};
-    if (!trans) {
+    if (!TRANS) {
       if (gk < kend) {
         const double* p = X + gi + gk * ld;
         if (gi + 1 < nI) {
@@ -204,8 +218,8 @@ __device__ __forceinline__ void big_load(const double* __restrict__ X, int64_t l
   }
 }
 
-template <int T, int NT>
-__device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v], bool trans,
+template <int T, int NT, bool TRANS>
+__device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v],
                                           const double2 (&r)[T * BK / (2 * NT)],
                                           const double* __restrict__ dk, int64_t k0,
                                           int64_t kend) {
@@ -214,10 +228,10 @@ __device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v], bool tra
   for (int q = 0; q < T * BK / (2 * NT); ++q) {
     const int e = tid + NT * q;
     int ii, kk;
-    if (!trans) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
+    if (!TRANS) { ii = 2 * (e % (T / 2)); kk = e / (T / 2); }
     else { kk = 2 * (e % (BK / 2)); ii = e / (BK / 2); }
     double x = r[q].x, y = r[q].y;
-    if (!trans) {
+    if (!TRANS) {
       if (dk != nullptr && k0 + kk < kend) { const double f = dk[k0 + kk]; x *= f; y *= f; }
       S[kk][ii] = x;
       S[kk][ii + 1] = y;
@@ -234,8 +248,9 @@ __device__ __forceinline__ void big_store(double (*S)[BigStride<T>::v], bool tra
 
 // T x T tile per workgroup of NT threads (NW = NT / 64 waves in a 2 x NW/2
 // grid); each wave owns a (T/2) x (2T/NW) block of QBI x QBJ MFMA blocks.
-template <int T, int NT>
+template <int T, int NT, bool AT, bool BT_>
 __global__ __launch_bounds__(NT, 2) void big_gemm_kernel(BigGemmArgs a) {
+  // AT: op(A) = A^T (ta); BT_: B read as X(j, k) along k (tb == 0)
   constexpr int LS = BigStride<T>::v;
   constexpr int NW = NT / 64, WJ = NW / 2;
   constexpr int QBI = T / 32;        // 16 x 16 blocks per wave, along i
@@ -280,17 +295,17 @@ __global__ __launch_bounds__(NT, 2) void big_gemm_kernel(BigGemmArgs a) {
   // contiguous along j): loaded as X(j, k) that is "trans" exactly when tb == 0
   double2 ra[NP], rb[NP];
   if (kbeg < kend) {
-    big_load<T, NT>(a.A, a.lda, a.ta != 0, true, i0, a.M, kbeg, kend, ra);
-    big_load<T, NT>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, kbeg, kend, rb);
+    big_load<T, NT, AT>(a.A, a.lda, true, i0, a.M, kbeg, kend, ra);
+    big_load<T, NT, BT_>(a.B, a.ldb, a.b_pairs != 0, j0, a.N, kbeg, kend, rb);
   }
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();  // the previous slice has been read
-    big_store<T, NT>(As, a.ta != 0, ra, a.dk, k0, kend);
-    big_store<T, NT>(Bs, a.tb == 0, rb, nullptr, k0, kend);
+    big_store<T, NT, AT>(As, ra, a.dk, k0, kend);
+    big_store<T, NT, BT_>(Bs, rb, nullptr, k0, kend);
     __syncthreads();
     if (k0 + BK < kend) {
-      big_load<T, NT>(a.A, a.lda, a.ta != 0, true, i0, a.M, k0 + BK, kend, ra);
-      big_load<T, NT>(a.B, a.ldb, a.tb == 0, a.b_pairs != 0, j0, a.N, k0 + BK, kend, rb);
+      big_load<T, NT, AT>(a.A, a.lda, true, i0, a.M, k0 + BK, kend, ra);
+      big_load<T, NT, BT_>(a.B, a.ldb, a.b_pairs != 0, j0, a.N, k0 + BK, kend, rb);
     }
     // fragments of step ks + 4 are read from LDS while step ks multiplies
     double fa[2][QBI], fb[2][QBJ];
@@ -515,6 +530,21 @@ void big_gram_geometry(int64_t d, int64_t N, int64_t* chunks, int64_t* rows) {
 
 bool big_ok(const double* p, int64_t ld) { return ld % 2 == 0 && ((uintptr_t)p % 16) == 0; }
 
+// big_gemm_kernel<64, 256> instantiated for the operand orientations of a
+void launch_big64(dim3 g, hipStream_t s, const BigGemmArgs& a) {
+  if (a.ta != 0) {
+    if (a.tb != 0)
+      hipLaunchKernelGGL((big_gemm_kernel<64, 256, true, false>), g, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((big_gemm_kernel<64, 256, true, true>), g, dim3(256), 0, s, a);
+  } else {
+    if (a.tb != 0)
+      hipLaunchKernelGGL((big_gemm_kernel<64, 256, false, false>), g, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((big_gemm_kernel<64, 256, false, true>), g, dim3(256), 0, s, a);
+  }
+}
+
 // Compute units of the current device (cached per device; 256 if the
 // query fails).
 int64_t device_cus() {
@@ -540,7 +570,7 @@ hipError_t launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double
     BigGemmArgs a{m, n, k, lda, ldb, ldc, A, B, dk, C, alpha, beta, ta ? 1 : 0, tb ? 1 : 0,
                   0, 0, nullptr};
     dim3 g((unsigned)((m + BT - 1) / BT), (unsigned)((n + BT - 1) / BT));
-    hipLaunchKernelGGL((big_gemm_kernel<BT, 256>), g, dim3(256), 0, s, a);
+    launch_big64(g, s, a);
     return hipGetLastError();
   }
   dim3 g((unsigned)((m + MT - 1) / MT), (unsigned)((n + MT - 1) / MT));
@@ -561,7 +591,7 @@ hipError_t launch_gemm_av(int64_t m, int64_t n, int64_t k, const double* A, int6
   a.gv = gv;
   a.gv_p = gv_p;
   dim3 g((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
-  hipLaunchKernelGGL((big_gemm_kernel<64, 256>), g, dim3(256), 0, s, a);
+  launch_big64(g, s, a);
   return hipGetLastError();
 }
 
@@ -609,11 +639,11 @@ hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha,
       a.ksplit = ks;
       a.kpart = ((slices + ks - 1) / ks) * BK;
       a.spart = ws;
-      hipLaunchKernelGGL((big_gemm_kernel<64, 256>), dim3((unsigned)(tiles * ks)), dim3(256), 0, s, a);
+      launch_big64(dim3((unsigned)(tiles * ks)), s, a);
       hipLaunchKernelGGL(big_sym_split_reduce_kernel, dim3((unsigned)tiles), dim3(256), 0, s, a);
       return hipGetLastError();
     }
-    hipLaunchKernelGGL((big_gemm_kernel<64, 256>), dim3((unsigned)tiles), dim3(256), 0, s, a);
+    launch_big64(dim3((unsigned)tiles), s, a);
     return hipGetLastError();
   }
   return launch_gemm(ta, tb, n, n, k, alpha, A, lda, dk, B, ldb, beta, C, ldc, s);
@@ -637,8 +667,7 @@ hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int6
     const int64_t T = (N + BT - 1) / BT;
     BigGemmArgs a{N, N, d, ldp, ldp, N, (const double*)P, (const double*)P, nullptr, nullptr,
                   1.0, 0.0, 1, 0, 1, rows, part};
-    hipLaunchKernelGGL((big_gemm_kernel<BT, 256>), dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks),
-                       dim3(256), 0, s, a);
+    launch_big64(dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks), s, a);
     return hipGetLastError();
   }
   if (gram_big(N, pdt)) return hipErrorInvalidValue;  // chunks were sized for the big kernel
