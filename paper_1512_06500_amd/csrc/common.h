@@ -512,6 +512,12 @@ hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha,
                            double beta, double* C, int64_t ldc, hipStream_t s,
                            double* ws = nullptr, int64_t ws_bytes = 0);
 int64_t gemm_sym_ws_bytes(int64_t n, int64_t k);
+// G = X^T X (N x N, ld ldg, exactly symmetric) of a float64 d x N block with
+// 16-byte aligned columns and an even ld, on the matrix cores; part holds
+// gram_block_chunks(d, N) partial N x N matrices.
+int64_t gram_block_chunks(int64_t d, int64_t N);
+hipError_t launch_gram_block(int64_t d, int64_t N, const double* X, int64_t ldx, double* part,
+                             int64_t chunks, double* G, int64_t ldg, hipStream_t s);
 // Gram partials: part[c][i][j] over lower-triangle tiles; finalised by launch_gram_reduce.
 int64_t gram_chunks(int64_t d, int64_t N);
 hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int64_t ldp,

@@ -55,18 +55,28 @@ eda_status cholqr_pass(eda_handle h, int64_t d, int64_t cols, const void* X, DT 
                        void* Xout, int64_t ldxo, const double* Rprev, double* Rout, int64_t ldro,
                        const double* hcol, int64_t mrows, int64_t ldhc, const int* gate,
                        int* flag) {
-  const int64_t chunks = tn_chunks(d, cols, cols);
-  STCHK(ensure(h, h->part, (size_t)chunks * cols * cols * 8));
+  int64_t chunks = tn_chunks(d, cols, cols);
   STCHK(ensure(h, h->Gs, (size_t)cols * cols * 8));
   STCHK(ensure(h, h->Rinv, (size_t)cols * cols * 8));
   // for a narrow block the Cholesky kernel sums the chunk partials of
-  // X^T X itself; wider ones use the parallel reduction first
+  // X^T X itself; wide float64 blocks (Ritz blocks) take the matrix-core
+  // Gram, others the tn partials and the parallel reduction
   const bool fused = cols <= 16;
-  HIPCHK(launch_tn_partial(d, cols, cols, X, xdt, ldx, X, xdt, ldx, h->part.d(), chunks, gate,
-                           h->stream));
-  if (!fused)
-    HIPCHK(launch_reduce_partials(chunks, cols, cols, h->part.d(), 1.0, 0.0, h->Gs.d(), cols,
-                                  0.0, nullptr, 0, gate, h->stream));
+  const bool gram = !fused && cols >= 48 && gate == nullptr && xdt == DT::F64 && ldx % 2 == 0 &&
+                    ((uintptr_t)X % 16) == 0;
+  if (gram) {
+    chunks = gram_block_chunks(d, cols);
+    STCHK(ensure(h, h->part, (size_t)chunks * cols * cols * 8));
+    HIPCHK(launch_gram_block(d, cols, (const double*)X, ldx, h->part.d(), chunks, h->Gs.d(), cols,
+                             h->stream));
+  } else {
+    STCHK(ensure(h, h->part, (size_t)chunks * cols * cols * 8));
+    HIPCHK(launch_tn_partial(d, cols, cols, X, xdt, ldx, X, xdt, ldx, h->part.d(), chunks, gate,
+                             h->stream));
+    if (!fused)
+      HIPCHK(launch_reduce_partials(chunks, cols, cols, h->part.d(), 1.0, 0.0, h->Gs.d(), cols,
+                                    0.0, nullptr, 0, gate, h->stream));
+  }
   HIPCHK(launch_chol(cols, h->Gs.d(), cols, h->Rinv.d(), cols, Rprev, cols, Rout, ldro, hcol,
                      mrows, ldhc, 1e-4, flag, gate, h->stream, fused ? h->part.d() : nullptr,
                      chunks));

@@ -413,9 +413,20 @@ __global__ __launch_bounds__(256) void big_gram_reduce_kernel(int64_t N, int64_t
   const int64_t j = e / N, i = e - j * N;
   const bool lower = (i / bt) >= (j / bt);
   const int64_t src = lower ? (i + j * N) : (j + i * N);
-  double s = 0.0;
-  for (int64_t c = 0; c < chunks; ++c) s += part[c * N * N + src];
-  G[i + j * ldg] = s;
+  // four partial sums (chunks c = u mod 4) so that four loads are in
+  // flight, added in a fixed order
+  const double* p = part + src;
+  const int64_t NN = N * N;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t c = 0;
+  for (; c + 3 < chunks; c += 4) {
+    s0 += p[c * NN];
+    s1 += p[(c + 1) * NN];
+    s2 += p[(c + 2) * NN];
+    s3 += p[(c + 3) * NN];
+  }
+  for (; c < chunks; ++c) s0 += p[c * NN];
+  G[i + j * ldg] = (s0 + s1) + (s2 + s3);
 }
 
 // Gram partials over one row chunk for one lower-triangle tile (ti >= tj).
@@ -490,9 +501,20 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t N, int64_t chu
   // read from the lower-triangle tile that holds (i, j) or its mirror
   const bool lower = (i / GT) >= (j / GT);
   const int64_t src = lower ? (i + j * N) : (j + i * N);
-  double s = 0.0;
-  for (int64_t c = 0; c < chunks; ++c) s += part[c * N * N + src];
-  G[i + j * ldg] = s;
+  // four partial sums (chunks c = u mod 4) so that four loads are in
+  // flight, added in a fixed order
+  const double* p = part + src;
+  const int64_t NN = N * N;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t c = 0;
+  for (; c + 3 < chunks; c += 4) {
+    s0 += p[c * NN];
+    s1 += p[(c + 1) * NN];
+    s2 += p[(c + 2) * NN];
+    s3 += p[(c + 3) * NN];
+  }
+  for (; c < chunks; ++c) s0 += p[c * NN];
+  G[i + j * ldg] = (s0 + s1) + (s2 + s3);
 }
 
 void gram_geometry(int64_t d, int64_t N, int64_t* chunks, int64_t* rows) {
@@ -647,6 +669,40 @@ hipError_t launch_gemm_sym(bool ta, bool tb, int64_t n, int64_t k, double alpha,
     return hipGetLastError();
   }
   return launch_gemm(ta, tb, n, n, k, alpha, A, lda, dk, B, ldb, beta, C, ldc, s);
+}
+
+// Gram X^T X of a float64 block of N columns (N >= 48) on the matrix cores:
+// lower 64 x 64 tiles x row chunks (about eight workgroups a compute unit,
+// at least 512 rows a chunk), partial tiles [chunk][N][N] summed in order
+// into G by big_gram_reduce_kernel (mirrored, exactly symmetric).
+static void gram_block_geometry(int64_t d, int64_t N, int64_t* chunks, int64_t* rows) {
+  const int64_t T = (N + BT - 1) / BT, tiles = T * (T + 1) / 2;
+  int64_t c = (8 * device_cus() + tiles - 1) / tiles;
+  c = std::max<int64_t>(1, std::min<int64_t>(c, d / 512));
+  int64_t rp = (d + c - 1) / c;
+  rp = ((rp + BK - 1) / BK) * BK;
+  *rows = rp;
+  *chunks = (d + rp - 1) / rp;
+}
+
+int64_t gram_block_chunks(int64_t d, int64_t N) {
+  int64_t c, r;
+  gram_block_geometry(d, N, &c, &r);
+  return c;
+}
+
+hipError_t launch_gram_block(int64_t d, int64_t N, const double* X, int64_t ldx, double* part,
+                             int64_t chunks, double* G, int64_t ldg, hipStream_t s) {
+  if (d <= 0 || N <= 0) return hipSuccess;
+  int64_t c, rows;
+  gram_block_geometry(d, N, &c, &rows);
+  if (c != chunks || !big_ok(X, ldx)) return hipErrorInvalidValue;
+  const int64_t T = (N + BT - 1) / BT;
+  BigGemmArgs a{N, N, d, ldx, ldx, N, X, X, nullptr, nullptr, 1.0, 0.0, 1, 0, 1, rows, part};
+  launch_big64(dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks), s, a);
+  hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0,
+                     s, N, chunks, BT, part, G, ldg);
+  return hipGetLastError();
 }
 
 int64_t gram_chunks(int64_t d, int64_t N) {
