@@ -181,7 +181,8 @@ eda_status gemm_sym(eda_handle h, bool ta, bool tb, int64_t n, int64_t k, double
 // which equals V diag(phi_c(lambda)) V^T.  X = c G_WW has its spectrum in
 // [-rho, 0] (c <= 0), and rho <= ||X^p||_1^{1/p} for every p, so the 1-norms
 // of X, X^2 and X^4 (the last two are powers the evaluation needs anyway)
-// bound it; with the scale f = 2^-q that brings the bound to at most 2,
+// bound it (X alone where the host must not wait for the device); with the
+// scale f = 2^-q that brings the bound to at most 2,
 // psi(f X) is the Taylor polynomial of degree 23 (alternating remainder
 // below 2^24 / 25! < 1.1e-18, terms at most 1 against psi(-2) = 0.43),
 // evaluated by Paterson-Stockmeyer on the powers of X with the powers of f
@@ -212,14 +213,16 @@ eda_status poly_core_W(eda_handle h, double c, double* out) {
   HIPCHK(launch_copy_block(n, n, c, h->G.d(), N, false, X, n, s));
   STCHK(gemm_sym(h, false, false, n, n, 1.0, X, n, nullptr, X, n, 0.0, A2, n));
   STCHK(gemm_sym(h, false, false, n, n, 1.0, A2, n, nullptr, A2, n, 0.0, A4, n));
-  HIPCHK(launch_norm1(n, A2, n, h->normbuf.d() + 1, s));
-  HIPCHK(launch_norm1(n, A4, n, h->normbuf.d() + 2, s));
-  double nrm[2] = {0.0, 0.0};
-  HIPCHK(hipMemcpyAsync(nrm, h->normbuf.d() + 1, sizeof(nrm), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
   double rho = std::fabs(c) * h->normW;
-  if (std::isfinite(nrm[0])) rho = std::min(rho, std::sqrt(nrm[0]));
-  if (std::isfinite(nrm[1])) rho = std::min(rho, std::sqrt(std::sqrt(nrm[1])));
+  if (h->poly_readback) {
+    HIPCHK(launch_norm1(n, A2, n, h->normbuf.d() + 1, s));
+    HIPCHK(launch_norm1(n, A4, n, h->normbuf.d() + 2, s));
+    double nrm[2] = {0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(nrm, h->normbuf.d() + 1, sizeof(nrm), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (std::isfinite(nrm[0])) rho = std::min(rho, std::sqrt(nrm[0]));
+    if (std::isfinite(nrm[1])) rho = std::min(rho, std::sqrt(std::sqrt(nrm[1])));
+  }
   int q = 0;
   while (rho > 2.0 && q < 60) {
     rho *= 0.5;

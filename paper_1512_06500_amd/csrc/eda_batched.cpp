@@ -713,6 +713,7 @@ extern "C" eda_status eda_solve_batched(eda_handle h, int32_t count, const eda_p
       if (sb != nullptr) eda_destroy(sb);
       return fail(h, s0, "internal handle creation failed");
     }
+    sb->poly_readback = false;
     Bs->subs.push_back(sb);
   }
   while (Bs->ev.size() < 4) {

@@ -78,6 +78,10 @@ struct eda_handle_s {
   hipEvent_t prep_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool prep_wbyeig = false;
   bool prep_overlap = false;  // eig(H_B^T H_B) on the second stream beside the W-cores
+  // the W-core polynomial may read its spectral bound back to the host (a
+  // drain of the stream); off for the per-problem handles of a batch, whose
+  // preparations are enqueued back to back
+  bool poly_readback = true;
 
   // workspaces
   eda::Buf part, Ysm, Zsm, syev_work, offs, flags, mask;
@@ -129,7 +133,9 @@ inline int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
 // kernel up to the small eigensolves, with the scalars the host needs copied
 // asynchronously into pinned memory; after the stream has drained,
 // prepare_end reads them (non-finite check, spectral shift) and enqueues the
-// core construction.  Nothing in either half blocks the host.
+// core construction.  Neither half blocks the host, except that prepare_end
+// waits once for the spectral bound of the W-core polynomial on a handle
+// with poly_readback set (the per-problem handles of a batch have it off).
 // With `overlap`, eig(H_B^T H_B) runs on the second stream so that
 // prepare_end can build the W-cores (which need only ||H_W^T H_W||_1) while
 // it runs; the caller then needs to drain only the main stream before
