@@ -25,6 +25,29 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // s_j to H_B (column j).  Then one thread per row: mu = (sum_j s_j) / n (the
 // sample-weighted global centroid) and H_B(:, j) = sqrt(n_j) (s_j / n_j - mu).
 // ---------------------------------------------------------------------------
+// A class of at most CM samples is read once: its entries of the thread's
+// row stay in registers (all loads issued before the first use; indices
+// past the class read its last sample again, a cache hit, and are unused).
+// Larger classes read their samples twice.  Either way s is the sum in
+// sample order.
+template <int CM>
+__device__ __forceinline__ void scatter_class_regs(int64_t i, const double* __restrict__ X,
+                                                   int64_t ldx, int64_t c0, int64_t nj,
+                                                   double* __restrict__ HW, int64_t ldw,
+                                                   double& s) {
+  double v[CM];
+#pragma unroll
+  for (int u = 0; u < CM; ++u) v[u] = X[i + (c0 + (u < nj ? u : nj - 1)) * ldx];
+  s = 0.0;
+#pragma unroll
+  for (int u = 0; u < CM; ++u)
+    if (u < nj) s += v[u];
+  const double mj = s / (double)nj;
+#pragma unroll
+  for (int u = 0; u < CM; ++u)
+    if (u < nj) HW[i + (c0 + u) * ldw] = v[u] - mj;
+}
+
 __global__ __launch_bounds__(256) void scatter_class_kernel(int64_t d, const double* __restrict__ X,
                                                             int64_t ldx,
                                                             const int64_t* __restrict__ offs,
@@ -33,11 +56,21 @@ __global__ __launch_bounds__(256) void scatter_class_kernel(int64_t d, const dou
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (i >= d) return;
-  const int64_t c0 = offs[j], c1 = offs[j + 1];
+  const int64_t c0 = offs[j], c1 = offs[j + 1], nj = c1 - c0;
   double s = 0.0;
-  for (int64_t c = c0; c < c1; ++c) s += X[i + c * ldx];
-  const double mj = s / (double)(c1 - c0);
-  for (int64_t c = c0; c < c1; ++c) HW[i + c * ldw] = X[i + c * ldx] - mj;
+  if (nj <= 8) {
+    scatter_class_regs<8>(i, X, ldx, c0, nj, HW, ldw, s);
+  } else if (nj <= 16) {
+    scatter_class_regs<16>(i, X, ldx, c0, nj, HW, ldw, s);
+  } else if (nj <= 24) {
+    scatter_class_regs<24>(i, X, ldx, c0, nj, HW, ldw, s);
+  } else if (nj <= 32) {
+    scatter_class_regs<32>(i, X, ldx, c0, nj, HW, ldw, s);
+  } else {
+    for (int64_t c = c0; c < c1; ++c) s += X[i + c * ldx];
+    const double mj = s / (double)nj;
+    for (int64_t c = c0; c < c1; ++c) HW[i + c * ldw] = X[i + c * ldx] - mj;
+  }
   HB[i + j * ldb] = s;
 }
 

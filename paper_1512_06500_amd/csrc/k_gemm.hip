@@ -404,29 +404,53 @@ __global__ __launch_bounds__(256) void big_sym_split_reduce_kernel(BigGemmArgs a
   }
 }
 
-// Sum of the Gram partials of big_gemm_kernel (tiles of BT), mirrored.
-__global__ __launch_bounds__(256) void big_gram_reduce_kernel(int64_t N, int64_t chunks, int bt,
+// Sum of the Gram partials of big_gemm_kernel, one lower tile (ti >= tj) of
+// BT x BT per workgroup: the partial tiles are read down their columns
+// (coalesced), the sum is written to G as it is and, off the diagonal,
+// mirrored through LDS (so that both writes are coalesced too).  The
+// chunks are added as four partial sums (chunks c = u mod 4, four loads in
+// flight) combined in a fixed order, and a mirrored entry is a copy of its
+// lower twin: G is exactly symmetric.
+__global__ __launch_bounds__(256) void big_gram_reduce_kernel(int64_t N, int64_t chunks,
                                                               const double* __restrict__ part,
                                                               double* __restrict__ G, int64_t ldg) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= N * N) return;
-  const int64_t j = e / N, i = e - j * N;
-  const bool lower = (i / bt) >= (j / bt);
-  const int64_t src = lower ? (i + j * N) : (j + i * N);
-  // four partial sums (chunks c = u mod 4) so that four loads are in
-  // flight, added in a fixed order
-  const double* p = part + src;
+  __shared__ double tile[BT][BT + 1];
+  const int64_t t = blockIdx.x;
+  int64_t ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int64_t tj = t - ti * (ti + 1) / 2;
+  const int64_t i0 = ti * BT, j0 = tj * BT;
+  const int r = threadIdx.x % BT, cg = threadIdx.x / BT;
+  constexpr int CG = 256 / BT;
   const int64_t NN = N * N;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t c = 0;
-  for (; c + 3 < chunks; c += 4) {
-    s0 += p[c * NN];
-    s1 += p[(c + 1) * NN];
-    s2 += p[(c + 2) * NN];
-    s3 += p[(c + 3) * NN];
+  const int64_t i = i0 + r;
+  for (int cc = cg; cc < BT; cc += CG) {
+    const int64_t j = j0 + cc;
+    double v = 0.0;
+    if (i < N && j < N) {
+      const double* p = part + i + j * N;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int64_t c = 0;
+      for (; c + 3 < chunks; c += 4) {
+        s0 += p[c * NN];
+        s1 += p[(c + 1) * NN];
+        s2 += p[(c + 2) * NN];
+        s3 += p[(c + 3) * NN];
+      }
+      for (; c < chunks; ++c) s0 += p[c * NN];
+      v = (s0 + s1) + (s2 + s3);
+      G[i + j * ldg] = v;
+    }
+    tile[cc][r] = v;
   }
-  for (; c < chunks; ++c) s0 += p[c * NN];
-  G[i + j * ldg] = (s0 + s1) + (s2 + s3);
+  if (ti == tj) return;  // a diagonal tile holds both triangles of its block
+  __syncthreads();
+  // G(j0 + r, i0 + cc) = G(i0 + cc, j0 + r), held in tile[r][cc]
+  const int64_t jr = j0 + r;
+  for (int cc = cg; cc < BT; cc += CG) {
+    const int64_t ic = i0 + cc;
+    if (jr < N && ic < N) G[jr + ic * ldg] = tile[r][cc];
+  }
 }
 
 // Gram partials over one row chunk for one lower-triangle tile (ti >= tj).
@@ -700,8 +724,8 @@ hipError_t launch_gram_block(int64_t d, int64_t N, const double* X, int64_t ldx,
   const int64_t T = (N + BT - 1) / BT;
   BigGemmArgs a{N, N, d, ldx, ldx, N, X, X, nullptr, nullptr, 1.0, 0.0, 1, 0, 1, rows, part};
   launch_big64(dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks), s, a);
-  hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0,
-                     s, N, chunks, BT, part, G, ldg);
+  hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, N,
+                     chunks, part, G, ldg);
   return hipGetLastError();
 }
 
@@ -743,8 +767,9 @@ hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int6
 hipError_t launch_gram_reduce(int64_t N, int64_t chunks, const double* part, double* G,
                               int64_t ldg, hipStream_t s) {
   if (gram_big(N, DT::F64)) {
-    hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0,
-                       s, N, chunks, BT, part, G, ldg);
+    const int64_t T = (N + BT - 1) / BT;
+    hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s,
+                       N, chunks, part, G, ldg);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, N,

@@ -807,40 +807,49 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
 
 // Streaming variant of nn for a long A (float64 or float32) with 16-byte
 // aligned columns and at most NB output columns (NB = 8 or 16), all in one
-// workgroup column: a
-// workgroup owns 64 VW rows (VW = 16 / sizeof(TA): each lane reads VW
-// consecutive rows of a column with one 16-byte load, so a wave instruction
-// moves 1 KB of one column), its 4 waves take the columns j = w mod 4.  Z is
-// staged in LDS in tiles of ns_zt<NB>() rows; each wave keeps two batches of NS_B
-// column loads in flight (the next batch is issued before the current one is
-// multiplied).  The 4 waves' sums meet in LDS in a fixed order.  Every
-// workgroup reads all of A's columns for its rows before it writes those
-// rows, so Out may be A itself (columns 0 .. nb, same leading dimension).
-// With kcols > 0 the columns are split into groups of kcols (blockIdx.y =
-// group) and every group writes its partial product, row-major, to
-// Out + group * d * nb (ldo = nb, no V term): a fixed-order reduction over
-// the groups finishes it.
+// workgroup column: a workgroup owns 64 VW rows (VW = 16 / sizeof(TA): each
+// lane reads VW consecutive rows of a column with one 16-byte load, so a
+// wave instruction moves 1 KB of one column), its 4 waves take the columns
+// j = w mod 4, NS_B column loads in flight per wave.  The row of Z that
+// multiplies a column is the same for the whole wave, so it is read with
+// scalar loads (through the scalar cache) straight from global memory: no
+// LDS staging and no barrier while A streams.  The 4 waves' sums meet in LDS
+// in a fixed order.  Every workgroup reads all of A's columns for its rows
+// before it writes those rows, so Out may be A itself (columns 0 .. nb, same
+// leading dimension).  With kcols > 0 the columns are split into groups of
+// kcols (blockIdx.y = group) and every group writes its partial product,
+// row-major, to Out + group * d * nb (ldo = nb, no V term): a fixed-order
+// reduction over the groups finishes it.
 constexpr int NS_B = 8;
-// Z tile rows: 1024 for 8 columns, 512 for 16 (64 KB of LDS either way)
-template <int NB>
-constexpr int ns_zt() {
-  return NB == 8 ? 1024 : 512;
+constexpr int NS_RED = 4096;  // doubles of LDS for the reduction over the 4 waves
+typedef const __attribute__((address_space(4))) double* ConstF64;
+
+// A 64-bit value made provably wave-uniform (the argument structs are read
+// through generic pointers, whose loads the compiler must treat as
+// per-lane): lets loads through it become scalar loads.
+__device__ __forceinline__ uint64_t wave_uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
-// Columns [t0, t0 + tn) of A times the staged Z tile, accumulated into acc:
-// wave w takes the columns t0 + w + 4 u, NS_B loads per batch issued before
+// Columns [k0, k1) of A times the matching rows of Z, accumulated into acc:
+// wave w takes the columns k0 + w + 4 u, NS_B loads per batch issued before
 // the batch's products.  FULL: every row of the workgroup is < d (plain
-// vector loads); else rows >= d read as zero.
-template <typename TA, int NB, bool FULL>
-__device__ __forceinline__ void nn_stream_tile(const TA* __restrict__ ar, int64_t lda, int64_t row0,
-                                               int64_t d, int t0, int tn, int w,
-                                               const double* __restrict__ zs,
+// vector loads); else rows >= d read as zero.  NBFULL: nb == NB, whole Z
+// rows in one scalar load each; else Z entries are read at indices below nb
+// only (one guarded load each), so a Z of exactly m rows of nb entries is
+// never overrun.
+template <typename TA, int NB, bool FULL, bool NBFULL>
+__device__ __forceinline__ void nn_stream_cols(const TA* __restrict__ ar, int64_t lda, int64_t row0,
+                                               int64_t d, int k0, int k1, int w,
+                                               const double* __restrict__ Z, int64_t ldz, int nb,
                                                double (&acc)[Vec16<TA>::VW][NB]) {
   constexpr int VW = Vec16<TA>::VW;
   typedef typename Vec16<TA>::type VA;
   typedef const __attribute__((address_space(1))) VA* GVA;
   typedef const __attribute__((address_space(1))) TA* GTA;
-  const int nloc = (tn - w + 3) / 4;  // columns of this wave in the tile (uniform)
+  const int nloc = (k1 - k0 - w + 3) / 4;  // columns of this wave (uniform)
   for (int c = 0; c < nloc; c += NS_B) {
     // loads of the batch first (columns past the wave's last are clamped to
     // its first and weighted by zero), then the products
@@ -848,7 +857,7 @@ __device__ __forceinline__ void nn_stream_tile(const TA* __restrict__ ar, int64_
 #pragma unroll
     for (int u = 0; u < NS_B; ++u) {
       const int cc = (c + u < nloc) ? c + u : 0;
-      const TA* colp = ar + (int64_t)(t0 + w + 4 * cc) * lda;
+      const TA* colp = ar + (int64_t)(k0 + w + 4 * cc) * lda;
       if constexpr (FULL) {
         raw[u] = *(GVA)colp;
       } else {
@@ -859,7 +868,16 @@ __device__ __forceinline__ void nn_stream_tile(const TA* __restrict__ ar, int64_
 #pragma unroll
     for (int u = 0; u < NS_B; ++u) {
       const bool live = c + u < nloc;
-      const double* zr = zs + (w + 4 * (live ? c + u : 0)) * NB;
+      const int64_t col = k0 + w + 4 * (live ? c + u : 0);
+      const ConstF64 zp = (ConstF64)(Z + col * ldz);
+      double zr[NB];
+      if constexpr (NBFULL) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) zr[j] = zp[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) zr[j] = (j < nb) ? zp[j < nb ? j : 0] : 0.0;
+      }
       const double f = live ? 1.0 : 0.0;
 #pragma unroll
       for (int h = 0; h < VW; ++h) {
@@ -875,14 +893,15 @@ template <typename TA, typename TV, typename TO, int NB>
 __device__ __forceinline__ void nn_stream_body(const NnArgs& a, int64_t bx, int by) {
   constexpr int VW = Vec16<TA>::VW;
   constexpr int R = 64 * VW;  // rows per workgroup
-  constexpr int ZT = ns_zt<NB>();
   const int64_t d = a.d;
-  const int m = (int)a.m, nb = (int)a.nb;
-  const bool split = a.kcols > 0;
-  const int k0 = split ? by * (int)a.kcols : 0;
-  const int k1 = split ? min(m, k0 + (int)a.kcols) : m;
+  const int m = __builtin_amdgcn_readfirstlane((int)a.m);
+  const int nb = __builtin_amdgcn_readfirstlane((int)a.nb);
+  const int kcols = __builtin_amdgcn_readfirstlane((int)a.kcols);
+  const bool split = kcols > 0;
+  const int k0 = split ? by * kcols : 0;
+  const int k1 = split ? min(m, k0 + kcols) : m;
   if (bx * R >= d || k0 >= k1) return;
-  __shared__ double zs[ZT * NB];
+  __shared__ double zs[NS_RED];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
   const int64_t row0 = bx * R + (int64_t)lane * VW;  // first of this lane's VW rows
@@ -893,23 +912,21 @@ __device__ __forceinline__ void nn_stream_body(const NnArgs& a, int64_t bx, int 
   for (int h = 0; h < VW; ++h)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[h][j] = 0.0;
-  for (int t0 = k0; t0 < k1; t0 += ZT) {
-    const int tn = (k1 - t0 < ZT) ? k1 - t0 : ZT;
-    __syncthreads();
-    for (int e = tid; e < tn * NB; e += 256) {
-      const int i = e / NB, j = e - i * NB;
-      double z = (j < nb) ? a.Z[(int64_t)(t0 + i) * a.ldz + j] : 0.0;
-      if (a.ascale != nullptr) z *= a.ascale[t0 + i];
-      zs[e] = z;
-    }
-    __syncthreads();
+  const double* Z = (const double*)wave_uniform64((uint64_t)a.Z);
+  const int64_t ldz = (int64_t)wave_uniform64((uint64_t)a.ldz);
+  if (nb == NB) {
     if (full)
-      nn_stream_tile<TA, NB, true>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
+      nn_stream_cols<TA, NB, true, true>(ar, a.lda, row0, d, k0, k1, w, Z, ldz, nb, acc);
     else
-      nn_stream_tile<TA, NB, false>(ar, a.lda, row0, d, t0, tn, w, zs, acc);
+      nn_stream_cols<TA, NB, false, true>(ar, a.lda, row0, d, k0, k1, w, Z, ldz, nb, acc);
+  } else {
+    if (full)
+      nn_stream_cols<TA, NB, true, false>(ar, a.lda, row0, d, k0, k1, w, Z, ldz, nb, acc);
+    else
+      nn_stream_cols<TA, NB, false, false>(ar, a.lda, row0, d, k0, k1, w, Z, ldz, nb, acc);
   }
-  // the 4 waves' sums meet in LDS (zs reused), JP columns at a time
-  constexpr int JP = (ZT * NB / (4 * R) < NB) ? ZT * NB / (4 * R) : NB;
+  // the 4 waves' sums meet in LDS, JP columns at a time
+  constexpr int JP = (NS_RED / (4 * R) < NB) ? NS_RED / (4 * R) : NB;
   static_assert(JP >= 1 && NB % JP == 0 && (R * JP) % 256 == 0, "reduction passes");
   const double alpha = split ? 0.0 : ((a.alpha_p != nullptr) ? *a.alpha_p : a.alpha);
   const TV* V = (const TV*)a.V;
@@ -1616,6 +1633,7 @@ hipError_t nn_launch_t(int count, const NnArgs* host, const NnArgs* dev, hipStre
       const NnArgs& a = host[p];
       split = split || a.kcols > 0;
       stream = ((a.lda * (int64_t)sizeof(TA)) % 16 == 0) && ((uintptr_t)a.A % 16 == 0) &&
+               a.ascale == nullptr &&
                (a.Out != a.A || (a.kcols == 0 && a.out_row == 0 && a.ldo == a.lda &&
                                  std::is_same<TO, TA>::value));
     }
