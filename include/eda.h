@@ -164,7 +164,10 @@ eda_status eda_scatter_factors(eda_handle h, int64_t d, int64_t n, int64_t k,
  * the Gram matrix P^T P is formed in float64, eig(H_B^T H_B) (and, when
  * requested, eig(H_W^T H_W)) are computed in float64, and the cores of the
  * exponentials are built.
- * Returns EDA_ERR_NONFINITE if a factor holds NaN/Inf.  Synchronises. */
+ * Returns EDA_ERR_NONFINITE if a factor holds NaN/Inf.  H_W and H_B are
+ * copied and checked before it returns (they may be reused at once); the
+ * cores are then built on the handle's stream without the host waiting, and
+ * every later call on the handle is ordered after them. */
 eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k,
                        const double* H_W, int64_t ldw, const double* H_B, int64_t ldb,
                        eda_dtype storage);

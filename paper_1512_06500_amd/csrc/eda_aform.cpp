@@ -432,7 +432,7 @@ eda_status solve_aform(eda_handle h, int32_t t, double tol, const eda_solve_opts
     // per block step: P^T V and P Y over the n + k columns of P for the
     // product with A, and again over the n columns of H_W for exp(S_W)
     info->bytes_moved = (double)iters * 2.0 * d * (h->N + h->n) * 8.0;
-    info->t_prepare_ms = h->t_prepare_ms;
+    info->t_prepare_ms = prepare_time_ms(h);
     info->t_krylov_ms = ms;
     info->shift_s = h->shiftB;
   }

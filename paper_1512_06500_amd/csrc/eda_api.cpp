@@ -573,6 +573,7 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
 
   for (int q = 0; q < 4; ++q)
     if (h->prep_ev[q] == nullptr) HIPCHK(hipEventCreate(&h->prep_ev[q]));
+  (void)prepare_time_ms(h);
   HIPCHK(hipEventRecord(h->prep_ev[0], h->stream));
 
   const int64_t N = n + k;
@@ -677,6 +678,17 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
   return EDA_OK;
 }
 
+double prepare_time_ms(eda_handle h) {
+  if (h->prep_time_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(h->prep_ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, h->prep_ev[0], h->prep_ev[1]) == hipSuccess)
+      h->t_prepare_ms = ms;
+    h->prep_time_pending = false;
+  }
+  return h->t_prepare_ms;
+}
+
 eda_status prepare_end(eda_handle h) {
   const double* pin = (const double*)h->pin;
   const int64_t n = h->n, k = h->k;
@@ -719,12 +731,13 @@ eda_status eda_prepare(eda_handle h, int64_t d, int64_t n, int64_t k, const doub
                        int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage) {
   if (h == nullptr) return EDA_ERR_ARG;
   STCHK(prepare_begin(h, d, n, k, H_W, ldw, H_B, ldb, storage, true));
+  // the factors have been copied and checked once this returns: H_W and
+  // H_B are not read after it
   HIPCHK(hipStreamSynchronize(h->stream));
   STCHK(prepare_end(h));
-  HIPCHK(hipEventSynchronize(h->prep_ev[1]));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, h->prep_ev[0], h->prep_ev[1]));
-  h->t_prepare_ms = ms;
+  // the cores are still being built on the stream; later calls on the
+  // handle are ordered after them, so the host does not wait here
+  h->prep_time_pending = true;
   return EDA_OK;
 }
 

@@ -148,7 +148,7 @@ extern "C" eda_status eda_solve_direct(eda_handle h, int32_t t, double* ritz, do
     info->flags = (t > h->k - 1) ? EDA_WARN_DEGENERATE : 0;
     info->ops = 2 * t;
     info->bytes_moved = 2.0 * (2.0 * d * N * 8.0 + 3.0 * d * t * 8.0);
-    info->t_prepare_ms = h->t_prepare_ms;
+    info->t_prepare_ms = prepare_time_ms(h);
     info->t_krylov_ms = ms;
     info->shift_s = h->shiftB;
   }

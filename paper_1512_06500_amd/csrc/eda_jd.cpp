@@ -285,7 +285,7 @@ eda_status solve_jd(eda_handle h, int32_t t, double tol, const eda_solve_opts& o
     info->flags = (floor_limited ? EDA_WARN_FLOOR : 0) | ((fl[0] | fl[1]) ? EDA_WARN_REPAIRED : 0);
     info->ops = ops;
     info->bytes_moved = (double)ops / b * (2.0 * d * N * 8.0 + 3.0 * d * b * 8.0);
-    info->t_prepare_ms = h->t_prepare_ms;
+    info->t_prepare_ms = prepare_time_ms(h);
     info->t_krylov_ms = kms;
     info->shift_s = h->shiftB;
   }

@@ -892,7 +892,7 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     info->flags = flags_out;
     info->ops = ops;
     info->bytes_moved = bytes;
-    info->t_prepare_ms = h->t_prepare_ms;
+    info->t_prepare_ms = prepare_time_ms(h);
     info->t_krylov_ms = kms;
     info->t_refine_ms = rms;
     info->shift_s = h->shiftB;

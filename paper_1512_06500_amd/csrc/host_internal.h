@@ -69,6 +69,7 @@ struct eda_handle_s {
   bool ca_ready = false;  // Arnoldi core C_A built for the current preparation
   std::vector<double> hwW, hwB;
   double t_prepare_ms = 0.0;
+  bool prep_time_pending = false;  // prep_ev[0..1] recorded, t_prepare_ms not yet read
   // pinned host scalars of the preparation (non-finite flag, ||G_WW||_1,
   // eigenvalues of G_BB and of G_WW), read back without a blocking copy
   void* pin = nullptr;
@@ -144,6 +145,10 @@ eda_status prepare_begin(eda_handle h, int64_t d, int64_t n, int64_t k, const do
                          int64_t ldw, const double* H_B, int64_t ldb, eda_dtype storage,
                          bool overlap = false);
 eda_status prepare_end(eda_handle h);
+// Duration of the last eda_prepare from its events, read on first use (by
+// then the preparation has normally finished: nothing waits for it at the
+// end of eda_prepare).
+double prepare_time_ms(eda_handle h);
 void destroy_batch_state(eda_handle h);
 void release_graphs(eda_handle h);
 

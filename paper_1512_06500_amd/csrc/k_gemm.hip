@@ -453,6 +453,45 @@ __global__ __launch_bounds__(256) void big_gram_reduce_kernel(int64_t N, int64_t
   }
 }
 
+// The same sum, one thread per entry of G (an entry above the diagonal
+// tiles reads its lower twin's partials): for Grams of few tiles, whose
+// tile-per-workgroup reduction would leave most of the chip idle.
+__global__ __launch_bounds__(256) void big_gram_reduce_elem_kernel(int64_t N, int64_t chunks,
+                                                                   const double* __restrict__ part,
+                                                                   double* __restrict__ G,
+                                                                   int64_t ldg) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  const int64_t j = e / N, i = e - j * N;
+  const bool lower = (i / BT) >= (j / BT);
+  const double* p = part + (lower ? (i + j * N) : (j + i * N));
+  const int64_t NN = N * N;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t c = 0;
+  for (; c + 3 < chunks; c += 4) {
+    s0 += p[c * NN];
+    s1 += p[(c + 1) * NN];
+    s2 += p[(c + 2) * NN];
+    s3 += p[(c + 3) * NN];
+  }
+  for (; c < chunks; ++c) s0 += p[c * NN];
+  G[i + j * ldg] = (s0 + s1) + (s2 + s3);
+}
+
+// Launch of the Gram reduction: a workgroup per lower tile when there are
+// enough tiles to fill the chip, else a thread per entry.
+hipError_t launch_big_gram_reduce(int64_t N, int64_t chunks, const double* part, double* G,
+                                  int64_t ldg, hipStream_t s) {
+  const int64_t T = (N + BT - 1) / BT, tiles = T * (T + 1) / 2;
+  if (tiles >= 256)
+    hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)tiles), dim3(256), 0, s, N, chunks,
+                       part, G, ldg);
+  else
+    hipLaunchKernelGGL(big_gram_reduce_elem_kernel, dim3((unsigned)((N * N + 255) / 256)),
+                       dim3(256), 0, s, N, chunks, part, G, ldg);
+  return hipGetLastError();
+}
+
 // Gram partials over one row chunk for one lower-triangle tile (ti >= tj).
 template <typename TP>
 __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t d, int64_t N,
@@ -724,9 +763,7 @@ hipError_t launch_gram_block(int64_t d, int64_t N, const double* X, int64_t ldx,
   const int64_t T = (N + BT - 1) / BT;
   BigGemmArgs a{N, N, d, ldx, ldx, N, X, X, nullptr, nullptr, 1.0, 0.0, 1, 0, 1, rows, part};
   launch_big64(dim3((unsigned)(T * (T + 1) / 2), (unsigned)chunks), s, a);
-  hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, N,
-                     chunks, part, G, ldg);
-  return hipGetLastError();
+  return launch_big_gram_reduce(N, chunks, part, G, ldg, s);
 }
 
 int64_t gram_chunks(int64_t d, int64_t N) {
@@ -767,10 +804,7 @@ hipError_t launch_gram_partial(int64_t d, int64_t N, const void* P, DT pdt, int6
 hipError_t launch_gram_reduce(int64_t N, int64_t chunks, const double* part, double* G,
                               int64_t ldg, hipStream_t s) {
   if (gram_big(N, DT::F64)) {
-    const int64_t T = (N + BT - 1) / BT;
-    hipLaunchKernelGGL(big_gram_reduce_kernel, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s,
-                       N, chunks, part, G, ldg);
-    return hipGetLastError();
+    return launch_big_gram_reduce(N, chunks, part, G, ldg, s);
   }
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, s, N,
                      chunks, part, G, ldg);
