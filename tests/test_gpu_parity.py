@@ -106,6 +106,24 @@ def test_scatter_factors(torch, eda, cname, request):
     h.close()
 
 
+def test_scatter_factors_class_sizes(torch, eda):
+    """Classes of 1 to 47 samples: those of at most 8, 16, 24 and 32 samples
+    are read once with the class held in registers (sizes at both ends of
+    each bound), larger ones take the two-pass loop; a ragged d (not a
+    multiple of the 256-row workgroup).  Against the oracle's eqs.
+    (1.1)-(1.2)."""
+    counts = [1, 7, 8, 9, 16, 17, 24, 25, 32, 33, 47]
+    X = datagen.make_samples(1003, counts, 24, seed=41)
+    case = Case("class sizes", X, counts, 3)
+    log(f"scatter factors d=1003 counts={counts}")
+    h = eda.Handle()
+    H_W, H_B = h.scatter_factors(dev(torch, X), counts)
+    torch.cuda.synchronize()
+    assert np.abs(host(H_W) - case.H_W).max() <= 1e-15 * 4
+    assert np.abs(host(H_B) - case.H_B).max() <= 1e-14
+    h.close()
+
+
 @pytest.mark.parametrize("cname", ["c1", "ragged", "c2"])
 def test_gram(torch, eda, cname, request):
     case = request.getfixturevalue(cname)
@@ -521,6 +539,31 @@ def test_expmv_opmv_blocks_of_9_to_16_columns(torch, eda, c2, tall, b):
         log(f"  M err={err:.2e}")
         assert err <= 1e-13
         h.close()
+
+
+@pytest.mark.parametrize("b", [1, 3, 8])
+def test_expmv_opmv_tall_blocks_up_to_8_columns(torch, eda, tall, b):
+    """Blocks of 1 to 8 columns at d = 40000: the 8-column streaming P Z,
+    whose Z rows are read with scalar loads (whole rows for b = 8, entry by
+    entry below), with a ragged last workgroup (40000 is not a multiple of
+    its 128 rows).  Oracle: the closed form of Theorem 3.1."""
+    case = tall
+    log(f"expmv/opmv {case.name} b={b}")
+    h, _, _ = prepared(torch, eda, case)
+    V = np.random.default_rng(200 + b).standard_normal((case.d, b))
+    sB = np.linalg.svd(case.H_B, compute_uv=False) ** 2
+    for which, H, c, En in (("W", case.H_W, -0.5, 1.0), ("B", case.H_B, 1.0, np.exp(sB[0]))):
+        out, s = h.expmv(which, c, dev(torch, V))
+        ref = O.exp_action_thm31(H, c, V)
+        err = rel_op_err(host(out) * np.exp(s), ref, En, V)
+        log(f"  {which} c={c} err={err:.2e}")
+        assert err <= 1e-13
+    out, s = h.opmv("M", dev(torch, V))
+    ref = O.lanczos_action_thm31(case.H_W, case.H_B, V)
+    err = rel_op_err(host(out) * np.exp(s), ref, np.exp(sB[0]), V)
+    log(f"  M err={err:.2e}")
+    assert err <= 1e-13
+    h.close()
 
 
 @pytest.mark.parametrize("b,max_basis", [(16, 0), (12, 72), (16, 80)])
