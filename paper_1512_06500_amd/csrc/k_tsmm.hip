@@ -834,8 +834,10 @@ __device__ __forceinline__ uint64_t wave_uniform64(uint64_t v) {
 }
 
 // Columns [k0, k1) of A times the matching rows of Z, accumulated into acc:
-// wave w takes the columns k0 + w + 4 u, NS_B loads per batch issued before
-// the batch's products.  FULL: every row of the workgroup is < d (plain
+// wave w takes the columns k1 - 1 - w - 4 u, from the last column down (the
+// P^T V pass that precedes a product walks P's columns upwards, so its last
+// columns may still be in the Infinity Cache), NS_B loads per batch issued
+// before the batch's products.  FULL: every row of the workgroup is < d (plain
 // vector loads); else rows >= d read as zero.  NBFULL: nb == NB, whole Z
 // rows in one scalar load each; else Z entries are read at indices below nb
 // only (one guarded load each), so a Z of exactly m rows of nb entries is
@@ -857,7 +859,7 @@ __device__ __forceinline__ void nn_stream_cols(const TA* __restrict__ ar, int64_
 #pragma unroll
     for (int u = 0; u < NS_B; ++u) {
       const int cc = (c + u < nloc) ? c + u : 0;
-      const TA* colp = ar + (int64_t)(k0 + w + 4 * cc) * lda;
+      const TA* colp = ar + (int64_t)(k1 - 1 - w - 4 * cc) * lda;
       if constexpr (FULL) {
         raw[u] = *(GVA)colp;
       } else {
@@ -868,7 +870,7 @@ __device__ __forceinline__ void nn_stream_cols(const TA* __restrict__ ar, int64_
 #pragma unroll
     for (int u = 0; u < NS_B; ++u) {
       const bool live = c + u < nloc;
-      const int64_t col = k0 + w + 4 * (live ? c + u : 0);
+      const int64_t col = k1 - 1 - w - 4 * (live ? c + u : 0);
       const ConstF64 zp = (ConstF64)(Z + col * ldz);
       double zr[NB];
       if constexpr (NBFULL) {
