@@ -738,7 +738,6 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
 
   // ---- float64 stage --------------------------------------------------------
   const double opbytes_t = 2.0 * d * h->N * 8.0 + 3.0 * d * t * 8.0;
-  const double opbytes_z = 2.0 * d * h->N * 8.0 + 3.0 * d * wz * 8.0;
   if (mixed && max_refine >= 0) {
     // orthonormalise the Ritz block in float64, apply the float64 operator
     // and take the Rayleigh-Ritz pairs of span(Y)
@@ -798,61 +797,74 @@ extern "C" eda_status eda_solve(eda_handle h, int32_t t, double tol, const eda_s
     if (std::getenv("EDA_LOG") != nullptr) log_pairs("f64", passes, t, theta.data(), res.data());
     bool ok = true;
     floor_limited = false;
+    std::vector<int64_t> miss;  // pairs that miss their target
     const double th1 = theta[0];
     for (int64_t i = 0; i < t; ++i) {
       const double thi = theta[i];
-      if (!(thi > 0.0)) { ok = false; continue; }
+      if (!(thi > 0.0)) { ok = false; miss.push_back(i); continue; }
       const double floor_i = 10.0 * kU64 * th1 / thi;
       if (floor_i > tol) floor_limited = true;
       const double r = (o.resmode == EDA_RES_REL_THETA) ? res[i] / thi : res[i] / th1;
-      if (!(r <= std::max(tol, floor_i))) ok = false;
+      if (!(r <= std::max(tol, floor_i))) { ok = false; miss.push_back(i); }
     }
     if (ok) { converged = true; break; }
     if (!kconv || passes >= max_refine) break;
-    // expand with the residual block: Z = orth(R) against Y and itself
+    // expand with the residuals of the pairs that miss their target: the
+    // others are locked (span[Y, Z] contains their Ritz vectors, so
+    // Rayleigh-Ritz keeps them), which keeps later passes narrow.
+    // Z = orth(R) against Y and itself
     double* Zt = h->Yb.d();
-    if (wz < t) {  // 2t > d: keep the residuals of the last (least converged) wz pairs
+    int64_t wzp = wz;
+    if ((int64_t)miss.size() <= wz) {
+      wzp = (int64_t)miss.size();
+      // in ascending order: column miss[q] >= q is read before anything
+      // overwrites it
+      for (int64_t q = 0; q < wzp; ++q)
+        if (miss[q] != q)
+          HIPCHK(launch_copy2d(d, 1, Z + (size_t)miss[q] * ldq, DT::F64, ldq, Z + (size_t)q * ldq,
+                               DT::F64, ldq, s));
+    } else if (wz < t) {  // 2t > d: keep the residuals of the last (least converged) wz pairs
       HIPCHK(launch_copy2d(d, wz, Z + (size_t)(t - wz) * ldq, DT::F64, ldq, Zt, DT::F64, ldq, s));
       HIPCHK(launch_copy2d(d, wz, Zt, DT::F64, ldq, Z, DT::F64, ldq, s));
     }
-    STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Z, ldq, wz, nullptr, 0, 0.0, nullptr));
-    STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Z, ldq, wz, nullptr, 0, 0.0, nullptr));
-    if (wz <= 64) {
+    STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Z, ldq, wzp, nullptr, 0, 0.0, nullptr));
+    STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Z, ldq, wzp, nullptr, 0, 0.0, nullptr));
+    if (wzp <= 64) {
       // rank revealing on unit-norm columns: converged pairs leave columns of
       // roundoff; those are replaced by random directions
-      const int64_t chunks = tn_chunks(d, wz, wz);
-      HIPCHK(launch_tn_partial(d, wz, wz, Z, DT::F64, ldq, Z, DT::F64, ldq, h->part.d(), chunks,
+      const int64_t chunks = tn_chunks(d, wzp, wzp);
+      HIPCHK(launch_tn_partial(d, wzp, wzp, Z, DT::F64, ldq, Z, DT::F64, ldq, h->part.d(), chunks,
                                nullptr, s));
-      const bool fused = wz <= 16;
+      const bool fused = wzp <= 16;
       if (!fused)
-        HIPCHK(launch_reduce_partials(chunks, wz, wz, h->part.d(), 1.0, 0.0, h->Gs.d(), wz, 0.0,
+        HIPCHK(launch_reduce_partials(chunks, wzp, wzp, h->part.d(), 1.0, 0.0, h->Gs.d(), wzp, 0.0,
                                       nullptr, 0, nullptr, s));
-      HIPCHK(launch_pchol(wz, h->Gs.d(), wz, nullptr, 0, 0, 1e-10, 1e-4, true, h->Rinv.d(), wz,
-                          h->R1.d(), wz, h->mask.i(), nullptr, s, fused ? h->part.d() : nullptr,
+      HIPCHK(launch_pchol(wzp, h->Gs.d(), wzp, nullptr, 0, 0, 1e-10, 1e-4, true, h->Rinv.d(), wzp,
+                          h->R1.d(), wzp, h->mask.i(), nullptr, s, fused ? h->part.d() : nullptr,
                           chunks));
-      HIPCHK(launch_nn(d, wz, wz, Z, DT::F64, ldq, h->Rinv.d(), wz, 0.0, nullptr, DT::F64, ldq, Zt,
+      HIPCHK(launch_nn(d, wzp, wzp, Z, DT::F64, ldq, h->Rinv.d(), wzp, 0.0, nullptr, DT::F64, ldq, Zt,
                        DT::F64, ldq, nullptr, s, false, nullptr, nullptr, h->mask.i(),
                        0x7e41e000ull + (uint64_t)passes));
-      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
-      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
-      STCHK(cholqr_pass(h, d, wz, Zt, DT::F64, ldq, Z, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wzp, nullptr, 0, 0.0, nullptr));
+      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wzp, nullptr, 0, 0.0, nullptr));
+      STCHK(cholqr_pass(h, d, wzp, Zt, DT::F64, ldq, Z, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
                         nullptr, nullptr));
     } else {
-      STCHK(cholqr_pass(h, d, wz, Z, DT::F64, ldq, Zt, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+      STCHK(cholqr_pass(h, d, wzp, Z, DT::F64, ldq, Zt, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
                         nullptr, nullptr));
-      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wz, nullptr, 0, 0.0, nullptr));
-      STCHK(cholqr_pass(h, d, wz, Zt, DT::F64, ldq, Z, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+      STCHK(cgs_pass(h, d, t, Y, DT::F64, ldq, Zt, ldq, wzp, nullptr, 0, 0.0, nullptr));
+      STCHK(cholqr_pass(h, d, wzp, Zt, DT::F64, ldq, Z, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
                         nullptr, nullptr));
     }
-    STCHK(cholqr_pass(h, d, wz, Z, DT::F64, ldq, Zt, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
+    STCHK(cholqr_pass(h, d, wzp, Z, DT::F64, ldq, Zt, ldq, nullptr, nullptr, 0, nullptr, 0, 0,
                       nullptr, nullptr));
-    HIPCHK(launch_copy2d(d, wz, Zt, DT::F64, ldq, Z, DT::F64, ldq, s));
-    STCHK(expop(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, wz, Z, DT::F64, ldq,
+    HIPCHK(launch_copy2d(d, wzp, Zt, DT::F64, ldq, Z, DT::F64, ldq, s));
+    STCHK(expop(h, true, 0, h->N, h->CM.d(), h->N, h->alphaB, wzp, Z, DT::F64, ldq,
                 MY + (size_t)t * ldq, DT::F64, ldq));
     ysm_of = nullptr;
-    ops += wz;
-    bytes += opbytes_z;
-    STCHK(rr_block(h, d, ldq, t + wz, t, mm, Y, MY, XB[1 - cb], MB[1 - cb]));
+    ops += wzp;
+    bytes += 2.0 * d * h->N * 8.0 + 3.0 * d * wzp * 8.0;
+    STCHK(rr_block(h, d, ldq, t + wzp, t, mm, Y, MY, XB[1 - cb], MB[1 - cb]));
     cb = 1 - cb;
     ++passes;
   }
