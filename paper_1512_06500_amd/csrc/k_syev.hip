@@ -32,7 +32,7 @@ namespace eda {
 namespace {
 
 constexpr int SYEV_NMAX = 2048;
-constexpr int kLdsMax = 112;      // largest n whose working matrix is kept in LDS
+constexpr int kLdsMax = 128;      // largest n whose working matrix is kept in LDS
 constexpr int kLdsDoubles = 160 * 1024 / 8;  // all of a CU's LDS (global path)
 constexpr int kClusterMax = 64;   // clusters up to this size use Cholesky QR
 
@@ -453,11 +453,20 @@ __host__ __device__ inline int64_t syev_work_doubles(int64_t nmax, int nt) {
 }
 
 // LDS layout (doubles):
-//   LDS path:    A [n (n+1)] | sv [n] | sw [n] | red [16] | Gc [kClusterMax^2]
+//   LDS path:    A [n (n+1)] | sv [n] | sw [n] | red [16] | Gc [syev_lds_gc(n)]
 //                | Zt [n nvec] (when it fits)
 //   global path: sv [n] | sw [n] | red [32] | stage [rest of the 160 KB]  (Gc = stage)
+// LDS path: the cluster Gram matrices (Gc) take what the working matrix
+// leaves of the 160 KB, at most kClusterMax^2 doubles (3680 at n = 128, so
+// clusters of up to 60 vectors use Cholesky QR there); Gc also holds the
+// wave partials of the tridiagonalisation (NW 128 + NW <= 1032 doubles).
+__host__ __device__ inline int64_t syev_lds_gc(int64_t n) {
+  const int64_t rest = kLdsDoubles - (n * (n + 1) + 2 * n + 32);
+  const int64_t full = (int64_t)kClusterMax * kClusterMax;
+  return rest < full ? rest : full;
+}
 __host__ __device__ inline int64_t syev_lds_doubles(int64_t n, bool lds_a) {
-  return lds_a ? n * (n + 1) + 2 * n + 32 + kClusterMax * kClusterMax : kLdsDoubles;
+  return lds_a ? n * (n + 1) + 2 * n + 32 + syev_lds_gc(n) : kLdsDoubles;
 }
 // LDS path: the eigenvectors of T (n x nvec) follow when they fit in 160 KB.
 inline int64_t syev_lds_alloc(int64_t nmax, int64_t nvmax, bool lds_a) {
@@ -989,6 +998,12 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
   __syncthreads();
 
   SYEV_MARK(3);
+  // largest cluster orthonormalised by Cholesky QR (its Gram matrix in Gc)
+  int cmax = kClusterMax;
+  if (lds_a) {
+    const int64_t gcap = syev_lds_gc(nmax);
+    while ((int64_t)cmax * cmax > gcap) --cmax;
+  }
   // ---- 3b. orthonormalise clusters of close eigenvalues --------------------
   // The independent iterates of a cluster (gap <= ctol) span its invariant
   // subspace; they are orthonormalised together, which mixes only vectors of
@@ -999,7 +1014,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
       int b = a + 1;
       while (b < n && (lamv[b] - lamv[b - 1]) <= ctol) ++b;
       const int c = b - a;
-      if (c > 1 && c <= kClusterMax) {
+      if (c > 1 && c <= cmax) {
         const int s0 = a - n0;
         for (int pass = 0; pass < 2; ++pass) {
           const int np = c * (c + 1) / 2;
@@ -1033,7 +1048,7 @@ __global__ __launch_bounds__(NT) void syev_kernel(const SyevArgs* __restrict__ s
           }
           __syncthreads();
         }
-      } else if (c > kClusterMax) {
+      } else if (c > cmax) {
         // classical Gram-Schmidt run twice, vector by vector, by the whole
         // workgroup: wave w forms the coefficients against vectors w, w+NW,
         // ... of the cluster (Gc), then every thread updates its positions
