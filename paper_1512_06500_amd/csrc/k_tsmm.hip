@@ -809,8 +809,8 @@ __global__ __launch_bounds__(256) void nn_kernel(const NnArgs* __restrict__ arr,
 // aligned columns and at most NB output columns (NB = 8 or 16), all in one
 // workgroup column: a workgroup owns 64 VW rows (VW = 16 / sizeof(TA): each
 // lane reads VW consecutive rows of a column with one 16-byte load, so a
-// wave instruction moves 1 KB of one column), its 4 waves take the columns
-// j = w mod 4, NS_B column loads in flight per wave.  The row of Z that
+// wave instruction moves 1 KB of one column), each of its 4 waves takes
+// every fourth column, NS_B column loads in flight per wave.  The row of Z that
 // multiplies a column is the same for the whole wave, so it is read with
 // scalar loads (through the scalar cache) straight from global memory: no
 // LDS staging and no barrier while A streams.  The 4 waves' sums meet in LDS
@@ -839,7 +839,7 @@ __device__ __forceinline__ uint64_t wave_uniform64(uint64_t v) {
 // columns may still be in the Infinity Cache), NS_B loads per batch issued
 // before the batch's products.  FULL: every row of the workgroup is < d (plain
 // vector loads); else rows >= d read as zero.  NBFULL: nb == NB, whole Z
-// rows in one scalar load each; else Z entries are read at indices below nb
+// rows by wide scalar loads; else Z entries are read at indices below nb
 // only (one guarded load each), so a Z of exactly m rows of nb entries is
 // never overrun.
 template <typename TA, int NB, bool FULL, bool NBFULL>
