@@ -235,6 +235,25 @@ def test_syev_special_matrices(torch, eda, c1):
     h.close()
 
 
+@pytest.mark.parametrize("n,c", [(112, 64), (120, 61), (128, 60), (128, 62), (128, 100)])
+def test_syev_large_clusters_in_lds(torch, eda, n, c):
+    """Matrices of up to 128 rows stay in LDS; a cluster of c equal
+    eigenvalues is orthonormalised by Cholesky QR when its Gram matrix fits
+    in the LDS left over by the matrix (64 x 64 up to n = 112, 60 x 60 at
+    n = 128) and by Gram-Schmidt otherwise.  Eigenvalues, residuals and
+    orthogonality against the definitions (check_eig)."""
+    log(f"syev n={n} cluster of {c}")
+    rng = np.random.default_rng(n + c)
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    lam = np.concatenate([np.full(c, 0.5), np.linspace(1.0, 2.0, n - c)])
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    h = eda.Handle()
+    w, Z = h.syev(dev(torch, A))
+    check_eig(A, host(w), host(Z))
+    h.close()
+
+
 # ---------------------------------------------------------------------------
 # a4: low-rank exponential apply
 # ---------------------------------------------------------------------------
